@@ -1,0 +1,207 @@
+"""Benchmark of the MSD-AFQMC hot path on one MI355X.
+
+One step = one pass of the whole hot path over the walker batch:
+  propagate (force bias -> VHS -> one-body/Taylor/one-body -> new overlap ->
+  phaseless weights -> QR) followed by a full measurement (overlap, Green's
+  function, force bias, local energy).
+Metric: MSD Wick evaluations per second = n_walkers * n_det / step time.
+Workload: the Medium synthetic system (M=64, N=8+8, 320 Cholesky vectors,
+1,000 determinants of excitation order 0-4, 128 walkers), FP64.
+
+Prints ONE JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+
+def stage_work(wl, lib_sys, stage):
+    """Algorithmic work of one launch group of a stage: (amount, unit, bound)."""
+    M, na, nb, NG, NW = wl.M, wl.n_alpha, wl.n_beta, wl.n_chol, wl.n_walkers
+    Ntot = na + nb
+    tt = lib_sys.tables
+    if stage == "lt_gemm":  # both spins are separate launch groups; average them
+        f = sum(2.0 * NG * (N + nv) * M * 2 * NW * N for N, nv in
+                ((na, tt["nv"][0]), (nb, tt["nv"][1]))) / 2
+        return f, "flop", "mfma"
+    if stage == "fb_gemm":
+        return 2.0 * NG * tt["P_all"] * M * 2 * NW, "flop", "mfma"
+    if stage == "vhs_gemm":
+        return 2.0 * 2 * NW * NG * M * M, "flop", "mfma"
+    if stage == "taylor":  # n_taylor complex GEMMs per launch group
+        return 6 * 8.0 * M * M * Ntot * NW, "flop", "mfma"
+    if stage == "one_body":
+        return 4.0 * M * M * Ntot * NW, "flop", "mfma"
+    if stage == "lambda":
+        f = 0.0
+        for N, nv, no in ((na, tt["nv"][0], tt["no"][0]), (nb, tt["nv"][1], tt["no"][1])):
+            f += NG * NW * 8.0 * (nv * N * N + nv * N * no + N * N)
+        return f, "flop", "alu"
+    if stage == "energy_gamma":
+        b = NW * NG * 16.0 * (tt["nv"][0] * tt["no"][0] + tt["nv"][1] * tt["no"][1])
+        return b, "byte", "hbm"
+    return None
+
+
+def cpu_baseline(wl, n_sample=6):
+    """The oracle on a bounded sample: n_sample walkers, all determinants,
+    one propagation step + one full measurement each."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import msd, propagate
+    from synth import fields_for_step
+
+    idx = list(range(n_sample))
+    t0 = time.perf_counter()
+    b1 = propagate.one_body_half_step(wl.h1, wl.chol, wl.dt)
+    lo = np.array([np.log(msd.trial_overlap(wl.ci, wl.occ_a, wl.occ_b, wl.phi_a[w], wl.phi_b[w]))
+                   for w in idx])
+    pa, pb, _, _, _ = propagate.step(wl.h1, wl.chol, wl.ci, wl.occ_a, wl.occ_b, wl.phi_a[idx],
+                                     wl.phi_b[idx], wl.weights[idx], lo,
+                                     fields_for_step(wl, 0)[idx], wl.dt, do_qr=True, b1=b1)
+    msd.measure(wl.h1, wl.chol, wl.e0, wl.ci, wl.occ_a, wl.occ_b, pa, pb, wl.dt)
+    dt = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    return {"value": n_sample * wl.n_det / dt, "unit": "walker*det/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"{n_sample} of {wl.n_walkers} walkers x all {wl.n_det} dets, one step "
+                      f"(propagate + measure), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build measures one GPU only (no multi-GPU path); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2406_08314_amd import MsdSystem
+    from synth import fields_for_step, make_config
+
+    wl = make_config("medium")
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    s = MsdSystem(wl.M, wl.n_alpha, wl.n_beta, wl.n_chol, wl.n_walkers, wl.n_det, device=0,
+                  stream=stream.cuda_stream, stabilize_freq=1, timing=True)
+    s.set_hamiltonian(wl.h1, wl.chol, wl.e0)
+    s.set_trial(wl.ci, wl.occ_a, wl.occ_b)
+    s.set_walkers(wl.phi_a, wl.phi_b, wl.weights)
+    s.tables = _tables(wl)
+    n_total = args.warmup + args.steps
+    fields = torch.from_numpy(np.stack([fields_for_step(wl, k) for k in range(n_total)])).to(dev)
+    lo = torch.empty(wl.n_walkers, dtype=torch.complex128, device=dev)
+    fb = torch.empty(wl.n_walkers, wl.n_chol, dtype=torch.complex128, device=dev)
+    el = torch.empty(wl.n_walkers, dtype=torch.complex128, device=dev)
+    per_step = wl.n_walkers * wl.n_chol
+
+    def step(k):
+        s.propagate_dev(fields[k].reshape(-1), wl.dt, 0.0, 1)
+        s.measure_dev(wl.dt, lo, fb, el)
+
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    s.reset_timings()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for k in range(args.warmup, n_total):
+        step(k)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    ms_step = ms / args.steps
+    value = wl.n_walkers * wl.n_det / (ms_step * 1e-3)
+    del per_step
+
+    stages = s.timings()
+    dom = max((k for k in stages if stages[k][1] > 0), key=lambda k: stages[k][0])
+    roof = None
+    for name in sorted(stages, key=lambda k: -stages[k][0]):
+        work = stage_work(wl, s, name)
+        if work is None:
+            continue
+        amount, unit, bound = work
+        avg_s = stages[name][0] / stages[name][1] * 1e-3
+        if unit == "flop":
+            ach = amount / avg_s / 1e12
+            peak = FP64_PEAK_TFLOPS
+            u = "TFLOP/s"
+        else:
+            ach = amount / avg_s / 1e9
+            peak = HBM_PEAK_GBS
+            u = "GB/s"
+        roof = {"kernel": name, "bound": bound, "achieved": round(ach, 3), "peak": peak,
+                "unit": u, "frac": round(ach / peak, 4), "traffic": None,
+                "avg_launch_ms": round(avg_s * 1e3, 4)}
+        break
+
+    line = {
+        "metric": "MSD Wick evals/s (walker*det/s), FP64",
+        "value": value,
+        "unit": "walker*det/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded Medium system; no molecular integrals)",
+        "config": {"workload": "medium: M=64, N=8+8, Nchol=320, Ndet=1000 (orders 0-4), "
+                               "128 walkers, dt=0.005, QR every step",
+                   "global_batch": wl.n_walkers, "n_det": wl.n_det, "parallelism": "none"},
+        "roofline": roof,
+        "dominant_stage": dom,
+        "stages_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in stages.items() if v[1]},
+        "wall_s": round(wall, 3),
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(line), flush=True)
+
+
+def _tables(wl):
+    """Window sizes of the trial (from its occupation lists)."""
+    out = {"nv": [], "no": []}
+    rows = set()
+    for occ in (wl.occ_a, wl.occ_b):
+        ref = set(occ[0].tolist())
+        holes, parts = set(), set()
+        for row in occ:
+            r = set(row.tolist())
+            holes |= ref - r
+            parts |= r - ref
+        out["nv"].append(len(parts))
+        out["no"].append(len(holes))
+        rows |= ref | parts
+    out["P_all"] = len(rows)
+    return out
+
+
+if __name__ == "__main__":
+    main()

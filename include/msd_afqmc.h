@@ -1,0 +1,178 @@
+/*
+ * msd_afqmc.h -- C ABI of the MI355X (gfx950) MSD-AFQMC hot-path library.
+ *
+ * The library evaluates, for a batch of walkers (each one Slater determinant
+ * per spin), the quantities of phaseless AFQMC with a multi-Slater-determinant
+ * (CI-expansion) trial:
+ *   - the trial overlap <Psi_T|Phi>               (Sec. II.A Eq. 13, Eq. 15)
+ *   - the mixed Green's function                  (Eq. 14)
+ *   - the force bias xbar                         (Eq. 7)
+ *   - the mixed local energy                      (Sec. II.A, generalised Wick)
+ * through the generalised Wick theorem relative to a reference determinant
+ * (Sec. III), and one propagation step                   (Eqs. 3-5, 8-12)
+ *   - VHS = i sqrt(dt) sum_g (x_g - xbar_g) L^g, Phi <- B1 exp_T(VHS) B1 Phi
+ *     with B1 = expm(-dt h'/2), h' = h - 1/2 sum_g L^g L^g (Eq. 4),
+ *   - new overlaps, phaseless weights, periodic re-orthonormalisation (QR).
+ *
+ * Conventions
+ *   Complex numbers are passed as interleaved (re, im) pairs of doubles.
+ *   All arrays are row-major (C order), densely packed.
+ *   Trial: c_I multiplies the determinant whose alpha and beta orbital sets
+ *   are the rows of occ_a / occ_b, each set in ascending order, alpha
+ *   creation operators before beta.  <Psi_T| carries conj(c_I).  Row 0 is the
+ *   reference determinant of the Wick expansion; every other row is an
+ *   excitation of it.  Rows are treated as sets (any order on input).
+ *   Hamiltonian: H = E0 + sum h_pq E_pq + 1/2 sum (pq|rs) a+_p a+_r a_s a_q
+ *   with (pq|rs) = sum_g L^g_pq L^g_rs; h and every L^g real symmetric.
+ *   Green's function G^s_pq = <Psi_T|a+_ps a_qs|Phi>/<Psi_T|Phi>.
+ *   Force bias xbar_g = -i sqrt(dt) sum_s sum_pq L^g_pq G^s_pq.
+ *   Weight update: S = <Psi_T|Phi'>/<Psi_T|Phi>,
+ *     w <- w |S exp(x.xbar - xbar.xbar/2)| max(0, cos arg S) exp(dt e_shift)
+ *   (bilinear dot products).  A walker of weight 0 is frozen (not moved).
+ *
+ * Ownership and errors
+ *   Inputs are caller-owned and copied before the call returns; outputs go to
+ *   caller buffers.  No pointer is retained.  Every call returns msd_status
+ *   (0 = success); no C++ exception crosses the ABI.  msd_last_error() gives
+ *   a message naming the offending index.  A handle is bound to one device
+ *   and one HIP stream; calls on one handle must not overlap.  "_dev" entry
+ *   points take device pointers and are stream-ordered on the handle's
+ *   stream (they return once the work is enqueued, except where noted).
+ */
+#ifndef MSD_AFQMC_H
+#define MSD_AFQMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MSD_OK = 0,
+  MSD_ERR_ARG = -1,         /* null pointer, non-finite value, bad option    */
+  MSD_ERR_SHAPE = -2,       /* inconsistent dimensions                        */
+  MSD_ERR_TRIAL = -3,       /* invalid occupation lists / excitations         */
+  MSD_ERR_SINGULAR = -4,    /* walker with zero overlap with the reference    */
+  MSD_ERR_DEVICE = -5,      /* HIP runtime error                              */
+  MSD_ERR_OOM = -6,         /* device allocation failed / plan too large      */
+  MSD_ERR_STATE = -7,       /* call order (e.g. measure before set_trial)     */
+  MSD_ERR_UNSUPPORTED = -8  /* shape outside what the kernels implement       */
+} msd_status;
+
+typedef struct msd_system msd_system;
+
+/* Problem sizes.  M spatial orbitals, n_alpha/n_beta electrons, n_chol
+ * Cholesky vectors, n_walkers walkers, n_det determinants in the trial. */
+typedef struct {
+  int32_t M;
+  int32_t n_alpha;
+  int32_t n_beta;
+  int32_t n_chol;
+  int32_t n_walkers;
+  int32_t reserved;
+  int64_t n_det;
+} msd_dims;
+
+typedef struct {
+  int32_t n_taylor;       /* Taylor order of exp(VHS) (terms 0..n_taylor), default 6 */
+  int32_t stabilize_freq; /* QR every this many propagate steps (0 = never), default 5 */
+  int32_t timing;         /* 1: record HIP events around every kernel stage   */
+  int32_t reserved[5];
+} msd_options;
+
+/* Limits of this implementation. */
+#define MSD_MAX_ELECTRONS 128   /* per spin                                   */
+#define MSD_MAX_EXCITATION 8    /* holes per spin per determinant             */
+
+const char* msd_status_string(msd_status s);
+const char* msd_last_error(const msd_system* sys);
+
+/* Fill *o with the defaults (n_taylor 6, stabilize_freq 5, timing 0). */
+msd_status msd_default_options(msd_options* o);
+
+/* Create a handle on HIP device `device`; `hip_stream` is a hipStream_t (NULL:
+ * the default stream).  Allocates the walker state for d->n_walkers walkers.
+ * MSD_ERR_SHAPE for non-positive sizes or n_alpha/n_beta > M or above
+ * MSD_MAX_ELECTRONS; MSD_ERR_DEVICE / MSD_ERR_OOM from the runtime. */
+msd_status msd_create(const msd_dims* d, const msd_options* o, int32_t device,
+                      void* hip_stream, msd_system** out);
+void msd_destroy(msd_system* sys);
+
+/* Hamiltonian (Eqs. 2-4).  h1: M*M doubles.  chol: n_chol*M*M doubles, row
+ * g*M*M + p*M + q = L^g_pq.  Both must be symmetric to 1e-12 (MSD_ERR_ARG
+ * names the first offending index otherwise).  Precomputes h' and the
+ * one-body half-step factor for the time step passed to msd_propagate. */
+msd_status msd_set_hamiltonian(msd_system* sys, const double* h1, const double* chol,
+                               double e0);
+
+/* Trial (Eq. 15).  ci: n_det complex (2*n_det doubles).  occ_a: n_det*n_alpha
+ * int32, occ_b: n_det*n_beta int32.  Row 0 is the Wick reference.
+ * MSD_ERR_TRIAL for an orbital outside [0, M), a repeated orbital in a row,
+ * or more than MSD_MAX_EXCITATION holes per spin.  Duplicate rows are allowed
+ * (their coefficients add). */
+msd_status msd_set_trial_occ(msd_system* sys, const double* ci, const int32_t* occ_a,
+                             const int32_t* occ_b);
+
+/* Walkers (host arrays).  phi_a: n_walkers*M*n_alpha complex, [w][p][j];
+ * phi_b likewise with n_beta; weights: n_walkers doubles (NULL: all 1).
+ * Needs the trial (MSD_ERR_STATE otherwise): computes log <Psi_T|Phi_w>.
+ * MSD_ERR_SINGULAR if a walker has a singular reference block. */
+msd_status msd_set_walkers(msd_system* sys, const double* phi_a, const double* phi_b,
+                           const double* weights);
+/* Same with device pointers (same layouts); synchronises the stream. */
+msd_status msd_set_walkers_dev(msd_system* sys, const double* phi_a, const double* phi_b,
+                               const double* weights);
+/* Copy the walker state out (any pointer may be NULL).  log_ovlp: n_walkers
+ * complex, log <Psi_T|Phi_w> (imaginary part defined modulo 2 pi). */
+msd_status msd_get_walkers(msd_system* sys, double* phi_a, double* phi_b, double* weights,
+                           double* log_ovlp);
+
+/* Measurement of every walker: log_ovlp (n_walkers complex), force_bias
+ * (n_walkers*n_chol complex, [w][g], uses time step dt), e_loc (n_walkers
+ * complex).  Any output may be NULL; the energy stages run only if e_loc is
+ * non-NULL.  Host pointers; synchronises the stream. */
+msd_status msd_measure(msd_system* sys, double dt, double* log_ovlp, double* force_bias,
+                       double* e_loc);
+/* Same with device output pointers; stream-ordered, does not synchronise
+ * (MSD_ERR_SINGULAR for a zero reference overlap is then reported by the
+ * next synchronising call). */
+msd_status msd_measure_dev(msd_system* sys, double dt, double* log_ovlp, double* force_bias,
+                           double* e_loc);
+
+/* n_steps propagation steps.  fields: n_steps*n_walkers*n_chol doubles,
+ * standard-normal auxiliary fields, [step][w][g] (host).  Each step: force
+ * bias, VHS, Taylor propagator with one-body half steps, new overlap,
+ * phaseless weight update, and QR every stabilize_freq steps (counted over
+ * the life of the handle).  Synchronises the stream. */
+msd_status msd_propagate(msd_system* sys, const double* fields, double dt, double e_shift,
+                         int32_t n_steps);
+/* Same with fields in device memory; stream-ordered, does not synchronise. */
+msd_status msd_propagate_dev(msd_system* sys, const double* fields, double dt,
+                             double e_shift, int32_t n_steps);
+
+/* Green's functions of one walker (M*M complex each, G_pq at [p][q]) from
+ * the most recent measure or propagate evaluation. */
+msd_status msd_get_green(msd_system* sys, int32_t walker, double* g_a, double* g_b);
+
+/* Stage timings accumulated since the last reset (timing option on).
+ * names: up to max_stages C strings owned by the library; ms: total
+ * milliseconds; counts: launches.  *n_stages receives the number written. */
+msd_status msd_get_timings(msd_system* sys, int32_t max_stages, const char** names,
+                           double* ms, int64_t* counts, int32_t* n_stages);
+msd_status msd_reset_timings(msd_system* sys);
+
+/* Host-only excitation analysis of a trial (no device needed), for checking
+ * the trial builder.  Per determinant: k_a/k_b = holes per spin, sign = the
+ * product of both spins' excitation signs (+1/-1; the sign of the permutation
+ * that sorts the reference with each hole replaced by its particle, holes
+ * and particles each ascending).  Returns MSD_ERR_TRIAL like set_trial_occ. */
+msd_status msd_trial_analyze(int32_t M, int32_t n_alpha, int32_t n_beta, int64_t n_det,
+                             const int32_t* occ_a, const int32_t* occ_b, int32_t* k_a,
+                             int32_t* k_b, int32_t* sign);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSD_AFQMC_H */

@@ -1,0 +1,1090 @@
+// Host runtime behind the C ABI declared in include/msd_afqmc.h.
+//
+// Owns the device memory of one walker batch, the trial tables and the
+// Hamiltonian, and enqueues the kernel pipeline on the handle's stream:
+//   measure   = reference inverse -> string dets/adjugates -> Obar ->
+//               CI weights -> CI matrix -> Green's rows -> force-bias GEMM
+//               [-> Cholesky GEMM -> Lam/Xi -> two-body coefficients ->
+//                   Cholesky-vector loop -> energy assembly]
+//   propagate = force bias -> VHS GEMM -> one-body half step -> Taylor chain
+//               (complex GEMMs) -> one-body half step -> new overlap ->
+//               weights [-> QR].
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "kernels.h"
+#include "msd_afqmc.h"
+#include "trial.h"
+
+using msd::cd;
+
+namespace {
+
+struct Error {
+  msd_status code;
+  std::string msg;
+};
+
+[[noreturn]] void fail(msd_status c, const std::string& m) { throw Error{c, m}; }
+
+void hip_check(hipError_t e, const char* what) {
+  if (e == hipErrorOutOfMemory) fail(MSD_ERR_OOM, std::string(what) + ": out of device memory");
+  if (e != hipSuccess) fail(MSD_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+enum Stage {
+  ST_REF, ST_STR, ST_OVLP, ST_CIW, ST_CIM, ST_GREEN, ST_FB_GEMM, ST_LT_GEMM, ST_LAMBDA,
+  ST_COEF, ST_EGAMMA, ST_EFINAL, ST_VHS_GEMM, ST_B1, ST_TAYLOR, ST_WEIGHTS, ST_QR, ST_COUNT
+};
+const char* kStageNames[ST_COUNT] = {
+    "ref_inverse", "strings",  "overlap",   "ci_weights", "ci_matrix",    "green",
+    "fb_gemm",     "lt_gemm",  "lambda",    "coef",       "energy_gamma", "energy_final",
+    "vhs_gemm",    "one_body", "taylor",    "weights",    "qr"};
+
+// Minimal device arena: every allocation is recorded and freed together.
+struct Arena {
+  std::vector<void*> ptrs;
+  template <class T>
+  T* get(size_t n) {
+    if (n == 0) n = 1;
+    void* p = nullptr;
+    hip_check(hipMalloc(&p, n * sizeof(T)), "hipMalloc");
+    ptrs.push_back(p);
+    return static_cast<T*>(p);
+  }
+  template <class T>
+  T* upload(const std::vector<T>& v, hipStream_t st) {
+    T* p = get<T>(v.size());
+    if (!v.empty())
+      hip_check(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st),
+                "upload");
+    return p;
+  }
+  void release() {
+    for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+  }
+};
+
+}  // namespace
+
+struct msd_system {
+  int dev = 0;
+  hipStream_t st = nullptr;
+  msd_dims d{};
+  msd_options o{};
+  std::string err;
+  int M = 0, na = 0, nb = 0, Ntot = 0, NG = 0, NW = 0;
+  int64_t ND = 0;
+  bool have_ham = false, have_trial = false, have_walkers = false;
+  Arena base, ham_mem, trial_mem, energy_mem;
+
+  // Hamiltonian
+  double* L = nullptr;    // [NG][M][M]
+  double* h1 = nullptr;   // [M][M]
+  double* B1 = nullptr;   // [M][M]  expm(-dt h'/2)
+  double B1_dt = NAN;
+  double e0 = 0.0;
+  std::vector<double> h1_host, sumll_host;
+
+  // trial
+  msd::TrialTables tt;
+  msd::DevSpin ds[2];
+  msd::DevPairs dp;
+  cd* det_c = nullptr;
+  int P_all = 0;
+  int* rmap[2] = {nullptr, nullptr};
+  int* rows_all_dev = nullptr;
+  double* L_rows = nullptr;   // [NG][P_all][M]
+  double* L_lt[2] = {nullptr, nullptr};  // [NG][P_s][M]
+  bool derived_ok = false;
+
+  // walkers
+  cd* phi = nullptr;       // [NW][M][Ntot]
+  double* weights = nullptr;
+  cd* logo = nullptr;
+  int64_t steps_done = 0;
+
+  // work
+  msd::SpinWork sw[2];
+  cd* obar = nullptr;
+  cd* opart = nullptr;
+  int n_ochunks = 1, ochunk = 2048;
+  int* flag = nullptr;
+  double* Gp = nullptr;
+  double* xraw = nullptr;
+  cd* xbar = nullptr;
+  cd* logo_tmp = nullptr;
+  cd* eloc = nullptr;
+  cd* onebody = nullptr;   // [2][NW]
+
+  // energy work (lazily sized)
+  int WT = 0, gl_chunk = 16, n_lchunks = 0, ge_chunk = 8, n_echunks = 0;
+  cd* LT[2] = {nullptr, nullptr};
+  cd* Lam[2] = {nullptr, nullptr};
+  cd* v0 = nullptr;
+  cd* ex0 = nullptr;
+  cd* ZWp[2] = {nullptr, nullptr};
+  cd* coefAB = nullptr;
+  cd* coef2[2] = {nullptr, nullptr};
+  cd* epart = nullptr;
+
+  // propagation work
+  double* Y = nullptr;
+  double* VHS = nullptr;
+  cd* term[2] = {nullptr, nullptr};
+  cd* acc = nullptr;
+  int* mask = nullptr;
+  double* fields = nullptr;  // staging for host fields [NW][NG]
+
+  // timing
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+  std::vector<hipEvent_t> pool;
+  double stage_ms[ST_COUNT] = {0};
+  int64_t stage_n[ST_COUNT] = {0};
+
+  hipEvent_t ev() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    hip_check(hipEventCreate(&e), "hipEventCreate");
+    return e;
+  }
+  void harvest() {
+    if (pending.empty()) return;
+    hip_check(hipStreamSynchronize(st), "synchronize");
+    for (auto& p : pending) {
+      float ms = 0.f;
+      hip_check(hipEventElapsedTime(&ms, p.second.first, p.second.second), "elapsed");
+      stage_ms[p.first] += ms;
+      stage_n[p.first] += 1;
+      pool.push_back(p.second.first);
+      pool.push_back(p.second.second);
+    }
+    pending.clear();
+  }
+  template <class F>
+  void timed(Stage s, F&& f) {
+    if (!o.timing) {
+      f();
+      return;
+    }
+    hipEvent_t a = ev(), b = ev();
+    hip_check(hipEventRecord(a, st), "record");
+    f();
+    hip_check(hipEventRecord(b, st), "record");
+    pending.push_back({(int)s, {a, b}});
+    if (pending.size() > 4096) harvest();
+  }
+  void sync() { hip_check(hipStreamSynchronize(st), "synchronize"); }
+  void check_launch(const char* what) { hip_check(hipGetLastError(), what); }
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+#define API_BEGIN \
+  try {
+#define API_END(sysp)                                        \
+  }                                                          \
+  catch (const Error& e) {                                   \
+    if (sysp) (sysp)->err = e.msg;                           \
+    g_err = e.msg;                                           \
+    return e.code;                                           \
+  }                                                          \
+  catch (const std::bad_alloc&) {                            \
+    if (sysp) (sysp)->err = "host allocation failed";        \
+    return MSD_ERR_OOM;                                      \
+  }                                                          \
+  catch (...) {                                              \
+    if (sysp) (sysp)->err = "unexpected internal error";     \
+    return MSD_ERR_DEVICE;                                   \
+  }                                                          \
+  return MSD_OK;
+
+void set_device(msd_system* s) { hip_check(hipSetDevice(s->dev), "hipSetDevice"); }
+
+// expm of a small real matrix by scaling and squaring of its Taylor series.
+std::vector<double> expm_host(const std::vector<double>& a, int n) {
+  double norm = 0.0;
+  for (int j = 0; j < n; ++j) {
+    double c = 0.0;
+    for (int i = 0; i < n; ++i) c += std::fabs(a[(size_t)i * n + j]);
+    norm = std::max(norm, c);
+  }
+  int s = 0;
+  while (norm / std::ldexp(1.0, s) > 0.25) ++s;
+  const double scale = std::ldexp(1.0, -s);
+  std::vector<double> x(a.size()), res((size_t)n * n, 0.0), term((size_t)n * n, 0.0),
+      tmp((size_t)n * n);
+  for (size_t i = 0; i < a.size(); ++i) x[i] = a[i] * scale;
+  for (int i = 0; i < n; ++i) res[(size_t)i * n + i] = term[(size_t)i * n + i] = 1.0;
+  auto mul = [n](const std::vector<double>& p, const std::vector<double>& q,
+                 std::vector<double>& out) {
+    std::fill(out.begin(), out.end(), 0.0);
+    for (int i = 0; i < n; ++i)
+      for (int k = 0; k < n; ++k) {
+        const double v = p[(size_t)i * n + k];
+        if (v == 0.0) continue;
+        const double* qr = &q[(size_t)k * n];
+        double* orow = &out[(size_t)i * n];
+        for (int j = 0; j < n; ++j) orow[j] += v * qr[j];
+      }
+  };
+  for (int k = 1; k <= 24; ++k) {
+    mul(term, x, tmp);
+    for (size_t i = 0; i < tmp.size(); ++i) term[i] = tmp[i] / k;
+    for (size_t i = 0; i < tmp.size(); ++i) res[i] += term[i];
+  }
+  for (int i = 0; i < s; ++i) {
+    mul(res, res, tmp);
+    res.swap(tmp);
+  }
+  return res;
+}
+
+void free_energy(msd_system* s) {
+  s->energy_mem.release();
+  s->WT = 0;
+}
+
+// Cholesky rows restricted to the orbitals the Wick kernels touch (needs both
+// the Hamiltonian and the trial).
+void build_derived(msd_system* s) {
+  if (s->derived_ok) return;
+  if (!s->have_ham || !s->have_trial) fail(MSD_ERR_STATE, "Hamiltonian and trial must both be set");
+  set_device(s);
+  for (int sp = 0; sp < 2; ++sp) {
+    const msd::DevSpin& D = s->ds[sp];
+    msd::launch_gather_rows(s->L, s->NG, s->M, D.rows, D.P, s->L_lt[sp], s->st);
+  }
+  msd::launch_gather_rows(s->L, s->NG, s->M, s->rows_all_dev, s->P_all, s->L_rows, s->st);
+  s->check_launch("gather rows");
+  s->derived_ok = true;
+}
+
+void alloc_energy(msd_system* s) {
+  if (s->WT > 0) return;
+  const msd::DevSpin& A = s->ds[0];
+  const msd::DevSpin& B = s->ds[1];
+  const int NG = s->NG, NW = s->NW;
+  const size_t per_w = (size_t)NG * ((size_t)A.P * A.N + (size_t)B.P * B.N) * sizeof(cd) +
+                       (size_t)NG * ((size_t)A.nv * A.no + (size_t)B.nv * B.no) * sizeof(cd);
+  const size_t budget = (size_t)16 << 30;
+  int wt = (int)std::max<size_t>(1, std::min<size_t>(NW, budget / std::max<size_t>(per_w, 1)));
+  s->WT = wt;
+  s->gl_chunk = 16;
+  s->n_lchunks = (NG + s->gl_chunk - 1) / s->gl_chunk;
+  const int X = A.nv * A.no + B.nv * B.no;
+  s->ge_chunk = std::max(1, std::min(NG, (int)((120 * 1024) / (std::max(X, 1) * sizeof(cd)))));
+  s->n_echunks = (NG + s->ge_chunk - 1) / s->ge_chunk;
+  Arena& E = s->energy_mem;
+  for (int sp = 0; sp < 2; ++sp) {
+    const msd::DevSpin& D = s->ds[sp];
+    s->LT[sp] = E.get<cd>((size_t)NG * D.P * wt * D.N);
+    s->Lam[sp] = E.get<cd>((size_t)wt * NG * D.nv * D.no);
+    s->ZWp[sp] = E.get<cd>((size_t)wt * s->n_lchunks * D.nv * D.no);
+    s->coef2[sp] = E.get<cd>((size_t)NW * D.n_minor);
+  }
+  s->v0 = E.get<cd>((size_t)2 * NW * NG);
+  s->ex0 = E.get<cd>((size_t)2 * NW * NG);
+  s->coefAB = E.get<cd>((size_t)NW * s->dp.n_pair);
+  s->epart = E.get<cd>((size_t)NW * s->n_echunks);
+}
+
+void need_ready(msd_system* s) {
+  if (!s->have_ham) fail(MSD_ERR_STATE, "msd_set_hamiltonian has not been called");
+  if (!s->have_trial) fail(MSD_ERR_STATE, "msd_set_trial_occ has not been called");
+  build_derived(s);
+}
+
+void clear_flags(msd_system* s) {
+  hip_check(hipMemsetAsync(s->flag, 0, sizeof(int) * s->NW, s->st), "memset");
+}
+
+void check_flags(msd_system* s, const char* what) {
+  std::vector<int> f(s->NW);
+  hip_check(hipMemcpyAsync(f.data(), s->flag, sizeof(int) * s->NW, hipMemcpyDeviceToHost, s->st),
+            "flags");
+  s->sync();
+  for (int w = 0; w < s->NW; ++w)
+    if (f[w])
+      fail(MSD_ERR_SINGULAR, std::string(what) + ": walker " + std::to_string(w) +
+                                 " has a singular reference block or zero trial overlap");
+}
+
+// A1 + A3: T, log det A, per-string dets/adjugates (minors if requested),
+// Obar and log <Psi_T|Phi> into `logo_out`.
+void run_overlap(msd_system* s, bool minors, cd* logo_out) {
+  for (int sp = 0; sp < 2; ++sp)
+    s->timed(ST_REF, [&] {
+      msd::launch_ref_inverse(s->phi, s->M, s->Ntot, s->NW, s->ds[sp], s->sw[sp].T,
+                              s->sw[sp].logdetA, s->flag, s->st);
+    });
+  for (int sp = 0; sp < 2; ++sp)
+    s->timed(ST_STR, [&] {
+      msd::launch_strings(s->ds[sp], s->sw[sp].T, s->NW, minors, s->sw[sp].d, s->sw[sp].adj,
+                          s->sw[sp].m2, s->st);
+    });
+  s->timed(ST_OVLP, [&] {
+    msd::launch_ovlp_partial(s->ND, s->NW, s->ds[0].det_s, s->ds[1].det_s, s->det_c,
+                             s->sw[0].d, s->ds[0].U, s->sw[1].d, s->ds[1].U, s->opart,
+                             s->n_ochunks, s->ochunk, s->st);
+    msd::launch_ovlp_final(s->NW, s->opart, s->n_ochunks, s->na ? s->sw[0].logdetA : nullptr,
+                           s->nb ? s->sw[1].logdetA : nullptr, s->obar, logo_out, s->flag,
+                           s->st);
+  });
+  s->check_launch("overlap");
+}
+
+// A4 + A5: CI weights, CI matrices, Green's rows, force bias into s->xbar.
+void run_green_fb(msd_system* s, double dt) {
+  for (int sp = 0; sp < 2; ++sp) {
+    const int o = 1 - sp;
+    s->timed(ST_CIW, [&] {
+      msd::launch_ci_weights(s->ds[sp], s->ds[o].det_s, s->det_c, s->sw[o].d, s->ds[o].U, s->NW,
+                             s->sw[sp].B, s->st);
+    });
+  }
+  for (int sp = 0; sp < 2; ++sp)
+    s->timed(ST_CIM, [&] {
+      msd::launch_ci_matrix(s->ds[sp], s->NW, s->sw[sp].adj, s->sw[sp].B, s->sw[sp].C, s->st);
+    });
+  for (int sp = 0; sp < 2; ++sp)
+    s->timed(ST_GREEN, [&] {
+      msd::launch_green(s->ds[sp], s->M, s->NW, s->sw[sp].T, s->sw[sp].C, s->obar, s->h1,
+                        s->sw[sp].G, s->onebody + (size_t)sp * s->NW, s->st);
+    });
+  s->timed(ST_GREEN, [&] {
+    msd::launch_green_sum(s->M, s->NW, s->P_all, s->rmap[0], s->rmap[1], s->ds[0].P,
+                          s->ds[1].P, s->sw[0].G, s->sw[1].G, s->Gp, s->st);
+  });
+  s->timed(ST_FB_GEMM, [&] {
+    msd::GemmArgs g;
+    g.M = s->NG;
+    g.N = 2 * s->NW;
+    g.K = s->P_all * s->M;
+    g.A = s->L_rows;
+    g.lda = g.K;
+    g.a_kmaj = true;
+    g.B = s->Gp;
+    g.ldb = g.K;
+    g.b_kmaj = true;
+    g.C = s->xraw;
+    g.ldc = 2 * s->NW;
+    msd::launch_gemm(g, s->st);
+    msd::launch_xbar(s->NW, s->NG, s->xraw, std::sqrt(dt), s->xbar, s->st);
+  });
+  s->check_launch("green/force bias");
+}
+
+// A6 + A7: local energies into s->eloc (needs run_overlap with minors and run_green_fb).
+void run_energy(msd_system* s) {
+  alloc_energy(s);
+  const msd::DevSpin& A = s->ds[0];
+  const msd::DevSpin& B = s->ds[1];
+  s->timed(ST_COEF, [&] {
+    msd::launch_pair_coef(s->dp, s->NW, s->det_c, s->sw[0].adj, A.A, s->sw[1].adj, B.A,
+                          s->coefAB, s->st);
+    for (int sp = 0; sp < 2; ++sp)
+      msd::launch_minor_coef(s->ds[sp], s->NW, s->sw[sp].B, s->ds[sp].U, s->sw[sp].m2,
+                             s->coef2[sp], s->st);
+  });
+  for (int w0 = 0; w0 < s->NW; w0 += s->WT) {
+    const int wt = std::min(s->WT, s->NW - w0);
+    for (int sp = 0; sp < 2; ++sp) {
+      const msd::DevSpin& D = s->ds[sp];
+      if (D.N == 0) continue;
+      s->timed(ST_LT_GEMM, [&] {
+        msd::GemmArgs g;
+        g.M = s->NG * D.P;
+        g.N = 2 * wt * D.N;
+        g.K = s->M;
+        g.A = s->L_lt[sp];
+        g.lda = s->M;
+        g.a_kmaj = true;
+        g.B = reinterpret_cast<const double*>(s->sw[sp].T + (size_t)w0 * D.N);
+        g.ldb = 2 * (int64_t)s->NW * D.N;
+        g.b_kmaj = false;
+        g.C = reinterpret_cast<double*>(s->LT[sp]);
+        g.ldc = 2 * (int64_t)wt * D.N;
+        msd::launch_gemm(g, s->st);
+      });
+    }
+    s->timed(ST_LAMBDA, [&] {
+      msd::launch_lambda(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, s->sw[0].T, s->sw[1].T,
+                         s->LT[0], s->LT[1], s->Lam[0], s->Lam[1], s->v0, s->ex0, s->ZWp[0],
+                         s->ZWp[1], s->st);
+    });
+    s->timed(ST_EGAMMA, [&] {
+      msd::launch_energy_gamma(A, B, s->dp, s->NW, w0, wt, s->NG, s->ge_chunk, s->Lam[0],
+                               s->Lam[1], s->coefAB, s->coef2[0], s->coef2[1], s->epart, s->st);
+    });
+    s->timed(ST_EFINAL, [&] {
+      msd::launch_energy_final(A, B, s->NW, w0, wt, s->NG, s->n_lchunks, s->n_echunks, s->obar,
+                               s->v0, s->ex0, s->ZWp[0], s->ZWp[1], s->sw[0].C, s->sw[1].C,
+                               s->epart, s->onebody, s->onebody + s->NW, s->e0, s->eloc,
+                               s->st);
+    });
+  }
+  s->check_launch("energy");
+}
+
+void measure_impl(msd_system* s, double dt, bool want_e) {
+  need_ready(s);
+  if (!s->have_walkers) fail(MSD_ERR_STATE, "walkers have not been set");
+  if (!(dt >= 0.0) || !std::isfinite(dt)) fail(MSD_ERR_ARG, "dt must be finite and >= 0");
+  if (want_e && s->tt.max_k() > msd::KMAX) fail(MSD_ERR_UNSUPPORTED, "excitation order too high");
+  clear_flags(s);
+  run_overlap(s, want_e, s->logo_tmp);
+  run_green_fb(s, dt);
+  if (want_e) run_energy(s);
+}
+
+void ensure_b1(msd_system* s, double dt) {
+  if (s->B1_dt == dt) return;
+  const int M = s->M;
+  std::vector<double> a((size_t)M * M);
+  for (size_t i = 0; i < a.size(); ++i) a[i] = -0.5 * dt * (s->h1_host[i] - 0.5 * s->sumll_host[i]);
+  std::vector<double> b1 = expm_host(a, M);
+  hip_check(hipMemcpyAsync(s->B1, b1.data(), b1.size() * sizeof(double), hipMemcpyHostToDevice,
+                           s->st),
+            "B1 upload");
+  s->sync();
+  s->B1_dt = dt;
+}
+
+void one_body_gemm(msd_system* s, const cd* in, cd* out, const int* mask) {
+  msd::GemmArgs g;
+  g.M = s->M;
+  g.N = 2 * s->Ntot;
+  g.K = s->M;
+  g.batch = s->NW;
+  g.A = s->B1;
+  g.lda = s->M;
+  g.strideA = 0;
+  g.a_kmaj = true;
+  g.B = reinterpret_cast<const double*>(in);
+  g.ldb = 2 * s->Ntot;
+  g.strideB = 2 * (int64_t)s->M * s->Ntot;
+  g.b_kmaj = false;
+  g.C = reinterpret_cast<double*>(out);
+  g.ldc = 2 * s->Ntot;
+  g.strideC = 2 * (int64_t)s->M * s->Ntot;
+  g.mask = mask;
+  msd::launch_gemm(g, s->st);
+}
+
+void propagate_impl(msd_system* s, const double* fields_dev, double dt, double e_shift,
+                    int n_steps) {
+  need_ready(s);
+  if (!s->have_walkers) fail(MSD_ERR_STATE, "walkers have not been set");
+  if (!(dt > 0.0) || !std::isfinite(dt)) fail(MSD_ERR_ARG, "dt must be finite and > 0");
+  if (!std::isfinite(e_shift)) fail(MSD_ERR_ARG, "e_shift must be finite");
+  if (n_steps < 0) fail(MSD_ERR_ARG, "n_steps must be >= 0");
+  ensure_b1(s, dt);
+  const int NW = s->NW, NG = s->NG, M = s->M, Ntot = s->Ntot;
+  const size_t mm = (size_t)M * M;
+  for (int step = 0; step < n_steps; ++step) {
+    const double* x = fields_dev + (size_t)step * NW * NG;
+    clear_flags(s);
+    msd::launch_frozen_mask(NW, s->weights, s->mask, s->st);
+    run_overlap(s, false, s->logo_tmp);
+    run_green_fb(s, dt);
+    s->timed(ST_VHS_GEMM, [&] {
+      msd::launch_vhs_prep(NW, NG, x, s->xbar, std::sqrt(dt), s->weights, s->Y, s->st);
+      msd::GemmArgs g;
+      g.M = 2 * NW;
+      g.N = (int)mm;
+      g.K = NG;
+      g.A = s->Y;
+      g.lda = NG;
+      g.a_kmaj = true;
+      g.B = s->L;
+      g.ldb = (int64_t)mm;
+      g.b_kmaj = false;
+      g.C = s->VHS;
+      g.ldc = (int64_t)mm;
+      msd::launch_gemm(g, s->st);
+    });
+    s->timed(ST_B1, [&] { one_body_gemm(s, s->phi, s->term[0], s->mask); });
+    s->timed(ST_TAYLOR, [&] {
+      hip_check(hipMemcpyAsync(s->acc, s->term[0], sizeof(cd) * NW * M * Ntot,
+                               hipMemcpyDeviceToDevice, s->st),
+                "copy");
+      for (int n = 1; n <= s->o.n_taylor; ++n) {
+        msd::GemmArgs g;
+        g.M = M;
+        g.N = 2 * Ntot;
+        g.K = M;
+        g.batch = NW;
+        g.A = s->VHS;
+        g.lda = M;
+        g.strideA = 2 * (int64_t)mm;
+        g.a_imag_off = (int64_t)mm;
+        g.a_kmaj = true;
+        g.B = reinterpret_cast<const double*>(s->term[(n - 1) & 1]);
+        g.ldb = 2 * Ntot;
+        g.strideB = 2 * (int64_t)M * Ntot;
+        g.b_kmaj = false;
+        g.C = reinterpret_cast<double*>(s->term[n & 1]);
+        g.ldc = 2 * Ntot;
+        g.strideC = 2 * (int64_t)M * Ntot;
+        g.Acc = reinterpret_cast<double*>(s->acc);
+        g.alpha = 1.0 / n;
+        g.cplx = true;
+        g.mask = s->mask;
+        msd::launch_gemm(g, s->st);
+      }
+    });
+    s->timed(ST_B1, [&] { one_body_gemm(s, s->acc, s->phi, s->mask); });
+    run_overlap(s, false, s->logo_tmp);
+    s->timed(ST_WEIGHTS, [&] {
+      msd::launch_weights(NW, NG, x, s->xbar, s->logo_tmp, s->logo, s->weights, dt, e_shift,
+                          s->st);
+    });
+    s->steps_done++;
+    if (s->o.stabilize_freq > 0 && s->steps_done % s->o.stabilize_freq == 0) {
+      s->timed(ST_QR, [&] {
+        msd::launch_qr(s->phi, M, Ntot, NW, s->na, 0, s->mask, s->logo, s->st);
+        msd::launch_qr(s->phi, M, Ntot, NW, s->nb, s->na, s->mask, s->logo, s->st);
+      });
+    }
+    s->check_launch("propagate");
+  }
+}
+
+void set_walkers_impl(msd_system* s, const cd* pa_dev, const cd* pb_dev, const double* w_dev) {
+  if (!s->have_trial || !s->have_ham)
+    fail(MSD_ERR_STATE, "msd_set_hamiltonian and msd_set_trial_occ must precede msd_set_walkers");
+  msd::launch_copy_walkers(s->NW, s->M, s->Ntot, s->na, s->nb, pa_dev, pb_dev, s->phi, true,
+                           nullptr, nullptr, s->st);
+  if (w_dev) {
+    hip_check(hipMemcpyAsync(s->weights, w_dev, sizeof(double) * s->NW, hipMemcpyDeviceToDevice,
+                             s->st),
+              "weights");
+  } else {
+    std::vector<double> ones(s->NW, 1.0);
+    hip_check(hipMemcpyAsync(s->weights, ones.data(), sizeof(double) * s->NW,
+                             hipMemcpyHostToDevice, s->st),
+              "weights");
+    s->sync();
+  }
+  s->have_walkers = true;
+  s->steps_done = 0;
+  need_ready(s);
+  clear_flags(s);
+  run_overlap(s, false, s->logo);
+  check_flags(s, "msd_set_walkers");
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+
+extern "C" {
+
+const char* msd_status_string(msd_status s) {
+  switch (s) {
+    case MSD_OK: return "ok";
+    case MSD_ERR_ARG: return "invalid argument";
+    case MSD_ERR_SHAPE: return "inconsistent dimensions";
+    case MSD_ERR_TRIAL: return "invalid trial wavefunction";
+    case MSD_ERR_SINGULAR: return "singular reference overlap";
+    case MSD_ERR_DEVICE: return "device error";
+    case MSD_ERR_OOM: return "out of memory";
+    case MSD_ERR_STATE: return "call order";
+    case MSD_ERR_UNSUPPORTED: return "unsupported shape";
+  }
+  return "unknown status";
+}
+
+const char* msd_last_error(const msd_system* sys) {
+  return sys ? sys->err.c_str() : g_err.c_str();
+}
+
+msd_status msd_default_options(msd_options* o) {
+  if (!o) return MSD_ERR_ARG;
+  std::memset(o, 0, sizeof(*o));
+  o->n_taylor = 6;
+  o->stabilize_freq = 5;
+  o->timing = 0;
+  return MSD_OK;
+}
+
+msd_status msd_create(const msd_dims* d, const msd_options* o, int32_t device, void* hip_stream,
+                      msd_system** out) {
+  msd_system* sys = nullptr;
+  API_BEGIN
+  if (!d || !out) fail(MSD_ERR_ARG, "null argument");
+  *out = nullptr;
+  if (d->M <= 0 || d->n_alpha < 0 || d->n_beta < 0 || d->n_alpha + d->n_beta <= 0 ||
+      d->n_chol <= 0 || d->n_walkers <= 0 || d->n_det <= 0)
+    fail(MSD_ERR_SHAPE, "all sizes must be positive");
+  if (d->n_alpha > d->M || d->n_beta > d->M) fail(MSD_ERR_SHAPE, "more electrons than orbitals");
+  if (d->n_alpha > msd::NMAX_LDS || d->n_beta > msd::NMAX_LDS)
+    fail(MSD_ERR_UNSUPPORTED, "at most 64 electrons per spin");
+  msd_options opt;
+  msd_default_options(&opt);
+  if (o) opt = *o;
+  if (opt.n_taylor < 0 || opt.n_taylor > 32 || opt.stabilize_freq < 0)
+    fail(MSD_ERR_ARG, "invalid options");
+  sys = new msd_system();
+  sys->dev = device;
+  sys->st = static_cast<hipStream_t>(hip_stream);
+  sys->d = *d;
+  sys->o = opt;
+  sys->M = d->M;
+  sys->na = d->n_alpha;
+  sys->nb = d->n_beta;
+  sys->Ntot = d->n_alpha + d->n_beta;
+  sys->NG = d->n_chol;
+  sys->NW = d->n_walkers;
+  sys->ND = d->n_det;
+  try {
+    set_device(sys);
+    msd::init_wick_attributes();
+    msd::init_prop_attributes();
+    Arena& A = sys->base;
+    const int M = sys->M, NW = sys->NW, NG = sys->NG, Ntot = sys->Ntot;
+    sys->phi = A.get<cd>((size_t)NW * M * Ntot);
+    sys->weights = A.get<double>(NW);
+    sys->logo = A.get<cd>(NW);
+    sys->logo_tmp = A.get<cd>(NW);
+    sys->obar = A.get<cd>(NW);
+    sys->flag = A.get<int>(NW);
+    sys->mask = A.get<int>(NW);
+    sys->xraw = A.get<double>((size_t)NG * 2 * NW);
+    sys->xbar = A.get<cd>((size_t)NW * NG);
+    sys->eloc = A.get<cd>(NW);
+    sys->onebody = A.get<cd>(2 * (size_t)NW);
+    sys->Y = A.get<double>((size_t)2 * NW * NG);
+    sys->VHS = A.get<double>((size_t)2 * NW * M * M);
+    sys->term[0] = A.get<cd>((size_t)NW * M * Ntot);
+    sys->term[1] = A.get<cd>((size_t)NW * M * Ntot);
+    sys->acc = A.get<cd>((size_t)NW * M * Ntot);
+    sys->fields = A.get<double>((size_t)NW * NG);
+    sys->L = A.get<double>((size_t)NG * M * M);
+    sys->h1 = A.get<double>((size_t)M * M);
+    sys->B1 = A.get<double>((size_t)M * M);
+    for (int sp = 0; sp < 2; ++sp) {
+      const int N = sp ? sys->nb : sys->na;
+      sys->sw[sp].T = A.get<cd>((size_t)M * NW * std::max(N, 1));
+      sys->sw[sp].logdetA = A.get<cd>(NW);
+    }
+    hip_check(hipMemsetAsync(sys->flag, 0, sizeof(int) * NW, sys->st), "memset");
+    hip_check(hipMemsetAsync(sys->sw[0].logdetA, 0, sizeof(cd) * NW, sys->st), "memset");
+    hip_check(hipMemsetAsync(sys->sw[1].logdetA, 0, sizeof(cd) * NW, sys->st), "memset");
+    sys->sync();
+  } catch (...) {
+    sys->base.release();
+    delete sys;
+    sys = nullptr;
+    throw;
+  }
+  *out = sys;
+  API_END(static_cast<msd_system*>(nullptr))
+}
+
+void msd_destroy(msd_system* sys) {
+  if (!sys) return;
+  (void)hipSetDevice(sys->dev);
+  (void)hipStreamSynchronize(sys->st);
+  for (auto& p : sys->pending) {
+    (void)hipEventDestroy(p.second.first);
+    (void)hipEventDestroy(p.second.second);
+  }
+  for (hipEvent_t e : sys->pool) (void)hipEventDestroy(e);
+  sys->energy_mem.release();
+  sys->trial_mem.release();
+  sys->ham_mem.release();
+  sys->base.release();
+  delete sys;
+}
+
+msd_status msd_set_hamiltonian(msd_system* sys, const double* h1, const double* chol, double e0) {
+  API_BEGIN
+  if (!sys || !h1 || !chol) fail(MSD_ERR_ARG, "null argument");
+  set_device(sys);
+  const int M = sys->M, NG = sys->NG;
+  if (!std::isfinite(e0)) fail(MSD_ERR_ARG, "e0 must be finite");
+  for (int p = 0; p < M; ++p)
+    for (int q = 0; q < M; ++q) {
+      const double a = h1[(size_t)p * M + q], b = h1[(size_t)q * M + p];
+      if (!std::isfinite(a) || std::fabs(a - b) > 1e-12 * std::max(1.0, std::fabs(a)))
+        fail(MSD_ERR_ARG, "h1 not finite/symmetric at (" + std::to_string(p) + "," +
+                              std::to_string(q) + ")");
+    }
+  for (int g = 0; g < NG; ++g) {
+    const double* Lg = chol + (size_t)g * M * M;
+    for (int p = 0; p < M; ++p)
+      for (int q = p; q < M; ++q) {
+        const double a = Lg[(size_t)p * M + q], b = Lg[(size_t)q * M + p];
+        if (!std::isfinite(a) || std::fabs(a - b) > 1e-12 * std::max(1.0, std::fabs(a)))
+          fail(MSD_ERR_ARG, "Cholesky vector " + std::to_string(g) + " not finite/symmetric at (" +
+                                std::to_string(p) + "," + std::to_string(q) + ")");
+      }
+  }
+  hip_check(hipMemcpyAsync(sys->L, chol, sizeof(double) * NG * M * M, hipMemcpyHostToDevice,
+                           sys->st),
+            "upload L");
+  hip_check(hipMemcpyAsync(sys->h1, h1, sizeof(double) * M * M, hipMemcpyHostToDevice, sys->st),
+            "upload h1");
+  sys->h1_host.assign(h1, h1 + (size_t)M * M);
+  sys->e0 = e0;
+  std::vector<double> tmp((size_t)M * M);
+  double* dtmp = nullptr;
+  hip_check(hipMalloc(&dtmp, sizeof(double) * M * M), "hipMalloc");
+  msd::launch_sum_ll(sys->L, NG, M, dtmp, sys->st);
+  hipError_t e1 = hipMemcpyAsync(tmp.data(), dtmp, sizeof(double) * M * M, hipMemcpyDeviceToHost,
+                                 sys->st);
+  hipError_t e2 = hipStreamSynchronize(sys->st);
+  (void)hipFree(dtmp);
+  hip_check(e1, "sum LL");
+  hip_check(e2, "sum LL");
+  sys->sumll_host = tmp;
+  sys->B1_dt = NAN;
+  sys->have_ham = true;
+  sys->derived_ok = false;
+  if (sys->have_trial) build_derived(sys);
+  API_END(sys)
+}
+
+msd_status msd_set_trial_occ(msd_system* sys, const double* ci, const int32_t* occ_a,
+                             const int32_t* occ_b) {
+  API_BEGIN
+  if (!sys || !ci || (!occ_a && sys->na) || (!occ_b && sys->nb)) fail(MSD_ERR_ARG, "null argument");
+  set_device(sys);
+  for (int64_t i = 0; i < 2 * sys->ND; ++i)
+    if (!std::isfinite(ci[i])) fail(MSD_ERR_ARG, "CI coefficient " + std::to_string(i / 2) + " not finite");
+  msd::TrialTables tt;
+  std::vector<int32_t> dummy;
+  std::string e = msd::build_trial(sys->M, sys->na, sys->nb, sys->ND, ci,
+                                   occ_a ? occ_a : dummy.data(), occ_b ? occ_b : dummy.data(), &tt);
+  if (!e.empty()) fail(MSD_ERR_TRIAL, e);
+  // capacity checks of the LDS kernels
+  for (int sp = 0; sp < 2; ++sp) {
+    const msd::SpinTable& S = tt.s[sp];
+    const size_t X = (size_t)S.nv() * S.no();
+    if (X > 256 * 4)
+      fail(MSD_ERR_UNSUPPORTED, "excitation window too large (n_vir_act * n_occ_act > 1024)");
+    const size_t green_lds = (X + (size_t)S.nv() * S.N + (size_t)S.nv() * 64) * sizeof(cd);
+    if (green_lds > 140 * 1024) fail(MSD_ERR_UNSUPPORTED, "excitation window too large for LDS");
+  }
+  {
+    size_t words = 0, lf = 0;
+    for (int sp = 0; sp < 2; ++sp) {
+      const msd::SpinTable& S = tt.s[sp];
+      words += (size_t)S.N * S.N + 2 * (size_t)S.nv() * S.N;
+      lf = std::max(lf, (size_t)S.nv() * S.N);
+    }
+    if ((words + lf) * sizeof(cd) > 140 * 1024)
+      fail(MSD_ERR_UNSUPPORTED, "Cholesky contraction tile exceeds LDS");
+  }
+  free_energy(sys);
+  sys->trial_mem.release();
+  sys->tt = std::move(tt);
+  Arena& T = sys->trial_mem;
+  hipStream_t st = sys->st;
+  const int M = sys->M, NW = sys->NW, NG = sys->NG;
+  std::vector<int> rows_all;
+  for (int sp = 0; sp < 2; ++sp) {
+    const msd::SpinTable& S = sys->tt.s[sp];
+    msd::DevSpin& D = sys->ds[sp];
+    D = msd::DevSpin();
+    D.N = S.N;
+    D.U = S.U;
+    D.nv = S.nv();
+    D.no = S.no();
+    D.P = S.N + S.nv();
+    D.col0 = sp ? sys->na : 0;
+    D.A = S.adj_off[S.U];
+    D.M2 = S.m2_off[S.U];
+    D.n_minor = S.n_minor;
+    std::vector<int> rows(S.ref);
+    rows.insert(rows.end(), S.vir_act.begin(), S.vir_act.end());
+    rows_all.insert(rows_all.end(), rows.begin(), rows.end());
+    D.ref = T.upload(S.ref, st);
+    D.vir = T.upload(S.vir_act, st);
+    D.oslot = T.upload(S.occ_slot, st);
+    D.rows = T.upload(rows, st);
+    D.k = T.upload(S.k, st);
+    D.hslot = T.upload(S.hslot, st);
+    D.hwin = T.upload(S.hwin, st);
+    D.part = T.upload(S.part, st);
+    D.pwin = T.upload(S.pwin, st);
+    D.adj_off = T.upload(S.adj_off, st);
+    D.m2_off = T.upload(S.m2_off, st);
+    D.bw_ptr = T.upload(S.bw_ptr, st);
+    D.bw_det = T.upload(S.bw_det, st);
+    D.c_ptr = T.upload(S.c_ptr, st);
+    D.c_adj = T.upload(S.c_adj, st);
+    D.c_str = T.upload(S.c_str, st);
+    D.mn_idx = T.upload(S.mn_idx, st);
+    D.mn_ptr = T.upload(S.mn_ptr, st);
+    D.mn_str = T.upload(S.mn_str, st);
+    D.mn_m2 = T.upload(S.mn_m2, st);
+    D.mn_sgn = T.upload(S.mn_sgn, st);
+    D.det_s = T.upload(sys->tt.det_s[sp], st);
+    for (int k = 0; k < msd::KMAX + 2; ++k) D.bucket[k] = S.bucket[k];
+    msd::SpinWork& W = sys->sw[sp];
+    W.d = T.get<cd>((size_t)NW * S.U);
+    W.adj = T.get<cd>((size_t)NW * std::max(D.A, 1));
+    W.m2 = T.get<cd>((size_t)NW * std::max(D.M2, 1));
+    W.B = T.get<cd>((size_t)NW * S.U);
+    W.C = T.get<cd>((size_t)NW * std::max(D.nv * D.no, 1));
+    W.G = T.get<cd>((size_t)NW * D.P * M);
+    sys->L_lt[sp] = T.get<double>((size_t)NG * D.P * M);
+  }
+  std::sort(rows_all.begin(), rows_all.end());
+  rows_all.erase(std::unique(rows_all.begin(), rows_all.end()), rows_all.end());
+  sys->P_all = (int)rows_all.size();
+  for (int sp = 0; sp < 2; ++sp) {
+    const msd::SpinTable& S = sys->tt.s[sp];
+    std::vector<int> rm(sys->P_all, -1);
+    for (int r = 0; r < sys->P_all; ++r) {
+      const int orb = rows_all[r];
+      for (int j = 0; j < S.N; ++j)
+        if (S.ref[j] == orb) rm[r] = j;
+      for (int a = 0; a < S.nv(); ++a)
+        if (S.vir_act[a] == orb) rm[r] = S.N + a;
+    }
+    sys->rmap[sp] = T.upload(rm, st);
+  }
+  sys->rows_all_dev = T.upload(rows_all, st);
+  sys->L_rows = T.get<double>((size_t)NG * sys->P_all * M);
+  sys->Gp = T.get<double>((size_t)2 * NW * sys->P_all * M);
+  sys->dp.n_pair = sys->tt.n_pair;
+  sys->dp.x = T.upload(sys->tt.pr_x, st);
+  sys->dp.y = T.upload(sys->tt.pr_y, st);
+  sys->dp.ptr = T.upload(sys->tt.pr_ptr, st);
+  sys->dp.det = T.upload(sys->tt.pr_det, st);
+  sys->dp.fa = T.upload(sys->tt.pr_fa, st);
+  sys->dp.fb = T.upload(sys->tt.pr_fb, st);
+  sys->det_c = reinterpret_cast<cd*>(T.upload(sys->tt.det_c, st));
+  sys->n_ochunks = (int)((sys->ND + sys->ochunk - 1) / sys->ochunk);
+  sys->opart = T.get<cd>((size_t)NW * sys->n_ochunks);
+  sys->derived_ok = false;
+  sys->sync();
+  sys->have_trial = true;
+  sys->have_walkers = false;
+  if (sys->have_ham) build_derived(sys);
+  API_END(sys)
+}
+
+
+static void copy_out(msd_system* s, void* host, const void* dev, size_t bytes) {
+  if (!host) return;
+  hip_check(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, s->st), "download");
+}
+
+static void copy_dd(msd_system* s, void* dst, const void* src, size_t bytes) {
+  if (!dst) return;
+  hip_check(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s->st), "copy");
+}
+
+msd_status msd_set_walkers(msd_system* sys, const double* phi_a, const double* phi_b,
+                           const double* weights) {
+  API_BEGIN
+  if (!sys || (!phi_a && sys->na) || (!phi_b && sys->nb)) fail(MSD_ERR_ARG, "null argument");
+  set_device(sys);
+  const size_t na = (size_t)sys->NW * sys->M * sys->na, nb = (size_t)sys->NW * sys->M * sys->nb;
+  for (size_t i = 0; i < 2 * na; ++i)
+    if (!std::isfinite(phi_a[i])) fail(MSD_ERR_ARG, "phi_a not finite at " + std::to_string(i / 2));
+  for (size_t i = 0; i < 2 * nb; ++i)
+    if (!std::isfinite(phi_b[i])) fail(MSD_ERR_ARG, "phi_b not finite at " + std::to_string(i / 2));
+  if (weights)
+    for (int w = 0; w < sys->NW; ++w)
+      if (!std::isfinite(weights[w]) || weights[w] < 0)
+        fail(MSD_ERR_ARG, "weight " + std::to_string(w) + " not finite and non-negative");
+  // stage through the propagation buffers (same capacity: NW*M*Ntot complex)
+  cd* da = sys->term[0];
+  cd* db = sys->term[1];
+  if (na) hip_check(hipMemcpyAsync(da, phi_a, na * sizeof(cd), hipMemcpyHostToDevice, sys->st), "upload");
+  if (nb) hip_check(hipMemcpyAsync(db, phi_b, nb * sizeof(cd), hipMemcpyHostToDevice, sys->st), "upload");
+  double* dw = nullptr;
+  if (weights) {
+    dw = sys->fields;
+    hip_check(hipMemcpyAsync(dw, weights, sizeof(double) * sys->NW, hipMemcpyHostToDevice, sys->st),
+              "upload");
+  }
+  set_walkers_impl(sys, da, db, dw);
+  API_END(sys)
+}
+
+msd_status msd_set_walkers_dev(msd_system* sys, const double* phi_a, const double* phi_b,
+                               const double* weights) {
+  API_BEGIN
+  if (!sys || (!phi_a && sys->na) || (!phi_b && sys->nb)) fail(MSD_ERR_ARG, "null argument");
+  set_device(sys);
+  const size_t na = (size_t)sys->NW * sys->M * sys->na, nb = (size_t)sys->NW * sys->M * sys->nb;
+  // copy first: the caller's buffers may alias nothing of ours, but the
+  // packing kernel reads them while writing the walker matrix
+  cd* da = sys->term[0];
+  cd* db = sys->term[1];
+  copy_dd(sys, da, phi_a, na * sizeof(cd));
+  copy_dd(sys, db, phi_b, nb * sizeof(cd));
+  double* dw = nullptr;
+  if (weights) {
+    dw = sys->fields;
+    copy_dd(sys, dw, weights, sizeof(double) * sys->NW);
+  }
+  set_walkers_impl(sys, da, db, dw);
+  API_END(sys)
+}
+
+msd_status msd_get_walkers(msd_system* sys, double* phi_a, double* phi_b, double* weights,
+                           double* log_ovlp) {
+  API_BEGIN
+  if (!sys) fail(MSD_ERR_ARG, "null argument");
+  if (!sys->have_walkers) fail(MSD_ERR_STATE, "walkers have not been set");
+  set_device(sys);
+  const size_t na = (size_t)sys->NW * sys->M * sys->na, nb = (size_t)sys->NW * sys->M * sys->nb;
+  msd::launch_copy_walkers(sys->NW, sys->M, sys->Ntot, sys->na, sys->nb, nullptr, nullptr, sys->phi,
+                           false, sys->term[0], sys->term[1], sys->st);
+  copy_out(sys, phi_a, sys->term[0], na * sizeof(cd));
+  copy_out(sys, phi_b, sys->term[1], nb * sizeof(cd));
+  copy_out(sys, weights, sys->weights, sizeof(double) * sys->NW);
+  copy_out(sys, log_ovlp, sys->logo, sizeof(cd) * sys->NW);
+  sys->sync();
+  API_END(sys)
+}
+
+msd_status msd_measure(msd_system* sys, double dt, double* log_ovlp, double* force_bias,
+                       double* e_loc) {
+  API_BEGIN
+  if (!sys) fail(MSD_ERR_ARG, "null argument");
+  set_device(sys);
+  measure_impl(sys, dt, e_loc != nullptr);
+  check_flags(sys, "msd_measure");
+  copy_out(sys, log_ovlp, sys->logo_tmp, sizeof(cd) * sys->NW);
+  copy_out(sys, force_bias, sys->xbar, sizeof(cd) * sys->NW * sys->NG);
+  copy_out(sys, e_loc, sys->eloc, sizeof(cd) * sys->NW);
+  sys->sync();
+  API_END(sys)
+}
+
+msd_status msd_measure_dev(msd_system* sys, double dt, double* log_ovlp, double* force_bias,
+                           double* e_loc) {
+  API_BEGIN
+  if (!sys) fail(MSD_ERR_ARG, "null argument");
+  set_device(sys);
+  measure_impl(sys, dt, e_loc != nullptr);
+  copy_dd(sys, log_ovlp, sys->logo_tmp, sizeof(cd) * sys->NW);
+  copy_dd(sys, force_bias, sys->xbar, sizeof(cd) * sys->NW * sys->NG);
+  copy_dd(sys, e_loc, sys->eloc, sizeof(cd) * sys->NW);
+  API_END(sys)
+}
+
+msd_status msd_propagate(msd_system* sys, const double* fields, double dt, double e_shift,
+                         int32_t n_steps) {
+  API_BEGIN
+  if (!sys || (!fields && n_steps > 0)) fail(MSD_ERR_ARG, "null argument");
+  set_device(sys);
+  const size_t per = (size_t)sys->NW * sys->NG;
+  for (size_t i = 0; i < per * (size_t)std::max(n_steps, 0); ++i)
+    if (!std::isfinite(fields[i])) fail(MSD_ERR_ARG, "field " + std::to_string(i) + " not finite");
+  for (int step = 0; step < n_steps; ++step) {
+    hip_check(hipMemcpyAsync(sys->fields, fields + step * per, per * sizeof(double),
+                             hipMemcpyHostToDevice, sys->st),
+              "upload fields");
+    propagate_impl(sys, sys->fields, dt, e_shift, 1);
+  }
+  sys->sync();
+  API_END(sys)
+}
+
+msd_status msd_propagate_dev(msd_system* sys, const double* fields, double dt, double e_shift,
+                             int32_t n_steps) {
+  API_BEGIN
+  if (!sys || (!fields && n_steps > 0)) fail(MSD_ERR_ARG, "null argument");
+  set_device(sys);
+  propagate_impl(sys, fields, dt, e_shift, n_steps);
+  API_END(sys)
+}
+
+msd_status msd_get_green(msd_system* sys, int32_t walker, double* g_a, double* g_b) {
+  API_BEGIN
+  if (!sys) fail(MSD_ERR_ARG, "null argument");
+  if (walker < 0 || walker >= sys->NW) fail(MSD_ERR_ARG, "walker index out of range");
+  if (!sys->have_trial) fail(MSD_ERR_STATE, "no trial");
+  set_device(sys);
+  const int M = sys->M;
+  double* outs[2] = {g_a, g_b};
+  for (int sp = 0; sp < 2; ++sp) {
+    if (!outs[sp]) continue;
+    const msd::SpinTable& S = sys->tt.s[sp];
+    const int P = S.N + S.nv();
+    std::vector<cd> rows((size_t)P * M);
+    hip_check(hipMemcpyAsync(rows.data(), sys->sw[sp].G + (size_t)walker * P * M,
+                             rows.size() * sizeof(cd), hipMemcpyDeviceToHost, sys->st),
+              "download");
+    sys->sync();
+    std::vector<int> orb(S.ref);
+    orb.insert(orb.end(), S.vir_act.begin(), S.vir_act.end());
+    cd* out = reinterpret_cast<cd*>(outs[sp]);
+    std::fill(out, out + (size_t)M * M, cd{0.0, 0.0});
+    for (int r = 0; r < P; ++r)
+      for (int q = 0; q < M; ++q) out[(size_t)orb[r] * M + q] = rows[(size_t)r * M + q];
+  }
+  API_END(sys)
+}
+
+msd_status msd_get_timings(msd_system* sys, int32_t max_stages, const char** names, double* ms,
+                           int64_t* counts, int32_t* n_stages) {
+  API_BEGIN
+  if (!sys || !n_stages) fail(MSD_ERR_ARG, "null argument");
+  set_device(sys);
+  sys->harvest();
+  int n = 0;
+  for (int i = 0; i < ST_COUNT && n < max_stages; ++i, ++n) {
+    if (names) names[n] = kStageNames[i];
+    if (ms) ms[n] = sys->stage_ms[i];
+    if (counts) counts[n] = sys->stage_n[i];
+  }
+  *n_stages = n;
+  API_END(sys)
+}
+
+msd_status msd_reset_timings(msd_system* sys) {
+  API_BEGIN
+  if (!sys) fail(MSD_ERR_ARG, "null argument");
+  set_device(sys);
+  sys->harvest();
+  for (int i = 0; i < ST_COUNT; ++i) {
+    sys->stage_ms[i] = 0.0;
+    sys->stage_n[i] = 0;
+  }
+  API_END(sys)
+}
+
+msd_status msd_trial_analyze(int32_t M, int32_t n_alpha, int32_t n_beta, int64_t n_det,
+                             const int32_t* occ_a, const int32_t* occ_b, int32_t* k_a, int32_t* k_b,
+                             int32_t* sign) {
+  msd_system* none = nullptr;
+  API_BEGIN
+  if (!k_a || !k_b || !sign || (!occ_a && n_alpha) || (!occ_b && n_beta))
+    fail(MSD_ERR_ARG, "null argument");
+  if (M <= 0 || n_alpha < 0 || n_beta < 0 || n_alpha > M || n_beta > M)
+    fail(MSD_ERR_SHAPE, "invalid sizes");
+  std::vector<int32_t> dummy(1);
+  std::string e = msd::analyze_trial(M, n_alpha, n_beta, n_det, occ_a ? occ_a : dummy.data(),
+                                     occ_b ? occ_b : dummy.data(), k_a, k_b, sign);
+  if (!e.empty()) fail(MSD_ERR_TRIAL, e);
+  API_END(none)
+}
+
+}  // extern "C"

@@ -1,0 +1,138 @@
+// Launch interfaces of the HIP kernels (device pointers only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+namespace msd {
+
+// ---------------------------------------------------------------- GEMM
+struct GemmArgs {
+  int M = 0, N = 0, K = 0, batch = 1;
+  const double* A = nullptr;
+  const double* B = nullptr;
+  double* C = nullptr;
+  double* Acc = nullptr;        // optional: Acc += result (same layout as C)
+  int64_t lda = 0, ldb = 0, ldc = 0;
+  int64_t strideA = 0, strideB = 0, strideC = 0;
+  int64_t a_imag_off = 0;       // complex mode: offset of the imaginary plane of A
+  const int* mask = nullptr;    // optional per-batch skip mask (0 = skip)
+  double alpha = 1.0, beta = 0.0;
+  bool a_kmaj = true, b_kmaj = false, cplx = false;
+};
+void launch_gemm(const GemmArgs& g, hipStream_t st);
+
+// ---------------------------------------------------------------- device tables
+struct DevSpin {
+  int N = 0, U = 0, nv = 0, no = 0, P = 0;  // P = N + nv (rows R then V_act)
+  int col0 = 0;                              // column offset in the walker matrix
+  int A = 0, M2 = 0;                         // adj / minor entries per walker
+  int n_minor = 0;
+  const int* ref = nullptr;      // [N]
+  const int* vir = nullptr;      // [nv]
+  const int* oslot = nullptr;    // [no]
+  const int* rows = nullptr;     // [P]
+  const int* k = nullptr;        // [U]
+  const int* hslot = nullptr;    // [U*KMAX]
+  const int* hwin = nullptr;
+  const int* part = nullptr;
+  const int* pwin = nullptr;
+  const int* adj_off = nullptr;  // [U+1]
+  const int* m2_off = nullptr;   // [U+1]
+  const int* bw_ptr = nullptr;   // [U+1]
+  const int* bw_det = nullptr;
+  const int* c_ptr = nullptr;    // [nv*no+1]
+  const int* c_adj = nullptr;
+  const int* c_str = nullptr;
+  const int* mn_idx = nullptr;   // [n_minor*4]
+  const int* mn_ptr = nullptr;   // [n_minor+1]
+  const int* mn_str = nullptr;
+  const int* mn_m2 = nullptr;
+  const int* mn_sgn = nullptr;
+  const int* det_s = nullptr;    // [n_det]
+  int bucket[KMAX + 2] = {0};
+};
+
+struct DevPairs {
+  int n_pair = 0;
+  const int* x = nullptr;
+  const int* y = nullptr;
+  const int64_t* ptr = nullptr;
+  const int* det = nullptr;
+  const int* fa = nullptr;
+  const int* fb = nullptr;
+};
+
+// Per-spin walker-batch work arrays.
+struct SpinWork {
+  cd* T = nullptr;        // [M][NW][N]      T = Phi A^{-1}
+  cd* logdetA = nullptr;  // [NW]
+  cd* d = nullptr;        // [NW][U]         det X per string
+  cd* adj = nullptr;      // [NW][A]         adj X per string
+  cd* m2 = nullptr;       // [NW][M2]        second-order minors per string
+  cd* B = nullptr;        // [NW][U]         CI weight per string
+  cd* C = nullptr;        // [NW][nv*no]     first-order CI matrix
+  cd* G = nullptr;        // [NW][P][M]      Green's function rows R u V_act
+  double* onebody = nullptr;  // [NW*2]  complex
+};
+
+// ---------------------------------------------------------------- Wick kernels
+void launch_ref_inverse(const cd* phi, int M, int Ntot, int NW, const DevSpin& s, cd* T,
+                        cd* logdetA, int* flag, hipStream_t st);
+void launch_strings(const DevSpin& s, const cd* T, int NW, bool minors, cd* d, cd* adj,
+                    cd* m2, hipStream_t st);
+void launch_ovlp_partial(int64_t n_det, int NW, const int* sa, const int* sb, const cd* c,
+                         const cd* da, int Ua, const cd* db, int Ub, cd* partial,
+                         int n_chunks, int chunk, hipStream_t st);
+void launch_ovlp_final(int NW, const cd* partial, int n_chunks, const cd* ldA,
+                       const cd* ldB, cd* obar, cd* log_ovlp, int* flag, hipStream_t st);
+void launch_ci_weights(const DevSpin& s, const int* det_s_other, const cd* det_c,
+                       const cd* d_other, int U_other, int NW, cd* B, hipStream_t st);
+void launch_ci_matrix(const DevSpin& s, int NW, const cd* adj, const cd* B, cd* C,
+                      hipStream_t st);
+void launch_green(const DevSpin& s, int M, int NW, const cd* T, const cd* C,
+                  const cd* obar, const double* h1, cd* G, cd* onebody, hipStream_t st);
+void launch_green_sum(int M, int NW, int P_all, const int* rmap_a, const int* rmap_b,
+                      int Pa, int Pb, const cd* Ga, const cd* Gb, double* Gp,
+                      hipStream_t st);
+void launch_xbar(int NW, int NG, const double* raw, double sqrt_dt, cd* xbar, hipStream_t st);
+
+// energy (one walker tile of WT walkers starting at w0)
+void launch_lambda(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
+                   int g_chunk, const cd* Ta, const cd* Tb, const cd* LTa, const cd* LTb,
+                   cd* Lam_a, cd* Lam_b, cd* v0, cd* ex0, cd* ZWpart_a, cd* ZWpart_b,
+                   hipStream_t st);
+void launch_pair_coef(const DevPairs& pr, int NW, const cd* det_c, const cd* adj_a, int Aa,
+                      const cd* adj_b, int Ab, cd* coef, hipStream_t st);
+void launch_minor_coef(const DevSpin& s, int NW, const cd* B, int U, const cd* m2, cd* coef,
+                       hipStream_t st);
+void launch_energy_gamma(const DevSpin& sa, const DevSpin& sb, const DevPairs& pr, int NW,
+                         int w0, int WT, int NG, int g_chunk, const cd* Lam_a,
+                         const cd* Lam_b, const cd* coef_pair, const cd* coef_ma,
+                         const cd* coef_mb, cd* partial, hipStream_t st);
+void launch_energy_final(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
+                         int n_lchunks, int n_echunks, const cd* obar, const cd* v0,
+                         const cd* ex0, const cd* ZWpart_a, const cd* ZWpart_b,
+                         const cd* Ca, const cd* Cb, const cd* epart, const cd* onebody_a,
+                         const cd* onebody_b, double e0, cd* e_loc, hipStream_t st);
+
+// ---------------------------------------------------------------- propagation
+void launch_vhs_prep(int NW, int NG, const double* x, const cd* xbar, double sqrt_dt,
+                     const double* weights, double* Y, hipStream_t st);
+void launch_weights(int NW, int NG, const double* x, const cd* xbar, const cd* logo_new,
+                    cd* logo, double* weights, double dt, double e_shift, hipStream_t st);
+void launch_qr(cd* phi, int M, int Ntot, int NW, int N, int col0, const int* mask, cd* logo,
+               hipStream_t st);
+void launch_frozen_mask(int NW, const double* weights, int* mask, hipStream_t st);
+void launch_copy_walkers(int NW, int M, int Ntot, int na, int nb, const cd* pa, const cd* pb,
+                         cd* phi, bool to_internal, cd* out_a, cd* out_b, hipStream_t st);
+void launch_sum_ll(const double* chol, int NG, int M, double* out, hipStream_t st);
+void launch_gather_rows(const double* L, int NG, int M, const int* rows, int P, double* out,
+                        hipStream_t st);
+
+// raise the dynamic-LDS limit of the kernels that may need more than 64 KB
+void init_wick_attributes();
+void init_prop_attributes();
+
+}  // namespace msd

@@ -1,0 +1,222 @@
+// Propagation-step kernels (Eqs. 4-5, 8-12 and the periodic QR).
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace msd {
+
+// Y rows (w, 0) = -sqrt(dt) Im(x - xbar), (w, 1) = sqrt(dt) Re(x - xbar), so that
+// Y . L gives the real and imaginary planes of VHS = i sqrt(dt) sum_g (x - xbar)_g L^g.
+__global__ void k_vhs_prep(int NW, int NG, const double* __restrict__ x,
+                           const cd* __restrict__ xbar, double sqrt_dt,
+                           const double* __restrict__ weights, double* __restrict__ Y) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= (int64_t)NW * NG) return;
+  const int w = (int)(tid / NG), g = (int)(tid % NG);
+  const cd xb = xbar[tid];
+  const double yr = x[tid] - xb.re, yi = -xb.im;
+  const bool live = weights[w] != 0.0;
+  Y[((size_t)2 * w) * NG + g] = live ? -sqrt_dt * yi : 0.0;
+  Y[((size_t)2 * w + 1) * NG + g] = live ? sqrt_dt * yr : 0.0;
+}
+
+void launch_vhs_prep(int NW, int NG, const double* x, const cd* xbar, double sqrt_dt,
+                     const double* weights, double* Y, hipStream_t st) {
+  const int64_t n = (int64_t)NW * NG;
+  hipLaunchKernelGGL(k_vhs_prep, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, NW, NG, x,
+                     xbar, sqrt_dt, weights, Y);
+}
+
+// Phaseless weight update (Eqs. 8-12) for walkers that were live at the start
+// of the step; the stored log-overlap moves to the propagated walker.
+__global__ __launch_bounds__(256) void k_weights(int NW, int NG, const double* __restrict__ x,
+                                                 const cd* __restrict__ xbar,
+                                                 const cd* __restrict__ logo_new,
+                                                 cd* __restrict__ logo,
+                                                 double* __restrict__ weights, double dt,
+                                                 double e_shift) {
+  __shared__ cd red_xx[256], red_bb[256];
+  const int w = blockIdx.x, tid = threadIdx.x;
+  cd xx{0.0, 0.0}, bb{0.0, 0.0};
+  for (int g = tid; g < NG; g += blockDim.x) {
+    const cd xb = xbar[(size_t)w * NG + g];
+    xx += x[(size_t)w * NG + g] * xb;
+    bb += xb * xb;
+  }
+  red_xx[tid] = xx;
+  red_bb[tid] = bb;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if (tid < off) {
+      red_xx[tid] += red_xx[tid + off];
+      red_bb[tid] += red_bb[tid + off];
+    }
+    __syncthreads();
+  }
+  if (tid != 0) return;
+  const double w0 = weights[w];
+  if (w0 == 0.0) return;
+  const cd ln = logo_new[w], lo = logo[w];
+  const double dre = ln.re - lo.re, dim = ln.im - lo.im;
+  // S = exp(dre + i dim); I = S exp(xx - bb/2)
+  const cd e = red_xx[0] - 0.5 * red_bb[0];
+  const double mag = exp(dre + e.re);
+  const double cos_theta = cos(dim);
+  double wn = w0 * mag * fmax(0.0, cos_theta) * exp(dt * e_shift);
+  if (!(wn < INFINITY) || !(ln.re > -INFINITY)) wn = 0.0;
+  weights[w] = wn;
+  logo[w] = ln;
+}
+
+void launch_weights(int NW, int NG, const double* x, const cd* xbar, const cd* logo_new,
+                    cd* logo, double* weights, double dt, double e_shift, hipStream_t st) {
+  hipLaunchKernelGGL(k_weights, dim3(NW), dim3(256), 0, st, NW, NG, x, xbar, logo_new, logo,
+                     weights, dt, e_shift);
+}
+
+__global__ void k_frozen_mask(int NW, const double* __restrict__ weights, int* __restrict__ mask) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w < NW) mask[w] = weights[w] != 0.0;
+}
+
+void launch_frozen_mask(int NW, const double* weights, int* mask, hipStream_t st) {
+  hipLaunchKernelGGL(k_frozen_mask, dim3((NW + 255) / 256), dim3(256), 0, st, NW, weights, mask);
+}
+
+// Re-orthonormalisation Phi = Q R, diag(R) > 0, by Cholesky QR applied twice
+// (Gram matrix, its Cholesky factor, Phi <- Phi R^{-1}); the log-overlap loses
+// sum_j log R_jj.  One workgroup per walker and spin; walkers with mask 0 are
+// skipped.
+__global__ __launch_bounds__(256) void k_qr(cd* __restrict__ phi, int M, int Ntot, int NW, int N,
+                                            int col0, const int* __restrict__ mask,
+                                            cd* __restrict__ logo) {
+  extern __shared__ cd sm[];
+  cd* R = sm;            // [N][N]  Gram -> upper Cholesky factor
+  cd* Ri = sm + N * N;   // [N][N]  R^{-1}
+  __shared__ double ldet;
+  __shared__ int bad;
+  const int w = blockIdx.x, tid = threadIdx.x, bd = blockDim.x;
+  if (mask && mask[w] == 0) return;
+  cd* P = phi + (size_t)w * M * Ntot + col0;
+  if (tid == 0) {
+    ldet = 0.0;
+    bad = 0;
+  }
+  for (int pass = 0; pass < 2; ++pass) {
+    __syncthreads();
+    for (int e = tid; e < N * N; e += bd) {
+      const int i = e / N, j = e % N;
+      cd acc{0.0, 0.0};
+      if (i <= j)
+        for (int q = 0; q < M; ++q) cfma(acc, conj(P[(size_t)q * Ntot + i]), P[(size_t)q * Ntot + j]);
+      R[e] = acc;
+      Ri[e] = cd{0.0, 0.0};
+    }
+    __syncthreads();
+    // right-looking Cholesky of the Hermitian Gram matrix, upper factor in place
+    for (int j = 0; j < N; ++j) {
+      if (tid == 0) {
+        const double dj = R[j * N + j].re;
+        if (!(dj > 0.0) || !(dj < INFINITY)) bad = 1;
+        const double r = sqrt(fmax(dj, 1e-300));
+        R[j * N + j] = cd{r, 0.0};
+        ldet += log(r);
+      }
+      __syncthreads();
+      const double rinv = 1.0 / R[j * N + j].re;
+      for (int c = j + 1 + tid; c < N; c += bd) R[j * N + c] = R[j * N + c] * rinv;
+      __syncthreads();
+      for (int e = tid; e < (N - j - 1) * (N - j - 1); e += bd) {
+        const int r = j + 1 + e / (N - j - 1), c = j + 1 + e % (N - j - 1);
+        if (r <= c) R[r * N + c] -= conj(R[j * N + r]) * R[j * N + c];
+      }
+      __syncthreads();
+    }
+    // columns of R^{-1}
+    for (int c = tid; c < N; c += bd) {
+      Ri[c * N + c] = cd{1.0 / R[c * N + c].re, 0.0};
+      for (int i = c - 1; i >= 0; --i) {
+        cd acc{0.0, 0.0};
+        for (int l = i + 1; l <= c; ++l) cfma(acc, R[i * N + l], Ri[l * N + c]);
+        Ri[i * N + c] = -acc * (1.0 / R[i * N + i].re);
+      }
+    }
+    __syncthreads();
+    for (int q = tid; q < M; q += bd) {
+      cd* row = P + (size_t)q * Ntot;
+      for (int j = N - 1; j >= 0; --j) {
+        cd acc{0.0, 0.0};
+        for (int i = 0; i <= j; ++i) cfma(acc, row[i], Ri[i * N + j]);
+        row[j] = acc;
+      }
+    }
+    __threadfence();
+  }
+  __syncthreads();
+  if (tid == 0) {
+    cd l = logo[w];
+    logo[w] = bad ? cd{-INFINITY, 0.0} : cd{l.re - ldet, l.im};
+  }
+}
+
+void launch_qr(cd* phi, int M, int Ntot, int NW, int N, int col0, const int* mask, cd* logo,
+               hipStream_t st) {
+  if (N == 0) return;
+  hipLaunchKernelGGL(k_qr, dim3(NW), dim3(256), 2 * (size_t)N * N * sizeof(cd), st, phi, M, Ntot,
+                     NW, N, col0, mask, logo);
+}
+
+// Pack the per-spin boundary layouts [w][M][n_s] into the internal [w][M][Ntot]
+// walker matrix (to_internal) or back.
+__global__ void k_copy_walkers(int NW, int M, int Ntot, int na, int nb, const cd* __restrict__ pa,
+                               const cd* __restrict__ pb, cd* __restrict__ phi, int to_internal,
+                               cd* __restrict__ oa, cd* __restrict__ ob) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= (int64_t)NW * M * Ntot) return;
+  const int c = (int)(tid % Ntot);
+  const int64_t wq = tid / Ntot;  // w*M + q
+  if (to_internal) {
+    phi[tid] = c < na ? pa[wq * na + c] : pb[wq * nb + (c - na)];
+  } else {
+    if (c < na) {
+      if (oa) oa[wq * na + c] = phi[tid];
+    } else {
+      if (ob) ob[wq * nb + (c - na)] = phi[tid];
+    }
+  }
+}
+
+void launch_copy_walkers(int NW, int M, int Ntot, int na, int nb, const cd* pa, const cd* pb,
+                         cd* phi, bool to_internal, cd* out_a, cd* out_b, hipStream_t st) {
+  const int64_t n = (int64_t)NW * M * Ntot;
+  hipLaunchKernelGGL(k_copy_walkers, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, NW, M,
+                     Ntot, na, nb, pa, pb, phi, to_internal ? 1 : 0, out_a, out_b);
+}
+
+// out[p][q] = sum_g sum_r L^g_pr L^g_rq  (the exchange-like one-body term of Eq. 4)
+__global__ void k_sum_ll(const double* __restrict__ L, int NG, int M, double* __restrict__ out) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= (int64_t)M * M) return;
+  const int p = (int)(tid / M), q = (int)(tid % M);
+  double acc = 0.0;
+  for (int g = 0; g < NG; ++g) {
+    const double* Lg = L + (size_t)g * M * M;
+    for (int r = 0; r < M; ++r) acc = fma(Lg[(size_t)p * M + r], Lg[(size_t)r * M + q], acc);
+  }
+  out[tid] = acc;
+}
+
+void launch_sum_ll(const double* chol, int NG, int M, double* out, hipStream_t st) {
+  const int64_t n = (int64_t)M * M;
+  hipLaunchKernelGGL(k_sum_ll, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, chol, NG, M,
+                     out);
+}
+
+}  // namespace msd
+
+namespace msd {
+void init_prop_attributes() {
+  hipFuncSetAttribute((const void*)k_qr, hipFuncAttributeMaxDynamicSharedMemorySize, 140 * 1024);
+}
+}  // namespace msd

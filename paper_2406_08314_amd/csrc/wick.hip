@@ -1,0 +1,902 @@
+// Generalised-Wick evaluation of the MSD trial (Sec. III, App. A of the paper;
+// Mahajan & Sharma's reference-based form).
+//
+// Per walker and spin, with R the reference orbitals and A = Phi[R, :]:
+//   T = Phi A^{-1}                       (M x N)
+//   X_I = T[P_I, slot(H_I)]^T            (k x k per string)
+//   Obar = sum_I c~_I det X^a_I det X^b_I, c~_I = conj(c_I) sgn^a_I sgn^b_I
+//   B^s_str = sum_{I contains str} c~_I det X^{other spin}_I
+//   C^s[a, i] = sum_str B^s_str adj(X_str)[n, m]      (a = p_n, i = h_m)
+//   G = G0 - (G0 - I)[:, V] C G0[O, :] / Obar        (Eq. 14 for the MSD trial)
+// Energy (factorised; every term is exact):
+//   Q^g = L^g[R, :] T, v0 = tr Q, ex0 = tr QQ, Lam^g = T[V,:] Q^g - (L^g T)[V,:],
+//   Xi^g = Lam^g Q^g,  ZW = sum_g Xi^g - (v0^a + v0^b) Lam^g,
+//   E_L = E0 + sum_s tr(h G^s) + sum_g (v0a v0b + (v0a^2-ex0a + v0b^2-ex0b)/2)
+//         + [ sum_s <C^s, ZW^s> + sum_g ( sum_pairs W_ab coef_ab
+//                                        + sum_s sum_minors det2(Lam^s) coef_s ) ] / Obar
+// with the opposite-spin coefficients coef_ab[(a,i),(b,j)] =
+// sum_I c~_I adj(X^a_I)[n,m] adj(X^b_I)[n',m'] and the same-spin ones
+// coef_s[(a,b),(i,j)] = sum_str B_str (-1)^{m+m'+n+n'} det X_str[~{m,m'}, ~{n,n'}].
+// All reductions use fixed orders (no atomics): results are run-to-run
+// reproducible.
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace msd {
+
+// ============================================================================
+// small complex determinants
+// ============================================================================
+
+template <int n>
+__device__ __forceinline__ cd det_small(const cd* a);
+
+template <>
+__device__ __forceinline__ cd det_small<0>(const cd*) { return cd{1.0, 0.0}; }
+template <>
+__device__ __forceinline__ cd det_small<1>(const cd* a) { return a[0]; }
+template <>
+__device__ __forceinline__ cd det_small<2>(const cd* a) { return a[0] * a[3] - a[1] * a[2]; }
+template <>
+__device__ __forceinline__ cd det_small<3>(const cd* a) {
+  return a[0] * (a[4] * a[8] - a[5] * a[7]) - a[1] * (a[3] * a[8] - a[5] * a[6]) +
+         a[2] * (a[3] * a[7] - a[4] * a[6]);
+}
+template <>
+__device__ __forceinline__ cd det_small<4>(const cd* a) {
+  // expansion along row 0 with the 2x2 minors of rows 2-3 shared
+  cd m01 = a[8] * a[13] - a[9] * a[12];
+  cd m02 = a[8] * a[14] - a[10] * a[12];
+  cd m03 = a[8] * a[15] - a[11] * a[12];
+  cd m12 = a[9] * a[14] - a[10] * a[13];
+  cd m13 = a[9] * a[15] - a[11] * a[13];
+  cd m23 = a[10] * a[15] - a[11] * a[14];
+  cd c0 = a[5] * m23 - a[6] * m13 + a[7] * m12;
+  cd c1 = a[4] * m23 - a[6] * m03 + a[7] * m02;
+  cd c2 = a[4] * m13 - a[5] * m03 + a[7] * m01;
+  cd c3 = a[4] * m12 - a[5] * m02 + a[6] * m01;
+  return a[0] * c0 - a[1] * c1 + a[2] * c2 - a[3] * c3;
+}
+
+// Determinant of an n x n matrix (row-major, leading dimension n) by LU with
+// partial pivoting on a private copy; exact zero for an exactly singular pivot.
+__device__ cd det_lu(const cd* a, int n) {
+  cd w[KMAX * KMAX];
+  for (int i = 0; i < n * n; ++i) w[i] = a[i];
+  cd det{1.0, 0.0};
+  for (int j = 0; j < n; ++j) {
+    int piv = j;
+    double best = abs2(w[j * n + j]);
+    for (int i = j + 1; i < n; ++i) {
+      double v = abs2(w[i * n + j]);
+      if (v > best) { best = v; piv = i; }
+    }
+    if (best == 0.0) return cd{0.0, 0.0};
+    if (piv != j) {
+      for (int c = 0; c < n; ++c) {
+        cd t = w[j * n + c];
+        w[j * n + c] = w[piv * n + c];
+        w[piv * n + c] = t;
+      }
+      det = -det;
+    }
+    cd p = w[j * n + j];
+    det = det * p;
+    for (int i = j + 1; i < n; ++i) {
+      cd f = cdiv(w[i * n + j], p);
+      for (int c = j + 1; c < n; ++c) w[i * n + c] -= f * w[j * n + c];
+    }
+  }
+  return det;
+}
+
+// ============================================================================
+// A1: reference overlap, log det A and T = Phi A^{-1} (Gauss-Jordan, LDS)
+// ============================================================================
+
+__global__ __launch_bounds__(256) void k_ref_inverse(const cd* __restrict__ phi, int M, int Ntot,
+                                                     int NW, DevSpin s, cd* __restrict__ T,
+                                                     cd* __restrict__ logdetA,
+                                                     int* __restrict__ flag) {
+  extern __shared__ cd aug[];  // [N][2N]
+  __shared__ cd fac[NMAX_LDS];
+  __shared__ int piv_s;
+  const int w = blockIdx.x, tid = threadIdx.x, bd = blockDim.x;
+  const int N = s.N, N2 = 2 * N;
+  const cd* P = phi + (size_t)w * M * Ntot + s.col0;
+  for (int e = tid; e < N * N2; e += bd) {
+    int i = e / N2, c = e % N2;
+    aug[e] = c < N ? P[(size_t)s.ref[i] * Ntot + c] : cd{c - N == i ? 1.0 : 0.0, 0.0};
+  }
+  __syncthreads();
+  double lmag = 0.0, larg = 0.0;
+  int nswap = 0;
+  bool singular = false;
+  for (int j = 0; j < N; ++j) {
+    if (tid == 0) {
+      int piv = j;
+      double best = abs2(aug[j * N2 + j]);
+      for (int i = j + 1; i < N; ++i) {
+        double v = abs2(aug[i * N2 + j]);
+        if (v > best) { best = v; piv = i; }
+      }
+      piv_s = (best > 0.0 && best < INFINITY) ? piv : -1;
+    }
+    __syncthreads();
+    const int piv = piv_s;
+    if (piv < 0) { singular = true; break; }
+    if (piv != j) {
+      for (int c = tid; c < N2; c += bd) {
+        cd t = aug[j * N2 + c];
+        aug[j * N2 + c] = aug[piv * N2 + c];
+        aug[piv * N2 + c] = t;
+      }
+      ++nswap;
+    }
+    __syncthreads();
+    const cd p = aug[j * N2 + j];
+    if (tid == 0) {
+      lmag += 0.5 * log(abs2(p));
+      larg += atan2(p.im, p.re);
+    }
+    const cd inv = cdiv(cd{1.0, 0.0}, p);
+    for (int i = tid; i < N; i += bd) fac[i] = aug[i * N2 + j];
+    __syncthreads();
+    for (int c = j + 1 + tid; c < N2; c += bd) aug[j * N2 + c] = aug[j * N2 + c] * inv;
+    __syncthreads();
+    for (int e = tid; e < N * (N2 - j - 1); e += bd) {
+      int i = e / (N2 - j - 1), c = j + 1 + e % (N2 - j - 1);
+      if (i != j) aug[i * N2 + c] -= fac[i] * aug[j * N2 + c];
+    }
+    __syncthreads();
+  }
+  if (singular) {
+    for (int e = tid; e < M * N; e += bd) {
+      int q = e / N, c = e % N;
+      T[((size_t)q * NW + w) * N + c] = cd{0.0, 0.0};
+    }
+    if (tid == 0) {
+      flag[w] = 1;
+      logdetA[w] = cd{-INFINITY, 0.0};
+    }
+    return;
+  }
+  if (tid == 0) logdetA[w] = cd{lmag, larg + ((nswap & 1) ? M_PI : 0.0)};
+  for (int e = tid; e < M * N; e += bd) {
+    int q = e / N, c = e % N;
+    cd acc{0.0, 0.0};
+    const cd* row = P + (size_t)q * Ntot;
+    for (int i = 0; i < N; ++i) cfma(acc, row[i], aug[i * N2 + N + c]);
+    T[((size_t)q * NW + w) * N + c] = acc;
+  }
+}
+
+void launch_ref_inverse(const cd* phi, int M, int Ntot, int NW, const DevSpin& s, cd* T,
+                        cd* logdetA, int* flag, hipStream_t st) {
+  if (s.N == 0) return;
+  size_t lds = (size_t)s.N * 2 * s.N * sizeof(cd);
+  hipLaunchKernelGGL(k_ref_inverse, dim3(NW), dim3(256), lds, st, phi, M, Ntot, NW, s, T,
+                     logdetA, flag);
+}
+
+// ============================================================================
+// A3: per-string excitation determinants, adjugates, second-order minors
+// ============================================================================
+
+template <int K>
+__device__ __forceinline__ void sub1(const cd* X, int rm, int cn, cd* out) {
+  int o = 0;
+#pragma unroll
+  for (int r = 0; r < K; ++r) {
+    if (r == rm) continue;
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+      if (c == cn) continue;
+      out[o++] = X[r * K + c];
+    }
+  }
+}
+
+template <int K>
+__device__ __forceinline__ void sub2(const cd* X, int r0, int r1, int c0, int c1, cd* out) {
+  int o = 0;
+#pragma unroll
+  for (int r = 0; r < K; ++r) {
+    if (r == r0 || r == r1) continue;
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+      if (c == c0 || c == c1) continue;
+      out[o++] = X[r * K + c];
+    }
+  }
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_strings_t(DevSpin s, const cd* __restrict__ T, int NW,
+                                                   int s0, int ns, bool minors,
+                                                   cd* __restrict__ d, cd* __restrict__ adj,
+                                                   cd* __restrict__ m2) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= (int64_t)ns * NW) return;
+  const int str = s0 + (int)(tid % ns);
+  const int w = (int)(tid / ns);
+  const int N = s.N;
+  cd X[K > 0 ? K * K : 1];
+#pragma unroll
+  for (int m = 0; m < K; ++m)
+#pragma unroll
+    for (int n = 0; n < K; ++n)
+      X[m * K + n] =
+          T[((size_t)s.part[str * KMAX + n] * NW + w) * N + s.hslot[str * KMAX + m]];
+  d[(size_t)w * s.U + str] = det_small<K>(X);
+  if constexpr (K >= 1) {
+    cd* ao = adj + (size_t)w * s.A + s.adj_off[str];
+#pragma unroll
+    for (int n = 0; n < K; ++n)
+#pragma unroll
+      for (int m = 0; m < K; ++m) {
+        cd sub[(K - 1) * (K - 1) > 0 ? (K - 1) * (K - 1) : 1];
+        sub1<K>(X, m, n, sub);
+        cd v = det_small<K - 1>(sub);
+        ao[n * K + m] = ((n + m) & 1) ? -v : v;
+      }
+  }
+  if constexpr (K >= 2) {
+    if (minors) {
+      constexpr int P = K * (K - 1) / 2;
+      cd* mo = m2 + (size_t)w * s.M2 + s.m2_off[str];
+#pragma unroll
+      for (int m = 0; m < K; ++m)
+#pragma unroll
+        for (int mp = m + 1; mp < K; ++mp)
+#pragma unroll
+          for (int n = 0; n < K; ++n)
+#pragma unroll
+            for (int np = n + 1; np < K; ++np) {
+              cd sub[(K - 2) * (K - 2) > 0 ? (K - 2) * (K - 2) : 1];
+              sub2<K>(X, m, mp, n, np, sub);
+              mo[pair_index(m, mp, K) * P + pair_index(n, np, K)] = det_small<K - 2>(sub);
+            }
+    }
+  }
+}
+
+// Orders above 4: runtime k with LU-based sub-determinants.
+__global__ __launch_bounds__(128) void k_strings_big(DevSpin s, const cd* __restrict__ T, int NW,
+                                                     int s0, int ns, int K, bool minors,
+                                                     cd* __restrict__ d, cd* __restrict__ adj,
+                                                     cd* __restrict__ m2) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= (int64_t)ns * NW) return;
+  const int str = s0 + (int)(tid % ns);
+  const int w = (int)(tid / ns);
+  const int N = s.N;
+  cd X[KMAX * KMAX], sub[KMAX * KMAX];
+  for (int m = 0; m < K; ++m)
+    for (int n = 0; n < K; ++n)
+      X[m * K + n] =
+          T[((size_t)s.part[str * KMAX + n] * NW + w) * N + s.hslot[str * KMAX + m]];
+  d[(size_t)w * s.U + str] = det_lu(X, K);
+  cd* ao = adj + (size_t)w * s.A + s.adj_off[str];
+  for (int n = 0; n < K; ++n)
+    for (int m = 0; m < K; ++m) {
+      int o = 0;
+      for (int r = 0; r < K; ++r) {
+        if (r == m) continue;
+        for (int c = 0; c < K; ++c)
+          if (c != n) sub[o++] = X[r * K + c];
+      }
+      cd v = det_lu(sub, K - 1);
+      ao[n * K + m] = ((n + m) & 1) ? -v : v;
+    }
+  if (minors) {
+    const int P = K * (K - 1) / 2;
+    cd* mo = m2 + (size_t)w * s.M2 + s.m2_off[str];
+    for (int m = 0; m < K; ++m)
+      for (int mp = m + 1; mp < K; ++mp)
+        for (int n = 0; n < K; ++n)
+          for (int np = n + 1; np < K; ++np) {
+            int o = 0;
+            for (int r = 0; r < K; ++r) {
+              if (r == m || r == mp) continue;
+              for (int c = 0; c < K; ++c)
+                if (c != n && c != np) sub[o++] = X[r * K + c];
+            }
+            mo[pair_index(m, mp, K) * P + pair_index(n, np, K)] = det_lu(sub, K - 2);
+          }
+  }
+}
+
+void launch_strings(const DevSpin& s, const cd* T, int NW, bool minors, cd* d, cd* adj, cd* m2,
+                    hipStream_t st) {
+  for (int k = 0; k <= KMAX; ++k) {
+    const int s0 = s.bucket[k], ns = s.bucket[k + 1] - s.bucket[k];
+    if (ns <= 0) continue;
+    const int64_t n = (int64_t)ns * NW;
+    const int bs = k <= 4 ? 256 : 128;
+    dim3 grid((unsigned)((n + bs - 1) / bs));
+    switch (k) {
+      case 0: hipLaunchKernelGGL(k_strings_t<0>, grid, dim3(bs), 0, st, s, T, NW, s0, ns, minors, d, adj, m2); break;
+      case 1: hipLaunchKernelGGL(k_strings_t<1>, grid, dim3(bs), 0, st, s, T, NW, s0, ns, minors, d, adj, m2); break;
+      case 2: hipLaunchKernelGGL(k_strings_t<2>, grid, dim3(bs), 0, st, s, T, NW, s0, ns, minors, d, adj, m2); break;
+      case 3: hipLaunchKernelGGL(k_strings_t<3>, grid, dim3(bs), 0, st, s, T, NW, s0, ns, minors, d, adj, m2); break;
+      case 4: hipLaunchKernelGGL(k_strings_t<4>, grid, dim3(bs), 0, st, s, T, NW, s0, ns, minors, d, adj, m2); break;
+      default: hipLaunchKernelGGL(k_strings_big, grid, dim3(bs), 0, st, s, T, NW, s0, ns, k, minors, d, adj, m2); break;
+    }
+  }
+}
+
+// ============================================================================
+// block reduction helper (fixed order)
+// ============================================================================
+
+__device__ cd block_reduce(cd v, cd* red) {
+  const int tid = threadIdx.x, bd = blockDim.x;
+  red[tid] = v;
+  __syncthreads();
+  for (int off = bd / 2; off > 0; off >>= 1) {
+    if (tid < off) red[tid] += red[tid + off];
+    __syncthreads();
+  }
+  cd r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// ============================================================================
+// A3: trial overlap Obar = sum_I c~_I det X^a det X^b (compensated sums)
+// ============================================================================
+
+__global__ __launch_bounds__(256) void k_ovlp_partial(int64_t n_det, int NW, const int* __restrict__ sa,
+                                                      const int* __restrict__ sb,
+                                                      const cd* __restrict__ c,
+                                                      const cd* __restrict__ da, int Ua,
+                                                      const cd* __restrict__ db, int Ub,
+                                                      cd* __restrict__ partial, int n_chunks,
+                                                      int chunk) {
+  __shared__ cd red[256];
+  const int w = blockIdx.y, ch = blockIdx.x, tid = threadIdx.x;
+  const int64_t I0 = (int64_t)ch * chunk;
+  const int64_t I1 = min(n_det, I0 + chunk);
+  double sr = 0, si = 0, cr = 0, ci = 0;  // Kahan sums
+  for (int64_t I = I0 + tid; I < I1; I += blockDim.x) {
+    cd t = c[I] * da[(size_t)w * Ua + sa[I]] * db[(size_t)w * Ub + sb[I]];
+    double y = t.re - cr, z = sr + y;
+    cr = (z - sr) - y;
+    sr = z;
+    y = t.im - ci;
+    z = si + y;
+    ci = (z - si) - y;
+    si = z;
+  }
+  cd r = block_reduce(cd{sr, si}, red);
+  if (tid == 0) partial[(size_t)w * n_chunks + ch] = r;
+}
+
+__global__ void k_ovlp_final(int NW, const cd* __restrict__ partial, int n_chunks,
+                             const cd* __restrict__ ldA, const cd* __restrict__ ldB,
+                             cd* __restrict__ obar, cd* __restrict__ log_ovlp, int* __restrict__ flag) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= NW) return;
+  cd o{0.0, 0.0};
+  for (int c = 0; c < n_chunks; ++c) o += partial[(size_t)w * n_chunks + c];
+  obar[w] = o;
+  const double a2 = abs2(o);
+  cd la = ldA ? ldA[w] : cd{0.0, 0.0};
+  cd lb = ldB ? ldB[w] : cd{0.0, 0.0};
+  if (!(a2 > 0.0) || !(a2 < INFINITY)) {
+    flag[w] = 1;
+    log_ovlp[w] = cd{-INFINITY, 0.0};
+    return;
+  }
+  log_ovlp[w] = cd{0.5 * log(a2) + la.re + lb.re, atan2(o.im, o.re) + la.im + lb.im};
+}
+
+void launch_ovlp_partial(int64_t n_det, int NW, const int* sa, const int* sb, const cd* c,
+                         const cd* da, int Ua, const cd* db, int Ub, cd* partial, int n_chunks,
+                         int chunk, hipStream_t st) {
+  hipLaunchKernelGGL(k_ovlp_partial, dim3(n_chunks, NW), dim3(256), 0, st, n_det, NW, sa, sb,
+                     c, da, Ua, db, Ub, partial, n_chunks, chunk);
+}
+
+void launch_ovlp_final(int NW, const cd* partial, int n_chunks, const cd* ldA, const cd* ldB,
+                       cd* obar, cd* log_ovlp, int* flag, hipStream_t st) {
+  hipLaunchKernelGGL(k_ovlp_final, dim3((NW + 127) / 128), dim3(128), 0, st, NW, partial,
+                     n_chunks, ldA, ldB, obar, log_ovlp, flag);
+}
+
+// ============================================================================
+// A4: CI weights per string and the first-order CI matrix (gather form of the
+// paper's reduce_CI: each output entry sums its own contribution list)
+// ============================================================================
+
+__global__ void k_ci_weights(DevSpin s, const int* __restrict__ det_s_other,
+                             const cd* __restrict__ det_c, const cd* __restrict__ d_other,
+                             int U_other, int NW, cd* __restrict__ B) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= (int64_t)s.U * NW) return;
+  const int str = (int)(tid % s.U), w = (int)(tid / s.U);
+  cd acc{0.0, 0.0};
+  for (int e = s.bw_ptr[str]; e < s.bw_ptr[str + 1]; ++e) {
+    const int I = s.bw_det[e];
+    cfma(acc, det_c[I], d_other[(size_t)w * U_other + det_s_other[I]]);
+  }
+  B[(size_t)w * s.U + str] = acc;
+}
+
+void launch_ci_weights(const DevSpin& s, const int* det_s_other, const cd* det_c,
+                       const cd* d_other, int U_other, int NW, cd* B, hipStream_t st) {
+  const int64_t n = (int64_t)s.U * NW;
+  hipLaunchKernelGGL(k_ci_weights, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s,
+                     det_s_other, det_c, d_other, U_other, NW, B);
+}
+
+__global__ void k_ci_matrix(DevSpin s, int NW, const cd* __restrict__ adj,
+                            const cd* __restrict__ B, cd* __restrict__ C) {
+  const int X = s.nv * s.no;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= (int64_t)X * NW) return;
+  const int e = (int)(tid % X), w = (int)(tid / X);
+  cd acc{0.0, 0.0};
+  for (int q = s.c_ptr[e]; q < s.c_ptr[e + 1]; ++q)
+    cfma(acc, adj[(size_t)w * s.A + s.c_adj[q]], B[(size_t)w * s.U + s.c_str[q]]);
+  C[(size_t)w * X + e] = acc;
+}
+
+void launch_ci_matrix(const DevSpin& s, int NW, const cd* adj, const cd* B, cd* C,
+                      hipStream_t st) {
+  const int64_t n = (int64_t)s.nv * s.no * NW;
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_ci_matrix, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s, NW,
+                     adj, B, C);
+}
+
+// ============================================================================
+// A5: Green's function rows R u V_act and one-body energy
+// ============================================================================
+
+constexpr int G_QT = 64;
+
+__global__ __launch_bounds__(256) void k_green(DevSpin s, int M, int NW, const cd* __restrict__ T,
+                                               const cd* __restrict__ C,
+                                               const cd* __restrict__ obar,
+                                               const double* __restrict__ h1,
+                                               cd* __restrict__ G, cd* __restrict__ onebody) {
+  extern __shared__ cd sm[];
+  __shared__ cd red[256];
+  const int nv = s.nv, no = s.no, N = s.N, P = s.P;
+  cd* Cs = sm;                 // [nv*no]
+  cd* TV = Cs + nv * no;       // [nv*N]
+  cd* D = TV + nv * N;         // [nv*G_QT]
+  const int w = blockIdx.x, tid = threadIdx.x, bd = blockDim.x;
+  const cd inv_o = cdiv(cd{1.0, 0.0}, obar[w]);
+  for (int e = tid; e < nv * no; e += bd) Cs[e] = C[(size_t)w * nv * no + e];
+  for (int e = tid; e < nv * N; e += bd) {
+    int a = e / N, j = e % N;
+    TV[e] = T[((size_t)s.vir[a] * NW + w) * N + j];
+  }
+  __syncthreads();
+  cd ob{0.0, 0.0};
+  for (int q0 = 0; q0 < M; q0 += G_QT) {
+    for (int e = tid; e < nv * G_QT; e += bd) {
+      int a = e / G_QT, q = q0 + e % G_QT;
+      cd acc{0.0, 0.0};
+      if (q < M) {
+        const cd* Tq = T + ((size_t)q * NW + w) * N;
+        for (int i = 0; i < no; ++i) cfma(acc, Cs[a * no + i], Tq[s.oslot[i]]);
+      }
+      D[e] = acc;
+    }
+    __syncthreads();
+    for (int e = tid; e < P * G_QT; e += bd) {
+      int r = e / G_QT, ql = e % G_QT, q = q0 + ql;
+      if (q >= M) continue;
+      cd g;
+      if (r < N) {
+        cd acc{0.0, 0.0};
+        for (int a = 0; a < nv; ++a) cfma(acc, TV[a * N + r], D[a * G_QT + ql]);
+        g = T[((size_t)q * NW + w) * N + r] - inv_o * acc;
+      } else {
+        g = inv_o * D[(r - N) * G_QT + ql];
+      }
+      G[((size_t)w * P + r) * M + q] = g;
+      ob += h1[(size_t)s.rows[r] * M + q] * g;
+    }
+    __syncthreads();
+  }
+  cd tot = block_reduce(ob, red);
+  if (tid == 0) onebody[w] = tot;
+}
+
+void launch_green(const DevSpin& s, int M, int NW, const cd* T, const cd* C, const cd* obar,
+                  const double* h1, cd* G, cd* onebody, hipStream_t st) {
+  size_t lds = ((size_t)s.nv * s.no + (size_t)s.nv * s.N + (size_t)s.nv * G_QT) * sizeof(cd);
+  hipLaunchKernelGGL(k_green, dim3(NW), dim3(256), lds, st, s, M, NW, T, C, obar, h1, G,
+                     onebody);
+}
+
+__global__ void k_green_sum(int M, int NW, int P_all, const int* __restrict__ rmap_a,
+                            const int* __restrict__ rmap_b, int Pa, int Pb,
+                            const cd* __restrict__ Ga, const cd* __restrict__ Gb,
+                            double* __restrict__ Gp) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per = (int64_t)P_all * M;
+  if (tid >= per * NW) return;
+  const int w = (int)(tid / per);
+  const int64_t e = tid % per;
+  const int r = (int)(e / M), q = (int)(e % M);
+  cd g{0.0, 0.0};
+  if (rmap_a[r] >= 0) g += Ga[((size_t)w * Pa + rmap_a[r]) * M + q];
+  if (rmap_b[r] >= 0) g += Gb[((size_t)w * Pb + rmap_b[r]) * M + q];
+  Gp[((size_t)w * 2) * per + e] = g.re;
+  Gp[((size_t)w * 2 + 1) * per + e] = g.im;
+}
+
+void launch_green_sum(int M, int NW, int P_all, const int* rmap_a, const int* rmap_b, int Pa,
+                      int Pb, const cd* Ga, const cd* Gb, double* Gp, hipStream_t st) {
+  const int64_t n = (int64_t)P_all * M * NW;
+  hipLaunchKernelGGL(k_green_sum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, M, NW,
+                     P_all, rmap_a, rmap_b, Pa, Pb, Ga, Gb, Gp);
+}
+
+// xbar[w][g] = -i sqrt(dt) vbar, vbar = raw[g][2w] + i raw[g][2w+1]
+__global__ void k_xbar(int NW, int NG, const double* __restrict__ raw, double sqrt_dt,
+                       cd* __restrict__ xbar) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= (int64_t)NW * NG) return;
+  const int w = (int)(tid / NG), g = (int)(tid % NG);
+  const double vr = raw[(size_t)g * 2 * NW + 2 * w], vi = raw[(size_t)g * 2 * NW + 2 * w + 1];
+  xbar[tid] = cd{sqrt_dt * vi, -sqrt_dt * vr};
+}
+
+void launch_xbar(int NW, int NG, const double* raw, double sqrt_dt, cd* xbar, hipStream_t st) {
+  const int64_t n = (int64_t)NW * NG;
+  hipLaunchKernelGGL(k_xbar, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, NW, NG, raw,
+                     sqrt_dt, xbar);
+}
+
+// ============================================================================
+// A6: energy intermediates per (walker, Cholesky chunk): v0, ex0, Lam (window),
+// and the chunk's share of ZW = sum_g Xi^g - (v0a + v0b) Lam^g.
+// LT^s layout: row g*P + p, column wl*N + c (complex), row length WT*N.
+// ============================================================================
+
+constexpr int ZW_PER_THREAD = 4;
+
+__global__ __launch_bounds__(256) void k_lambda(DevSpin sa, DevSpin sb, int NW, int w0, int WT,
+                                                int NG, int g_chunk, const cd* __restrict__ Ta,
+                                                const cd* __restrict__ Tb,
+                                                const cd* __restrict__ LTa,
+                                                const cd* __restrict__ LTb,
+                                                cd* __restrict__ Lam_a, cd* __restrict__ Lam_b,
+                                                cd* __restrict__ v0, cd* __restrict__ ex0,
+                                                cd* __restrict__ ZWa, cd* __restrict__ ZWb) {
+  extern __shared__ cd sm[];
+  __shared__ cd rowv[2][NMAX_LDS], rowx[2][NMAX_LDS];
+  __shared__ cd v0s[2], ex0s[2];
+  const int wl = blockIdx.x, chunk = blockIdx.y, n_chunks = gridDim.y;
+  const int w = w0 + wl, tid = threadIdx.x, bd = blockDim.x;
+  const DevSpin* sp[2] = {&sa, &sb};
+  const cd* Tt[2] = {Ta, Tb};
+  const cd* LT[2] = {LTa, LTb};
+  cd* Lam[2] = {Lam_a, Lam_b};
+  cd* ZW[2] = {ZWa, ZWb};
+  cd* Q[2];
+  cd* LTV[2];
+  cd* TV[2];
+  cd* ptr = sm;
+  for (int s2 = 0; s2 < 2; ++s2) {
+    const int N = sp[s2]->N, nv = sp[s2]->nv;
+    Q[s2] = ptr; ptr += N * N;
+    LTV[s2] = ptr; ptr += nv * N;
+    TV[s2] = ptr; ptr += nv * N;
+  }
+  cd* Lf = ptr;  // [max nv*N]
+  for (int s2 = 0; s2 < 2; ++s2) {
+    const DevSpin& S = *sp[s2];
+    for (int e = tid; e < S.nv * S.N; e += bd) {
+      int a = e / S.N, j = e % S.N;
+      TV[s2][e] = Tt[s2][((size_t)S.vir[a] * NW + w) * S.N + j];
+    }
+  }
+  cd zacc[2][ZW_PER_THREAD];
+#pragma unroll
+  for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+    for (int j = 0; j < ZW_PER_THREAD; ++j) zacc[s2][j] = cd{0.0, 0.0};
+
+  const int g0 = chunk * g_chunk, g1 = min(NG, g0 + g_chunk);
+  for (int g = g0; g < g1; ++g) {
+    for (int s2 = 0; s2 < 2; ++s2) {
+      const DevSpin& S = *sp[s2];
+      const int N = S.N, P = S.P;
+      const cd* base = LT[s2] + ((size_t)g * P) * WT * N + (size_t)wl * N;
+      for (int e = tid; e < N * N; e += bd) {
+        int j = e / N, c = e % N;
+        Q[s2][e] = base[(size_t)j * WT * N + c];
+      }
+      for (int e = tid; e < S.nv * N; e += bd) {
+        int a = e / N, c = e % N;
+        LTV[s2][e] = base[(size_t)(N + a) * WT * N + c];
+      }
+    }
+    __syncthreads();
+    for (int s2 = 0; s2 < 2; ++s2) {
+      const int N = sp[s2]->N;
+      for (int j = tid; j < N; j += bd) {
+        cd x{0.0, 0.0};
+        for (int c = 0; c < N; ++c) cfma(x, Q[s2][j * N + c], Q[s2][c * N + j]);
+        rowv[s2][j] = Q[s2][j * N + j];
+        rowx[s2][j] = x;
+      }
+    }
+    __syncthreads();
+    if (tid < 2) {
+      const int N = sp[tid]->N;
+      cd v{0.0, 0.0}, x{0.0, 0.0};
+      for (int j = 0; j < N; ++j) {
+        v += rowv[tid][j];
+        x += rowx[tid][j];
+      }
+      v0s[tid] = v;
+      ex0s[tid] = x;
+      v0[((size_t)tid * NW + w) * NG + g] = v;
+      ex0[((size_t)tid * NW + w) * NG + g] = x;
+    }
+    __syncthreads();
+    const cd vsum = v0s[0] + v0s[1];
+    for (int s2 = 0; s2 < 2; ++s2) {
+      const DevSpin& S = *sp[s2];
+      const int N = S.N, nv = S.nv, no = S.no;
+      for (int e = tid; e < nv * N; e += bd) {
+        int a = e / N, c = e % N;
+        cd acc = -LTV[s2][e];
+        for (int j = 0; j < N; ++j) cfma(acc, TV[s2][a * N + j], Q[s2][j * N + c]);
+        Lf[e] = acc;
+      }
+      __syncthreads();
+      cd* Lo = Lam[s2] + ((size_t)wl * NG + g) * nv * no;
+#pragma unroll
+      for (int j = 0; j < ZW_PER_THREAD; ++j) {
+        const int e = tid + j * bd;
+        if (e < nv * no) {
+          const int a = e / no, i = e % no, oc = S.oslot[i];
+          cd xi{0.0, 0.0};
+          for (int c = 0; c < N; ++c) cfma(xi, Lf[a * N + c], Q[s2][c * N + oc]);
+          const cd lam = Lf[a * N + oc];
+          Lo[e] = lam;
+          zacc[s2][j] += xi - vsum * lam;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int s2 = 0; s2 < 2; ++s2) {
+    const int X = sp[s2]->nv * sp[s2]->no;
+#pragma unroll
+    for (int j = 0; j < ZW_PER_THREAD; ++j) {
+      const int e = tid + j * bd;
+      if (e < X) ZW[s2][((size_t)wl * n_chunks + chunk) * X + e] = zacc[s2][j];
+    }
+  }
+}
+
+void launch_lambda(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
+                   int g_chunk, const cd* Ta, const cd* Tb, const cd* LTa, const cd* LTb,
+                   cd* Lam_a, cd* Lam_b, cd* v0, cd* ex0, cd* ZWpart_a, cd* ZWpart_b,
+                   hipStream_t st) {
+  const int n_chunks = (NG + g_chunk - 1) / g_chunk;
+  size_t words = 0;
+  int lf = 0;
+  for (const DevSpin* s : {&sa, &sb}) {
+    words += (size_t)s->N * s->N + 2 * (size_t)s->nv * s->N;
+    lf = max(lf, s->nv * s->N);
+  }
+  words += lf;
+  hipLaunchKernelGGL(k_lambda, dim3(WT, n_chunks), dim3(256), words * sizeof(cd), st, sa, sb,
+                     NW, w0, WT, NG, g_chunk, Ta, Tb, LTa, LTb, Lam_a, Lam_b, v0, ex0,
+                     ZWpart_a, ZWpart_b);
+}
+
+// ============================================================================
+// A7: two-body CI coefficients per walker
+// ============================================================================
+
+__global__ void k_pair_coef(DevPairs pr, int NW, const cd* __restrict__ det_c,
+                            const cd* __restrict__ adj_a, int Aa, const cd* __restrict__ adj_b,
+                            int Ab, cd* __restrict__ coef) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= (int64_t)pr.n_pair * NW) return;
+  const int t = (int)(tid % pr.n_pair), w = (int)(tid / pr.n_pair);
+  cd acc{0.0, 0.0};
+  const cd* aa = adj_a + (size_t)w * Aa;
+  const cd* ab = adj_b + (size_t)w * Ab;
+  for (int64_t e = pr.ptr[t]; e < pr.ptr[t + 1]; ++e)
+    cfma(acc, det_c[pr.det[e]] * aa[pr.fa[e]], ab[pr.fb[e]]);
+  coef[(size_t)w * pr.n_pair + t] = acc;
+}
+
+void launch_pair_coef(const DevPairs& pr, int NW, const cd* det_c, const cd* adj_a, int Aa,
+                      const cd* adj_b, int Ab, cd* coef, hipStream_t st) {
+  const int64_t n = (int64_t)pr.n_pair * NW;
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_pair_coef, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pr, NW,
+                     det_c, adj_a, Aa, adj_b, Ab, coef);
+}
+
+__global__ void k_minor_coef(DevSpin s, int NW, const cd* __restrict__ B, int U,
+                             const cd* __restrict__ m2, cd* __restrict__ coef) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= (int64_t)s.n_minor * NW) return;
+  const int t = (int)(tid % s.n_minor), w = (int)(tid / s.n_minor);
+  cd acc{0.0, 0.0};
+  for (int e = s.mn_ptr[t]; e < s.mn_ptr[t + 1]; ++e) {
+    cd v = B[(size_t)w * U + s.mn_str[e]] * m2[(size_t)w * s.M2 + s.mn_m2[e]];
+    if (s.mn_sgn[e] < 0) acc -= v;
+    else acc += v;
+  }
+  coef[(size_t)w * s.n_minor + t] = acc;
+}
+
+void launch_minor_coef(const DevSpin& s, int NW, const cd* B, int U, const cd* m2, cd* coef,
+                       hipStream_t st) {
+  const int64_t n = (int64_t)s.n_minor * NW;
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_minor_coef, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s, NW,
+                     B, U, m2, coef);
+}
+
+// ============================================================================
+// A7: the Cholesky-vector loop.  Per (walker, chunk of Cholesky vectors) the
+// chunk's Lam^a, Lam^b windows are staged in LDS and every touched bilinear
+// term is accumulated: partial = sum_g [ sum_pairs coef Lam^a[x] Lam^b[y]
+//                   + sum_s sum_minors coef (Lam[ai]Lam[bj] - Lam[aj]Lam[bi]) ].
+// ============================================================================
+
+__global__ __launch_bounds__(256) void k_energy_gamma(DevSpin sa, DevSpin sb, DevPairs pr, int NW,
+                                                      int w0, int WT, int NG, int g_chunk,
+                                                      const cd* __restrict__ Lam_a,
+                                                      const cd* __restrict__ Lam_b,
+                                                      const cd* __restrict__ coef_pair,
+                                                      const cd* __restrict__ coef_ma,
+                                                      const cd* __restrict__ coef_mb,
+                                                      cd* __restrict__ partial) {
+  extern __shared__ cd sm[];
+  __shared__ cd red[256];
+  const int wl = blockIdx.x, chunk = blockIdx.y, n_chunks = gridDim.y;
+  const int w = w0 + wl, tid = threadIdx.x, bd = blockDim.x;
+  const int Xa = sa.nv * sa.no, Xb = sb.nv * sb.no;
+  const int g0 = chunk * g_chunk, G = min(NG, g0 + g_chunk) - g0;
+  cd* La = sm;            // [G][Xa]
+  cd* Lb = sm + (size_t)g_chunk * Xa;  // [G][Xb]
+  for (int e = tid; e < G * Xa; e += bd) La[e] = Lam_a[((size_t)wl * NG + g0) * Xa + e];
+  for (int e = tid; e < G * Xb; e += bd) Lb[e] = Lam_b[((size_t)wl * NG + g0) * Xb + e];
+  __syncthreads();
+  cd acc{0.0, 0.0};
+  for (int t = tid; t < pr.n_pair; t += bd) {
+    const int x = pr.x[t], y = pr.y[t];
+    cd s{0.0, 0.0};
+    for (int gl = 0; gl < G; ++gl) cfma(s, La[gl * Xa + x], Lb[gl * Xb + y]);
+    acc += coef_pair[(size_t)w * pr.n_pair + t] * s;
+  }
+  const DevSpin* sp[2] = {&sa, &sb};
+  const cd* Ls[2] = {La, Lb};
+  const cd* cf[2] = {coef_ma, coef_mb};
+  const int Xs[2] = {Xa, Xb};
+  for (int s2 = 0; s2 < 2; ++s2) {
+    const DevSpin& S = *sp[s2];
+    const cd* L = Ls[s2];
+    const int X = Xs[s2];
+    for (int t = tid; t < S.n_minor; t += bd) {
+      const int ai = S.mn_idx[4 * t], bj = S.mn_idx[4 * t + 1];
+      const int aj = S.mn_idx[4 * t + 2], bi = S.mn_idx[4 * t + 3];
+      cd s{0.0, 0.0};
+      for (int gl = 0; gl < G; ++gl) {
+        const cd* Lg = L + gl * X;
+        cfma(s, Lg[ai], Lg[bj]);
+        s -= Lg[aj] * Lg[bi];
+      }
+      acc += cf[s2][(size_t)w * S.n_minor + t] * s;
+    }
+  }
+  cd tot = block_reduce(acc, red);
+  if (tid == 0) partial[(size_t)w * n_chunks + chunk] = tot;
+}
+
+void launch_energy_gamma(const DevSpin& sa, const DevSpin& sb, const DevPairs& pr, int NW,
+                         int w0, int WT, int NG, int g_chunk, const cd* Lam_a, const cd* Lam_b,
+                         const cd* coef_pair, const cd* coef_ma, const cd* coef_mb, cd* partial,
+                         hipStream_t st) {
+  const int n_chunks = (NG + g_chunk - 1) / g_chunk;
+  size_t lds = (size_t)g_chunk * (sa.nv * sa.no + sb.nv * sb.no) * sizeof(cd);
+  hipLaunchKernelGGL(k_energy_gamma, dim3(WT, n_chunks), dim3(256), lds, st, sa, sb, pr, NW,
+                     w0, WT, NG, g_chunk, Lam_a, Lam_b, coef_pair, coef_ma, coef_mb, partial);
+}
+
+// ============================================================================
+// Energy assembly per walker
+// ============================================================================
+
+__global__ __launch_bounds__(256) void k_energy_final(DevSpin sa, DevSpin sb, int NW, int w0,
+                                                      int NG, int n_lchunks, int n_echunks,
+                                                      const cd* __restrict__ obar,
+                                                      const cd* __restrict__ v0,
+                                                      const cd* __restrict__ ex0,
+                                                      const cd* __restrict__ ZWa,
+                                                      const cd* __restrict__ ZWb,
+                                                      const cd* __restrict__ Ca,
+                                                      const cd* __restrict__ Cb,
+                                                      const cd* __restrict__ epart,
+                                                      const cd* __restrict__ oba,
+                                                      const cd* __restrict__ obb, double e0,
+                                                      cd* __restrict__ e_loc) {
+  __shared__ cd red[256];
+  const int wl = blockIdx.x, w = w0 + wl, tid = threadIdx.x, bd = blockDim.x;
+  cd vab{0.0, 0.0}, kk{0.0, 0.0};
+  const cd* va = v0 + (size_t)w * NG;
+  const cd* vb = v0 + ((size_t)NW + w) * NG;
+  const cd* xa = ex0 + (size_t)w * NG;
+  const cd* xb = ex0 + ((size_t)NW + w) * NG;
+  for (int g = tid; g < NG; g += bd) {
+    vab += va[g] * vb[g];
+    kk += va[g] * va[g] - xa[g] + vb[g] * vb[g] - xb[g];
+  }
+  cd first = vab + 0.5 * kk;
+  first = block_reduce(first, red);
+  cd czw{0.0, 0.0};
+  const DevSpin* sp[2] = {&sa, &sb};
+  const cd* ZW[2] = {ZWa, ZWb};
+  const cd* C[2] = {Ca, Cb};
+  for (int s2 = 0; s2 < 2; ++s2) {
+    const int X = sp[s2]->nv * sp[s2]->no;
+    for (int e = tid; e < X; e += bd) {
+      cd z{0.0, 0.0};
+      for (int c = 0; c < n_lchunks; ++c) z += ZW[s2][((size_t)wl * n_lchunks + c) * X + e];
+      czw += C[s2][(size_t)w * X + e] * z;
+    }
+  }
+  for (int c = tid; c < n_echunks; c += bd) czw += epart[(size_t)w * n_echunks + c];
+  czw = block_reduce(czw, red);
+  if (tid == 0) e_loc[w] = cd{e0, 0.0} + oba[w] + obb[w] + first + cdiv(czw, obar[w]);
+}
+
+void launch_energy_final(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
+                         int n_lchunks, int n_echunks, const cd* obar, const cd* v0,
+                         const cd* ex0, const cd* ZWpart_a, const cd* ZWpart_b, const cd* Ca,
+                         const cd* Cb, const cd* epart, const cd* onebody_a,
+                         const cd* onebody_b, double e0, cd* e_loc, hipStream_t st) {
+  hipLaunchKernelGGL(k_energy_final, dim3(WT), dim3(256), 0, st, sa, sb, NW, w0, NG, n_lchunks,
+                     n_echunks, obar, v0, ex0, ZWpart_a, ZWpart_b, Ca, Cb, epart, onebody_a,
+                     onebody_b, e0, e_loc);
+}
+
+// out[g][r][q] = L[g][rows[r]][q]: Cholesky rows restricted to an orbital subset
+__global__ void k_gather_rows(const double* __restrict__ L, int NG, int M,
+                              const int* __restrict__ rows, int P, double* __restrict__ out) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= (int64_t)NG * P * M) return;
+  const int q = (int)(tid % M);
+  const int64_t gr = tid / M;
+  const int r = (int)(gr % P), g = (int)(gr / P);
+  out[tid] = L[((size_t)g * M + rows[r]) * M + q];
+}
+
+void launch_gather_rows(const double* L, int NG, int M, const int* rows, int P, double* out,
+                        hipStream_t st) {
+  const int64_t n = (int64_t)NG * P * M;
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, L, NG,
+                     M, rows, P, out);
+}
+
+void init_wick_attributes() {
+  const int lim = 150 * 1024;
+  hipFuncSetAttribute((const void*)k_ref_inverse, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  hipFuncSetAttribute((const void*)k_green, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  hipFuncSetAttribute((const void*)k_lambda, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  hipFuncSetAttribute((const void*)k_energy_gamma, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+}
+
+}  // namespace msd

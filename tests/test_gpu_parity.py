@@ -1,0 +1,322 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+FP64 bar: 1e-10 relative (log-overlaps compared through exp(difference), force
+biases relative to their largest element, energies relative to max(1, |E|)).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import fock, msd, propagate
+from paper_2406_08314_amd import MsdError, MsdSystem
+from synth import fields_for_step, make_config, make_workload
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def system_for(wl, **kw):
+    s = MsdSystem(wl.M, wl.n_alpha, wl.n_beta, wl.n_chol, wl.n_walkers, wl.n_det, **kw)
+    s.set_hamiltonian(wl.h1, wl.chol, wl.e0)
+    s.set_trial(wl.ci, wl.occ_a, wl.occ_b)
+    s.set_walkers(wl.phi_a, wl.phi_b, wl.weights)
+    return s
+
+
+def assert_logo(gpu, ref, tol=TOL):
+    z = np.exp(np.asarray(gpu) - np.asarray(ref))
+    assert np.max(np.abs(z - 1)) <= tol, np.max(np.abs(z - 1))
+
+
+def assert_rel(gpu, ref, tol=TOL, floor=1.0):
+    gpu, ref = np.asarray(gpu), np.asarray(ref)
+    scale = max(floor, float(np.max(np.abs(ref))))
+    err = float(np.max(np.abs(gpu - ref)))
+    assert err <= tol * scale, (err, scale)
+
+
+def oracle_walker(wl, w, dt, energy=True):
+    r = msd.measure(wl.h1, wl.chol, wl.e0, wl.ci, wl.occ_a, wl.occ_b, wl.phi_a, wl.phi_b, dt,
+                    walkers=[w], energy=energy)
+    return {k: v[0] for k, v in r.items()}
+
+
+def compare_walkers(wl, out, walkers, dt, energy=True, sys_=None):
+    for w in walkers:
+        ref = oracle_walker(wl, w, dt, energy)
+        assert_logo(out["log_ovlp"][w], ref["log_ovlp"])
+        assert_rel(out["force_bias"][w], ref["force_bias"], floor=0.0)
+        if energy:
+            assert_rel(out["e_loc"][w], ref["e_loc"])
+        if sys_ is not None:
+            ga, gb = sys_.get_green(w)
+            ra, rb = msd.green(wl.ci, wl.occ_a, wl.occ_b, wl.phi_a[w], wl.phi_b[w])
+            assert_rel(ga, ra)
+            assert_rel(gb, rb)
+
+
+# ----------------------------------------------------------------------------
+# measurement
+# ----------------------------------------------------------------------------
+
+def test_tiny_measure_all_walkers():
+    wl = make_config("tiny")
+    s = system_for(wl)
+    out = s.measure(wl.dt)
+    compare_walkers(wl, out, range(wl.n_walkers), wl.dt, sys_=s)
+    # set_walkers stored the same log-overlaps
+    _, _, w, lo = s.get_walkers()
+    assert_logo(lo, out["log_ovlp"], 1e-13)
+    np.testing.assert_array_equal(w, wl.weights)
+
+
+def test_tiny_measure_is_reproducible():
+    wl = make_config("tiny")
+    s = system_for(wl)
+    a = s.measure(wl.dt)
+    b = s.measure(wl.dt)
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k])
+
+
+def test_medium_full_batch_sampled_walkers():
+    wl = make_config("medium")
+    s = system_for(wl)
+    out = s.measure(wl.dt)
+    lo_ref = np.array([np.log(msd.trial_overlap(wl.ci, wl.occ_a, wl.occ_b, wl.phi_a[w], wl.phi_b[w]))
+                       for w in range(wl.n_walkers)])
+    assert_logo(out["log_ovlp"], lo_ref)
+    compare_walkers(wl, out, [0, 77, 127], wl.dt, sys_=s)
+
+
+def test_medium_flat_coefficients():
+    wl = make_config("medium", c_law="flat", n_walkers=16, n_det=400)
+    s = system_for(wl)
+    out = s.measure(wl.dt)
+    compare_walkers(wl, out, [3, 15], wl.dt)
+
+
+@pytest.mark.parametrize("na,nb,kmax,window,nd", [(6, 5, 10, (6, 8), 60), (4, 2, 6, (4, 6), 60),
+                                                 (3, 0, 3, (3, 5), 40)])
+def test_high_order_unequal_spins_complex_ci(na, nb, kmax, window, nd):
+    wl = make_workload("edge", M=16, n_alpha=na, n_beta=nb, n_chol=20, n_det=nd, k_max=kmax,
+                       window=window, c_law="flat", n_walkers=5, seed=77 + na, complex_ci=True,
+                       noise=0.5)
+    s = system_for(wl)
+    out = s.measure(0.01)
+    compare_walkers(wl, out, range(5), 0.01, sys_=s)
+
+
+def test_single_determinant():
+    wl = make_config("tiny", n_det=1)
+    s = system_for(wl)
+    out = s.measure(wl.dt)
+    compare_walkers(wl, out, range(wl.n_walkers), wl.dt, sys_=s)
+
+
+def test_duplicate_rows_and_zero_coefficients():
+    wl = make_config("tiny", complex_ci=True)
+    base = system_for(wl).measure(wl.dt)
+    ci = np.concatenate([wl.ci, [0.0, wl.ci[5] / 2]])
+    ci[5] = wl.ci[5] / 2
+    oa = np.concatenate([wl.occ_a, wl.occ_a[7:8], wl.occ_a[5:6]])
+    ob = np.concatenate([wl.occ_b, wl.occ_b[2:3], wl.occ_b[5:6]])
+    s = MsdSystem(wl.M, 3, 3, wl.n_chol, wl.n_walkers, len(ci))
+    s.set_hamiltonian(wl.h1, wl.chol, wl.e0)
+    s.set_trial(ci, oa, ob)
+    s.set_walkers(wl.phi_a, wl.phi_b)
+    out = s.measure(wl.dt)
+    assert_logo(out["log_ovlp"], base["log_ovlp"], 1e-12)
+    assert_rel(out["force_bias"], base["force_bias"], 1e-12, floor=0.0)
+    assert_rel(out["e_loc"], base["e_loc"], 1e-12)
+
+
+def test_walker_equal_to_reference_fock():
+    """Every excitation block X is exactly zero (or singular); the adjugate and
+    minor forms must still give the exact G and E_L (Fock-space oracle)."""
+    rng = np.random.default_rng(101)
+    M, na, nb = 5, 2, 2
+    h1 = rng.standard_normal((M, M))
+    h1 = (h1 + h1.T) / 2
+    chol = rng.standard_normal((4, M, M)) * 0.4
+    chol = (chol + chol.transpose(0, 2, 1)) / 2
+    oa = np.array([[0, 1], [0, 2], [1, 3], [2, 4], [0, 1], [3, 4]], np.int32)
+    ob = np.array([[0, 1], [0, 1], [0, 4], [2, 3], [1, 2], [0, 3]], np.int32)
+    ci = rng.standard_normal(6) + 1j * rng.standard_normal(6)
+    u = np.linalg.qr(rng.standard_normal((2, 2)) + 1j * rng.standard_normal((2, 2)))[0]
+    pa = np.stack([np.eye(M)[:, :na] @ u, np.eye(M)[:, :na]]).astype(complex)
+    pb = np.stack([np.eye(M)[:, :nb], np.eye(M)[:, :nb] @ u]).astype(complex)
+    s = MsdSystem(M, na, nb, 4, 2, 6)
+    s.set_hamiltonian(h1, chol, 0.1)
+    s.set_trial(ci, oa, ob)
+    s.set_walkers(pa, pb)
+    out = s.measure(0.01)
+    fs = fock.FockSpace(M)
+    H = fs.hamiltonian(h1, fock.eri_from_chol(chol), 0.1)
+    psi = fs.trial(ci, oa, ob)
+    for w in range(2):
+        phi = fs.slater(pa[w], pb[w])
+        o = np.vdot(psi, phi)
+        assert_logo(out["log_ovlp"][w], np.log(o), 1e-12)
+        e_ref = np.vdot(psi, H @ phi) / o
+        assert_rel(out["e_loc"][w], e_ref, 1e-11)
+        ga, gb = s.get_green(w)
+        for spin, g in ((0, ga), (1, gb)):
+            for p in range(M):
+                for q in range(M):
+                    ref = np.vdot(psi, fs.cdag(p, spin) @ fs.ann(q, spin) @ phi) / o
+                    assert abs(g[p, q] - ref) < 1e-11
+
+
+def test_fci_trial_zero_variance_on_gpu():
+    rng = np.random.default_rng(5)
+    M, na, nb = 5, 2, 2
+    h1 = rng.standard_normal((M, M))
+    h1 = (h1 + h1.T) / 2
+    chol = rng.standard_normal((5, M, M)) * 0.4
+    chol = (chol + chol.transpose(0, 2, 1)) / 2
+    fs = fock.FockSpace(M)
+    H = fs.hamiltonian(h1, fock.eri_from_chol(chol), -0.7)
+    e_fci, vec = fs.ground_state(H, na, nb)
+    ci, oa, ob = fs.expansion(vec, na, nb)
+    # put the largest coefficient first (the Wick reference)
+    order = np.argsort(-np.abs(ci), kind="stable")
+    ci, oa, ob = ci[order], oa[order], ob[order]
+    nw = 6
+    pa = rng.standard_normal((nw, M, na)) + 1j * rng.standard_normal((nw, M, na))
+    pb = rng.standard_normal((nw, M, nb)) + 1j * rng.standard_normal((nw, M, nb))
+    s = MsdSystem(M, na, nb, 5, nw, len(ci))
+    s.set_hamiltonian(h1, chol, -0.7)
+    s.set_trial(ci, oa, ob)
+    s.set_walkers(pa, pb)
+    out = s.measure(0.01)
+    assert np.max(np.abs(out["e_loc"] - e_fci)) < 1e-10
+
+
+# ----------------------------------------------------------------------------
+# propagation
+# ----------------------------------------------------------------------------
+
+def run_oracle_steps(wl, walkers, n_steps, dt, stabilize, e_shift=0.0):
+    idx = list(walkers)
+    pa, pb = wl.phi_a[idx].copy(), wl.phi_b[idx].copy()
+    wts = wl.weights[idx].copy()
+    lo = np.array([np.log(msd.trial_overlap(wl.ci, wl.occ_a, wl.occ_b, pa[i], pb[i]))
+                   for i in range(len(idx))])
+    b1 = propagate.one_body_half_step(wl.h1, wl.chol, dt)
+    for step in range(n_steps):
+        x = fields_for_step(wl, step)[idx]
+        do_qr = stabilize > 0 and (step + 1) % stabilize == 0
+        pa, pb, wts, lo, _ = propagate.step(wl.h1, wl.chol, wl.ci, wl.occ_a, wl.occ_b, pa, pb,
+                                             wts, lo, x, dt, e_shift=e_shift, do_qr=do_qr, b1=b1)
+    return pa, pb, wts, lo
+
+
+@pytest.mark.parametrize("stabilize", [2, 0])
+def test_tiny_propagation_matches_oracle(stabilize):
+    wl = make_config("tiny")
+    s = system_for(wl, stabilize_freq=stabilize)
+    n_steps = 6
+    fields = np.stack([fields_for_step(wl, k) for k in range(n_steps)])
+    s.propagate(fields, wl.dt, e_shift=0.3)
+    pa, pb, w, lo = s.get_walkers()
+    ra, rb, rw, rlo = run_oracle_steps(wl, range(wl.n_walkers), n_steps, wl.dt, stabilize, 0.3)
+    assert_rel(pa, ra, 1e-10)
+    assert_rel(pb, rb, 1e-10)
+    assert_rel(w, rw, 1e-10)
+    assert_logo(lo, rlo, 1e-10)
+
+
+def test_medium_ten_steps_sampled_walkers():
+    wl = make_config("medium")
+    s = system_for(wl, stabilize_freq=5)
+    n_steps = 10
+    fields = np.stack([fields_for_step(wl, k) for k in range(n_steps)])
+    s.propagate(fields, wl.dt)
+    pa, pb, w, lo = s.get_walkers()
+    sample = [0, 64, 127]
+    ra, rb, rw, rlo = run_oracle_steps(wl, sample, n_steps, wl.dt, 5)
+    assert_rel(pa[sample], ra, 1e-10)
+    assert_rel(pb[sample], rb, 1e-10)
+    assert_rel(w[sample], rw, 1e-10)
+    assert_logo(lo[sample], rlo, 1e-10)
+    # orthonormal after the last QR (walkers removed by the phaseless
+    # constraint are frozen where they were)
+    for i in sample:
+        if w[i] == 0.0:
+            continue
+        np.testing.assert_allclose(pa[i].conj().T @ pa[i], np.eye(wl.n_alpha), atol=1e-12)
+
+
+def test_frozen_walker_stays_put():
+    wl = make_config("tiny")
+    wts = wl.weights.copy()
+    wts[2] = 0.0
+    s = MsdSystem(wl.M, 3, 3, wl.n_chol, wl.n_walkers, wl.n_det, stabilize_freq=1)
+    s.set_hamiltonian(wl.h1, wl.chol, wl.e0)
+    s.set_trial(wl.ci, wl.occ_a, wl.occ_b)
+    s.set_walkers(wl.phi_a, wl.phi_b, wts)
+    _, _, _, lo0 = s.get_walkers()
+    s.propagate(fields_for_step(wl, 0), wl.dt)
+    pa, pb, w, lo = s.get_walkers()
+    np.testing.assert_array_equal(pa[2], wl.phi_a[2])
+    assert w[2] == 0.0 and lo[2] == lo0[2]
+
+
+# ----------------------------------------------------------------------------
+# boundary behaviour
+# ----------------------------------------------------------------------------
+
+def test_device_entry_points_match_host():
+    torch = pytest.importorskip("torch")
+    wl = make_config("tiny")
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream().cuda_stream
+    s = MsdSystem(wl.M, 3, 3, wl.n_chol, wl.n_walkers, wl.n_det, stream=stream)
+    s.set_hamiltonian(wl.h1, wl.chol, wl.e0)
+    s.set_trial(wl.ci, wl.occ_a, wl.occ_b)
+    s.set_walkers_dev(torch.from_numpy(wl.phi_a).to(dev), torch.from_numpy(wl.phi_b).to(dev),
+                      torch.from_numpy(wl.weights).to(dev))
+    lo = torch.empty(wl.n_walkers, dtype=torch.complex128, device=dev)
+    fb = torch.empty(wl.n_walkers, wl.n_chol, dtype=torch.complex128, device=dev)
+    el = torch.empty(wl.n_walkers, dtype=torch.complex128, device=dev)
+    s.measure_dev(wl.dt, lo, fb, el)
+    torch.cuda.synchronize()
+    host = system_for(wl).measure(wl.dt)
+    np.testing.assert_array_equal(lo.cpu().numpy(), host["log_ovlp"])
+    np.testing.assert_array_equal(fb.cpu().numpy(), host["force_bias"])
+    np.testing.assert_array_equal(el.cpu().numpy(), host["e_loc"])
+    x = torch.from_numpy(np.stack([fields_for_step(wl, k) for k in range(3)])).to(dev)
+    s.propagate_dev(x, wl.dt, 0.0, 3)
+    torch.cuda.synchronize()
+    h = system_for(wl)
+    h.propagate(x.cpu().numpy(), wl.dt)
+    a = s.get_walkers()
+    b = h.get_walkers()
+    for u, v in zip(a, b):
+        np.testing.assert_array_equal(u, v)
+
+
+def test_error_paths():
+    wl = make_config("tiny")
+    s = MsdSystem(wl.M, 3, 3, wl.n_chol, wl.n_walkers, wl.n_det)
+    with pytest.raises(MsdError) as e:
+        s.measure(0.01)
+    assert e.value.name == "MSD_ERR_STATE"
+    s.set_hamiltonian(wl.h1, wl.chol, 0.0)
+    s.set_trial(wl.ci, wl.occ_a, wl.occ_b)
+    bad = wl.phi_a.copy()
+    bad[4, :3, :] = 0.0  # walker 4: zero reference block
+    with pytest.raises(MsdError) as e:
+        s.set_walkers(bad, wl.phi_b)
+    assert e.value.name == "MSD_ERR_SINGULAR" and "walker 4" in str(e.value)
+    with pytest.raises(MsdError) as e:
+        s.set_trial(wl.ci, np.where(wl.occ_a == 0, 99, wl.occ_a), wl.occ_b)
+    assert e.value.name == "MSD_ERR_TRIAL"
+    h = wl.h1.copy()
+    h[0, 1] += 1.0
+    with pytest.raises(MsdError) as e:
+        s.set_hamiltonian(h, wl.chol, 0.0)
+    assert e.value.name == "MSD_ERR_ARG"
