@@ -78,11 +78,13 @@ typedef struct {
   int32_t n_taylor;       /* Taylor order of exp(VHS) (terms 0..n_taylor), default 6 */
   int32_t stabilize_freq; /* QR every this many propagate steps (0 = never), default 5 */
   int32_t timing;         /* 1: record HIP events around every kernel stage   */
-  int32_t reserved[5];
+  int32_t energy_algo;    /* same-spin second-order energy terms: 0 = choose per spin
+                             (fewest gathers), 1 = per-minor lists, 2 = per-string   */
+  int32_t reserved[4];
 } msd_options;
 
 /* Limits of this implementation. */
-#define MSD_MAX_ELECTRONS 128   /* per spin                                   */
+#define MSD_MAX_ELECTRONS 64    /* per spin (reference inverse and QR in LDS)  */
 #define MSD_MAX_EXCITATION 8    /* holes per spin per determinant             */
 
 const char* msd_status_string(msd_status s);
@@ -99,7 +101,8 @@ msd_status msd_create(const msd_dims* d, const msd_options* o, int32_t device,
                       void* hip_stream, msd_system** out);
 void msd_destroy(msd_system* sys);
 
-/* Hamiltonian (Eqs. 2-4).  h1: M*M doubles.  chol: n_chol*M*M doubles, row
+/* Hamiltonian (Sec. II.A: Eq. 2 one-body h and E0, Eq. 3 Cholesky vectors,
+ * Eq. 4 h' for the propagator).  h1: M*M doubles.  chol: n_chol*M*M doubles, row
  * g*M*M + p*M + q = L^g_pq.  Both must be symmetric to 1e-12 (MSD_ERR_ARG
  * names the first offending index otherwise).  Precomputes h' and the
  * one-body half-step factor for the time step passed to msd_propagate. */
@@ -128,19 +131,23 @@ msd_status msd_set_walkers_dev(msd_system* sys, const double* phi_a, const doubl
 msd_status msd_get_walkers(msd_system* sys, double* phi_a, double* phi_b, double* weights,
                            double* log_ovlp);
 
-/* Measurement of every walker: log_ovlp (n_walkers complex), force_bias
+/* Measurement (Eq. 13/15 overlap, Eq. 14 mixed Green's function, Eq. 7 force
+ * bias, the mixed-estimator local energy of Sec. II.A evaluated by the
+ * generalised Wick theorem of Sec. III) of every walker: log_ovlp (n_walkers complex), force_bias
  * (n_walkers*n_chol complex, [w][g], uses time step dt), e_loc (n_walkers
  * complex).  Any output may be NULL; the energy stages run only if e_loc is
  * non-NULL.  Host pointers; synchronises the stream. */
 msd_status msd_measure(msd_system* sys, double dt, double* log_ovlp, double* force_bias,
                        double* e_loc);
-/* Same with device output pointers; stream-ordered, does not synchronise
- * (MSD_ERR_SINGULAR for a zero reference overlap is then reported by the
- * next synchronising call). */
+/* Same with device output pointers; stream-ordered, does not synchronise.
+ * No singularity check is made here: a walker with a singular reference block
+ * or zero trial overlap gets log_ovlp = (-inf, 0) and non-finite G-derived
+ * outputs. */
 msd_status msd_measure_dev(msd_system* sys, double dt, double* log_ovlp, double* force_bias,
                            double* e_loc);
 
-/* n_steps propagation steps.  fields: n_steps*n_walkers*n_chol doubles,
+/* n_steps propagation steps (Eq. 5 with the first-order split, Eqs. 8-12
+ * phaseless weights, periodic re-orthonormalisation as in Listing 1).  fields: n_steps*n_walkers*n_chol doubles,
  * standard-normal auxiliary fields, [step][w][g] (host).  Each step: force
  * bias, VHS, Taylor propagator with one-body half steps, new overlap,
  * phaseless weight update, and QR every stabilize_freq steps (counted over
@@ -151,7 +158,7 @@ msd_status msd_propagate(msd_system* sys, const double* fields, double dt, doubl
 msd_status msd_propagate_dev(msd_system* sys, const double* fields, double dt,
                              double e_shift, int32_t n_steps);
 
-/* Green's functions of one walker (M*M complex each, G_pq at [p][q]) from
+/* Green's functions (Eq. 14) of one walker (M*M complex each, G_pq at [p][q]) from
  * the most recent measure or propagate evaluation. */
 msd_status msd_get_green(msd_system* sys, int32_t walker, double* g_a, double* g_b);
 
@@ -163,7 +170,7 @@ msd_status msd_get_timings(msd_system* sys, int32_t max_stages, const char** nam
 msd_status msd_reset_timings(msd_system* sys);
 
 /* Host-only excitation analysis of a trial (no device needed), for checking
- * the trial builder.  Per determinant: k_a/k_b = holes per spin, sign = the
+ * the trial builder (excitations relative to the reference, Sec. II.B).  Per determinant: k_a/k_b = holes per spin, sign = the
  * product of both spins' excitation signs (+1/-1; the sign of the permutation
  * that sorts the reference with each hole replaced by its particle, holes
  * and particles each ascending).  Returns MSD_ERR_TRIAL like set_trial_occ. */

@@ -23,7 +23,7 @@ class MsdDims(C.Structure):
 
 class MsdOptions(C.Structure):
     _fields_ = [("n_taylor", C.c_int32), ("stabilize_freq", C.c_int32), ("timing", C.c_int32),
-                ("reserved", C.c_int32 * 5)]
+                ("energy_algo", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
 _dp = C.POINTER(C.c_double)

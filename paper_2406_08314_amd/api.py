@@ -39,7 +39,8 @@ class MsdSystem:
 
     def __init__(self, M: int, n_alpha: int, n_beta: int, n_chol: int, n_walkers: int,
                  n_det: int, device: int = 0, stream: Optional[int] = None,
-                 n_taylor: int = 6, stabilize_freq: int = 5, timing: bool = False):
+                 n_taylor: int = 6, stabilize_freq: int = 5, timing: bool = False,
+                 energy_algo: int = 0):
         self.lib = _lib.load()
         self.dims = _lib.MsdDims(M, n_alpha, n_beta, n_chol, n_walkers, 0, n_det)
         opts = _lib.MsdOptions()
@@ -47,6 +48,7 @@ class MsdSystem:
         opts.n_taylor = n_taylor
         opts.stabilize_freq = stabilize_freq
         opts.timing = 1 if timing else 0
+        opts.energy_algo = int(energy_algo)
         self.M, self.na, self.nb, self.ng, self.nw, self.nd = (
             M, n_alpha, n_beta, n_chol, n_walkers, n_det)
         h = C.c_void_p()

@@ -124,9 +124,17 @@ struct msd_system {
   cd* logo_tmp = nullptr;
   cd* eloc = nullptr;
   cd* onebody = nullptr;   // [2][NW]
+  cd* segp[2] = {nullptr, nullptr};  // CI-weight segment partials
+  double* fb_ws = nullptr;           // split-K workspace of the force-bias GEMM
+  int fb_splitk = 1;
 
   // energy work (lazily sized)
-  int WT = 0, gl_chunk = 16, n_lchunks = 0, ge_chunk = 8, n_echunks = 0;
+  int WT = 0, gl_chunk = 16, n_lchunks = 0;
+  // second-order energy plan: per-spin algorithm and partial slots
+  int gsplit = 1, n_slots = 0, slot_pairs = 0;
+  bool use_strings[2] = {false, false};
+  int slot_str[2][msd::KMAX + 1] = {{0}};
+  int slot_min[2] = {0, 0};
   cd* LT[2] = {nullptr, nullptr};
   cd* Lam[2] = {nullptr, nullptr};
   cd* v0 = nullptr;
@@ -142,6 +150,7 @@ struct msd_system {
   cd* term[2] = {nullptr, nullptr};
   cd* acc = nullptr;
   int* mask = nullptr;
+  double* qr_ldet = nullptr;  // [NW][2] log det R per spin
   double* fields = nullptr;  // staging for host fields [NW][NG]
 
   // timing
@@ -286,9 +295,38 @@ void alloc_energy(msd_system* s) {
   s->WT = wt;
   s->gl_chunk = 16;
   s->n_lchunks = (NG + s->gl_chunk - 1) / s->gl_chunk;
-  const int X = A.nv * A.no + B.nv * B.no;
-  s->ge_chunk = std::max(1, std::min(NG, (int)((120 * 1024) / (std::max(X, 1) * sizeof(cd)))));
-  s->n_echunks = (NG + s->ge_chunk - 1) / s->ge_chunk;
+  // split the Cholesky range so the second-order kernels have ~512+ workgroups
+  s->gsplit = std::max(1, std::min((512 + wt - 1) / wt, std::max(1, NG / 8)));
+  int slot = 0;
+  s->slot_pairs = slot;
+  slot += msd::energy_pair_blocks(s->dp.n_pair) * s->gsplit;
+  for (int sp = 0; sp < 2; ++sp) {
+    const msd::DevSpin& D = s->ds[sp];
+    const msd::SpinTable& S = s->tt.s[sp];
+    // LDS gathers per Cholesky vector: k^2 per string vs 4 per distinct minor
+    long g_str = 0;
+    bool big = false;
+    for (int i = 0; i < S.U; ++i) {
+      if (S.k[i] >= 2) g_str += (long)S.k[i] * S.k[i];
+      if (S.k[i] > 4) big = true;
+    }
+    const long g_min = 4L * S.n_minor;
+    bool strings = g_str < g_min;
+    if (s->o.energy_algo == 1) strings = false;
+    if (s->o.energy_algo == 2) strings = true;
+    if (big) strings = false;  // orders above 4 only in the minor-list form
+    s->use_strings[sp] = strings;
+    if (strings) {
+      for (int k = 2; k <= 4; ++k) {
+        s->slot_str[sp][k] = slot;
+        slot += msd::energy_string_blocks(D, k) * s->gsplit;
+      }
+    } else {
+      s->slot_min[sp] = slot;
+      slot += msd::energy_minor_blocks(D) * s->gsplit;
+    }
+  }
+  s->n_slots = slot;  // every slot is written by exactly one workgroup
   Arena& E = s->energy_mem;
   for (int sp = 0; sp < 2; ++sp) {
     const msd::DevSpin& D = s->ds[sp];
@@ -300,7 +338,7 @@ void alloc_energy(msd_system* s) {
   s->v0 = E.get<cd>((size_t)2 * NW * NG);
   s->ex0 = E.get<cd>((size_t)2 * NW * NG);
   s->coefAB = E.get<cd>((size_t)NW * s->dp.n_pair);
-  s->epart = E.get<cd>((size_t)NW * s->n_echunks);
+  s->epart = E.get<cd>((size_t)NW * std::max(s->n_slots, 1));
 }
 
 void need_ready(msd_system* s) {
@@ -327,16 +365,14 @@ void check_flags(msd_system* s, const char* what) {
 // A1 + A3: T, log det A, per-string dets/adjugates (minors if requested),
 // Obar and log <Psi_T|Phi> into `logo_out`.
 void run_overlap(msd_system* s, bool minors, cd* logo_out) {
-  for (int sp = 0; sp < 2; ++sp)
-    s->timed(ST_REF, [&] {
-      msd::launch_ref_inverse(s->phi, s->M, s->Ntot, s->NW, s->ds[sp], s->sw[sp].T,
-                              s->sw[sp].logdetA, s->flag, s->st);
-    });
-  for (int sp = 0; sp < 2; ++sp)
-    s->timed(ST_STR, [&] {
-      msd::launch_strings(s->ds[sp], s->sw[sp].T, s->NW, minors, s->sw[sp].d, s->sw[sp].adj,
-                          s->sw[sp].m2, s->st);
-    });
+  s->timed(ST_REF, [&] {
+    msd::launch_ref_inverse(s->phi, s->M, s->Ntot, s->NW, s->ds[0], s->ds[1], s->sw[0].T,
+                            s->sw[1].T, s->sw[0].logdetA, s->sw[1].logdetA, s->flag, s->st);
+  });
+  s->timed(ST_STR, [&] {
+    msd::launch_strings(s->ds[0], s->ds[1], s->sw[0].T, s->sw[1].T, s->NW, minors, s->sw[0],
+                        s->sw[1], s->st);
+  });
   s->timed(ST_OVLP, [&] {
     msd::launch_ovlp_partial(s->ND, s->NW, s->ds[0].det_s, s->ds[1].det_s, s->det_c,
                              s->sw[0].d, s->ds[0].U, s->sw[1].d, s->ds[1].U, s->opart,
@@ -350,22 +386,15 @@ void run_overlap(msd_system* s, bool minors, cd* logo_out) {
 
 // A4 + A5: CI weights, CI matrices, Green's rows, force bias into s->xbar.
 void run_green_fb(msd_system* s, double dt) {
-  for (int sp = 0; sp < 2; ++sp) {
-    const int o = 1 - sp;
-    s->timed(ST_CIW, [&] {
-      msd::launch_ci_weights(s->ds[sp], s->ds[o].det_s, s->det_c, s->sw[o].d, s->ds[o].U, s->NW,
-                             s->sw[sp].B, s->st);
-    });
-  }
-  for (int sp = 0; sp < 2; ++sp)
-    s->timed(ST_CIM, [&] {
-      msd::launch_ci_matrix(s->ds[sp], s->NW, s->sw[sp].adj, s->sw[sp].B, s->sw[sp].C, s->st);
-    });
-  for (int sp = 0; sp < 2; ++sp)
-    s->timed(ST_GREEN, [&] {
-      msd::launch_green(s->ds[sp], s->M, s->NW, s->sw[sp].T, s->sw[sp].C, s->obar, s->h1,
-                        s->sw[sp].G, s->onebody + (size_t)sp * s->NW, s->st);
-    });
+  s->timed(ST_CIW, [&] {
+    msd::launch_ci_weights(s->ds[0], s->ds[1], s->det_c, s->sw[0], s->sw[1], s->segp[0],
+                           s->segp[1], s->NW, s->st);
+  });
+  s->timed(ST_CIM, [&] { msd::launch_ci_matrix(s->ds[0], s->ds[1], s->NW, s->sw[0], s->sw[1], s->st); });
+  s->timed(ST_GREEN, [&] {
+    msd::launch_green(s->ds[0], s->ds[1], s->M, s->NW, s->sw[0], s->sw[1], s->onebody,
+                      s->onebody + s->NW, s->obar, s->h1, s->st);
+  });
   s->timed(ST_GREEN, [&] {
     msd::launch_green_sum(s->M, s->NW, s->P_all, s->rmap[0], s->rmap[1], s->ds[0].P,
                           s->ds[1].P, s->sw[0].G, s->sw[1].G, s->Gp, s->st);
@@ -383,6 +412,8 @@ void run_green_fb(msd_system* s, double dt) {
     g.b_kmaj = true;
     g.C = s->xraw;
     g.ldc = 2 * s->NW;
+    g.splitk = s->fb_splitk;
+    g.ws = s->fb_ws;
     msd::launch_gemm(g, s->st);
     msd::launch_xbar(s->NW, s->NG, s->xraw, std::sqrt(dt), s->xbar, s->st);
   });
@@ -398,8 +429,9 @@ void run_energy(msd_system* s) {
     msd::launch_pair_coef(s->dp, s->NW, s->det_c, s->sw[0].adj, A.A, s->sw[1].adj, B.A,
                           s->coefAB, s->st);
     for (int sp = 0; sp < 2; ++sp)
-      msd::launch_minor_coef(s->ds[sp], s->NW, s->sw[sp].B, s->ds[sp].U, s->sw[sp].m2,
-                             s->coef2[sp], s->st);
+      if (!s->use_strings[sp])
+        msd::launch_minor_coef(s->ds[sp], s->NW, s->sw[sp].B, s->ds[sp].U, s->sw[sp].m2,
+                               s->coef2[sp], s->st);
   });
   for (int w0 = 0; w0 < s->NW; w0 += s->WT) {
     const int wt = std::min(s->WT, s->NW - w0);
@@ -428,11 +460,25 @@ void run_energy(msd_system* s) {
                          s->ZWp[1], s->st);
     });
     s->timed(ST_EGAMMA, [&] {
-      msd::launch_energy_gamma(A, B, s->dp, s->NW, w0, wt, s->NG, s->ge_chunk, s->Lam[0],
-                               s->Lam[1], s->coefAB, s->coef2[0], s->coef2[1], s->epart, s->st);
+      const int Xa = A.nv * A.no, Xb = B.nv * B.no;
+      msd::launch_energy_pairs(s->dp, Xa, Xb, s->NW, w0, wt, s->NG, s->gsplit, s->Lam[0],
+                               s->Lam[1], s->coefAB, s->epart, s->n_slots, s->slot_pairs, s->st);
+      for (int sp = 0; sp < 2; ++sp) {
+        const msd::DevSpin& D = s->ds[sp];
+        if (D.nv * D.no == 0) continue;
+        if (s->use_strings[sp]) {
+          for (int k = 2; k <= 4; ++k)
+            msd::launch_energy_strings(D, k, s->NW, w0, wt, s->NG, s->gsplit, s->Lam[sp],
+                                       s->sw[sp].m2, s->sw[sp].B, s->epart, s->n_slots,
+                                       s->slot_str[sp][k], s->st);
+        } else {
+          msd::launch_energy_minors(D, s->NW, w0, wt, s->NG, s->gsplit, s->Lam[sp], s->coef2[sp],
+                                    s->epart, s->n_slots, s->slot_min[sp], s->st);
+        }
+      }
     });
     s->timed(ST_EFINAL, [&] {
-      msd::launch_energy_final(A, B, s->NW, w0, wt, s->NG, s->n_lchunks, s->n_echunks, s->obar,
+      msd::launch_energy_final(A, B, s->NW, w0, wt, s->NG, s->n_lchunks, s->n_slots, s->obar,
                                s->v0, s->ex0, s->ZWp[0], s->ZWp[1], s->sw[0].C, s->sw[1].C,
                                s->epart, s->onebody, s->onebody + s->NW, s->e0, s->eloc,
                                s->st);
@@ -557,8 +603,7 @@ void propagate_impl(msd_system* s, const double* fields_dev, double dt, double e
     s->steps_done++;
     if (s->o.stabilize_freq > 0 && s->steps_done % s->o.stabilize_freq == 0) {
       s->timed(ST_QR, [&] {
-        msd::launch_qr(s->phi, M, Ntot, NW, s->na, 0, s->mask, s->logo, s->st);
-        msd::launch_qr(s->phi, M, Ntot, NW, s->nb, s->na, s->mask, s->logo, s->st);
+        msd::launch_qr(s->phi, M, Ntot, NW, s->na, s->nb, s->mask, s->qr_ldet, s->logo, s->st);
       });
     }
     s->check_launch("propagate");
@@ -640,7 +685,8 @@ msd_status msd_create(const msd_dims* d, const msd_options* o, int32_t device, v
   msd_options opt;
   msd_default_options(&opt);
   if (o) opt = *o;
-  if (opt.n_taylor < 0 || opt.n_taylor > 32 || opt.stabilize_freq < 0)
+  if (opt.n_taylor < 0 || opt.n_taylor > 32 || opt.stabilize_freq < 0 || opt.energy_algo < 0 ||
+      opt.energy_algo > 2)
     fail(MSD_ERR_ARG, "invalid options");
   sys = new msd_system();
   sys->dev = device;
@@ -667,6 +713,7 @@ msd_status msd_create(const msd_dims* d, const msd_options* o, int32_t device, v
     sys->obar = A.get<cd>(NW);
     sys->flag = A.get<int>(NW);
     sys->mask = A.get<int>(NW);
+    sys->qr_ldet = A.get<double>(2 * (size_t)NW);
     sys->xraw = A.get<double>((size_t)NG * 2 * NW);
     sys->xbar = A.get<cd>((size_t)NW * NG);
     sys->eloc = A.get<cd>(NW);
@@ -779,19 +826,19 @@ msd_status msd_set_trial_occ(msd_system* sys, const double* ci, const int32_t* o
   for (int sp = 0; sp < 2; ++sp) {
     const msd::SpinTable& S = tt.s[sp];
     const size_t X = (size_t)S.nv() * S.no();
-    if (X > 256 * 4)
+    if (X > 64 * 16)
       fail(MSD_ERR_UNSUPPORTED, "excitation window too large (n_vir_act * n_occ_act > 1024)");
     const size_t green_lds = (X + (size_t)S.nv() * S.N + (size_t)S.nv() * 64) * sizeof(cd);
     if (green_lds > 140 * 1024) fail(MSD_ERR_UNSUPPORTED, "excitation window too large for LDS");
   }
   {
-    size_t words = 0, lf = 0;
-    for (int sp = 0; sp < 2; ++sp) {
-      const msd::SpinTable& S = tt.s[sp];
-      words += (size_t)S.N * S.N + 2 * (size_t)S.nv() * S.N;
-      lf = std::max(lf, (size_t)S.nv() * S.N);
-    }
-    if ((words + lf) * sizeof(cd) > 140 * 1024)
+    const msd::SpinTable& A = tt.s[0];
+    const msd::SpinTable& B = tt.s[1];
+    const size_t words = (size_t)A.nv() * A.N + (size_t)B.nv() * B.N +
+                         std::max((size_t)A.N * A.N, (size_t)B.N * B.N) +
+                         std::max((size_t)A.nv() * A.N, (size_t)B.nv() * B.N) +
+                         (size_t)A.nv() * A.no() + (size_t)B.nv() * B.no();
+    if (words * sizeof(cd) > 140 * 1024)
       fail(MSD_ERR_UNSUPPORTED, "Cholesky contraction tile exceeds LDS");
   }
   free_energy(sys);
@@ -830,6 +877,9 @@ msd_status msd_set_trial_occ(msd_system* sys, const double* ci, const int32_t* o
     D.m2_off = T.upload(S.m2_off, st);
     D.bw_ptr = T.upload(S.bw_ptr, st);
     D.bw_det = T.upload(S.bw_det, st);
+    D.n_seg = (int)S.seg_ptr.size() - 1;
+    D.seg_ptr = T.upload(S.seg_ptr, st);
+    D.str_seg = T.upload(S.str_seg, st);
     D.c_ptr = T.upload(S.c_ptr, st);
     D.c_adj = T.upload(S.c_adj, st);
     D.c_str = T.upload(S.c_str, st);
@@ -845,6 +895,7 @@ msd_status msd_set_trial_occ(msd_system* sys, const double* ci, const int32_t* o
     W.adj = T.get<cd>((size_t)NW * std::max(D.A, 1));
     W.m2 = T.get<cd>((size_t)NW * std::max(D.M2, 1));
     W.B = T.get<cd>((size_t)NW * S.U);
+    sys->segp[sp] = T.get<cd>((size_t)NW * std::max(D.n_seg, 1));
     W.C = T.get<cd>((size_t)NW * std::max(D.nv * D.no, 1));
     W.G = T.get<cd>((size_t)NW * D.P * M);
     sys->L_lt[sp] = T.get<double>((size_t)NG * D.P * M);
@@ -865,6 +916,14 @@ msd_status msd_set_trial_occ(msd_system* sys, const double* ci, const int32_t* o
     sys->rmap[sp] = T.upload(rm, st);
   }
   sys->rows_all_dev = T.upload(rows_all, st);
+  {
+    // enough (M-tile, N-tile, K-slice) workgroups to fill the chip, slices >= 256 deep
+    const int64_t K = (int64_t)sys->P_all * M;
+    const int64_t tiles = (int64_t)((NG + 63) / 64) * ((2 * NW + 63) / 64);
+    int sk = (int)std::max<int64_t>(1, std::min<int64_t>(512 / std::max<int64_t>(tiles, 1), K / 256));
+    sys->fb_splitk = sk;
+    sys->fb_ws = sk > 1 ? T.get<double>((size_t)sk * NG * 2 * NW) : nullptr;
+  }
   sys->L_rows = T.get<double>((size_t)NG * sys->P_all * M);
   sys->Gp = T.get<double>((size_t)2 * NW * sys->P_all * M);
   sys->dp.n_pair = sys->tt.n_pair;

@@ -15,9 +15,11 @@
 // An optional accumulator (same layout as C) receives acc += C_new.
 //
 // Tiling for gfx950: 64x64 output tile per 256-thread workgroup (4 wave64),
-// each wave 32x32 = 2x2 v_mfma_f64_16x16x4 tiles; K staged through LDS in
-// slabs of 16 with a 16-double row pad so the two half-waves of each
-// ds_read_b64 hit disjoint banks.
+// each wave 32x32 = 2x2 v_mfma_f64_16x16x4 tiles; K staged through two LDS
+// buffers in slabs of 16 (the next slab's global loads are in flight while
+// the current slab feeds the MFMAs; one barrier per slab), with a 16-double
+// row pad so the two half-waves of each ds_read_b64 hit disjoint banks.
+// Interior tiles of 16-byte-aligned operands use 16-byte global loads.
 #include <hip/hip_runtime.h>
 
 #include "common.h"
@@ -29,17 +31,56 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 
 constexpr int GB_M = 64, GB_N = 64, GB_K = 16, GPAD = 16;
 
+// Element (m, k) of A and (k, n) of B with bounds checks (zero outside), and in
+// complex mode the [Ar Ai] / [B ; B~] views described above.
+template <bool A_KMAJ, bool CPLX>
+__device__ __forceinline__ double a_at(const GemmArgs& g, const double* A, int gm, int gk,
+                                       int kend) {
+  if (gm >= g.M || gk >= kend) return 0.0;
+  if (CPLX) {
+    const bool im = gk >= g.K;
+    const int kr = im ? gk - g.K : gk;
+    const double* Ap = A + (im ? g.a_imag_off : 0);
+    return A_KMAJ ? Ap[(int64_t)gm * g.lda + kr] : Ap[(int64_t)kr * g.lda + gm];
+  }
+  return A_KMAJ ? A[(int64_t)gm * g.lda + gk] : A[(int64_t)gk * g.lda + gm];
+}
+
+template <bool B_KMAJ, bool CPLX>
+__device__ __forceinline__ double b_at(const GemmArgs& g, const double* B, int gk, int gn,
+                                       int kend) {
+  if (gn >= g.N || gk >= kend) return 0.0;
+  if (CPLX) {
+    const bool im = gk >= g.K;
+    const int kr = im ? gk - g.K : gk;
+    int cn = gn;
+    double sgn = 1.0;
+    if (im) {
+      cn = gn ^ 1;                  // swap real/imag column
+      sgn = (gn & 1) ? 1.0 : -1.0;  // -Im into the real column
+    }
+    return sgn * (B_KMAJ ? B[(int64_t)cn * g.ldb + kr] : B[(int64_t)kr * g.ldb + cn]);
+  }
+  return B_KMAJ ? B[(int64_t)gn * g.ldb + gk] : B[(int64_t)gk * g.ldb + gn];
+}
+
 template <bool A_KMAJ, bool B_KMAJ, bool CPLX>
 __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
   const int bz = blockIdx.z;
   if (g.mask && g.mask[bz] == 0) return;
-  const double* A = g.A + (int64_t)bz * g.strideA;
-  const double* B = g.B + (int64_t)bz * g.strideB;
-  double* C = g.C + (int64_t)bz * g.strideC;
-  double* Acc = g.Acc ? g.Acc + (int64_t)bz * g.strideC : nullptr;
+  // split-K: slice z owns K range [kbeg, kend) and writes a private partial
+  const bool split = g.splitk > 1;
+  const int kchunk = split ? ((g.K + g.splitk * GB_K - 1) / (g.splitk * GB_K)) * GB_K : 0;
+  const int kbeg = split ? bz * kchunk : 0;
+  const int kend = split ? min(g.K, kbeg + kchunk) : (CPLX ? 2 * g.K : g.K);
+  const double* A = g.A + (split ? 0 : (int64_t)bz * g.strideA);
+  const double* B = g.B + (split ? 0 : (int64_t)bz * g.strideB);
+  double* C = split ? g.ws + (int64_t)bz * g.M * g.N : g.C + (int64_t)bz * g.strideC;
+  const int64_t ldc = split ? g.N : g.ldc;
+  double* Acc = (!split && g.Acc) ? g.Acc + (int64_t)bz * g.strideC : nullptr;
 
-  __shared__ double As[GB_K][GB_M + GPAD];
-  __shared__ double Bs[GB_K][GB_N + GPAD];
+  __shared__ double As[2][GB_K][GB_M + GPAD];
+  __shared__ double Bs[2][GB_K][GB_N + GPAD];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -49,83 +90,130 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
   const int wm = (wave >> 1) * 32;
   const int wn = (wave & 1) * 32;
 
+  // per-thread staging coordinates: 4 consecutive elements along the
+  // contiguous dimension of each operand
+  const int a_mm = A_KMAJ ? (tid >> 2) : (tid & 15) * 4;
+  const int a_kk = A_KMAJ ? (tid & 3) * 4 : (tid >> 4);
+  const int b_nn = B_KMAJ ? (tid >> 2) : (tid & 15) * 4;
+  const int b_kk = B_KMAJ ? (tid & 3) * 4 : (tid >> 4);
+  // 16-byte loads are legal when every row start is 16-byte aligned
+  const bool a_vec = ((g.lda & 1) == 0) && ((((uintptr_t)A) & 15) == 0) &&
+                     (!CPLX || ((g.a_imag_off & 1) == 0 && (g.K & 3) == 0));
+  const bool b_vec = ((g.ldb & 1) == 0) && ((((uintptr_t)B) & 15) == 0) &&
+                     (!CPLX || (g.K & 3) == 0);
+  const bool m_full = m0 + GB_M <= g.M;
+  const bool n_full = n0 + GB_N <= g.N;
+
+  double ra[4], rb[4];
+  auto load = [&](int k0) {
+    const bool k_full = k0 + GB_K <= kend;
+    // A
+    if (a_vec && m_full && k_full) {
+      const int gm = m0 + a_mm, gk = k0 + a_kk;
+      const double* p;
+      if (A_KMAJ) {
+        if (CPLX) {
+          const bool im = gk >= g.K;
+          p = A + (im ? g.a_imag_off : 0) + (int64_t)gm * g.lda + (im ? gk - g.K : gk);
+        } else {
+          p = A + (int64_t)gm * g.lda + gk;
+        }
+      } else {
+        if (CPLX) {
+          const bool im = gk >= g.K;
+          p = A + (im ? g.a_imag_off : 0) + (int64_t)(im ? gk - g.K : gk) * g.lda + gm;
+        } else {
+          p = A + (int64_t)gk * g.lda + gm;
+        }
+      }
+      const double2 v0 = *reinterpret_cast<const double2*>(p);
+      const double2 v1 = *reinterpret_cast<const double2*>(p + 2);
+      ra[0] = v0.x; ra[1] = v0.y; ra[2] = v1.x; ra[3] = v1.y;
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        ra[r] = A_KMAJ ? a_at<A_KMAJ, CPLX>(g, A, m0 + a_mm, k0 + a_kk + r, kend)
+                       : a_at<A_KMAJ, CPLX>(g, A, m0 + a_mm + r, k0 + a_kk, kend);
+    }
+    // B
+    if (b_vec && n_full && k_full) {
+      const int gn = n0 + b_nn, gk = k0 + b_kk;
+      if (B_KMAJ) {
+        // 4 consecutive k of one column
+        if (CPLX) {
+          const bool im = gk >= g.K;
+          const int kr = im ? gk - g.K : gk;
+          const int cn = im ? (gn ^ 1) : gn;
+          const double sgn = im ? ((gn & 1) ? 1.0 : -1.0) : 1.0;
+          const double* p = B + (int64_t)cn * g.ldb + kr;
+          const double2 v0 = *reinterpret_cast<const double2*>(p);
+          const double2 v1 = *reinterpret_cast<const double2*>(p + 2);
+          rb[0] = sgn * v0.x; rb[1] = sgn * v0.y; rb[2] = sgn * v1.x; rb[3] = sgn * v1.y;
+        } else {
+          const double* p = B + (int64_t)gn * g.ldb + gk;
+          const double2 v0 = *reinterpret_cast<const double2*>(p);
+          const double2 v1 = *reinterpret_cast<const double2*>(p + 2);
+          rb[0] = v0.x; rb[1] = v0.y; rb[2] = v1.x; rb[3] = v1.y;
+        }
+      } else {
+        // 4 consecutive n (two complex pairs in complex mode) of one row
+        if (CPLX) {
+          const bool im = gk >= g.K;
+          const int kr = im ? gk - g.K : gk;
+          const double* p = B + (int64_t)kr * g.ldb + gn;
+          const double2 v0 = *reinterpret_cast<const double2*>(p);
+          const double2 v1 = *reinterpret_cast<const double2*>(p + 2);
+          if (im) {
+            rb[0] = -v0.y; rb[1] = v0.x; rb[2] = -v1.y; rb[3] = v1.x;
+          } else {
+            rb[0] = v0.x; rb[1] = v0.y; rb[2] = v1.x; rb[3] = v1.y;
+          }
+        } else {
+          const double* p = B + (int64_t)gk * g.ldb + gn;
+          const double2 v0 = *reinterpret_cast<const double2*>(p);
+          const double2 v1 = *reinterpret_cast<const double2*>(p + 2);
+          rb[0] = v0.x; rb[1] = v0.y; rb[2] = v1.x; rb[3] = v1.y;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        rb[r] = B_KMAJ ? b_at<B_KMAJ, CPLX>(g, B, k0 + b_kk + r, n0 + b_nn, kend)
+                       : b_at<B_KMAJ, CPLX>(g, B, k0 + b_kk, n0 + b_nn + r, kend);
+    }
+  };
+
   double4_t acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = double4_t{0.0, 0.0, 0.0, 0.0};
 
-  const int Keff = CPLX ? 2 * g.K : g.K;
-  for (int k0 = 0; k0 < Keff; k0 += GB_K) {
-    // ---- stage A slab (GB_M x GB_K) into As[k][m]
+  int buf = 0;
+  if (kbeg < kend) load(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += GB_K) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      int mm, kk;
-      if (A_KMAJ) {
-        mm = tid >> 2;
-        kk = (tid & 3) * 4 + r;
-      } else {
-        kk = tid >> 4;
-        mm = (tid & 15) * 4 + r;
-      }
-      const int gm = m0 + mm, gk = k0 + kk;
-      double v = 0.0;
-      if (gm < g.M && gk < Keff) {
-        if (CPLX) {
-          const bool im = gk >= g.K;
-          const int kr = im ? gk - g.K : gk;
-          const double* Ap = A + (im ? g.a_imag_off : 0);
-          v = A_KMAJ ? Ap[(int64_t)gm * g.lda + kr] : Ap[(int64_t)kr * g.lda + gm];
-        } else {
-          v = A_KMAJ ? A[(int64_t)gm * g.lda + gk] : A[(int64_t)gk * g.lda + gm];
-        }
-      }
-      As[kk][mm] = v;
-    }
-    // ---- stage B slab (GB_K x GB_N) into Bs[k][n]
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      int nn, kk;
-      if (B_KMAJ) {
-        nn = tid >> 2;
-        kk = (tid & 3) * 4 + r;
-      } else {
-        kk = tid >> 4;
-        nn = (tid & 15) * 4 + r;
-      }
-      const int gn = n0 + nn, gk = k0 + kk;
-      double v = 0.0;
-      if (gn < g.N && gk < Keff) {
-        if (CPLX) {
-          const bool im = gk >= g.K;
-          const int kr = im ? gk - g.K : gk;
-          int cn = gn;
-          double sgn = 1.0;
-          if (im) {
-            cn = gn ^ 1;                  // swap real/imag column
-            sgn = (gn & 1) ? 1.0 : -1.0;  // -Im into the real column
-          }
-          v = sgn * (B_KMAJ ? B[(int64_t)cn * g.ldb + kr] : B[(int64_t)kr * g.ldb + cn]);
-        } else {
-          v = B_KMAJ ? B[(int64_t)gn * g.ldb + gk] : B[(int64_t)gk * g.ldb + gn];
-        }
-      }
-      Bs[kk][nn] = v;
+      if (A_KMAJ) As[buf][a_kk + r][a_mm] = ra[r];
+      else As[buf][a_kk][a_mm + r] = ra[r];
+      if (B_KMAJ) Bs[buf][b_kk + r][b_nn] = rb[r];
+      else Bs[buf][b_kk][b_nn + r] = rb[r];
     }
     __syncthreads();
+    if (k0 + GB_K < kend) load(k0 + GB_K);  // in flight during the MFMAs below
 #pragma unroll
     for (int kk = 0; kk < GB_K; kk += 4) {
       const int kr = kk + (lane >> 4);
-      double a0 = As[kr][wm + (lane & 15)];
-      double a1 = As[kr][wm + 16 + (lane & 15)];
-      double b0 = Bs[kr][wn + (lane & 15)];
-      double b1 = Bs[kr][wn + 16 + (lane & 15)];
+      const double a0 = As[buf][kr][wm + (lane & 15)];
+      const double a1 = As[buf][kr][wm + 16 + (lane & 15)];
+      const double b0 = Bs[buf][kr][wn + (lane & 15)];
+      const double b1 = Bs[buf][kr][wn + 16 + (lane & 15)];
       acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
       acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
       acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
       acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
     }
-    __syncthreads();
+    buf ^= 1;
   }
 
   // ---- epilogue: register r of lane l holds D[l/16 + 4r][l % 16]
@@ -138,7 +226,11 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
         const int gm = m0 + wm + i * 16 + (lane >> 4) + 4 * r;
         const int gn = n0 + wn + j * 16 + (lane & 15);
         if (gm < g.M && gn < g.N) {
-          const int64_t off = (int64_t)gm * g.ldc + gn;
+          const int64_t off = (int64_t)gm * ldc + gn;
+          if (split) {
+            C[off] = acc[i][j][r];
+            continue;
+          }
           double v = g.alpha * acc[i][j][r];
           if (g.beta != 0.0) v += g.beta * C[off];
           C[off] = v;
@@ -147,14 +239,33 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
       }
 }
 
+// Sum of the split-K partials in slice order (deterministic), then alpha/beta.
+__global__ void k_splitk_reduce(GemmArgs g) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= (int64_t)g.M * g.N) return;
+  const int m = (int)(tid / g.N), n = (int)(tid % g.N);
+  double s = 0.0;
+  for (int z = 0; z < g.splitk; ++z) s += g.ws[(int64_t)z * g.M * g.N + tid];
+  const int64_t off = (int64_t)m * g.ldc + n;
+  double v = g.alpha * s;
+  if (g.beta != 0.0) v += g.beta * g.C[off];
+  g.C[off] = v;
+}
+
 template <bool AK, bool BK, bool CX>
 static void launch_t(const GemmArgs& g, hipStream_t st) {
-  dim3 grid((g.N + GB_N - 1) / GB_N, (g.M + GB_M - 1) / GB_M, g.batch);
+  const int z = g.splitk > 1 ? g.splitk : g.batch;
+  dim3 grid((g.N + GB_N - 1) / GB_N, (g.M + GB_M - 1) / GB_M, z);
   hipLaunchKernelGGL((k_gemm_f64<AK, BK, CX>), grid, dim3(256), 0, st, g);
+  if (g.splitk > 1) {
+    const int64_t n = (int64_t)g.M * g.N;
+    hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g);
+  }
 }
 
 void launch_gemm(const GemmArgs& g, hipStream_t st) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return;
+  if (g.splitk > 1 && (g.batch != 1 || g.cplx || !g.ws || g.Acc)) return;  // unsupported combination
   if (g.cplx) {
     if (g.a_kmaj && !g.b_kmaj) launch_t<true, false, true>(g, st);
     else if (g.a_kmaj && g.b_kmaj) launch_t<true, true, true>(g, st);

@@ -18,6 +18,8 @@ struct GemmArgs {
   int64_t strideA = 0, strideB = 0, strideC = 0;
   int64_t a_imag_off = 0;       // complex mode: offset of the imaginary plane of A
   const int* mask = nullptr;    // optional per-batch skip mask (0 = skip)
+  int splitk = 1;               // >1: K split over blockIdx.z (batch must be 1)
+  double* ws = nullptr;         // split-K workspace: splitk * M * N doubles
   double alpha = 1.0, beta = 0.0;
   bool a_kmaj = true, b_kmaj = false, cplx = false;
 };
@@ -42,6 +44,9 @@ struct DevSpin {
   const int* m2_off = nullptr;   // [U+1]
   const int* bw_ptr = nullptr;   // [U+1]
   const int* bw_det = nullptr;
+  int n_seg = 0;                 // det lists cut into segments of <= 16
+  const int* seg_ptr = nullptr;  // [n_seg+1] into bw_det
+  const int* str_seg = nullptr;  // [U+1] segments of each string
   const int* c_ptr = nullptr;    // [nv*no+1]
   const int* c_adj = nullptr;
   const int* c_str = nullptr;
@@ -78,21 +83,23 @@ struct SpinWork {
 };
 
 // ---------------------------------------------------------------- Wick kernels
-void launch_ref_inverse(const cd* phi, int M, int Ntot, int NW, const DevSpin& s, cd* T,
-                        cd* logdetA, int* flag, hipStream_t st);
-void launch_strings(const DevSpin& s, const cd* T, int NW, bool minors, cd* d, cd* adj,
-                    cd* m2, hipStream_t st);
+void launch_ref_inverse(const cd* phi, int M, int Ntot, int NW, const DevSpin& sa,
+                        const DevSpin& sb, cd* Ta, cd* Tb, cd* ldA, cd* ldB, int* flag,
+                        hipStream_t st);
+void launch_strings(const DevSpin& sa, const DevSpin& sb, const cd* Ta, const cd* Tb, int NW,
+                    bool minors, const SpinWork& wa, const SpinWork& wb, hipStream_t st);
 void launch_ovlp_partial(int64_t n_det, int NW, const int* sa, const int* sb, const cd* c,
                          const cd* da, int Ua, const cd* db, int Ub, cd* partial,
                          int n_chunks, int chunk, hipStream_t st);
 void launch_ovlp_final(int NW, const cd* partial, int n_chunks, const cd* ldA,
                        const cd* ldB, cd* obar, cd* log_ovlp, int* flag, hipStream_t st);
-void launch_ci_weights(const DevSpin& s, const int* det_s_other, const cd* det_c,
-                       const cd* d_other, int U_other, int NW, cd* B, hipStream_t st);
-void launch_ci_matrix(const DevSpin& s, int NW, const cd* adj, const cd* B, cd* C,
-                      hipStream_t st);
-void launch_green(const DevSpin& s, int M, int NW, const cd* T, const cd* C,
-                  const cd* obar, const double* h1, cd* G, cd* onebody, hipStream_t st);
+void launch_ci_weights(const DevSpin& sa, const DevSpin& sb, const cd* det_c, const SpinWork& wa,
+                       const SpinWork& wb, cd* seg_a, cd* seg_b, int NW, hipStream_t st);
+void launch_ci_matrix(const DevSpin& sa, const DevSpin& sb, int NW, const SpinWork& wa,
+                      const SpinWork& wb, hipStream_t st);
+void launch_green(const DevSpin& sa, const DevSpin& sb, int M, int NW, const SpinWork& wa,
+                  const SpinWork& wb, cd* ob_a, cd* ob_b, const cd* obar, const double* h1,
+                  hipStream_t st);
 void launch_green_sum(int M, int NW, int P_all, const int* rmap_a, const int* rmap_b,
                       int Pa, int Pb, const cd* Ga, const cd* Gb, double* Gp,
                       hipStream_t st);
@@ -107,10 +114,19 @@ void launch_pair_coef(const DevPairs& pr, int NW, const cd* det_c, const cd* adj
                       const cd* adj_b, int Ab, cd* coef, hipStream_t st);
 void launch_minor_coef(const DevSpin& s, int NW, const cd* B, int U, const cd* m2, cd* coef,
                        hipStream_t st);
-void launch_energy_gamma(const DevSpin& sa, const DevSpin& sb, const DevPairs& pr, int NW,
-                         int w0, int WT, int NG, int g_chunk, const cd* Lam_a,
-                         const cd* Lam_b, const cd* coef_pair, const cd* coef_ma,
-                         const cd* coef_mb, cd* partial, hipStream_t st);
+// second-order energy terms; each launch writes blocks into partial[w][slot0 + ...]
+int energy_pair_blocks(int n_pair);
+int energy_string_blocks(const DevSpin& s, int k);
+int energy_minor_blocks(const DevSpin& s);
+void launch_energy_pairs(const DevPairs& pr, int Xa, int Xb, int NW, int w0, int WT, int NG,
+                         int n_gsplit, const cd* Lam_a, const cd* Lam_b, const cd* coef,
+                         cd* partial, int n_slots, int slot0, hipStream_t st);
+void launch_energy_strings(const DevSpin& s, int k, int NW, int w0, int WT, int NG, int n_gsplit,
+                           const cd* Lam, const cd* m2, const cd* B, cd* partial, int n_slots,
+                           int slot0, hipStream_t st);
+void launch_energy_minors(const DevSpin& s, int NW, int w0, int WT, int NG, int n_gsplit,
+                          const cd* Lam, const cd* coef, cd* partial, int n_slots, int slot0,
+                          hipStream_t st);
 void launch_energy_final(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
                          int n_lchunks, int n_echunks, const cd* obar, const cd* v0,
                          const cd* ex0, const cd* ZWpart_a, const cd* ZWpart_b,
@@ -122,8 +138,8 @@ void launch_vhs_prep(int NW, int NG, const double* x, const cd* xbar, double sqr
                      const double* weights, double* Y, hipStream_t st);
 void launch_weights(int NW, int NG, const double* x, const cd* xbar, const cd* logo_new,
                     cd* logo, double* weights, double dt, double e_shift, hipStream_t st);
-void launch_qr(cd* phi, int M, int Ntot, int NW, int N, int col0, const int* mask, cd* logo,
-               hipStream_t st);
+void launch_qr(cd* phi, int M, int Ntot, int NW, int na, int nb, const int* mask, double* ldet,
+               cd* logo, hipStream_t st);
 void launch_frozen_mask(int NW, const double* weights, int* mask, hipStream_t st);
 void launch_copy_walkers(int NW, int M, int Ntot, int na, int nb, const cd* pa, const cd* pb,
                          cd* phi, bool to_internal, cd* out_a, cd* out_b, hipStream_t st);

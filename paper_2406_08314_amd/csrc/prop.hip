@@ -88,9 +88,11 @@ void launch_frozen_mask(int NW, const double* weights, int* mask, hipStream_t st
 // (Gram matrix, its Cholesky factor, Phi <- Phi R^{-1}); the log-overlap loses
 // sum_j log R_jj.  One workgroup per walker and spin; walkers with mask 0 are
 // skipped.
-__global__ __launch_bounds__(256) void k_qr(cd* __restrict__ phi, int M, int Ntot, int NW, int N,
-                                            int col0, const int* __restrict__ mask,
-                                            cd* __restrict__ logo) {
+__global__ __launch_bounds__(256) void k_qr(cd* __restrict__ phi, int M, int Ntot, int NW, int na,
+                                            int nb, const int* __restrict__ mask,
+                                            double* __restrict__ ldet_out) {
+  const int N = blockIdx.y ? nb : na, col0 = blockIdx.y ? na : 0;
+  if (N == 0) return;
   extern __shared__ cd sm[];
   cd* R = sm;            // [N][N]  Gram -> upper Cholesky factor
   cd* Ri = sm + N * N;   // [N][N]  R^{-1}
@@ -154,17 +156,25 @@ __global__ __launch_bounds__(256) void k_qr(cd* __restrict__ phi, int M, int Nto
     __threadfence();
   }
   __syncthreads();
-  if (tid == 0) {
-    cd l = logo[w];
-    logo[w] = bad ? cd{-INFINITY, 0.0} : cd{l.re - ldet, l.im};
-  }
+  if (tid == 0) ldet_out[2 * w + blockIdx.y] = bad ? INFINITY : ldet;
 }
 
-void launch_qr(cd* phi, int M, int Ntot, int NW, int N, int col0, const int* mask, cd* logo,
-               hipStream_t st) {
-  if (N == 0) return;
-  hipLaunchKernelGGL(k_qr, dim3(NW), dim3(256), 2 * (size_t)N * N * sizeof(cd), st, phi, M, Ntot,
-                     NW, N, col0, mask, logo);
+// log <Psi_T|Phi> -= sum_s log det R^s after the re-orthonormalisation
+__global__ void k_qr_logo(int NW, const int* __restrict__ mask, const double* __restrict__ ldet,
+                          cd* __restrict__ logo) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= NW || (mask && mask[w] == 0)) return;
+  const double l = ldet[2 * w] + ldet[2 * w + 1];
+  const cd o = logo[w];
+  logo[w] = l < INFINITY ? cd{o.re - l, o.im} : cd{-INFINITY, 0.0};
+}
+
+void launch_qr(cd* phi, int M, int Ntot, int NW, int na, int nb, const int* mask, double* ldet,
+               cd* logo, hipStream_t st) {
+  const int N = max(na, nb);
+  hipLaunchKernelGGL(k_qr, dim3(NW, 2), dim3(256), 2 * (size_t)N * N * sizeof(cd), st, phi, M, Ntot,
+                     NW, na, nb, mask, ldet);
+  hipLaunchKernelGGL(k_qr_logo, dim3((NW + 255) / 256), dim3(256), 0, st, NW, mask, ldet, logo);
 }
 
 // Pack the per-spin boundary layouts [w][M][n_s] into the internal [w][M][Ntot]

@@ -250,6 +250,14 @@ std::string build_trial(int M, int na, int nb, int64_t n_det, const double* ci,
       std::vector<int> fill(S.bw_ptr.begin(), S.bw_ptr.end() - 1);
       for (int64_t I = 0; I < n_det; ++I) S.bw_det[fill[t.det_s[sp][I]]++] = (int)I;
     }
+    // segments of at most 16 determinants (balanced CI-weight sums)
+    S.str_seg.assign(U + 1, 0);
+    S.seg_ptr.assign(1, 0);
+    for (int i = 0; i < U; ++i) {
+      for (int b = S.bw_ptr[i]; b < S.bw_ptr[i + 1]; b += 16)
+        S.seg_ptr.push_back(std::min(b + 16, S.bw_ptr[i + 1]));
+      S.str_seg[i + 1] = (int)S.seg_ptr.size() - 1;
+    }
     // first-order CI entries
     S.c_ptr.assign((size_t)nv * no + 1, 0);
     for (int i = 0; i < U; ++i) {

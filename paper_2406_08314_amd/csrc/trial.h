@@ -39,6 +39,8 @@ struct SpinTable {
   // string -> determinants containing it (CSR)
   std::vector<int> bw_ptr;        // [U+1]
   std::vector<int> bw_det;        // determinant ids
+  std::vector<int> seg_ptr;       // each string's list cut into segments of <= 16 ids
+  std::vector<int> str_seg;       // [U+1] segment range of each string
   // first-order CI matrix entry (a, i) (a in vir_act, i in occ_act) -> (adj index, string)
   std::vector<int> c_ptr;         // [nv*no + 1]
   std::vector<int> c_adj;         // flat index into the walker's adj array

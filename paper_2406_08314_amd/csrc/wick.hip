@@ -97,12 +97,18 @@ __device__ cd det_lu(const cd* a, int n) {
 // ============================================================================
 
 __global__ __launch_bounds__(256) void k_ref_inverse(const cd* __restrict__ phi, int M, int Ntot,
-                                                     int NW, DevSpin s, cd* __restrict__ T,
-                                                     cd* __restrict__ logdetA,
+                                                     int NW, DevSpin sa, DevSpin sb,
+                                                     cd* __restrict__ Ta, cd* __restrict__ Tb,
+                                                     cd* __restrict__ lda_, cd* __restrict__ ldb_,
                                                      int* __restrict__ flag) {
   extern __shared__ cd aug[];  // [N][2N]
   __shared__ cd fac[NMAX_LDS];
   __shared__ int piv_s;
+  const bool beta = blockIdx.y == 1;
+  const DevSpin& s = beta ? sb : sa;
+  cd* __restrict__ T = beta ? Tb : Ta;
+  cd* __restrict__ logdetA = beta ? ldb_ : lda_;
+  if (s.N == 0) return;
   const int w = blockIdx.x, tid = threadIdx.x, bd = blockDim.x;
   const int N = s.N, N2 = 2 * N;
   const cd* P = phi + (size_t)w * M * Ntot + s.col0;
@@ -173,12 +179,14 @@ __global__ __launch_bounds__(256) void k_ref_inverse(const cd* __restrict__ phi,
   }
 }
 
-void launch_ref_inverse(const cd* phi, int M, int Ntot, int NW, const DevSpin& s, cd* T,
-                        cd* logdetA, int* flag, hipStream_t st) {
-  if (s.N == 0) return;
-  size_t lds = (size_t)s.N * 2 * s.N * sizeof(cd);
-  hipLaunchKernelGGL(k_ref_inverse, dim3(NW), dim3(256), lds, st, phi, M, Ntot, NW, s, T,
-                     logdetA, flag);
+void launch_ref_inverse(const cd* phi, int M, int Ntot, int NW, const DevSpin& sa,
+                        const DevSpin& sb, cd* Ta, cd* Tb, cd* ldA, cd* ldB, int* flag,
+                        hipStream_t st) {
+  const int N = max(sa.N, sb.N);
+  if (N == 0) return;
+  size_t lds = (size_t)N * 2 * N * sizeof(cd);
+  hipLaunchKernelGGL(k_ref_inverse, dim3(NW, 2), dim3(256), lds, st, phi, M, Ntot, NW, sa, sb,
+                     Ta, Tb, ldA, ldB, flag);
 }
 
 // ============================================================================
@@ -213,11 +221,24 @@ __device__ __forceinline__ void sub2(const cd* X, int r0, int r1, int c0, int c1
   }
 }
 
+struct StrOut {
+  const cd* T;
+  cd* d;
+  cd* adj;
+  cd* m2;
+};
+
 template <int K>
-__global__ __launch_bounds__(256) void k_strings_t(DevSpin s, const cd* __restrict__ T, int NW,
-                                                   int s0, int ns, bool minors,
-                                                   cd* __restrict__ d, cd* __restrict__ adj,
-                                                   cd* __restrict__ m2) {
+__global__ __launch_bounds__(256) void k_strings_t(DevSpin sa, DevSpin sb, StrOut oa, StrOut ob,
+                                                   int NW, bool minors) {
+  const bool beta = blockIdx.y == 1;
+  const DevSpin& s = beta ? sb : sa;
+  const StrOut& o = beta ? ob : oa;
+  const cd* __restrict__ T = o.T;
+  cd* __restrict__ d = o.d;
+  cd* __restrict__ adj = o.adj;
+  cd* __restrict__ m2 = o.m2;
+  const int s0 = s.bucket[K], ns = s.bucket[K + 1] - s.bucket[K];
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (tid >= (int64_t)ns * NW) return;
   const int str = s0 + (int)(tid % ns);
@@ -264,10 +285,16 @@ __global__ __launch_bounds__(256) void k_strings_t(DevSpin s, const cd* __restri
 }
 
 // Orders above 4: runtime k with LU-based sub-determinants.
-__global__ __launch_bounds__(128) void k_strings_big(DevSpin s, const cd* __restrict__ T, int NW,
-                                                     int s0, int ns, int K, bool minors,
-                                                     cd* __restrict__ d, cd* __restrict__ adj,
-                                                     cd* __restrict__ m2) {
+__global__ __launch_bounds__(128) void k_strings_big(DevSpin sa, DevSpin sb, StrOut oa, StrOut ob,
+                                                     int NW, int K, bool minors) {
+  const bool beta = blockIdx.y == 1;
+  const DevSpin& s = beta ? sb : sa;
+  const StrOut& o = beta ? ob : oa;
+  const cd* __restrict__ T = o.T;
+  cd* __restrict__ d = o.d;
+  cd* __restrict__ adj = o.adj;
+  cd* __restrict__ m2 = o.m2;
+  const int s0 = s.bucket[K], ns = s.bucket[K + 1] - s.bucket[K];
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (tid >= (int64_t)ns * NW) return;
   const int str = s0 + (int)(tid % ns);
@@ -309,21 +336,22 @@ __global__ __launch_bounds__(128) void k_strings_big(DevSpin s, const cd* __rest
   }
 }
 
-void launch_strings(const DevSpin& s, const cd* T, int NW, bool minors, cd* d, cd* adj, cd* m2,
-                    hipStream_t st) {
+void launch_strings(const DevSpin& sa, const DevSpin& sb, const cd* Ta, const cd* Tb, int NW,
+                    bool minors, const SpinWork& wa, const SpinWork& wb, hipStream_t st) {
+  const StrOut oa{Ta, wa.d, wa.adj, wa.m2}, ob{Tb, wb.d, wb.adj, wb.m2};
   for (int k = 0; k <= KMAX; ++k) {
-    const int s0 = s.bucket[k], ns = s.bucket[k + 1] - s.bucket[k];
+    const int ns = max(sa.bucket[k + 1] - sa.bucket[k], sb.bucket[k + 1] - sb.bucket[k]);
     if (ns <= 0) continue;
     const int64_t n = (int64_t)ns * NW;
     const int bs = k <= 4 ? 256 : 128;
-    dim3 grid((unsigned)((n + bs - 1) / bs));
+    dim3 grid((unsigned)((n + bs - 1) / bs), 2);
     switch (k) {
-      case 0: hipLaunchKernelGGL(k_strings_t<0>, grid, dim3(bs), 0, st, s, T, NW, s0, ns, minors, d, adj, m2); break;
-      case 1: hipLaunchKernelGGL(k_strings_t<1>, grid, dim3(bs), 0, st, s, T, NW, s0, ns, minors, d, adj, m2); break;
-      case 2: hipLaunchKernelGGL(k_strings_t<2>, grid, dim3(bs), 0, st, s, T, NW, s0, ns, minors, d, adj, m2); break;
-      case 3: hipLaunchKernelGGL(k_strings_t<3>, grid, dim3(bs), 0, st, s, T, NW, s0, ns, minors, d, adj, m2); break;
-      case 4: hipLaunchKernelGGL(k_strings_t<4>, grid, dim3(bs), 0, st, s, T, NW, s0, ns, minors, d, adj, m2); break;
-      default: hipLaunchKernelGGL(k_strings_big, grid, dim3(bs), 0, st, s, T, NW, s0, ns, k, minors, d, adj, m2); break;
+      case 0: hipLaunchKernelGGL(k_strings_t<0>, grid, dim3(bs), 0, st, sa, sb, oa, ob, NW, minors); break;
+      case 1: hipLaunchKernelGGL(k_strings_t<1>, grid, dim3(bs), 0, st, sa, sb, oa, ob, NW, minors); break;
+      case 2: hipLaunchKernelGGL(k_strings_t<2>, grid, dim3(bs), 0, st, sa, sb, oa, ob, NW, minors); break;
+      case 3: hipLaunchKernelGGL(k_strings_t<3>, grid, dim3(bs), 0, st, sa, sb, oa, ob, NW, minors); break;
+      case 4: hipLaunchKernelGGL(k_strings_t<4>, grid, dim3(bs), 0, st, sa, sb, oa, ob, NW, minors); break;
+      default: hipLaunchKernelGGL(k_strings_big, grid, dim3(bs), 0, st, sa, sb, oa, ob, NW, k, minors); break;
     }
   }
 }
@@ -412,29 +440,61 @@ void launch_ovlp_final(int NW, const cd* partial, int n_chunks, const cd* ldA, c
 // paper's reduce_CI: each output entry sums its own contribution list)
 // ============================================================================
 
-__global__ void k_ci_weights(DevSpin s, const int* __restrict__ det_s_other,
-                             const cd* __restrict__ det_c, const cd* __restrict__ d_other,
-                             int U_other, int NW, cd* __restrict__ B) {
+// Segment sums of c~_I det X^{other}_I over each string's determinant list
+// (segments of <= 16), then per-string sums of its segments in order.
+// blockIdx.y selects the spin; the other spin's dets are read.
+__global__ void k_ci_segments(DevSpin sa, DevSpin sb, const cd* __restrict__ det_c,
+                              const cd* __restrict__ da, const cd* __restrict__ db, int NW,
+                              cd* __restrict__ pa, cd* __restrict__ pb) {
+  const bool beta = blockIdx.y == 1;
+  const DevSpin& s = beta ? sb : sa;
+  const DevSpin& o = beta ? sa : sb;
+  const cd* __restrict__ d_other = beta ? da : db;
+  cd* __restrict__ seg_part = beta ? pb : pa;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= (int64_t)s.n_seg * NW) return;
+  const int seg = (int)(tid % s.n_seg), w = (int)(tid / s.n_seg);
+  cd acc{0.0, 0.0};
+  for (int e = s.seg_ptr[seg]; e < s.seg_ptr[seg + 1]; ++e) {
+    const int I = s.bw_det[e];
+    cfma(acc, det_c[I], d_other[(size_t)w * o.U + o.det_s[I]]);
+  }
+  seg_part[(size_t)w * s.n_seg + seg] = acc;
+}
+
+__global__ void k_ci_weights(DevSpin sa, DevSpin sb, int NW, const cd* __restrict__ pa,
+                             const cd* __restrict__ pb, cd* __restrict__ Ba,
+                             cd* __restrict__ Bb) {
+  const bool beta = blockIdx.y == 1;
+  const DevSpin& s = beta ? sb : sa;
+  const cd* __restrict__ seg_part = beta ? pb : pa;
+  cd* __restrict__ B = beta ? Bb : Ba;
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (tid >= (int64_t)s.U * NW) return;
   const int str = (int)(tid % s.U), w = (int)(tid / s.U);
   cd acc{0.0, 0.0};
-  for (int e = s.bw_ptr[str]; e < s.bw_ptr[str + 1]; ++e) {
-    const int I = s.bw_det[e];
-    cfma(acc, det_c[I], d_other[(size_t)w * U_other + det_s_other[I]]);
-  }
+  for (int q = s.str_seg[str]; q < s.str_seg[str + 1]; ++q) acc += seg_part[(size_t)w * s.n_seg + q];
   B[(size_t)w * s.U + str] = acc;
 }
 
-void launch_ci_weights(const DevSpin& s, const int* det_s_other, const cd* det_c,
-                       const cd* d_other, int U_other, int NW, cd* B, hipStream_t st) {
-  const int64_t n = (int64_t)s.U * NW;
-  hipLaunchKernelGGL(k_ci_weights, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s,
-                     det_s_other, det_c, d_other, U_other, NW, B);
+void launch_ci_weights(const DevSpin& sa, const DevSpin& sb, const cd* det_c, const SpinWork& wa,
+                       const SpinWork& wb, cd* seg_a, cd* seg_b, int NW, hipStream_t st) {
+  int64_t n = (int64_t)max(sa.n_seg, sb.n_seg) * NW;
+  hipLaunchKernelGGL(k_ci_segments, dim3((unsigned)((n + 255) / 256), 2), dim3(256), 0, st, sa, sb,
+                     det_c, wa.d, wb.d, NW, seg_a, seg_b);
+  n = (int64_t)max(sa.U, sb.U) * NW;
+  hipLaunchKernelGGL(k_ci_weights, dim3((unsigned)((n + 255) / 256), 2), dim3(256), 0, st, sa, sb,
+                     NW, seg_a, seg_b, wa.B, wb.B);
 }
 
-__global__ void k_ci_matrix(DevSpin s, int NW, const cd* __restrict__ adj,
-                            const cd* __restrict__ B, cd* __restrict__ C) {
+__global__ void k_ci_matrix(DevSpin sa, DevSpin sb, int NW, const cd* __restrict__ adja,
+                            const cd* __restrict__ adjb, const cd* __restrict__ Ba,
+                            const cd* __restrict__ Bb, cd* __restrict__ Ca, cd* __restrict__ Cb) {
+  const bool beta = blockIdx.y == 1;
+  const DevSpin& s = beta ? sb : sa;
+  const cd* __restrict__ adj = beta ? adjb : adja;
+  const cd* __restrict__ B = beta ? Bb : Ba;
+  cd* __restrict__ C = beta ? Cb : Ca;
   const int X = s.nv * s.no;
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (tid >= (int64_t)X * NW) return;
@@ -445,12 +505,12 @@ __global__ void k_ci_matrix(DevSpin s, int NW, const cd* __restrict__ adj,
   C[(size_t)w * X + e] = acc;
 }
 
-void launch_ci_matrix(const DevSpin& s, int NW, const cd* adj, const cd* B, cd* C,
-                      hipStream_t st) {
-  const int64_t n = (int64_t)s.nv * s.no * NW;
+void launch_ci_matrix(const DevSpin& sa, const DevSpin& sb, int NW, const SpinWork& wa,
+                      const SpinWork& wb, hipStream_t st) {
+  const int64_t n = (int64_t)max(sa.nv * sa.no, sb.nv * sb.no) * NW;
   if (n == 0) return;
-  hipLaunchKernelGGL(k_ci_matrix, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s, NW,
-                     adj, B, C);
+  hipLaunchKernelGGL(k_ci_matrix, dim3((unsigned)((n + 255) / 256), 2), dim3(256), 0, st, sa, sb,
+                     NW, wa.adj, wb.adj, wa.B, wb.B, wa.C, wb.C);
 }
 
 // ============================================================================
@@ -459,11 +519,23 @@ void launch_ci_matrix(const DevSpin& s, int NW, const cd* adj, const cd* B, cd* 
 
 constexpr int G_QT = 64;
 
-__global__ __launch_bounds__(256) void k_green(DevSpin s, int M, int NW, const cd* __restrict__ T,
-                                               const cd* __restrict__ C,
-                                               const cd* __restrict__ obar,
-                                               const double* __restrict__ h1,
-                                               cd* __restrict__ G, cd* __restrict__ onebody) {
+struct GreenIO {
+  const cd* T;
+  const cd* C;
+  cd* G;
+  cd* onebody;
+};
+
+__global__ __launch_bounds__(256) void k_green(DevSpin sa, DevSpin sb, GreenIO ia, GreenIO ib,
+                                               int M, int NW, const cd* __restrict__ obar,
+                                               const double* __restrict__ h1) {
+  const bool beta = blockIdx.y == 1;
+  const DevSpin& s = beta ? sb : sa;
+  const GreenIO& io = beta ? ib : ia;
+  const cd* __restrict__ T = io.T;
+  const cd* __restrict__ C = io.C;
+  cd* __restrict__ G = io.G;
+  cd* __restrict__ onebody = io.onebody;
   extern __shared__ cd sm[];
   __shared__ cd red[256];
   const int nv = s.nv, no = s.no, N = s.N, P = s.P;
@@ -510,11 +582,15 @@ __global__ __launch_bounds__(256) void k_green(DevSpin s, int M, int NW, const c
   if (tid == 0) onebody[w] = tot;
 }
 
-void launch_green(const DevSpin& s, int M, int NW, const cd* T, const cd* C, const cd* obar,
-                  const double* h1, cd* G, cd* onebody, hipStream_t st) {
-  size_t lds = ((size_t)s.nv * s.no + (size_t)s.nv * s.N + (size_t)s.nv * G_QT) * sizeof(cd);
-  hipLaunchKernelGGL(k_green, dim3(NW), dim3(256), lds, st, s, M, NW, T, C, obar, h1, G,
-                     onebody);
+void launch_green(const DevSpin& sa, const DevSpin& sb, int M, int NW, const SpinWork& wa,
+                  const SpinWork& wb, cd* ob_a, cd* ob_b, const cd* obar, const double* h1,
+                  hipStream_t st) {
+  size_t lds = 0;
+  for (const DevSpin* s : {&sa, &sb})
+    lds = max(lds, ((size_t)s->nv * s->no + (size_t)s->nv * s->N + (size_t)s->nv * G_QT) *
+                       sizeof(cd));
+  const GreenIO ia{wa.T, wa.C, wa.G, ob_a}, ib{wb.T, wb.C, wb.G, ob_b};
+  hipLaunchKernelGGL(k_green, dim3(NW, 2), dim3(256), lds, st, sa, sb, ia, ib, M, NW, obar, h1);
 }
 
 __global__ void k_green_sum(int M, int NW, int P_all, const int* __restrict__ rmap_a,
@@ -561,125 +637,110 @@ void launch_xbar(int NW, int NG, const double* raw, double sqrt_dt, cd* xbar, hi
 // A6: energy intermediates per (walker, Cholesky chunk): v0, ex0, Lam (window),
 // and the chunk's share of ZW = sum_g Xi^g - (v0a + v0b) Lam^g.
 // LT^s layout: row g*P + p, column wl*N + c (complex), row length WT*N.
+// One wave per workgroup: barriers are cheap and reductions use shuffles.
 // ============================================================================
 
-constexpr int ZW_PER_THREAD = 4;
+__device__ __forceinline__ cd wave_sum(cd v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    v.re += __shfl_xor(v.re, off, 64);
+    v.im += __shfl_xor(v.im, off, 64);
+  }
+  return v;
+}
 
-__global__ __launch_bounds__(256) void k_lambda(DevSpin sa, DevSpin sb, int NW, int w0, int WT,
-                                                int NG, int g_chunk, const cd* __restrict__ Ta,
-                                                const cd* __restrict__ Tb,
-                                                const cd* __restrict__ LTa,
-                                                const cd* __restrict__ LTb,
-                                                cd* __restrict__ Lam_a, cd* __restrict__ Lam_b,
-                                                cd* __restrict__ v0, cd* __restrict__ ex0,
-                                                cd* __restrict__ ZWa, cd* __restrict__ ZWb) {
+__global__ __launch_bounds__(64) void k_lambda(DevSpin sa, DevSpin sb, int NW, int w0, int WT,
+                                               int NG, int g_chunk, const cd* __restrict__ Ta,
+                                               const cd* __restrict__ Tb,
+                                               const cd* __restrict__ LTa,
+                                               const cd* __restrict__ LTb,
+                                               cd* __restrict__ Lam_a, cd* __restrict__ Lam_b,
+                                               cd* __restrict__ v0, cd* __restrict__ ex0,
+                                               cd* __restrict__ ZWa, cd* __restrict__ ZWb) {
   extern __shared__ cd sm[];
-  __shared__ cd rowv[2][NMAX_LDS], rowx[2][NMAX_LDS];
-  __shared__ cd v0s[2], ex0s[2];
   const int wl = blockIdx.x, chunk = blockIdx.y, n_chunks = gridDim.y;
-  const int w = w0 + wl, tid = threadIdx.x, bd = blockDim.x;
-  const DevSpin* sp[2] = {&sa, &sb};
-  const cd* Tt[2] = {Ta, Tb};
-  const cd* LT[2] = {LTa, LTb};
-  cd* Lam[2] = {Lam_a, Lam_b};
-  cd* ZW[2] = {ZWa, ZWb};
-  cd* Q[2];
-  cd* LTV[2];
-  cd* TV[2];
-  cd* ptr = sm;
-  for (int s2 = 0; s2 < 2; ++s2) {
-    const int N = sp[s2]->N, nv = sp[s2]->nv;
-    Q[s2] = ptr; ptr += N * N;
-    LTV[s2] = ptr; ptr += nv * N;
-    TV[s2] = ptr; ptr += nv * N;
+  const int w = w0 + wl, lane = threadIdx.x;
+  cd* TVa = sm;                                   // [nv_a*N_a]
+  cd* TVb = TVa + sa.nv * sa.N;                   // [nv_b*N_b]
+  cd* Q = TVb + sb.nv * sb.N;                     // [max N^2]
+  cd* Lf = Q + max(sa.N * sa.N, sb.N * sb.N);     // [max nv*N]
+  cd* ZWs[2];
+  ZWs[0] = Lf + max(sa.nv * sa.N, sb.nv * sb.N);  // [nv_a*no_a] accumulators
+  ZWs[1] = ZWs[0] + sa.nv * sa.no;                // [nv_b*no_b]
+  for (int e = lane; e < sa.nv * sa.no; e += 64) ZWs[0][e] = cd{0.0, 0.0};
+  for (int e = lane; e < sb.nv * sb.no; e += 64) ZWs[1][e] = cd{0.0, 0.0};
+  for (int e = lane; e < sa.nv * sa.N; e += 64) {
+    const int a = e / sa.N, j = e % sa.N;
+    TVa[e] = Ta[((size_t)sa.vir[a] * NW + w) * sa.N + j];
   }
-  cd* Lf = ptr;  // [max nv*N]
-  for (int s2 = 0; s2 < 2; ++s2) {
-    const DevSpin& S = *sp[s2];
-    for (int e = tid; e < S.nv * S.N; e += bd) {
-      int a = e / S.N, j = e % S.N;
-      TV[s2][e] = Tt[s2][((size_t)S.vir[a] * NW + w) * S.N + j];
-    }
+  for (int e = lane; e < sb.nv * sb.N; e += 64) {
+    const int a = e / sb.N, j = e % sb.N;
+    TVb[e] = Tb[((size_t)sb.vir[a] * NW + w) * sb.N + j];
   }
-  cd zacc[2][ZW_PER_THREAD];
-#pragma unroll
-  for (int s2 = 0; s2 < 2; ++s2)
-#pragma unroll
-    for (int j = 0; j < ZW_PER_THREAD; ++j) zacc[s2][j] = cd{0.0, 0.0};
+  __syncthreads();
 
   const int g0 = chunk * g_chunk, g1 = min(NG, g0 + g_chunk);
   for (int g = g0; g < g1; ++g) {
+    // traces of both spins first: ZW needs v0a + v0b
+    cd va{0.0, 0.0}, vb{0.0, 0.0};
+    if (lane < sa.N) va = LTa[((size_t)g * sa.P + lane) * WT * sa.N + (size_t)wl * sa.N + lane];
+    if (lane < sb.N) vb = LTb[((size_t)g * sb.P + lane) * WT * sb.N + (size_t)wl * sb.N + lane];
+    va = wave_sum(va);
+    vb = wave_sum(vb);
+    const cd vsum = va + vb;
+#pragma unroll
     for (int s2 = 0; s2 < 2; ++s2) {
-      const DevSpin& S = *sp[s2];
-      const int N = S.N, P = S.P;
-      const cd* base = LT[s2] + ((size_t)g * P) * WT * N + (size_t)wl * N;
-      for (int e = tid; e < N * N; e += bd) {
-        int j = e / N, c = e % N;
-        Q[s2][e] = base[(size_t)j * WT * N + c];
+      const DevSpin& S = s2 ? sb : sa;
+      const cd* TV = s2 ? TVb : TVa;
+      const int N = S.N, nv = S.nv, no = S.no, X = nv * no;
+      if (N == 0) {  // spin without electrons: zero traces
+        if (lane == 0) {
+          v0[((size_t)s2 * NW + w) * NG + g] = cd{0.0, 0.0};
+          ex0[((size_t)s2 * NW + w) * NG + g] = cd{0.0, 0.0};
+        }
+        continue;
       }
-      for (int e = tid; e < S.nv * N; e += bd) {
-        int a = e / N, c = e % N;
-        LTV[s2][e] = base[(size_t)(N + a) * WT * N + c];
+      const cd* base = (s2 ? LTb : LTa) + ((size_t)g * S.P) * WT * N + (size_t)wl * N;
+      const size_t ld = (size_t)WT * N;
+      cd x{0.0, 0.0};
+      for (int e = lane; e < N * N; e += 64) {
+        const int j = e / N, c = e % N;
+        Q[e] = base[(size_t)j * ld + c];
       }
-    }
-    __syncthreads();
-    for (int s2 = 0; s2 < 2; ++s2) {
-      const int N = sp[s2]->N;
-      for (int j = tid; j < N; j += bd) {
-        cd x{0.0, 0.0};
-        for (int c = 0; c < N; ++c) cfma(x, Q[s2][j * N + c], Q[s2][c * N + j]);
-        rowv[s2][j] = Q[s2][j * N + j];
-        rowx[s2][j] = x;
+      __syncthreads();
+      for (int e = lane; e < N * N; e += 64) {
+        const int j = e / N, c = e % N;
+        cfma(x, Q[e], Q[c * N + j]);
       }
-    }
-    __syncthreads();
-    if (tid < 2) {
-      const int N = sp[tid]->N;
-      cd v{0.0, 0.0}, x{0.0, 0.0};
-      for (int j = 0; j < N; ++j) {
-        v += rowv[tid][j];
-        x += rowx[tid][j];
+      x = wave_sum(x);
+      if (lane == 0) {
+        v0[((size_t)s2 * NW + w) * NG + g] = s2 ? vb : va;
+        ex0[((size_t)s2 * NW + w) * NG + g] = x;
       }
-      v0s[tid] = v;
-      ex0s[tid] = x;
-      v0[((size_t)tid * NW + w) * NG + g] = v;
-      ex0[((size_t)tid * NW + w) * NG + g] = x;
-    }
-    __syncthreads();
-    const cd vsum = v0s[0] + v0s[1];
-    for (int s2 = 0; s2 < 2; ++s2) {
-      const DevSpin& S = *sp[s2];
-      const int N = S.N, nv = S.nv, no = S.no;
-      for (int e = tid; e < nv * N; e += bd) {
-        int a = e / N, c = e % N;
-        cd acc = -LTV[s2][e];
-        for (int j = 0; j < N; ++j) cfma(acc, TV[s2][a * N + j], Q[s2][j * N + c]);
+      for (int e = lane; e < nv * N; e += 64) {
+        const int a = e / N, c = e % N;
+        cd acc = -base[(size_t)(N + a) * ld + c];
+        for (int j = 0; j < N; ++j) cfma(acc, TV[a * N + j], Q[j * N + c]);
         Lf[e] = acc;
       }
       __syncthreads();
-      cd* Lo = Lam[s2] + ((size_t)wl * NG + g) * nv * no;
-#pragma unroll
-      for (int j = 0; j < ZW_PER_THREAD; ++j) {
-        const int e = tid + j * bd;
-        if (e < nv * no) {
-          const int a = e / no, i = e % no, oc = S.oslot[i];
-          cd xi{0.0, 0.0};
-          for (int c = 0; c < N; ++c) cfma(xi, Lf[a * N + c], Q[s2][c * N + oc]);
-          const cd lam = Lf[a * N + oc];
-          Lo[e] = lam;
-          zacc[s2][j] += xi - vsum * lam;
-        }
+      cd* Lo = (s2 ? Lam_b : Lam_a) + ((size_t)wl * NG + g) * X;
+      cd* Z = ZWs[s2];
+      for (int e = lane; e < X; e += 64) {
+        const int a = e / no, i = e % no, oc = S.oslot[i];
+        cd xi{0.0, 0.0};
+        for (int c = 0; c < N; ++c) cfma(xi, Lf[a * N + c], Q[c * N + oc]);
+        const cd lam = Lf[a * N + oc];
+        Lo[e] = lam;
+        Z[e] += xi - vsum * lam;
       }
       __syncthreads();
     }
   }
   for (int s2 = 0; s2 < 2; ++s2) {
-    const int X = sp[s2]->nv * sp[s2]->no;
-#pragma unroll
-    for (int j = 0; j < ZW_PER_THREAD; ++j) {
-      const int e = tid + j * bd;
-      if (e < X) ZW[s2][((size_t)wl * n_chunks + chunk) * X + e] = zacc[s2][j];
-    }
+    const int X = (s2 ? sb : sa).nv * (s2 ? sb : sa).no;
+    cd* ZW = s2 ? ZWb : ZWa;
+    for (int e = lane; e < X; e += 64) ZW[((size_t)wl * n_chunks + chunk) * X + e] = ZWs[s2][e];
   }
 }
 
@@ -688,16 +749,13 @@ void launch_lambda(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT,
                    cd* Lam_a, cd* Lam_b, cd* v0, cd* ex0, cd* ZWpart_a, cd* ZWpart_b,
                    hipStream_t st) {
   const int n_chunks = (NG + g_chunk - 1) / g_chunk;
-  size_t words = 0;
-  int lf = 0;
-  for (const DevSpin* s : {&sa, &sb}) {
-    words += (size_t)s->N * s->N + 2 * (size_t)s->nv * s->N;
-    lf = max(lf, s->nv * s->N);
-  }
-  words += lf;
-  hipLaunchKernelGGL(k_lambda, dim3(WT, n_chunks), dim3(256), words * sizeof(cd), st, sa, sb,
-                     NW, w0, WT, NG, g_chunk, Ta, Tb, LTa, LTb, Lam_a, Lam_b, v0, ex0,
-                     ZWpart_a, ZWpart_b);
+  const size_t words = (size_t)sa.nv * sa.N + (size_t)sb.nv * sb.N +
+                       (size_t)max(sa.N * sa.N, sb.N * sb.N) +
+                       (size_t)max(sa.nv * sa.N, sb.nv * sb.N) + (size_t)sa.nv * sa.no +
+                       (size_t)sb.nv * sb.no;
+  hipLaunchKernelGGL(k_lambda, dim3(WT, n_chunks), dim3(64), words * sizeof(cd), st, sa, sb, NW,
+                     w0, WT, NG, g_chunk, Ta, Tb, LTa, LTb, Lam_a, Lam_b, v0, ex0, ZWpart_a,
+                     ZWpart_b);
 }
 
 // ============================================================================
@@ -749,70 +807,284 @@ void launch_minor_coef(const DevSpin& s, int NW, const cd* B, int U, const cd* m
 }
 
 // ============================================================================
-// A7: the Cholesky-vector loop.  Per (walker, chunk of Cholesky vectors) the
-// chunk's Lam^a, Lam^b windows are staged in LDS and every touched bilinear
-// term is accumulated: partial = sum_g [ sum_pairs coef Lam^a[x] Lam^b[y]
-//                   + sum_s sum_minors coef (Lam[ai]Lam[bj] - Lam[aj]Lam[bi]) ].
+// A7: the Cholesky-vector loop.  Second-order energy terms
+//   sum_g [ sum_pairs coef Lam^a_g[x] Lam^b_g[y]
+//         + sum_s sum_strings B_str e2(X_str, Y_str^g)     (same spin) ]
+// Every kernel streams Lam_g through LDS for its share of the Cholesky
+// vectors (double-buffered stages of G_STAGE vectors) and writes one partial
+// per workgroup into its own slot of partial[w][slot]; the energy assembly
+// sums the slots in order.
 // ============================================================================
 
-__global__ __launch_bounds__(256) void k_energy_gamma(DevSpin sa, DevSpin sb, DevPairs pr, int NW,
-                                                      int w0, int WT, int NG, int g_chunk,
-                                                      const cd* __restrict__ Lam_a,
-                                                      const cd* __restrict__ Lam_b,
-                                                      const cd* __restrict__ coef_pair,
-                                                      const cd* __restrict__ coef_ma,
-                                                      const cd* __restrict__ coef_mb,
-                                                      cd* __restrict__ partial) {
+constexpr int G_STAGE = 2;
+
+// Opposite-spin pairs: W_t = sum_g Lam^a[x_t] Lam^b[y_t] per pair (PAIRS_PER_THREAD
+// pairs per thread, kept in registers for the whole Cholesky range), then
+// sum_t coef_t W_t.
+constexpr int PAIRS_PER_THREAD = 8;
+constexpr int PAIR_THREADS = 512;
+
+__global__ __launch_bounds__(PAIR_THREADS) void k_energy_pairs(
+    DevPairs pr, int Xa, int Xb, int NW, int w0, int NG, int n_gsplit,
+    const cd* __restrict__ Lam_a, const cd* __restrict__ Lam_b, const cd* __restrict__ coef,
+    cd* __restrict__ partial, int n_slots, int slot0) {
   extern __shared__ cd sm[];
-  __shared__ cd red[256];
-  const int wl = blockIdx.x, chunk = blockIdx.y, n_chunks = gridDim.y;
-  const int w = w0 + wl, tid = threadIdx.x, bd = blockDim.x;
-  const int Xa = sa.nv * sa.no, Xb = sb.nv * sb.no;
-  const int g0 = chunk * g_chunk, G = min(NG, g0 + g_chunk) - g0;
-  cd* La = sm;            // [G][Xa]
-  cd* Lb = sm + (size_t)g_chunk * Xa;  // [G][Xb]
-  for (int e = tid; e < G * Xa; e += bd) La[e] = Lam_a[((size_t)wl * NG + g0) * Xa + e];
-  for (int e = tid; e < G * Xb; e += bd) Lb[e] = Lam_b[((size_t)wl * NG + g0) * Xb + e];
-  __syncthreads();
-  cd acc{0.0, 0.0};
-  for (int t = tid; t < pr.n_pair; t += bd) {
-    const int x = pr.x[t], y = pr.y[t];
-    cd s{0.0, 0.0};
-    for (int gl = 0; gl < G; ++gl) cfma(s, La[gl * Xa + x], Lb[gl * Xb + y]);
-    acc += coef_pair[(size_t)w * pr.n_pair + t] * s;
+  __shared__ cd red[PAIR_THREADS];
+  const int wl = blockIdx.x, gs = blockIdx.y, pb = blockIdx.z;
+  const int w = w0 + wl, tid = threadIdx.x;
+  const int gper = (NG + n_gsplit - 1) / n_gsplit;
+  const int g0 = gs * gper, g1 = min(NG, g0 + gper);
+  const int X = Xa + Xb;
+  cd* buf[2] = {sm, sm + G_STAGE * X};
+  int xs[PAIRS_PER_THREAD], ys[PAIRS_PER_THREAD];
+  cd acc[PAIRS_PER_THREAD];
+#pragma unroll
+  for (int j = 0; j < PAIRS_PER_THREAD; ++j) {
+    const int t = pb * PAIR_THREADS * PAIRS_PER_THREAD + j * PAIR_THREADS + tid;
+    xs[j] = t < pr.n_pair ? pr.x[t] : -1;
+    ys[j] = t < pr.n_pair ? Xa + pr.y[t] : 0;
+    acc[j] = cd{0.0, 0.0};
   }
-  const DevSpin* sp[2] = {&sa, &sb};
-  const cd* Ls[2] = {La, Lb};
-  const cd* cf[2] = {coef_ma, coef_mb};
-  const int Xs[2] = {Xa, Xb};
-  for (int s2 = 0; s2 < 2; ++s2) {
-    const DevSpin& S = *sp[s2];
-    const cd* L = Ls[s2];
-    const int X = Xs[s2];
-    for (int t = tid; t < S.n_minor; t += bd) {
-      const int ai = S.mn_idx[4 * t], bj = S.mn_idx[4 * t + 1];
-      const int aj = S.mn_idx[4 * t + 2], bi = S.mn_idx[4 * t + 3];
-      cd s{0.0, 0.0};
-      for (int gl = 0; gl < G; ++gl) {
-        const cd* Lg = L + gl * X;
-        cfma(s, Lg[ai], Lg[bj]);
-        s -= Lg[aj] * Lg[bi];
-      }
-      acc += cf[s2][(size_t)w * S.n_minor + t] * s;
+  auto stage = [&](int gb, cd* dst) {
+    const int G = min(G_STAGE, g1 - gb);
+    for (int e = tid; e < G * X; e += PAIR_THREADS) {
+      const int gl = e / X, x = e % X;
+      dst[e] = x < Xa ? Lam_a[((size_t)wl * NG + gb + gl) * Xa + x]
+                      : Lam_b[((size_t)wl * NG + gb + gl) * Xb + (x - Xa)];
     }
+  };
+  if (g0 < g1) stage(g0, buf[0]);
+  __syncthreads();
+  int it = 0;
+  for (int gb = g0; gb < g1; gb += G_STAGE, ++it) {
+    if (gb + G_STAGE < g1) stage(gb + G_STAGE, buf[(it + 1) & 1]);
+    const cd* L = buf[it & 1];
+    const int G = min(G_STAGE, g1 - gb);
+    for (int gl = 0; gl < G; ++gl) {
+      const cd* Lg = L + gl * X;
+#pragma unroll
+      for (int j = 0; j < PAIRS_PER_THREAD; ++j)
+        if (xs[j] >= 0) cfma(acc[j], Lg[xs[j]], Lg[ys[j]]);
+    }
+    __syncthreads();
   }
-  cd tot = block_reduce(acc, red);
-  if (tid == 0) partial[(size_t)w * n_chunks + chunk] = tot;
+  cd tot{0.0, 0.0};
+#pragma unroll
+  for (int j = 0; j < PAIRS_PER_THREAD; ++j) {
+    const int t = pb * PAIR_THREADS * PAIRS_PER_THREAD + j * PAIR_THREADS + tid;
+    if (xs[j] >= 0) cfma(tot, coef[(size_t)w * pr.n_pair + t], acc[j]);
+  }
+  red[tid] = tot;
+  __syncthreads();
+  for (int off = PAIR_THREADS / 2; off > 0; off >>= 1) {
+    if (tid < off) red[tid] += red[tid + off];
+    __syncthreads();
+  }
+  if (tid == 0)
+    partial[(size_t)w * n_slots + slot0 + (size_t)pb * n_gsplit + gs] = red[0];
 }
 
-void launch_energy_gamma(const DevSpin& sa, const DevSpin& sb, const DevPairs& pr, int NW,
-                         int w0, int WT, int NG, int g_chunk, const cd* Lam_a, const cd* Lam_b,
-                         const cd* coef_pair, const cd* coef_ma, const cd* coef_mb, cd* partial,
-                         hipStream_t st) {
-  const int n_chunks = (NG + g_chunk - 1) / g_chunk;
-  size_t lds = (size_t)g_chunk * (sa.nv * sa.no + sb.nv * sb.no) * sizeof(cd);
-  hipLaunchKernelGGL(k_energy_gamma, dim3(WT, n_chunks), dim3(256), lds, st, sa, sb, pr, NW,
-                     w0, WT, NG, g_chunk, Lam_a, Lam_b, coef_pair, coef_ma, coef_mb, partial);
+// Same-spin terms per string of order K (2..4): the K x K block
+// Y_mn = Lam_g[p_n, h_m] is gathered once per Cholesky vector and all
+// C(K,2)^2 second-order minors are formed from registers:
+//   e2 = sum (-1)^{m+m'+n+n'} det X[~{m,m'},~{n,n'}] (Y_mn Y_m'n' - Y_mn' Y_m'n).
+constexpr int STR_THREADS = 256;
+
+template <int K>
+__global__ __launch_bounds__(STR_THREADS) void k_energy_strings(
+    DevSpin s, int NW, int w0, int NG, int n_gsplit, const cd* __restrict__ Lam,
+    const cd* __restrict__ m2, const cd* __restrict__ B, cd* __restrict__ partial, int n_slots,
+    int slot0) {
+  constexpr int P = K * (K - 1) / 2;
+  extern __shared__ cd sm[];
+  __shared__ cd red[STR_THREADS];
+  const int wl = blockIdx.x, gs = blockIdx.y, sc = blockIdx.z;
+  const int w = w0 + wl, tid = threadIdx.x;
+  const int X = s.nv * s.no;
+  const int gper = (NG + n_gsplit - 1) / n_gsplit;
+  const int g0 = gs * gper, g1 = min(NG, g0 + gper);
+  const int str = s.bucket[K] + sc * STR_THREADS + tid;
+  const bool live = str < s.bucket[K + 1];
+  cd* buf[2] = {sm, sm + G_STAGE * X};
+  int idx[K * K];
+  cd mm[P * P];
+#pragma unroll
+  for (int m = 0; m < K; ++m)
+#pragma unroll
+    for (int n = 0; n < K; ++n)
+      idx[m * K + n] = live ? s.pwin[str * KMAX + n] * s.no + s.hwin[str * KMAX + m] : 0;
+  if (live) {
+    const cd* src = m2 + (size_t)w * s.M2 + s.m2_off[str];
+#pragma unroll
+    for (int a = 0; a < P * P; ++a) mm[a] = src[a];
+  } else {
+#pragma unroll
+    for (int a = 0; a < P * P; ++a) mm[a] = cd{0.0, 0.0};
+  }
+  // fold the signs (-1)^{m+m'+n+n'} into the minors
+#pragma unroll
+  for (int m = 0; m < K; ++m)
+#pragma unroll
+    for (int mp = m + 1; mp < K; ++mp)
+#pragma unroll
+      for (int n = 0; n < K; ++n)
+#pragma unroll
+        for (int np = n + 1; np < K; ++np)
+          if ((m + mp + n + np) & 1) mm[pair_index(m, mp, K) * P + pair_index(n, np, K)] =
+              -mm[pair_index(m, mp, K) * P + pair_index(n, np, K)];
+  auto stage = [&](int gb, cd* dst) {
+    const int G = min(G_STAGE, g1 - gb);
+    for (int e = tid; e < G * X; e += STR_THREADS)
+      dst[e] = Lam[((size_t)wl * NG + gb) * X + e];
+  };
+  if (g0 < g1) stage(g0, buf[0]);
+  __syncthreads();
+  cd acc{0.0, 0.0};
+  int it = 0;
+  for (int gb = g0; gb < g1; gb += G_STAGE, ++it) {
+    if (gb + G_STAGE < g1) stage(gb + G_STAGE, buf[(it + 1) & 1]);
+    const cd* L = buf[it & 1];
+    const int G = min(G_STAGE, g1 - gb);
+    for (int gl = 0; gl < G; ++gl) {
+      const cd* Lg = L + gl * X;
+      cd Y[K * K];
+#pragma unroll
+      for (int a = 0; a < K * K; ++a) Y[a] = Lg[idx[a]];
+#pragma unroll
+      for (int m = 0; m < K; ++m)
+#pragma unroll
+        for (int mp = m + 1; mp < K; ++mp)
+#pragma unroll
+          for (int n = 0; n < K; ++n)
+#pragma unroll
+            for (int np = n + 1; np < K; ++np) {
+              const cd d2 = Y[m * K + n] * Y[mp * K + np] - Y[m * K + np] * Y[mp * K + n];
+              cfma(acc, mm[pair_index(m, mp, K) * P + pair_index(n, np, K)], d2);
+            }
+    }
+    __syncthreads();
+  }
+  cd tot{0.0, 0.0};
+  if (live) tot = B[(size_t)w * s.U + str] * acc;
+  red[tid] = tot;
+  __syncthreads();
+  for (int off = STR_THREADS / 2; off > 0; off >>= 1) {
+    if (tid < off) red[tid] += red[tid + off];
+    __syncthreads();
+  }
+  if (tid == 0)
+    partial[(size_t)w * n_slots + slot0 + (size_t)sc * n_gsplit + gs] = red[0];
+}
+
+// Same-spin terms through the trial's list of distinct second-order minors
+// (a < b, i < j): sum_t coef_t sum_g det2(Lam_g; a,b; i,j).  Preferred when the
+// excitation window is small and many strings share the same minors.
+constexpr int MINOR_THREADS = 256;
+
+__global__ __launch_bounds__(MINOR_THREADS) void k_energy_minors(
+    DevSpin s, int NW, int w0, int NG, int n_gsplit, const cd* __restrict__ Lam,
+    const cd* __restrict__ coef, cd* __restrict__ partial, int n_slots, int slot0) {
+  extern __shared__ cd sm[];
+  __shared__ cd red[MINOR_THREADS];
+  const int wl = blockIdx.x, gs = blockIdx.y, mb = blockIdx.z;
+  const int w = w0 + wl, tid = threadIdx.x;
+  const int X = s.nv * s.no;
+  const int gper = (NG + n_gsplit - 1) / n_gsplit;
+  const int g0 = gs * gper, g1 = min(NG, g0 + gper);
+  cd* buf[2] = {sm, sm + G_STAGE * X};
+  constexpr int MPT = 8;
+  int id[MPT][4];
+  cd acc[MPT];
+#pragma unroll
+  for (int j = 0; j < MPT; ++j) {
+    const int t = mb * MINOR_THREADS * MPT + j * MINOR_THREADS + tid;
+    const bool ok = t < s.n_minor;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) id[j][q] = ok ? s.mn_idx[4 * t + q] : -1;
+    acc[j] = cd{0.0, 0.0};
+  }
+  auto stage = [&](int gb, cd* dst) {
+    const int G = min(G_STAGE, g1 - gb);
+    for (int e = tid; e < G * X; e += MINOR_THREADS)
+      dst[e] = Lam[((size_t)wl * NG + gb) * X + e];
+  };
+  if (g0 < g1) stage(g0, buf[0]);
+  __syncthreads();
+  int it = 0;
+  for (int gb = g0; gb < g1; gb += G_STAGE, ++it) {
+    if (gb + G_STAGE < g1) stage(gb + G_STAGE, buf[(it + 1) & 1]);
+    const cd* L = buf[it & 1];
+    const int G = min(G_STAGE, g1 - gb);
+    for (int gl = 0; gl < G; ++gl) {
+      const cd* Lg = L + gl * X;
+#pragma unroll
+      for (int j = 0; j < MPT; ++j)
+        if (id[j][0] >= 0) {
+          cfma(acc[j], Lg[id[j][0]], Lg[id[j][1]]);
+          acc[j] -= Lg[id[j][2]] * Lg[id[j][3]];
+        }
+    }
+    __syncthreads();
+  }
+  cd tot{0.0, 0.0};
+#pragma unroll
+  for (int j = 0; j < MPT; ++j) {
+    const int t = mb * MINOR_THREADS * MPT + j * MINOR_THREADS + tid;
+    if (id[j][0] >= 0) cfma(tot, coef[(size_t)w * s.n_minor + t], acc[j]);
+  }
+  red[tid] = tot;
+  __syncthreads();
+  for (int off = MINOR_THREADS / 2; off > 0; off >>= 1) {
+    if (tid < off) red[tid] += red[tid + off];
+    __syncthreads();
+  }
+  if (tid == 0)
+    partial[(size_t)w * n_slots + slot0 + (size_t)mb * n_gsplit + gs] = red[0];
+}
+
+int energy_pair_blocks(int n_pair) {
+  return (n_pair + PAIR_THREADS * PAIRS_PER_THREAD - 1) / (PAIR_THREADS * PAIRS_PER_THREAD);
+}
+int energy_string_blocks(const DevSpin& s, int k) {
+  return (s.bucket[k + 1] - s.bucket[k] + STR_THREADS - 1) / STR_THREADS;
+}
+int energy_minor_blocks(const DevSpin& s) {
+  return (s.n_minor + MINOR_THREADS * 8 - 1) / (MINOR_THREADS * 8);
+}
+
+void launch_energy_pairs(const DevPairs& pr, int Xa, int Xb, int NW, int w0, int WT, int NG,
+                         int n_gsplit, const cd* Lam_a, const cd* Lam_b, const cd* coef,
+                         cd* partial, int n_slots, int slot0, hipStream_t st) {
+  const int nb = energy_pair_blocks(pr.n_pair);
+  if (nb == 0) return;
+  const size_t lds = 2 * (size_t)G_STAGE * (Xa + Xb) * sizeof(cd);
+  hipLaunchKernelGGL(k_energy_pairs, dim3(WT, n_gsplit, nb), dim3(PAIR_THREADS), lds, st, pr, Xa,
+                     Xb, NW, w0, NG, n_gsplit, Lam_a, Lam_b, coef, partial, n_slots, slot0);
+}
+
+void launch_energy_strings(const DevSpin& s, int k, int NW, int w0, int WT, int NG, int n_gsplit,
+                           const cd* Lam, const cd* m2, const cd* B, cd* partial, int n_slots,
+                           int slot0, hipStream_t st) {
+  const int nb = energy_string_blocks(s, k);
+  if (nb == 0) return;
+  const size_t lds = 2 * (size_t)G_STAGE * s.nv * s.no * sizeof(cd);
+  dim3 grid(WT, n_gsplit, nb);
+  switch (k) {
+    case 2: hipLaunchKernelGGL(k_energy_strings<2>, grid, dim3(STR_THREADS), lds, st, s, NW, w0, NG, n_gsplit, Lam, m2, B, partial, n_slots, slot0); break;
+    case 3: hipLaunchKernelGGL(k_energy_strings<3>, grid, dim3(STR_THREADS), lds, st, s, NW, w0, NG, n_gsplit, Lam, m2, B, partial, n_slots, slot0); break;
+    case 4: hipLaunchKernelGGL(k_energy_strings<4>, grid, dim3(STR_THREADS), lds, st, s, NW, w0, NG, n_gsplit, Lam, m2, B, partial, n_slots, slot0); break;
+    default: break;
+  }
+}
+
+void launch_energy_minors(const DevSpin& s, int NW, int w0, int WT, int NG, int n_gsplit,
+                          const cd* Lam, const cd* coef, cd* partial, int n_slots, int slot0,
+                          hipStream_t st) {
+  const int nb = energy_minor_blocks(s);
+  if (nb == 0) return;
+  const size_t lds = 2 * (size_t)G_STAGE * s.nv * s.no * sizeof(cd);
+  hipLaunchKernelGGL(k_energy_minors, dim3(WT, n_gsplit, nb), dim3(MINOR_THREADS), lds, st, s, NW,
+                     w0, NG, n_gsplit, Lam, coef, partial, n_slots, slot0);
 }
 
 // ============================================================================
@@ -857,7 +1129,7 @@ __global__ __launch_bounds__(256) void k_energy_final(DevSpin sa, DevSpin sb, in
       czw += C[s2][(size_t)w * X + e] * z;
     }
   }
-  for (int c = tid; c < n_echunks; c += bd) czw += epart[(size_t)w * n_echunks + c];
+  for (int c = tid; c < n_echunks; c += bd) czw += epart[(size_t)w * n_echunks + c];  // slots
   czw = block_reduce(czw, red);
   if (tid == 0) e_loc[w] = cd{e0, 0.0} + oba[w] + obb[w] + first + cdiv(czw, obar[w]);
 }
@@ -896,7 +1168,11 @@ void init_wick_attributes() {
   hipFuncSetAttribute((const void*)k_ref_inverse, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   hipFuncSetAttribute((const void*)k_green, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   hipFuncSetAttribute((const void*)k_lambda, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-  hipFuncSetAttribute((const void*)k_energy_gamma, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  hipFuncSetAttribute((const void*)k_energy_pairs, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  hipFuncSetAttribute((const void*)k_energy_minors, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  hipFuncSetAttribute((const void*)k_energy_strings<2>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  hipFuncSetAttribute((const void*)k_energy_strings<3>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  hipFuncSetAttribute((const void*)k_energy_strings<4>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
 }
 
 }  // namespace msd

@@ -320,3 +320,15 @@ def test_error_paths():
     with pytest.raises(MsdError) as e:
         s.set_hamiltonian(h, wl.chol, 0.0)
     assert e.value.name == "MSD_ERR_ARG"
+
+
+@pytest.mark.parametrize("algo", [1, 2])
+def test_energy_algorithms_agree_with_oracle(algo):
+    """Both forms of the same-spin second-order terms (per-minor lists and
+    per-string registers) against the oracle, including orders up to 4."""
+    wl = make_workload("algo", M=20, n_alpha=5, n_beta=4, n_chol=24, n_det=80, k_max=6,
+                       window=(4, 9), c_law="flat", n_walkers=4, seed=91 + algo,
+                       complex_ci=True, noise=0.4)
+    s = system_for(wl, energy_algo=algo)
+    out = s.measure(0.01)
+    compare_walkers(wl, out, range(4), 0.01)
