@@ -51,8 +51,15 @@ def stage_work(wl, lib_sys, stage):
             f += NG * NW * 8.0 * (nv * N * N + nv * N * no + N * N)
         return f, "flop", "alu"
     if stage == "energy_gamma":
-        b = NW * NG * 16.0 * (tt["nv"][0] * tt["no"][0] + tt["nv"][1] * tt["no"][1])
-        return b, "byte", "hbm"
+        # per walker and Cholesky vector: one complex MAC per opposite-spin
+        # pair; per string of order k, k(k-1)/2 x k(k-1)/2 two-by-two minors of
+        # Y, each 2 complex products, a difference and a complex MAC (22 flop)
+        f = 8.0 * tt["n_pair"]
+        for sp in (0, 1):
+            for k, n in tt["strings"][sp].items():
+                p = k * (k - 1) // 2
+                f += 22.0 * p * p * n
+        return NW * NG * f, "flop", "alu"
     return None
 
 
@@ -116,41 +123,54 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
-    s = MsdSystem(wl.M, wl.n_alpha, wl.n_beta, wl.n_chol, wl.n_walkers, wl.n_det, device=0,
-                  stream=stream.cuda_stream, stabilize_freq=1, timing=True)
-    s.set_hamiltonian(wl.h1, wl.chol, wl.e0)
-    s.set_trial(wl.ci, wl.occ_a, wl.occ_b)
-    s.set_walkers(wl.phi_a, wl.phi_b, wl.weights)
-    s.tables = _tables(wl)
+
+    def system(timing):
+        s = MsdSystem(wl.M, wl.n_alpha, wl.n_beta, wl.n_chol, wl.n_walkers, wl.n_det, device=0,
+                      stream=stream.cuda_stream, stabilize_freq=1, timing=timing,
+                      graphs=not timing)
+        s.set_hamiltonian(wl.h1, wl.chol, wl.e0)
+        s.set_trial(wl.ci, wl.occ_a, wl.occ_b)
+        s.set_walkers(wl.phi_a, wl.phi_b, wl.weights)
+        s.tables = _tables(wl)
+        return s
+
     n_total = args.warmup + args.steps
     fields = torch.from_numpy(np.stack([fields_for_step(wl, k) for k in range(n_total)])).to(dev)
     lo = torch.empty(wl.n_walkers, dtype=torch.complex128, device=dev)
     fb = torch.empty(wl.n_walkers, wl.n_chol, dtype=torch.complex128, device=dev)
     el = torch.empty(wl.n_walkers, dtype=torch.complex128, device=dev)
-    per_step = wl.n_walkers * wl.n_chol
 
-    def step(k):
+    def step(s, k):
         s.propagate_dev(fields[k].reshape(-1), wl.dt, 0.0, 1)
         s.measure_dev(wl.dt, lo, fb, el)
 
+    def timed(s, fn, n):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for k in range(n):
+            fn(k)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1), time.perf_counter() - t0
+
+    # main timed region: every step replayed from HIP graphs
+    s = system(False)
     for k in range(args.warmup):
-        step(k)
-    torch.cuda.synchronize()
-    s.reset_timings()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record(stream)
-    for k in range(args.warmup, n_total):
-        step(k)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1)
+        step(s, k)
+    ms, wall = timed(s, lambda k: step(s, args.warmup + k), args.steps)
     ms_step = ms / args.steps
     value = wl.n_walkers * wl.n_det / (ms_step * 1e-3)
-    del per_step
-
+    ms_meas, _ = timed(s, lambda k: s.measure_dev(wl.dt, lo, fb, el), args.steps)
+    meas_value = wl.n_walkers * wl.n_det / (ms_meas / args.steps * 1e-3)
+    # instrumented pass of the same steps: HIP events around every stage
+    s = system(True)
+    for k in range(args.warmup):
+        step(s, k)
+    torch.cuda.synchronize()
+    s.reset_timings()
+    timed(s, lambda k: step(s, args.warmup + k), args.steps)
     stages = s.timings()
     dom = max((k for k in stages if stages[k][1] > 0), key=lambda k: stages[k][0])
     roof = None
@@ -193,6 +213,10 @@ def main():
         "dominant_stage": dom,
         "stages_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in stages.items() if v[1]},
         "wall_s": round(wall, 3),
+        "measure_only": {"value": meas_value, "ms": round(ms_meas / args.steps, 4),
+                         "note": "msd_measure_dev alone (overlap, G, force bias, E_L)"},
+        "stage_timing_note": "stages_ms and roofline from a second pass of the same steps with "
+                             "HIP events around every stage (no graphs)",
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl)
@@ -200,19 +224,39 @@ def main():
 
 
 def _tables(wl):
-    """Window sizes of the trial (from its occupation lists)."""
-    out = {"nv": [], "no": []}
+    """Window sizes, distinct strings per order and distinct opposite-spin
+    (particle, hole) pairs of the trial, from its occupation lists."""
+    out = {"nv": [], "no": [], "strings": []}
     rows = set()
+    exc = []
     for occ in (wl.occ_a, wl.occ_b):
         ref = set(occ[0].tolist())
         holes, parts = set(), set()
+        strings = set()
+        per_det = []
         for row in occ:
             r = set(row.tolist())
-            holes |= ref - r
-            parts |= r - ref
+            h, p = tuple(sorted(ref - r)), tuple(sorted(r - ref))
+            holes |= set(h)
+            parts |= set(p)
+            strings.add((h, p))
+            per_det.append((h, p))
         out["nv"].append(len(parts))
         out["no"].append(len(holes))
+        counts = {}
+        for h, _ in strings:
+            if len(h) >= 2:
+                counts[len(h)] = counts.get(len(h), 0) + 1
+        out["strings"].append(counts)
         rows |= ref | parts
+        exc.append(per_det)
+    pairs = set()
+    for (ha, pa), (hb, pb) in zip(*exc):
+        if ha and hb:
+            xa = [(q, h) for q in pa for h in ha]
+            xb = [(q, h) for q in pb for h in hb]
+            pairs.update((x, y) for x in xa for y in xb)
+    out["n_pair"] = len(pairs)
     out["P_all"] = len(rows)
     return out
 

@@ -79,8 +79,13 @@ typedef struct {
   int32_t stabilize_freq; /* QR every this many propagate steps (0 = never), default 5 */
   int32_t timing;         /* 1: record HIP events around every kernel stage   */
   int32_t energy_algo;    /* same-spin second-order energy terms: 0 = choose per spin
-                             (fewest gathers), 1 = per-minor lists, 2 = per-string   */
-  int32_t reserved[4];
+                             (fewest gathers), 1 = per-minor lists, 2 = per-string;
+                             3 = automatic choice with the fused Cholesky contraction
+                             (GEMM tile consumed in LDS) where its tile fits         */
+  int32_t graphs;         /* 1: record each measure / propagate step once as a HIP graph
+                             (on a private stream) and replay it on the handle's stream;
+                             ignored while timing is on.  Default 0                  */
+  int32_t reserved[3];
 } msd_options;
 
 /* Limits of this implementation. */
@@ -117,6 +122,22 @@ msd_status msd_set_hamiltonian(msd_system* sys, const double* h1, const double* 
 msd_status msd_set_trial_occ(msd_system* sys, const double* ci, const int32_t* occ_a,
                              const int32_t* occ_b);
 
+/* Trial as excitations of a reference (Sec. II.B, Eq. 15), same meaning as
+ * msd_set_trial_occ.  ref_a: n_alpha int32, ref_b: n_beta int32 (the reference
+ * determinant's orbitals).  Determinant I has k_a[I] alpha and k_b[I] beta
+ * holes: holes[offsets[I] + m] / parts[offsets[I] + m] for m < k_a[I] are its
+ * alpha hole/particle orbitals, the next k_b[I] entries its beta ones; pairing
+ * of holes with particles is irrelevant (the determinant is the orbital set
+ * reference - holes + particles, in ascending order, as in msd_set_trial_occ).
+ * offsets: n_det + 1 int64, offsets[0] = 0, offsets[I+1] - offsets[I] =
+ * k_a[I] + k_b[I].  ci: n_det complex.  n_det must equal the handle's n_det
+ * (MSD_ERR_SHAPE).  MSD_ERR_TRIAL for a hole outside the reference, a
+ * particle inside it, a repeat, or inconsistent offsets. */
+msd_status msd_set_trial_exc(msd_system* sys, const int32_t* ref_a, const int32_t* ref_b,
+                             int64_t n_det, const double* ci, const int32_t* k_a,
+                             const int32_t* k_b, const int64_t* offsets, const int32_t* holes,
+                             const int32_t* parts);
+
 /* Walkers (host arrays).  phi_a: n_walkers*M*n_alpha complex, [w][p][j];
  * phi_b likewise with n_beta; weights: n_walkers doubles (NULL: all 1).
  * Needs the trial (MSD_ERR_STATE otherwise): computes log <Psi_T|Phi_w>.
@@ -130,6 +151,10 @@ msd_status msd_set_walkers_dev(msd_system* sys, const double* phi_a, const doubl
  * complex, log <Psi_T|Phi_w> (imaginary part defined modulo 2 pi). */
 msd_status msd_get_walkers(msd_system* sys, double* phi_a, double* phi_b, double* weights,
                            double* log_ovlp);
+
+/* Weights and log <Psi_T|Phi_w> only (Eqs. 8-12 state); same as
+ * msd_get_walkers with NULL orbitals. */
+msd_status msd_get_weights(msd_system* sys, double* weights, double* log_ovlp);
 
 /* Measurement (Eq. 13/15 overlap, Eq. 14 mixed Green's function, Eq. 7 force
  * bias, the mixed-estimator local energy of Sec. II.A evaluated by the

@@ -23,7 +23,7 @@ class MsdDims(C.Structure):
 
 class MsdOptions(C.Structure):
     _fields_ = [("n_taylor", C.c_int32), ("stabilize_freq", C.c_int32), ("timing", C.c_int32),
-                ("energy_algo", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("energy_algo", C.c_int32), ("graphs", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -40,9 +40,11 @@ SIGNATURES = {
     "msd_destroy": (None, [_vp]),
     "msd_set_hamiltonian": (C.c_int, [_vp, _vp, _vp, C.c_double]),
     "msd_set_trial_occ": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "msd_set_trial_exc": (C.c_int, [_vp, _vp, _vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "msd_set_walkers": (C.c_int, [_vp, _vp, _vp, _vp]),
     "msd_set_walkers_dev": (C.c_int, [_vp, _vp, _vp, _vp]),
     "msd_get_walkers": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "msd_get_weights": (C.c_int, [_vp, _vp, _vp]),
     "msd_measure": (C.c_int, [_vp, C.c_double, _vp, _vp, _vp]),
     "msd_measure_dev": (C.c_int, [_vp, C.c_double, _vp, _vp, _vp]),
     "msd_propagate": (C.c_int, [_vp, _vp, C.c_double, C.c_double, C.c_int32]),

@@ -40,7 +40,7 @@ class MsdSystem:
     def __init__(self, M: int, n_alpha: int, n_beta: int, n_chol: int, n_walkers: int,
                  n_det: int, device: int = 0, stream: Optional[int] = None,
                  n_taylor: int = 6, stabilize_freq: int = 5, timing: bool = False,
-                 energy_algo: int = 0):
+                 energy_algo: int = 0, graphs: bool = False):
         self.lib = _lib.load()
         self.dims = _lib.MsdDims(M, n_alpha, n_beta, n_chol, n_walkers, 0, n_det)
         opts = _lib.MsdOptions()
@@ -49,6 +49,7 @@ class MsdSystem:
         opts.stabilize_freq = stabilize_freq
         opts.timing = 1 if timing else 0
         opts.energy_algo = int(energy_algo)
+        opts.graphs = 1 if graphs else 0
         self.M, self.na, self.nb, self.ng, self.nw, self.nd = (
             M, n_alpha, n_beta, n_chol, n_walkers, n_det)
         h = C.c_void_p()
@@ -88,6 +89,20 @@ class MsdSystem:
         ob = _host(occ_b, np.int32)
         self._check(self.lib.msd_set_trial_occ(self.h, _ptr(ci), _ptr(oa), _ptr(ob)))
 
+    def set_trial_exc(self, ref_a, ref_b, ci, k_a, k_b, offsets, holes, parts):
+        """Trial as excitation lists (see msd_set_trial_exc)."""
+        ra = _host(ref_a, np.int32)
+        rb = _host(ref_b, np.int32)
+        ci = _host(ci, np.complex128)
+        ka = _host(k_a, np.int32)
+        kb = _host(k_b, np.int32)
+        off = _host(offsets, np.int64)
+        h = _host(holes, np.int32)
+        p = _host(parts, np.int32)
+        self._check(self.lib.msd_set_trial_exc(self.h, _ptr(ra), _ptr(rb), int(ci.shape[0]),
+                                               _ptr(ci), _ptr(ka), _ptr(kb), _ptr(off), _ptr(h),
+                                               _ptr(p)))
+
     def set_walkers(self, phi_a, phi_b, weights=None):
         pa = _host(phi_a, np.complex128)
         pb = _host(phi_b, np.complex128)
@@ -106,6 +121,12 @@ class MsdSystem:
         lo = np.empty(self.nw, np.complex128)
         self._check(self.lib.msd_get_walkers(self.h, _ptr(pa), _ptr(pb), _ptr(w), _ptr(lo)))
         return pa, pb, w, lo
+
+    def get_weights(self):
+        w = np.empty(self.nw, np.float64)
+        lo = np.empty(self.nw, np.complex128)
+        self._check(self.lib.msd_get_weights(self.h, _ptr(w), _ptr(lo)))
+        return w, lo
 
     def measure(self, dt: float, energy: bool = True, force_bias: bool = True):
         lo = np.empty(self.nw, np.complex128)

@@ -131,10 +131,14 @@ struct msd_system {
   // energy work (lazily sized)
   int WT = 0, gl_chunk = 16, n_lchunks = 0;
   // second-order energy plan: per-spin algorithm and partial slots
-  int gsplit = 1, n_slots = 0, slot_pairs = 0;
+  int gsplit = 1, n_slots = 0;
   bool use_strings[2] = {false, false};
-  int slot_str[2][msd::KMAX + 1] = {{0}};
   int slot_min[2] = {0, 0};
+  // merged second-order kernel: wave plan (role | spin << 8, first string of
+  // the order, first item, item end), ER_WAVES entries per item block
+  std::vector<int4> plan_host;
+  int4* plan = nullptr;
+  int n_itemblocks = 0, slot_second = 0, second_G = 1;
   cd* LT[2] = {nullptr, nullptr};
   cd* Lam[2] = {nullptr, nullptr};
   cd* v0 = nullptr;
@@ -152,6 +156,23 @@ struct msd_system {
   int* mask = nullptr;
   double* qr_ldet = nullptr;  // [NW][2] log det R per spin
   double* fields = nullptr;  // staging for host fields [NW][NG]
+
+  // graph replay: one executable graph per (kind, variant), captured on a
+  // private stream and launched on st; keyed by the scalars baked into it
+  struct GraphSlot {
+    hipGraphExec_t exec = nullptr;
+    double dt = 0.0, e_shift = 0.0;
+  };
+  hipStream_t cap_st = nullptr;
+  GraphSlot g_step[2];     // [QR in this step]
+  GraphSlot g_measure[2];  // [energy requested]
+  void drop_graphs() {
+    for (GraphSlot* g : {&g_step[0], &g_step[1], &g_measure[0], &g_measure[1]}) {
+      if (g->exec) (void)hipGraphExecDestroy(g->exec);
+      g->exec = nullptr;
+    }
+  }
+  bool graphs_on() const { return o.graphs && !o.timing; }
 
   // timing
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
@@ -264,6 +285,7 @@ std::vector<double> expm_host(const std::vector<double>& a, int n) {
 }
 
 void free_energy(msd_system* s) {
+  s->drop_graphs();
   s->energy_mem.release();
   s->WT = 0;
 }
@@ -295,42 +317,59 @@ void alloc_energy(msd_system* s) {
   s->WT = wt;
   s->gl_chunk = 16;
   s->n_lchunks = (NG + s->gl_chunk - 1) / s->gl_chunk;
-  // split the Cholesky range so the second-order kernels have ~512+ workgroups
-  s->gsplit = std::max(1, std::min((512 + wt - 1) / wt, std::max(1, NG / 8)));
   int slot = 0;
-  s->slot_pairs = slot;
-  slot += msd::energy_pair_blocks(s->dp.n_pair) * s->gsplit;
+  // Per spin: same-spin second-order terms as row-pair items of each string
+  // (merged kernel) or as a list of distinct minors.  Cost per Cholesky vector
+  // in LDS gathers plus complex products: a row-pair item of order k gathers 2k
+  // values and forms k(k-1)/2 products; a distinct minor gathers 4 and forms 2.
+  std::vector<int4>& pl = s->plan_host;
+  pl.clear();
+  const int np = s->dp.n_pair;
+  for (int f = 0; f < np; f += 64 * 8) pl.push_back(int4{msd::ER_PAIRS, 0, f, np});
   for (int sp = 0; sp < 2; ++sp) {
-    const msd::DevSpin& D = s->ds[sp];
     const msd::SpinTable& S = s->tt.s[sp];
-    // LDS gathers per Cholesky vector: k^2 per string vs 4 per distinct minor
-    long g_str = 0;
+    long c_str = 0;
     bool big = false;
     for (int i = 0; i < S.U; ++i) {
-      if (S.k[i] >= 2) g_str += (long)S.k[i] * S.k[i];
-      if (S.k[i] > 4) big = true;
+      const long k = S.k[i];
+      if (k >= 2) c_str += k * (k - 1) / 2 * (2 * k + 3 * k * (k - 1) / 2);
+      if (k > msd::ER_MAX_ORDER) big = true;
     }
-    const long g_min = 4L * S.n_minor;
-    bool strings = g_str < g_min;
+    const long c_min = 10L * S.n_minor;
+    bool strings = c_str < c_min;
     if (s->o.energy_algo == 1) strings = false;
     if (s->o.energy_algo == 2) strings = true;
-    if (big) strings = false;  // orders above 4 only in the minor-list form
+    if (big) strings = false;  // orders above ER_MAX_ORDER only in the minor-list form
     s->use_strings[sp] = strings;
-    if (strings) {
-      for (int k = 2; k <= 4; ++k) {
-        s->slot_str[sp][k] = slot;
-        slot += msd::energy_string_blocks(D, k) * s->gsplit;
-      }
-    } else {
-      s->slot_min[sp] = slot;
-      slot += msd::energy_minor_blocks(D) * s->gsplit;
+    if (!strings) continue;
+    for (int k = 2; k <= msd::ER_MAX_ORDER; ++k) {
+      const int n_items = (S.bucket[k + 1] - S.bucket[k]) * (k * (k - 1) / 2);
+      for (int f = 0; f < n_items; f += 64) pl.push_back(int4{k | (sp << 8), S.bucket[k], f, n_items});
     }
+  }
+  while (pl.size() % msd::ER_WAVES) pl.push_back(int4{msd::ER_NONE, 0, 0, 0});
+  s->n_itemblocks = (int)(pl.size() / msd::ER_WAVES);
+  // split the Cholesky range so the second-order kernels have ~1024+ workgroups
+  const int units = std::max(1, s->n_itemblocks);
+  s->gsplit = std::max(1, std::min((1024 + wt * units - 1) / (wt * units), std::max(1, NG / 8)));
+  s->slot_second = slot;
+  slot += s->n_itemblocks * s->gsplit;
+  for (int sp = 0; sp < 2; ++sp) {
+    if (s->use_strings[sp]) continue;
+    s->slot_min[sp] = slot;
+    slot += msd::energy_minor_blocks(s->ds[sp]) * s->gsplit;
+  }
+  {
+    const int X = A.nv * A.no + B.nv * B.no;
+    s->second_G = std::max(1, std::min(32, (int)((64 << 10) / (2 * 16 * std::max(X, 1)))));
   }
   s->n_slots = slot;  // every slot is written by exactly one workgroup
   Arena& E = s->energy_mem;
   for (int sp = 0; sp < 2; ++sp) {
     const msd::DevSpin& D = s->ds[sp];
-    s->LT[sp] = E.get<cd>((size_t)NG * D.P * wt * D.N);
+    int wbf = 0;
+    if (!(s->o.energy_algo == 3 && msd::chol_contract_fits(s->ds[0], s->ds[1], &wbf)))
+      s->LT[sp] = E.get<cd>((size_t)NG * D.P * wt * D.N);
     s->Lam[sp] = E.get<cd>((size_t)wt * NG * D.nv * D.no);
     s->ZWp[sp] = E.get<cd>((size_t)wt * s->n_lchunks * D.nv * D.no);
     s->coef2[sp] = E.get<cd>((size_t)NW * D.n_minor);
@@ -339,6 +378,7 @@ void alloc_energy(msd_system* s) {
   s->ex0 = E.get<cd>((size_t)2 * NW * NG);
   s->coefAB = E.get<cd>((size_t)NW * s->dp.n_pair);
   s->epart = E.get<cd>((size_t)NW * std::max(s->n_slots, 1));
+  s->plan = E.upload(s->plan_host, s->st);
 }
 
 void need_ready(msd_system* s) {
@@ -347,8 +387,46 @@ void need_ready(msd_system* s) {
   build_derived(s);
 }
 
-void clear_flags(msd_system* s) {
-  hip_check(hipMemsetAsync(s->flag, 0, sizeof(int) * s->NW, s->st), "memset");
+void clear_flags(msd_system* s) { msd::launch_fill_i32(s->flag, s->NW, 0, s->st); }
+
+// Runs `body` once on the handle's stream, or, with graphs on, replays the
+// graph of `slot` (capturing it first, on the private stream, if it is missing
+// or was made for other dt / e_shift).  Everything `body` allocates must be
+// allocated before (the caller prepares lazily-sized buffers).
+template <class F>
+void run_or_replay(msd_system* s, msd_system::GraphSlot& slot, double dt, double e_shift,
+                   F&& body) {
+  if (!s->graphs_on()) {
+    body();
+    return;
+  }
+  if (slot.exec && (slot.dt != dt || slot.e_shift != e_shift)) {
+    hip_check(hipGraphExecDestroy(slot.exec), "hipGraphExecDestroy");
+    slot.exec = nullptr;
+  }
+  if (!slot.exec) {
+    if (!s->cap_st) hip_check(hipStreamCreateWithFlags(&s->cap_st, hipStreamNonBlocking), "stream");
+    hipStream_t user = s->st;
+    s->st = s->cap_st;
+    hipGraph_t g = nullptr;
+    hip_check(hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal), "begin capture");
+    try {
+      body();
+    } catch (...) {
+      (void)hipStreamEndCapture(s->st, &g);
+      if (g) (void)hipGraphDestroy(g);
+      s->st = user;
+      throw;
+    }
+    s->st = user;
+    hip_check(hipStreamEndCapture(s->cap_st, &g), "end capture");
+    hipError_t e = hipGraphInstantiate(&slot.exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    hip_check(e, "hipGraphInstantiate");
+    slot.dt = dt;
+    slot.e_shift = e_shift;
+  }
+  hip_check(hipGraphLaunch(slot.exec, s->st), "hipGraphLaunch");
 }
 
 void check_flags(msd_system* s, const char* what) {
@@ -433,48 +511,58 @@ void run_energy(msd_system* s) {
         msd::launch_minor_coef(s->ds[sp], s->NW, s->sw[sp].B, s->ds[sp].U, s->sw[sp].m2,
                                s->coef2[sp], s->st);
   });
+  int wb = 0;
+  const bool fused = s->o.energy_algo == 3 && msd::chol_contract_fits(A, B, &wb);
   for (int w0 = 0; w0 < s->NW; w0 += s->WT) {
     const int wt = std::min(s->WT, s->NW - w0);
-    for (int sp = 0; sp < 2; ++sp) {
-      const msd::DevSpin& D = s->ds[sp];
-      if (D.N == 0) continue;
-      s->timed(ST_LT_GEMM, [&] {
-        msd::GemmArgs g;
-        g.M = s->NG * D.P;
-        g.N = 2 * wt * D.N;
-        g.K = s->M;
-        g.A = s->L_lt[sp];
-        g.lda = s->M;
-        g.a_kmaj = true;
-        g.B = reinterpret_cast<const double*>(s->sw[sp].T + (size_t)w0 * D.N);
-        g.ldb = 2 * (int64_t)s->NW * D.N;
-        g.b_kmaj = false;
-        g.C = reinterpret_cast<double*>(s->LT[sp]);
-        g.ldc = 2 * (int64_t)wt * D.N;
-        msd::launch_gemm(g, s->st);
+    if (fused) {
+      s->timed(ST_LAMBDA, [&] {
+        msd::launch_chol_contract(A, B, s->L_lt[0], s->L_lt[1], s->sw[0].T, s->sw[1].T, s->Lam[0],
+                                  s->Lam[1], s->ZWp[0], s->ZWp[1], s->M, s->NW, w0, wt, s->NG,
+                                  s->gl_chunk, wb, s->v0, s->ex0, s->st);
       });
-    }
-    s->timed(ST_LAMBDA, [&] {
-      msd::launch_lambda(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, s->sw[0].T, s->sw[1].T,
-                         s->LT[0], s->LT[1], s->Lam[0], s->Lam[1], s->v0, s->ex0, s->ZWp[0],
-                         s->ZWp[1], s->st);
-    });
-    s->timed(ST_EGAMMA, [&] {
-      const int Xa = A.nv * A.no, Xb = B.nv * B.no;
-      msd::launch_energy_pairs(s->dp, Xa, Xb, s->NW, w0, wt, s->NG, s->gsplit, s->Lam[0],
-                               s->Lam[1], s->coefAB, s->epart, s->n_slots, s->slot_pairs, s->st);
+    } else {
       for (int sp = 0; sp < 2; ++sp) {
         const msd::DevSpin& D = s->ds[sp];
-        if (D.nv * D.no == 0) continue;
-        if (s->use_strings[sp]) {
-          for (int k = 2; k <= 4; ++k)
-            msd::launch_energy_strings(D, k, s->NW, w0, wt, s->NG, s->gsplit, s->Lam[sp],
-                                       s->sw[sp].m2, s->sw[sp].B, s->epart, s->n_slots,
-                                       s->slot_str[sp][k], s->st);
-        } else {
-          msd::launch_energy_minors(D, s->NW, w0, wt, s->NG, s->gsplit, s->Lam[sp], s->coef2[sp],
-                                    s->epart, s->n_slots, s->slot_min[sp], s->st);
-        }
+        if (D.N == 0) continue;
+        s->timed(ST_LT_GEMM, [&] {
+          msd::GemmArgs g;
+          g.M = s->NG * D.P;
+          g.N = 2 * wt * D.N;
+          g.K = s->M;
+          g.A = s->L_lt[sp];
+          g.lda = s->M;
+          g.a_kmaj = true;
+          g.B = reinterpret_cast<const double*>(s->sw[sp].T + (size_t)w0 * D.N);
+          g.ldb = 2 * (int64_t)s->NW * D.N;
+          g.b_kmaj = false;
+          g.C = reinterpret_cast<double*>(s->LT[sp]);
+          g.ldc = 2 * (int64_t)wt * D.N;
+          msd::launch_gemm(g, s->st);
+        });
+      }
+      int nmax = 0;
+      s->timed(ST_LAMBDA, [&] {
+        if (msd::lambda_rows_fits(A, B, &nmax))
+          msd::launch_lambda_rows(A, B, nmax, s->NW, w0, wt, s->NG, s->gl_chunk, s->sw[0].T,
+                                  s->sw[1].T, s->LT[0], s->LT[1], s->Lam[0], s->Lam[1], s->v0,
+                                  s->ex0, s->ZWp[0], s->ZWp[1], s->st);
+        else
+          msd::launch_lambda(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, s->sw[0].T, s->sw[1].T,
+                             s->LT[0], s->LT[1], s->Lam[0], s->Lam[1], s->v0, s->ex0, s->ZWp[0],
+                             s->ZWp[1], s->st);
+      });
+    }
+    s->timed(ST_EGAMMA, [&] {
+      msd::launch_energy_second(A, B, s->dp, s->plan, s->n_itemblocks, msd::ER_WAVES, s->NW, w0,
+                                wt, s->NG, s->gsplit, s->second_G, s->Lam[0], s->Lam[1],
+                                s->coefAB, s->sw[0].m2, s->sw[1].m2, s->sw[0].B, s->sw[1].B,
+                                s->epart, s->n_slots, s->slot_second, s->st);
+      for (int sp = 0; sp < 2; ++sp) {
+        const msd::DevSpin& D = s->ds[sp];
+        if (D.nv * D.no == 0 || s->use_strings[sp]) continue;
+        msd::launch_energy_minors(D, s->NW, w0, wt, s->NG, s->gsplit, s->Lam[sp], s->coef2[sp],
+                                  s->epart, s->n_slots, s->slot_min[sp], s->st);
       }
     });
     s->timed(ST_EFINAL, [&] {
@@ -492,10 +580,13 @@ void measure_impl(msd_system* s, double dt, bool want_e) {
   if (!s->have_walkers) fail(MSD_ERR_STATE, "walkers have not been set");
   if (!(dt >= 0.0) || !std::isfinite(dt)) fail(MSD_ERR_ARG, "dt must be finite and >= 0");
   if (want_e && s->tt.max_k() > msd::KMAX) fail(MSD_ERR_UNSUPPORTED, "excitation order too high");
-  clear_flags(s);
-  run_overlap(s, want_e, s->logo_tmp);
-  run_green_fb(s, dt);
-  if (want_e) run_energy(s);
+  if (want_e) alloc_energy(s);
+  run_or_replay(s, s->g_measure[want_e ? 1 : 0], dt, 0.0, [&] {
+    clear_flags(s);
+    run_overlap(s, want_e, s->logo_tmp);
+    run_green_fb(s, dt);
+    if (want_e) run_energy(s);
+  });
 }
 
 void ensure_b1(msd_system* s, double dt) {
@@ -532,6 +623,74 @@ void one_body_gemm(msd_system* s, const cd* in, cd* out, const int* mask) {
   msd::launch_gemm(g, s->st);
 }
 
+// One propagation step (force bias, VHS, B1 exp_T(VHS) B1, new overlap,
+// phaseless weights, QR if `qr`).
+void propagate_step(msd_system* s, const double* x, double dt, double e_shift, bool qr) {
+  const int NW = s->NW, NG = s->NG, M = s->M, Ntot = s->Ntot;
+  const size_t mm = (size_t)M * M;
+  clear_flags(s);
+  msd::launch_frozen_mask(NW, s->weights, s->mask, s->st);
+  run_overlap(s, false, s->logo_tmp);
+  run_green_fb(s, dt);
+  s->timed(ST_VHS_GEMM, [&] {
+    msd::launch_vhs_prep(NW, NG, x, s->xbar, std::sqrt(dt), s->weights, s->Y, s->st);
+    msd::GemmArgs g;
+    g.M = 2 * NW;
+    g.N = (int)mm;
+    g.K = NG;
+    g.A = s->Y;
+    g.lda = NG;
+    g.a_kmaj = true;
+    g.B = s->L;
+    g.ldb = (int64_t)mm;
+    g.b_kmaj = false;
+    g.C = s->VHS;
+    g.ldc = (int64_t)mm;
+    msd::launch_gemm(g, s->st);
+  });
+  s->timed(ST_B1, [&] { one_body_gemm(s, s->phi, s->term[0], s->mask); });
+  s->timed(ST_TAYLOR, [&] {
+    hip_check(hipMemcpyAsync(s->acc, s->term[0], sizeof(cd) * NW * M * Ntot,
+                             hipMemcpyDeviceToDevice, s->st),
+              "copy");
+    for (int n = 1; n <= s->o.n_taylor; ++n) {
+      msd::GemmArgs g;
+      g.M = M;
+      g.N = 2 * Ntot;
+      g.K = M;
+      g.batch = NW;
+      g.A = s->VHS;
+      g.lda = M;
+      g.strideA = 2 * (int64_t)mm;
+      g.a_imag_off = (int64_t)mm;
+      g.a_kmaj = true;
+      g.B = reinterpret_cast<const double*>(s->term[(n - 1) & 1]);
+      g.ldb = 2 * Ntot;
+      g.strideB = 2 * (int64_t)M * Ntot;
+      g.b_kmaj = false;
+      g.C = reinterpret_cast<double*>(s->term[n & 1]);
+      g.ldc = 2 * Ntot;
+      g.strideC = 2 * (int64_t)M * Ntot;
+      g.Acc = reinterpret_cast<double*>(s->acc);
+      g.alpha = 1.0 / n;
+      g.cplx = true;
+      g.mask = s->mask;
+      msd::launch_gemm(g, s->st);
+    }
+  });
+  s->timed(ST_B1, [&] { one_body_gemm(s, s->acc, s->phi, s->mask); });
+  run_overlap(s, false, s->logo_tmp);
+  s->timed(ST_WEIGHTS, [&] {
+    msd::launch_weights(NW, NG, x, s->xbar, s->logo_tmp, s->logo, s->weights, dt, e_shift,
+                        s->st);
+  });
+  if (qr) {
+    s->timed(ST_QR, [&] {
+      msd::launch_qr(s->phi, M, Ntot, NW, s->na, s->nb, s->mask, s->qr_ldet, s->logo, s->st);
+    });
+  }
+}
+
 void propagate_impl(msd_system* s, const double* fields_dev, double dt, double e_shift,
                     int n_steps) {
   need_ready(s);
@@ -540,72 +699,21 @@ void propagate_impl(msd_system* s, const double* fields_dev, double dt, double e
   if (!std::isfinite(e_shift)) fail(MSD_ERR_ARG, "e_shift must be finite");
   if (n_steps < 0) fail(MSD_ERR_ARG, "n_steps must be >= 0");
   ensure_b1(s, dt);
-  const int NW = s->NW, NG = s->NG, M = s->M, Ntot = s->Ntot;
-  const size_t mm = (size_t)M * M;
+  const int NW = s->NW, NG = s->NG;
   for (int step = 0; step < n_steps; ++step) {
     const double* x = fields_dev + (size_t)step * NW * NG;
-    clear_flags(s);
-    msd::launch_frozen_mask(NW, s->weights, s->mask, s->st);
-    run_overlap(s, false, s->logo_tmp);
-    run_green_fb(s, dt);
-    s->timed(ST_VHS_GEMM, [&] {
-      msd::launch_vhs_prep(NW, NG, x, s->xbar, std::sqrt(dt), s->weights, s->Y, s->st);
-      msd::GemmArgs g;
-      g.M = 2 * NW;
-      g.N = (int)mm;
-      g.K = NG;
-      g.A = s->Y;
-      g.lda = NG;
-      g.a_kmaj = true;
-      g.B = s->L;
-      g.ldb = (int64_t)mm;
-      g.b_kmaj = false;
-      g.C = s->VHS;
-      g.ldc = (int64_t)mm;
-      msd::launch_gemm(g, s->st);
-    });
-    s->timed(ST_B1, [&] { one_body_gemm(s, s->phi, s->term[0], s->mask); });
-    s->timed(ST_TAYLOR, [&] {
-      hip_check(hipMemcpyAsync(s->acc, s->term[0], sizeof(cd) * NW * M * Ntot,
-                               hipMemcpyDeviceToDevice, s->st),
-                "copy");
-      for (int n = 1; n <= s->o.n_taylor; ++n) {
-        msd::GemmArgs g;
-        g.M = M;
-        g.N = 2 * Ntot;
-        g.K = M;
-        g.batch = NW;
-        g.A = s->VHS;
-        g.lda = M;
-        g.strideA = 2 * (int64_t)mm;
-        g.a_imag_off = (int64_t)mm;
-        g.a_kmaj = true;
-        g.B = reinterpret_cast<const double*>(s->term[(n - 1) & 1]);
-        g.ldb = 2 * Ntot;
-        g.strideB = 2 * (int64_t)M * Ntot;
-        g.b_kmaj = false;
-        g.C = reinterpret_cast<double*>(s->term[n & 1]);
-        g.ldc = 2 * Ntot;
-        g.strideC = 2 * (int64_t)M * Ntot;
-        g.Acc = reinterpret_cast<double*>(s->acc);
-        g.alpha = 1.0 / n;
-        g.cplx = true;
-        g.mask = s->mask;
-        msd::launch_gemm(g, s->st);
-      }
-    });
-    s->timed(ST_B1, [&] { one_body_gemm(s, s->acc, s->phi, s->mask); });
-    run_overlap(s, false, s->logo_tmp);
-    s->timed(ST_WEIGHTS, [&] {
-      msd::launch_weights(NW, NG, x, s->xbar, s->logo_tmp, s->logo, s->weights, dt, e_shift,
-                          s->st);
-    });
     s->steps_done++;
-    if (s->o.stabilize_freq > 0 && s->steps_done % s->o.stabilize_freq == 0) {
-      s->timed(ST_QR, [&] {
-        msd::launch_qr(s->phi, M, Ntot, NW, s->na, s->nb, s->mask, s->qr_ldet, s->logo, s->st);
-      });
+    const bool qr = s->o.stabilize_freq > 0 && s->steps_done % s->o.stabilize_freq == 0;
+    if (s->graphs_on() && x != s->fields) {
+      // the graph reads its fields from the staging buffer
+      hip_check(hipMemcpyAsync(s->fields, x, sizeof(double) * NW * NG, hipMemcpyDeviceToDevice,
+                               s->st),
+                "fields");
+      x = s->fields;
     }
+    run_or_replay(s, s->g_step[qr ? 1 : 0], dt, e_shift, [&] {
+      propagate_step(s, x, dt, e_shift, qr);
+    });
     s->check_launch("propagate");
   }
 }
@@ -686,7 +794,7 @@ msd_status msd_create(const msd_dims* d, const msd_options* o, int32_t device, v
   msd_default_options(&opt);
   if (o) opt = *o;
   if (opt.n_taylor < 0 || opt.n_taylor > 32 || opt.stabilize_freq < 0 || opt.energy_algo < 0 ||
-      opt.energy_algo > 2)
+      opt.energy_algo > 3 || opt.graphs < 0 || opt.graphs > 1)
     fail(MSD_ERR_ARG, "invalid options");
   sys = new msd_system();
   sys->dev = device;
@@ -704,6 +812,7 @@ msd_status msd_create(const msd_dims* d, const msd_options* o, int32_t device, v
     set_device(sys);
     msd::init_wick_attributes();
     msd::init_prop_attributes();
+    msd::init_gemm_attributes();
     Arena& A = sys->base;
     const int M = sys->M, NW = sys->NW, NG = sys->NG, Ntot = sys->Ntot;
     sys->phi = A.get<cd>((size_t)NW * M * Ntot);
@@ -750,6 +859,8 @@ void msd_destroy(msd_system* sys) {
   if (!sys) return;
   (void)hipSetDevice(sys->dev);
   (void)hipStreamSynchronize(sys->st);
+  sys->drop_graphs();
+  if (sys->cap_st) (void)hipStreamDestroy(sys->cap_st);
   for (auto& p : sys->pending) {
     (void)hipEventDestroy(p.second.first);
     (void)hipEventDestroy(p.second.second);
@@ -806,15 +917,16 @@ msd_status msd_set_hamiltonian(msd_system* sys, const double* h1, const double* 
   sys->B1_dt = NAN;
   sys->have_ham = true;
   sys->derived_ok = false;
+  sys->drop_graphs();
   if (sys->have_trial) build_derived(sys);
   API_END(sys)
 }
 
-msd_status msd_set_trial_occ(msd_system* sys, const double* ci, const int32_t* occ_a,
-                             const int32_t* occ_b) {
-  API_BEGIN
-  if (!sys || !ci || (!occ_a && sys->na) || (!occ_b && sys->nb)) fail(MSD_ERR_ARG, "null argument");
-  set_device(sys);
+namespace {
+
+// Shared by both trial entry points: occupation rows -> device tables.
+void set_trial_rows(msd_system* sys, const double* ci, const int32_t* occ_a,
+                    const int32_t* occ_b) {
   for (int64_t i = 0; i < 2 * sys->ND; ++i)
     if (!std::isfinite(ci[i])) fail(MSD_ERR_ARG, "CI coefficient " + std::to_string(i / 2) + " not finite");
   msd::TrialTables tt;
@@ -937,12 +1049,86 @@ msd_status msd_set_trial_occ(msd_system* sys, const double* ci, const int32_t* o
   sys->n_ochunks = (int)((sys->ND + sys->ochunk - 1) / sys->ochunk);
   sys->opart = T.get<cd>((size_t)NW * sys->n_ochunks);
   sys->derived_ok = false;
+  sys->drop_graphs();
   sys->sync();
   sys->have_trial = true;
   sys->have_walkers = false;
   if (sys->have_ham) build_derived(sys);
+}
+
+// Occupation rows of an excitation list: the reference with the holes removed
+// and the particles added, sorted ascending.  Validates that every hole is in
+// the reference and every particle outside it, without repeats.
+void rows_from_excitations(const int32_t* ref, int N, int M, int64_t n_det, const int32_t* k,
+                           const int64_t* offsets, const int32_t* holes, const int32_t* parts,
+                           const int32_t* k_other, bool beta,
+                           std::vector<int32_t>& rows) {
+  const char* nm = beta ? "beta" : "alpha";
+  std::vector<char> in_ref(M, 0);
+  for (int j = 0; j < N; ++j) {
+    if (ref[j] < 0 || ref[j] >= M) fail(MSD_ERR_TRIAL, std::string(nm) + " reference orbital out of range");
+    if (in_ref[ref[j]]) fail(MSD_ERR_TRIAL, std::string(nm) + " reference orbital repeated");
+    in_ref[ref[j]] = 1;
+  }
+  rows.assign((size_t)n_det * N, 0);
+  std::vector<char> occ(M);
+  for (int64_t I = 0; I < n_det; ++I) {
+    const std::string who = "determinant " + std::to_string(I) + " (" + nm + "): ";
+    const int kk = k[I];
+    if (kk < 0 || kk > std::min(N, msd::KMAX) || kk > M - N)
+      fail(MSD_ERR_TRIAL, who + "excitation order out of range");
+    if (offsets[I] < 0 || offsets[I + 1] < offsets[I] ||
+        offsets[I + 1] - offsets[I] != (int64_t)k[I] + k_other[I])
+      fail(MSD_ERR_TRIAL, who + "offsets do not match k_a + k_b");
+    const int64_t o = offsets[I] + (beta ? k_other[I] : 0);
+    std::copy(in_ref.begin(), in_ref.end(), occ.begin());
+    for (int m = 0; m < kk; ++m) {
+      const int h = holes[o + m], p = parts[o + m];
+      if (h < 0 || h >= M || !in_ref[h] || !occ[h]) fail(MSD_ERR_TRIAL, who + "bad hole " + std::to_string(h));
+      occ[h] = 0;
+      if (p < 0 || p >= M || in_ref[p] || occ[p] == 2) fail(MSD_ERR_TRIAL, who + "bad particle " + std::to_string(p));
+      occ[p] = 2;
+    }
+    int32_t* r = rows.data() + (size_t)I * N;
+    int c = 0;
+    for (int q = 0; q < M; ++q)
+      if (occ[q]) r[c++] = q;
+  }
+}
+
+}  // namespace
+
+msd_status msd_set_trial_occ(msd_system* sys, const double* ci, const int32_t* occ_a,
+                             const int32_t* occ_b) {
+  API_BEGIN
+  if (!sys || !ci || (!occ_a && sys->na) || (!occ_b && sys->nb)) fail(MSD_ERR_ARG, "null argument");
+  set_device(sys);
+  set_trial_rows(sys, ci, occ_a, occ_b);
   API_END(sys)
 }
+
+msd_status msd_set_trial_exc(msd_system* sys, const int32_t* ref_a, const int32_t* ref_b,
+                             int64_t n_det, const double* ci, const int32_t* k_a,
+                             const int32_t* k_b, const int64_t* offsets, const int32_t* holes,
+                             const int32_t* parts) {
+  API_BEGIN
+  if (!sys || !ci || !k_a || !k_b || !offsets || (!ref_a && sys->na) || (!ref_b && sys->nb))
+    fail(MSD_ERR_ARG, "null argument");
+  if (n_det != sys->ND) fail(MSD_ERR_SHAPE, "n_det differs from the handle's n_det");
+  if (offsets[0] != 0) fail(MSD_ERR_TRIAL, "offsets[0] must be 0");
+  if (offsets[n_det] > 0 && (!holes || !parts)) fail(MSD_ERR_ARG, "null argument");
+  set_device(sys);
+  std::vector<int32_t> ra, rb;
+  rows_from_excitations(ref_a, sys->na, sys->M, n_det, k_a, offsets, holes, parts, k_b, false, ra);
+  rows_from_excitations(ref_b, sys->nb, sys->M, n_det, k_b, offsets, holes, parts, k_a, true, rb);
+  set_trial_rows(sys, ci, ra.data(), rb.data());
+  API_END(sys)
+}
+
+msd_status msd_get_weights(msd_system* sys, double* weights, double* log_ovlp) {
+  return msd_get_walkers(sys, nullptr, nullptr, weights, log_ovlp);
+}
+
 
 
 static void copy_out(msd_system* s, void* host, const void* dev, size_t bytes) {

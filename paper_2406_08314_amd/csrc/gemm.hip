@@ -280,3 +280,254 @@ void launch_gemm(const GemmArgs& g, hipStream_t st) {
 }
 
 }  // namespace msd
+
+namespace msd {
+
+// ============================================================================
+// A2 + A6 fused: Cholesky contraction and energy intermediates.
+// Workgroup = (group of WB walkers, chunk of Cholesky vectors).  For every g
+// in the chunk and each spin the tile LT^g = L^g[R u V, :] T (P x 2N*WB real,
+// P <= 64, 2N*WB <= 64) is formed with v_mfma_f64_16x16x4 into LDS and
+// consumed there: v0 = tr Q, ex0 = tr QQ (Q = LT^g[R, :]),
+// Lam = T[V,:] Q - LT^g[V,:], Xi = Lam Q[:, O], Lam window -> HBM, and
+// ZW += Xi - (v0a + v0b) Lam accumulated in registers.
+// ============================================================================
+
+constexpr int CC_THREADS = 512;
+constexpr int CC_ZPT = 4;  // window entries per thread and spin: WB*nv*no <= 2048
+
+struct CCSpin {
+  const double* Llt;  // [NG][P][M]
+  const cd* T;        // [M][NW][N]
+  cd* Lam;            // [WT][NG][X]   (walker-tile local)
+  cd* ZW;             // [WT][n_chunks][X]
+};
+
+__device__ __forceinline__ cd wave_sum_cc(cd v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    v.re += __shfl_xor(v.re, off, 64);
+    v.im += __shfl_xor(v.im, off, 64);
+  }
+  return v;
+}
+
+__global__ __launch_bounds__(CC_THREADS) void k_chol_contract(DevSpin sa, DevSpin sb, CCSpin ca,
+                                                              CCSpin cb, int M, int NW, int w0,
+                                                              int WT, int NG, int g_chunk, int WB,
+                                                              cd* __restrict__ v0,
+                                                              cd* __restrict__ ex0) {
+  // LDS: region0 holds the GEMM staging slabs, then T[V,:] of the walker
+  // group and the full Lam rows; Ct holds the LT^g tile.
+  extern __shared__ double smem[];
+  typedef double Slab[GB_K][GB_M + GPAD];
+  Slab* As = reinterpret_cast<Slab*>(smem);                              // [2]
+  Slab* Bs = reinterpret_cast<Slab*>(smem + 2 * GB_K * (GB_M + GPAD));  // [2]
+  __shared__ double Ct[64][64 + 1];
+  __shared__ cd v0s[2][16];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wg = blockIdx.x, chunk = blockIdx.y, n_chunks = gridDim.y;
+  const int wl0 = wg * WB;                   // first tile-local walker of the group
+  const int WBv = min(WB, WT - wl0);         // walkers present
+  const int g0 = chunk * g_chunk, g1 = min(NG, g0 + g_chunk);
+  const int wm = ((wave & 3) >> 1) * 32, wn = (wave & 1) * 32;
+  const int Xa = sa.nv * sa.no, Xb = sb.nv * sb.no;
+
+  cd za[CC_ZPT], zb[CC_ZPT];
+#pragma unroll
+  for (int q = 0; q < CC_ZPT; ++q) za[q] = zb[q] = cd{0.0, 0.0};
+
+  for (int g = g0; g < g1; ++g) {
+#pragma unroll 1
+    for (int s2 = 0; s2 < 2; ++s2) {
+      const DevSpin& S = s2 ? sb : sa;
+      const CCSpin& C = s2 ? cb : ca;
+      const int N = S.N, P = S.P, nv = S.nv, no = S.no, X = nv * no;
+      if (N == 0) {
+        if (tid < WBv) {
+          const int w = w0 + wl0 + tid;
+          v0[((size_t)s2 * NW + w) * NG + g] = cd{0.0, 0.0};
+          ex0[((size_t)s2 * NW + w) * NG + g] = cd{0.0, 0.0};
+          v0s[s2][tid] = cd{0.0, 0.0};
+        }
+        __syncthreads();
+        continue;
+      }
+      // ---------------- tile GEMM: Ct[r][c] = sum_k L^g[r][k] Tcols[k][c]
+      const int ncol = 2 * N * WBv;
+      const double* Ab = C.Llt + (size_t)g * P * M;
+      const double* Bb = reinterpret_cast<const double*>(C.T) + 2 * (size_t)(w0 + wl0) * N;
+      const int64_t ldb = 2 * (int64_t)NW * N;
+      double4_t acc[2][2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = double4_t{0.0, 0.0, 0.0, 0.0};
+      // 512 threads stage 64x16 of A and 16x64 of B: 2 + 2 elements each
+      const int a_mm = tid >> 3, a_kk = (tid & 7) * 2;
+      const int b_kk = tid >> 5, b_nn = (tid & 31) * 2;
+      double ra[2], rb[2];
+      auto load = [&](int k0) {
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+          const int gk = k0 + a_kk + r;
+          ra[r] = (a_mm < P && gk < M) ? Ab[(size_t)a_mm * M + gk] : 0.0;
+          const int bk = k0 + b_kk, bn = b_nn + r;
+          rb[r] = (bk < M && bn < ncol) ? Bb[(size_t)bk * ldb + bn] : 0.0;
+        }
+      };
+      int buf = 0;
+      load(0);
+      for (int k0 = 0; k0 < M; k0 += GB_K) {
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+          As[buf][a_kk + r][a_mm] = ra[r];
+          Bs[buf][b_kk][b_nn + r] = rb[r];
+        }
+        __syncthreads();
+        if (k0 + GB_K < M) load(k0 + GB_K);
+        if (wave < 4) {
+#pragma unroll
+          for (int kk = 0; kk < GB_K; kk += 4) {
+            const int kr = kk + (lane >> 4);
+            const double a0 = As[buf][kr][wm + (lane & 15)];
+            const double a1 = As[buf][kr][wm + 16 + (lane & 15)];
+            const double b0 = Bs[buf][kr][wn + (lane & 15)];
+            const double b1 = Bs[buf][kr][wn + 16 + (lane & 15)];
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+          }
+        }
+        buf ^= 1;
+      }
+      if (wave < 4) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              Ct[wm + i * 16 + (lane >> 4) + 4 * r][wn + j * 16 + (lane & 15)] = acc[i][j][r];
+      }
+      __syncthreads();  // Ct complete; staging slabs free
+      // complex view: Q_j(r, c) = Ct[r][j*2N + 2c] + i Ct[r][j*2N + 2c + 1]
+      auto ct = [&](int r, int jw, int c) {
+        return cd{Ct[r][jw * 2 * N + 2 * c], Ct[r][jw * 2 * N + 2 * c + 1]};
+      };
+      const int LW = nv * N;
+      cd* TVs = reinterpret_cast<cd*>(smem);  // [WBv][nv][N]
+      cd* Lf = TVs + (size_t)WB * LW;         // [WBv][nv][N]
+      for (int e = tid; e < WBv * LW; e += CC_THREADS) {
+        const int jw = e / LW, rem = e % LW, a = rem / N, jj = rem % N;
+        TVs[e] = C.T[((size_t)S.vir[a] * NW + w0 + wl0 + jw) * N + jj];
+      }
+      // ---------------- v0, ex0 per walker (one wave per walker)
+      for (int jw = wave; jw < WBv; jw += CC_THREADS / 64) {
+        cd v{0.0, 0.0}, x{0.0, 0.0};
+        for (int e = lane; e < N * N; e += 64) {
+          const int r = e / N, c = e % N;
+          cfma(x, ct(r, jw, c), ct(c, jw, r));
+          if (r == c) v += ct(r, jw, c);
+        }
+        v = wave_sum_cc(v);
+        x = wave_sum_cc(x);
+        if (lane == 0) {
+          const int w = w0 + wl0 + jw;
+          v0s[s2][jw] = v;
+          v0[((size_t)s2 * NW + w) * NG + g] = v;
+          ex0[((size_t)s2 * NW + w) * NG + g] = x;
+        }
+      }
+      __syncthreads();
+      // ---------------- Lam full rows: Lam = T[V,:] Q - LT[V,:]
+      for (int e = tid; e < WBv * LW; e += CC_THREADS) {
+        const int jw = e / LW, rem = e % LW, a = rem / N, c = rem % N;
+        const cd* tv = TVs + (size_t)jw * LW + a * N;
+        cd accl = -ct(N + a, jw, c);
+        for (int jj = 0; jj < N; ++jj) cfma(accl, tv[jj], ct(jj, jw, c));
+        Lf[e] = accl;
+      }
+      __syncthreads();
+      // ---------------- Xi, Lam window, ZW
+#pragma unroll
+      for (int q = 0; q < CC_ZPT; ++q) {
+        const int e = tid + CC_THREADS * q;
+        if (e < WBv * X) {
+          const int jw = e / X, rem = e % X, a = rem / no, i = rem % no;
+          const int oc = S.oslot[i];
+          const cd* Lrow = Lf + (size_t)jw * LW + a * N;
+          cd xi{0.0, 0.0};
+          for (int c = 0; c < N; ++c) cfma(xi, Lrow[c], ct(c, jw, oc));
+          const cd lam = Lrow[oc];
+          C.Lam[((size_t)(wl0 + jw) * NG + g) * X + rem] = lam;
+          if (s2 == 0) {
+            za[q] += xi - v0s[0][jw] * lam;
+          } else {
+            zb[q] += xi - (v0s[0][jw] + v0s[1][jw]) * lam;
+          }
+        }
+      }
+      if (s2 == 1) {
+        // the alpha accumulators still miss -v0b * Lam^a of this g; the alpha
+        // window values were written by this same thread in the alpha pass
+#pragma unroll
+        for (int q = 0; q < CC_ZPT; ++q) {
+          const int e = tid + CC_THREADS * q;
+          if (e < WBv * Xa) {
+            const int jw = e / Xa;
+            za[q] -= v0s[1][jw] * ca.Lam[((size_t)(wl0 + jw) * NG + g) * Xa + e % Xa];
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < CC_ZPT; ++q) {
+    int e = tid + CC_THREADS * q;
+    if (e < WBv * Xa) {
+      const int jw = e / Xa;
+      ca.ZW[((size_t)(wl0 + jw) * n_chunks + chunk) * Xa + e % Xa] = za[q];
+    }
+    if (e < WBv * Xb) {
+      const int jw = e / Xb;
+      cb.ZW[((size_t)(wl0 + jw) * n_chunks + chunk) * Xb + e % Xb] = zb[q];
+    }
+  }
+}
+
+static size_t chol_contract_lds(const DevSpin& sa, const DevSpin& sb, int WB) {
+  const size_t tv_lf = 2 * (size_t)WB * max(sa.nv * sa.N, sb.nv * sb.N) * sizeof(cd);
+  return max(tv_lf, 4 * (size_t)GB_K * (GB_M + GPAD) * sizeof(double));
+}
+
+bool chol_contract_fits(const DevSpin& sa, const DevSpin& sb, int* WB) {
+  int nmax = max(sa.N, sb.N);
+  if (nmax == 0 || nmax > 32 || sa.P > 64 || sb.P > 64) return false;
+  int wb = min(64 / (2 * nmax), 16);
+  if (wb * sa.nv * sa.no > CC_THREADS * CC_ZPT || wb * sb.nv * sb.no > CC_THREADS * CC_ZPT)
+    return false;
+  if (chol_contract_lds(sa, sb, wb) > 110 * 1024) return false;
+  *WB = wb;
+  return true;
+}
+
+void launch_chol_contract(const DevSpin& sa, const DevSpin& sb, const double* Llt_a,
+                          const double* Llt_b, const cd* Ta, const cd* Tb, cd* Lam_a, cd* Lam_b,
+                          cd* ZW_a, cd* ZW_b, int M, int NW, int w0, int WT, int NG, int g_chunk,
+                          int WB, cd* v0, cd* ex0, hipStream_t st) {
+  const int n_chunks = (NG + g_chunk - 1) / g_chunk;
+  const CCSpin ca{Llt_a, Ta, Lam_a, ZW_a}, cb{Llt_b, Tb, Lam_b, ZW_b};
+  dim3 grid((WT + WB - 1) / WB, n_chunks);
+  hipLaunchKernelGGL(k_chol_contract, grid, dim3(CC_THREADS), chol_contract_lds(sa, sb, WB), st, sa,
+                     sb, ca, cb, M, NW, w0, WT, NG, g_chunk, WB, v0, ex0);
+}
+
+void init_gemm_attributes() {
+  hipFuncSetAttribute((const void*)k_chol_contract, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      112 * 1024);
+}
+
+}  // namespace msd

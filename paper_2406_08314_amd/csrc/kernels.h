@@ -110,11 +110,25 @@ void launch_lambda(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT,
                    int g_chunk, const cd* Ta, const cd* Tb, const cd* LTa, const cd* LTb,
                    cd* Lam_a, cd* Lam_b, cd* v0, cd* ex0, cd* ZWpart_a, cd* ZWpart_b,
                    hipStream_t st);
+bool lambda_rows_fits(const DevSpin& sa, const DevSpin& sb, int* nmax);
+void launch_lambda_rows(const DevSpin& sa, const DevSpin& sb, int nmax, int NW, int w0, int WT,
+                        int NG, int g_chunk, const cd* Ta, const cd* Tb, const cd* LTa,
+                        const cd* LTb, cd* Lam_a, cd* Lam_b, cd* v0, cd* ex0, cd* ZWpart_a,
+                        cd* ZWpart_b, hipStream_t st);
 void launch_pair_coef(const DevPairs& pr, int NW, const cd* det_c, const cd* adj_a, int Aa,
                       const cd* adj_b, int Ab, cd* coef, hipStream_t st);
 void launch_minor_coef(const DevSpin& s, int NW, const cd* B, int U, const cd* m2, cd* coef,
                        hipStream_t st);
 // second-order energy terms; each launch writes blocks into partial[w][slot0 + ...]
+// plan roles: ER_PAIRS, or 2..6 = row-pair items of strings of that order
+enum EnergyRole { ER_NONE = 0, ER_PAIRS = 1 };
+constexpr int ER_MAX_ORDER = 6;
+constexpr int ER_WAVES = 8;  // waves per workgroup of the merged second-order kernel
+void launch_energy_second(const DevSpin& sa, const DevSpin& sb, const DevPairs& pr,
+                          const int4* plan, int n_itemblocks, int waves_per_block, int NW, int w0,
+                          int WT, int NG, int n_gsplit, int G, const cd* Lam_a, const cd* Lam_b,
+                          const cd* coef, const cd* m2a, const cd* m2b, const cd* Ba,
+                          const cd* Bb, cd* partial, int n_slots, int slot0, hipStream_t st);
 int energy_pair_blocks(int n_pair);
 int energy_string_blocks(const DevSpin& s, int k);
 int energy_minor_blocks(const DevSpin& s);
@@ -141,11 +155,20 @@ void launch_weights(int NW, int NG, const double* x, const cd* xbar, const cd* l
 void launch_qr(cd* phi, int M, int Ntot, int NW, int na, int nb, const int* mask, double* ldet,
                cd* logo, hipStream_t st);
 void launch_frozen_mask(int NW, const double* weights, int* mask, hipStream_t st);
+void launch_fill_i32(int* p, int n, int v, hipStream_t st);
 void launch_copy_walkers(int NW, int M, int Ntot, int na, int nb, const cd* pa, const cd* pb,
                          cd* phi, bool to_internal, cd* out_a, cd* out_b, hipStream_t st);
 void launch_sum_ll(const double* chol, int NG, int M, double* out, hipStream_t st);
 void launch_gather_rows(const double* L, int NG, int M, const int* rows, int P, double* out,
                         hipStream_t st);
+
+// A2 + A6 fused (Cholesky contraction + energy intermediates) when the tile fits
+bool chol_contract_fits(const DevSpin& sa, const DevSpin& sb, int* WB);
+void launch_chol_contract(const DevSpin& sa, const DevSpin& sb, const double* Llt_a,
+                          const double* Llt_b, const cd* Ta, const cd* Tb, cd* Lam_a, cd* Lam_b,
+                          cd* ZW_a, cd* ZW_b, int M, int NW, int w0, int WT, int NG, int g_chunk,
+                          int WB, cd* v0, cd* ex0, hipStream_t st);
+void init_gemm_attributes();
 
 // raise the dynamic-LDS limit of the kernels that may need more than 64 KB
 void init_wick_attributes();

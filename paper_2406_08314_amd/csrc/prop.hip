@@ -84,6 +84,18 @@ void launch_frozen_mask(int NW, const double* weights, int* mask, hipStream_t st
   hipLaunchKernelGGL(k_frozen_mask, dim3((NW + 255) / 256), dim3(256), 0, st, NW, weights, mask);
 }
 
+// Plain fill (used instead of a memset node where the work may be captured
+// into a graph).
+__global__ void k_fill_i32(int* __restrict__ p, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+void launch_fill_i32(int* p, int n, int v, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, st, p, n, v);
+}
+
 // Re-orthonormalisation Phi = Q R, diag(R) > 0, by Cholesky QR applied twice
 // (Gram matrix, its Cholesky factor, Phi <- Phi R^{-1}); the log-overlap loses
 // sum_j log R_jj.  One workgroup per walker and spin; walkers with mask 0 are

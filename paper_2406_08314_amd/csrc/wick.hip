@@ -744,6 +744,133 @@ __global__ __launch_bounds__(64) void k_lambda(DevSpin sa, DevSpin sb, int NW, i
   }
 }
 
+// Row-per-lane form of the same computation: one wave per (walker, spin) in a
+// workgroup of two waves, lane = virtual-orbital row a (n_vir_act <= 64).  Each
+// lane keeps T[v_a, :], its Lam row, its Xi row and its ZW row in registers;
+// Q^g is broadcast from LDS.  NMAX bounds N, NOMAX bounds n_occ_act.
+constexpr int NOMAX = 16;
+
+template <int NMAX>
+__global__ __launch_bounds__(128) void k_lambda_rows(DevSpin sa, DevSpin sb, int NW, int w0,
+                                                     int WT, int NG, int g_chunk,
+                                                     const cd* __restrict__ Ta,
+                                                     const cd* __restrict__ Tb,
+                                                     const cd* __restrict__ LTa,
+                                                     const cd* __restrict__ LTb,
+                                                     cd* __restrict__ Lam_a,
+                                                     cd* __restrict__ Lam_b,
+                                                     cd* __restrict__ v0, cd* __restrict__ ex0,
+                                                     cd* __restrict__ ZWa, cd* __restrict__ ZWb) {
+  __shared__ cd Qs[2][NMAX * NMAX];
+  __shared__ cd v0s[2];
+  const int wl = blockIdx.x, chunk = blockIdx.y, n_chunks = gridDim.y;
+  const int w = w0 + wl, lane = threadIdx.x & 63, s2 = threadIdx.x >> 6;
+  const DevSpin& S = s2 ? sb : sa;
+  const int N = S.N, nv = S.nv, no = S.no, P = S.P, X = nv * no;
+  const cd* __restrict__ T = s2 ? Tb : Ta;
+  const cd* __restrict__ LT = s2 ? LTb : LTa;
+  cd* __restrict__ Lam = s2 ? Lam_b : Lam_a;
+  cd* __restrict__ ZW = s2 ? ZWb : ZWa;
+  const bool row = lane < nv;
+  cd tv[NMAX], zw[NOMAX];
+  int osl[NOMAX];
+#pragma unroll
+  for (int j = 0; j < NMAX; ++j)
+    tv[j] = (row && j < N) ? T[((size_t)S.vir[lane] * NW + w) * N + j] : cd{0.0, 0.0};
+#pragma unroll
+  for (int i = 0; i < NOMAX; ++i) {
+    osl[i] = i < no ? S.oslot[i] : 0;
+    zw[i] = cd{0.0, 0.0};
+  }
+  const size_t ld = (size_t)WT * N;
+  const int g0 = chunk * g_chunk, g1 = min(NG, g0 + g_chunk);
+  for (int g = g0; g < g1; ++g) {
+    const cd* base = LT + ((size_t)g * P) * ld + (size_t)wl * N;
+    // Q^g of this spin into LDS; traces
+    cd v{0.0, 0.0}, x{0.0, 0.0};
+    for (int e = lane; e < N * N; e += 64) {
+      const int j = e / N, c = e % N;
+      const cd q = base[(size_t)j * ld + c];
+      Qs[s2][e] = q;
+      if (j == c) v += q;
+    }
+    // this lane's LT^g[V, :] row (independent of the LDS writes above)
+    cd ltv[NMAX];
+#pragma unroll
+    for (int c = 0; c < NMAX; ++c)
+      ltv[c] = (row && c < N) ? base[(size_t)(N + lane) * ld + c] : cd{0.0, 0.0};
+    v = wave_sum(v);
+    if (lane == 0) v0s[s2] = v;
+    __syncthreads();
+    const cd* Q = Qs[s2];
+    for (int e = lane; e < N * N; e += 64) {
+      const int j = e / N, c = e % N;
+      cfma(x, Q[e], Q[c * N + j]);
+    }
+    x = wave_sum(x);
+    if (lane == 0 && N > 0) {
+      v0[((size_t)s2 * NW + w) * NG + g] = v;
+      ex0[((size_t)s2 * NW + w) * NG + g] = x;
+    } else if (lane == 0) {
+      v0[((size_t)s2 * NW + w) * NG + g] = cd{0.0, 0.0};
+      ex0[((size_t)s2 * NW + w) * NG + g] = cd{0.0, 0.0};
+    }
+    const cd vsum = v0s[0] + v0s[1];
+    if (row) {
+      cd lam[NMAX];
+#pragma unroll
+      for (int c = 0; c < NMAX; ++c) {
+        cd a = -ltv[c];
+#pragma unroll
+        for (int j = 0; j < NMAX; ++j)
+          if (j < N && c < N) cfma(a, tv[j], Q[j * N + c]);
+        lam[c] = a;
+      }
+      cd* Lo = Lam + ((size_t)wl * NG + g) * X + (size_t)lane * no;
+#pragma unroll
+      for (int i = 0; i < NOMAX; ++i) {
+        if (i < no) {
+          const int oc = osl[i];
+          cd xi{0.0, 0.0}, lw{0.0, 0.0};
+#pragma unroll
+          for (int c = 0; c < NMAX; ++c) {
+            if (c < N) cfma(xi, lam[c], Q[c * N + oc]);
+            if (c == oc) lw = lam[c];
+          }
+          Lo[i] = lw;
+          zw[i] += xi - vsum * lw;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (row) {
+#pragma unroll
+    for (int i = 0; i < NOMAX; ++i)
+      if (i < no) ZW[((size_t)wl * n_chunks + chunk) * X + (size_t)lane * no + i] = zw[i];
+  }
+}
+
+bool lambda_rows_fits(const DevSpin& sa, const DevSpin& sb, int* nmax) {
+  const int n = max(sa.N, sb.N);
+  if (sa.nv > 64 || sb.nv > 64 || sa.no > NOMAX || sb.no > NOMAX || n > 32) return false;
+  *nmax = n <= 8 ? 8 : (n <= 16 ? 16 : 32);
+  return true;
+}
+
+void launch_lambda_rows(const DevSpin& sa, const DevSpin& sb, int nmax, int NW, int w0, int WT,
+                        int NG, int g_chunk, const cd* Ta, const cd* Tb, const cd* LTa,
+                        const cd* LTb, cd* Lam_a, cd* Lam_b, cd* v0, cd* ex0, cd* ZWpart_a,
+                        cd* ZWpart_b, hipStream_t st) {
+  const int n_chunks = (NG + g_chunk - 1) / g_chunk;
+  dim3 grid(WT, n_chunks);
+  switch (nmax) {
+    case 8: hipLaunchKernelGGL(k_lambda_rows<8>, grid, dim3(128), 0, st, sa, sb, NW, w0, WT, NG, g_chunk, Ta, Tb, LTa, LTb, Lam_a, Lam_b, v0, ex0, ZWpart_a, ZWpart_b); break;
+    case 16: hipLaunchKernelGGL(k_lambda_rows<16>, grid, dim3(128), 0, st, sa, sb, NW, w0, WT, NG, g_chunk, Ta, Tb, LTa, LTb, Lam_a, Lam_b, v0, ex0, ZWpart_a, ZWpart_b); break;
+    default: hipLaunchKernelGGL(k_lambda_rows<32>, grid, dim3(128), 0, st, sa, sb, NW, w0, WT, NG, g_chunk, Ta, Tb, LTa, LTb, Lam_a, Lam_b, v0, ex0, ZWpart_a, ZWpart_b); break;
+  }
+}
+
 void launch_lambda(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
                    int g_chunk, const cd* Ta, const cd* Tb, const cd* LTa, const cd* LTb,
                    cd* Lam_a, cd* Lam_b, cd* v0, cd* ex0, cd* ZWpart_a, cd* ZWpart_b,
@@ -1042,6 +1169,191 @@ __global__ __launch_bounds__(MINOR_THREADS) void k_energy_minors(
     partial[(size_t)w * n_slots + slot0 + (size_t)mb * n_gsplit + gs] = red[0];
 }
 
+// ----------------------------------------------------------------------------
+// All second-order terms of a walker in one workgroup: each wave has one role
+// (ER_PAIRS: 8 opposite-spin pairs per lane; ER_STR2 / ER_STR3: one string of
+// that order per lane; ER_STR4: one order-4 string per lane pair, each lane
+// taking three of its six row pairs).  Lam^a and Lam^b of the workgroup's
+// Cholesky range stream through double-buffered LDS once.
+// ----------------------------------------------------------------------------
+
+// Row-pair items: one (string of order K, row pair m < m') per lane.  It needs
+// rows m and m' of Y_mn = Lam[p_n, h_m] (2K gathers per Cholesky vector) and
+// the K(K-1)/2 signed complementary minors of that row pair:
+//   e2 += sum_{n<n'} (-1)^{m+m'+n+n'} det X[~{m,m'},~{n,n'}] (Y_mn Y_m'n' - Y_mn' Y_m'n).
+template <int K>
+__device__ __forceinline__ void rp_setup(const int* __restrict__ hwin, const int* __restrict__ pwin,
+                                         int no, int str, int rp, int off, const cd* m2s,
+                                         int* idx, cd* mm) {
+  constexpr int P = K * (K - 1) / 2;
+  int m = 0, mp = 1;
+  for (int a = 0, q = 0; a < K; ++a)
+    for (int b = a + 1; b < K; ++b, ++q)
+      if (q == rp) { m = a; mp = b; }
+#pragma unroll
+  for (int n = 0; n < K; ++n) {
+    const int col = pwin[str * KMAX + n] * no;
+    idx[n] = off + col + hwin[str * KMAX + m];
+    idx[K + n] = off + col + hwin[str * KMAX + mp];
+  }
+  const cd* src = m2s + rp * P;
+  int q = 0;
+#pragma unroll
+  for (int n = 0; n < K; ++n)
+#pragma unroll
+    for (int np = n + 1; np < K; ++np, ++q) {
+      cd v = src[q];
+      if ((m + mp + n + np) & 1) v = -v;
+      mm[q] = v;
+    }
+}
+
+template <int K>
+__device__ __forceinline__ void rp_eval(const cd* Lg, const int* idx, const cd* mm, cd& acc) {
+  cd y0[K], y1[K];
+#pragma unroll
+  for (int n = 0; n < K; ++n) {
+    y0[n] = Lg[idx[n]];
+    y1[n] = Lg[idx[K + n]];
+  }
+  int q = 0;
+#pragma unroll
+  for (int n = 0; n < K; ++n)
+#pragma unroll
+    for (int np = n + 1; np < K; ++np, ++q) cfma(acc, mm[q], y0[n] * y1[np] - y0[np] * y1[n]);
+}
+
+__global__ __launch_bounds__(512) void k_energy_second(
+    DevSpin sa, DevSpin sb, DevPairs pr, const int4* __restrict__ plan, int n_ib,
+    int waves_per_block, int NW, int w0, int NG, int n_gsplit, int G, const cd* __restrict__ Lam_a,
+    const cd* __restrict__ Lam_b, const cd* __restrict__ coef, const cd* __restrict__ m2a,
+    const cd* __restrict__ m2b, const cd* __restrict__ Ba, const cd* __restrict__ Bb,
+    cd* __restrict__ partial, int n_slots, int slot0) {
+  extern __shared__ cd sm[];
+  __shared__ cd red[16];
+  // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs, so the
+  // item blocks of one (walker, Cholesky range), which stage the same Lambda
+  // slabs, are given consecutive ids on one XCD and share its L2.
+  const int nblk = gridDim.x, b = blockIdx.x;
+  const int per = nblk / 8, rem = nblk % 8, xcd = b % 8;
+  const int logical = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + b / 8;
+  const int ib = logical % n_ib, gs = (logical / n_ib) % n_gsplit, wl = logical / (n_ib * n_gsplit);
+  const int w = w0 + wl, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int Xa = sa.nv * sa.no, Xb = sb.nv * sb.no, X = Xa + Xb;
+  const int gper = (NG + n_gsplit - 1) / n_gsplit;
+  const int g0 = gs * gper, g1 = min(NG, g0 + gper);
+  cd* buf[2] = {sm, sm + (size_t)G * X};
+  // plan entry of this wave: (role | spin << 8, first string of the order,
+  // first item, item end)
+  const int4 pl = plan[ib * waves_per_block + wave];
+  const int role = pl.x & 0xff, sp = pl.x >> 8;
+  const int off = sp ? Xa : 0;  // spin block inside a staged Cholesky vector
+  int idx[16];
+  cd mm[15];
+  cd acc[8];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) idx[j] = 0;
+#pragma unroll
+  for (int j = 0; j < 15; ++j) mm[j] = cd{0.0, 0.0};
+#pragma unroll
+  for (int j = 0; j < 8; ++j) acc[j] = cd{0.0, 0.0};
+  const int item = role == ER_PAIRS ? pl.z + lane * 8 : pl.z + lane;
+  const bool live = role != ER_NONE && item < pl.w;
+  int str = 0;
+  if (live) {
+    if (role == ER_PAIRS) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int t = item + j;
+        const bool ok = t < pl.w;
+        idx[j] = ok ? pr.x[t] : -1;
+        idx[8 + j] = ok ? Xa + pr.y[t] : 0;
+      }
+    } else {
+      const int K = role;  // row-pair roles equal the string order
+      const int P = K * (K - 1) / 2;
+      str = pl.y + item / P;
+      const int rp = item % P;
+      const int* hwin = sp ? sb.hwin : sa.hwin;
+      const int* pwin = sp ? sb.pwin : sa.pwin;
+      const int no = sp ? sb.no : sa.no;
+      const cd* m2s = (sp ? m2b + (size_t)w * sb.M2 + sb.m2_off[str]
+                          : m2a + (size_t)w * sa.M2 + sa.m2_off[str]);
+      switch (K) {
+        case 2: rp_setup<2>(hwin, pwin, no, str, rp, off, m2s, idx, mm); break;
+        case 3: rp_setup<3>(hwin, pwin, no, str, rp, off, m2s, idx, mm); break;
+        case 4: rp_setup<4>(hwin, pwin, no, str, rp, off, m2s, idx, mm); break;
+        case 5: rp_setup<5>(hwin, pwin, no, str, rp, off, m2s, idx, mm); break;
+        default: rp_setup<6>(hwin, pwin, no, str, rp, off, m2s, idx, mm); break;
+      }
+    }
+  }
+  auto stage = [&](int gb, cd* dst) {
+    const int Gs = min(G, g1 - gb);
+    for (int e = tid; e < Gs * X; e += blockDim.x) {
+      const int gl = e / X, x = e % X;
+      dst[e] = x < Xa ? Lam_a[((size_t)wl * NG + gb + gl) * Xa + x]
+                      : Lam_b[((size_t)wl * NG + gb + gl) * Xb + (x - Xa)];
+    }
+  };
+  if (g0 < g1) stage(g0, buf[0]);
+  __syncthreads();
+  int it = 0;
+  for (int gb = g0; gb < g1; gb += G, ++it) {
+    if (gb + G < g1) stage(gb + G, buf[(it + 1) & 1]);
+    const cd* L = buf[it & 1];
+    const int Gs = min(G, g1 - gb);
+    if (live) {
+      for (int gl = 0; gl < Gs; ++gl) {
+        const cd* Lg = L + gl * X;
+        switch (role) {
+          case ER_PAIRS:
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+              if (idx[j] >= 0) cfma(acc[j], Lg[idx[j]], Lg[idx[8 + j]]);
+            break;
+          case 2: rp_eval<2>(Lg, idx, mm, acc[0]); break;
+          case 3: rp_eval<3>(Lg, idx, mm, acc[0]); break;
+          case 4: rp_eval<4>(Lg, idx, mm, acc[0]); break;
+          case 5: rp_eval<5>(Lg, idx, mm, acc[0]); break;
+          default: rp_eval<6>(Lg, idx, mm, acc[0]); break;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  cd tot{0.0, 0.0};
+  if (live) {
+    if (role == ER_PAIRS) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (idx[j] >= 0) cfma(tot, coef[(size_t)w * pr.n_pair + item + j], acc[j]);
+    } else {
+      tot = (sp ? Bb[(size_t)w * sb.U + str] : Ba[(size_t)w * sa.U + str]) * acc[0];
+    }
+  }
+  tot = wave_sum(tot);
+  if (lane == 0) red[wave] = tot;
+  __syncthreads();
+  if (tid == 0) {
+    cd t{0.0, 0.0};
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) t += red[q];
+    partial[(size_t)w * n_slots + slot0 + (size_t)ib * n_gsplit + gs] = t;
+  }
+}
+
+void launch_energy_second(const DevSpin& sa, const DevSpin& sb, const DevPairs& pr,
+                          const int4* plan, int n_itemblocks, int waves_per_block, int NW, int w0,
+                          int WT, int NG, int n_gsplit, int G, const cd* Lam_a, const cd* Lam_b,
+                          const cd* coef, const cd* m2a, const cd* m2b, const cd* Ba,
+                          const cd* Bb, cd* partial, int n_slots, int slot0, hipStream_t st) {
+  if (n_itemblocks == 0) return;
+  const size_t lds = 2 * (size_t)G * (sa.nv * sa.no + sb.nv * sb.no) * sizeof(cd);
+  hipLaunchKernelGGL(k_energy_second, dim3(WT * n_gsplit * n_itemblocks, 1), dim3(64 * waves_per_block),
+                     lds, st, sa, sb, pr, plan, n_itemblocks, waves_per_block, NW, w0, NG, n_gsplit, G, Lam_a,
+                     Lam_b, coef, m2a, m2b, Ba, Bb, partial, n_slots, slot0);
+}
+
 int energy_pair_blocks(int n_pair) {
   return (n_pair + PAIR_THREADS * PAIRS_PER_THREAD - 1) / (PAIR_THREADS * PAIRS_PER_THREAD);
 }
@@ -1169,6 +1481,7 @@ void init_wick_attributes() {
   hipFuncSetAttribute((const void*)k_green, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   hipFuncSetAttribute((const void*)k_lambda, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   hipFuncSetAttribute((const void*)k_energy_pairs, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  hipFuncSetAttribute((const void*)k_energy_second, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   hipFuncSetAttribute((const void*)k_energy_minors, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   hipFuncSetAttribute((const void*)k_energy_strings<2>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   hipFuncSetAttribute((const void*)k_energy_strings<3>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);

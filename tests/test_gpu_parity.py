@@ -81,9 +81,10 @@ def test_tiny_measure_is_reproducible():
         np.testing.assert_array_equal(a[k], b[k])
 
 
-def test_medium_full_batch_sampled_walkers():
+@pytest.mark.parametrize("algo", [0, 3])
+def test_medium_full_batch_sampled_walkers(algo):
     wl = make_config("medium")
-    s = system_for(wl)
+    s = system_for(wl, energy_algo=algo)
     out = s.measure(wl.dt)
     lo_ref = np.array([np.log(msd.trial_overlap(wl.ci, wl.occ_a, wl.occ_b, wl.phi_a[w], wl.phi_b[w]))
                        for w in range(wl.n_walkers)])
@@ -299,6 +300,52 @@ def test_device_entry_points_match_host():
         np.testing.assert_array_equal(u, v)
 
 
+def _excitation_lists(wl, rng):
+    """Occupation rows -> (ref, k, offsets, holes, parts) with each spin's
+    holes and particles in a random pairing order."""
+    ref = [wl.occ_a[0], wl.occ_b[0]]
+    ks, hs, ps = [[], []], [], []
+    offsets = [0]
+    for I in range(wl.n_det):
+        h_all, p_all = [], []
+        for sp, occ in enumerate((wl.occ_a, wl.occ_b)):
+            r, row = set(ref[sp].tolist()), set(occ[I].tolist())
+            h = rng.permutation(sorted(r - row)).tolist()
+            p = rng.permutation(sorted(row - r)).tolist()
+            ks[sp].append(len(h))
+            h_all += h
+            p_all += p
+        hs += h_all
+        ps += p_all
+        offsets.append(offsets[-1] + len(h_all))
+    return (ref[0], ref[1], np.array(ks[0]), np.array(ks[1]), np.array(offsets),
+            np.array(hs, dtype=np.int32), np.array(ps, dtype=np.int32))
+
+
+def test_trial_from_excitation_lists_matches_occupations():
+    wl = make_config("medium", n_walkers=8, n_det=300)
+    ra, rb, ka, kb, off, hs, ps = _excitation_lists(wl, np.random.default_rng(5))
+    a = system_for(wl).measure(wl.dt)
+    s = MsdSystem(wl.M, wl.n_alpha, wl.n_beta, wl.n_chol, wl.n_walkers, wl.n_det)
+    s.set_hamiltonian(wl.h1, wl.chol, wl.e0)
+    s.set_trial_exc(ra, rb, wl.ci, ka, kb, off, hs, ps)
+    s.set_walkers(wl.phi_a, wl.phi_b, wl.weights)
+    b = s.measure(wl.dt)
+    for key in a:
+        np.testing.assert_array_equal(a[key], b[key])
+    w, lo = s.get_weights()
+    np.testing.assert_array_equal(w, wl.weights)
+    np.testing.assert_array_equal(lo, b["log_ovlp"])
+    bad = ps.copy()
+    bad[0] = ra[0]  # a particle inside the reference
+    with pytest.raises(MsdError) as e:
+        s.set_trial_exc(ra, rb, wl.ci, ka, kb, off, hs, bad)
+    assert e.value.name == "MSD_ERR_TRIAL"
+    with pytest.raises(MsdError) as e:
+        s.set_trial_exc(ra, rb, wl.ci, ka, kb, off + 1, hs, ps)
+    assert e.value.name == "MSD_ERR_TRIAL"
+
+
 def test_error_paths():
     wl = make_config("tiny")
     s = MsdSystem(wl.M, 3, 3, wl.n_chol, wl.n_walkers, wl.n_det)
@@ -322,13 +369,42 @@ def test_error_paths():
     assert e.value.name == "MSD_ERR_ARG"
 
 
-@pytest.mark.parametrize("algo", [1, 2])
+@pytest.mark.parametrize("algo", [1, 2, 3])
 def test_energy_algorithms_agree_with_oracle(algo):
     """Both forms of the same-spin second-order terms (per-minor lists and
-    per-string registers) against the oracle, including orders up to 4."""
+    row-pair items of each string), and the fused Cholesky contraction
+    (algo 3), against the oracle, with excitation orders up to 6."""
     wl = make_workload("algo", M=20, n_alpha=5, n_beta=4, n_chol=24, n_det=80, k_max=6,
                        window=(4, 9), c_law="flat", n_walkers=4, seed=91 + algo,
                        complex_ci=True, noise=0.4)
     s = system_for(wl, energy_algo=algo)
     out = s.measure(0.01)
     compare_walkers(wl, out, range(4), 0.01)
+
+
+def test_graph_replay_matches_eager():
+    """Steps and measurements replayed from HIP graphs equal the eager
+    launches bit for bit, across several replays (with eager work between
+    them), both step variants (with and without QR) and a change of dt."""
+    wl = make_config("medium", n_walkers=16, n_det=300)
+
+    def make(graphs):
+        s = MsdSystem(wl.M, wl.n_alpha, wl.n_beta, wl.n_chol, wl.n_walkers, wl.n_det,
+                      stabilize_freq=2, graphs=graphs)
+        s.set_hamiltonian(wl.h1, wl.chol, wl.e0)
+        s.set_trial(wl.ci, wl.occ_a, wl.occ_b)
+        s.set_walkers(wl.phi_a, wl.phi_b, wl.weights)
+        return s
+
+    eager, graph = make(False), make(True)
+    for k in range(5):
+        dt = wl.dt if k < 3 else 2 * wl.dt
+        x = fields_for_step(wl, k)
+        for s in (eager, graph):
+            s.propagate(x, dt, 0.1)
+        a, b = eager.get_walkers(), graph.get_walkers()
+        for u, v in zip(a, b):
+            np.testing.assert_array_equal(u, v)
+        ma, mb = eager.measure(dt, energy=k % 2 == 0), graph.measure(dt, energy=k % 2 == 0)
+        for key in ma:
+            np.testing.assert_array_equal(ma[key], mb[key])
