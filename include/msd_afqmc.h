@@ -85,7 +85,15 @@ typedef struct {
   int32_t graphs;         /* 1: record each measure / propagate step once as a HIP graph
                              (on a private stream) and replay it on the handle's stream;
                              ignored while timing is on.  Default 0                  */
-  int32_t reserved[3];
+  int32_t precision;      /* 0 = FP64 throughout (default).  1 = mixed form: the dense
+                             Cholesky contractions (force bias, LT = L T, VHS) run as
+                             FP32 MFMA GEMMs, the energy intermediates Lambda and the
+                             Cholesky-vector sums of the second-order energy terms in
+                             FP32; the reference inverse, k x k determinants and
+                             cofactors, Taylor propagator, QR, overlaps and weights
+                             stay FP64.  Energies of trials with excitation orders
+                             above 6 per spin are evaluated in FP64.                 */
+  int32_t reserved[2];
 } msd_options;
 
 /* Limits of this implementation. */

@@ -24,6 +24,7 @@
 #include "trial.h"
 
 using msd::cd;
+using msd::cf;
 
 namespace {
 
@@ -127,6 +128,19 @@ struct msd_system {
   cd* segp[2] = {nullptr, nullptr};  // CI-weight segment partials
   double* fb_ws = nullptr;           // split-K workspace of the force-bias GEMM
   int fb_splitk = 1;
+
+  // mixed form: single-precision copies of the GEMM operands
+  bool mixed = false;
+  float* L32 = nullptr;                     // [NG][M][M]
+  float* Llt32[2] = {nullptr, nullptr};     // [NG][P_s][M]
+  float* Lrows32 = nullptr;                 // [NG][P_all][M]
+  float* T32[2] = {nullptr, nullptr};       // [M][NW][N_s] complex
+  float* Gp32 = nullptr;                    // [2 NW][P_all M]
+  float* Y32 = nullptr;                     // [2 NW][NG]
+  float* fb_ws32 = nullptr;
+  cf* LT32[2] = {nullptr, nullptr};
+  cf* Lam32[2] = {nullptr, nullptr};
+  bool energy_mixed = false;                // mixed energy path usable for this trial
 
   // energy work (lazily sized)
   int WT = 0, gl_chunk = 16, n_lchunks = 0;
@@ -301,6 +315,11 @@ void build_derived(msd_system* s) {
     msd::launch_gather_rows(s->L, s->NG, s->M, D.rows, D.P, s->L_lt[sp], s->st);
   }
   msd::launch_gather_rows(s->L, s->NG, s->M, s->rows_all_dev, s->P_all, s->L_rows, s->st);
+  if (s->mixed) {
+    for (int sp = 0; sp < 2; ++sp)
+      msd::launch_f64_to_f32(s->L_lt[sp], s->Llt32[sp], (int64_t)s->NG * s->ds[sp].P * s->M, s->st);
+    msd::launch_f64_to_f32(s->L_rows, s->Lrows32, (int64_t)s->NG * s->P_all * s->M, s->st);
+  }
   s->check_launch("gather rows");
   s->derived_ok = true;
 }
@@ -339,6 +358,7 @@ void alloc_energy(msd_system* s) {
     bool strings = c_str < c_min;
     if (s->o.energy_algo == 1) strings = false;
     if (s->o.energy_algo == 2) strings = true;
+    if (s->mixed) strings = true;  // the mixed form has only the row-pair kernel
     if (big) strings = false;  // orders above ER_MAX_ORDER only in the minor-list form
     s->use_strings[sp] = strings;
     if (!strings) continue;
@@ -360,17 +380,26 @@ void alloc_energy(msd_system* s) {
     slot += msd::energy_minor_blocks(s->ds[sp]) * s->gsplit;
   }
   {
+    int nmax = 0;
+    s->energy_mixed = s->mixed && s->use_strings[0] && s->use_strings[1] &&
+                      msd::lambda_rows_fits(A, B, &nmax);
     const int X = A.nv * A.no + B.nv * B.no;
-    s->second_G = std::max(1, std::min(32, (int)((64 << 10) / (2 * 16 * std::max(X, 1)))));
+    const int elem = s->energy_mixed ? 8 : 16;  // bytes per staged Lambda entry
+    s->second_G = std::max(1, std::min(32, (int)((64 << 10) / (2 * elem * std::max(X, 1)))));
   }
   s->n_slots = slot;  // every slot is written by exactly one workgroup
   Arena& E = s->energy_mem;
   for (int sp = 0; sp < 2; ++sp) {
     const msd::DevSpin& D = s->ds[sp];
     int wbf = 0;
-    if (!(s->o.energy_algo == 3 && msd::chol_contract_fits(s->ds[0], s->ds[1], &wbf)))
-      s->LT[sp] = E.get<cd>((size_t)NG * D.P * wt * D.N);
-    s->Lam[sp] = E.get<cd>((size_t)wt * NG * D.nv * D.no);
+    if (s->energy_mixed) {
+      s->LT32[sp] = E.get<cf>((size_t)NG * D.P * wt * D.N);
+      s->Lam32[sp] = E.get<cf>((size_t)wt * NG * D.nv * D.no);
+    } else {
+      if (!(s->o.energy_algo == 3 && msd::chol_contract_fits(s->ds[0], s->ds[1], &wbf)))
+        s->LT[sp] = E.get<cd>((size_t)NG * D.P * wt * D.N);
+      s->Lam[sp] = E.get<cd>((size_t)wt * NG * D.nv * D.no);
+    }
     s->ZWp[sp] = E.get<cd>((size_t)wt * s->n_lchunks * D.nv * D.no);
     s->coef2[sp] = E.get<cd>((size_t)NW * D.n_minor);
   }
@@ -477,6 +506,29 @@ void run_green_fb(msd_system* s, double dt) {
     msd::launch_green_sum(s->M, s->NW, s->P_all, s->rmap[0], s->rmap[1], s->ds[0].P,
                           s->ds[1].P, s->sw[0].G, s->sw[1].G, s->Gp, s->st);
   });
+  if (s->mixed) {
+    s->timed(ST_FB_GEMM, [&] {
+      msd::launch_f64_to_f32(s->Gp, s->Gp32, (int64_t)2 * s->NW * s->P_all * s->M, s->st);
+      msd::GemmArgs32 g;
+      g.M = s->NG;
+      g.N = 2 * s->NW;
+      g.K = s->P_all * s->M;
+      g.A = s->Lrows32;
+      g.lda = g.K;
+      g.a_kmaj = true;
+      g.B = s->Gp32;
+      g.ldb = g.K;
+      g.b_kmaj = true;
+      g.C64 = s->xraw;
+      g.ldc = 2 * s->NW;
+      g.splitk = s->fb_splitk;
+      g.ws = s->fb_ws32;
+      msd::launch_gemm32(g, s->st);
+      msd::launch_xbar(s->NW, s->NG, s->xraw, std::sqrt(dt), s->xbar, s->st);
+    });
+    s->check_launch("green/force bias");
+    return;
+  }
   s->timed(ST_FB_GEMM, [&] {
     msd::GemmArgs g;
     g.M = s->NG;
@@ -498,6 +550,63 @@ void run_green_fb(msd_system* s, double dt) {
   s->check_launch("green/force bias");
 }
 
+// A6 + A7 in the mixed form: FP32 copies of T, FP32 MFMA LT GEMM, FP32 Lambda
+// and second-order Cholesky sums; v0, ex0, ZW, cofactors and the assembly in
+// FP64.
+void run_energy_mixed(msd_system* s) {
+  const msd::DevSpin& A = s->ds[0];
+  const msd::DevSpin& B = s->ds[1];
+  int nmax = 0;
+  msd::lambda_rows_fits(A, B, &nmax);
+  s->timed(ST_LT_GEMM, [&] {
+    for (int sp = 0; sp < 2; ++sp)
+      msd::launch_f64_to_f32(reinterpret_cast<const double*>(s->sw[sp].T), s->T32[sp],
+                             (int64_t)2 * s->M * s->NW * s->ds[sp].N, s->st);
+  });
+  for (int w0 = 0; w0 < s->NW; w0 += s->WT) {
+    const int wt = std::min(s->WT, s->NW - w0);
+    for (int sp = 0; sp < 2; ++sp) {
+      const msd::DevSpin& D = s->ds[sp];
+      if (D.N == 0) continue;
+      s->timed(ST_LT_GEMM, [&] {
+        msd::GemmArgs32 g;
+        g.M = s->NG * D.P;
+        g.N = 2 * wt * D.N;
+        g.K = s->M;
+        g.A = s->Llt32[sp];
+        g.lda = s->M;
+        g.a_kmaj = true;
+        g.B = s->T32[sp] + (size_t)2 * w0 * D.N;
+        g.ldb = 2 * (int64_t)s->NW * D.N;
+        g.b_kmaj = false;
+        g.C32 = reinterpret_cast<float*>(s->LT32[sp]);
+        g.ldc = 2 * (int64_t)wt * D.N;
+        msd::launch_gemm32(g, s->st);
+      });
+    }
+    s->timed(ST_LAMBDA, [&] {
+      msd::launch_lambda_rows32(A, B, nmax, s->NW, w0, wt, s->NG, s->gl_chunk,
+                                reinterpret_cast<const cf*>(s->T32[0]),
+                                reinterpret_cast<const cf*>(s->T32[1]), s->LT32[0], s->LT32[1],
+                                s->Lam32[0], s->Lam32[1], s->v0, s->ex0, s->ZWp[0], s->ZWp[1],
+                                s->st);
+    });
+    s->timed(ST_EGAMMA, [&] {
+      msd::launch_energy_second32(A, B, s->dp, s->plan, s->n_itemblocks, msd::ER_WAVES, s->NW,
+                                  w0, wt, s->NG, s->gsplit, s->second_G, s->Lam32[0],
+                                  s->Lam32[1], s->coefAB, s->sw[0].m2, s->sw[1].m2, s->sw[0].B,
+                                  s->sw[1].B, s->epart, s->n_slots, s->slot_second, s->st);
+    });
+    s->timed(ST_EFINAL, [&] {
+      msd::launch_energy_final(A, B, s->NW, w0, wt, s->NG, s->n_lchunks, s->n_slots, s->obar,
+                               s->v0, s->ex0, s->ZWp[0], s->ZWp[1], s->sw[0].C, s->sw[1].C,
+                               s->epart, s->onebody, s->onebody + s->NW, s->e0, s->eloc,
+                               s->st);
+    });
+  }
+  s->check_launch("energy");
+}
+
 // A6 + A7: local energies into s->eloc (needs run_overlap with minors and run_green_fb).
 void run_energy(msd_system* s) {
   alloc_energy(s);
@@ -511,6 +620,10 @@ void run_energy(msd_system* s) {
         msd::launch_minor_coef(s->ds[sp], s->NW, s->sw[sp].B, s->ds[sp].U, s->sw[sp].m2,
                                s->coef2[sp], s->st);
   });
+  if (s->energy_mixed) {
+    run_energy_mixed(s);
+    return;
+  }
   int wb = 0;
   const bool fused = s->o.energy_algo == 3 && msd::chol_contract_fits(A, B, &wb);
   for (int w0 = 0; w0 < s->NW; w0 += s->WT) {
@@ -634,6 +747,23 @@ void propagate_step(msd_system* s, const double* x, double dt, double e_shift, b
   run_green_fb(s, dt);
   s->timed(ST_VHS_GEMM, [&] {
     msd::launch_vhs_prep(NW, NG, x, s->xbar, std::sqrt(dt), s->weights, s->Y, s->st);
+    if (s->mixed) {
+      msd::launch_f64_to_f32(s->Y, s->Y32, (int64_t)2 * NW * NG, s->st);
+      msd::GemmArgs32 g;
+      g.M = 2 * NW;
+      g.N = (int)mm;
+      g.K = NG;
+      g.A = s->Y32;
+      g.lda = NG;
+      g.a_kmaj = true;
+      g.B = s->L32;
+      g.ldb = (int64_t)mm;
+      g.b_kmaj = false;
+      g.C64 = s->VHS;
+      g.ldc = (int64_t)mm;
+      msd::launch_gemm32(g, s->st);
+      return;
+    }
     msd::GemmArgs g;
     g.M = 2 * NW;
     g.N = (int)mm;
@@ -794,7 +924,8 @@ msd_status msd_create(const msd_dims* d, const msd_options* o, int32_t device, v
   msd_default_options(&opt);
   if (o) opt = *o;
   if (opt.n_taylor < 0 || opt.n_taylor > 32 || opt.stabilize_freq < 0 || opt.energy_algo < 0 ||
-      opt.energy_algo > 3 || opt.graphs < 0 || opt.graphs > 1)
+      opt.energy_algo > 3 || opt.graphs < 0 || opt.graphs > 1 || opt.precision < 0 ||
+      opt.precision > 1)
     fail(MSD_ERR_ARG, "invalid options");
   sys = new msd_system();
   sys->dev = device;
@@ -840,6 +971,15 @@ msd_status msd_create(const msd_dims* d, const msd_options* o, int32_t device, v
       const int N = sp ? sys->nb : sys->na;
       sys->sw[sp].T = A.get<cd>((size_t)M * NW * std::max(N, 1));
       sys->sw[sp].logdetA = A.get<cd>(NW);
+    }
+    sys->mixed = opt.precision == 1;
+    if (sys->mixed) {
+      sys->L32 = A.get<float>((size_t)NG * M * M);
+      sys->Y32 = A.get<float>((size_t)2 * NW * NG);
+      for (int sp = 0; sp < 2; ++sp) {
+        const int N = sp ? sys->nb : sys->na;
+        sys->T32[sp] = A.get<float>((size_t)2 * M * NW * std::max(N, 1));
+      }
     }
     hip_check(hipMemsetAsync(sys->flag, 0, sizeof(int) * NW, sys->st), "memset");
     hip_check(hipMemsetAsync(sys->sw[0].logdetA, 0, sizeof(cd) * NW, sys->st), "memset");
@@ -914,6 +1054,7 @@ msd_status msd_set_hamiltonian(msd_system* sys, const double* h1, const double* 
   hip_check(e1, "sum LL");
   hip_check(e2, "sum LL");
   sys->sumll_host = tmp;
+  if (sys->mixed) msd::launch_f64_to_f32(sys->L, sys->L32, (int64_t)NG * M * M, sys->st);
   sys->B1_dt = NAN;
   sys->have_ham = true;
   sys->derived_ok = false;
@@ -1035,9 +1176,15 @@ void set_trial_rows(msd_system* sys, const double* ci, const int32_t* occ_a,
     int sk = (int)std::max<int64_t>(1, std::min<int64_t>(512 / std::max<int64_t>(tiles, 1), K / 256));
     sys->fb_splitk = sk;
     sys->fb_ws = sk > 1 ? T.get<double>((size_t)sk * NG * 2 * NW) : nullptr;
+    sys->fb_ws32 = (sk > 1 && sys->mixed) ? T.get<float>((size_t)sk * NG * 2 * NW) : nullptr;
   }
   sys->L_rows = T.get<double>((size_t)NG * sys->P_all * M);
   sys->Gp = T.get<double>((size_t)2 * NW * sys->P_all * M);
+  if (sys->mixed) {
+    sys->Gp32 = T.get<float>((size_t)2 * NW * sys->P_all * M);
+    sys->Lrows32 = T.get<float>((size_t)NG * sys->P_all * M);
+    for (int sp = 0; sp < 2; ++sp) sys->Llt32[sp] = T.get<float>((size_t)NG * sys->ds[sp].P * M);
+  }
   sys->dp.n_pair = sys->tt.n_pair;
   sys->dp.x = T.upload(sys->tt.pr_x, st);
   sys->dp.y = T.upload(sys->tt.pr_y, st);

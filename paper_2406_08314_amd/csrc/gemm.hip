@@ -279,6 +279,176 @@ void launch_gemm(const GemmArgs& g, hipStream_t st) {
   }
 }
 
+// ============================================================================
+// FP32 MFMA GEMM (mixed-precision form): the same 64x64 tile, 4 waves of 2x2
+// v_mfma_f32_16x16x4f32, K slabs of 16 double-buffered in LDS.  Row pad of 16
+// floats puts the four k-rows read by one ds_read_b32 wave in disjoint banks.
+// ============================================================================
+
+typedef float float4_t __attribute__((ext_vector_type(4)));
+constexpr int GPAD32 = 16;
+
+template <bool A_KMAJ, bool B_KMAJ, bool OUT64>
+__global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs32 g) {
+  const int bz = blockIdx.z;
+  if (g.mask && g.mask[bz] == 0) return;
+  const bool split = g.splitk > 1;
+  const int kchunk = split ? ((g.K + g.splitk * GB_K - 1) / (g.splitk * GB_K)) * GB_K : 0;
+  const int kbeg = split ? bz * kchunk : 0;
+  const int kend = split ? min(g.K, kbeg + kchunk) : g.K;
+  const float* A = g.A + (split ? 0 : (int64_t)bz * g.strideA);
+  const float* B = g.B + (split ? 0 : (int64_t)bz * g.strideB);
+
+  __shared__ float As[2][GB_K][GB_M + GPAD32];
+  __shared__ float Bs[2][GB_K][GB_N + GPAD32];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int m0 = blockIdx.y * GB_M;
+  const int n0 = blockIdx.x * GB_N;
+  const int wm = (wave >> 1) * 32;
+  const int wn = (wave & 1) * 32;
+  const int a_mm = A_KMAJ ? (tid >> 2) : (tid & 15) * 4;
+  const int a_kk = A_KMAJ ? (tid & 3) * 4 : (tid >> 4);
+  const int b_nn = B_KMAJ ? (tid >> 2) : (tid & 15) * 4;
+  const int b_kk = B_KMAJ ? (tid & 3) * 4 : (tid >> 4);
+  const bool a_vec = ((g.lda & 3) == 0) && ((((uintptr_t)A) & 15) == 0);
+  const bool b_vec = ((g.ldb & 3) == 0) && ((((uintptr_t)B) & 15) == 0);
+  const bool m_full = m0 + GB_M <= g.M;
+  const bool n_full = n0 + GB_N <= g.N;
+
+  float ra[4], rb[4];
+  auto load = [&](int k0) {
+    const bool k_full = k0 + GB_K <= kend;
+    if (a_vec && m_full && k_full) {
+      const int gm = m0 + a_mm, gk = k0 + a_kk;
+      const float* p = A_KMAJ ? A + (int64_t)gm * g.lda + gk : A + (int64_t)gk * g.lda + gm;
+      const float4 v = *reinterpret_cast<const float4*>(p);
+      ra[0] = v.x; ra[1] = v.y; ra[2] = v.z; ra[3] = v.w;
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + a_mm + (A_KMAJ ? 0 : r), gk = k0 + a_kk + (A_KMAJ ? r : 0);
+        ra[r] = (gm < g.M && gk < kend)
+                    ? (A_KMAJ ? A[(int64_t)gm * g.lda + gk] : A[(int64_t)gk * g.lda + gm])
+                    : 0.f;
+      }
+    }
+    if (b_vec && n_full && k_full) {
+      const int gn = n0 + b_nn, gk = k0 + b_kk;
+      const float* p = B_KMAJ ? B + (int64_t)gn * g.ldb + gk : B + (int64_t)gk * g.ldb + gn;
+      const float4 v = *reinterpret_cast<const float4*>(p);
+      rb[0] = v.x; rb[1] = v.y; rb[2] = v.z; rb[3] = v.w;
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gn = n0 + b_nn + (B_KMAJ ? 0 : r), gk = k0 + b_kk + (B_KMAJ ? r : 0);
+        rb[r] = (gn < g.N && gk < kend)
+                    ? (B_KMAJ ? B[(int64_t)gn * g.ldb + gk] : B[(int64_t)gk * g.ldb + gn])
+                    : 0.f;
+      }
+    }
+  };
+
+  float4_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
+
+  int buf = 0;
+  if (kbeg < kend) load(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += GB_K) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (A_KMAJ) As[buf][a_kk + r][a_mm] = ra[r];
+      else As[buf][a_kk][a_mm + r] = ra[r];
+      if (B_KMAJ) Bs[buf][b_kk + r][b_nn] = rb[r];
+      else Bs[buf][b_kk][b_nn + r] = rb[r];
+    }
+    __syncthreads();
+    if (k0 + GB_K < kend) load(k0 + GB_K);
+#pragma unroll
+    for (int kk = 0; kk < GB_K; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      const float a0 = As[buf][kr][wm + (lane & 15)];
+      const float a1 = As[buf][kr][wm + 16 + (lane & 15)];
+      const float b0 = Bs[buf][kr][wn + (lane & 15)];
+      const float b1 = Bs[buf][kr][wn + 16 + (lane & 15)];
+      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    buf ^= 1;
+  }
+
+  // epilogue: register r of lane l holds D[4 (l/16) + r][l % 16]
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
+        const int gn = n0 + wn + j * 16 + (lane & 15);
+        if (gm < g.M && gn < g.N) {
+          if (split) {
+            g.ws[(int64_t)bz * g.M * g.N + (int64_t)gm * g.N + gn] = acc[i][j][r];
+            continue;
+          }
+          const int64_t off = (int64_t)bz * g.strideC + (int64_t)gm * g.ldc + gn;
+          const double v = g.alpha * (double)acc[i][j][r];
+          if (OUT64) g.C64[off] = v;
+          else g.C32[off] = (float)v;
+        }
+      }
+}
+
+__global__ void k_splitk_reduce32(GemmArgs32 g) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= (int64_t)g.M * g.N) return;
+  const int m = (int)(tid / g.N), n = (int)(tid % g.N);
+  double s = 0.0;
+  for (int z = 0; z < g.splitk; ++z) s += (double)g.ws[(int64_t)z * g.M * g.N + tid];
+  const int64_t off = (int64_t)m * g.ldc + n;
+  if (g.C64) g.C64[off] = g.alpha * s;
+  else g.C32[off] = (float)(g.alpha * s);
+}
+
+template <bool AK, bool BK>
+static void launch32_t(const GemmArgs32& g, hipStream_t st) {
+  const int z = g.splitk > 1 ? g.splitk : g.batch;
+  dim3 grid((g.N + GB_N - 1) / GB_N, (g.M + GB_M - 1) / GB_M, z);
+  if (g.C64) hipLaunchKernelGGL((k_gemm_f32<AK, BK, true>), grid, dim3(256), 0, st, g);
+  else hipLaunchKernelGGL((k_gemm_f32<AK, BK, false>), grid, dim3(256), 0, st, g);
+  if (g.splitk > 1) {
+    const int64_t n = (int64_t)g.M * g.N;
+    hipLaunchKernelGGL(k_splitk_reduce32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g);
+  }
+}
+
+void launch_gemm32(const GemmArgs32& g, hipStream_t st) {
+  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return;
+  if (!g.C32 == !g.C64) return;                              // exactly one output
+  if (g.splitk > 1 && (g.batch != 1 || !g.ws)) return;      // unsupported combination
+  if (g.a_kmaj && !g.b_kmaj) launch32_t<true, false>(g, st);
+  else if (g.a_kmaj && g.b_kmaj) launch32_t<true, true>(g, st);
+  else if (!g.a_kmaj && !g.b_kmaj) launch32_t<false, false>(g, st);
+  else launch32_t<false, true>(g, st);
+}
+
+__global__ void k_f64_to_f32(const double* __restrict__ src, float* __restrict__ dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (float)src[i];
+}
+
+void launch_f64_to_f32(const double* src, float* dst, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_f64_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, dst, n);
+}
+
 }  // namespace msd
 
 namespace msd {

@@ -25,6 +25,26 @@ struct GemmArgs {
 };
 void launch_gemm(const GemmArgs& g, hipStream_t st);
 
+// FP32 MFMA GEMM (real operands, FP32 accumulation), same operand conventions
+// as GemmArgs; the result goes to C32 (float) or C64 (double).
+struct GemmArgs32 {
+  int M = 0, N = 0, K = 0, batch = 1;
+  const float* A = nullptr;
+  const float* B = nullptr;
+  float* C32 = nullptr;
+  double* C64 = nullptr;
+  int64_t lda = 0, ldb = 0, ldc = 0;
+  int64_t strideA = 0, strideB = 0, strideC = 0;
+  const int* mask = nullptr;
+  int splitk = 1;               // >1: K split over blockIdx.z (batch must be 1)
+  float* ws = nullptr;          // split-K workspace: splitk * M * N floats
+  double alpha = 1.0;
+  bool a_kmaj = true, b_kmaj = false;
+};
+void launch_gemm32(const GemmArgs32& g, hipStream_t st);
+// Element-wise precision conversions (n elements).
+void launch_f64_to_f32(const double* src, float* dst, int64_t n, hipStream_t st);
+
 // ---------------------------------------------------------------- device tables
 struct DevSpin {
   int N = 0, U = 0, nv = 0, no = 0, P = 0;  // P = N + nv (rows R then V_act)
@@ -115,6 +135,12 @@ void launch_lambda_rows(const DevSpin& sa, const DevSpin& sb, int nmax, int NW, 
                         int NG, int g_chunk, const cd* Ta, const cd* Tb, const cd* LTa,
                         const cd* LTb, cd* Lam_a, cd* Lam_b, cd* v0, cd* ex0, cd* ZWpart_a,
                         cd* ZWpart_b, hipStream_t st);
+// Same in single precision (mixed form): T, LT and Lambda as cf; v0, ex0 and
+// the ZW partial sums accumulate in double.
+void launch_lambda_rows32(const DevSpin& sa, const DevSpin& sb, int nmax, int NW, int w0, int WT,
+                          int NG, int g_chunk, const cf* Ta, const cf* Tb, const cf* LTa,
+                          const cf* LTb, cf* Lam_a, cf* Lam_b, cd* v0, cd* ex0, cd* ZWpart_a,
+                          cd* ZWpart_b, hipStream_t st);
 void launch_pair_coef(const DevPairs& pr, int NW, const cd* det_c, const cd* adj_a, int Aa,
                       const cd* adj_b, int Ab, cd* coef, hipStream_t st);
 void launch_minor_coef(const DevSpin& s, int NW, const cd* B, int U, const cd* m2, cd* coef,
@@ -129,6 +155,14 @@ void launch_energy_second(const DevSpin& sa, const DevSpin& sb, const DevPairs& 
                           int WT, int NG, int n_gsplit, int G, const cd* Lam_a, const cd* Lam_b,
                           const cd* coef, const cd* m2a, const cd* m2b, const cd* Ba,
                           const cd* Bb, cd* partial, int n_slots, int slot0, hipStream_t st);
+// Same with single-precision Lambda (mixed form); the minors, CI weights and
+// the final products stay in double.
+void launch_energy_second32(const DevSpin& sa, const DevSpin& sb, const DevPairs& pr,
+                            const int4* plan, int n_itemblocks, int waves_per_block, int NW,
+                            int w0, int WT, int NG, int n_gsplit, int G, const cf* Lam_a,
+                            const cf* Lam_b, const cd* coef, const cd* m2a, const cd* m2b,
+                            const cd* Ba, const cd* Bb, cd* partial, int n_slots, int slot0,
+                            hipStream_t st);
 int energy_pair_blocks(int n_pair);
 int energy_string_blocks(const DevSpin& s, int k);
 int energy_minor_blocks(const DevSpin& s);

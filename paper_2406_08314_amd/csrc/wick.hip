@@ -640,6 +640,15 @@ void launch_xbar(int NW, int NG, const double* raw, double sqrt_dt, cd* xbar, hi
 // One wave per workgroup: barriers are cheap and reductions use shuffles.
 // ============================================================================
 
+__device__ __forceinline__ cf wave_sum(cf v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    v.re += __shfl_xor(v.re, off, 64);
+    v.im += __shfl_xor(v.im, off, 64);
+  }
+  return v;
+}
+
 __device__ __forceinline__ cd wave_sum(cd v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
@@ -750,95 +759,98 @@ __global__ __launch_bounds__(64) void k_lambda(DevSpin sa, DevSpin sb, int NW, i
 // Q^g is broadcast from LDS.  NMAX bounds N, NOMAX bounds n_occ_act.
 constexpr int NOMAX = 16;
 
-template <int NMAX>
+template <int NMAX, class CT>
 __global__ __launch_bounds__(128) void k_lambda_rows(DevSpin sa, DevSpin sb, int NW, int w0,
                                                      int WT, int NG, int g_chunk,
-                                                     const cd* __restrict__ Ta,
-                                                     const cd* __restrict__ Tb,
-                                                     const cd* __restrict__ LTa,
-                                                     const cd* __restrict__ LTb,
-                                                     cd* __restrict__ Lam_a,
-                                                     cd* __restrict__ Lam_b,
+                                                     const CT* __restrict__ Ta,
+                                                     const CT* __restrict__ Tb,
+                                                     const CT* __restrict__ LTa,
+                                                     const CT* __restrict__ LTb,
+                                                     CT* __restrict__ Lam_a,
+                                                     CT* __restrict__ Lam_b,
                                                      cd* __restrict__ v0, cd* __restrict__ ex0,
                                                      cd* __restrict__ ZWa, cd* __restrict__ ZWb) {
-  __shared__ cd Qs[2][NMAX * NMAX];
-  __shared__ cd v0s[2];
+  __shared__ CT Qs[2][NMAX * NMAX];
+  __shared__ CT v0s[2];
   const int wl = blockIdx.x, chunk = blockIdx.y, n_chunks = gridDim.y;
   const int w = w0 + wl, lane = threadIdx.x & 63, s2 = threadIdx.x >> 6;
-  const DevSpin& S = s2 ? sb : sa;
-  const int N = S.N, nv = S.nv, no = S.no, P = S.P, X = nv * no;
-  const cd* __restrict__ T = s2 ? Tb : Ta;
-  const cd* __restrict__ LT = s2 ? LTb : LTa;
-  cd* __restrict__ Lam = s2 ? Lam_b : Lam_a;
+  const int N = s2 ? sb.N : sa.N, nv = s2 ? sb.nv : sa.nv, no = s2 ? sb.no : sa.no;
+  const int P = s2 ? sb.P : sa.P, X = nv * no;
+  const int* __restrict__ vir = s2 ? sb.vir : sa.vir;
+  const int* __restrict__ oslot = s2 ? sb.oslot : sa.oslot;
+  const CT* __restrict__ T = s2 ? Tb : Ta;
+  const CT* __restrict__ LT = s2 ? LTb : LTa;
+  CT* __restrict__ Lam = s2 ? Lam_b : Lam_a;
   cd* __restrict__ ZW = s2 ? ZWb : ZWa;
   const bool row = lane < nv;
-  cd tv[NMAX], zw[NOMAX];
+  CT tv[NMAX];
+  cd zw[NOMAX];
   int osl[NOMAX];
 #pragma unroll
   for (int j = 0; j < NMAX; ++j)
-    tv[j] = (row && j < N) ? T[((size_t)S.vir[lane] * NW + w) * N + j] : cd{0.0, 0.0};
+    tv[j] = (row && j < N) ? T[((size_t)vir[lane] * NW + w) * N + j] : CT{};
 #pragma unroll
   for (int i = 0; i < NOMAX; ++i) {
-    osl[i] = i < no ? S.oslot[i] : 0;
+    osl[i] = i < no ? oslot[i] : 0;
     zw[i] = cd{0.0, 0.0};
   }
   const size_t ld = (size_t)WT * N;
   const int g0 = chunk * g_chunk, g1 = min(NG, g0 + g_chunk);
   for (int g = g0; g < g1; ++g) {
-    const cd* base = LT + ((size_t)g * P) * ld + (size_t)wl * N;
+    const CT* base = LT + ((size_t)g * P) * ld + (size_t)wl * N;
     // Q^g of this spin into LDS; traces
-    cd v{0.0, 0.0}, x{0.0, 0.0};
+    CT v{}, x{};
     for (int e = lane; e < N * N; e += 64) {
       const int j = e / N, c = e % N;
-      const cd q = base[(size_t)j * ld + c];
+      const CT q = base[(size_t)j * ld + c];
       Qs[s2][e] = q;
       if (j == c) v += q;
     }
     // this lane's LT^g[V, :] row (independent of the LDS writes above)
-    cd ltv[NMAX];
+    CT ltv[NMAX];
 #pragma unroll
     for (int c = 0; c < NMAX; ++c)
-      ltv[c] = (row && c < N) ? base[(size_t)(N + lane) * ld + c] : cd{0.0, 0.0};
+      ltv[c] = (row && c < N) ? base[(size_t)(N + lane) * ld + c] : CT{};
     v = wave_sum(v);
     if (lane == 0) v0s[s2] = v;
     __syncthreads();
-    const cd* Q = Qs[s2];
+    const CT* Q = Qs[s2];
     for (int e = lane; e < N * N; e += 64) {
       const int j = e / N, c = e % N;
       cfma(x, Q[e], Q[c * N + j]);
     }
     x = wave_sum(x);
     if (lane == 0 && N > 0) {
-      v0[((size_t)s2 * NW + w) * NG + g] = v;
-      ex0[((size_t)s2 * NW + w) * NG + g] = x;
+      v0[((size_t)s2 * NW + w) * NG + g] = to_cd(v);
+      ex0[((size_t)s2 * NW + w) * NG + g] = to_cd(x);
     } else if (lane == 0) {
       v0[((size_t)s2 * NW + w) * NG + g] = cd{0.0, 0.0};
       ex0[((size_t)s2 * NW + w) * NG + g] = cd{0.0, 0.0};
     }
-    const cd vsum = v0s[0] + v0s[1];
+    const CT vsum = v0s[0] + v0s[1];
     if (row) {
-      cd lam[NMAX];
+      CT lam[NMAX];
 #pragma unroll
       for (int c = 0; c < NMAX; ++c) {
-        cd a = -ltv[c];
+        CT a = -ltv[c];
 #pragma unroll
         for (int j = 0; j < NMAX; ++j)
           if (j < N && c < N) cfma(a, tv[j], Q[j * N + c]);
         lam[c] = a;
       }
-      cd* Lo = Lam + ((size_t)wl * NG + g) * X + (size_t)lane * no;
+      CT* Lo = Lam + ((size_t)wl * NG + g) * X + (size_t)lane * no;
 #pragma unroll
       for (int i = 0; i < NOMAX; ++i) {
         if (i < no) {
           const int oc = osl[i];
-          cd xi{0.0, 0.0}, lw{0.0, 0.0};
+          CT xi{}, lw{};
 #pragma unroll
           for (int c = 0; c < NMAX; ++c) {
             if (c < N) cfma(xi, lam[c], Q[c * N + oc]);
             if (c == oc) lw = lam[c];
           }
           Lo[i] = lw;
-          zw[i] += xi - vsum * lw;
+          zw[i] += to_cd(xi - vsum * lw);
         }
       }
     }
@@ -858,17 +870,34 @@ bool lambda_rows_fits(const DevSpin& sa, const DevSpin& sb, int* nmax) {
   return true;
 }
 
+template <class CT>
+void launch_lambda_rows_t(const DevSpin& sa, const DevSpin& sb, int nmax, int NW, int w0, int WT,
+                          int NG, int g_chunk, const CT* Ta, const CT* Tb, const CT* LTa,
+                          const CT* LTb, CT* Lam_a, CT* Lam_b, cd* v0, cd* ex0, cd* ZWpart_a,
+                          cd* ZWpart_b, hipStream_t st) {
+  const int n_chunks = (NG + g_chunk - 1) / g_chunk;
+  dim3 grid(WT, n_chunks);
+  switch (nmax) {
+    case 8: hipLaunchKernelGGL((k_lambda_rows<8, CT>), grid, dim3(128), 0, st, sa, sb, NW, w0, WT, NG, g_chunk, Ta, Tb, LTa, LTb, Lam_a, Lam_b, v0, ex0, ZWpart_a, ZWpart_b); break;
+    case 16: hipLaunchKernelGGL((k_lambda_rows<16, CT>), grid, dim3(128), 0, st, sa, sb, NW, w0, WT, NG, g_chunk, Ta, Tb, LTa, LTb, Lam_a, Lam_b, v0, ex0, ZWpart_a, ZWpart_b); break;
+    default: hipLaunchKernelGGL((k_lambda_rows<32, CT>), grid, dim3(128), 0, st, sa, sb, NW, w0, WT, NG, g_chunk, Ta, Tb, LTa, LTb, Lam_a, Lam_b, v0, ex0, ZWpart_a, ZWpart_b); break;
+  }
+}
+
 void launch_lambda_rows(const DevSpin& sa, const DevSpin& sb, int nmax, int NW, int w0, int WT,
                         int NG, int g_chunk, const cd* Ta, const cd* Tb, const cd* LTa,
                         const cd* LTb, cd* Lam_a, cd* Lam_b, cd* v0, cd* ex0, cd* ZWpart_a,
                         cd* ZWpart_b, hipStream_t st) {
-  const int n_chunks = (NG + g_chunk - 1) / g_chunk;
-  dim3 grid(WT, n_chunks);
-  switch (nmax) {
-    case 8: hipLaunchKernelGGL(k_lambda_rows<8>, grid, dim3(128), 0, st, sa, sb, NW, w0, WT, NG, g_chunk, Ta, Tb, LTa, LTb, Lam_a, Lam_b, v0, ex0, ZWpart_a, ZWpart_b); break;
-    case 16: hipLaunchKernelGGL(k_lambda_rows<16>, grid, dim3(128), 0, st, sa, sb, NW, w0, WT, NG, g_chunk, Ta, Tb, LTa, LTb, Lam_a, Lam_b, v0, ex0, ZWpart_a, ZWpart_b); break;
-    default: hipLaunchKernelGGL(k_lambda_rows<32>, grid, dim3(128), 0, st, sa, sb, NW, w0, WT, NG, g_chunk, Ta, Tb, LTa, LTb, Lam_a, Lam_b, v0, ex0, ZWpart_a, ZWpart_b); break;
-  }
+  launch_lambda_rows_t<cd>(sa, sb, nmax, NW, w0, WT, NG, g_chunk, Ta, Tb, LTa, LTb, Lam_a, Lam_b,
+                           v0, ex0, ZWpart_a, ZWpart_b, st);
+}
+
+void launch_lambda_rows32(const DevSpin& sa, const DevSpin& sb, int nmax, int NW, int w0, int WT,
+                          int NG, int g_chunk, const cf* Ta, const cf* Tb, const cf* LTa,
+                          const cf* LTb, cf* Lam_a, cf* Lam_b, cd* v0, cd* ex0, cd* ZWpart_a,
+                          cd* ZWpart_b, hipStream_t st) {
+  launch_lambda_rows_t<cf>(sa, sb, nmax, NW, w0, WT, NG, g_chunk, Ta, Tb, LTa, LTb, Lam_a, Lam_b,
+                           v0, ex0, ZWpart_a, ZWpart_b, st);
 }
 
 void launch_lambda(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
@@ -1181,10 +1210,10 @@ __global__ __launch_bounds__(MINOR_THREADS) void k_energy_minors(
 // rows m and m' of Y_mn = Lam[p_n, h_m] (2K gathers per Cholesky vector) and
 // the K(K-1)/2 signed complementary minors of that row pair:
 //   e2 += sum_{n<n'} (-1)^{m+m'+n+n'} det X[~{m,m'},~{n,n'}] (Y_mn Y_m'n' - Y_mn' Y_m'n).
-template <int K>
+template <int K, class CT>
 __device__ __forceinline__ void rp_setup(const int* __restrict__ hwin, const int* __restrict__ pwin,
                                          int no, int str, int rp, int off, const cd* m2s,
-                                         int* idx, cd* mm) {
+                                         int* idx, CT* mm) {
   constexpr int P = K * (K - 1) / 2;
   int m = 0, mp = 1;
   for (int a = 0, q = 0; a < K; ++a)
@@ -1204,13 +1233,13 @@ __device__ __forceinline__ void rp_setup(const int* __restrict__ hwin, const int
     for (int np = n + 1; np < K; ++np, ++q) {
       cd v = src[q];
       if ((m + mp + n + np) & 1) v = -v;
-      mm[q] = v;
+      mm[q] = from_cd<CT>(v);
     }
 }
 
-template <int K>
-__device__ __forceinline__ void rp_eval(const cd* Lg, const int* idx, const cd* mm, cd& acc) {
-  cd y0[K], y1[K];
+template <int K, class CT>
+__device__ __forceinline__ void rp_eval(const CT* Lg, const int* idx, const CT* mm, CT& acc) {
+  CT y0[K], y1[K];
 #pragma unroll
   for (int n = 0; n < K; ++n) {
     y0[n] = Lg[idx[n]];
@@ -1223,13 +1252,15 @@ __device__ __forceinline__ void rp_eval(const cd* Lg, const int* idx, const cd* 
     for (int np = n + 1; np < K; ++np, ++q) cfma(acc, mm[q], y0[n] * y1[np] - y0[np] * y1[n]);
 }
 
+template <class CT>
 __global__ __launch_bounds__(512) void k_energy_second(
     DevSpin sa, DevSpin sb, DevPairs pr, const int4* __restrict__ plan, int n_ib,
-    int waves_per_block, int NW, int w0, int NG, int n_gsplit, int G, const cd* __restrict__ Lam_a,
-    const cd* __restrict__ Lam_b, const cd* __restrict__ coef, const cd* __restrict__ m2a,
+    int waves_per_block, int NW, int w0, int NG, int n_gsplit, int G, const CT* __restrict__ Lam_a,
+    const CT* __restrict__ Lam_b, const cd* __restrict__ coef, const cd* __restrict__ m2a,
     const cd* __restrict__ m2b, const cd* __restrict__ Ba, const cd* __restrict__ Bb,
     cd* __restrict__ partial, int n_slots, int slot0) {
-  extern __shared__ cd sm[];
+  extern __shared__ __align__(16) unsigned char sm_raw[];
+  CT* sm = reinterpret_cast<CT*>(sm_raw);
   __shared__ cd red[16];
   // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs, so the
   // item blocks of one (walker, Cholesky range), which stage the same Lambda
@@ -1242,21 +1273,21 @@ __global__ __launch_bounds__(512) void k_energy_second(
   const int Xa = sa.nv * sa.no, Xb = sb.nv * sb.no, X = Xa + Xb;
   const int gper = (NG + n_gsplit - 1) / n_gsplit;
   const int g0 = gs * gper, g1 = min(NG, g0 + gper);
-  cd* buf[2] = {sm, sm + (size_t)G * X};
+  CT* buf[2] = {sm, sm + (size_t)G * X};
   // plan entry of this wave: (role | spin << 8, first string of the order,
   // first item, item end)
   const int4 pl = plan[ib * waves_per_block + wave];
   const int role = pl.x & 0xff, sp = pl.x >> 8;
   const int off = sp ? Xa : 0;  // spin block inside a staged Cholesky vector
   int idx[16];
-  cd mm[15];
-  cd acc[8];
+  CT mm[15];
+  CT acc[8];
 #pragma unroll
   for (int j = 0; j < 16; ++j) idx[j] = 0;
 #pragma unroll
-  for (int j = 0; j < 15; ++j) mm[j] = cd{0.0, 0.0};
+  for (int j = 0; j < 15; ++j) mm[j] = CT{};
 #pragma unroll
-  for (int j = 0; j < 8; ++j) acc[j] = cd{0.0, 0.0};
+  for (int j = 0; j < 8; ++j) acc[j] = CT{};
   const int item = role == ER_PAIRS ? pl.z + lane * 8 : pl.z + lane;
   const bool live = role != ER_NONE && item < pl.w;
   int str = 0;
@@ -1280,15 +1311,15 @@ __global__ __launch_bounds__(512) void k_energy_second(
       const cd* m2s = (sp ? m2b + (size_t)w * sb.M2 + sb.m2_off[str]
                           : m2a + (size_t)w * sa.M2 + sa.m2_off[str]);
       switch (K) {
-        case 2: rp_setup<2>(hwin, pwin, no, str, rp, off, m2s, idx, mm); break;
-        case 3: rp_setup<3>(hwin, pwin, no, str, rp, off, m2s, idx, mm); break;
-        case 4: rp_setup<4>(hwin, pwin, no, str, rp, off, m2s, idx, mm); break;
-        case 5: rp_setup<5>(hwin, pwin, no, str, rp, off, m2s, idx, mm); break;
-        default: rp_setup<6>(hwin, pwin, no, str, rp, off, m2s, idx, mm); break;
+        case 2: rp_setup<2, CT>(hwin, pwin, no, str, rp, off, m2s, idx, mm); break;
+        case 3: rp_setup<3, CT>(hwin, pwin, no, str, rp, off, m2s, idx, mm); break;
+        case 4: rp_setup<4, CT>(hwin, pwin, no, str, rp, off, m2s, idx, mm); break;
+        case 5: rp_setup<5, CT>(hwin, pwin, no, str, rp, off, m2s, idx, mm); break;
+        default: rp_setup<6, CT>(hwin, pwin, no, str, rp, off, m2s, idx, mm); break;
       }
     }
   }
-  auto stage = [&](int gb, cd* dst) {
+  auto stage = [&](int gb, CT* dst) {
     const int Gs = min(G, g1 - gb);
     for (int e = tid; e < Gs * X; e += blockDim.x) {
       const int gl = e / X, x = e % X;
@@ -1301,22 +1332,22 @@ __global__ __launch_bounds__(512) void k_energy_second(
   int it = 0;
   for (int gb = g0; gb < g1; gb += G, ++it) {
     if (gb + G < g1) stage(gb + G, buf[(it + 1) & 1]);
-    const cd* L = buf[it & 1];
+    const CT* L = buf[it & 1];
     const int Gs = min(G, g1 - gb);
     if (live) {
       for (int gl = 0; gl < Gs; ++gl) {
-        const cd* Lg = L + gl * X;
+        const CT* Lg = L + gl * X;
         switch (role) {
           case ER_PAIRS:
 #pragma unroll
             for (int j = 0; j < 8; ++j)
               if (idx[j] >= 0) cfma(acc[j], Lg[idx[j]], Lg[idx[8 + j]]);
             break;
-          case 2: rp_eval<2>(Lg, idx, mm, acc[0]); break;
-          case 3: rp_eval<3>(Lg, idx, mm, acc[0]); break;
-          case 4: rp_eval<4>(Lg, idx, mm, acc[0]); break;
-          case 5: rp_eval<5>(Lg, idx, mm, acc[0]); break;
-          default: rp_eval<6>(Lg, idx, mm, acc[0]); break;
+          case 2: rp_eval<2, CT>(Lg, idx, mm, acc[0]); break;
+          case 3: rp_eval<3, CT>(Lg, idx, mm, acc[0]); break;
+          case 4: rp_eval<4, CT>(Lg, idx, mm, acc[0]); break;
+          case 5: rp_eval<5, CT>(Lg, idx, mm, acc[0]); break;
+          default: rp_eval<6, CT>(Lg, idx, mm, acc[0]); break;
         }
       }
     }
@@ -1327,9 +1358,9 @@ __global__ __launch_bounds__(512) void k_energy_second(
     if (role == ER_PAIRS) {
 #pragma unroll
       for (int j = 0; j < 8; ++j)
-        if (idx[j] >= 0) cfma(tot, coef[(size_t)w * pr.n_pair + item + j], acc[j]);
+        if (idx[j] >= 0) cfma(tot, coef[(size_t)w * pr.n_pair + item + j], to_cd(acc[j]));
     } else {
-      tot = (sp ? Bb[(size_t)w * sb.U + str] : Ba[(size_t)w * sa.U + str]) * acc[0];
+      tot = (sp ? Bb[(size_t)w * sb.U + str] : Ba[(size_t)w * sa.U + str]) * to_cd(acc[0]);
     }
   }
   tot = wave_sum(tot);
@@ -1342,16 +1373,40 @@ __global__ __launch_bounds__(512) void k_energy_second(
   }
 }
 
+template <class CT>
+static void launch_energy_second_t(const DevSpin& sa, const DevSpin& sb, const DevPairs& pr,
+                                   const int4* plan, int n_itemblocks, int waves_per_block, int NW,
+                                   int w0, int WT, int NG, int n_gsplit, int G, const CT* Lam_a,
+                                   const CT* Lam_b, const cd* coef, const cd* m2a, const cd* m2b,
+                                   const cd* Ba, const cd* Bb, cd* partial, int n_slots, int slot0,
+                                   hipStream_t st) {
+  if (n_itemblocks == 0) return;
+  const size_t lds = 2 * (size_t)G * (sa.nv * sa.no + sb.nv * sb.no) * sizeof(CT);
+  hipLaunchKernelGGL((k_energy_second<CT>), dim3(WT * n_gsplit * n_itemblocks, 1),
+                     dim3(64 * waves_per_block), lds, st, sa, sb, pr, plan, n_itemblocks,
+                     waves_per_block, NW, w0, NG, n_gsplit, G, Lam_a, Lam_b, coef, m2a, m2b, Ba,
+                     Bb, partial, n_slots, slot0);
+}
+
 void launch_energy_second(const DevSpin& sa, const DevSpin& sb, const DevPairs& pr,
                           const int4* plan, int n_itemblocks, int waves_per_block, int NW, int w0,
                           int WT, int NG, int n_gsplit, int G, const cd* Lam_a, const cd* Lam_b,
                           const cd* coef, const cd* m2a, const cd* m2b, const cd* Ba,
                           const cd* Bb, cd* partial, int n_slots, int slot0, hipStream_t st) {
-  if (n_itemblocks == 0) return;
-  const size_t lds = 2 * (size_t)G * (sa.nv * sa.no + sb.nv * sb.no) * sizeof(cd);
-  hipLaunchKernelGGL(k_energy_second, dim3(WT * n_gsplit * n_itemblocks, 1), dim3(64 * waves_per_block),
-                     lds, st, sa, sb, pr, plan, n_itemblocks, waves_per_block, NW, w0, NG, n_gsplit, G, Lam_a,
-                     Lam_b, coef, m2a, m2b, Ba, Bb, partial, n_slots, slot0);
+  launch_energy_second_t<cd>(sa, sb, pr, plan, n_itemblocks, waves_per_block, NW, w0, WT, NG,
+                             n_gsplit, G, Lam_a, Lam_b, coef, m2a, m2b, Ba, Bb, partial, n_slots,
+                             slot0, st);
+}
+
+void launch_energy_second32(const DevSpin& sa, const DevSpin& sb, const DevPairs& pr,
+                            const int4* plan, int n_itemblocks, int waves_per_block, int NW,
+                            int w0, int WT, int NG, int n_gsplit, int G, const cf* Lam_a,
+                            const cf* Lam_b, const cd* coef, const cd* m2a, const cd* m2b,
+                            const cd* Ba, const cd* Bb, cd* partial, int n_slots, int slot0,
+                            hipStream_t st) {
+  launch_energy_second_t<cf>(sa, sb, pr, plan, n_itemblocks, waves_per_block, NW, w0, WT, NG,
+                             n_gsplit, G, Lam_a, Lam_b, coef, m2a, m2b, Ba, Bb, partial, n_slots,
+                             slot0, st);
 }
 
 int energy_pair_blocks(int n_pair) {
@@ -1481,7 +1536,8 @@ void init_wick_attributes() {
   hipFuncSetAttribute((const void*)k_green, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   hipFuncSetAttribute((const void*)k_lambda, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   hipFuncSetAttribute((const void*)k_energy_pairs, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-  hipFuncSetAttribute((const void*)k_energy_second, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  hipFuncSetAttribute((const void*)k_energy_second<cd>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  hipFuncSetAttribute((const void*)k_energy_second<cf>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   hipFuncSetAttribute((const void*)k_energy_minors, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   hipFuncSetAttribute((const void*)k_energy_strings<2>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   hipFuncSetAttribute((const void*)k_energy_strings<3>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);

@@ -408,3 +408,70 @@ def test_graph_replay_matches_eager():
         ma, mb = eager.measure(dt, energy=k % 2 == 0), graph.measure(dt, energy=k % 2 == 0)
         for key in ma:
             np.testing.assert_array_equal(ma[key], mb[key])
+
+
+# ----------------------------------------------------------------------------
+# mixed-precision form
+# ----------------------------------------------------------------------------
+
+MIXED_E_TOL = 1e-4  # Ha: the mixed form's per-walker local-energy bound (0.1 mHa)
+
+
+def test_mixed_medium_full_batch_against_fp64():
+    """Mixed form on the Medium system: every walker's local energy within
+    0.1 mHa of the FP64 path, force biases within FP32 rounding, and the FP64
+    parts (overlaps, Green's functions) unchanged."""
+    wl = make_config("medium")
+    ref = system_for(wl).measure(wl.dt)
+    s = system_for(wl, precision="mixed")
+    out = s.measure(wl.dt)
+    np.testing.assert_array_equal(out["log_ovlp"], ref["log_ovlp"])
+    de = np.abs(out["e_loc"] - ref["e_loc"])
+    assert de.max() <= MIXED_E_TOL, de.max()
+    assert_rel(out["force_bias"], ref["force_bias"], tol=1e-5, floor=0.0)
+    # and against the oracle on two walkers
+    for w in (0, 77):
+        o = oracle_walker(wl, w, wl.dt)
+        assert abs(out["e_loc"][w] - o["e_loc"]) <= MIXED_E_TOL
+
+
+@pytest.mark.parametrize("kmax,na,nb", [(6, 5, 4), (3, 3, 0)])
+def test_mixed_high_orders_against_oracle(kmax, na, nb):
+    wl = make_workload("mixed", M=20, n_alpha=na, n_beta=nb, n_chol=24, n_det=60, k_max=kmax,
+                       window=(min(na, 4), 9), c_law="flat", n_walkers=4, seed=131 + kmax,
+                       complex_ci=True, noise=0.4)
+    s = system_for(wl, precision="mixed")
+    out = s.measure(0.01)
+    for w in range(4):
+        o = oracle_walker(wl, w, 0.01)
+        assert_logo(out["log_ovlp"][w], o["log_ovlp"])
+        assert abs(out["e_loc"][w] - o["e_loc"]) <= MIXED_E_TOL
+        assert_rel(out["force_bias"][w], o["force_bias"], tol=1e-5, floor=0.0)
+
+
+def test_mixed_orders_above_six_use_fp64_energy():
+    """Alpha excitations up to order 8: the mixed form keeps the FP64 energy."""
+    wl = make_workload("mixed8", M=20, n_alpha=8, n_beta=5, n_chol=20, n_det=60, k_max=12,
+                       window=(8, 10), c_law="flat", n_walkers=3, seed=83, complex_ci=True,
+                       noise=0.5)
+    a = system_for(wl).measure(0.01)
+    b = system_for(wl, precision="mixed").measure(0.01)
+    np.testing.assert_array_equal(a["e_loc"], b["e_loc"])
+    o = oracle_walker(wl, 1, 0.01)
+    assert_rel(a["e_loc"][1], o["e_loc"])
+
+
+def test_mixed_propagation_two_steps_close_to_fp64():
+    """Two steps with FP32 VHS and force bias stay close to the FP64 steps
+    (trajectories of the two forms drift apart slowly; only short runs are
+    compared)."""
+    wl = make_config("medium", n_walkers=16, n_det=200)
+    a, b = system_for(wl), system_for(wl, precision="mixed")
+    for k in range(2):
+        x = fields_for_step(wl, k)
+        a.propagate(x, wl.dt)
+        b.propagate(x, wl.dt)
+    pa, pb = a.get_walkers(), b.get_walkers()
+    for u, v in zip(pa[:2], pb[:2]):
+        assert np.max(np.abs(u - v)) <= 1e-5 * np.max(np.abs(u))
+    assert np.max(np.abs(pa[2] - pb[2]) / np.maximum(pa[2], 1e-300)) <= 1e-4
