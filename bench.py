@@ -124,10 +124,10 @@ def main():
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
 
-    def system(timing):
+    def system(timing, precision="fp64"):
         s = MsdSystem(wl.M, wl.n_alpha, wl.n_beta, wl.n_chol, wl.n_walkers, wl.n_det, device=0,
                       stream=stream.cuda_stream, stabilize_freq=1, timing=timing,
-                      graphs=not timing)
+                      graphs=not timing, precision=precision)
         s.set_hamiltonian(wl.h1, wl.chol, wl.e0)
         s.set_trial(wl.ci, wl.occ_a, wl.occ_b)
         s.set_walkers(wl.phi_a, wl.phi_b, wl.weights)
@@ -155,22 +155,41 @@ def main():
         torch.cuda.synchronize()
         return e0.elapsed_time(e1), time.perf_counter() - t0
 
-    # main timed region: every step replayed from HIP graphs
-    s = system(False)
-    for k in range(args.warmup):
-        step(s, k)
-    ms, wall = timed(s, lambda k: step(s, args.warmup + k), args.steps)
-    ms_step = ms / args.steps
+    def run_form(precision):
+        """Graph-replayed steps and measurements of one form; also returns the
+        local energies of the initial walkers (same input for both forms)."""
+        s = system(False, precision)
+        e_init = s.measure(wl.dt)["e_loc"]
+        for k in range(args.warmup):
+            step(s, k)
+        ms, wall = timed(s, lambda k: step(s, args.warmup + k), args.steps)
+        ms_meas, _ = timed(s, lambda k: s.measure_dev(wl.dt, lo, fb, el), args.steps)
+        s.close()
+        return ms / args.steps, ms_meas / args.steps, wall, e_init
+
+    ms_step, ms_meas, wall, e64 = run_form("fp64")
     value = wl.n_walkers * wl.n_det / (ms_step * 1e-3)
-    ms_meas, _ = timed(s, lambda k: s.measure_dev(wl.dt, lo, fb, el), args.steps)
-    meas_value = wl.n_walkers * wl.n_det / (ms_meas / args.steps * 1e-3)
-    # instrumented pass of the same steps: HIP events around every stage
-    s = system(True)
-    for k in range(args.warmup):
-        step(s, k)
-    torch.cuda.synchronize()
-    s.reset_timings()
-    timed(s, lambda k: step(s, args.warmup + k), args.steps)
+    meas_value = wl.n_walkers * wl.n_det / (ms_meas * 1e-3)
+    mx_step, mx_meas, _, emx = run_form("mixed")
+    mixed = {"value": wl.n_walkers * wl.n_det / (mx_step * 1e-3), "ms_per_step": round(mx_step, 4),
+             "measure_only_value": wl.n_walkers * wl.n_det / (mx_meas * 1e-3),
+             "measure_only_ms": round(mx_meas, 4),
+             "speedup_vs_fp64": round(ms_step / mx_step, 3),
+             "max_abs_dE_L_mHa": float(np.max(np.abs(emx - e64))) * 1e3,
+             "error_sample": f"all {wl.n_walkers} walkers, one measurement of the initial walkers"}
+    # instrumented passes of the same steps: HIP events around every stage
+    def stage_pass(precision):
+        s = system(True, precision)
+        for k in range(args.warmup):
+            step(s, k)
+        torch.cuda.synchronize()
+        s.reset_timings()
+        timed(s, lambda k: step(s, args.warmup + k), args.steps)
+        return s
+    sm = stage_pass("mixed")
+    mixed["stages_ms"] = {k: round(v[0] / max(v[1], 1), 4) for k, v in sm.timings().items() if v[1]}
+    sm.close()
+    s = stage_pass("fp64")
     stages = s.timings()
     dom = max((k for k in stages if stages[k][1] > 0), key=lambda k: stages[k][0])
     roof = None
@@ -213,8 +232,9 @@ def main():
         "dominant_stage": dom,
         "stages_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in stages.items() if v[1]},
         "wall_s": round(wall, 3),
-        "measure_only": {"value": meas_value, "ms": round(ms_meas / args.steps, 4),
+        "measure_only": {"value": meas_value, "ms": round(ms_meas, 4),
                          "note": "msd_measure_dev alone (overlap, G, force bias, E_L)"},
+        "mixed": mixed,
         "stage_timing_note": "stages_ms and roofline from a second pass of the same steps with "
                              "HIP events around every stage (no graphs)",
     }

@@ -202,6 +202,33 @@ msd_status msd_get_timings(msd_system* sys, int32_t max_stages, const char** nam
                            double* ms, int64_t* counts, int32_t* n_stages);
 msd_status msd_reset_timings(msd_system* sys);
 
+/* Results of the most recent measurement (msd_measure[_dev] or a measuring
+ * msd_batch_step) copied to host buffers; any pointer may be NULL.  Layouts as
+ * in msd_measure.  Synchronises the handle's stream. */
+msd_status msd_get_measurement(msd_system* sys, double* log_ovlp, double* force_bias,
+                               double* e_loc);
+
+/* Batches of independent systems (walker sets, trials and Hamiltonians of
+ * uneven sizes) stepped together: each msd_batch_step enqueues, for every
+ * system, one propagation step (as msd_propagate_dev with n_steps = 1) and,
+ * if do_measure, one measurement (as msd_measure_dev with energies), all on
+ * the batch's stream.  With timing off on every system the whole step is
+ * recorded once as one HIP graph (per combination of QR steps, measurement
+ * flag, dt and e_shift) and replayed afterwards; graphs are re-recorded after
+ * any system's trial or Hamiltonian changes.  The systems must be on one
+ * device and stay alive until msd_batch_destroy; they may still be used on
+ * their own between batch steps (the batch orders itself against each
+ * system's stream with events).  A batch is not thread-safe.
+ * fields[i]: device pointer, n_walkers_i * n_chol_i standard-normal fields of
+ * system i, [w][g].  No singularity check is made (see msd_measure_dev); read
+ * results with msd_get_walkers / msd_get_weights / msd_get_measurement. */
+typedef struct msd_batch msd_batch;
+msd_status msd_batch_create(msd_system* const* systems, int32_t n, void* hip_stream,
+                            msd_batch** out);
+void msd_batch_destroy(msd_batch* b);
+msd_status msd_batch_step(msd_batch* b, const double* const* fields, double dt, double e_shift,
+                          int32_t do_measure);
+
 /* Host-only excitation analysis of a trial (no device needed), for checking
  * the trial builder (excitations relative to the reference, Sec. II.B).  Per determinant: k_a/k_b = holes per spin, sign = the
  * product of both spins' excitation signs (+1/-1; the sign of the permutation

@@ -54,6 +54,10 @@ SIGNATURES = {
     "msd_get_timings": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_char_p), _dp,
                                   C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
     "msd_reset_timings": (C.c_int, [_vp]),
+    "msd_get_measurement": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "msd_batch_create": (C.c_int, [C.POINTER(_vp), C.c_int32, _vp, C.POINTER(_vp)]),
+    "msd_batch_destroy": (None, [_vp]),
+    "msd_batch_step": (C.c_int, [_vp, C.POINTER(_vp), C.c_double, C.c_double, C.c_int32]),
     "msd_trial_analyze": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int64, _vp, _vp, _vp,
                                     _vp, _vp]),
 }

@@ -164,6 +164,17 @@ class MsdSystem:
         self._check(self.lib.msd_get_green(self.h, int(walker), _ptr(ga), _ptr(gb)))
         return ga, gb
 
+    def get_measurement(self, force_bias: bool = True):
+        """Host copies of the most recent measurement."""
+        lo = np.empty(self.nw, np.complex128)
+        fb = np.empty((self.nw, self.ng), np.complex128) if force_bias else None
+        el = np.empty(self.nw, np.complex128)
+        self._check(self.lib.msd_get_measurement(self.h, _ptr(lo), _ptr(fb), _ptr(el)))
+        out = dict(log_ovlp=lo, e_loc=el)
+        if force_bias:
+            out["force_bias"] = fb
+        return out
+
     def timings(self):
         n = 64
         names = (C.c_char_p * n)()
@@ -175,6 +186,42 @@ class MsdSystem:
 
     def reset_timings(self):
         self._check(self.lib.msd_reset_timings(self.h))
+
+
+class MsdBatch:
+    """Several MsdSystem handles stepped together, one HIP graph per step
+    (see msd_batch_step)."""
+
+    def __init__(self, systems, stream: Optional[int] = None):
+        self.lib = _lib.load()
+        self.systems = list(systems)  # keeps the handles alive
+        arr = (C.c_void_p * len(self.systems))(*[s.h.value for s in self.systems])
+        h = C.c_void_p()
+        st = self.lib.msd_batch_create(arr, len(self.systems),
+                                       C.c_void_p(stream) if stream else None, C.byref(h))
+        if st != 0:
+            raise MsdError(st, (self.lib.msd_last_error(None) or b"").decode())
+        self.h = h
+
+    def step(self, fields, dt: float, e_shift: float = 0.0, measure: bool = True):
+        """fields: one device array per system ([n_walkers][n_chol] float64)."""
+        if len(fields) != len(self.systems):
+            raise ValueError("one field array per system")
+        arr = (C.c_void_p * len(fields))(*[f.data_ptr() for f in fields])
+        st = self.lib.msd_batch_step(self.h, arr, float(dt), float(e_shift), 1 if measure else 0)
+        if st != 0:
+            raise MsdError(st, (self.lib.msd_last_error(None) or b"").decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.msd_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def trial_analyze(M: int, occ_a, occ_b):

@@ -13,7 +13,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -180,7 +182,9 @@ struct msd_system {
   hipStream_t cap_st = nullptr;
   GraphSlot g_step[2];     // [QR in this step]
   GraphSlot g_measure[2];  // [energy requested]
+  uint64_t version = 0;  // bumped whenever captured graphs become stale
   void drop_graphs() {
+    ++version;
     for (GraphSlot* g : {&g_step[0], &g_step[1], &g_measure[0], &g_measure[1]}) {
       if (g->exec) (void)hipGraphExecDestroy(g->exec);
       g->exec = nullptr;
@@ -688,18 +692,21 @@ void run_energy(msd_system* s) {
   s->check_launch("energy");
 }
 
+// The measurement kernels (A1-A7) into logo_tmp, xbar, eloc.
+void measure_body(msd_system* s, double dt, bool want_e) {
+  clear_flags(s);
+  run_overlap(s, want_e, s->logo_tmp);
+  run_green_fb(s, dt);
+  if (want_e) run_energy(s);
+}
+
 void measure_impl(msd_system* s, double dt, bool want_e) {
   need_ready(s);
   if (!s->have_walkers) fail(MSD_ERR_STATE, "walkers have not been set");
   if (!(dt >= 0.0) || !std::isfinite(dt)) fail(MSD_ERR_ARG, "dt must be finite and >= 0");
   if (want_e && s->tt.max_k() > msd::KMAX) fail(MSD_ERR_UNSUPPORTED, "excitation order too high");
   if (want_e) alloc_energy(s);
-  run_or_replay(s, s->g_measure[want_e ? 1 : 0], dt, 0.0, [&] {
-    clear_flags(s);
-    run_overlap(s, want_e, s->logo_tmp);
-    run_green_fb(s, dt);
-    if (want_e) run_energy(s);
-  });
+  run_or_replay(s, s->g_measure[want_e ? 1 : 0], dt, 0.0, [&] { measure_body(s, dt, want_e); });
 }
 
 void ensure_b1(msd_system* s, double dt) {
@@ -1480,3 +1487,172 @@ msd_status msd_trial_analyze(int32_t M, int32_t n_alpha, int32_t n_beta, int64_t
 }
 
 }  // extern "C"
+
+// ============================================================================
+// Batches of independent systems: one graph per step for all of them
+// ============================================================================
+
+struct msd_batch {
+  int dev = 0;
+  hipStream_t st = nullptr;
+  hipStream_t cap_st = nullptr;
+  hipEvent_t ev = nullptr;
+  std::vector<msd_system*> sys;
+  struct Entry {
+    std::vector<uint64_t> versions;
+    hipGraphExec_t exec = nullptr;
+  };
+  std::map<std::string, Entry> graphs;  // key: QR flags, measure flag, dt, e_shift
+  void drop() {
+    for (auto& kv : graphs)
+      if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    graphs.clear();
+  }
+};
+
+msd_status msd_batch_create(msd_system* const* systems, int32_t n, void* hip_stream,
+                            msd_batch** out) {
+  msd_batch* b = nullptr;
+  API_BEGIN
+  if (!systems || !out || n <= 0) fail(MSD_ERR_ARG, "null argument or empty batch");
+  *out = nullptr;
+  for (int i = 0; i < n; ++i) {
+    if (!systems[i]) fail(MSD_ERR_ARG, "system " + std::to_string(i) + " is null");
+    if (systems[i]->dev != systems[0]->dev)
+      fail(MSD_ERR_ARG, "system " + std::to_string(i) + " is on another device");
+    for (int j = 0; j < i; ++j)
+      if (systems[j] == systems[i]) fail(MSD_ERR_ARG, "system " + std::to_string(i) + " repeated");
+  }
+  b = new msd_batch();
+  b->dev = systems[0]->dev;
+  b->st = static_cast<hipStream_t>(hip_stream);
+  b->sys.assign(systems, systems + n);
+  try {
+    hip_check(hipSetDevice(b->dev), "hipSetDevice");
+    hip_check(hipStreamCreateWithFlags(&b->cap_st, hipStreamNonBlocking), "stream");
+    hip_check(hipEventCreateWithFlags(&b->ev, hipEventDisableTiming), "event");
+  } catch (...) {
+    if (b->cap_st) (void)hipStreamDestroy(b->cap_st);
+    delete b;
+    b = nullptr;
+    throw;
+  }
+  *out = b;
+  API_END(static_cast<msd_system*>(nullptr))
+}
+
+void msd_batch_destroy(msd_batch* b) {
+  if (!b) return;
+  (void)hipSetDevice(b->dev);
+  (void)hipStreamSynchronize(b->st);
+  b->drop();
+  if (b->cap_st) (void)hipStreamDestroy(b->cap_st);
+  if (b->ev) (void)hipEventDestroy(b->ev);
+  delete b;
+}
+
+msd_status msd_batch_step(msd_batch* b, const double* const* fields, double dt, double e_shift,
+                          int32_t do_measure) {
+  API_BEGIN
+  if (!b || !fields) fail(MSD_ERR_ARG, "null argument");
+  hip_check(hipSetDevice(b->dev), "hipSetDevice");
+  if (!(dt > 0.0) || !std::isfinite(dt)) fail(MSD_ERR_ARG, "dt must be finite and > 0");
+  if (!std::isfinite(e_shift)) fail(MSD_ERR_ARG, "e_shift must be finite");
+  const int n = (int)b->sys.size();
+  bool timing = false;
+  for (int i = 0; i < n; ++i) {
+    msd_system* s = b->sys[i];
+    const std::string who = "system " + std::to_string(i) + ": ";
+    if (!fields[i]) fail(MSD_ERR_ARG, who + "null fields");
+    try {
+      need_ready(s);
+      if (!s->have_walkers) fail(MSD_ERR_STATE, "walkers have not been set");
+      if (do_measure && s->tt.max_k() > msd::KMAX) fail(MSD_ERR_UNSUPPORTED, "excitation order too high");
+      ensure_b1(s, dt);
+      if (do_measure) alloc_energy(s);
+    } catch (const Error& e) {
+      throw Error{e.code, who + e.msg};
+    }
+    timing = timing || s->o.timing;
+  }
+  // order against work already queued on the systems' own streams
+  for (msd_system* s : b->sys) {
+    hip_check(hipEventRecord(b->ev, s->st), "record");
+    hip_check(hipStreamWaitEvent(b->st, b->ev, 0), "wait");
+  }
+  std::string key = do_measure ? "m" : "p";
+  std::vector<char> qr(n);
+  for (int i = 0; i < n; ++i) {
+    msd_system* s = b->sys[i];
+    s->steps_done++;
+    qr[i] = s->o.stabilize_freq > 0 && s->steps_done % s->o.stabilize_freq == 0;
+    key += qr[i] ? '1' : '0';
+    hip_check(hipMemcpyAsync(s->fields, fields[i], sizeof(double) * s->NW * s->NG,
+                             hipMemcpyDeviceToDevice, b->st),
+              "fields");
+  }
+  char buf[64];
+  std::snprintf(buf, sizeof buf, "|%.17g|%.17g", dt, e_shift);
+  key += buf;
+  auto body = [&](hipStream_t st) {
+    for (int i = 0; i < n; ++i) {
+      msd_system* s = b->sys[i];
+      hipStream_t own = s->st;
+      s->st = st;
+      try {
+        propagate_step(s, s->fields, dt, e_shift, qr[i]);
+        if (do_measure) measure_body(s, dt, true);
+      } catch (...) {
+        s->st = own;
+        throw;
+      }
+      s->st = own;
+    }
+  };
+  if (timing) {
+    body(b->st);  // timing events cannot live in a graph: run the launches directly
+  } else {
+    std::vector<uint64_t> versions(n);
+    for (int i = 0; i < n; ++i) versions[i] = b->sys[i]->version;
+    msd_batch::Entry& e = b->graphs[key];
+    if (e.exec && e.versions != versions) {
+      hip_check(hipGraphExecDestroy(e.exec), "hipGraphExecDestroy");
+      e.exec = nullptr;
+    }
+    if (!e.exec) {
+      hipGraph_t g = nullptr;
+      hip_check(hipStreamBeginCapture(b->cap_st, hipStreamCaptureModeThreadLocal), "begin capture");
+      try {
+        body(b->cap_st);
+      } catch (...) {
+        (void)hipStreamEndCapture(b->cap_st, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      hip_check(hipStreamEndCapture(b->cap_st, &g), "end capture");
+      hipError_t err = hipGraphInstantiate(&e.exec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      hip_check(err, "hipGraphInstantiate");
+      e.versions = versions;
+    }
+    hip_check(hipGraphLaunch(e.exec, b->st), "hipGraphLaunch");
+  }
+  // later work on each system's stream sees this step
+  hip_check(hipEventRecord(b->ev, b->st), "record");
+  for (msd_system* s : b->sys) hip_check(hipStreamWaitEvent(s->st, b->ev, 0), "wait");
+  hip_check(hipGetLastError(), "batch step");
+  API_END(static_cast<msd_system*>(nullptr))
+}
+
+msd_status msd_get_measurement(msd_system* sys, double* log_ovlp, double* force_bias,
+                               double* e_loc) {
+  API_BEGIN
+  if (!sys) fail(MSD_ERR_ARG, "null argument");
+  if (!sys->have_walkers) fail(MSD_ERR_STATE, "walkers have not been set");
+  set_device(sys);
+  copy_out(sys, log_ovlp, sys->logo_tmp, sizeof(cd) * sys->NW);
+  copy_out(sys, force_bias, sys->xbar, sizeof(cd) * sys->NW * sys->NG);
+  copy_out(sys, e_loc, sys->eloc, sizeof(cd) * sys->NW);
+  sys->sync();
+  API_END(sys)
+}

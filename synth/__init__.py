@@ -9,4 +9,5 @@ from .gen import (  # noqa: F401
     make_workload,
     make_config,
     fields_for_step,
+    make_uneven,
 )

@@ -215,3 +215,26 @@ def fields_for_step(wl: Workload, step: int) -> np.ndarray:
     """Auxiliary fields x ~ N(0,1), shape (n_walkers, n_chol), for one step."""
     rng = np.random.default_rng(wl.seed + 1000 + step)
     return rng.standard_normal((wl.n_walkers, wl.n_chol))
+
+
+def make_uneven(n_systems: int = 32, M_range=(32, 200), N_max: int = 30,
+                n_det_range=(100, 100_000), walker_range=(64, 512),
+                seed: int = BASE_SEED + 4) -> list:
+    """A batch of independent systems of uneven size: M uniform in M_range,
+    N_alpha = N_beta uniform in [4, min(N_max, M/2)], n_chol = 5 M, n_det
+    log-uniform in n_det_range with total excitation order <= 4, window
+    min(N, 16) x min(M - N, 32), |c| ~ (1 + rank)^-1, walkers uniform in
+    walker_range.  System i is drawn with seed + 1 + i."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n_systems):
+        M = int(rng.integers(M_range[0], M_range[1] + 1))
+        N = int(rng.integers(min(4, M // 2), min(N_max, M // 2) + 1))
+        lo, hi = np.log(n_det_range[0]), np.log(n_det_range[1])
+        nd = int(round(np.exp(rng.uniform(lo, hi))))
+        nw = int(rng.integers(walker_range[0], walker_range[1] + 1))
+        window = (min(N, 16), min(M - N, 32))
+        out.append(make_workload(name=f"uneven{i}", M=M, n_alpha=N, n_beta=N, n_chol=5 * M,
+                                 n_det=nd, k_max=4, window=window, c_law="power1",
+                                 n_walkers=nw, seed=seed + 1 + i))
+    return out

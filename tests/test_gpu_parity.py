@@ -475,3 +475,45 @@ def test_mixed_propagation_two_steps_close_to_fp64():
     for u, v in zip(pa[:2], pb[:2]):
         assert np.max(np.abs(u - v)) <= 1e-5 * np.max(np.abs(u))
     assert np.max(np.abs(pa[2] - pb[2]) / np.maximum(pa[2], 1e-300)) <= 1e-4
+
+
+# ----------------------------------------------------------------------------
+# batches of uneven systems
+# ----------------------------------------------------------------------------
+
+def test_uneven_batch_graph_matches_separate_systems():
+    """Four systems of different M, N, n_chol, n_det and walker counts stepped
+    by one graph per batch step equal the same systems stepped one by one."""
+    torch = pytest.importorskip("torch")
+    from paper_2406_08314_amd import MsdBatch
+    from synth import make_uneven
+
+    wls = make_uneven(4, M_range=(12, 40), N_max=8, n_det_range=(20, 300),
+                      walker_range=(4, 16))
+    dev = torch.device("cuda:0")
+
+    def make(wl):
+        s = MsdSystem(wl.M, wl.n_alpha, wl.n_beta, wl.n_chol, wl.n_walkers, wl.n_det,
+                      stabilize_freq=2)
+        s.set_hamiltonian(wl.h1, wl.chol, wl.e0)
+        s.set_trial(wl.ci, wl.occ_a, wl.occ_b)
+        s.set_walkers(wl.phi_a, wl.phi_b, wl.weights)
+        return s
+
+    solo = [make(wl) for wl in wls]
+    batched = [make(wl) for wl in wls]
+    batch = MsdBatch(batched)
+    for k in range(4):
+        xs = [torch.from_numpy(fields_for_step(wl, k)).to(dev) for wl in wls]
+        batch.step(xs, 0.01, 0.05, measure=True)
+        for s, wl, x in zip(solo, wls, xs):
+            s.propagate(x.cpu().numpy(), 0.01, 0.05)
+        torch.cuda.synchronize()
+        for s, b in zip(solo, batched):
+            m = s.measure(0.01)
+            mb = b.get_measurement()
+            for key in ("log_ovlp", "force_bias", "e_loc"):
+                np.testing.assert_array_equal(m[key], mb[key])
+            for u, v in zip(s.get_walkers(), b.get_walkers()):
+                np.testing.assert_array_equal(u, v)
+    batch.close()
