@@ -160,6 +160,7 @@ def main():
         local energies of the initial walkers (same input for both forms)."""
         s = system(False, precision)
         e_init = s.measure(wl.dt)["e_loc"]
+        tunings[precision] = s.autotune(wl.dt, reps=3)
         for k in range(args.warmup):
             step(s, k)
         ms, wall = timed(s, lambda k: step(s, args.warmup + k), args.steps)
@@ -167,6 +168,7 @@ def main():
         s.close()
         return ms / args.steps, ms_meas / args.steps, wall, e_init
 
+    tunings = {}
     ms_step, ms_meas, wall, e64 = run_form("fp64")
     value = wl.n_walkers * wl.n_det / (ms_step * 1e-3)
     meas_value = wl.n_walkers * wl.n_det / (ms_meas * 1e-3)
@@ -180,6 +182,7 @@ def main():
     # instrumented passes of the same steps: HIP events around every stage
     def stage_pass(precision):
         s = system(True, precision)
+        s.set_tuning(**tunings[precision])
         for k in range(args.warmup):
             step(s, k)
         torch.cuda.synchronize()
@@ -235,6 +238,7 @@ def main():
         "measure_only": {"value": meas_value, "ms": round(ms_meas, 4),
                          "note": "msd_measure_dev alone (overlap, G, force bias, E_L)"},
         "mixed": mixed,
+        "tuning": tunings,
         "stage_timing_note": "stages_ms and roofline from a second pass of the same steps with "
                              "HIP events around every stage (no graphs)",
     }

@@ -202,6 +202,31 @@ msd_status msd_get_timings(msd_system* sys, int32_t max_stages, const char** nam
                            double* ms, int64_t* counts, int32_t* n_stages);
 msd_status msd_reset_timings(msd_system* sys);
 
+/* Launch-shape tuning of one handle.  Every field 0 = the library's choice;
+ * msd_get_tuning reports the values in use (after the first measurement with
+ * energies, when the energy plan exists).  Changing them never changes
+ * results beyond floating-point summation order. */
+typedef struct {
+  int32_t fb_splitk;      /* K slices of the force-bias GEMM (1..16)                      */
+  int32_t lambda_variant; /* energy intermediates: 1 = two-wave rows kernel,
+                             2 = one-wave pipelined kernel (N <= 16)                       */
+  int32_t lambda_chunk;   /* Cholesky vectors per intermediates workgroup (1..NG)         */
+  int32_t second_gsplit;  /* Cholesky-range split of the second-order kernel (1..64)      */
+  int32_t second_stage;   /* Cholesky vectors per LDS stage of the second-order kernel
+                             (1..32, bounded by 150 KB of LDS)                             */
+  int32_t reserved[3];
+} msd_tuning;
+msd_status msd_get_tuning(msd_system* sys, msd_tuning* out);
+/* Sets overrides (validated; MSD_ERR_ARG names the bad field).  Drops the
+ * energy plan and recorded graphs; they are rebuilt on the next call. */
+msd_status msd_set_tuning(msd_system* sys, const msd_tuning* t);
+/* Autotuner: times candidate values of each field in turn (fb_splitk,
+ * lambda_variant, lambda_chunk, second_gsplit, second_stage) over `reps`
+ * measurements with energies of the current walkers (time step dt), keeps the
+ * fastest and leaves it set (*out, if not NULL, receives it).  Overwrites the
+ * last-measurement buffers; walkers are unchanged.  Needs walkers. */
+msd_status msd_autotune(msd_system* sys, double dt, int32_t reps, msd_tuning* out);
+
 /* Results of the most recent measurement (msd_measure[_dev] or a measuring
  * msd_batch_step) copied to host buffers; any pointer may be NULL.  Layouts as
  * in msd_measure.  Synchronises the handle's stream. */

@@ -21,6 +21,12 @@ class MsdDims(C.Structure):
                 ("n_det", C.c_int64)]
 
 
+class MsdTuning(C.Structure):
+    _fields_ = [("fb_splitk", C.c_int32), ("lambda_variant", C.c_int32),
+                ("lambda_chunk", C.c_int32), ("second_gsplit", C.c_int32),
+                ("second_stage", C.c_int32), ("reserved", C.c_int32 * 3)]
+
+
 class MsdOptions(C.Structure):
     _fields_ = [("n_taylor", C.c_int32), ("stabilize_freq", C.c_int32), ("timing", C.c_int32),
                 ("energy_algo", C.c_int32), ("graphs", C.c_int32), ("precision", C.c_int32),
@@ -55,6 +61,9 @@ SIGNATURES = {
                                   C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
     "msd_reset_timings": (C.c_int, [_vp]),
     "msd_get_measurement": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "msd_get_tuning": (C.c_int, [_vp, C.POINTER(MsdTuning)]),
+    "msd_set_tuning": (C.c_int, [_vp, C.POINTER(MsdTuning)]),
+    "msd_autotune": (C.c_int, [_vp, C.c_double, C.c_int32, C.POINTER(MsdTuning)]),
     "msd_batch_create": (C.c_int, [C.POINTER(_vp), C.c_int32, _vp, C.POINTER(_vp)]),
     "msd_batch_destroy": (None, [_vp]),
     "msd_batch_step": (C.c_int, [_vp, C.POINTER(_vp), C.c_double, C.c_double, C.c_int32]),

@@ -175,6 +175,27 @@ class MsdSystem:
             out["force_bias"] = fb
         return out
 
+    _TUNING = ("fb_splitk", "lambda_variant", "lambda_chunk", "second_gsplit", "second_stage")
+
+    def get_tuning(self):
+        t = _lib.MsdTuning()
+        self._check(self.lib.msd_get_tuning(self.h, C.byref(t)))
+        return {k: getattr(t, k) for k in self._TUNING}
+
+    def set_tuning(self, **kw):
+        """Launch-shape overrides (0 = automatic); see msd_tuning."""
+        t = _lib.MsdTuning()
+        for k, v in kw.items():
+            if k not in self._TUNING:
+                raise ValueError(f"unknown tuning field {k}")
+            setattr(t, k, int(v))
+        self._check(self.lib.msd_set_tuning(self.h, C.byref(t)))
+
+    def autotune(self, dt: float, reps: int = 3):
+        t = _lib.MsdTuning()
+        self._check(self.lib.msd_autotune(self.h, float(dt), int(reps), C.byref(t)))
+        return {k: getattr(t, k) for k in self._TUNING}
+
     def timings(self):
         n = 64
         names = (C.c_char_p * n)()

@@ -129,7 +129,9 @@ struct msd_system {
   cd* onebody = nullptr;   // [2][NW]
   cd* segp[2] = {nullptr, nullptr};  // CI-weight segment partials
   double* fb_ws = nullptr;           // split-K workspace of the force-bias GEMM
-  int fb_splitk = 1;
+  int fb_splitk = 1, fb_splitk_auto = 1, fb_ws_cap = 0;
+  msd_tuning tune{};                 // launch-shape overrides (0 = automatic)
+  int lambda_variant = 1;            // resolved: 1 rows kernel, 2 one-wave kernel
 
   // mixed form: single-precision copies of the GEMM operands
   bool mixed = false;
@@ -154,7 +156,7 @@ struct msd_system {
   // the order, first item, item end), ER_WAVES entries per item block
   std::vector<int4> plan_host;
   int4* plan = nullptr;
-  int n_itemblocks = 0, slot_second = 0, second_G = 1;
+  int n_itemblocks = 0, slot_second = 0, second_G = 1, second_maxk = 0;
   cd* LT[2] = {nullptr, nullptr};
   cd* Lam[2] = {nullptr, nullptr};
   cd* v0 = nullptr;
@@ -338,7 +340,7 @@ void alloc_energy(msd_system* s) {
   const size_t budget = (size_t)16 << 30;
   int wt = (int)std::max<size_t>(1, std::min<size_t>(NW, budget / std::max<size_t>(per_w, 1)));
   s->WT = wt;
-  s->gl_chunk = 16;
+  s->gl_chunk = s->tune.lambda_chunk > 0 ? std::min(s->tune.lambda_chunk, NG) : 16;
   s->n_lchunks = (NG + s->gl_chunk - 1) / s->gl_chunk;
   int slot = 0;
   // Per spin: same-spin second-order terms as row-pair items of each string
@@ -347,8 +349,9 @@ void alloc_energy(msd_system* s) {
   // values and forms k(k-1)/2 products; a distinct minor gathers 4 and forms 2.
   std::vector<int4>& pl = s->plan_host;
   pl.clear();
+  s->second_maxk = 0;
   const int np = s->dp.n_pair;
-  for (int f = 0; f < np; f += 64 * 8) pl.push_back(int4{msd::ER_PAIRS, 0, f, np});
+  for (int f = 0; f < np; f += msd::ER_PAIRS_PER_WAVE) pl.push_back(int4{msd::ER_PAIRS, 0, f, np});
   for (int sp = 0; sp < 2; ++sp) {
     const msd::SpinTable& S = s->tt.s[sp];
     long c_str = 0;
@@ -366,6 +369,7 @@ void alloc_energy(msd_system* s) {
     if (big) strings = false;  // orders above ER_MAX_ORDER only in the minor-list form
     s->use_strings[sp] = strings;
     if (!strings) continue;
+    for (int i = 0; i < S.U; ++i) s->second_maxk = std::max(s->second_maxk, (int)S.k[i]);
     for (int k = 2; k <= msd::ER_MAX_ORDER; ++k) {
       const int n_items = (S.bucket[k + 1] - S.bucket[k]) * (k * (k - 1) / 2);
       for (int f = 0; f < n_items; f += 64) pl.push_back(int4{k | (sp << 8), S.bucket[k], f, n_items});
@@ -376,6 +380,7 @@ void alloc_energy(msd_system* s) {
   // split the Cholesky range so the second-order kernels have ~1024+ workgroups
   const int units = std::max(1, s->n_itemblocks);
   s->gsplit = std::max(1, std::min((1024 + wt * units - 1) / (wt * units), std::max(1, NG / 8)));
+  if (s->tune.second_gsplit > 0) s->gsplit = std::min(s->tune.second_gsplit, NG);
   s->slot_second = slot;
   slot += s->n_itemblocks * s->gsplit;
   for (int sp = 0; sp < 2; ++sp) {
@@ -385,11 +390,16 @@ void alloc_energy(msd_system* s) {
   }
   {
     int nmax = 0;
-    s->energy_mixed = s->mixed && s->use_strings[0] && s->use_strings[1] &&
-                      msd::lambda_rows_fits(A, B, &nmax);
+    const bool rows_fit = msd::lambda_rows_fits(A, B, &nmax);
+    s->energy_mixed = s->mixed && s->use_strings[0] && s->use_strings[1] && rows_fit;
     const int X = A.nv * A.no + B.nv * B.no;
     const int elem = s->energy_mixed ? 8 : 16;  // bytes per staged Lambda entry
-    s->second_G = std::max(1, std::min(32, (int)((64 << 10) / (2 * elem * std::max(X, 1)))));
+    s->second_G = std::max(1, std::min(32, (int)((72 << 10) / (2 * elem * std::max(X, 1)))));
+    if (s->tune.second_stage > 0)
+      s->second_G = std::max(1, std::min(s->tune.second_stage,
+                                         (int)((150 << 10) / (2 * elem * std::max(X, 1)))));
+    // 0: the generic one-wave kernel (windows beyond the row kernels' limits)
+    s->lambda_variant = !rows_fit ? 0 : (s->tune.lambda_variant == 1 || nmax > 16) ? 1 : 2;
   }
   s->n_slots = slot;  // every slot is written by exactly one workgroup
   Arena& E = s->energy_mem;
@@ -589,15 +599,21 @@ void run_energy_mixed(msd_system* s) {
       });
     }
     s->timed(ST_LAMBDA, [&] {
-      msd::launch_lambda_rows32(A, B, nmax, s->NW, w0, wt, s->NG, s->gl_chunk,
-                                reinterpret_cast<const cf*>(s->T32[0]),
-                                reinterpret_cast<const cf*>(s->T32[1]), s->LT32[0], s->LT32[1],
-                                s->Lam32[0], s->Lam32[1], s->v0, s->ex0, s->ZWp[0], s->ZWp[1],
-                                s->st);
+      const cf* Ta = reinterpret_cast<const cf*>(s->T32[0]);
+      const cf* Tb = reinterpret_cast<const cf*>(s->T32[1]);
+      if (s->lambda_variant == 2)
+        msd::launch_lambda_wave32(A, B, nmax, s->NW, w0, wt, s->NG, s->gl_chunk, Ta, Tb,
+                                  s->LT32[0], s->LT32[1], s->Lam32[0], s->Lam32[1], s->v0, s->ex0,
+                                  s->ZWp[0], s->ZWp[1], s->st);
+      else
+        msd::launch_lambda_rows32(A, B, nmax, s->NW, w0, wt, s->NG, s->gl_chunk, Ta, Tb,
+                                  s->LT32[0], s->LT32[1], s->Lam32[0], s->Lam32[1], s->v0, s->ex0,
+                                  s->ZWp[0], s->ZWp[1], s->st);
     });
     s->timed(ST_EGAMMA, [&] {
       msd::launch_energy_second32(A, B, s->dp, s->plan, s->n_itemblocks, msd::ER_WAVES, s->NW,
-                                  w0, wt, s->NG, s->gsplit, s->second_G, s->Lam32[0],
+                                  w0, wt, s->NG, s->gsplit, s->second_G, s->second_maxk,
+                                  s->Lam32[0],
                                   s->Lam32[1], s->coefAB, s->sw[0].m2, s->sw[1].m2, s->sw[0].B,
                                   s->sw[1].B, s->epart, s->n_slots, s->slot_second, s->st);
     });
@@ -660,7 +676,11 @@ void run_energy(msd_system* s) {
       }
       int nmax = 0;
       s->timed(ST_LAMBDA, [&] {
-        if (msd::lambda_rows_fits(A, B, &nmax))
+        if (s->lambda_variant == 2 && msd::lambda_rows_fits(A, B, &nmax))
+          msd::launch_lambda_wave(A, B, nmax, s->NW, w0, wt, s->NG, s->gl_chunk, s->sw[0].T,
+                                  s->sw[1].T, s->LT[0], s->LT[1], s->Lam[0], s->Lam[1], s->v0,
+                                  s->ex0, s->ZWp[0], s->ZWp[1], s->st);
+        else if (s->lambda_variant == 1 && msd::lambda_rows_fits(A, B, &nmax))
           msd::launch_lambda_rows(A, B, nmax, s->NW, w0, wt, s->NG, s->gl_chunk, s->sw[0].T,
                                   s->sw[1].T, s->LT[0], s->LT[1], s->Lam[0], s->Lam[1], s->v0,
                                   s->ex0, s->ZWp[0], s->ZWp[1], s->st);
@@ -672,7 +692,8 @@ void run_energy(msd_system* s) {
     }
     s->timed(ST_EGAMMA, [&] {
       msd::launch_energy_second(A, B, s->dp, s->plan, s->n_itemblocks, msd::ER_WAVES, s->NW, w0,
-                                wt, s->NG, s->gsplit, s->second_G, s->Lam[0], s->Lam[1],
+                                wt, s->NG, s->gsplit, s->second_G, s->second_maxk, s->Lam[0],
+                                s->Lam[1],
                                 s->coefAB, s->sw[0].m2, s->sw[1].m2, s->sw[0].B, s->sw[1].B,
                                 s->epart, s->n_slots, s->slot_second, s->st);
       for (int sp = 0; sp < 2; ++sp) {
@@ -1072,6 +1093,20 @@ msd_status msd_set_hamiltonian(msd_system* sys, const double* h1, const double* 
 
 namespace {
 
+// Force-bias split-K from the override or the automatic choice; grows the
+// workspace (in the trial arena) when a larger split is asked for.
+void apply_fb_splitk(msd_system* s) {
+  const int64_t K = (int64_t)s->P_all * s->M;
+  int sk = s->tune.fb_splitk > 0 ? s->tune.fb_splitk : s->fb_splitk_auto;
+  sk = (int)std::max<int64_t>(1, std::min<int64_t>(sk, std::max<int64_t>(1, K / 16)));
+  if (sk > 1 && sk > s->fb_ws_cap) {
+    s->fb_ws = s->trial_mem.get<double>((size_t)sk * s->NG * 2 * s->NW);
+    s->fb_ws32 = s->mixed ? s->trial_mem.get<float>((size_t)sk * s->NG * 2 * s->NW) : nullptr;
+    s->fb_ws_cap = sk;
+  }
+  s->fb_splitk = sk;
+}
+
 // Shared by both trial entry points: occupation rows -> device tables.
 void set_trial_rows(msd_system* sys, const double* ci, const int32_t* occ_a,
                     const int32_t* occ_b) {
@@ -1181,9 +1216,9 @@ void set_trial_rows(msd_system* sys, const double* ci, const int32_t* occ_a,
     const int64_t K = (int64_t)sys->P_all * M;
     const int64_t tiles = (int64_t)((NG + 63) / 64) * ((2 * NW + 63) / 64);
     int sk = (int)std::max<int64_t>(1, std::min<int64_t>(512 / std::max<int64_t>(tiles, 1), K / 256));
-    sys->fb_splitk = sk;
-    sys->fb_ws = sk > 1 ? T.get<double>((size_t)sk * NG * 2 * NW) : nullptr;
-    sys->fb_ws32 = (sk > 1 && sys->mixed) ? T.get<float>((size_t)sk * NG * 2 * NW) : nullptr;
+    sys->fb_splitk_auto = std::min(sk, 16);
+    sys->fb_ws_cap = 0;
+    apply_fb_splitk(sys);
   }
   sys->L_rows = T.get<double>((size_t)NG * sys->P_all * M);
   sys->Gp = T.get<double>((size_t)2 * NW * sys->P_all * M);
@@ -1654,5 +1689,124 @@ msd_status msd_get_measurement(msd_system* sys, double* log_ovlp, double* force_
   copy_out(sys, force_bias, sys->xbar, sizeof(cd) * sys->NW * sys->NG);
   copy_out(sys, e_loc, sys->eloc, sizeof(cd) * sys->NW);
   sys->sync();
+  API_END(sys)
+}
+
+// ============================================================================
+// Launch-shape tuning and the autotuner
+// ============================================================================
+
+namespace {
+
+void set_tuning_impl(msd_system* s, const msd_tuning& t) {
+  auto bad = [](const char* f) { fail(MSD_ERR_ARG, std::string("tuning field ") + f + " out of range"); };
+  if (t.fb_splitk < 0 || t.fb_splitk > 16) bad("fb_splitk");
+  if (t.lambda_variant < 0 || t.lambda_variant > 2) bad("lambda_variant");
+  if (t.lambda_chunk < 0) bad("lambda_chunk");
+  if (t.second_gsplit < 0 || t.second_gsplit > 64) bad("second_gsplit");
+  if (t.second_stage < 0 || t.second_stage > 32) bad("second_stage");
+  s->tune = t;
+  free_energy(s);
+  s->drop_graphs();
+  if (s->have_trial) apply_fb_splitk(s);
+}
+
+double time_measures(msd_system* s, double dt, int reps) {
+  measure_impl(s, dt, true);  // builds the plan; warms caches
+  hipEvent_t a = s->ev(), b = s->ev();
+  hip_check(hipEventRecord(a, s->st), "record");
+  for (int r = 0; r < reps; ++r) measure_impl(s, dt, true);
+  hip_check(hipEventRecord(b, s->st), "record");
+  hip_check(hipEventSynchronize(b), "synchronize");
+  float ms = 0.f;
+  hip_check(hipEventElapsedTime(&ms, a, b), "elapsed");
+  s->pool.push_back(a);
+  s->pool.push_back(b);
+  return ms;
+}
+
+}  // namespace
+
+msd_status msd_get_tuning(msd_system* sys, msd_tuning* out) {
+  API_BEGIN
+  if (!sys || !out) fail(MSD_ERR_ARG, "null argument");
+  std::memset(out, 0, sizeof(*out));
+  out->fb_splitk = sys->fb_splitk;
+  if (sys->WT > 0) {
+    out->lambda_variant = sys->lambda_variant;
+    out->lambda_chunk = sys->gl_chunk;
+    out->second_gsplit = sys->gsplit;
+    out->second_stage = sys->second_G;
+  }
+  API_END(sys)
+}
+
+msd_status msd_set_tuning(msd_system* sys, const msd_tuning* t) {
+  API_BEGIN
+  if (!sys || !t) fail(MSD_ERR_ARG, "null argument");
+  set_device(sys);
+  set_tuning_impl(sys, *t);
+  API_END(sys)
+}
+
+msd_status msd_autotune(msd_system* sys, double dt, int32_t reps, msd_tuning* out) {
+  API_BEGIN
+  if (!sys) fail(MSD_ERR_ARG, "null argument");
+  if (reps < 1 || reps > 100) fail(MSD_ERR_ARG, "reps must be in 1..100");
+  set_device(sys);
+  need_ready(sys);
+  if (!sys->have_walkers) fail(MSD_ERR_STATE, "walkers have not been set");
+  const int32_t graphs = sys->o.graphs, timing = sys->o.timing;
+  sys->o.graphs = 0;
+  sys->o.timing = 0;
+  msd_tuning best = sys->tune;
+  try {
+    auto sweep = [&](int32_t msd_tuning::*field, const std::vector<int>& cands) {
+      double t_best = 1e300;
+      int v_best = best.*field;
+      for (int v : cands) {
+        msd_tuning t = best;
+        t.*field = v;
+        set_tuning_impl(sys, t);
+        const double ms = time_measures(sys, dt, reps);
+        if (ms < t_best) {
+          t_best = ms;
+          v_best = v;
+        }
+      }
+      best.*field = v_best;
+      set_tuning_impl(sys, best);
+    };
+    sweep(&msd_tuning::fb_splitk, {1, 2, 4, 8, 16});
+    int nmax = 0;
+    if (msd::lambda_rows_fits(sys->ds[0], sys->ds[1], &nmax) && nmax <= 16)
+      sweep(&msd_tuning::lambda_variant, {1, 2});
+    sweep(&msd_tuning::lambda_chunk, {4, 8, 16, 32});
+    sweep(&msd_tuning::second_gsplit, {1, 2, 4, 8});
+    {
+      const int X = sys->ds[0].nv * sys->ds[0].no + sys->ds[1].nv * sys->ds[1].no;
+      const int elem = sys->mixed ? 8 : 16;
+      std::vector<int> c;
+      for (int g : {1, 2, 3, 4, 6, 8})
+        if ((size_t)2 * g * elem * std::max(X, 1) <= ((size_t)150 << 10)) c.push_back(g);
+      sweep(&msd_tuning::second_stage, c);
+    }
+  } catch (...) {
+    sys->o.graphs = graphs;
+    sys->o.timing = timing;
+    throw;
+  }
+  sys->o.graphs = graphs;
+  sys->o.timing = timing;
+  measure_impl(sys, dt, true);  // leaves the chosen plan built
+  sys->sync();
+  if (out) {
+    std::memset(out, 0, sizeof(*out));
+    out->fb_splitk = sys->fb_splitk;
+    out->lambda_variant = sys->lambda_variant;
+    out->lambda_chunk = sys->gl_chunk;
+    out->second_gsplit = sys->gsplit;
+    out->second_stage = sys->second_G;
+  }
   API_END(sys)
 }

@@ -863,6 +863,168 @@ __global__ __launch_bounds__(128) void k_lambda_rows(DevSpin sa, DevSpin sb, int
   }
 }
 
+// Same quantities with one wave per (walker, Cholesky chunk, spin) and no
+// cross-wave barrier: each wave also sums the other spin's trace v0 from the
+// diagonal of its Q, and the loads of the next vector (Q entries, this lane's
+// LT row, the other spin's diagonal) are issued before the current vector's
+// arithmetic.
+template <int NMAX, int NOX, class CT>
+__global__ __launch_bounds__(64) void k_lambda_wave(DevSpin sa, DevSpin sb, int NW, int w0,
+                                                    int WT, int NG, int g_chunk,
+                                                    const CT* __restrict__ Ta,
+                                                    const CT* __restrict__ Tb,
+                                                    const CT* __restrict__ LTa,
+                                                    const CT* __restrict__ LTb,
+                                                    CT* __restrict__ Lam_a, CT* __restrict__ Lam_b,
+                                                    cd* __restrict__ v0, cd* __restrict__ ex0,
+                                                    cd* __restrict__ ZWa, cd* __restrict__ ZWb) {
+  constexpr int QPL = (NMAX * NMAX + 63) / 64;  // Q entries per lane
+  __shared__ CT Qs[NMAX * NMAX];
+  const int wl = blockIdx.x, chunk = blockIdx.y, n_chunks = gridDim.y, s2 = blockIdx.z;
+  const int w = w0 + wl, lane = threadIdx.x;
+  const int N = s2 ? sb.N : sa.N, nv = s2 ? sb.nv : sa.nv, no = s2 ? sb.no : sa.no;
+  const int P = s2 ? sb.P : sa.P, X = nv * no;
+  const int No = s2 ? sa.N : sb.N, Po = s2 ? sa.P : sb.P;
+  const int* __restrict__ vir = s2 ? sb.vir : sa.vir;
+  const int* __restrict__ oslot = s2 ? sb.oslot : sa.oslot;
+  const CT* __restrict__ T = s2 ? Tb : Ta;
+  const CT* __restrict__ LT = s2 ? LTb : LTa;
+  const CT* __restrict__ LTo = s2 ? LTa : LTb;
+  CT* __restrict__ Lam = s2 ? Lam_b : Lam_a;
+  cd* __restrict__ ZW = s2 ? ZWb : ZWa;
+  const bool row = lane < nv;
+  CT tv[NMAX];
+  cd zw[NOX];
+  int osl[NOX];
+#pragma unroll
+  for (int j = 0; j < NMAX; ++j)
+    tv[j] = (row && j < N) ? T[((size_t)vir[lane] * NW + w) * N + j] : CT{};
+#pragma unroll
+  for (int i = 0; i < NOX; ++i) {
+    osl[i] = i < no ? oslot[i] : 0;
+    zw[i] = cd{0.0, 0.0};
+  }
+  const size_t ld = (size_t)WT * N, ldo = (size_t)WT * No;
+  const int g0 = chunk * g_chunk, g1 = min(NG, g0 + g_chunk);
+  CT qn[QPL], ltn[NMAX], dn{};
+  auto fetch = [&](int g) {
+    const CT* base = LT + ((size_t)g * P) * ld + (size_t)wl * N;
+#pragma unroll
+    for (int r = 0; r < QPL; ++r) {
+      const int e = lane + 64 * r;
+      qn[r] = e < N * N ? base[(size_t)(e / N) * ld + e % N] : CT{};
+    }
+#pragma unroll
+    for (int c = 0; c < NMAX; ++c)
+      ltn[c] = (row && c < N) ? base[(size_t)(N + lane) * ld + c] : CT{};
+    const CT* baseo = LTo + ((size_t)g * Po) * ldo + (size_t)wl * No;
+    dn = lane < No ? baseo[(size_t)lane * ldo + lane] : CT{};
+  };
+  if (g0 < g1) fetch(g0);
+  for (int g = g0; g < g1; ++g) {
+    CT q[QPL], ltv[NMAX];
+#pragma unroll
+    for (int r = 0; r < QPL; ++r) q[r] = qn[r];
+#pragma unroll
+    for (int c = 0; c < NMAX; ++c) ltv[c] = ltn[c];
+    const CT d = dn;
+    __syncthreads();  // the previous vector's reads of Qs are done
+#pragma unroll
+    for (int r = 0; r < QPL; ++r) {
+      const int e = lane + 64 * r;
+      if (e < N * N) Qs[e] = q[r];
+    }
+    if (g + 1 < g1) fetch(g + 1);
+    CT v{};
+#pragma unroll
+    for (int r = 0; r < QPL; ++r) {
+      const int e = lane + 64 * r;
+      if (e < N * N && e / N == e % N) v += q[r];
+    }
+    v = wave_sum(v);
+    const CT vo = wave_sum(d);
+    __syncthreads();
+    CT x{};
+#pragma unroll
+    for (int r = 0; r < QPL; ++r) {
+      const int e = lane + 64 * r;
+      if (e < N * N) cfma(x, q[r], Qs[(e % N) * N + e / N]);
+    }
+    x = wave_sum(x);
+    if (lane == 0) {
+      v0[((size_t)s2 * NW + w) * NG + g] = N > 0 ? to_cd(v) : cd{0.0, 0.0};
+      ex0[((size_t)s2 * NW + w) * NG + g] = N > 0 ? to_cd(x) : cd{0.0, 0.0};
+    }
+    const CT vsum = v + vo;
+    if (row) {
+      CT lam[NMAX];
+#pragma unroll
+      for (int c = 0; c < NMAX; ++c) {
+        CT a = -ltv[c];
+#pragma unroll
+        for (int j = 0; j < NMAX; ++j)
+          if (j < N && c < N) cfma(a, tv[j], Qs[j * N + c]);
+        lam[c] = a;
+      }
+      CT* Lo = Lam + ((size_t)wl * NG + g) * X + (size_t)lane * no;
+#pragma unroll
+      for (int i = 0; i < NOX; ++i) {
+        if (i < no) {
+          const int oc = osl[i];
+          CT xi{}, lw{};
+#pragma unroll
+          for (int c = 0; c < NMAX; ++c) {
+            if (c < N) cfma(xi, lam[c], Qs[c * N + oc]);
+            if (c == oc) lw = lam[c];
+          }
+          Lo[i] = lw;
+          zw[i] += to_cd(xi - vsum * lw);
+        }
+      }
+    }
+  }
+  if (row) {
+#pragma unroll
+    for (int i = 0; i < NOX; ++i)
+      if (i < no) ZW[((size_t)wl * n_chunks + chunk) * X + (size_t)lane * no + i] = zw[i];
+  }
+}
+
+template <class CT>
+static void launch_lambda_wave_t(const DevSpin& sa, const DevSpin& sb, int nmax, int NW, int w0,
+                                 int WT, int NG, int g_chunk, const CT* Ta, const CT* Tb,
+                                 const CT* LTa, const CT* LTb, CT* Lam_a, CT* Lam_b, cd* v0,
+                                 cd* ex0, cd* ZWpart_a, cd* ZWpart_b, hipStream_t st) {
+  const int n_chunks = (NG + g_chunk - 1) / g_chunk;
+  const dim3 grid(WT, n_chunks, 2);
+  const bool o8 = max(sa.no, sb.no) <= 8;
+#define MSD_LW(NM, NO) \
+  hipLaunchKernelGGL((k_lambda_wave<NM, NO, CT>), grid, dim3(64), 0, st, sa, sb, NW, w0, WT, NG, \
+                     g_chunk, Ta, Tb, LTa, LTb, Lam_a, Lam_b, v0, ex0, ZWpart_a, ZWpart_b)
+  if (nmax <= 8) {
+    if (o8) MSD_LW(8, 8); else MSD_LW(8, 16);
+  } else {
+    if (o8) MSD_LW(16, 8); else MSD_LW(16, 16);
+  }
+#undef MSD_LW
+}
+
+void launch_lambda_wave(const DevSpin& sa, const DevSpin& sb, int nmax, int NW, int w0, int WT,
+                        int NG, int g_chunk, const cd* Ta, const cd* Tb, const cd* LTa,
+                        const cd* LTb, cd* Lam_a, cd* Lam_b, cd* v0, cd* ex0, cd* ZWpart_a,
+                        cd* ZWpart_b, hipStream_t st) {
+  launch_lambda_wave_t<cd>(sa, sb, nmax, NW, w0, WT, NG, g_chunk, Ta, Tb, LTa, LTb, Lam_a, Lam_b,
+                           v0, ex0, ZWpart_a, ZWpart_b, st);
+}
+
+void launch_lambda_wave32(const DevSpin& sa, const DevSpin& sb, int nmax, int NW, int w0, int WT,
+                          int NG, int g_chunk, const cf* Ta, const cf* Tb, const cf* LTa,
+                          const cf* LTb, cf* Lam_a, cf* Lam_b, cd* v0, cd* ex0, cd* ZWpart_a,
+                          cd* ZWpart_b, hipStream_t st) {
+  launch_lambda_wave_t<cf>(sa, sb, nmax, NW, w0, WT, NG, g_chunk, Ta, Tb, LTa, LTb, Lam_a, Lam_b,
+                           v0, ex0, ZWpart_a, ZWpart_b, st);
+}
+
 bool lambda_rows_fits(const DevSpin& sa, const DevSpin& sb, int* nmax) {
   const int n = max(sa.N, sb.N);
   if (sa.nv > 64 || sb.nv > 64 || sa.no > NOMAX || sb.no > NOMAX || n > 32) return false;
@@ -1210,10 +1372,12 @@ __global__ __launch_bounds__(MINOR_THREADS) void k_energy_minors(
 // rows m and m' of Y_mn = Lam[p_n, h_m] (2K gathers per Cholesky vector) and
 // the K(K-1)/2 signed complementary minors of that row pair:
 //   e2 += sum_{n<n'} (-1)^{m+m'+n+n'} det X[~{m,m'},~{n,n'}] (Y_mn Y_m'n' - Y_mn' Y_m'n).
+// idx[] holds window offsets (p_n * n_occ_act + slot(h_m)) within the spin's
+// Lambda row.
 template <int K, class CT>
 __device__ __forceinline__ void rp_setup(const int* __restrict__ hwin, const int* __restrict__ pwin,
-                                         int no, int str, int rp, int off, const cd* m2s,
-                                         int* idx, CT* mm) {
+                                         int no, int str, int rp, const cd* m2s, int* idx,
+                                         CT* mm) {
   constexpr int P = K * (K - 1) / 2;
   int m = 0, mp = 1;
   for (int a = 0, q = 0; a < K; ++a)
@@ -1222,8 +1386,8 @@ __device__ __forceinline__ void rp_setup(const int* __restrict__ hwin, const int
 #pragma unroll
   for (int n = 0; n < K; ++n) {
     const int col = pwin[str * KMAX + n] * no;
-    idx[n] = off + col + hwin[str * KMAX + m];
-    idx[K + n] = off + col + hwin[str * KMAX + mp];
+    idx[n] = col + hwin[str * KMAX + m];
+    idx[K + n] = col + hwin[str * KMAX + mp];
   }
   const cd* src = m2s + rp * P;
   int q = 0;
@@ -1252,13 +1416,22 @@ __device__ __forceinline__ void rp_eval(const CT* Lg, const int* idx, const CT* 
     for (int np = n + 1; np < K; ++np, ++q) cfma(acc, mm[q], y0[n] * y1[np] - y0[np] * y1[n]);
 }
 
-template <class CT>
+// Merged second-order kernel.  Workgroup = (walker, Cholesky range, item
+// block); each wave takes one plan entry: 64 x ER_PPL opposite-spin pairs, or
+// 64 row-pair items of one spin and order.  The Lambda rows of the range are
+// staged through LDS in double-buffered stages of G vectors, laid out
+// [alpha: G x Xa][beta: G x Xb] so each stage is two contiguous copies.
+constexpr int ER_PPL = 4;  // opposite-spin pairs per lane
+
+template <class CT, int MAXK>
 __global__ __launch_bounds__(512) void k_energy_second(
     DevSpin sa, DevSpin sb, DevPairs pr, const int4* __restrict__ plan, int n_ib,
     int waves_per_block, int NW, int w0, int NG, int n_gsplit, int G, const CT* __restrict__ Lam_a,
     const CT* __restrict__ Lam_b, const cd* __restrict__ coef, const cd* __restrict__ m2a,
     const cd* __restrict__ m2b, const cd* __restrict__ Ba, const cd* __restrict__ Bb,
     cd* __restrict__ partial, int n_slots, int slot0) {
+  constexpr int NIDX = 2 * MAXK > 2 * ER_PPL ? 2 * MAXK : 2 * ER_PPL;
+  constexpr int NMM = MAXK * (MAXK - 1) / 2;
   extern __shared__ __align__(16) unsigned char sm_raw[];
   CT* sm = reinterpret_cast<CT*>(sm_raw);
   __shared__ cd red[16];
@@ -1278,27 +1451,26 @@ __global__ __launch_bounds__(512) void k_energy_second(
   // first item, item end)
   const int4 pl = plan[ib * waves_per_block + wave];
   const int role = pl.x & 0xff, sp = pl.x >> 8;
-  const int off = sp ? Xa : 0;  // spin block inside a staged Cholesky vector
-  int idx[16];
-  CT mm[15];
-  CT acc[8];
+  int idx[NIDX];
+  CT mm[NMM];
+  CT acc[ER_PPL];
 #pragma unroll
-  for (int j = 0; j < 16; ++j) idx[j] = 0;
+  for (int j = 0; j < NIDX; ++j) idx[j] = 0;
 #pragma unroll
-  for (int j = 0; j < 15; ++j) mm[j] = CT{};
+  for (int j = 0; j < NMM; ++j) mm[j] = CT{};
 #pragma unroll
-  for (int j = 0; j < 8; ++j) acc[j] = CT{};
-  const int item = role == ER_PAIRS ? pl.z + lane * 8 : pl.z + lane;
+  for (int j = 0; j < ER_PPL; ++j) acc[j] = CT{};
+  const int item = role == ER_PAIRS ? pl.z + lane * ER_PPL : pl.z + lane;
   const bool live = role != ER_NONE && item < pl.w;
   int str = 0;
   if (live) {
     if (role == ER_PAIRS) {
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
+      for (int j = 0; j < ER_PPL; ++j) {
         const int t = item + j;
         const bool ok = t < pl.w;
         idx[j] = ok ? pr.x[t] : -1;
-        idx[8 + j] = ok ? Xa + pr.y[t] : 0;
+        idx[ER_PPL + j] = ok ? pr.y[t] : 0;
       }
     } else {
       const int K = role;  // row-pair roles equal the string order
@@ -1311,43 +1483,53 @@ __global__ __launch_bounds__(512) void k_energy_second(
       const cd* m2s = (sp ? m2b + (size_t)w * sb.M2 + sb.m2_off[str]
                           : m2a + (size_t)w * sa.M2 + sa.m2_off[str]);
       switch (K) {
-        case 2: rp_setup<2, CT>(hwin, pwin, no, str, rp, off, m2s, idx, mm); break;
-        case 3: rp_setup<3, CT>(hwin, pwin, no, str, rp, off, m2s, idx, mm); break;
-        case 4: rp_setup<4, CT>(hwin, pwin, no, str, rp, off, m2s, idx, mm); break;
-        case 5: rp_setup<5, CT>(hwin, pwin, no, str, rp, off, m2s, idx, mm); break;
-        default: rp_setup<6, CT>(hwin, pwin, no, str, rp, off, m2s, idx, mm); break;
+        case 2: rp_setup<2, CT>(hwin, pwin, no, str, rp, m2s, idx, mm); break;
+        case 3: rp_setup<3, CT>(hwin, pwin, no, str, rp, m2s, idx, mm); break;
+        case 4: rp_setup<4, CT>(hwin, pwin, no, str, rp, m2s, idx, mm); break;
+        case 5: if constexpr (MAXK >= 5) rp_setup<5 <= MAXK ? 5 : 2, CT>(hwin, pwin, no, str, rp, m2s, idx, mm); break;
+        default: if constexpr (MAXK >= 6) rp_setup<6 <= MAXK ? 6 : 2, CT>(hwin, pwin, no, str, rp, m2s, idx, mm); break;
       }
     }
   }
   auto stage = [&](int gb, CT* dst) {
     const int Gs = min(G, g1 - gb);
-    for (int e = tid; e < Gs * X; e += blockDim.x) {
-      const int gl = e / X, x = e % X;
-      dst[e] = x < Xa ? Lam_a[((size_t)wl * NG + gb + gl) * Xa + x]
-                      : Lam_b[((size_t)wl * NG + gb + gl) * Xb + (x - Xa)];
-    }
+    const CT* sa_ = Lam_a + ((size_t)wl * NG + gb) * Xa;
+    const CT* sb_ = Lam_b + ((size_t)wl * NG + gb) * Xb;
+    for (int e = tid; e < Gs * Xa; e += blockDim.x) dst[e] = sa_[e];
+    CT* db = dst + (size_t)G * Xa;
+    for (int e = tid; e < Gs * Xb; e += blockDim.x) db[e] = sb_[e];
   };
   if (g0 < g1) stage(g0, buf[0]);
   __syncthreads();
   int it = 0;
   for (int gb = g0; gb < g1; gb += G, ++it) {
     if (gb + G < g1) stage(gb + G, buf[(it + 1) & 1]);
-    const CT* L = buf[it & 1];
+    const CT* La = buf[it & 1];
+    const CT* Lb = La + (size_t)G * Xa;
     const int Gs = min(G, g1 - gb);
     if (live) {
-      for (int gl = 0; gl < Gs; ++gl) {
-        const CT* Lg = L + gl * X;
-        switch (role) {
-          case ER_PAIRS:
+      if (role == ER_PAIRS) {
+#pragma unroll 2
+        for (int gl = 0; gl < Gs; ++gl) {
+          const CT* x = La + gl * Xa;
+          const CT* y = Lb + gl * Xb;
 #pragma unroll
-            for (int j = 0; j < 8; ++j)
-              if (idx[j] >= 0) cfma(acc[j], Lg[idx[j]], Lg[idx[8 + j]]);
-            break;
-          case 2: rp_eval<2, CT>(Lg, idx, mm, acc[0]); break;
-          case 3: rp_eval<3, CT>(Lg, idx, mm, acc[0]); break;
-          case 4: rp_eval<4, CT>(Lg, idx, mm, acc[0]); break;
-          case 5: rp_eval<5, CT>(Lg, idx, mm, acc[0]); break;
-          default: rp_eval<6, CT>(Lg, idx, mm, acc[0]); break;
+          for (int j = 0; j < ER_PPL; ++j)
+            if (idx[j] >= 0) cfma(acc[j], x[idx[j]], y[idx[ER_PPL + j]]);
+        }
+      } else {
+        const CT* Ls = sp ? Lb : La;
+        const int Xs = sp ? Xb : Xa;
+#pragma unroll 2
+        for (int gl = 0; gl < Gs; ++gl) {
+          const CT* Lg = Ls + gl * Xs;
+          switch (role) {
+            case 2: rp_eval<2, CT>(Lg, idx, mm, acc[0]); break;
+            case 3: rp_eval<3, CT>(Lg, idx, mm, acc[0]); break;
+            case 4: rp_eval<4, CT>(Lg, idx, mm, acc[0]); break;
+            case 5: if constexpr (MAXK >= 5) rp_eval<5 <= MAXK ? 5 : 2, CT>(Lg, idx, mm, acc[0]); break;
+            default: if constexpr (MAXK >= 6) rp_eval<6 <= MAXK ? 6 : 2, CT>(Lg, idx, mm, acc[0]); break;
+          }
         }
       }
     }
@@ -1357,7 +1539,7 @@ __global__ __launch_bounds__(512) void k_energy_second(
   if (live) {
     if (role == ER_PAIRS) {
 #pragma unroll
-      for (int j = 0; j < 8; ++j)
+      for (int j = 0; j < ER_PPL; ++j)
         if (idx[j] >= 0) cfma(tot, coef[(size_t)w * pr.n_pair + item + j], to_cd(acc[j]));
     } else {
       tot = (sp ? Bb[(size_t)w * sb.U + str] : Ba[(size_t)w * sa.U + str]) * to_cd(acc[0]);
@@ -1376,37 +1558,43 @@ __global__ __launch_bounds__(512) void k_energy_second(
 template <class CT>
 static void launch_energy_second_t(const DevSpin& sa, const DevSpin& sb, const DevPairs& pr,
                                    const int4* plan, int n_itemblocks, int waves_per_block, int NW,
-                                   int w0, int WT, int NG, int n_gsplit, int G, const CT* Lam_a,
-                                   const CT* Lam_b, const cd* coef, const cd* m2a, const cd* m2b,
-                                   const cd* Ba, const cd* Bb, cd* partial, int n_slots, int slot0,
-                                   hipStream_t st) {
+                                   int w0, int WT, int NG, int n_gsplit, int G, int max_order,
+                                   const CT* Lam_a, const CT* Lam_b, const cd* coef,
+                                   const cd* m2a, const cd* m2b, const cd* Ba, const cd* Bb,
+                                   cd* partial, int n_slots, int slot0, hipStream_t st) {
   if (n_itemblocks == 0) return;
   const size_t lds = 2 * (size_t)G * (sa.nv * sa.no + sb.nv * sb.no) * sizeof(CT);
-  hipLaunchKernelGGL((k_energy_second<CT>), dim3(WT * n_gsplit * n_itemblocks, 1),
-                     dim3(64 * waves_per_block), lds, st, sa, sb, pr, plan, n_itemblocks,
-                     waves_per_block, NW, w0, NG, n_gsplit, G, Lam_a, Lam_b, coef, m2a, m2b, Ba,
-                     Bb, partial, n_slots, slot0);
+  const dim3 grid(WT * n_gsplit * n_itemblocks), block(64 * waves_per_block);
+  if (max_order <= 4)
+    hipLaunchKernelGGL((k_energy_second<CT, 4>), grid, block, lds, st, sa, sb, pr, plan,
+                       n_itemblocks, waves_per_block, NW, w0, NG, n_gsplit, G, Lam_a, Lam_b,
+                       coef, m2a, m2b, Ba, Bb, partial, n_slots, slot0);
+  else
+    hipLaunchKernelGGL((k_energy_second<CT, ER_MAX_ORDER>), grid, block, lds, st, sa, sb, pr,
+                       plan, n_itemblocks, waves_per_block, NW, w0, NG, n_gsplit, G, Lam_a,
+                       Lam_b, coef, m2a, m2b, Ba, Bb, partial, n_slots, slot0);
 }
 
 void launch_energy_second(const DevSpin& sa, const DevSpin& sb, const DevPairs& pr,
                           const int4* plan, int n_itemblocks, int waves_per_block, int NW, int w0,
-                          int WT, int NG, int n_gsplit, int G, const cd* Lam_a, const cd* Lam_b,
-                          const cd* coef, const cd* m2a, const cd* m2b, const cd* Ba,
-                          const cd* Bb, cd* partial, int n_slots, int slot0, hipStream_t st) {
+                          int WT, int NG, int n_gsplit, int G, int max_order, const cd* Lam_a,
+                          const cd* Lam_b, const cd* coef, const cd* m2a, const cd* m2b,
+                          const cd* Ba, const cd* Bb, cd* partial, int n_slots, int slot0,
+                          hipStream_t st) {
   launch_energy_second_t<cd>(sa, sb, pr, plan, n_itemblocks, waves_per_block, NW, w0, WT, NG,
-                             n_gsplit, G, Lam_a, Lam_b, coef, m2a, m2b, Ba, Bb, partial, n_slots,
-                             slot0, st);
+                             n_gsplit, G, max_order, Lam_a, Lam_b, coef, m2a, m2b, Ba, Bb,
+                             partial, n_slots, slot0, st);
 }
 
 void launch_energy_second32(const DevSpin& sa, const DevSpin& sb, const DevPairs& pr,
                             const int4* plan, int n_itemblocks, int waves_per_block, int NW,
-                            int w0, int WT, int NG, int n_gsplit, int G, const cf* Lam_a,
-                            const cf* Lam_b, const cd* coef, const cd* m2a, const cd* m2b,
-                            const cd* Ba, const cd* Bb, cd* partial, int n_slots, int slot0,
-                            hipStream_t st) {
+                            int w0, int WT, int NG, int n_gsplit, int G, int max_order,
+                            const cf* Lam_a, const cf* Lam_b, const cd* coef, const cd* m2a,
+                            const cd* m2b, const cd* Ba, const cd* Bb, cd* partial, int n_slots,
+                            int slot0, hipStream_t st) {
   launch_energy_second_t<cf>(sa, sb, pr, plan, n_itemblocks, waves_per_block, NW, w0, WT, NG,
-                             n_gsplit, G, Lam_a, Lam_b, coef, m2a, m2b, Ba, Bb, partial, n_slots,
-                             slot0, st);
+                             n_gsplit, G, max_order, Lam_a, Lam_b, coef, m2a, m2b, Ba, Bb,
+                             partial, n_slots, slot0, st);
 }
 
 int energy_pair_blocks(int n_pair) {
@@ -1536,8 +1724,10 @@ void init_wick_attributes() {
   hipFuncSetAttribute((const void*)k_green, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   hipFuncSetAttribute((const void*)k_lambda, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   hipFuncSetAttribute((const void*)k_energy_pairs, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-  hipFuncSetAttribute((const void*)k_energy_second<cd>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-  hipFuncSetAttribute((const void*)k_energy_second<cf>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  hipFuncSetAttribute((const void*)k_energy_second<cd, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  hipFuncSetAttribute((const void*)k_energy_second<cf, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  hipFuncSetAttribute((const void*)k_energy_second<cd, ER_MAX_ORDER>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  hipFuncSetAttribute((const void*)k_energy_second<cf, ER_MAX_ORDER>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   hipFuncSetAttribute((const void*)k_energy_minors, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   hipFuncSetAttribute((const void*)k_energy_strings<2>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   hipFuncSetAttribute((const void*)k_energy_strings<3>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
