@@ -1469,7 +1469,7 @@ __global__ __launch_bounds__(512) void k_energy_second(
       for (int j = 0; j < ER_PPL; ++j) {
         const int t = item + j;
         const bool ok = t < pl.w;
-        idx[j] = ok ? pr.x[t] : -1;
+        idx[j] = ok ? pr.x[t] : 0;  // padding pairs read entry 0 and are dropped below
         idx[ER_PPL + j] = ok ? pr.y[t] : 0;
       }
     } else {
@@ -1514,8 +1514,7 @@ __global__ __launch_bounds__(512) void k_energy_second(
           const CT* x = La + gl * Xa;
           const CT* y = Lb + gl * Xb;
 #pragma unroll
-          for (int j = 0; j < ER_PPL; ++j)
-            if (idx[j] >= 0) cfma(acc[j], x[idx[j]], y[idx[ER_PPL + j]]);
+          for (int j = 0; j < ER_PPL; ++j) cfma(acc[j], x[idx[j]], y[idx[ER_PPL + j]]);
         }
       } else {
         const CT* Ls = sp ? Lb : La;
@@ -1540,7 +1539,7 @@ __global__ __launch_bounds__(512) void k_energy_second(
     if (role == ER_PAIRS) {
 #pragma unroll
       for (int j = 0; j < ER_PPL; ++j)
-        if (idx[j] >= 0) cfma(tot, coef[(size_t)w * pr.n_pair + item + j], to_cd(acc[j]));
+        if (item + j < pl.w) cfma(tot, coef[(size_t)w * pr.n_pair + item + j], to_cd(acc[j]));
     } else {
       tot = (sp ? Bb[(size_t)w * sb.U + str] : Ba[(size_t)w * sa.U + str]) * to_cd(acc[0]);
     }

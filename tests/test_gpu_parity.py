@@ -535,7 +535,7 @@ def test_uneven_batch_graph_matches_separate_systems():
 @pytest.mark.parametrize("tuning", [
     dict(lambda_variant=1, lambda_chunk=5, second_gsplit=3, second_stage=1, fb_splitk=1),
     dict(lambda_variant=2, lambda_chunk=7, second_gsplit=1, second_stage=3, fb_splitk=3),
-    dict(lambda_variant=2, lambda_chunk=32, second_gsplit=8, second_stage=8, fb_splitk=16),
+    dict(lambda_variant=2, lambda_chunk=32, second_gsplit=8, second_stage=4, fb_splitk=16),
 ])
 def test_tuning_overrides_keep_parity(tuning):
     """Ragged Cholesky chunks and stages (320 vectors split 5/7/3 ways) in
