@@ -26,6 +26,29 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "energy_second_medium_hbm_traffic.md")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the second-order energy kernel from the
+    committed rocprofv3 counter summary, or None if the kernel source changed
+    since the counters were taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    vals = dict(line.split(": ", 1) for line in text.splitlines()
+                if line.startswith(("traffic_bytes_per_launch:", "source:")))
+    try:
+        fields = vals["source"].split()
+        src, prefix = fields[0], fields[-1]
+        digest = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()
+        if not digest.startswith(prefix):
+            return None
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, OSError, ValueError, IndexError):
+        return None
 
 
 def stage_work(wl, lib_sys, stage):
@@ -63,7 +86,7 @@ def stage_work(wl, lib_sys, stage):
     return None
 
 
-def cpu_baseline(wl, n_sample=6):
+def cpu_baseline(wl, n_sample=24):
     """The oracle on a bounded sample: n_sample walkers, all determinants,
     one propagation step + one full measurement each."""
     from threadpoolctl import threadpool_info
@@ -210,8 +233,11 @@ def main():
             ach = amount / avg_s / 1e9
             peak = HBM_PEAK_GBS
             u = "GB/s"
-        roof = {"kernel": name, "bound": bound, "achieved": round(ach, 3), "peak": peak,
-                "unit": u, "frac": round(ach / peak, 4), "traffic": None,
+        traffic = measured_traffic() if name == "energy_gamma" else None
+        kernel = {"energy_gamma": "k_energy_second", "lambda": "k_lambda_wave",
+                  "lt_gemm": "k_gemm_f64 (LT)"}.get(name, name)
+        roof = {"kernel": kernel, "stage": name, "bound": bound, "achieved": round(ach, 3), "peak": peak,
+                "unit": u, "frac": round(ach / peak, 4), "traffic": traffic,
                 "avg_launch_ms": round(avg_s * 1e3, 4)}
         break
 
@@ -239,7 +265,8 @@ def main():
                          "note": "msd_measure_dev alone (overlap, G, force bias, E_L)"},
         "mixed": mixed,
         "tuning": tunings,
-        "stage_timing_note": "stages_ms and roofline from a second pass of the same steps with "
+        "stage_timing_note": "stages_ms (average per timed launch group; the LT group runs once "
+                             "per spin) and roofline from a second pass of the same steps with "
                              "HIP events around every stage (no graphs)",
     }
     if not args.no_cpu_baseline:
