@@ -209,7 +209,10 @@ msd_status msd_reset_timings(msd_system* sys);
 typedef struct {
   int32_t fb_splitk;      /* K slices of the force-bias GEMM (1..16)                      */
   int32_t lambda_variant; /* energy intermediates: 1 = two-wave rows kernel,
-                             2 = one-wave pipelined kernel (N <= 16)                       */
+                             2 = one-wave kernel with the next vector's loads in flight,
+                             3 = one-wave kernel loading each vector when used (fewer
+                             registers; only where both spins have N = 8 or 16 and the
+                             whole occupied window, else as 2).  2 and 3 need N <= 16 */
   int32_t lambda_chunk;   /* Cholesky vectors per intermediates workgroup (1..NG)         */
   int32_t second_gsplit;  /* Cholesky-range split of the second-order kernel (1..64)      */
   int32_t second_stage;   /* Cholesky vectors per LDS stage of the second-order kernel

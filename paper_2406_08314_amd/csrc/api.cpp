@@ -132,6 +132,7 @@ struct msd_system {
   int fb_splitk = 1, fb_splitk_auto = 1, fb_ws_cap = 0;
   msd_tuning tune{};                 // launch-shape overrides (0 = automatic)
   int lambda_variant = 1;            // resolved: 1 rows kernel, 2 one-wave kernel
+  bool lambda_exact = false;         // N == nmax per spin and identity occupied window
 
   // mixed form: single-precision copies of the GEMM operands
   bool mixed = false;
@@ -398,8 +399,17 @@ void alloc_energy(msd_system* s) {
     if (s->tune.second_stage > 0)
       s->second_G = std::max(1, std::min(s->tune.second_stage,
                                          (int)((150 << 10) / (2 * elem * std::max(X, 1)))));
+    s->lambda_exact = rows_fit && A.N == nmax && B.N == nmax;
+    for (int sp = 0; sp < 2 && s->lambda_exact; ++sp) {
+      const msd::SpinTable& S = s->tt.s[sp];
+      if (S.no() != S.N) s->lambda_exact = false;
+      for (int i = 0; i < S.no() && s->lambda_exact; ++i)
+        if (S.occ_slot[i] != i) s->lambda_exact = false;
+    }
     // 0: the generic one-wave kernel (windows beyond the row kernels' limits)
-    s->lambda_variant = !rows_fit ? 0 : (s->tune.lambda_variant == 1 || nmax > 16) ? 1 : 2;
+    s->lambda_variant = !rows_fit ? 0
+                        : (s->tune.lambda_variant == 1 || nmax > 16) ? 1
+                        : (s->tune.lambda_variant == 3 && s->lambda_exact) ? 3 : 2;
   }
   s->n_slots = slot;  // every slot is written by exactly one workgroup
   Arena& E = s->energy_mem;
@@ -601,8 +611,8 @@ void run_energy_mixed(msd_system* s) {
     s->timed(ST_LAMBDA, [&] {
       const cf* Ta = reinterpret_cast<const cf*>(s->T32[0]);
       const cf* Tb = reinterpret_cast<const cf*>(s->T32[1]);
-      if (s->lambda_variant == 2)
-        msd::launch_lambda_wave32(A, B, nmax, s->NW, w0, wt, s->NG, s->gl_chunk, Ta, Tb,
+      if (s->lambda_variant >= 2)
+        msd::launch_lambda_wave32(A, B, nmax, s->lambda_exact, s->lambda_variant == 2, s->NW, w0, wt, s->NG, s->gl_chunk, Ta, Tb,
                                   s->LT32[0], s->LT32[1], s->Lam32[0], s->Lam32[1], s->v0, s->ex0,
                                   s->ZWp[0], s->ZWp[1], s->st);
       else
@@ -676,8 +686,8 @@ void run_energy(msd_system* s) {
       }
       int nmax = 0;
       s->timed(ST_LAMBDA, [&] {
-        if (s->lambda_variant == 2 && msd::lambda_rows_fits(A, B, &nmax))
-          msd::launch_lambda_wave(A, B, nmax, s->NW, w0, wt, s->NG, s->gl_chunk, s->sw[0].T,
+        if (s->lambda_variant >= 2 && msd::lambda_rows_fits(A, B, &nmax))
+          msd::launch_lambda_wave(A, B, nmax, s->lambda_exact, s->lambda_variant == 2, s->NW, w0, wt, s->NG, s->gl_chunk, s->sw[0].T,
                                   s->sw[1].T, s->LT[0], s->LT[1], s->Lam[0], s->Lam[1], s->v0,
                                   s->ex0, s->ZWp[0], s->ZWp[1], s->st);
         else if (s->lambda_variant == 1 && msd::lambda_rows_fits(A, B, &nmax))
@@ -1701,7 +1711,7 @@ namespace {
 void set_tuning_impl(msd_system* s, const msd_tuning& t) {
   auto bad = [](const char* f) { fail(MSD_ERR_ARG, std::string("tuning field ") + f + " out of range"); };
   if (t.fb_splitk < 0 || t.fb_splitk > 16) bad("fb_splitk");
-  if (t.lambda_variant < 0 || t.lambda_variant > 2) bad("lambda_variant");
+  if (t.lambda_variant < 0 || t.lambda_variant > 3) bad("lambda_variant");
   if (t.lambda_chunk < 0) bad("lambda_chunk");
   if (t.second_gsplit < 0 || t.second_gsplit > 64) bad("second_gsplit");
   if (t.second_stage < 0 || t.second_stage > 32) bad("second_stage");
@@ -1780,7 +1790,7 @@ msd_status msd_autotune(msd_system* sys, double dt, int32_t reps, msd_tuning* ou
     sweep(&msd_tuning::fb_splitk, {1, 2, 4, 8, 16});
     int nmax = 0;
     if (msd::lambda_rows_fits(sys->ds[0], sys->ds[1], &nmax) && nmax <= 16)
-      sweep(&msd_tuning::lambda_variant, {1, 2});
+      sweep(&msd_tuning::lambda_variant, {1, 2, 3});
     sweep(&msd_tuning::lambda_chunk, {4, 8, 16, 32});
     sweep(&msd_tuning::second_gsplit, {1, 2, 4, 8});
     {

@@ -144,14 +144,16 @@ void launch_lambda_rows32(const DevSpin& sa, const DevSpin& sb, int nmax, int NW
 // One-wave-per-(walker, chunk, spin) variant of the same computation (no
 // cross-wave barrier, next vector's loads in flight); same outputs.  For
 // N <= 16 (nmax 8 or 16 from lambda_rows_fits).
-void launch_lambda_wave(const DevSpin& sa, const DevSpin& sb, int nmax, int NW, int w0, int WT,
-                        int NG, int g_chunk, const cd* Ta, const cd* Tb, const cd* LTa,
-                        const cd* LTb, cd* Lam_a, cd* Lam_b, cd* v0, cd* ex0, cd* ZWpart_a,
-                        cd* ZWpart_b, hipStream_t st);
-void launch_lambda_wave32(const DevSpin& sa, const DevSpin& sb, int nmax, int NW, int w0, int WT,
-                          int NG, int g_chunk, const cf* Ta, const cf* Tb, const cf* LTa,
-                          const cf* LTb, cf* Lam_a, cf* Lam_b, cd* v0, cd* ex0, cd* ZWpart_a,
-                          cd* ZWpart_b, hipStream_t st);
+// exact: both spins have N == nmax and an identity occupied window;
+// prefetch: next vector's LT row loaded ahead into registers (exact shapes).
+void launch_lambda_wave(const DevSpin& sa, const DevSpin& sb, int nmax, bool exact, bool prefetch,
+                        int NW, int w0, int WT, int NG, int g_chunk, const cd* Ta, const cd* Tb,
+                        const cd* LTa, const cd* LTb, cd* Lam_a, cd* Lam_b, cd* v0, cd* ex0,
+                        cd* ZWpart_a, cd* ZWpart_b, hipStream_t st);
+void launch_lambda_wave32(const DevSpin& sa, const DevSpin& sb, int nmax, bool exact,
+                          bool prefetch, int NW, int w0, int WT, int NG, int g_chunk, const cf* Ta, const cf* Tb,
+                          const cf* LTa, const cf* LTb, cf* Lam_a, cf* Lam_b, cd* v0, cd* ex0,
+                          cd* ZWpart_a, cd* ZWpart_b, hipStream_t st);
 void launch_pair_coef(const DevPairs& pr, int NW, const cd* det_c, const cd* adj_a, int Aa,
                       const cd* adj_b, int Ab, cd* coef, hipStream_t st);
 void launch_minor_coef(const DevSpin& s, int NW, const cd* B, int U, const cd* m2, cd* coef,
@@ -176,15 +178,7 @@ void launch_energy_second32(const DevSpin& sa, const DevSpin& sb, const DevPairs
                             const cf* Lam_a, const cf* Lam_b, const cd* coef, const cd* m2a,
                             const cd* m2b, const cd* Ba, const cd* Bb, cd* partial, int n_slots,
                             int slot0, hipStream_t st);
-int energy_pair_blocks(int n_pair);
-int energy_string_blocks(const DevSpin& s, int k);
 int energy_minor_blocks(const DevSpin& s);
-void launch_energy_pairs(const DevPairs& pr, int Xa, int Xb, int NW, int w0, int WT, int NG,
-                         int n_gsplit, const cd* Lam_a, const cd* Lam_b, const cd* coef,
-                         cd* partial, int n_slots, int slot0, hipStream_t st);
-void launch_energy_strings(const DevSpin& s, int k, int NW, int w0, int WT, int NG, int n_gsplit,
-                           const cd* Lam, const cd* m2, const cd* B, cd* partial, int n_slots,
-                           int slot0, hipStream_t st);
 void launch_energy_minors(const DevSpin& s, int NW, int w0, int WT, int NG, int n_gsplit,
                           const cd* Lam, const cd* coef, cd* partial, int n_slots, int slot0,
                           hipStream_t st);

@@ -868,7 +868,12 @@ __global__ __launch_bounds__(128) void k_lambda_rows(DevSpin sa, DevSpin sb, int
 // diagonal of its Q, and the loads of the next vector (Q entries, this lane's
 // LT row, the other spin's diagonal) are issued before the current vector's
 // arithmetic.
-template <int NMAX, int NOX, class CT>
+// EXACT: both spins have N == NMAX electrons and the occupied window is all
+// of them in order (slot i = i), so every bound and the window columns are
+// compile-time constants.
+// PF: prefetch the next vector's LT row into registers (more registers,
+// fewer exposed loads).
+template <int NMAX, int NOX, bool EXACT, bool PF, class CT>
 __global__ __launch_bounds__(64) void k_lambda_wave(DevSpin sa, DevSpin sb, int NW, int w0,
                                                     int WT, int NG, int g_chunk,
                                                     const CT* __restrict__ Ta,
@@ -914,9 +919,11 @@ __global__ __launch_bounds__(64) void k_lambda_wave(DevSpin sa, DevSpin sb, int 
       const int e = lane + 64 * r;
       qn[r] = e < N * N ? base[(size_t)(e / N) * ld + e % N] : CT{};
     }
+    if (PF) {
 #pragma unroll
-    for (int c = 0; c < NMAX; ++c)
-      ltn[c] = (row && c < N) ? base[(size_t)(N + lane) * ld + c] : CT{};
+      for (int c = 0; c < NMAX; ++c)
+        ltn[c] = (row && c < N) ? base[(size_t)(N + lane) * ld + c] : CT{};
+    }
     const CT* baseo = LTo + ((size_t)g * Po) * ldo + (size_t)wl * No;
     dn = lane < No ? baseo[(size_t)lane * ldo + lane] : CT{};
   };
@@ -925,8 +932,15 @@ __global__ __launch_bounds__(64) void k_lambda_wave(DevSpin sa, DevSpin sb, int 
     CT q[QPL], ltv[NMAX];
 #pragma unroll
     for (int r = 0; r < QPL; ++r) q[r] = qn[r];
+    if (PF) {
 #pragma unroll
-    for (int c = 0; c < NMAX; ++c) ltv[c] = ltn[c];
+      for (int c = 0; c < NMAX; ++c) ltv[c] = ltn[c];
+    } else {
+      const CT* base = LT + ((size_t)g * P) * ld + (size_t)wl * N;
+#pragma unroll
+      for (int c = 0; c < NMAX; ++c)
+        ltv[c] = (row && c < N) ? base[(size_t)(N + lane) * ld + c] : CT{};
+    }
     const CT d = dn;
     __syncthreads();  // the previous vector's reads of Qs are done
 #pragma unroll
@@ -956,7 +970,29 @@ __global__ __launch_bounds__(64) void k_lambda_wave(DevSpin sa, DevSpin sb, int 
       ex0[((size_t)s2 * NW + w) * NG + g] = N > 0 ? to_cd(x) : cd{0.0, 0.0};
     }
     const CT vsum = v + vo;
-    if (row) {
+    if (EXACT && row) {
+      // row j of Q at a time (scheduling barriers keep the compiler from
+      // hoisting all N^2 LDS reads into registers)
+      CT lam[NMAX];
+#pragma unroll
+      for (int c = 0; c < NMAX; ++c) lam[c] = -ltv[c];
+#pragma unroll
+      for (int j = 0; j < NMAX; ++j) {
+#pragma unroll
+        for (int c = 0; c < NMAX; ++c) cfma(lam[c], tv[j], Qs[j * NMAX + c]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      CT* Lo = Lam + ((size_t)wl * NG + g) * X + (size_t)lane * NMAX;
+#pragma unroll
+      for (int i = 0; i < NMAX; ++i) {
+        CT xi{};
+#pragma unroll
+        for (int c = 0; c < NMAX; ++c) cfma(xi, lam[c], Qs[c * NMAX + i]);
+        Lo[i] = lam[i];
+        zw[i] += to_cd(xi - vsum * lam[i]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    } else if (row) {
       CT lam[NMAX];
 #pragma unroll
       for (int c = 0; c < NMAX; ++c) {
@@ -991,37 +1027,41 @@ __global__ __launch_bounds__(64) void k_lambda_wave(DevSpin sa, DevSpin sb, int 
 }
 
 template <class CT>
-static void launch_lambda_wave_t(const DevSpin& sa, const DevSpin& sb, int nmax, int NW, int w0,
-                                 int WT, int NG, int g_chunk, const CT* Ta, const CT* Tb,
-                                 const CT* LTa, const CT* LTb, CT* Lam_a, CT* Lam_b, cd* v0,
-                                 cd* ex0, cd* ZWpart_a, cd* ZWpart_b, hipStream_t st) {
+static void launch_lambda_wave_t(const DevSpin& sa, const DevSpin& sb, int nmax, bool exact,
+                                 bool prefetch, int NW, int w0, int WT, int NG, int g_chunk, const CT* Ta,
+                                 const CT* Tb, const CT* LTa, const CT* LTb, CT* Lam_a, CT* Lam_b,
+                                 cd* v0, cd* ex0, cd* ZWpart_a, cd* ZWpart_b, hipStream_t st) {
   const int n_chunks = (NG + g_chunk - 1) / g_chunk;
   const dim3 grid(WT, n_chunks, 2);
   const bool o8 = max(sa.no, sb.no) <= 8;
-#define MSD_LW(NM, NO) \
-  hipLaunchKernelGGL((k_lambda_wave<NM, NO, CT>), grid, dim3(64), 0, st, sa, sb, NW, w0, WT, NG, \
-                     g_chunk, Ta, Tb, LTa, LTb, Lam_a, Lam_b, v0, ex0, ZWpart_a, ZWpart_b)
-  if (nmax <= 8) {
-    if (o8) MSD_LW(8, 8); else MSD_LW(8, 16);
+#define MSD_LW(NM, NO, EX, PF) \
+  hipLaunchKernelGGL((k_lambda_wave<NM, NO, EX, PF, CT>), grid, dim3(64), 0, st, sa, sb, NW, w0, \
+                     WT, NG, g_chunk, Ta, Tb, LTa, LTb, Lam_a, Lam_b, v0, ex0, ZWpart_a, ZWpart_b)
+  if (exact && nmax == 8) {
+    if (prefetch) MSD_LW(8, 8, true, true); else MSD_LW(8, 8, true, false);
+  } else if (exact && nmax == 16) {
+    if (prefetch) MSD_LW(16, 16, true, true); else MSD_LW(16, 16, true, false);
+  } else if (nmax <= 8) {
+    if (o8) MSD_LW(8, 8, false, true); else MSD_LW(8, 16, false, true);
   } else {
-    if (o8) MSD_LW(16, 8); else MSD_LW(16, 16);
+    if (o8) MSD_LW(16, 8, false, true); else MSD_LW(16, 16, false, true);
   }
 #undef MSD_LW
 }
 
-void launch_lambda_wave(const DevSpin& sa, const DevSpin& sb, int nmax, int NW, int w0, int WT,
-                        int NG, int g_chunk, const cd* Ta, const cd* Tb, const cd* LTa,
-                        const cd* LTb, cd* Lam_a, cd* Lam_b, cd* v0, cd* ex0, cd* ZWpart_a,
-                        cd* ZWpart_b, hipStream_t st) {
-  launch_lambda_wave_t<cd>(sa, sb, nmax, NW, w0, WT, NG, g_chunk, Ta, Tb, LTa, LTb, Lam_a, Lam_b,
+void launch_lambda_wave(const DevSpin& sa, const DevSpin& sb, int nmax, bool exact, bool prefetch,
+                        int NW, int w0, int WT, int NG, int g_chunk, const cd* Ta, const cd* Tb,
+                        const cd* LTa, const cd* LTb, cd* Lam_a, cd* Lam_b, cd* v0, cd* ex0,
+                        cd* ZWpart_a, cd* ZWpart_b, hipStream_t st) {
+  launch_lambda_wave_t<cd>(sa, sb, nmax, exact, prefetch, NW, w0, WT, NG, g_chunk, Ta, Tb, LTa, LTb, Lam_a, Lam_b,
                            v0, ex0, ZWpart_a, ZWpart_b, st);
 }
 
-void launch_lambda_wave32(const DevSpin& sa, const DevSpin& sb, int nmax, int NW, int w0, int WT,
-                          int NG, int g_chunk, const cf* Ta, const cf* Tb, const cf* LTa,
-                          const cf* LTb, cf* Lam_a, cf* Lam_b, cd* v0, cd* ex0, cd* ZWpart_a,
-                          cd* ZWpart_b, hipStream_t st) {
-  launch_lambda_wave_t<cf>(sa, sb, nmax, NW, w0, WT, NG, g_chunk, Ta, Tb, LTa, LTb, Lam_a, Lam_b,
+void launch_lambda_wave32(const DevSpin& sa, const DevSpin& sb, int nmax, bool exact,
+                          bool prefetch, int NW, int w0, int WT, int NG, int g_chunk, const cf* Ta, const cf* Tb,
+                          const cf* LTa, const cf* LTb, cf* Lam_a, cf* Lam_b, cd* v0, cd* ex0,
+                          cd* ZWpart_a, cd* ZWpart_b, hipStream_t st) {
+  launch_lambda_wave_t<cf>(sa, sb, nmax, exact, prefetch, NW, w0, WT, NG, g_chunk, Ta, Tb, LTa, LTb, Lam_a, Lam_b,
                            v0, ex0, ZWpart_a, ZWpart_b, st);
 }
 
@@ -1136,167 +1176,9 @@ void launch_minor_coef(const DevSpin& s, int NW, const cd* B, int U, const cd* m
 
 constexpr int G_STAGE = 2;
 
-// Opposite-spin pairs: W_t = sum_g Lam^a[x_t] Lam^b[y_t] per pair (PAIRS_PER_THREAD
-// pairs per thread, kept in registers for the whole Cholesky range), then
-// sum_t coef_t W_t.
-constexpr int PAIRS_PER_THREAD = 8;
-constexpr int PAIR_THREADS = 512;
-
-__global__ __launch_bounds__(PAIR_THREADS) void k_energy_pairs(
-    DevPairs pr, int Xa, int Xb, int NW, int w0, int NG, int n_gsplit,
-    const cd* __restrict__ Lam_a, const cd* __restrict__ Lam_b, const cd* __restrict__ coef,
-    cd* __restrict__ partial, int n_slots, int slot0) {
-  extern __shared__ cd sm[];
-  __shared__ cd red[PAIR_THREADS];
-  const int wl = blockIdx.x, gs = blockIdx.y, pb = blockIdx.z;
-  const int w = w0 + wl, tid = threadIdx.x;
-  const int gper = (NG + n_gsplit - 1) / n_gsplit;
-  const int g0 = gs * gper, g1 = min(NG, g0 + gper);
-  const int X = Xa + Xb;
-  cd* buf[2] = {sm, sm + G_STAGE * X};
-  int xs[PAIRS_PER_THREAD], ys[PAIRS_PER_THREAD];
-  cd acc[PAIRS_PER_THREAD];
-#pragma unroll
-  for (int j = 0; j < PAIRS_PER_THREAD; ++j) {
-    const int t = pb * PAIR_THREADS * PAIRS_PER_THREAD + j * PAIR_THREADS + tid;
-    xs[j] = t < pr.n_pair ? pr.x[t] : -1;
-    ys[j] = t < pr.n_pair ? Xa + pr.y[t] : 0;
-    acc[j] = cd{0.0, 0.0};
-  }
-  auto stage = [&](int gb, cd* dst) {
-    const int G = min(G_STAGE, g1 - gb);
-    for (int e = tid; e < G * X; e += PAIR_THREADS) {
-      const int gl = e / X, x = e % X;
-      dst[e] = x < Xa ? Lam_a[((size_t)wl * NG + gb + gl) * Xa + x]
-                      : Lam_b[((size_t)wl * NG + gb + gl) * Xb + (x - Xa)];
-    }
-  };
-  if (g0 < g1) stage(g0, buf[0]);
-  __syncthreads();
-  int it = 0;
-  for (int gb = g0; gb < g1; gb += G_STAGE, ++it) {
-    if (gb + G_STAGE < g1) stage(gb + G_STAGE, buf[(it + 1) & 1]);
-    const cd* L = buf[it & 1];
-    const int G = min(G_STAGE, g1 - gb);
-    for (int gl = 0; gl < G; ++gl) {
-      const cd* Lg = L + gl * X;
-#pragma unroll
-      for (int j = 0; j < PAIRS_PER_THREAD; ++j)
-        if (xs[j] >= 0) cfma(acc[j], Lg[xs[j]], Lg[ys[j]]);
-    }
-    __syncthreads();
-  }
-  cd tot{0.0, 0.0};
-#pragma unroll
-  for (int j = 0; j < PAIRS_PER_THREAD; ++j) {
-    const int t = pb * PAIR_THREADS * PAIRS_PER_THREAD + j * PAIR_THREADS + tid;
-    if (xs[j] >= 0) cfma(tot, coef[(size_t)w * pr.n_pair + t], acc[j]);
-  }
-  red[tid] = tot;
-  __syncthreads();
-  for (int off = PAIR_THREADS / 2; off > 0; off >>= 1) {
-    if (tid < off) red[tid] += red[tid + off];
-    __syncthreads();
-  }
-  if (tid == 0)
-    partial[(size_t)w * n_slots + slot0 + (size_t)pb * n_gsplit + gs] = red[0];
-}
-
-// Same-spin terms per string of order K (2..4): the K x K block
-// Y_mn = Lam_g[p_n, h_m] is gathered once per Cholesky vector and all
-// C(K,2)^2 second-order minors are formed from registers:
-//   e2 = sum (-1)^{m+m'+n+n'} det X[~{m,m'},~{n,n'}] (Y_mn Y_m'n' - Y_mn' Y_m'n).
-constexpr int STR_THREADS = 256;
-
-template <int K>
-__global__ __launch_bounds__(STR_THREADS) void k_energy_strings(
-    DevSpin s, int NW, int w0, int NG, int n_gsplit, const cd* __restrict__ Lam,
-    const cd* __restrict__ m2, const cd* __restrict__ B, cd* __restrict__ partial, int n_slots,
-    int slot0) {
-  constexpr int P = K * (K - 1) / 2;
-  extern __shared__ cd sm[];
-  __shared__ cd red[STR_THREADS];
-  const int wl = blockIdx.x, gs = blockIdx.y, sc = blockIdx.z;
-  const int w = w0 + wl, tid = threadIdx.x;
-  const int X = s.nv * s.no;
-  const int gper = (NG + n_gsplit - 1) / n_gsplit;
-  const int g0 = gs * gper, g1 = min(NG, g0 + gper);
-  const int str = s.bucket[K] + sc * STR_THREADS + tid;
-  const bool live = str < s.bucket[K + 1];
-  cd* buf[2] = {sm, sm + G_STAGE * X};
-  int idx[K * K];
-  cd mm[P * P];
-#pragma unroll
-  for (int m = 0; m < K; ++m)
-#pragma unroll
-    for (int n = 0; n < K; ++n)
-      idx[m * K + n] = live ? s.pwin[str * KMAX + n] * s.no + s.hwin[str * KMAX + m] : 0;
-  if (live) {
-    const cd* src = m2 + (size_t)w * s.M2 + s.m2_off[str];
-#pragma unroll
-    for (int a = 0; a < P * P; ++a) mm[a] = src[a];
-  } else {
-#pragma unroll
-    for (int a = 0; a < P * P; ++a) mm[a] = cd{0.0, 0.0};
-  }
-  // fold the signs (-1)^{m+m'+n+n'} into the minors
-#pragma unroll
-  for (int m = 0; m < K; ++m)
-#pragma unroll
-    for (int mp = m + 1; mp < K; ++mp)
-#pragma unroll
-      for (int n = 0; n < K; ++n)
-#pragma unroll
-        for (int np = n + 1; np < K; ++np)
-          if ((m + mp + n + np) & 1) mm[pair_index(m, mp, K) * P + pair_index(n, np, K)] =
-              -mm[pair_index(m, mp, K) * P + pair_index(n, np, K)];
-  auto stage = [&](int gb, cd* dst) {
-    const int G = min(G_STAGE, g1 - gb);
-    for (int e = tid; e < G * X; e += STR_THREADS)
-      dst[e] = Lam[((size_t)wl * NG + gb) * X + e];
-  };
-  if (g0 < g1) stage(g0, buf[0]);
-  __syncthreads();
-  cd acc{0.0, 0.0};
-  int it = 0;
-  for (int gb = g0; gb < g1; gb += G_STAGE, ++it) {
-    if (gb + G_STAGE < g1) stage(gb + G_STAGE, buf[(it + 1) & 1]);
-    const cd* L = buf[it & 1];
-    const int G = min(G_STAGE, g1 - gb);
-    for (int gl = 0; gl < G; ++gl) {
-      const cd* Lg = L + gl * X;
-      cd Y[K * K];
-#pragma unroll
-      for (int a = 0; a < K * K; ++a) Y[a] = Lg[idx[a]];
-#pragma unroll
-      for (int m = 0; m < K; ++m)
-#pragma unroll
-        for (int mp = m + 1; mp < K; ++mp)
-#pragma unroll
-          for (int n = 0; n < K; ++n)
-#pragma unroll
-            for (int np = n + 1; np < K; ++np) {
-              const cd d2 = Y[m * K + n] * Y[mp * K + np] - Y[m * K + np] * Y[mp * K + n];
-              cfma(acc, mm[pair_index(m, mp, K) * P + pair_index(n, np, K)], d2);
-            }
-    }
-    __syncthreads();
-  }
-  cd tot{0.0, 0.0};
-  if (live) tot = B[(size_t)w * s.U + str] * acc;
-  red[tid] = tot;
-  __syncthreads();
-  for (int off = STR_THREADS / 2; off > 0; off >>= 1) {
-    if (tid < off) red[tid] += red[tid + off];
-    __syncthreads();
-  }
-  if (tid == 0)
-    partial[(size_t)w * n_slots + slot0 + (size_t)sc * n_gsplit + gs] = red[0];
-}
-
-// Same-spin terms through the trial's list of distinct second-order minors
-// (a < b, i < j): sum_t coef_t sum_g det2(Lam_g; a,b; i,j).  Preferred when the
-// excitation window is small and many strings share the same minors.
+// Same-spin terms as a list of distinct minors (orders above 6, or on
+// request): coef_t sum_g (Lam[a,i] Lam[b,j] - Lam[a,j] Lam[b,i]) per minor t,
+// 8 minors per thread.
 constexpr int MINOR_THREADS = 256;
 
 __global__ __launch_bounds__(MINOR_THREADS) void k_energy_minors(
@@ -1309,7 +1191,6 @@ __global__ __launch_bounds__(MINOR_THREADS) void k_energy_minors(
   const int X = s.nv * s.no;
   const int gper = (NG + n_gsplit - 1) / n_gsplit;
   const int g0 = gs * gper, g1 = min(NG, g0 + gper);
-  cd* buf[2] = {sm, sm + G_STAGE * X};
   constexpr int MPT = 8;
   int id[MPT][4];
   cd acc[MPT];
@@ -1317,30 +1198,30 @@ __global__ __launch_bounds__(MINOR_THREADS) void k_energy_minors(
   for (int j = 0; j < MPT; ++j) {
     const int t = mb * MINOR_THREADS * MPT + j * MINOR_THREADS + tid;
     const bool ok = t < s.n_minor;
+    // padding minors read entry 0 and are dropped below
 #pragma unroll
-    for (int q = 0; q < 4; ++q) id[j][q] = ok ? s.mn_idx[4 * t + q] : -1;
+    for (int q = 0; q < 4; ++q) id[j][q] = ok ? s.mn_idx[4 * t + q] : 0;
     acc[j] = cd{0.0, 0.0};
   }
-  auto stage = [&](int gb, cd* dst) {
+  // stage buffer b starts at sm[b * G_STAGE * X] (integer offsets keep LDS addressing)
+  auto stage = [&](int gb, int b) {
     const int G = min(G_STAGE, g1 - gb);
-    for (int e = tid; e < G * X; e += MINOR_THREADS)
-      dst[e] = Lam[((size_t)wl * NG + gb) * X + e];
+    const cd* src = Lam + ((size_t)wl * NG + gb) * X;
+    for (int e = tid; e < G * X; e += MINOR_THREADS) sm[b * G_STAGE * X + e] = src[e];
   };
-  if (g0 < g1) stage(g0, buf[0]);
+  if (g0 < g1) stage(g0, 0);
   __syncthreads();
   int it = 0;
   for (int gb = g0; gb < g1; gb += G_STAGE, ++it) {
-    if (gb + G_STAGE < g1) stage(gb + G_STAGE, buf[(it + 1) & 1]);
-    const cd* L = buf[it & 1];
+    if (gb + G_STAGE < g1) stage(gb + G_STAGE, (it + 1) & 1);
     const int G = min(G_STAGE, g1 - gb);
     for (int gl = 0; gl < G; ++gl) {
-      const cd* Lg = L + gl * X;
+      const int o = ((it & 1) * G_STAGE + gl) * X;
 #pragma unroll
-      for (int j = 0; j < MPT; ++j)
-        if (id[j][0] >= 0) {
-          cfma(acc[j], Lg[id[j][0]], Lg[id[j][1]]);
-          acc[j] -= Lg[id[j][2]] * Lg[id[j][3]];
-        }
+      for (int j = 0; j < MPT; ++j) {
+        cfma(acc[j], sm[o + id[j][0]], sm[o + id[j][1]]);
+        acc[j] -= sm[o + id[j][2]] * sm[o + id[j][3]];
+      }
     }
     __syncthreads();
   }
@@ -1348,7 +1229,7 @@ __global__ __launch_bounds__(MINOR_THREADS) void k_energy_minors(
 #pragma unroll
   for (int j = 0; j < MPT; ++j) {
     const int t = mb * MINOR_THREADS * MPT + j * MINOR_THREADS + tid;
-    if (id[j][0] >= 0) cfma(tot, coef[(size_t)w * s.n_minor + t], acc[j]);
+    if (t < s.n_minor) cfma(tot, coef[(size_t)w * s.n_minor + t], acc[j]);
   }
   red[tid] = tot;
   __syncthreads();
@@ -1359,14 +1240,6 @@ __global__ __launch_bounds__(MINOR_THREADS) void k_energy_minors(
   if (tid == 0)
     partial[(size_t)w * n_slots + slot0 + (size_t)mb * n_gsplit + gs] = red[0];
 }
-
-// ----------------------------------------------------------------------------
-// All second-order terms of a walker in one workgroup: each wave has one role
-// (ER_PAIRS: 8 opposite-spin pairs per lane; ER_STR2 / ER_STR3: one string of
-// that order per lane; ER_STR4: one order-4 string per lane pair, each lane
-// taking three of its six row pairs).  Lam^a and Lam^b of the workgroup's
-// Cholesky range stream through double-buffered LDS once.
-// ----------------------------------------------------------------------------
 
 // Row-pair items: one (string of order K, row pair m < m') per lane.  It needs
 // rows m and m' of Y_mn = Lam[p_n, h_m] (2K gathers per Cholesky vector) and
@@ -1401,13 +1274,16 @@ __device__ __forceinline__ void rp_setup(const int* __restrict__ hwin, const int
     }
 }
 
+// sm: the LDS array itself (indexed with an integer offset so the compiler
+// keeps LDS addressing instead of generic flat loads).
 template <int K, class CT>
-__device__ __forceinline__ void rp_eval(const CT* Lg, const int* idx, const CT* mm, CT& acc) {
+__device__ __forceinline__ void rp_eval(const CT* sm, int base, const int* idx, const CT* mm,
+                                        CT& acc) {
   CT y0[K], y1[K];
 #pragma unroll
   for (int n = 0; n < K; ++n) {
-    y0[n] = Lg[idx[n]];
-    y1[n] = Lg[idx[K + n]];
+    y0[n] = sm[base + idx[n]];
+    y1[n] = sm[base + idx[K + n]];
   }
   int q = 0;
 #pragma unroll
@@ -1446,7 +1322,6 @@ __global__ __launch_bounds__(512) void k_energy_second(
   const int Xa = sa.nv * sa.no, Xb = sb.nv * sb.no, X = Xa + Xb;
   const int gper = (NG + n_gsplit - 1) / n_gsplit;
   const int g0 = gs * gper, g1 = min(NG, g0 + gper);
-  CT* buf[2] = {sm, sm + (size_t)G * X};
   // plan entry of this wave: (role | spin << 8, first string of the order,
   // first item, item end)
   const int4 pl = plan[ib * waves_per_block + wave];
@@ -1491,43 +1366,42 @@ __global__ __launch_bounds__(512) void k_energy_second(
       }
     }
   }
-  auto stage = [&](int gb, CT* dst) {
+  // stage buffer b (0/1) starts at sm[b * G * X]: [alpha G x Xa][beta G x Xb]
+  auto stage = [&](int gb, int b) {
     const int Gs = min(G, g1 - gb);
     const CT* sa_ = Lam_a + ((size_t)wl * NG + gb) * Xa;
     const CT* sb_ = Lam_b + ((size_t)wl * NG + gb) * Xb;
-    for (int e = tid; e < Gs * Xa; e += blockDim.x) dst[e] = sa_[e];
-    CT* db = dst + (size_t)G * Xa;
-    for (int e = tid; e < Gs * Xb; e += blockDim.x) db[e] = sb_[e];
+    const int d0 = b * G * X, d1 = d0 + G * Xa;
+    for (int e = tid; e < Gs * Xa; e += blockDim.x) sm[d0 + e] = sa_[e];
+    for (int e = tid; e < Gs * Xb; e += blockDim.x) sm[d1 + e] = sb_[e];
   };
-  if (g0 < g1) stage(g0, buf[0]);
+  if (g0 < g1) stage(g0, 0);
   __syncthreads();
   int it = 0;
   for (int gb = g0; gb < g1; gb += G, ++it) {
-    if (gb + G < g1) stage(gb + G, buf[(it + 1) & 1]);
-    const CT* La = buf[it & 1];
-    const CT* Lb = La + (size_t)G * Xa;
+    if (gb + G < g1) stage(gb + G, (it + 1) & 1);
+    const int oa = (it & 1) * G * X, ob = oa + G * Xa;
     const int Gs = min(G, g1 - gb);
     if (live) {
       if (role == ER_PAIRS) {
 #pragma unroll 2
         for (int gl = 0; gl < Gs; ++gl) {
-          const CT* x = La + gl * Xa;
-          const CT* y = Lb + gl * Xb;
+          const int x = oa + gl * Xa, y = ob + gl * Xb;
 #pragma unroll
-          for (int j = 0; j < ER_PPL; ++j) cfma(acc[j], x[idx[j]], y[idx[ER_PPL + j]]);
+          for (int j = 0; j < ER_PPL; ++j) cfma(acc[j], sm[x + idx[j]], sm[y + idx[ER_PPL + j]]);
         }
       } else {
-        const CT* Ls = sp ? Lb : La;
+        const int os = sp ? ob : oa;
         const int Xs = sp ? Xb : Xa;
 #pragma unroll 2
         for (int gl = 0; gl < Gs; ++gl) {
-          const CT* Lg = Ls + gl * Xs;
+          const int base = os + gl * Xs;
           switch (role) {
-            case 2: rp_eval<2, CT>(Lg, idx, mm, acc[0]); break;
-            case 3: rp_eval<3, CT>(Lg, idx, mm, acc[0]); break;
-            case 4: rp_eval<4, CT>(Lg, idx, mm, acc[0]); break;
-            case 5: if constexpr (MAXK >= 5) rp_eval<5 <= MAXK ? 5 : 2, CT>(Lg, idx, mm, acc[0]); break;
-            default: if constexpr (MAXK >= 6) rp_eval<6 <= MAXK ? 6 : 2, CT>(Lg, idx, mm, acc[0]); break;
+            case 2: rp_eval<2, CT>(sm, base, idx, mm, acc[0]); break;
+            case 3: rp_eval<3, CT>(sm, base, idx, mm, acc[0]); break;
+            case 4: rp_eval<4, CT>(sm, base, idx, mm, acc[0]); break;
+            case 5: if constexpr (MAXK >= 5) rp_eval<5 <= MAXK ? 5 : 2, CT>(sm, base, idx, mm, acc[0]); break;
+            default: if constexpr (MAXK >= 6) rp_eval<6 <= MAXK ? 6 : 2, CT>(sm, base, idx, mm, acc[0]); break;
           }
         }
       }
@@ -1596,39 +1470,8 @@ void launch_energy_second32(const DevSpin& sa, const DevSpin& sb, const DevPairs
                              partial, n_slots, slot0, st);
 }
 
-int energy_pair_blocks(int n_pair) {
-  return (n_pair + PAIR_THREADS * PAIRS_PER_THREAD - 1) / (PAIR_THREADS * PAIRS_PER_THREAD);
-}
-int energy_string_blocks(const DevSpin& s, int k) {
-  return (s.bucket[k + 1] - s.bucket[k] + STR_THREADS - 1) / STR_THREADS;
-}
 int energy_minor_blocks(const DevSpin& s) {
   return (s.n_minor + MINOR_THREADS * 8 - 1) / (MINOR_THREADS * 8);
-}
-
-void launch_energy_pairs(const DevPairs& pr, int Xa, int Xb, int NW, int w0, int WT, int NG,
-                         int n_gsplit, const cd* Lam_a, const cd* Lam_b, const cd* coef,
-                         cd* partial, int n_slots, int slot0, hipStream_t st) {
-  const int nb = energy_pair_blocks(pr.n_pair);
-  if (nb == 0) return;
-  const size_t lds = 2 * (size_t)G_STAGE * (Xa + Xb) * sizeof(cd);
-  hipLaunchKernelGGL(k_energy_pairs, dim3(WT, n_gsplit, nb), dim3(PAIR_THREADS), lds, st, pr, Xa,
-                     Xb, NW, w0, NG, n_gsplit, Lam_a, Lam_b, coef, partial, n_slots, slot0);
-}
-
-void launch_energy_strings(const DevSpin& s, int k, int NW, int w0, int WT, int NG, int n_gsplit,
-                           const cd* Lam, const cd* m2, const cd* B, cd* partial, int n_slots,
-                           int slot0, hipStream_t st) {
-  const int nb = energy_string_blocks(s, k);
-  if (nb == 0) return;
-  const size_t lds = 2 * (size_t)G_STAGE * s.nv * s.no * sizeof(cd);
-  dim3 grid(WT, n_gsplit, nb);
-  switch (k) {
-    case 2: hipLaunchKernelGGL(k_energy_strings<2>, grid, dim3(STR_THREADS), lds, st, s, NW, w0, NG, n_gsplit, Lam, m2, B, partial, n_slots, slot0); break;
-    case 3: hipLaunchKernelGGL(k_energy_strings<3>, grid, dim3(STR_THREADS), lds, st, s, NW, w0, NG, n_gsplit, Lam, m2, B, partial, n_slots, slot0); break;
-    case 4: hipLaunchKernelGGL(k_energy_strings<4>, grid, dim3(STR_THREADS), lds, st, s, NW, w0, NG, n_gsplit, Lam, m2, B, partial, n_slots, slot0); break;
-    default: break;
-  }
 }
 
 void launch_energy_minors(const DevSpin& s, int NW, int w0, int WT, int NG, int n_gsplit,
@@ -1722,15 +1565,11 @@ void init_wick_attributes() {
   hipFuncSetAttribute((const void*)k_ref_inverse, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   hipFuncSetAttribute((const void*)k_green, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   hipFuncSetAttribute((const void*)k_lambda, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-  hipFuncSetAttribute((const void*)k_energy_pairs, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   hipFuncSetAttribute((const void*)k_energy_second<cd, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   hipFuncSetAttribute((const void*)k_energy_second<cf, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   hipFuncSetAttribute((const void*)k_energy_second<cd, ER_MAX_ORDER>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   hipFuncSetAttribute((const void*)k_energy_second<cf, ER_MAX_ORDER>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   hipFuncSetAttribute((const void*)k_energy_minors, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-  hipFuncSetAttribute((const void*)k_energy_strings<2>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-  hipFuncSetAttribute((const void*)k_energy_strings<3>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-  hipFuncSetAttribute((const void*)k_energy_strings<4>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
 }
 
 }  // namespace msd

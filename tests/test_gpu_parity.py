@@ -536,6 +536,7 @@ def test_uneven_batch_graph_matches_separate_systems():
     dict(lambda_variant=1, lambda_chunk=5, second_gsplit=3, second_stage=1, fb_splitk=1),
     dict(lambda_variant=2, lambda_chunk=7, second_gsplit=1, second_stage=3, fb_splitk=3),
     dict(lambda_variant=2, lambda_chunk=32, second_gsplit=8, second_stage=4, fb_splitk=16),
+    dict(lambda_variant=3, lambda_chunk=11, second_gsplit=2, second_stage=2, fb_splitk=4),
 ])
 def test_tuning_overrides_keep_parity(tuning):
     """Ragged Cholesky chunks and stages (320 vectors split 5/7/3 ways) in
@@ -556,7 +557,7 @@ def test_autotune_picks_valid_shapes_and_keeps_results():
     for precision in ("fp64", "mixed"):
         s = system_for(wl, precision=precision)
         t = s.autotune(wl.dt, reps=2)
-        assert 1 <= t["fb_splitk"] <= 16 and t["lambda_variant"] in (1, 2)
+        assert 1 <= t["fb_splitk"] <= 16 and t["lambda_variant"] in (1, 2, 3)
         assert t["lambda_chunk"] >= 1 and t["second_gsplit"] >= 1 and t["second_stage"] >= 1
         out = s.measure(wl.dt)
         np.testing.assert_array_equal(out["log_ovlp"], ref["log_ovlp"])
