@@ -175,7 +175,8 @@ class MsdSystem:
             out["force_bias"] = fb
         return out
 
-    _TUNING = ("fb_splitk", "lambda_variant", "lambda_chunk", "second_gsplit", "second_stage")
+    _TUNING = ("fb_splitk", "lambda_variant", "lambda_chunk", "second_gsplit", "second_stage",
+               "second_gather")
 
     def get_tuning(self):
         t = _lib.MsdTuning()

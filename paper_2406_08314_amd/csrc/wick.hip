@@ -1274,8 +1274,8 @@ __device__ __forceinline__ void rp_setup(const int* __restrict__ hwin, const int
     }
 }
 
-// sm: the LDS array itself (indexed with an integer offset so the compiler
-// keeps LDS addressing instead of generic flat loads).
+// sm: the LDS stage (indexed with an integer offset, so with the LDS array
+// itself the compiler emits LDS instructions).
 template <int K, class CT>
 __device__ __forceinline__ void rp_eval(const CT* sm, int base, const int* idx, const CT* mm,
                                         CT& acc) {
@@ -1299,7 +1299,10 @@ __device__ __forceinline__ void rp_eval(const CT* sm, int base, const int* idx, 
 // [alpha: G x Xa][beta: G x Xb] so each stage is two contiguous copies.
 constexpr int ER_PPL = 4;  // opposite-spin pairs per lane
 
-template <class CT, int MAXK>
+// FLATG: gather through a generic (flat) pointer to the LDS stage instead of
+// LDS instructions.  The two paths group a wave's random 16-byte reads
+// differently; which is faster is measured (launch-shape tuning).
+template <class CT, int MAXK, bool FLATG>
 __global__ __launch_bounds__(512) void k_energy_second(
     DevSpin sa, DevSpin sb, DevPairs pr, const int4* __restrict__ plan, int n_ib,
     int waves_per_block, int NW, int w0, int NG, int n_gsplit, int G, const CT* __restrict__ Lam_a,
@@ -1375,6 +1378,12 @@ __global__ __launch_bounds__(512) void k_energy_second(
     for (int e = tid; e < Gs * Xa; e += blockDim.x) sm[d0 + e] = sa_[e];
     for (int e = tid; e < Gs * Xb; e += blockDim.x) sm[d1 + e] = sb_[e];
   };
+  const CT* gs_ = sm;
+  if constexpr (FLATG) {
+    uintptr_t u = reinterpret_cast<uintptr_t>(gs_);
+    asm volatile("" : "+s"(u));  // opaque: the compiler cannot tell it is LDS
+    gs_ = reinterpret_cast<const CT*>(u);
+  }
   if (g0 < g1) stage(g0, 0);
   __syncthreads();
   int it = 0;
@@ -1388,7 +1397,7 @@ __global__ __launch_bounds__(512) void k_energy_second(
         for (int gl = 0; gl < Gs; ++gl) {
           const int x = oa + gl * Xa, y = ob + gl * Xb;
 #pragma unroll
-          for (int j = 0; j < ER_PPL; ++j) cfma(acc[j], sm[x + idx[j]], sm[y + idx[ER_PPL + j]]);
+          for (int j = 0; j < ER_PPL; ++j) cfma(acc[j], gs_[x + idx[j]], gs_[y + idx[ER_PPL + j]]);
         }
       } else {
         const int os = sp ? ob : oa;
@@ -1397,11 +1406,11 @@ __global__ __launch_bounds__(512) void k_energy_second(
         for (int gl = 0; gl < Gs; ++gl) {
           const int base = os + gl * Xs;
           switch (role) {
-            case 2: rp_eval<2, CT>(sm, base, idx, mm, acc[0]); break;
-            case 3: rp_eval<3, CT>(sm, base, idx, mm, acc[0]); break;
-            case 4: rp_eval<4, CT>(sm, base, idx, mm, acc[0]); break;
-            case 5: if constexpr (MAXK >= 5) rp_eval<5 <= MAXK ? 5 : 2, CT>(sm, base, idx, mm, acc[0]); break;
-            default: if constexpr (MAXK >= 6) rp_eval<6 <= MAXK ? 6 : 2, CT>(sm, base, idx, mm, acc[0]); break;
+            case 2: rp_eval<2, CT>(gs_, base, idx, mm, acc[0]); break;
+            case 3: rp_eval<3, CT>(gs_, base, idx, mm, acc[0]); break;
+            case 4: rp_eval<4, CT>(gs_, base, idx, mm, acc[0]); break;
+            case 5: if constexpr (MAXK >= 5) rp_eval<5 <= MAXK ? 5 : 2, CT>(gs_, base, idx, mm, acc[0]); break;
+            default: if constexpr (MAXK >= 6) rp_eval<6 <= MAXK ? 6 : 2, CT>(gs_, base, idx, mm, acc[0]); break;
           }
         }
       }
@@ -1432,41 +1441,43 @@ template <class CT>
 static void launch_energy_second_t(const DevSpin& sa, const DevSpin& sb, const DevPairs& pr,
                                    const int4* plan, int n_itemblocks, int waves_per_block, int NW,
                                    int w0, int WT, int NG, int n_gsplit, int G, int max_order,
-                                   const CT* Lam_a, const CT* Lam_b, const cd* coef,
+                                   bool flat_gather, const CT* Lam_a, const CT* Lam_b, const cd* coef,
                                    const cd* m2a, const cd* m2b, const cd* Ba, const cd* Bb,
                                    cd* partial, int n_slots, int slot0, hipStream_t st) {
   if (n_itemblocks == 0) return;
   const size_t lds = 2 * (size_t)G * (sa.nv * sa.no + sb.nv * sb.no) * sizeof(CT);
   const dim3 grid(WT * n_gsplit * n_itemblocks), block(64 * waves_per_block);
-  if (max_order <= 4)
-    hipLaunchKernelGGL((k_energy_second<CT, 4>), grid, block, lds, st, sa, sb, pr, plan,
-                       n_itemblocks, waves_per_block, NW, w0, NG, n_gsplit, G, Lam_a, Lam_b,
-                       coef, m2a, m2b, Ba, Bb, partial, n_slots, slot0);
-  else
-    hipLaunchKernelGGL((k_energy_second<CT, ER_MAX_ORDER>), grid, block, lds, st, sa, sb, pr,
-                       plan, n_itemblocks, waves_per_block, NW, w0, NG, n_gsplit, G, Lam_a,
-                       Lam_b, coef, m2a, m2b, Ba, Bb, partial, n_slots, slot0);
+#define MSD_ES(MK, FL)                                                                       \
+  hipLaunchKernelGGL((k_energy_second<CT, MK, FL>), grid, block, lds, st, sa, sb, pr, plan,   \
+                     n_itemblocks, waves_per_block, NW, w0, NG, n_gsplit, G, Lam_a, Lam_b, coef, \
+                     m2a, m2b, Ba, Bb, partial, n_slots, slot0)
+  if (max_order <= 4) {
+    if (flat_gather) MSD_ES(4, true); else MSD_ES(4, false);
+  } else {
+    if (flat_gather) MSD_ES(ER_MAX_ORDER, true); else MSD_ES(ER_MAX_ORDER, false);
+  }
+#undef MSD_ES
 }
 
 void launch_energy_second(const DevSpin& sa, const DevSpin& sb, const DevPairs& pr,
                           const int4* plan, int n_itemblocks, int waves_per_block, int NW, int w0,
-                          int WT, int NG, int n_gsplit, int G, int max_order, const cd* Lam_a,
-                          const cd* Lam_b, const cd* coef, const cd* m2a, const cd* m2b,
-                          const cd* Ba, const cd* Bb, cd* partial, int n_slots, int slot0,
-                          hipStream_t st) {
+                          int WT, int NG, int n_gsplit, int G, int max_order, bool flat_gather,
+                          const cd* Lam_a, const cd* Lam_b, const cd* coef, const cd* m2a,
+                          const cd* m2b, const cd* Ba, const cd* Bb, cd* partial, int n_slots,
+                          int slot0, hipStream_t st) {
   launch_energy_second_t<cd>(sa, sb, pr, plan, n_itemblocks, waves_per_block, NW, w0, WT, NG,
-                             n_gsplit, G, max_order, Lam_a, Lam_b, coef, m2a, m2b, Ba, Bb,
+                             n_gsplit, G, max_order, flat_gather, Lam_a, Lam_b, coef, m2a, m2b, Ba, Bb,
                              partial, n_slots, slot0, st);
 }
 
 void launch_energy_second32(const DevSpin& sa, const DevSpin& sb, const DevPairs& pr,
                             const int4* plan, int n_itemblocks, int waves_per_block, int NW,
                             int w0, int WT, int NG, int n_gsplit, int G, int max_order,
-                            const cf* Lam_a, const cf* Lam_b, const cd* coef, const cd* m2a,
-                            const cd* m2b, const cd* Ba, const cd* Bb, cd* partial, int n_slots,
-                            int slot0, hipStream_t st) {
+                            bool flat_gather, const cf* Lam_a, const cf* Lam_b, const cd* coef,
+                            const cd* m2a, const cd* m2b, const cd* Ba, const cd* Bb,
+                            cd* partial, int n_slots, int slot0, hipStream_t st) {
   launch_energy_second_t<cf>(sa, sb, pr, plan, n_itemblocks, waves_per_block, NW, w0, WT, NG,
-                             n_gsplit, G, max_order, Lam_a, Lam_b, coef, m2a, m2b, Ba, Bb,
+                             n_gsplit, G, max_order, flat_gather, Lam_a, Lam_b, coef, m2a, m2b, Ba, Bb,
                              partial, n_slots, slot0, st);
 }
 
@@ -1565,10 +1576,15 @@ void init_wick_attributes() {
   hipFuncSetAttribute((const void*)k_ref_inverse, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   hipFuncSetAttribute((const void*)k_green, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   hipFuncSetAttribute((const void*)k_lambda, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-  hipFuncSetAttribute((const void*)k_energy_second<cd, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-  hipFuncSetAttribute((const void*)k_energy_second<cf, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-  hipFuncSetAttribute((const void*)k_energy_second<cd, ER_MAX_ORDER>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-  hipFuncSetAttribute((const void*)k_energy_second<cf, ER_MAX_ORDER>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  for (const void* f : {(const void*)k_energy_second<cd, 4, false>,
+                        (const void*)k_energy_second<cd, 4, true>,
+                        (const void*)k_energy_second<cf, 4, false>,
+                        (const void*)k_energy_second<cf, 4, true>,
+                        (const void*)k_energy_second<cd, ER_MAX_ORDER, false>,
+                        (const void*)k_energy_second<cd, ER_MAX_ORDER, true>,
+                        (const void*)k_energy_second<cf, ER_MAX_ORDER, false>,
+                        (const void*)k_energy_second<cf, ER_MAX_ORDER, true>})
+    hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   hipFuncSetAttribute((const void*)k_energy_minors, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
 }
 
