@@ -1303,7 +1303,7 @@ constexpr int ER_PPL = 4;  // opposite-spin pairs per lane
 // LDS instructions.  The two paths group a wave's random 16-byte reads
 // differently; which is faster is measured (launch-shape tuning).
 template <class CT, int MAXK, bool FLATG>
-__global__ __launch_bounds__(512) void k_energy_second(
+__global__ __launch_bounds__(512, (MAXK <= 4 ? 4 : 2)) void k_energy_second(
     DevSpin sa, DevSpin sb, DevPairs pr, const int4* __restrict__ plan, int n_ib,
     int waves_per_block, int NW, int w0, int NG, int n_gsplit, int G, const CT* __restrict__ Lam_a,
     const CT* __restrict__ Lam_b, const cd* __restrict__ coef, const cd* __restrict__ m2a,
