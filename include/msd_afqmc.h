@@ -219,14 +219,18 @@ typedef struct {
                              (1..32, bounded by 150 KB of LDS)                             */
   int32_t second_gather;  /* second-order kernel reads its LDS stage with 1 = LDS
                              instructions, 2 = generic (flat) loads                       */
-  int32_t reserved[2];
+  int32_t second_copy;    /* second-order kernel fills its LDS stage 1 = through
+                             registers, 2 = by direct global-to-LDS loads (where the
+                             Lambda rows are 16-byte aligned; else through registers)   */
+  int32_t reserved[1];
 } msd_tuning;
 msd_status msd_get_tuning(msd_system* sys, msd_tuning* out);
 /* Sets overrides (validated; MSD_ERR_ARG names the bad field).  Drops the
  * energy plan and recorded graphs; they are rebuilt on the next call. */
 msd_status msd_set_tuning(msd_system* sys, const msd_tuning* t);
 /* Autotuner: times candidate values of each field in turn (fb_splitk,
- * lambda_variant, lambda_chunk, second_gather, second_gsplit, second_stage) over `reps`
+ * lambda_variant, lambda_chunk, second_gather, second_copy, second_gsplit,
+ * second_stage) over `reps`
  * measurements with energies of the current walkers (time step dt), keeps the
  * fastest and leaves it set (*out, if not NULL, receives it).  Overwrites the
  * last-measurement buffers; walkers are unchanged.  Needs walkers. */

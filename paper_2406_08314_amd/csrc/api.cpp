@@ -159,6 +159,7 @@ struct msd_system {
   int4* plan = nullptr;
   int n_itemblocks = 0, slot_second = 0, second_G = 1, second_maxk = 0;
   bool second_flat = false;  // gathers through a generic pointer (see k_energy_second)
+  bool second_dma = true;    // stages Lambda by direct global-to-LDS loads
   cd* LT[2] = {nullptr, nullptr};
   cd* Lam[2] = {nullptr, nullptr};
   cd* v0 = nullptr;
@@ -400,9 +401,8 @@ void alloc_energy(msd_system* s) {
     if (s->tune.second_stage > 0)
       s->second_G = std::max(1, std::min(s->tune.second_stage,
                                          (int)((150 << 10) / (2 * elem * std::max(X, 1)))));
-    // default gather path per precision (measured: flat for 16-byte FP64
-    // entries, LDS instructions for 8-byte FP32 entries)
-    s->second_flat = s->tune.second_gather ? s->tune.second_gather == 2 : !s->energy_mixed;
+    s->second_flat = s->tune.second_gather == 2;
+    s->second_dma = s->tune.second_copy != 1;
     s->lambda_exact = rows_fit && A.N == nmax && B.N == nmax;
     for (int sp = 0; sp < 2 && s->lambda_exact; ++sp) {
       const msd::SpinTable& S = s->tt.s[sp];
@@ -627,7 +627,7 @@ void run_energy_mixed(msd_system* s) {
     s->timed(ST_EGAMMA, [&] {
       msd::launch_energy_second32(A, B, s->dp, s->plan, s->n_itemblocks, msd::ER_WAVES, s->NW,
                                   w0, wt, s->NG, s->gsplit, s->second_G, s->second_maxk,
-                                  s->second_flat,
+                                  s->second_flat, s->second_dma,
                                   s->Lam32[0],
                                   s->Lam32[1], s->coefAB, s->sw[0].m2, s->sw[1].m2, s->sw[0].B,
                                   s->sw[1].B, s->epart, s->n_slots, s->slot_second, s->st);
@@ -708,7 +708,7 @@ void run_energy(msd_system* s) {
     s->timed(ST_EGAMMA, [&] {
       msd::launch_energy_second(A, B, s->dp, s->plan, s->n_itemblocks, msd::ER_WAVES, s->NW, w0,
                                 wt, s->NG, s->gsplit, s->second_G, s->second_maxk,
-                                s->second_flat, s->Lam[0],
+                                s->second_flat, s->second_dma, s->Lam[0],
                                 s->Lam[1],
                                 s->coefAB, s->sw[0].m2, s->sw[1].m2, s->sw[0].B, s->sw[1].B,
                                 s->epart, s->n_slots, s->slot_second, s->st);
@@ -1722,6 +1722,7 @@ void set_tuning_impl(msd_system* s, const msd_tuning& t) {
   if (t.second_gsplit < 0 || t.second_gsplit > 64) bad("second_gsplit");
   if (t.second_stage < 0 || t.second_stage > 32) bad("second_stage");
   if (t.second_gather < 0 || t.second_gather > 2) bad("second_gather");
+  if (t.second_copy < 0 || t.second_copy > 2) bad("second_copy");
   s->tune = t;
   free_energy(s);
   s->drop_graphs();
@@ -1755,6 +1756,7 @@ msd_status msd_get_tuning(msd_system* sys, msd_tuning* out) {
     out->second_gsplit = sys->gsplit;
     out->second_stage = sys->second_G;
     out->second_gather = sys->second_flat ? 2 : 1;
+    out->second_copy = sys->second_dma ? 2 : 1;
   }
   API_END(sys)
 }
@@ -1801,6 +1803,7 @@ msd_status msd_autotune(msd_system* sys, double dt, int32_t reps, msd_tuning* ou
       sweep(&msd_tuning::lambda_variant, {1, 2, 3});
     sweep(&msd_tuning::lambda_chunk, {4, 8, 16, 32});
     sweep(&msd_tuning::second_gather, {1, 2});
+    sweep(&msd_tuning::second_copy, {1, 2});
     sweep(&msd_tuning::second_gsplit, {1, 2, 4, 8});
     {
       const int X = sys->ds[0].nv * sys->ds[0].no + sys->ds[1].nv * sys->ds[1].no;
@@ -1827,6 +1830,7 @@ msd_status msd_autotune(msd_system* sys, double dt, int32_t reps, msd_tuning* ou
     out->second_gsplit = sys->gsplit;
     out->second_stage = sys->second_G;
     out->second_gather = sys->second_flat ? 2 : 1;
+    out->second_copy = sys->second_dma ? 2 : 1;
   }
   API_END(sys)
 }

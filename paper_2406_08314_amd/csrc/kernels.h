@@ -167,17 +167,17 @@ constexpr int ER_PAIRS_PER_WAVE = 256;  // 64 lanes x 4 pairs
 void launch_energy_second(const DevSpin& sa, const DevSpin& sb, const DevPairs& pr,
                           const int4* plan, int n_itemblocks, int waves_per_block, int NW, int w0,
                           int WT, int NG, int n_gsplit, int G, int max_order, bool flat_gather,
-                          const cd* Lam_a, const cd* Lam_b, const cd* coef, const cd* m2a,
-                          const cd* m2b, const cd* Ba, const cd* Bb, cd* partial, int n_slots,
-                          int slot0, hipStream_t st);
+                          bool use_dma, const cd* Lam_a, const cd* Lam_b, const cd* coef,
+                          const cd* m2a, const cd* m2b, const cd* Ba, const cd* Bb, cd* partial,
+                          int n_slots, int slot0, hipStream_t st);
 // Same with single-precision Lambda (mixed form); the minors, CI weights and
 // the final products stay in double.
 void launch_energy_second32(const DevSpin& sa, const DevSpin& sb, const DevPairs& pr,
                             const int4* plan, int n_itemblocks, int waves_per_block, int NW,
                             int w0, int WT, int NG, int n_gsplit, int G, int max_order,
-                            bool flat_gather, const cf* Lam_a, const cf* Lam_b, const cd* coef,
-                            const cd* m2a, const cd* m2b, const cd* Ba, const cd* Bb,
-                            cd* partial, int n_slots, int slot0, hipStream_t st);
+                            bool flat_gather, bool use_dma, const cf* Lam_a, const cf* Lam_b,
+                            const cd* coef, const cd* m2a, const cd* m2b, const cd* Ba,
+                            const cd* Bb, cd* partial, int n_slots, int slot0, hipStream_t st);
 int energy_minor_blocks(const DevSpin& s);
 void launch_energy_minors(const DevSpin& s, int NW, int w0, int WT, int NG, int n_gsplit,
                           const cd* Lam, const cd* coef, cd* partial, int n_slots, int slot0,

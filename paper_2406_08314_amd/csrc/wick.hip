@@ -1299,6 +1299,15 @@ __device__ __forceinline__ void rp_eval(const CT* sm, int base, const int* idx, 
 // [alpha: G x Xa][beta: G x Xb] so each stage is two contiguous copies.
 constexpr int ER_PPL = 4;  // opposite-spin pairs per lane
 
+// Direct global-to-LDS load of 16 bytes per lane: lane i of the wave writes
+// lds + 16 i (lds must be wave-uniform).  Device-only instruction; the host
+// pass of this file sees an empty body.
+__device__ __forceinline__ void lds_dma16(const void* g, void* lds) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void*)lds, 16, 0, 0);
+#endif
+}
+
 // FLATG: gather through a generic (flat) pointer to the LDS stage instead of
 // LDS instructions.  The two paths group a wave's random 16-byte reads
 // differently; which is faster is measured (launch-shape tuning).
@@ -1308,7 +1317,7 @@ __global__ __launch_bounds__(512, (MAXK <= 4 ? 4 : 2)) void k_energy_second(
     int waves_per_block, int NW, int w0, int NG, int n_gsplit, int G, const CT* __restrict__ Lam_a,
     const CT* __restrict__ Lam_b, const cd* __restrict__ coef, const cd* __restrict__ m2a,
     const cd* __restrict__ m2b, const cd* __restrict__ Ba, const cd* __restrict__ Bb,
-    cd* __restrict__ partial, int n_slots, int slot0) {
+    cd* __restrict__ partial, int n_slots, int slot0, bool lds_dma) {
   constexpr int NIDX = 2 * MAXK > 2 * ER_PPL ? 2 * MAXK : 2 * ER_PPL;
   constexpr int NMM = MAXK * (MAXK - 1) / 2;
   extern __shared__ __align__(16) unsigned char sm_raw[];
@@ -1369,14 +1378,30 @@ __global__ __launch_bounds__(512, (MAXK <= 4 ? 4 : 2)) void k_energy_second(
       }
     }
   }
-  // stage buffer b (0/1) starts at sm[b * G * X]: [alpha G x Xa][beta G x Xb]
+  // stage buffer b (0/1) starts at sm[b * G * X]: [alpha G x Xa][beta G x Xb].
+  // With lds_dma the copies are direct global-to-LDS loads (16 bytes per lane,
+  // each wave filling 1 KB runs), which need no registers and no wait before
+  // the next stage's arithmetic; the host enables it when every run start is
+  // 16-byte aligned.
+  const int nwaves = blockDim.x >> 6;
+  auto copy = [&](const CT* src, int dst, int n) {
+    if (lds_dma) {
+      constexpr int per = 16 / sizeof(CT);  // elements per 16-byte lane load
+      const int n16 = n / per;
+      for (int c = wave; c * 64 < n16; c += nwaves) {
+        const int e = c * 64 + lane;
+        if (e < n16)
+          lds_dma16(src + (size_t)e * per, sm + dst + c * 64 * per);
+      }
+    } else {
+      for (int e = tid; e < n; e += blockDim.x) sm[dst + e] = src[e];
+    }
+  };
   auto stage = [&](int gb, int b) {
     const int Gs = min(G, g1 - gb);
-    const CT* sa_ = Lam_a + ((size_t)wl * NG + gb) * Xa;
-    const CT* sb_ = Lam_b + ((size_t)wl * NG + gb) * Xb;
-    const int d0 = b * G * X, d1 = d0 + G * Xa;
-    for (int e = tid; e < Gs * Xa; e += blockDim.x) sm[d0 + e] = sa_[e];
-    for (int e = tid; e < Gs * Xb; e += blockDim.x) sm[d1 + e] = sb_[e];
+    const int d0 = b * G * X;
+    copy(Lam_a + ((size_t)wl * NG + gb) * Xa, d0, Gs * Xa);
+    copy(Lam_b + ((size_t)wl * NG + gb) * Xb, d0 + G * Xa, Gs * Xb);
   };
   const CT* gs_ = sm;
   if constexpr (FLATG) {
@@ -1441,7 +1466,7 @@ template <class CT>
 static void launch_energy_second_t(const DevSpin& sa, const DevSpin& sb, const DevPairs& pr,
                                    const int4* plan, int n_itemblocks, int waves_per_block, int NW,
                                    int w0, int WT, int NG, int n_gsplit, int G, int max_order,
-                                   bool flat_gather, const CT* Lam_a, const CT* Lam_b, const cd* coef,
+                                   bool flat_gather, bool use_dma, const CT* Lam_a, const CT* Lam_b, const cd* coef,
                                    const cd* m2a, const cd* m2b, const cd* Ba, const cd* Bb,
                                    cd* partial, int n_slots, int slot0, hipStream_t st) {
   if (n_itemblocks == 0) return;
@@ -1450,7 +1475,11 @@ static void launch_energy_second_t(const DevSpin& sa, const DevSpin& sb, const D
 #define MSD_ES(MK, FL)                                                                       \
   hipLaunchKernelGGL((k_energy_second<CT, MK, FL>), grid, block, lds, st, sa, sb, pr, plan,   \
                      n_itemblocks, waves_per_block, NW, w0, NG, n_gsplit, G, Lam_a, Lam_b, coef, \
-                     m2a, m2b, Ba, Bb, partial, n_slots, slot0)
+                     m2a, m2b, Ba, Bb, partial, n_slots, slot0, lds_dma)
+  // direct LDS loads need 16-byte aligned runs: every Lambda row of both spins
+  // (and each spin's stage region) starts on a 16-byte boundary
+  const int per = 16 / (int)sizeof(CT);
+  const bool lds_dma = use_dma && (sa.nv * sa.no) % per == 0 && (sb.nv * sb.no) % per == 0;
   if (max_order <= 4) {
     if (flat_gather) MSD_ES(4, true); else MSD_ES(4, false);
   } else {
@@ -1462,22 +1491,22 @@ static void launch_energy_second_t(const DevSpin& sa, const DevSpin& sb, const D
 void launch_energy_second(const DevSpin& sa, const DevSpin& sb, const DevPairs& pr,
                           const int4* plan, int n_itemblocks, int waves_per_block, int NW, int w0,
                           int WT, int NG, int n_gsplit, int G, int max_order, bool flat_gather,
-                          const cd* Lam_a, const cd* Lam_b, const cd* coef, const cd* m2a,
-                          const cd* m2b, const cd* Ba, const cd* Bb, cd* partial, int n_slots,
-                          int slot0, hipStream_t st) {
+                          bool use_dma, const cd* Lam_a, const cd* Lam_b, const cd* coef,
+                          const cd* m2a, const cd* m2b, const cd* Ba, const cd* Bb, cd* partial,
+                          int n_slots, int slot0, hipStream_t st) {
   launch_energy_second_t<cd>(sa, sb, pr, plan, n_itemblocks, waves_per_block, NW, w0, WT, NG,
-                             n_gsplit, G, max_order, flat_gather, Lam_a, Lam_b, coef, m2a, m2b, Ba, Bb,
+                             n_gsplit, G, max_order, flat_gather, use_dma, Lam_a, Lam_b, coef, m2a, m2b, Ba, Bb,
                              partial, n_slots, slot0, st);
 }
 
 void launch_energy_second32(const DevSpin& sa, const DevSpin& sb, const DevPairs& pr,
                             const int4* plan, int n_itemblocks, int waves_per_block, int NW,
                             int w0, int WT, int NG, int n_gsplit, int G, int max_order,
-                            bool flat_gather, const cf* Lam_a, const cf* Lam_b, const cd* coef,
-                            const cd* m2a, const cd* m2b, const cd* Ba, const cd* Bb,
-                            cd* partial, int n_slots, int slot0, hipStream_t st) {
+                            bool flat_gather, bool use_dma, const cf* Lam_a, const cf* Lam_b,
+                            const cd* coef, const cd* m2a, const cd* m2b, const cd* Ba,
+                            const cd* Bb, cd* partial, int n_slots, int slot0, hipStream_t st) {
   launch_energy_second_t<cf>(sa, sb, pr, plan, n_itemblocks, waves_per_block, NW, w0, WT, NG,
-                             n_gsplit, G, max_order, flat_gather, Lam_a, Lam_b, coef, m2a, m2b, Ba, Bb,
+                             n_gsplit, G, max_order, flat_gather, use_dma, Lam_a, Lam_b, coef, m2a, m2b, Ba, Bb,
                              partial, n_slots, slot0, st);
 }
 

@@ -534,9 +534,9 @@ def test_uneven_batch_graph_matches_separate_systems():
 
 @pytest.mark.parametrize("tuning", [
     dict(lambda_variant=1, lambda_chunk=5, second_gsplit=3, second_stage=1, fb_splitk=1,
-         second_gather=2),
+         second_gather=2, second_copy=1),
     dict(lambda_variant=2, lambda_chunk=7, second_gsplit=1, second_stage=3, fb_splitk=3,
-         second_gather=1),
+         second_gather=1, second_copy=2),
     dict(lambda_variant=2, lambda_chunk=32, second_gsplit=8, second_stage=4, fb_splitk=16),
     dict(lambda_variant=3, lambda_chunk=11, second_gsplit=2, second_stage=2, fb_splitk=4),
 ])
