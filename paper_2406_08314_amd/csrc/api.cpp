@@ -608,7 +608,7 @@ void run_energy_mixed(msd_system* s) {
         g.ldb = 2 * (int64_t)s->NW * D.N;
         g.b_kmaj = false;
         g.C32 = reinterpret_cast<float*>(s->LT32[sp]);
-        g.ldc = 2 * (int64_t)wt * D.N;
+        g.c_block = 2 * D.N;  // LT tile of (walker, vector) contiguous: [wl][g][p][n]
         msd::launch_gemm32(g, s->st);
       });
     }
@@ -685,7 +685,7 @@ void run_energy(msd_system* s) {
           g.ldb = 2 * (int64_t)s->NW * D.N;
           g.b_kmaj = false;
           g.C = reinterpret_cast<double*>(s->LT[sp]);
-          g.ldc = 2 * (int64_t)wt * D.N;
+          g.c_block = 2 * D.N;  // LT tile of (walker, vector) contiguous: [wl][g][p][n]
           msd::launch_gemm(g, s->st);
         });
       }

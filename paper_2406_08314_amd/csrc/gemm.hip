@@ -226,7 +226,10 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
         const int gm = m0 + wm + i * 16 + (lane >> 4) + 4 * r;
         const int gn = n0 + wn + j * 16 + (lane & 15);
         if (gm < g.M && gn < g.N) {
-          const int64_t off = (int64_t)gm * ldc + gn;
+          const int64_t off = g.c_block > 0
+                                  ? ((int64_t)(gn / g.c_block) * g.M + gm) * g.c_block +
+                                        gn % g.c_block
+                                  : (int64_t)gm * ldc + gn;
           if (split) {
             C[off] = acc[i][j][r];
             continue;
@@ -265,6 +268,7 @@ static void launch_t(const GemmArgs& g, hipStream_t st) {
 
 void launch_gemm(const GemmArgs& g, hipStream_t st) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return;
+  if (g.c_block > 0 && (g.batch != 1 || g.splitk > 1 || g.beta != 0.0 || g.Acc)) return;
   if (g.splitk > 1 && (g.batch != 1 || g.cplx || !g.ws || g.Acc)) return;  // unsupported combination
   if (g.cplx) {
     if (g.a_kmaj && !g.b_kmaj) launch_t<true, false, true>(g, st);
@@ -398,7 +402,10 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs32 g) {
             g.ws[(int64_t)bz * g.M * g.N + (int64_t)gm * g.N + gn] = acc[i][j][r];
             continue;
           }
-          const int64_t off = (int64_t)bz * g.strideC + (int64_t)gm * g.ldc + gn;
+          const int64_t off = g.c_block > 0
+                                  ? ((int64_t)(gn / g.c_block) * g.M + gm) * g.c_block +
+                                        gn % g.c_block
+                                  : (int64_t)bz * g.strideC + (int64_t)gm * g.ldc + gn;
           const double v = g.alpha * (double)acc[i][j][r];
           if (OUT64) g.C64[off] = v;
           else g.C32[off] = (float)v;
@@ -432,6 +439,7 @@ static void launch32_t(const GemmArgs32& g, hipStream_t st) {
 void launch_gemm32(const GemmArgs32& g, hipStream_t st) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return;
   if (!g.C32 == !g.C64) return;                              // exactly one output
+  if (g.c_block > 0 && (g.batch != 1 || g.splitk > 1)) return;
   if (g.splitk > 1 && (g.batch != 1 || !g.ws)) return;      // unsupported combination
   if (g.a_kmaj && !g.b_kmaj) launch32_t<true, false>(g, st);
   else if (g.a_kmaj && g.b_kmaj) launch32_t<true, true>(g, st);

@@ -22,6 +22,10 @@ struct GemmArgs {
   double* ws = nullptr;         // split-K workspace: splitk * M * N doubles
   double alpha = 1.0, beta = 0.0;
   bool a_kmaj = true, b_kmaj = false, cplx = false;
+  // >0: column-blocked output, C element (m, n) at
+  // (n / c_block) * M * c_block + m * c_block + n % c_block (ldc unused;
+  // no batch, split-K, beta or Acc)
+  int c_block = 0;
 };
 void launch_gemm(const GemmArgs& g, hipStream_t st);
 
@@ -40,6 +44,7 @@ struct GemmArgs32 {
   float* ws = nullptr;          // split-K workspace: splitk * M * N floats
   double alpha = 1.0;
   bool a_kmaj = true, b_kmaj = false;
+  int c_block = 0;  // as GemmArgs::c_block
 };
 void launch_gemm32(const GemmArgs32& g, hipStream_t st);
 // Element-wise precision conversions (n elements).

@@ -692,8 +692,8 @@ __global__ __launch_bounds__(64) void k_lambda(DevSpin sa, DevSpin sb, int NW, i
   for (int g = g0; g < g1; ++g) {
     // traces of both spins first: ZW needs v0a + v0b
     cd va{0.0, 0.0}, vb{0.0, 0.0};
-    if (lane < sa.N) va = LTa[((size_t)g * sa.P + lane) * WT * sa.N + (size_t)wl * sa.N + lane];
-    if (lane < sb.N) vb = LTb[((size_t)g * sb.P + lane) * WT * sb.N + (size_t)wl * sb.N + lane];
+    if (lane < sa.N) va = LTa[(((size_t)wl * NG + g) * sa.P + lane) * sa.N + lane];
+    if (lane < sb.N) vb = LTb[(((size_t)wl * NG + g) * sb.P + lane) * sb.N + lane];
     va = wave_sum(va);
     vb = wave_sum(vb);
     const cd vsum = va + vb;
@@ -709,8 +709,8 @@ __global__ __launch_bounds__(64) void k_lambda(DevSpin sa, DevSpin sb, int NW, i
         }
         continue;
       }
-      const cd* base = (s2 ? LTb : LTa) + ((size_t)g * S.P) * WT * N + (size_t)wl * N;
-      const size_t ld = (size_t)WT * N;
+      const cd* base = (s2 ? LTb : LTa) + ((size_t)wl * NG + g) * S.P * N;
+      const size_t ld = (size_t)N;
       cd x{0.0, 0.0};
       for (int e = lane; e < N * N; e += 64) {
         const int j = e / N, c = e % N;
@@ -794,10 +794,10 @@ __global__ __launch_bounds__(128) void k_lambda_rows(DevSpin sa, DevSpin sb, int
     osl[i] = i < no ? oslot[i] : 0;
     zw[i] = cd{0.0, 0.0};
   }
-  const size_t ld = (size_t)WT * N;
+  const size_t ld = (size_t)N;  // LT tile of (walker, vector): P x N, contiguous
   const int g0 = chunk * g_chunk, g1 = min(NG, g0 + g_chunk);
   for (int g = g0; g < g1; ++g) {
-    const CT* base = LT + ((size_t)g * P) * ld + (size_t)wl * N;
+    const CT* base = LT + ((size_t)wl * NG + g) * P * N;
     // Q^g of this spin into LDS; traces
     CT v{}, x{};
     for (int e = lane; e < N * N; e += 64) {
@@ -909,11 +909,11 @@ __global__ __launch_bounds__(64) void k_lambda_wave(DevSpin sa, DevSpin sb, int 
     osl[i] = i < no ? oslot[i] : 0;
     zw[i] = cd{0.0, 0.0};
   }
-  const size_t ld = (size_t)WT * N, ldo = (size_t)WT * No;
+  const size_t ld = (size_t)N, ldo = (size_t)No;  // contiguous P x N tiles per (walker, vector)
   const int g0 = chunk * g_chunk, g1 = min(NG, g0 + g_chunk);
   CT qn[QPL], ltn[NMAX], dn{};
   auto fetch = [&](int g) {
-    const CT* base = LT + ((size_t)g * P) * ld + (size_t)wl * N;
+    const CT* base = LT + ((size_t)wl * NG + g) * P * N;
 #pragma unroll
     for (int r = 0; r < QPL; ++r) {
       const int e = lane + 64 * r;
@@ -924,7 +924,7 @@ __global__ __launch_bounds__(64) void k_lambda_wave(DevSpin sa, DevSpin sb, int 
       for (int c = 0; c < NMAX; ++c)
         ltn[c] = (row && c < N) ? base[(size_t)(N + lane) * ld + c] : CT{};
     }
-    const CT* baseo = LTo + ((size_t)g * Po) * ldo + (size_t)wl * No;
+    const CT* baseo = LTo + ((size_t)wl * NG + g) * Po * No;
     dn = lane < No ? baseo[(size_t)lane * ldo + lane] : CT{};
   };
   if (g0 < g1) fetch(g0);
@@ -936,7 +936,7 @@ __global__ __launch_bounds__(64) void k_lambda_wave(DevSpin sa, DevSpin sb, int 
 #pragma unroll
       for (int c = 0; c < NMAX; ++c) ltv[c] = ltn[c];
     } else {
-      const CT* base = LT + ((size_t)g * P) * ld + (size_t)wl * N;
+      const CT* base = LT + ((size_t)wl * NG + g) * P * N;
 #pragma unroll
       for (int c = 0; c < NMAX; ++c)
         ltv[c] = (row && c < N) ? base[(size_t)(N + lane) * ld + c] : CT{};
