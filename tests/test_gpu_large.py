@@ -10,7 +10,7 @@ import pytest
 
 from oracle import msd
 from paper_2406_08314_amd import MsdSystem
-from synth import make_config
+from synth import make_config, make_workload
 
 pytestmark = pytest.mark.gpu
 
@@ -49,3 +49,51 @@ def test_cu_oxo_full_batch_energy_truncated_trial():
         ref = msd.local_energy(wl.h1, wl.chol, wl.e0, wl.ci, wl.occ_a, wl.occ_b,
                                wl.phi_a[w], wl.phi_b[w])
         assert abs(out["e_loc"][w] - ref) <= TOL * max(1.0, abs(ref))
+
+
+def test_fe2s2_full_batch_overlap():
+    """Fe2S2-shaped system at full size (M=300, N=45+45, 2,000 Cholesky
+    vectors, 200,000 determinants of orders up to 6, 512 walkers): the whole
+    batch's overlaps, one walker checked against the brute-force oracle."""
+    wl = make_config("fe2s2")
+    s = _system(wl)
+    out = s.measure(wl.dt, energy=False)
+    assert np.all(np.isfinite(out["log_ovlp"]))
+    for w in (3,):
+        ref = np.log(msd.trial_overlap(wl.ci, wl.occ_a, wl.occ_b, wl.phi_a[w], wl.phi_b[w]))
+        assert abs(np.exp(out["log_ovlp"][w] - ref) - 1) < TOL
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fe2s2_shape_energy_high_orders(precision):
+    """Fe2S2 shapes (window 15 x 5, excitation orders up to 6) with a short
+    trial, all quantities of one walker against the oracle.  The mixed form's
+    energy error is bounded relative to |E_L| (about 6e3 Ha for this synthetic
+    Hamiltonian)."""
+    wl = make_workload("fe2s2_small", M=300, n_alpha=45, n_beta=45, n_chol=2000, n_det=24,
+                       k_max=6, window=(15, 5), c_law="power1", n_walkers=64,
+                       seed=240608317, complex_ci=True)
+    s = MsdSystem(wl.M, wl.n_alpha, wl.n_beta, wl.n_chol, wl.n_walkers, wl.n_det,
+                  precision=precision)
+    s.set_hamiltonian(wl.h1, wl.chol, wl.e0)
+    s.set_trial(wl.ci, wl.occ_a, wl.occ_b)
+    s.set_walkers(wl.phi_a, wl.phi_b, wl.weights)
+    out = s.measure(wl.dt)
+    w = 5
+    ref = msd.measure(wl.h1, wl.chol, wl.e0, wl.ci, wl.occ_a, wl.occ_b, wl.phi_a, wl.phi_b,
+                      wl.dt, walkers=[w])
+    assert abs(np.exp(out["log_ovlp"][w] - ref["log_ovlp"][0]) - 1) < TOL
+    fb = ref["force_bias"][0]
+    e = ref["e_loc"][0]
+    if precision == "fp64":
+        assert np.max(np.abs(out["force_bias"][w] - fb)) <= TOL * np.max(np.abs(fb))
+        assert abs(out["e_loc"][w] - e) <= TOL * max(1.0, abs(e))
+        ga, gb = msd.green(wl.ci, wl.occ_a, wl.occ_b, wl.phi_a[w], wl.phi_b[w])
+        g_a, g_b = s.get_green(w)
+        assert np.max(np.abs(g_a - ga)) <= TOL * max(1.0, np.max(np.abs(ga)))
+        assert np.max(np.abs(g_b - gb)) <= TOL * max(1.0, np.max(np.abs(gb)))
+    else:
+        assert np.max(np.abs(out["force_bias"][w] - fb)) <= 1e-5 * np.max(np.abs(fb))
+        err = abs(out["e_loc"][w] - e)
+        print(f"mixed-form |dE_L| at the Fe2S2 shape: {err:.3e} Ha (|E_L| = {abs(e):.1f})")
+        assert err <= 1e-7 * abs(e)
