@@ -28,7 +28,6 @@
 namespace msd {
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
-typedef float float4_t __attribute__((ext_vector_type(4)));
 
 constexpr int GB_M = 64, GB_N = 64, GB_K = 16, GPAD = 16;
 
@@ -243,128 +242,6 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
       }
 }
 
-// ============================================================================
-// Short-K GEMM (K <= 64): C = alpha A B with A k-major (A[m*lda + k]) and B
-// row-major in k (B[k*ldb + n]), no batch.  A workgroup keeps its 64 x K slab
-// of A in LDS for the whole launch and walks KT_NT consecutive 64-column tiles
-// of B, double-buffering each B tile through registers, so each A slab is
-// loaded once per KT_NT output tiles.  This is the shape of the Cholesky
-// contraction LT = L[R u V, :] T (K = M orbitals, output written once).
-// T = double (v_mfma_f64_16x16x4f64) or float (v_mfma_f32_16x16x4f32).
-// ============================================================================
-
-constexpr int KT_NT = 8;    // output tiles per workgroup along N
-constexpr int KT_KMAX = 64;
-
-template <class T>
-struct KtOut;
-template <>
-struct KtOut<double> {
-  typedef double4_t acc_t;
-  // register r of lane l holds D[l/16 + 4r][l % 16]
-  static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
-};
-template <>
-struct KtOut<float> {
-  typedef float4_t acc_t;
-  // register r of lane l holds D[4 (l/16) + r][l % 16]
-  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
-};
-
-__device__ __forceinline__ double4_t kt_mfma(double a, double b, double4_t c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-__device__ __forceinline__ float4_t kt_mfma(float a, float b, float4_t c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-
-template <class T, class OutT>
-__global__ __launch_bounds__(256) void k_gemm_ktile(int M, int N, int K, const T* __restrict__ A,
-                                                    int64_t lda, const T* __restrict__ B,
-                                                    int64_t ldb, OutT* __restrict__ C,
-                                                    int64_t ldc, int c_block, double alpha) {
-  typedef typename KtOut<T>::acc_t acc_t;
-  constexpr int PADK = 16;  // row pad (elements), as in the general kernels
-  __shared__ T As[KT_KMAX][GB_M + PADK];
-  __shared__ T Bs[KT_KMAX][GB_N + PADK];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int m0 = blockIdx.y * GB_M;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  const int Kp = (K + 3) & ~3;  // MFMA k-steps of 4 (zero padded)
-  // A slab: 64 rows x K, thread t loads rows (t >> 2) and k quarter (t & 3)
-  for (int e = tid; e < GB_M * Kp; e += 256) {
-    const int m = e / Kp, k = e % Kp;
-    As[k][m] = (m0 + m < M && k < K) ? A[(int64_t)(m0 + m) * lda + k] : T(0);
-  }
-  // B tile: K x 64, each thread 4 consecutive n of one k row per pass
-  constexpr int BPT = KT_KMAX * GB_N / 256;  // elements per thread (16)
-  T rb[BPT];
-  auto loadB = [&](int n0) {
-#pragma unroll
-    for (int q = 0; q < BPT / 4; ++q) {
-      const int k = (tid >> 4) + 16 * q, nn = (tid & 15) * 4;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int n = n0 + nn + r;
-        rb[4 * q + r] = (k < K && n < N) ? B[(int64_t)k * ldb + n] : T(0);
-      }
-    }
-  };
-  const int nt0 = blockIdx.x * KT_NT;
-  const int n_tiles = (N + GB_N - 1) / GB_N;
-  if (nt0 < n_tiles) loadB(nt0 * GB_N);
-  for (int t = 0; t < KT_NT && nt0 + t < n_tiles; ++t) {
-    const int n0 = (nt0 + t) * GB_N;
-    __syncthreads();  // previous tile's reads of Bs (and the A slab writes) are done
-#pragma unroll
-    for (int q = 0; q < BPT / 4; ++q) {
-      const int k = (tid >> 4) + 16 * q, nn = (tid & 15) * 4;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) Bs[k][nn + r] = rb[4 * q + r];
-    }
-    __syncthreads();
-    if (nt0 + t + 1 < n_tiles && t + 1 < KT_NT) loadB(n0 + GB_N);  // in flight below
-    acc_t acc[2][2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
-    for (int kk = 0; kk < Kp; kk += 4) {
-      const int kr = kk + (lane >> 4);
-      const T a0 = As[kr][wm + (lane & 15)], a1 = As[kr][wm + 16 + (lane & 15)];
-      const T b0 = Bs[kr][wn + (lane & 15)], b1 = Bs[kr][wn + 16 + (lane & 15)];
-      acc[0][0] = kt_mfma(a0, b0, acc[0][0]);
-      acc[0][1] = kt_mfma(a0, b1, acc[0][1]);
-      acc[1][0] = kt_mfma(a1, b0, acc[1][0]);
-      acc[1][1] = kt_mfma(a1, b1, acc[1][1]);
-    }
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int gm = m0 + wm + i * 16 + KtOut<T>::row(lane, r);
-          const int gn = n0 + wn + j * 16 + (lane & 15);
-          if (gm < M && gn < N) {
-            const int64_t off = c_block > 0
-                                    ? ((int64_t)(gn / c_block) * M + gm) * c_block + gn % c_block
-                                    : (int64_t)gm * ldc + gn;
-            C[off] = (OutT)(alpha * (double)acc[i][j][r]);
-          }
-        }
-  }
-}
-
-template <class T, class OutT>
-static void launch_ktile(int M, int N, int K, const T* A, int64_t lda, const T* B, int64_t ldb,
-                         OutT* C, int64_t ldc, int c_block, double alpha, hipStream_t st) {
-  const int n_tiles = (N + GB_N - 1) / GB_N;
-  dim3 grid((n_tiles + KT_NT - 1) / KT_NT, (M + GB_M - 1) / GB_M);
-  hipLaunchKernelGGL((k_gemm_ktile<T, OutT>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C,
-                     ldc, c_block, alpha);
-}
-
 // Sum of the split-K partials in slice order (deterministic), then alpha/beta.
 __global__ void k_splitk_reduce(GemmArgs g) {
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -392,12 +269,6 @@ static void launch_t(const GemmArgs& g, hipStream_t st) {
 void launch_gemm(const GemmArgs& g, hipStream_t st) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return;
   if (g.c_block > 0 && (g.batch != 1 || g.splitk > 1 || g.beta != 0.0 || g.Acc)) return;
-  if (!g.cplx && g.a_kmaj && !g.b_kmaj && g.batch == 1 && g.splitk <= 1 && !g.Acc &&
-      g.beta == 0.0 && !g.mask && g.K <= KT_KMAX) {
-    launch_ktile<double, double>(g.M, g.N, g.K, g.A, g.lda, g.B, g.ldb, g.C, g.ldc, g.c_block,
-                                 g.alpha, st);
-    return;
-  }
   if (g.splitk > 1 && (g.batch != 1 || g.cplx || !g.ws || g.Acc)) return;  // unsupported combination
   if (g.cplx) {
     if (g.a_kmaj && !g.b_kmaj) launch_t<true, false, true>(g, st);
@@ -418,6 +289,7 @@ void launch_gemm(const GemmArgs& g, hipStream_t st) {
 // floats puts the four k-rows read by one ds_read_b32 wave in disjoint banks.
 // ============================================================================
 
+typedef float float4_t __attribute__((ext_vector_type(4)));
 constexpr int GPAD32 = 16;
 
 template <bool A_KMAJ, bool B_KMAJ, bool OUT64>
@@ -568,15 +440,6 @@ void launch_gemm32(const GemmArgs32& g, hipStream_t st) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return;
   if (!g.C32 == !g.C64) return;                              // exactly one output
   if (g.c_block > 0 && (g.batch != 1 || g.splitk > 1)) return;
-  if (g.a_kmaj && !g.b_kmaj && g.batch == 1 && g.splitk <= 1 && !g.mask && g.K <= KT_KMAX) {
-    if (g.C64)
-      launch_ktile<float, double>(g.M, g.N, g.K, g.A, g.lda, g.B, g.ldb, g.C64, g.ldc, g.c_block,
-                                  g.alpha, st);
-    else
-      launch_ktile<float, float>(g.M, g.N, g.K, g.A, g.lda, g.B, g.ldb, g.C32, g.ldc, g.c_block,
-                                 g.alpha, st);
-    return;
-  }
   if (g.splitk > 1 && (g.batch != 1 || !g.ws)) return;      // unsupported combination
   if (g.a_kmaj && !g.b_kmaj) launch32_t<true, false>(g, st);
   else if (g.a_kmaj && g.b_kmaj) launch32_t<true, true>(g, st);
