@@ -212,7 +212,9 @@ typedef struct {
                              2 = one-wave kernel with the next vector's loads in flight,
                              3 = one-wave kernel loading each vector when used (fewer
                              registers; only where both spins have N = 8 or 16 and the
-                             whole occupied window, else as 2).  2 and 3 need N <= 16 */
+                             whole occupied window, else as 2), 4 = matrix-core kernel
+                             (both spins N = 8 with the whole occupied window and at
+                             most 64 active virtuals, else as 2).  2-4 need N <= 16    */
   int32_t lambda_chunk;   /* Cholesky vectors per intermediates workgroup (1..NG)         */
   int32_t second_gsplit;  /* Cholesky-range split of the second-order kernel (1..64)      */
   int32_t second_stage;   /* Cholesky vectors per LDS stage of the second-order kernel

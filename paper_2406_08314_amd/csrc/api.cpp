@@ -413,7 +413,9 @@ void alloc_energy(msd_system* s) {
     // 0: the generic one-wave kernel (windows beyond the row kernels' limits)
     s->lambda_variant = !rows_fit ? 0
                         : (s->tune.lambda_variant == 1 || nmax > 16) ? 1
-                        : (s->tune.lambda_variant == 3 && s->lambda_exact) ? 3 : 2;
+                        : (s->tune.lambda_variant == 3 && s->lambda_exact) ? 3
+                        : (s->tune.lambda_variant == 4 && s->lambda_exact &&
+                           msd::lambda_mfma_fits(A, B)) ? 4 : 2;
   }
   s->n_slots = slot;  // every slot is written by exactly one workgroup
   Arena& E = s->energy_mem;
@@ -615,7 +617,11 @@ void run_energy_mixed(msd_system* s) {
     s->timed(ST_LAMBDA, [&] {
       const cf* Ta = reinterpret_cast<const cf*>(s->T32[0]);
       const cf* Tb = reinterpret_cast<const cf*>(s->T32[1]);
-      if (s->lambda_variant >= 2)
+      if (s->lambda_variant == 4)
+        msd::launch_lambda_mfma32(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, Ta, Tb, s->LT32[0],
+                                  s->LT32[1], s->Lam32[0], s->Lam32[1], s->v0, s->ex0,
+                                  s->ZWp[0], s->ZWp[1], s->st);
+      else if (s->lambda_variant >= 2)
         msd::launch_lambda_wave32(A, B, nmax, s->lambda_exact, s->lambda_variant == 2, s->NW, w0, wt, s->NG, s->gl_chunk, Ta, Tb,
                                   s->LT32[0], s->LT32[1], s->Lam32[0], s->Lam32[1], s->v0, s->ex0,
                                   s->ZWp[0], s->ZWp[1], s->st);
@@ -691,7 +697,11 @@ void run_energy(msd_system* s) {
       }
       int nmax = 0;
       s->timed(ST_LAMBDA, [&] {
-        if (s->lambda_variant >= 2 && msd::lambda_rows_fits(A, B, &nmax))
+        if (s->lambda_variant == 4)
+          msd::launch_lambda_mfma(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, s->sw[0].T,
+                                  s->sw[1].T, s->LT[0], s->LT[1], s->Lam[0], s->Lam[1], s->v0,
+                                  s->ex0, s->ZWp[0], s->ZWp[1], s->st);
+        else if (s->lambda_variant >= 2 && msd::lambda_rows_fits(A, B, &nmax))
           msd::launch_lambda_wave(A, B, nmax, s->lambda_exact, s->lambda_variant == 2, s->NW, w0, wt, s->NG, s->gl_chunk, s->sw[0].T,
                                   s->sw[1].T, s->LT[0], s->LT[1], s->Lam[0], s->Lam[1], s->v0,
                                   s->ex0, s->ZWp[0], s->ZWp[1], s->st);
@@ -1717,7 +1727,7 @@ namespace {
 void set_tuning_impl(msd_system* s, const msd_tuning& t) {
   auto bad = [](const char* f) { fail(MSD_ERR_ARG, std::string("tuning field ") + f + " out of range"); };
   if (t.fb_splitk < 0 || t.fb_splitk > 16) bad("fb_splitk");
-  if (t.lambda_variant < 0 || t.lambda_variant > 3) bad("lambda_variant");
+  if (t.lambda_variant < 0 || t.lambda_variant > 4) bad("lambda_variant");
   if (t.lambda_chunk < 0) bad("lambda_chunk");
   if (t.second_gsplit < 0 || t.second_gsplit > 64) bad("second_gsplit");
   if (t.second_stage < 0 || t.second_stage > 32) bad("second_stage");
@@ -1800,7 +1810,7 @@ msd_status msd_autotune(msd_system* sys, double dt, int32_t reps, msd_tuning* ou
     sweep(&msd_tuning::fb_splitk, {1, 2, 4, 8, 16});
     int nmax = 0;
     if (msd::lambda_rows_fits(sys->ds[0], sys->ds[1], &nmax) && nmax <= 16)
-      sweep(&msd_tuning::lambda_variant, {1, 2, 3});
+      sweep(&msd_tuning::lambda_variant, {1, 2, 3, 4});
     sweep(&msd_tuning::lambda_chunk, {4, 8, 16, 32});
     sweep(&msd_tuning::second_gather, {1, 2});
     sweep(&msd_tuning::second_copy, {1, 2});

@@ -149,6 +149,17 @@ void launch_lambda_rows32(const DevSpin& sa, const DevSpin& sb, int nmax, int NW
 // One-wave-per-(walker, chunk, spin) variant of the same computation (no
 // cross-wave barrier, next vector's loads in flight); same outputs.  For
 // N <= 16 (nmax 8 or 16 from lambda_rows_fits).
+// Matrix-core variant of the energy intermediates for N = 8 per spin with the
+// whole occupied set in the window (identity slots) and n_vir_act <= 64.
+bool lambda_mfma_fits(const DevSpin& sa, const DevSpin& sb);
+void launch_lambda_mfma(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
+                        int g_chunk, const cd* Ta, const cd* Tb, const cd* LTa, const cd* LTb,
+                        cd* Lam_a, cd* Lam_b, cd* v0, cd* ex0, cd* ZWpart_a, cd* ZWpart_b,
+                        hipStream_t st);
+void launch_lambda_mfma32(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
+                          int g_chunk, const cf* Ta, const cf* Tb, const cf* LTa, const cf* LTb,
+                          cf* Lam_a, cf* Lam_b, cd* v0, cd* ex0, cd* ZWpart_a, cd* ZWpart_b,
+                          hipStream_t st);
 // exact: both spins have N == nmax and an identity occupied window;
 // prefetch: next vector's LT row loaded ahead into registers (exact shapes).
 void launch_lambda_wave(const DevSpin& sa, const DevSpin& sb, int nmax, bool exact, bool prefetch,

@@ -539,6 +539,8 @@ def test_uneven_batch_graph_matches_separate_systems():
          second_gather=1, second_copy=2),
     dict(lambda_variant=2, lambda_chunk=32, second_gsplit=8, second_stage=4, fb_splitk=16),
     dict(lambda_variant=3, lambda_chunk=11, second_gsplit=2, second_stage=2, fb_splitk=4),
+    dict(lambda_variant=4, lambda_chunk=13, second_gsplit=2, second_stage=2, fb_splitk=4),
+    dict(lambda_variant=4, lambda_chunk=1, second_gsplit=1, second_stage=1, fb_splitk=1),
 ])
 def test_tuning_overrides_keep_parity(tuning):
     """Ragged Cholesky chunks and stages (320 vectors split 5/7/3 ways) in
@@ -559,9 +561,22 @@ def test_autotune_picks_valid_shapes_and_keeps_results():
     for precision in ("fp64", "mixed"):
         s = system_for(wl, precision=precision)
         t = s.autotune(wl.dt, reps=2)
-        assert 1 <= t["fb_splitk"] <= 16 and t["lambda_variant"] in (1, 2, 3)
+        assert 1 <= t["fb_splitk"] <= 16 and t["lambda_variant"] in (1, 2, 3, 4)
         assert t["lambda_chunk"] >= 1 and t["second_gsplit"] >= 1 and t["second_stage"] >= 1
         out = s.measure(wl.dt)
         np.testing.assert_array_equal(out["log_ovlp"], ref["log_ovlp"])
         tol = 1e-10 * max(1.0, np.max(np.abs(ref["e_loc"]))) if precision == "fp64" else MIXED_E_TOL
         assert np.max(np.abs(out["e_loc"] - ref["e_loc"])) <= tol
+
+
+@pytest.mark.parametrize("variant", [2, 3, 4])
+def test_mixed_lambda_variants_against_fp64(variant):
+    """Each single-precision energy-intermediate kernel keeps every walker's
+    local energy within 0.1 mHa of the FP64 path (Medium, 32 walkers)."""
+    wl = make_config("medium", n_walkers=32)
+    ref = system_for(wl).measure(wl.dt)
+    s = system_for(wl, precision="mixed")
+    s.set_tuning(lambda_variant=variant)
+    out = s.measure(wl.dt)
+    assert s.get_tuning()["lambda_variant"] == variant
+    assert np.max(np.abs(out["e_loc"] - ref["e_loc"])) <= MIXED_E_TOL
