@@ -343,7 +343,7 @@ void alloc_energy(msd_system* s) {
   const size_t budget = (size_t)16 << 30;
   int wt = (int)std::max<size_t>(1, std::min<size_t>(NW, budget / std::max<size_t>(per_w, 1)));
   s->WT = wt;
-  s->gl_chunk = s->tune.lambda_chunk > 0 ? std::min(s->tune.lambda_chunk, NG) : 16;
+  s->gl_chunk = s->tune.lambda_chunk > 0 ? std::min(s->tune.lambda_chunk, NG) : std::min(32, NG);
   s->n_lchunks = (NG + s->gl_chunk - 1) / s->gl_chunk;
   int slot = 0;
   // Per spin: same-spin second-order terms as row-pair items of each string
@@ -411,11 +411,13 @@ void alloc_energy(msd_system* s) {
         if (S.occ_slot[i] != i) s->lambda_exact = false;
     }
     // 0: the generic one-wave kernel (windows beyond the row kernels' limits)
+    // default: the matrix-core kernel where it applies, else the one-wave kernel
+    const bool mfma_ok = s->lambda_exact && msd::lambda_mfma_fits(A, B);
+    const int want = s->tune.lambda_variant ? s->tune.lambda_variant : (mfma_ok ? 4 : 2);
     s->lambda_variant = !rows_fit ? 0
-                        : (s->tune.lambda_variant == 1 || nmax > 16) ? 1
-                        : (s->tune.lambda_variant == 3 && s->lambda_exact) ? 3
-                        : (s->tune.lambda_variant == 4 && s->lambda_exact &&
-                           msd::lambda_mfma_fits(A, B)) ? 4 : 2;
+                        : (want == 1 || nmax > 16) ? 1
+                        : (want == 3 && s->lambda_exact) ? 3
+                        : (want == 4 && mfma_ok) ? 4 : 2;
   }
   s->n_slots = slot;  // every slot is written by exactly one workgroup
   Arena& E = s->energy_mem;
