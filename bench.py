@@ -30,23 +30,25 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "energy_second_medium_hbm_traff
 
 
 def measured_traffic():
-    """HBM bytes per launch of the second-order energy kernel from the
-    committed rocprofv3 counter summary, or None if the kernel source changed
-    since the counters were taken."""
+    """(HBM bytes per launch, launch shape) of the second-order energy kernel
+    from the committed rocprofv3 counter summary, or None if the kernel source
+    changed since the counters were taken.  The shape is (Cholesky split,
+    vectors per LDS stage, stage copy mode)."""
     import hashlib
     try:
         text = open(TRAFFIC_PROFILE).read()
     except OSError:
         return None
     vals = dict(line.split(": ", 1) for line in text.splitlines()
-                if line.startswith(("traffic_bytes_per_launch:", "source:")))
+                if line.startswith(("traffic_bytes_per_launch:", "source:", "launch_shape:")))
     try:
         fields = vals["source"].split()
         src, prefix = fields[0], fields[-1]
         digest = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()
         if not digest.startswith(prefix):
             return None
-        return float(vals["traffic_bytes_per_launch"])
+        shape = tuple(int(v) for v in vals["launch_shape"].split())
+        return float(vals["traffic_bytes_per_launch"]), shape
     except (KeyError, OSError, ValueError, IndexError):
         return None
 
@@ -117,6 +119,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the library's default launch shapes (for counter runs)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (for scaling "
                          "rocprofv3 FETCH_SIZE/WRITE_SIZE counters) and exit")
@@ -183,7 +187,7 @@ def main():
         local energies of the initial walkers (same input for both forms)."""
         s = system(False, precision)
         e_init = s.measure(wl.dt)["e_loc"]
-        tunings[precision] = s.autotune(wl.dt, reps=3)
+        tunings[precision] = s.get_tuning() if args.no_autotune else s.autotune(wl.dt, reps=3)
         for k in range(args.warmup):
             step(s, k)
         ms, wall = timed(s, lambda k: step(s, args.warmup + k), args.steps)
@@ -233,7 +237,12 @@ def main():
             ach = amount / avg_s / 1e9
             peak = HBM_PEAK_GBS
             u = "GB/s"
-        traffic = measured_traffic() if name == "energy_gamma" else None
+        traffic = None
+        if name == "energy_gamma":
+            prof = measured_traffic()
+            t = tunings["fp64"]
+            if prof and prof[1] == (t["second_gsplit"], t["second_stage"], t["second_copy"]):
+                traffic = prof[0]
         kernel = {"energy_gamma": "k_energy_second", "lambda": "k_lambda_wave",
                   "lt_gemm": "k_gemm_f64 (LT)"}.get(name, name)
         roof = {"kernel": kernel, "stage": name, "bound": bound, "achieved": round(ach, 3), "peak": peak,

@@ -1793,15 +1793,20 @@ msd_status msd_autotune(msd_system* sys, double dt, int32_t reps, msd_tuning* ou
   sys->o.timing = 0;
   msd_tuning best = sys->tune;
   try {
+    // a candidate replaces the incumbent (the current value, automatic if
+    // unset) only when it is faster by more than 3%, so timing noise does not
+    // move the choice
     auto sweep = [&](int32_t msd_tuning::*field, const std::vector<int>& cands) {
-      double t_best = 1e300;
+      set_tuning_impl(sys, best);
+      double t_best = time_measures(sys, dt, reps);
       int v_best = best.*field;
       for (int v : cands) {
+        if (v == best.*field) continue;
         msd_tuning t = best;
         t.*field = v;
         set_tuning_impl(sys, t);
         const double ms = time_measures(sys, dt, reps);
-        if (ms < t_best) {
+        if (ms < 0.97 * t_best) {
           t_best = ms;
           v_best = v;
         }
