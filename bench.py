@@ -122,8 +122,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's default launch shapes (for counter runs)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
-                    help="only run a plain device-to-device copy of MIB MiB (for scaling "
-                         "rocprofv3 FETCH_SIZE/WRITE_SIZE counters) and exit")
+                    help="only run a plain elementwise copy kernel over MIB MiB (for "
+                         "scaling rocprofv3 FETCH_SIZE/WRITE_SIZE counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build measures one GPU only (no multi-GPU path); run with --gpus 1",
@@ -138,7 +138,7 @@ def main():
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
         for _ in range(3):
-            dst.copy_(src)
+            torch.mul(src, 1.0, out=dst)  # plain elementwise kernel: reads n, writes n
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes_each_way": n * 8, "copies": 3}))
         return

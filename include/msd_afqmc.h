@@ -224,15 +224,16 @@ typedef struct {
   int32_t second_copy;    /* second-order kernel fills its LDS stage 1 = through
                              registers, 2 = by direct global-to-LDS loads (where the
                              Lambda rows are 16-byte aligned; else through registers)   */
-  int32_t reserved[1];
+  int32_t second_waves;   /* waves per second-order workgroup: 8 or 16 (16 only where
+                             no spin has excitations above order 4; else 8)             */
 } msd_tuning;
 msd_status msd_get_tuning(msd_system* sys, msd_tuning* out);
 /* Sets overrides (validated; MSD_ERR_ARG names the bad field).  Drops the
  * energy plan and recorded graphs; they are rebuilt on the next call. */
 msd_status msd_set_tuning(msd_system* sys, const msd_tuning* t);
 /* Autotuner: times candidate values of each field in turn (fb_splitk,
- * lambda_variant, lambda_chunk, second_gather, second_copy, second_gsplit,
- * second_stage) over `reps`
+ * lambda_variant, lambda_chunk, second_gather, second_copy, second_waves,
+ * second_gsplit, second_stage) over `reps`
  * measurements with energies of the current walkers (time step dt), keeps the
  * fastest and leaves it set (*out, if not NULL, receives it).  Overwrites the
  * last-measurement buffers; walkers are unchanged.  Needs walkers. */

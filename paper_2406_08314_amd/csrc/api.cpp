@@ -157,7 +157,7 @@ struct msd_system {
   // the order, first item, item end), ER_WAVES entries per item block
   std::vector<int4> plan_host;
   int4* plan = nullptr;
-  int n_itemblocks = 0, slot_second = 0, second_G = 1, second_maxk = 0;
+  int n_itemblocks = 0, slot_second = 0, second_G = 1, second_maxk = 0, second_waves = 8;
   bool second_flat = false;  // gathers through a generic pointer (see k_energy_second)
   bool second_dma = true;    // stages Lambda by direct global-to-LDS loads
   cd* LT[2] = {nullptr, nullptr};
@@ -378,8 +378,22 @@ void alloc_energy(msd_system* s) {
       for (int f = 0; f < n_items; f += 64) pl.push_back(int4{k | (sp << 8), S.bucket[k], f, n_items});
     }
   }
-  while (pl.size() % msd::ER_WAVES) pl.push_back(int4{msd::ER_NONE, 0, 0, 0});
-  s->n_itemblocks = (int)(pl.size() / msd::ER_WAVES);
+  // waves per workgroup; each workgroup stages only the spins its waves read
+  // (pairs read both), recorded in bits 16-17 of every entry of the workgroup
+  const int wpb = (s->tune.second_waves == 16 && s->second_maxk <= 4) ? 16 : msd::ER_WAVES;
+  s->second_waves = wpb;
+  while (pl.size() % wpb) pl.push_back(int4{msd::ER_NONE, 0, 0, 0});
+  s->n_itemblocks = (int)(pl.size() / wpb);
+  for (int ib = 0; ib < s->n_itemblocks; ++ib) {
+    int need = 0;
+    for (int q = 0; q < wpb; ++q) {
+      const int4 e = pl[ib * wpb + q];
+      const int role = e.x & 0xff;
+      if (role == msd::ER_PAIRS) need |= 3;
+      else if (role != msd::ER_NONE) need |= 1 << (e.x >> 8);
+    }
+    for (int q = 0; q < wpb; ++q) pl[ib * wpb + q].x |= need << 16;
+  }
   // split the Cholesky range so the second-order kernels have ~1024+ workgroups
   const int units = std::max(1, s->n_itemblocks);
   s->gsplit = std::max(1, std::min((1024 + wt * units - 1) / (wt * units), std::max(1, NG / 8)));
@@ -397,7 +411,9 @@ void alloc_energy(msd_system* s) {
     s->energy_mixed = s->mixed && s->use_strings[0] && s->use_strings[1] && rows_fit;
     const int X = A.nv * A.no + B.nv * B.no;
     const int elem = s->energy_mixed ? 8 : 16;  // bytes per staged Lambda entry
-    s->second_G = std::max(1, std::min(32, (int)((72 << 10) / (2 * elem * std::max(X, 1)))));
+    // two 8-wave workgroups or one 16-wave workgroup per CU share its LDS
+    const int budget = s->second_waves == 16 ? (144 << 10) : (72 << 10);
+    s->second_G = std::max(1, std::min(32, (int)(budget / (2 * elem * std::max(X, 1)))));
     if (s->tune.second_stage > 0)
       s->second_G = std::max(1, std::min(s->tune.second_stage,
                                          (int)((150 << 10) / (2 * elem * std::max(X, 1)))));
@@ -633,7 +649,7 @@ void run_energy_mixed(msd_system* s) {
                                   s->ZWp[0], s->ZWp[1], s->st);
     });
     s->timed(ST_EGAMMA, [&] {
-      msd::launch_energy_second32(A, B, s->dp, s->plan, s->n_itemblocks, msd::ER_WAVES, s->NW,
+      msd::launch_energy_second32(A, B, s->dp, s->plan, s->n_itemblocks, s->second_waves, s->NW,
                                   w0, wt, s->NG, s->gsplit, s->second_G, s->second_maxk,
                                   s->second_flat, s->second_dma,
                                   s->Lam32[0],
@@ -718,7 +734,7 @@ void run_energy(msd_system* s) {
       });
     }
     s->timed(ST_EGAMMA, [&] {
-      msd::launch_energy_second(A, B, s->dp, s->plan, s->n_itemblocks, msd::ER_WAVES, s->NW, w0,
+      msd::launch_energy_second(A, B, s->dp, s->plan, s->n_itemblocks, s->second_waves, s->NW, w0,
                                 wt, s->NG, s->gsplit, s->second_G, s->second_maxk,
                                 s->second_flat, s->second_dma, s->Lam[0],
                                 s->Lam[1],
@@ -1735,6 +1751,7 @@ void set_tuning_impl(msd_system* s, const msd_tuning& t) {
   if (t.second_stage < 0 || t.second_stage > 32) bad("second_stage");
   if (t.second_gather < 0 || t.second_gather > 2) bad("second_gather");
   if (t.second_copy < 0 || t.second_copy > 2) bad("second_copy");
+  if (t.second_waves != 0 && t.second_waves != 8 && t.second_waves != 16) bad("second_waves");
   s->tune = t;
   free_energy(s);
   s->drop_graphs();
@@ -1769,6 +1786,7 @@ msd_status msd_get_tuning(msd_system* sys, msd_tuning* out) {
     out->second_stage = sys->second_G;
     out->second_gather = sys->second_flat ? 2 : 1;
     out->second_copy = sys->second_dma ? 2 : 1;
+    out->second_waves = sys->second_waves;
   }
   API_END(sys)
 }
@@ -1821,6 +1839,7 @@ msd_status msd_autotune(msd_system* sys, double dt, int32_t reps, msd_tuning* ou
     sweep(&msd_tuning::lambda_chunk, {4, 8, 16, 32});
     sweep(&msd_tuning::second_gather, {1, 2});
     sweep(&msd_tuning::second_copy, {1, 2});
+    sweep(&msd_tuning::second_waves, {8, 16});
     sweep(&msd_tuning::second_gsplit, {1, 2, 4, 8});
     {
       const int X = sys->ds[0].nv * sys->ds[0].no + sys->ds[1].nv * sys->ds[1].no;
@@ -1848,6 +1867,7 @@ msd_status msd_autotune(msd_system* sys, double dt, int32_t reps, msd_tuning* ou
     out->second_stage = sys->second_G;
     out->second_gather = sys->second_flat ? 2 : 1;
     out->second_copy = sys->second_dma ? 2 : 1;
+    out->second_waves = sys->second_waves;
   }
   API_END(sys)
 }

@@ -1312,7 +1312,7 @@ __device__ __forceinline__ void lds_dma16(const void* g, void* lds) {
 // LDS instructions.  The two paths group a wave's random 16-byte reads
 // differently; which is faster is measured (launch-shape tuning).
 template <class CT, int MAXK, bool FLATG>
-__global__ __launch_bounds__(512, (MAXK <= 4 ? 4 : 2)) void k_energy_second(
+__global__ __launch_bounds__((MAXK <= 4 ? 1024 : 512)) void k_energy_second(
     DevSpin sa, DevSpin sb, DevPairs pr, const int4* __restrict__ plan, int n_ib,
     int waves_per_block, int NW, int w0, int NG, int n_gsplit, int G, const CT* __restrict__ Lam_a,
     const CT* __restrict__ Lam_b, const cd* __restrict__ coef, const cd* __restrict__ m2a,
@@ -1337,7 +1337,7 @@ __global__ __launch_bounds__(512, (MAXK <= 4 ? 4 : 2)) void k_energy_second(
   // plan entry of this wave: (role | spin << 8, first string of the order,
   // first item, item end)
   const int4 pl = plan[ib * waves_per_block + wave];
-  const int role = pl.x & 0xff, sp = pl.x >> 8;
+  const int role = pl.x & 0xff, sp = (pl.x >> 8) & 0xff, need = (pl.x >> 16) & 3;
   int idx[NIDX];
   CT mm[NMM];
   CT acc[ER_PPL];
@@ -1397,11 +1397,11 @@ __global__ __launch_bounds__(512, (MAXK <= 4 ? 4 : 2)) void k_energy_second(
       for (int e = tid; e < n; e += blockDim.x) sm[dst + e] = src[e];
     }
   };
-  auto stage = [&](int gb, int b) {
+  auto stage = [&](int gb, int b) {  // only the spins this workgroup reads
     const int Gs = min(G, g1 - gb);
     const int d0 = b * G * X;
-    copy(Lam_a + ((size_t)wl * NG + gb) * Xa, d0, Gs * Xa);
-    copy(Lam_b + ((size_t)wl * NG + gb) * Xb, d0 + G * Xa, Gs * Xb);
+    if (need & 1) copy(Lam_a + ((size_t)wl * NG + gb) * Xa, d0, Gs * Xa);
+    if (need & 2) copy(Lam_b + ((size_t)wl * NG + gb) * Xb, d0 + G * Xa, Gs * Xb);
   };
   const CT* gs_ = sm;
   if constexpr (FLATG) {
