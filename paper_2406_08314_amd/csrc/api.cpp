@@ -380,7 +380,10 @@ void alloc_energy(msd_system* s) {
   }
   // waves per workgroup; each workgroup stages only the spins its waves read
   // (pairs read both), recorded in bits 16-17 of every entry of the workgroup
-  const int wpb = (s->tune.second_waves == 16 && s->second_maxk <= 4) ? 16 : msd::ER_WAVES;
+  // default 16 (one workgroup per CU, deeper LDS stages) where the order-4
+  // kernel applies
+  const int want_w = s->tune.second_waves ? s->tune.second_waves : 16;
+  const int wpb = (want_w == 16 && s->second_maxk <= 4) ? 16 : msd::ER_WAVES;
   s->second_waves = wpb;
   while (pl.size() % wpb) pl.push_back(int4{msd::ER_NONE, 0, 0, 0});
   s->n_itemblocks = (int)(pl.size() / wpb);
@@ -413,7 +416,7 @@ void alloc_energy(msd_system* s) {
     const int elem = s->energy_mixed ? 8 : 16;  // bytes per staged Lambda entry
     // two 8-wave workgroups or one 16-wave workgroup per CU share its LDS
     const int budget = s->second_waves == 16 ? (144 << 10) : (72 << 10);
-    s->second_G = std::max(1, std::min(32, (int)(budget / (2 * elem * std::max(X, 1)))));
+    s->second_G = std::max(1, std::min(5, (int)(budget / (2 * elem * std::max(X, 1)))));
     if (s->tune.second_stage > 0)
       s->second_G = std::max(1, std::min(s->tune.second_stage,
                                          (int)((150 << 10) / (2 * elem * std::max(X, 1)))));
