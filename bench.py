@@ -26,18 +26,21 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "energy_second_medium_hbm_traffic.md")
+TRAFFIC_PROFILES = {
+    "energy_gamma": os.path.join(ROOT, "profiles", "energy_second_medium_hbm_traffic.md"),
+    "lambda": os.path.join(ROOT, "profiles", "lambda_mfma_medium_hbm_traffic.md"),
+}
 
 
-def measured_traffic():
+def measured_traffic(stage):
     """(HBM bytes per launch, launch shape) of the second-order energy kernel
     from the committed rocprofv3 counter summary, or None if the kernel source
     changed since the counters were taken.  The shape is (Cholesky split,
     vectors per LDS stage, stage copy mode)."""
     import hashlib
     try:
-        text = open(TRAFFIC_PROFILE).read()
-    except OSError:
+        text = open(TRAFFIC_PROFILES[stage]).read()
+    except (KeyError, OSError):
         return None
     vals = dict(line.split(": ", 1) for line in text.splitlines()
                 if line.startswith(("traffic_bytes_per_launch:", "source:", "launch_shape:")))
@@ -47,7 +50,7 @@ def measured_traffic():
         digest = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()
         if not digest.startswith(prefix):
             return None
-        shape = tuple(int(v) for v in vals["launch_shape"].split())
+        shape = tuple(int(v) for v in vals.get("launch_shape", "").split())
         return float(vals["traffic_bytes_per_launch"]), shape
     except (KeyError, OSError, ValueError, IndexError):
         return None
@@ -71,10 +74,15 @@ def stage_work(wl, lib_sys, stage):
     if stage == "one_body":
         return 4.0 * M * M * Ntot * NW, "flop", "mfma"
     if stage == "lambda":
-        f = 0.0
+        # matrix-core kernel: bound by its HBM stream (LT tiles in, Lambda
+        # windows, ZW partials, v0 and ex0 out)
+        chunk = lib_sys.get_tuning()["lambda_chunk"] or 16
+        n_chunks = (NG + chunk - 1) // chunk
+        b = 0.0
         for N, nv, no in ((na, tt["nv"][0], tt["no"][0]), (nb, tt["nv"][1], tt["no"][1])):
-            f += NG * NW * 8.0 * (nv * N * N + nv * N * no + N * N)
-        return f, "flop", "alu"
+            b += NW * NG * 16.0 * ((N + nv) * N + nv * no) + NW * n_chunks * nv * no * 16.0
+        b += 2 * 2 * NW * NG * 16.0
+        return b, "byte", "hbm"
     if stage == "energy_gamma":
         # per walker and Cholesky vector: one complex MAC per opposite-spin
         # pair; per string of order k, k(k-1)/2 x k(k-1)/2 two-by-two minors of
@@ -238,12 +246,16 @@ def main():
             peak = HBM_PEAK_GBS
             u = "GB/s"
         traffic = None
-        if name == "energy_gamma":
-            prof = measured_traffic()
-            t = tunings["fp64"]
-            if prof and prof[1] == (t["second_gsplit"], t["second_stage"], t["second_copy"]):
+        prof = measured_traffic(name)
+        t = tunings["fp64"]
+        if prof and name == "energy_gamma":
+            if prof[1] == (t["second_gsplit"], t["second_stage"], t["second_copy"]):
                 traffic = prof[0]
-        kernel = {"energy_gamma": "k_energy_second", "lambda": "k_lambda_wave",
+        elif prof and name == "lambda" and t["lambda_variant"] == 4:
+            traffic = prof[0]
+        lam_kernel = {1: "k_lambda_rows", 2: "k_lambda_wave", 3: "k_lambda_wave",
+                      4: "k_lambda_mfma"}.get(t["lambda_variant"], "k_lambda")
+        kernel = {"energy_gamma": "k_energy_second", "lambda": lam_kernel,
                   "lt_gemm": "k_gemm_f64 (LT)"}.get(name, name)
         roof = {"kernel": kernel, "stage": name, "bound": bound, "achieved": round(ach, 3), "peak": peak,
                 "unit": u, "frac": round(ach / peak, 4), "traffic": traffic,
