@@ -1119,9 +1119,30 @@ msd_status msd_set_hamiltonian(msd_system* sys, const double* h1, const double* 
   sys->h1_host.assign(h1, h1 + (size_t)M * M);
   sys->e0 = e0;
   std::vector<double> tmp((size_t)M * M);
+  // sum_g L^g L^g = S^T S with S the (NG*M) x M stack of the (symmetric) L^g,
+  // as one split-K GEMM
+  const int64_t K = (int64_t)NG * M;
+  const int tiles = ((M + 63) / 64) * ((M + 63) / 64);
+  const int sk = (int)std::max<int64_t>(1, std::min<int64_t>(std::max(1, 256 / tiles), K / 256));
   double* dtmp = nullptr;
-  hip_check(hipMalloc(&dtmp, sizeof(double) * M * M), "hipMalloc");
-  msd::launch_sum_ll(sys->L, NG, M, dtmp, sys->st);
+  hip_check(hipMalloc(&dtmp, sizeof(double) * M * M * (size_t)(1 + sk)), "hipMalloc");
+  {
+    msd::GemmArgs g;
+    g.M = M;
+    g.N = M;
+    g.K = (int)K;
+    g.A = sys->L;
+    g.lda = M;
+    g.a_kmaj = false;
+    g.B = sys->L;
+    g.ldb = M;
+    g.b_kmaj = false;
+    g.C = dtmp;
+    g.ldc = M;
+    g.splitk = sk;
+    g.ws = dtmp + (size_t)M * M;
+    msd::launch_gemm(g, sys->st);
+  }
   hipError_t e1 = hipMemcpyAsync(tmp.data(), dtmp, sizeof(double) * M * M, hipMemcpyDeviceToHost,
                                  sys->st);
   hipError_t e2 = hipStreamSynchronize(sys->st);

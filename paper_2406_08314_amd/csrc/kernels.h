@@ -215,7 +215,6 @@ void launch_frozen_mask(int NW, const double* weights, int* mask, hipStream_t st
 void launch_fill_i32(int* p, int n, int v, hipStream_t st);
 void launch_copy_walkers(int NW, int M, int Ntot, int na, int nb, const cd* pa, const cd* pb,
                          cd* phi, bool to_internal, cd* out_a, cd* out_b, hipStream_t st);
-void launch_sum_ll(const double* chol, int NG, int M, double* out, hipStream_t st);
 void launch_gather_rows(const double* L, int NG, int M, const int* rows, int P, double* out,
                         hipStream_t st);
 

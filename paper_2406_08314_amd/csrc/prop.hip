@@ -217,24 +217,6 @@ void launch_copy_walkers(int NW, int M, int Ntot, int na, int nb, const cd* pa, 
 }
 
 // out[p][q] = sum_g sum_r L^g_pr L^g_rq  (the exchange-like one-body term of Eq. 4)
-__global__ void k_sum_ll(const double* __restrict__ L, int NG, int M, double* __restrict__ out) {
-  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid >= (int64_t)M * M) return;
-  const int p = (int)(tid / M), q = (int)(tid % M);
-  double acc = 0.0;
-  for (int g = 0; g < NG; ++g) {
-    const double* Lg = L + (size_t)g * M * M;
-    for (int r = 0; r < M; ++r) acc = fma(Lg[(size_t)p * M + r], Lg[(size_t)r * M + q], acc);
-  }
-  out[tid] = acc;
-}
-
-void launch_sum_ll(const double* chol, int NG, int M, double* out, hipStream_t st) {
-  const int64_t n = (int64_t)M * M;
-  hipLaunchKernelGGL(k_sum_ll, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, chol, NG, M,
-                     out);
-}
-
 }  // namespace msd
 
 namespace msd {
