@@ -226,14 +226,18 @@ typedef struct {
                              Lambda rows are 16-byte aligned; else through registers)   */
   int32_t second_waves;   /* waves per second-order workgroup: 8 or 16 (16 only where
                              no spin has excitations above order 4; else 8)             */
+  int32_t walker_tile;    /* walkers per pass of the energy stages (1..n_walkers); small
+                             tiles keep the LT and Lambda intermediates of a pass in the
+                             last-level cache                                            */
+  int32_t reserved[3];
 } msd_tuning;
 msd_status msd_get_tuning(msd_system* sys, msd_tuning* out);
 /* Sets overrides (validated; MSD_ERR_ARG names the bad field).  Drops the
  * energy plan and recorded graphs; they are rebuilt on the next call. */
 msd_status msd_set_tuning(msd_system* sys, const msd_tuning* t);
 /* Autotuner: times candidate values of each field in turn (fb_splitk,
- * lambda_variant, lambda_chunk, second_gather, second_copy, second_waves,
- * second_gsplit, second_stage) over `reps`
+ * walker_tile, lambda_variant, lambda_chunk, second_gather, second_copy,
+ * second_waves, second_gsplit, second_stage) over `reps`
  * measurements with energies of the current walkers (time step dt), keeps the
  * fastest and leaves it set (*out, if not NULL, receives it).  Overwrites the
  * last-measurement buffers; walkers are unchanged.  Needs walkers. */

@@ -25,7 +25,8 @@ class MsdTuning(C.Structure):
     _fields_ = [("fb_splitk", C.c_int32), ("lambda_variant", C.c_int32),
                 ("lambda_chunk", C.c_int32), ("second_gsplit", C.c_int32),
                 ("second_stage", C.c_int32), ("second_gather", C.c_int32),
-                ("second_copy", C.c_int32), ("second_waves", C.c_int32)]
+                ("second_copy", C.c_int32), ("second_waves", C.c_int32),
+                ("walker_tile", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class MsdOptions(C.Structure):

@@ -176,7 +176,7 @@ class MsdSystem:
         return out
 
     _TUNING = ("fb_splitk", "lambda_variant", "lambda_chunk", "second_gsplit", "second_stage",
-               "second_gather", "second_copy", "second_waves")
+               "second_gather", "second_copy", "second_waves", "walker_tile")
 
     def get_tuning(self):
         t = _lib.MsdTuning()

@@ -342,6 +342,7 @@ void alloc_energy(msd_system* s) {
                        (size_t)NG * ((size_t)A.nv * A.no + (size_t)B.nv * B.no) * sizeof(cd);
   const size_t budget = (size_t)16 << 30;
   int wt = (int)std::max<size_t>(1, std::min<size_t>(NW, budget / std::max<size_t>(per_w, 1)));
+  if (s->tune.walker_tile > 0) wt = std::min(wt, s->tune.walker_tile);
   s->WT = wt;
   s->gl_chunk = s->tune.lambda_chunk > 0 ? std::min(s->tune.lambda_chunk, NG) : std::min(32, NG);
   s->n_lchunks = (NG + s->gl_chunk - 1) / s->gl_chunk;
@@ -1776,6 +1777,7 @@ void set_tuning_impl(msd_system* s, const msd_tuning& t) {
   if (t.second_gather < 0 || t.second_gather > 2) bad("second_gather");
   if (t.second_copy < 0 || t.second_copy > 2) bad("second_copy");
   if (t.second_waves != 0 && t.second_waves != 8 && t.second_waves != 16) bad("second_waves");
+  if (t.walker_tile < 0) bad("walker_tile");
   s->tune = t;
   free_energy(s);
   s->drop_graphs();
@@ -1811,6 +1813,7 @@ msd_status msd_get_tuning(msd_system* sys, msd_tuning* out) {
     out->second_gather = sys->second_flat ? 2 : 1;
     out->second_copy = sys->second_dma ? 2 : 1;
     out->second_waves = sys->second_waves;
+    out->walker_tile = sys->WT;
   }
   API_END(sys)
 }
@@ -1857,6 +1860,13 @@ msd_status msd_autotune(msd_system* sys, double dt, int32_t reps, msd_tuning* ou
       set_tuning_impl(sys, best);
     };
     sweep(&msd_tuning::fb_splitk, {1, 2, 4, 8, 16});
+    {
+      std::vector<int> c;
+      for (int wt : {16, 32, 64, 128, 256, 512})
+        if (wt < sys->NW) c.push_back(wt);
+      c.push_back(sys->NW);
+      sweep(&msd_tuning::walker_tile, c);
+    }
     int nmax = 0;
     if (msd::lambda_rows_fits(sys->ds[0], sys->ds[1], &nmax) && nmax <= 16)
       sweep(&msd_tuning::lambda_variant, {1, 2, 3, 4});
@@ -1892,6 +1902,7 @@ msd_status msd_autotune(msd_system* sys, double dt, int32_t reps, msd_tuning* ou
     out->second_gather = sys->second_flat ? 2 : 1;
     out->second_copy = sys->second_dma ? 2 : 1;
     out->second_waves = sys->second_waves;
+    out->walker_tile = sys->WT;
   }
   API_END(sys)
 }

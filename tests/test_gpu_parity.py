@@ -543,6 +543,7 @@ def test_uneven_batch_graph_matches_separate_systems():
     dict(lambda_variant=4, lambda_chunk=1, second_gsplit=1, second_stage=1, fb_splitk=1),
     dict(second_waves=16, second_stage=5, second_gsplit=3, second_copy=2),
     dict(second_waves=16, second_stage=3, second_gsplit=1, second_copy=1, second_gather=2),
+    dict(walker_tile=4),
 ])
 def test_tuning_overrides_keep_parity(tuning):
     """Ragged Cholesky chunks and stages (320 vectors split 5/7/3 ways) in
