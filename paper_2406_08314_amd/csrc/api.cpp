@@ -412,7 +412,7 @@ void alloc_energy(msd_system* s) {
   {
     int nmax = 0;
     const bool rows_fit = msd::lambda_rows_fits(A, B, &nmax);
-    s->energy_mixed = s->mixed && s->use_strings[0] && s->use_strings[1] && rows_fit;
+    s->energy_mixed = s->mixed && s->use_strings[0] && s->use_strings[1];
     const int X = A.nv * A.no + B.nv * B.no;
     const int elem = s->energy_mixed ? 8 : 16;  // bytes per staged Lambda entry
     // two 8-wave workgroups or one 16-wave workgroup per CU share its LDS
@@ -643,6 +643,10 @@ void run_energy_mixed(msd_system* s) {
         msd::launch_lambda_mfma32(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, Ta, Tb, s->LT32[0],
                                   s->LT32[1], s->Lam32[0], s->Lam32[1], s->v0, s->ex0,
                                   s->ZWp[0], s->ZWp[1], s->st);
+      else if (s->lambda_variant == 0)
+        msd::launch_lambda32(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, Ta, Tb, s->LT32[0],
+                             s->LT32[1], s->Lam32[0], s->Lam32[1], s->v0, s->ex0, s->ZWp[0],
+                             s->ZWp[1], s->st);
       else if (s->lambda_variant >= 2)
         msd::launch_lambda_wave32(A, B, nmax, s->lambda_exact, s->lambda_variant == 2, s->NW, w0, wt, s->NG, s->gl_chunk, Ta, Tb,
                                   s->LT32[0], s->LT32[1], s->Lam32[0], s->Lam32[1], s->v0, s->ex0,

@@ -135,6 +135,10 @@ void launch_lambda(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT,
                    int g_chunk, const cd* Ta, const cd* Tb, const cd* LTa, const cd* LTb,
                    cd* Lam_a, cd* Lam_b, cd* v0, cd* ex0, cd* ZWpart_a, cd* ZWpart_b,
                    hipStream_t st);
+void launch_lambda32(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
+                     int g_chunk, const cf* Ta, const cf* Tb, const cf* LTa, const cf* LTb,
+                     cf* Lam_a, cf* Lam_b, cd* v0, cd* ex0, cd* ZWpart_a, cd* ZWpart_b,
+                     hipStream_t st);
 bool lambda_rows_fits(const DevSpin& sa, const DevSpin& sb, int* nmax);
 void launch_lambda_rows(const DevSpin& sa, const DevSpin& sb, int nmax, int NW, int w0, int WT,
                         int NG, int g_chunk, const cd* Ta, const cd* Tb, const cd* LTa,

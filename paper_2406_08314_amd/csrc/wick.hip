@@ -658,24 +658,27 @@ __device__ __forceinline__ cd wave_sum(cd v) {
   return v;
 }
 
+template <class CT>
 __global__ __launch_bounds__(64) void k_lambda(DevSpin sa, DevSpin sb, int NW, int w0, int WT,
-                                               int NG, int g_chunk, const cd* __restrict__ Ta,
-                                               const cd* __restrict__ Tb,
-                                               const cd* __restrict__ LTa,
-                                               const cd* __restrict__ LTb,
-                                               cd* __restrict__ Lam_a, cd* __restrict__ Lam_b,
+                                               int NG, int g_chunk, const CT* __restrict__ Ta,
+                                               const CT* __restrict__ Tb,
+                                               const CT* __restrict__ LTa,
+                                               const CT* __restrict__ LTb,
+                                               CT* __restrict__ Lam_a, CT* __restrict__ Lam_b,
                                                cd* __restrict__ v0, cd* __restrict__ ex0,
                                                cd* __restrict__ ZWa, cd* __restrict__ ZWb) {
-  extern __shared__ cd sm[];
+  // LDS: ZW accumulators (double) first, then T[V,:] of both spins, Q and the
+  // Lambda rows in the working precision
+  extern __shared__ __align__(16) unsigned char sm_raw[];
   const int wl = blockIdx.x, chunk = blockIdx.y, n_chunks = gridDim.y;
   const int w = w0 + wl, lane = threadIdx.x;
-  cd* TVa = sm;                                   // [nv_a*N_a]
-  cd* TVb = TVa + sa.nv * sa.N;                   // [nv_b*N_b]
-  cd* Q = TVb + sb.nv * sb.N;                     // [max N^2]
-  cd* Lf = Q + max(sa.N * sa.N, sb.N * sb.N);     // [max nv*N]
   cd* ZWs[2];
-  ZWs[0] = Lf + max(sa.nv * sa.N, sb.nv * sb.N);  // [nv_a*no_a] accumulators
+  ZWs[0] = reinterpret_cast<cd*>(sm_raw);         // [nv_a*no_a] accumulators
   ZWs[1] = ZWs[0] + sa.nv * sa.no;                // [nv_b*no_b]
+  CT* TVa = reinterpret_cast<CT*>(ZWs[1] + sb.nv * sb.no);  // [nv_a*N_a]
+  CT* TVb = TVa + sa.nv * sa.N;                   // [nv_b*N_b]
+  CT* Q = TVb + sb.nv * sb.N;                     // [max N^2]
+  CT* Lf = Q + max(sa.N * sa.N, sb.N * sb.N);     // [max nv*N]
   for (int e = lane; e < sa.nv * sa.no; e += 64) ZWs[0][e] = cd{0.0, 0.0};
   for (int e = lane; e < sb.nv * sb.no; e += 64) ZWs[1][e] = cd{0.0, 0.0};
   for (int e = lane; e < sa.nv * sa.N; e += 64) {
@@ -691,16 +694,16 @@ __global__ __launch_bounds__(64) void k_lambda(DevSpin sa, DevSpin sb, int NW, i
   const int g0 = chunk * g_chunk, g1 = min(NG, g0 + g_chunk);
   for (int g = g0; g < g1; ++g) {
     // traces of both spins first: ZW needs v0a + v0b
-    cd va{0.0, 0.0}, vb{0.0, 0.0};
+    CT va{}, vb{};
     if (lane < sa.N) va = LTa[(((size_t)wl * NG + g) * sa.P + lane) * sa.N + lane];
     if (lane < sb.N) vb = LTb[(((size_t)wl * NG + g) * sb.P + lane) * sb.N + lane];
     va = wave_sum(va);
     vb = wave_sum(vb);
-    const cd vsum = va + vb;
+    const CT vsum = va + vb;
 #pragma unroll
     for (int s2 = 0; s2 < 2; ++s2) {
       const DevSpin& S = s2 ? sb : sa;
-      const cd* TV = s2 ? TVb : TVa;
+      const CT* TV = s2 ? TVb : TVa;
       const int N = S.N, nv = S.nv, no = S.no, X = nv * no;
       if (N == 0) {  // spin without electrons: zero traces
         if (lane == 0) {
@@ -709,9 +712,9 @@ __global__ __launch_bounds__(64) void k_lambda(DevSpin sa, DevSpin sb, int NW, i
         }
         continue;
       }
-      const cd* base = (s2 ? LTb : LTa) + ((size_t)wl * NG + g) * S.P * N;
+      const CT* base = (s2 ? LTb : LTa) + ((size_t)wl * NG + g) * S.P * N;
       const size_t ld = (size_t)N;
-      cd x{0.0, 0.0};
+      CT x{};
       for (int e = lane; e < N * N; e += 64) {
         const int j = e / N, c = e % N;
         Q[e] = base[(size_t)j * ld + c];
@@ -723,25 +726,25 @@ __global__ __launch_bounds__(64) void k_lambda(DevSpin sa, DevSpin sb, int NW, i
       }
       x = wave_sum(x);
       if (lane == 0) {
-        v0[((size_t)s2 * NW + w) * NG + g] = s2 ? vb : va;
-        ex0[((size_t)s2 * NW + w) * NG + g] = x;
+        v0[((size_t)s2 * NW + w) * NG + g] = to_cd(s2 ? vb : va);
+        ex0[((size_t)s2 * NW + w) * NG + g] = to_cd(x);
       }
       for (int e = lane; e < nv * N; e += 64) {
         const int a = e / N, c = e % N;
-        cd acc = -base[(size_t)(N + a) * ld + c];
+        CT acc = -base[(size_t)(N + a) * ld + c];
         for (int j = 0; j < N; ++j) cfma(acc, TV[a * N + j], Q[j * N + c]);
         Lf[e] = acc;
       }
       __syncthreads();
-      cd* Lo = (s2 ? Lam_b : Lam_a) + ((size_t)wl * NG + g) * X;
+      CT* Lo = (s2 ? Lam_b : Lam_a) + ((size_t)wl * NG + g) * X;
       cd* Z = ZWs[s2];
       for (int e = lane; e < X; e += 64) {
         const int a = e / no, i = e % no, oc = S.oslot[i];
-        cd xi{0.0, 0.0};
+        CT xi{};
         for (int c = 0; c < N; ++c) cfma(xi, Lf[a * N + c], Q[c * N + oc]);
-        const cd lam = Lf[a * N + oc];
+        const CT lam = Lf[a * N + oc];
         Lo[e] = lam;
-        Z[e] += xi - vsum * lam;
+        Z[e] += to_cd(xi - vsum * lam);
       }
       __syncthreads();
     }
@@ -1102,18 +1105,35 @@ void launch_lambda_rows32(const DevSpin& sa, const DevSpin& sb, int nmax, int NW
                            v0, ex0, ZWpart_a, ZWpart_b, st);
 }
 
+template <class CT>
+static void launch_lambda_t(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
+                            int g_chunk, const CT* Ta, const CT* Tb, const CT* LTa,
+                            const CT* LTb, CT* Lam_a, CT* Lam_b, cd* v0, cd* ex0, cd* ZWpart_a,
+                            cd* ZWpart_b, hipStream_t st) {
+  const int n_chunks = (NG + g_chunk - 1) / g_chunk;
+  const size_t words = (size_t)sa.nv * sa.N + (size_t)sb.nv * sb.N +
+                       (size_t)max(sa.N * sa.N, sb.N * sb.N) +
+                       (size_t)max(sa.nv * sa.N, sb.nv * sb.N);
+  const size_t bytes = ((size_t)sa.nv * sa.no + (size_t)sb.nv * sb.no) * sizeof(cd) +
+                       words * sizeof(CT);
+  hipLaunchKernelGGL((k_lambda<CT>), dim3(WT, n_chunks), dim3(64), bytes, st, sa, sb, NW, w0, WT,
+                     NG, g_chunk, Ta, Tb, LTa, LTb, Lam_a, Lam_b, v0, ex0, ZWpart_a, ZWpart_b);
+}
+
 void launch_lambda(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
                    int g_chunk, const cd* Ta, const cd* Tb, const cd* LTa, const cd* LTb,
                    cd* Lam_a, cd* Lam_b, cd* v0, cd* ex0, cd* ZWpart_a, cd* ZWpart_b,
                    hipStream_t st) {
-  const int n_chunks = (NG + g_chunk - 1) / g_chunk;
-  const size_t words = (size_t)sa.nv * sa.N + (size_t)sb.nv * sb.N +
-                       (size_t)max(sa.N * sa.N, sb.N * sb.N) +
-                       (size_t)max(sa.nv * sa.N, sb.nv * sb.N) + (size_t)sa.nv * sa.no +
-                       (size_t)sb.nv * sb.no;
-  hipLaunchKernelGGL(k_lambda, dim3(WT, n_chunks), dim3(64), words * sizeof(cd), st, sa, sb, NW,
-                     w0, WT, NG, g_chunk, Ta, Tb, LTa, LTb, Lam_a, Lam_b, v0, ex0, ZWpart_a,
-                     ZWpart_b);
+  launch_lambda_t<cd>(sa, sb, NW, w0, WT, NG, g_chunk, Ta, Tb, LTa, LTb, Lam_a, Lam_b, v0, ex0,
+                      ZWpart_a, ZWpart_b, st);
+}
+
+void launch_lambda32(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
+                     int g_chunk, const cf* Ta, const cf* Tb, const cf* LTa, const cf* LTb,
+                     cf* Lam_a, cf* Lam_b, cd* v0, cd* ex0, cd* ZWpart_a, cd* ZWpart_b,
+                     hipStream_t st) {
+  launch_lambda_t<cf>(sa, sb, NW, w0, WT, NG, g_chunk, Ta, Tb, LTa, LTb, Lam_a, Lam_b, v0, ex0,
+                      ZWpart_a, ZWpart_b, st);
 }
 
 // ============================================================================
@@ -1604,7 +1624,8 @@ void init_wick_attributes() {
   const int lim = 150 * 1024;
   hipFuncSetAttribute((const void*)k_ref_inverse, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   hipFuncSetAttribute((const void*)k_green, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-  hipFuncSetAttribute((const void*)k_lambda, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  hipFuncSetAttribute((const void*)k_lambda<cd>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  hipFuncSetAttribute((const void*)k_lambda<cf>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   for (const void* f : {(const void*)k_energy_second<cd, 4, false>,
                         (const void*)k_energy_second<cd, 4, true>,
                         (const void*)k_energy_second<cf, 4, false>,
