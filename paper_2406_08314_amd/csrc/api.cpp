@@ -144,6 +144,8 @@ struct msd_system {
   float* Y32 = nullptr;                     // [2 NW][NG]
   float* fb_ws32 = nullptr;
   cf* LT32[2] = {nullptr, nullptr};
+  double* LR64[2] = {nullptr, nullptr};     // [NG][N_s][M] reference rows of L (FP64)
+  cd* Q64[2] = {nullptr, nullptr};          // [wl][g][N_s x N_s] FP64 Q for the traces
   cf* Lam32[2] = {nullptr, nullptr};
   bool energy_mixed = false;                // mixed energy path usable for this trial
 
@@ -325,8 +327,11 @@ void build_derived(msd_system* s) {
   }
   msd::launch_gather_rows(s->L, s->NG, s->M, s->rows_all_dev, s->P_all, s->L_rows, s->st);
   if (s->mixed) {
-    for (int sp = 0; sp < 2; ++sp)
+    for (int sp = 0; sp < 2; ++sp) {
       msd::launch_f64_to_f32(s->L_lt[sp], s->Llt32[sp], (int64_t)s->NG * s->ds[sp].P * s->M, s->st);
+      // the first N rows of a spin's row list are its reference orbitals
+      msd::launch_gather_rows(s->L, s->NG, s->M, s->ds[sp].rows, s->ds[sp].N, s->LR64[sp], s->st);
+    }
     msd::launch_f64_to_f32(s->L_rows, s->Lrows32, (int64_t)s->NG * s->P_all * s->M, s->st);
   }
   s->check_launch("gather rows");
@@ -339,7 +344,9 @@ void alloc_energy(msd_system* s) {
   const msd::DevSpin& B = s->ds[1];
   const int NG = s->NG, NW = s->NW;
   const size_t per_w = (size_t)NG * ((size_t)A.P * A.N + (size_t)B.P * B.N) * sizeof(cd) +
-                       (size_t)NG * ((size_t)A.nv * A.no + (size_t)B.nv * B.no) * sizeof(cd);
+                       (size_t)NG * ((size_t)A.nv * A.no + (size_t)B.nv * B.no) * sizeof(cd) +
+                       (s->mixed ? (size_t)NG * ((size_t)A.N * A.N + (size_t)B.N * B.N) * sizeof(cd)
+                                 : 0);
   const size_t budget = (size_t)16 << 30;
   int wt = (int)std::max<size_t>(1, std::min<size_t>(NW, budget / std::max<size_t>(per_w, 1)));
   if (s->tune.walker_tile > 0) wt = std::min(wt, s->tune.walker_tile);
@@ -447,6 +454,7 @@ void alloc_energy(msd_system* s) {
     if (s->energy_mixed) {
       s->LT32[sp] = E.get<cf>((size_t)NG * D.P * wt * D.N);
       s->Lam32[sp] = E.get<cf>((size_t)wt * NG * D.nv * D.no);
+      s->Q64[sp] = E.get<cd>((size_t)NG * D.N * wt * D.N);
     } else {
       if (!(s->o.energy_algo == 3 && msd::chol_contract_fits(s->ds[0], s->ds[1], &wbf)))
         s->LT[sp] = E.get<cd>((size_t)NG * D.P * wt * D.N);
@@ -634,6 +642,20 @@ void run_energy_mixed(msd_system* s) {
         g.C32 = reinterpret_cast<float*>(s->LT32[sp]);
         g.c_block = 2 * D.N;  // LT tile of (walker, vector) contiguous: [wl][g][p][n]
         msd::launch_gemm32(g, s->st);
+        // FP64 Q = L[R, :] T for the mean-field traces
+        msd::GemmArgs q;
+        q.M = s->NG * D.N;
+        q.N = 2 * wt * D.N;
+        q.K = s->M;
+        q.A = s->LR64[sp];
+        q.lda = s->M;
+        q.a_kmaj = true;
+        q.B = reinterpret_cast<const double*>(s->sw[sp].T + (size_t)w0 * D.N);
+        q.ldb = 2 * (int64_t)s->NW * D.N;
+        q.b_kmaj = false;
+        q.C = reinterpret_cast<double*>(s->Q64[sp]);
+        q.c_block = 2 * D.N;
+        msd::launch_gemm(q, s->st);
       });
     }
     s->timed(ST_LAMBDA, [&] {
@@ -655,6 +677,10 @@ void run_energy_mixed(msd_system* s) {
         msd::launch_lambda_rows32(A, B, nmax, s->NW, w0, wt, s->NG, s->gl_chunk, Ta, Tb,
                                   s->LT32[0], s->LT32[1], s->Lam32[0], s->Lam32[1], s->v0, s->ex0,
                                   s->ZWp[0], s->ZWp[1], s->st);
+    });
+    s->timed(ST_LAMBDA, [&] {
+      msd::launch_traces64(s->Q64[0], s->Q64[1], A.N, B.N, s->NW, w0, wt, s->NG, s->v0, s->ex0,
+                           s->st);
     });
     s->timed(ST_EGAMMA, [&] {
       msd::launch_energy_second32(A, B, s->dp, s->plan, s->n_itemblocks, s->second_waves, s->NW,
@@ -1298,7 +1324,10 @@ void set_trial_rows(msd_system* sys, const double* ci, const int32_t* occ_a,
   if (sys->mixed) {
     sys->Gp32 = T.get<float>((size_t)2 * NW * sys->P_all * M);
     sys->Lrows32 = T.get<float>((size_t)NG * sys->P_all * M);
-    for (int sp = 0; sp < 2; ++sp) sys->Llt32[sp] = T.get<float>((size_t)NG * sys->ds[sp].P * M);
+    for (int sp = 0; sp < 2; ++sp) {
+      sys->Llt32[sp] = T.get<float>((size_t)NG * sys->ds[sp].P * M);
+      sys->LR64[sp] = T.get<double>((size_t)NG * sys->ds[sp].N * M);
+    }
   }
   sys->dp.n_pair = sys->tt.n_pair;
   sys->dp.x = T.upload(sys->tt.pr_x, st);

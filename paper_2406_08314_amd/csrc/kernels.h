@@ -216,6 +216,9 @@ void launch_weights(int NW, int NG, const double* x, const cd* xbar, const cd* l
 void launch_qr(cd* phi, int M, int Ntot, int NW, int na, int nb, const int* mask, double* ldet,
                cd* logo, hipStream_t st);
 void launch_frozen_mask(int NW, const double* weights, int* mask, hipStream_t st);
+// v0 = tr Q, ex0 = tr QQ in FP64 from Q tiles [wl][g][N x N] of both spins.
+void launch_traces64(const cd* Qa, const cd* Qb, int Na, int Nb, int NW, int w0, int WT, int NG,
+                     cd* v0, cd* ex0, hipStream_t st);
 void launch_fill_i32(int* p, int n, int v, hipStream_t st);
 void launch_copy_walkers(int NW, int M, int Ntot, int na, int nb, const cd* pa, const cd* pb,
                          cd* phi, bool to_internal, cd* out_a, cd* out_b, hipStream_t st);
