@@ -218,33 +218,41 @@ void launch_copy_walkers(int NW, int M, int Ntot, int na, int nb, const cd* pa, 
 
 // out[p][q] = sum_g sum_r L^g_pr L^g_rq  (the exchange-like one-body term of Eq. 4)
 // Mean-field traces in double precision for the mixed form: v0 = tr Q and
-// ex0 = tr QQ of Q^g = L^g[R, :] T, from FP64 tiles [wl][g][N x N] (one
-// thread per walker, vector and spin).  They overwrite the values the
-// single-precision intermediates kernel derived from the FP32 Q.
-__global__ void k_traces64(const cd* __restrict__ Qa, const cd* __restrict__ Qb, int Na, int Nb,
-                           int NW, int w0, int WT, int NG, cd* __restrict__ v0,
-                           cd* __restrict__ ex0) {
-  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid >= (int64_t)2 * WT * NG) return;
-  const int s2 = (int)(tid / ((int64_t)WT * NG));
-  const int64_t r = tid % ((int64_t)WT * NG);
-  const int wl = (int)(r / NG), g = (int)(r % NG);
+// ex0 = tr QQ of Q^g = L^g[R, :] T, from FP64 tiles [wl][g][N x N] (one wave
+// per walker, vector and spin; lanes over the tile's entries).  They overwrite
+// the values the single-precision intermediates kernel derived from the FP32 Q.
+__global__ __launch_bounds__(64) void k_traces64(const cd* __restrict__ Qa,
+                                                 const cd* __restrict__ Qb, int Na, int Nb,
+                                                 int NW, int w0, int NG, cd* __restrict__ v0,
+                                                 cd* __restrict__ ex0) {
+  const int s2 = blockIdx.y, lane = threadIdx.x;
+  const int wl = blockIdx.x / NG, g = blockIdx.x % NG;
   const int N = s2 ? Nb : Na;
   const cd* Q = (s2 ? Qb : Qa) + ((size_t)wl * NG + g) * N * N;
   cd v{0.0, 0.0}, x{0.0, 0.0};
-  for (int j = 0; j < N; ++j) {
-    v += Q[j * N + j];
-    for (int c = 0; c < N; ++c) cfma(x, Q[j * N + c], Q[c * N + j]);
+  for (int e = lane; e < N * N; e += 64) {
+    const int j = e / N, c = e % N;
+    const cd q = Q[e];
+    if (j == c) v += q;
+    cfma(x, q, Q[c * N + j]);
   }
-  v0[((size_t)s2 * NW + w0 + wl) * NG + g] = v;
-  ex0[((size_t)s2 * NW + w0 + wl) * NG + g] = x;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    v.re += __shfl_xor(v.re, off, 64);
+    v.im += __shfl_xor(v.im, off, 64);
+    x.re += __shfl_xor(x.re, off, 64);
+    x.im += __shfl_xor(x.im, off, 64);
+  }
+  if (lane == 0) {
+    v0[((size_t)s2 * NW + w0 + wl) * NG + g] = v;
+    ex0[((size_t)s2 * NW + w0 + wl) * NG + g] = x;
+  }
 }
 
 void launch_traces64(const cd* Qa, const cd* Qb, int Na, int Nb, int NW, int w0, int WT, int NG,
                      cd* v0, cd* ex0, hipStream_t st) {
-  const int64_t n = (int64_t)2 * WT * NG;
-  hipLaunchKernelGGL(k_traces64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Qa, Qb, Na,
-                     Nb, NW, w0, WT, NG, v0, ex0);
+  hipLaunchKernelGGL(k_traces64, dim3((unsigned)WT * NG, 2), dim3(64), 0, st, Qa, Qb, Na, Nb, NW,
+                     w0, NG, v0, ex0);
 }
 
 }  // namespace msd
