@@ -664,7 +664,7 @@ void run_energy_mixed(msd_system* s) {
       if (s->lambda_variant == 4)
         msd::launch_lambda_mfma32(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, Ta, Tb, s->LT32[0],
                                   s->LT32[1], s->Lam32[0], s->Lam32[1], s->v0, s->ex0,
-                                  s->ZWp[0], s->ZWp[1], s->st);
+                                  s->ZWp[0], s->ZWp[1], s->Q64[0], s->Q64[1], s->st);
       else if (s->lambda_variant == 0)
         msd::launch_lambda32(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, Ta, Tb, s->LT32[0],
                              s->LT32[1], s->Lam32[0], s->Lam32[1], s->v0, s->ex0, s->ZWp[0],
@@ -678,10 +678,12 @@ void run_energy_mixed(msd_system* s) {
                                   s->LT32[0], s->LT32[1], s->Lam32[0], s->Lam32[1], s->v0, s->ex0,
                                   s->ZWp[0], s->ZWp[1], s->st);
     });
-    s->timed(ST_LAMBDA, [&] {
-      msd::launch_traces64(s->Q64[0], s->Q64[1], A.N, B.N, s->NW, w0, wt, s->NG, s->v0, s->ex0,
-                           s->st);
-    });
+    if (s->lambda_variant != 4) {  // the matrix-core kernel reads the FP64 Q itself
+      s->timed(ST_LAMBDA, [&] {
+        msd::launch_traces64(s->Q64[0], s->Q64[1], A.N, B.N, s->NW, w0, wt, s->NG, s->v0, s->ex0,
+                             s->st);
+      });
+    }
     s->timed(ST_EGAMMA, [&] {
       msd::launch_energy_second32(A, B, s->dp, s->plan, s->n_itemblocks, s->second_waves, s->NW,
                                   w0, wt, s->NG, s->gsplit, s->second_G, s->second_maxk,

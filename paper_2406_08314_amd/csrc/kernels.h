@@ -160,10 +160,11 @@ void launch_lambda_mfma(const DevSpin& sa, const DevSpin& sb, int NW, int w0, in
                         int g_chunk, const cd* Ta, const cd* Tb, const cd* LTa, const cd* LTb,
                         cd* Lam_a, cd* Lam_b, cd* v0, cd* ex0, cd* ZWpart_a, cd* ZWpart_b,
                         hipStream_t st);
+// (mixed form; v0, ex0 from the FP64 Q tiles Q64a/b when not null)
 void launch_lambda_mfma32(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
                           int g_chunk, const cf* Ta, const cf* Tb, const cf* LTa, const cf* LTb,
                           cf* Lam_a, cf* Lam_b, cd* v0, cd* ex0, cd* ZWpart_a, cd* ZWpart_b,
-                          hipStream_t st);
+                          const cd* Q64a, const cd* Q64b, hipStream_t st);
 // exact: both spins have N == nmax and an identity occupied window;
 // prefetch: next vector's LT row loaded ahead into registers (exact shapes).
 void launch_lambda_wave(const DevSpin& sa, const DevSpin& sb, int nmax, bool exact, bool prefetch,

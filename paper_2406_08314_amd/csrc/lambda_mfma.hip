@@ -9,6 +9,8 @@
 //   Xi  = Lam Q                            (window columns = all N)
 //   ZW += Xi - (v0_alpha + v0_beta) Lam     (summed over the workgroup's vectors)
 //   Lam -> HBM (window layout [w][g][a * N + i]).
+// In the mixed form v0 and ex0 come from FP64 tiles of Q (Q64a/b, [w][g][8 x 8])
+// instead of the FP32 LT tile.
 // Both complex products are real GEMMs on v_mfma_{f64,f32}_16x16x4:
 //   [Lr Li] = [Tr Ti] [[Qr Qi]; [-Qi Qr]]   (64 x 16 = (64 x 16)(16 x 16))
 // with A = [Tr Ti] of the walker's virtual rows held in registers for all
@@ -80,7 +82,9 @@ __global__ __launch_bounds__(64) void k_lambda_mfma(DevSpin sa, DevSpin sb, int 
                                                     typename Mfma<R>::cx_t* __restrict__ Lam_a,
                                                     typename Mfma<R>::cx_t* __restrict__ Lam_b,
                                                     cd* __restrict__ v0, cd* __restrict__ ex0,
-                                                    cd* __restrict__ ZWa, cd* __restrict__ ZWb) {
+                                                    cd* __restrict__ ZWa, cd* __restrict__ ZWb,
+                                                    const cd* __restrict__ Q64a,
+                                                    const cd* __restrict__ Q64b) {
   typedef typename Mfma<R>::cx_t C;
   typedef typename Mfma<R>::acc_t acc_t;
   // LT tiles (double buffer) and the Lambda transpose, all in LDS
@@ -135,24 +139,48 @@ __global__ __launch_bounds__(64) void k_lambda_mfma(DevSpin sa, DevSpin sb, int 
     __syncthreads();  // tile b has landed; the other buffer's readers are done
     if (g + 1 < g1) fetch(g + 1, b ^ 1);
     const C* Q = lt[b];  // rows 0..7 = Q, rows 8.. = LT[V]
-    // traces: v0 (this spin and the other), ex0 = sum_jc Q_jc Q_cj
-    C qe = Q[(lane >> 3) * LM_N + (lane & 7)];
-    C qt = Q[(lane & 7) * LM_N + (lane >> 3)];
-    C x = qe * qt;
-    C vd = (lane >> 3) == (lane & 7) ? qe : C{};
-    const C* o = LTo + ((size_t)wl * NG + g) * Po * LM_N;
-    C vo = lane < LM_N ? o[lane * LM_N + lane] : C{};
-    vd.re = wsum(vd.re);
-    vd.im = wsum(vd.im);
-    x.re = wsum(x.re);
-    x.im = wsum(x.im);
-    vo.re = wsum(vo.re);
-    vo.im = wsum(vo.im);
-    if (lane == 0) {
-      v0[((size_t)s2 * NW + w) * NG + g] = to_cd(vd);
-      ex0[((size_t)s2 * NW + w) * NG + g] = to_cd(x);
+    // traces: v0 (this spin and the other), ex0 = sum_jc Q_jc Q_cj; from the
+    // FP64 Q tiles when given (mixed form), else from this tile
+    R vr, vi;
+    if (Q64a) {
+      const cd* q = (s2 ? Q64b : Q64a) + ((size_t)wl * NG + g) * LM_N * LM_N;
+      const cd* qo = (s2 ? Q64a : Q64b) + ((size_t)wl * NG + g) * LM_N * LM_N;
+      const cd qe = q[(lane >> 3) * LM_N + (lane & 7)];
+      cd x = qe * q[(lane & 7) * LM_N + (lane >> 3)];
+      cd vd = (lane >> 3) == (lane & 7) ? qe : cd{0.0, 0.0};
+      cd vo = lane < LM_N ? qo[lane * LM_N + lane] : cd{0.0, 0.0};
+      vd.re = wsum(vd.re);
+      vd.im = wsum(vd.im);
+      x.re = wsum(x.re);
+      x.im = wsum(x.im);
+      vo.re = wsum(vo.re);
+      vo.im = wsum(vo.im);
+      if (lane == 0) {
+        v0[((size_t)s2 * NW + w) * NG + g] = vd;
+        ex0[((size_t)s2 * NW + w) * NG + g] = x;
+      }
+      vr = R(vd.re + vo.re);
+      vi = R(vd.im + vo.im);
+    } else {
+      C qe = Q[(lane >> 3) * LM_N + (lane & 7)];
+      C qt = Q[(lane & 7) * LM_N + (lane >> 3)];
+      C x = qe * qt;
+      C vd = (lane >> 3) == (lane & 7) ? qe : C{};
+      const C* o = LTo + ((size_t)wl * NG + g) * Po * LM_N;
+      C vo = lane < LM_N ? o[lane * LM_N + lane] : C{};
+      vd.re = wsum(vd.re);
+      vd.im = wsum(vd.im);
+      x.re = wsum(x.re);
+      x.im = wsum(x.im);
+      vo.re = wsum(vo.re);
+      vo.im = wsum(vo.im);
+      if (lane == 0) {
+        v0[((size_t)s2 * NW + w) * NG + g] = to_cd(vd);
+        ex0[((size_t)s2 * NW + w) * NG + g] = to_cd(x);
+      }
+      vr = vd.re + vo.re;
+      vi = vd.im + vo.im;
     }
-    const R vr = vd.re + vo.re, vi = vd.im + vo.im;
     // block matrix [[Qr Qi]; [-Qi Qr]]: operand lane l, k 4s + l / 16, column l % 16
     R bq[4];
 #pragma unroll
@@ -234,16 +262,18 @@ void launch_lambda_mfma(const DevSpin& sa, const DevSpin& sb, int NW, int w0, in
                         hipStream_t st) {
   const dim3 grid(WT, (NG + g_chunk - 1) / g_chunk, 2);
   hipLaunchKernelGGL(k_lambda_mfma<double>, grid, dim3(64), 0, st, sa, sb, NW, w0, WT, NG,
-                     g_chunk, Ta, Tb, LTa, LTb, Lam_a, Lam_b, v0, ex0, ZWpart_a, ZWpart_b);
+                     g_chunk, Ta, Tb, LTa, LTb, Lam_a, Lam_b, v0, ex0, ZWpart_a, ZWpart_b,
+                     (const cd*)nullptr, (const cd*)nullptr);
 }
 
 void launch_lambda_mfma32(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
                           int g_chunk, const cf* Ta, const cf* Tb, const cf* LTa, const cf* LTb,
                           cf* Lam_a, cf* Lam_b, cd* v0, cd* ex0, cd* ZWpart_a, cd* ZWpart_b,
-                          hipStream_t st) {
+                          const cd* Q64a, const cd* Q64b, hipStream_t st) {
   const dim3 grid(WT, (NG + g_chunk - 1) / g_chunk, 2);
   hipLaunchKernelGGL(k_lambda_mfma<float>, grid, dim3(64), 0, st, sa, sb, NW, w0, WT, NG,
-                     g_chunk, Ta, Tb, LTa, LTb, Lam_a, Lam_b, v0, ex0, ZWpart_a, ZWpart_b);
+                     g_chunk, Ta, Tb, LTa, LTb, Lam_a, Lam_b, v0, ex0, ZWpart_a, ZWpart_b, Q64a,
+                     Q64b);
 }
 
 }  // namespace msd
