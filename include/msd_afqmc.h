@@ -214,8 +214,13 @@ typedef struct {
                              registers; only where both spins have N = 8 or 16 and the
                              whole occupied window, else as 2), 4 = matrix-core kernel
                              (both spins N = 8 with the whole occupied window and at
-                             most 64 active virtuals, else as 2).  2-4 need N <= 16    */
-  int32_t lambda_chunk;   /* Cholesky vectors per intermediates workgroup (1..NG)         */
+                             most 64 active virtuals, else as 2), 5 = matrix-core kernel
+                             that also forms the Cholesky contraction L^g T itself, so
+                             it never goes through HBM (shapes of 4 with M <= 64 and
+                             n_vir_act + 8 <= 64 in FP64 / 80 in the mixed form, else
+                             as 4).  2-5 need N <= 16                                  */
+  int32_t lambda_chunk;   /* Cholesky vectors per intermediates workgroup (1..NG); the
+                             fused kernel's workgroup holds four walkers x two spins   */
   int32_t second_gsplit;  /* Cholesky-range split of the second-order kernel (1..64)      */
   int32_t second_stage;   /* Cholesky vectors per LDS stage of the second-order kernel
                              (1..32, bounded by 150 KB of LDS)                             */

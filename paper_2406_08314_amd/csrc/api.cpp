@@ -131,7 +131,8 @@ struct msd_system {
   double* fb_ws = nullptr;           // split-K workspace of the force-bias GEMM
   int fb_splitk = 1, fb_splitk_auto = 1, fb_ws_cap = 0;
   msd_tuning tune{};                 // launch-shape overrides (0 = automatic)
-  int lambda_variant = 1;            // resolved: 1 rows kernel, 2 one-wave kernel
+  int lambda_variant = 1;            // resolved: 0 generic, 1 rows, 2/3 one-wave, 4 matrix-core
+                                     // LT-tile kernel, 5 fused contraction + Lambda
   bool lambda_exact = false;         // N == nmax per spin and identity occupied window
 
   // mixed form: single-precision copies of the GEMM operands
@@ -148,6 +149,13 @@ struct msd_system {
   cd* Q64[2] = {nullptr, nullptr};          // [wl][g][N_s x N_s] FP64 Q for the traces
   cf* Lam32[2] = {nullptr, nullptr};
   bool energy_mixed = false;                // mixed energy path usable for this trial
+
+  // fused contraction + Lambda kernel: restricted rows of L per spin, k-major,
+  // [NG][64][lf_P16], rows V_act then R (FP64, and FP32 in the mixed form)
+  int lf_P16 = 0;
+  bool lf_fits64 = false, lf_fits32 = false;
+  double* Slf[2] = {nullptr, nullptr};
+  float* Slf32[2] = {nullptr, nullptr};
 
   // energy work (lazily sized)
   int WT = 0, gl_chunk = 16, n_lchunks = 0;
@@ -326,6 +334,10 @@ void build_derived(msd_system* s) {
     msd::launch_gather_rows(s->L, s->NG, s->M, D.rows, D.P, s->L_lt[sp], s->st);
   }
   msd::launch_gather_rows(s->L, s->NG, s->M, s->rows_all_dev, s->P_all, s->L_rows, s->st);
+  for (int sp = 0; sp < 2; ++sp)
+    if (s->lf_fits64 || s->lf_fits32)
+      msd::launch_gather_ltl(s->L, s->NG, s->M, s->ds[sp], s->lf_P16, s->Slf[sp], s->Slf32[sp],
+                             s->st);
   if (s->mixed) {
     for (int sp = 0; sp < 2; ++sp) {
       msd::launch_f64_to_f32(s->L_lt[sp], s->Llt32[sp], (int64_t)s->NG * s->ds[sp].P * s->M, s->st);
@@ -351,8 +363,6 @@ void alloc_energy(msd_system* s) {
   int wt = (int)std::max<size_t>(1, std::min<size_t>(NW, budget / std::max<size_t>(per_w, 1)));
   if (s->tune.walker_tile > 0) wt = std::min(wt, s->tune.walker_tile);
   s->WT = wt;
-  s->gl_chunk = s->tune.lambda_chunk > 0 ? std::min(s->tune.lambda_chunk, NG) : std::min(32, NG);
-  s->n_lchunks = (NG + s->gl_chunk - 1) / s->gl_chunk;
   int slot = 0;
   // Per spin: same-spin second-order terms as row-pair items of each string
   // (merged kernel) or as a list of distinct minors.  Cost per Cholesky vector
@@ -438,25 +448,44 @@ void alloc_energy(msd_system* s) {
         if (S.occ_slot[i] != i) s->lambda_exact = false;
     }
     // 0: the generic one-wave kernel (windows beyond the row kernels' limits)
-    // default: the matrix-core kernel where it applies, else the one-wave kernel
+    // default: the fused contraction + Lambda kernel where it applies, else the
+    // matrix-core LT-tile kernel, else the one-wave kernel
     const bool mfma_ok = s->lambda_exact && msd::lambda_mfma_fits(A, B);
-    const int want = s->tune.lambda_variant ? s->tune.lambda_variant : (mfma_ok ? 4 : 2);
+    const bool fused_ok = s->lambda_exact && (s->energy_mixed ? s->lf_fits32 : s->lf_fits64);
+    const int want = s->tune.lambda_variant ? s->tune.lambda_variant
+                     : fused_ok                 ? 5
+                     : mfma_ok                  ? 4
+                                                : 2;
     s->lambda_variant = !rows_fit ? 0
                         : (want == 1 || nmax > 16) ? 1
                         : (want == 3 && s->lambda_exact) ? 3
-                        : (want == 4 && mfma_ok) ? 4 : 2;
+                        : (want == 4 && mfma_ok) ? 4
+                        : (want == 5 && fused_ok) ? 5
+                        : (want >= 4 && mfma_ok) ? 4 : 2;
   }
+  if (s->tune.lambda_chunk > 0) {
+    s->gl_chunk = std::min(s->tune.lambda_chunk, NG);
+  } else if (s->lambda_variant == 5) {
+    // about one workgroup of four walkers per CU and chunk (two in FP32)
+    const int n_wgrp = (wt + 3) / 4, target = s->energy_mixed ? 512 : 256;
+    const int n_chunks = std::max(1, std::min(NG, (target + n_wgrp / 2) / n_wgrp));
+    s->gl_chunk = (NG + n_chunks - 1) / n_chunks;
+  } else {
+    s->gl_chunk = std::min(32, NG);
+  }
+  s->n_lchunks = (NG + s->gl_chunk - 1) / s->gl_chunk;
   s->n_slots = slot;  // every slot is written by exactly one workgroup
   Arena& E = s->energy_mem;
   for (int sp = 0; sp < 2; ++sp) {
     const msd::DevSpin& D = s->ds[sp];
     int wbf = 0;
     if (s->energy_mixed) {
-      s->LT32[sp] = E.get<cf>((size_t)NG * D.P * wt * D.N);
+      if (s->lambda_variant != 5) s->LT32[sp] = E.get<cf>((size_t)NG * D.P * wt * D.N);
       s->Lam32[sp] = E.get<cf>((size_t)wt * NG * D.nv * D.no);
       s->Q64[sp] = E.get<cd>((size_t)NG * D.N * wt * D.N);
     } else {
-      if (!(s->o.energy_algo == 3 && msd::chol_contract_fits(s->ds[0], s->ds[1], &wbf)))
+      if (!(s->o.energy_algo == 3 && msd::chol_contract_fits(s->ds[0], s->ds[1], &wbf)) &&
+          s->lambda_variant != 5)
         s->LT[sp] = E.get<cd>((size_t)NG * D.P * wt * D.N);
       s->Lam[sp] = E.get<cd>((size_t)wt * NG * D.nv * D.no);
     }
@@ -629,6 +658,7 @@ void run_energy_mixed(msd_system* s) {
       const msd::DevSpin& D = s->ds[sp];
       if (D.N == 0) continue;
       s->timed(ST_LT_GEMM, [&] {
+        if (s->lambda_variant != 5) {  // the fused kernel forms LT itself
         msd::GemmArgs32 g;
         g.M = s->NG * D.P;
         g.N = 2 * wt * D.N;
@@ -642,6 +672,7 @@ void run_energy_mixed(msd_system* s) {
         g.C32 = reinterpret_cast<float*>(s->LT32[sp]);
         g.c_block = 2 * D.N;  // LT tile of (walker, vector) contiguous: [wl][g][p][n]
         msd::launch_gemm32(g, s->st);
+        }
         // FP64 Q = L[R, :] T for the mean-field traces
         msd::GemmArgs q;
         q.M = s->NG * D.N;
@@ -661,7 +692,11 @@ void run_energy_mixed(msd_system* s) {
     s->timed(ST_LAMBDA, [&] {
       const cf* Ta = reinterpret_cast<const cf*>(s->T32[0]);
       const cf* Tb = reinterpret_cast<const cf*>(s->T32[1]);
-      if (s->lambda_variant == 4)
+      if (s->lambda_variant == 5)
+        msd::launch_ltl_mfma32(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, s->M, s->Slf32[0],
+                               s->Slf32[1], Ta, Tb, s->Lam32[0], s->Lam32[1], s->v0, s->ex0,
+                               s->ZWp[0], s->ZWp[1], s->Q64[0], s->Q64[1], s->st);
+      else if (s->lambda_variant == 4)
         msd::launch_lambda_mfma32(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, Ta, Tb, s->LT32[0],
                                   s->LT32[1], s->Lam32[0], s->Lam32[1], s->v0, s->ex0,
                                   s->ZWp[0], s->ZWp[1], s->Q64[0], s->Q64[1], s->st);
@@ -678,7 +713,7 @@ void run_energy_mixed(msd_system* s) {
                                   s->LT32[0], s->LT32[1], s->Lam32[0], s->Lam32[1], s->v0, s->ex0,
                                   s->ZWp[0], s->ZWp[1], s->st);
     });
-    if (s->lambda_variant != 4) {  // the matrix-core kernel reads the FP64 Q itself
+    if (s->lambda_variant < 4) {  // the matrix-core kernels read the FP64 Q themselves
       s->timed(ST_LAMBDA, [&] {
         msd::launch_traces64(s->Q64[0], s->Q64[1], A.N, B.N, s->NW, w0, wt, s->NG, s->v0, s->ex0,
                              s->st);
@@ -730,7 +765,7 @@ void run_energy(msd_system* s) {
                                   s->gl_chunk, wb, s->v0, s->ex0, s->st);
       });
     } else {
-      for (int sp = 0; sp < 2; ++sp) {
+      for (int sp = 0; sp < 2 && s->lambda_variant != 5; ++sp) {
         const msd::DevSpin& D = s->ds[sp];
         if (D.N == 0) continue;
         s->timed(ST_LT_GEMM, [&] {
@@ -751,7 +786,11 @@ void run_energy(msd_system* s) {
       }
       int nmax = 0;
       s->timed(ST_LAMBDA, [&] {
-        if (s->lambda_variant == 4)
+        if (s->lambda_variant == 5)
+          msd::launch_ltl_mfma(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, s->M, s->Slf[0],
+                               s->Slf[1], s->sw[0].T, s->sw[1].T, s->Lam[0], s->Lam[1], s->v0,
+                               s->ex0, s->ZWp[0], s->ZWp[1], s->st);
+        else if (s->lambda_variant == 4)
           msd::launch_lambda_mfma(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, s->sw[0].T,
                                   s->sw[1].T, s->LT[0], s->LT[1], s->Lam[0], s->Lam[1], s->v0,
                                   s->ex0, s->ZWp[0], s->ZWp[1], s->st);
@@ -1050,6 +1089,7 @@ msd_status msd_create(const msd_dims* d, const msd_options* o, int32_t device, v
   try {
     set_device(sys);
     msd::init_wick_attributes();
+    msd::init_ltl_attributes();
     msd::init_prop_attributes();
     msd::init_gemm_attributes();
     Arena& A = sys->base;
@@ -1323,6 +1363,14 @@ void set_trial_rows(msd_system* sys, const double* ci, const int32_t* occ_a,
   }
   sys->L_rows = T.get<double>((size_t)NG * sys->P_all * M);
   sys->Gp = T.get<double>((size_t)2 * NW * sys->P_all * M);
+  sys->lf_fits64 = msd::ltl_mfma_fits(sys->ds[0], sys->ds[1], M, false);
+  sys->lf_fits32 = sys->mixed && msd::ltl_mfma_fits(sys->ds[0], sys->ds[1], M, true);
+  sys->lf_P16 = msd::ltl_rows16(sys->ds[0], sys->ds[1]);
+  for (int sp = 0; sp < 2; ++sp) {
+    const size_t n = (size_t)NG * msd::ltl_stage_elems(sys->ds[0], sys->ds[1]);
+    sys->Slf[sp] = sys->lf_fits64 ? T.get<double>(n) : nullptr;
+    sys->Slf32[sp] = sys->lf_fits32 ? T.get<float>(n) : nullptr;
+  }
   if (sys->mixed) {
     sys->Gp32 = T.get<float>((size_t)2 * NW * sys->P_all * M);
     sys->Lrows32 = T.get<float>((size_t)NG * sys->P_all * M);
@@ -1805,7 +1853,7 @@ namespace {
 void set_tuning_impl(msd_system* s, const msd_tuning& t) {
   auto bad = [](const char* f) { fail(MSD_ERR_ARG, std::string("tuning field ") + f + " out of range"); };
   if (t.fb_splitk < 0 || t.fb_splitk > 16) bad("fb_splitk");
-  if (t.lambda_variant < 0 || t.lambda_variant > 4) bad("lambda_variant");
+  if (t.lambda_variant < 0 || t.lambda_variant > 5) bad("lambda_variant");
   if (t.lambda_chunk < 0) bad("lambda_chunk");
   if (t.second_gsplit < 0 || t.second_gsplit > 64) bad("second_gsplit");
   if (t.second_stage < 0 || t.second_stage > 32) bad("second_stage");
@@ -1904,7 +1952,7 @@ msd_status msd_autotune(msd_system* sys, double dt, int32_t reps, msd_tuning* ou
     }
     int nmax = 0;
     if (msd::lambda_rows_fits(sys->ds[0], sys->ds[1], &nmax) && nmax <= 16)
-      sweep(&msd_tuning::lambda_variant, {1, 2, 3, 4});
+      sweep(&msd_tuning::lambda_variant, {1, 2, 3, 4, 5});
     sweep(&msd_tuning::lambda_chunk, {4, 8, 16, 32});
     sweep(&msd_tuning::second_gather, {1, 2});
     sweep(&msd_tuning::second_copy, {1, 2});

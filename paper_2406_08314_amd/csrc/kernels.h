@@ -165,6 +165,25 @@ void launch_lambda_mfma32(const DevSpin& sa, const DevSpin& sb, int NW, int w0, 
                           int g_chunk, const cf* Ta, const cf* Tb, const cf* LTa, const cf* LTb,
                           cf* Lam_a, cf* Lam_b, cd* v0, cd* ex0, cd* ZWpart_a, cd* ZWpart_b,
                           const cd* Q64a, const cd* Q64b, hipStream_t st);
+// Fused Cholesky contraction + energy intermediates on the matrix cores (same
+// shapes as the LT-tile kernel, M <= 64): no LT in HBM.  S_a/S_b are the
+// restricted rows of L per spin, k-major and padded, [NG][64][P16] with rows
+// V_act then R (launch_gather_ltl); outputs as launch_lambda_mfma.
+bool ltl_mfma_fits(const DevSpin& sa, const DevSpin& sb, int M, bool fp32);
+size_t ltl_stage_elems(const DevSpin& sa, const DevSpin& sb);  // 64 * P16 per vector
+int ltl_rows16(const DevSpin& sa, const DevSpin& sb);
+void launch_gather_ltl(const double* L, int NG, int M, const DevSpin& D, int P16, double* S64,
+                       float* S32, hipStream_t st);
+void launch_ltl_mfma(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
+                     int g_chunk, int M, const double* Sa, const double* Sb, const cd* Ta,
+                     const cd* Tb, cd* Lam_a, cd* Lam_b, cd* v0, cd* ex0, cd* ZWpart_a,
+                     cd* ZWpart_b, hipStream_t st);
+// (mixed form: v0, ex0 from the FP64 Q tiles)
+void launch_ltl_mfma32(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
+                       int g_chunk, int M, const float* Sa, const float* Sb, const cf* Ta,
+                       const cf* Tb, cf* Lam_a, cf* Lam_b, cd* v0, cd* ex0, cd* ZWpart_a,
+                       cd* ZWpart_b, const cd* Q64a, const cd* Q64b, hipStream_t st);
+void init_ltl_attributes();
 // exact: both spins have N == nmax and an identity occupied window;
 // prefetch: next vector's LT row loaded ahead into registers (exact shapes).
 void launch_lambda_wave(const DevSpin& sa, const DevSpin& sb, int nmax, bool exact, bool prefetch,

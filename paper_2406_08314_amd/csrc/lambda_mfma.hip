@@ -276,4 +276,362 @@ void launch_lambda_mfma32(const DevSpin& sa, const DevSpin& sb, int NW, int w0, 
                      Q64b);
 }
 
+
+// ============================================================================
+// A2 + A6 fused on the matrix cores: the Cholesky contraction LT^g = L^g T and
+// the energy intermediates of Sec. III in one pass, without LT in HBM.
+//
+// Workgroup = 4 walkers x 2 spins (one wave each) and a chunk of Cholesky
+// vectors.  Per vector g both spins' restricted rows of L^g, stored k-major
+// as S[g][k][p] (p over V_act then R, zero padded to P16 rows and 64 k), are
+// staged in LDS by direct global-to-LDS loads, double-buffered one vector
+// ahead.  Each wave then forms
+//   [LTr LTi] = S^T [Tr Ti]             (P16 x 16 = (P16 x 64)(64 x 16))
+// with [Tr Ti] of its walker in registers for the whole chunk, extracts
+// Q = LT[R, :], exchanges tr Q with the other spin's wave of the same walker
+// through LDS, and continues as the LT-tile kernel above: Lam = T[V,:] Q -
+// LT[V,:] (C initialised from the LT accumulators), Xi = Lam Q, ZW, windows.
+// ============================================================================
+
+namespace {
+
+constexpr int LF_WB = 4;               // walkers per workgroup
+constexpr int LF_WAVES = 2 * LF_WB;    // one wave per (walker, spin)
+constexpr int LF_K = 64;               // contraction length (orbitals, zero padded)
+constexpr int LF_Q = LM_N * 16;        // Q scratch per wave (reals)
+constexpr int LF_LS = 2 * LM_N + 2;    // row stride of a Lambda tile (reals)
+constexpr int LF_WBUF = LF_Q + 16 * LF_LS;  // per-wave scratch (reals)
+
+// every outstanding memory operation of the wave done (including direct LDS
+// loads), then the workgroup barrier
+__device__ __forceinline__ void lf_bar_all() {
+  asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+// LDS operations of the wave done, then the workgroup barrier (loads to LDS
+// still in flight stay in flight)
+__device__ __forceinline__ void lf_bar_lds() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+// LDS writes of this wave visible to its own later reads
+__device__ __forceinline__ void lf_wave_lds() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+size_t lf_lds_bytes(int P16, size_t rsize) {
+  return (4 * (size_t)LF_K * P16 + (size_t)LF_WAVES * LF_WBUF + 2 * LF_WAVES) * rsize;
+}
+
+}  // namespace
+
+template <class R, int NT>
+__global__ __launch_bounds__(64 * LF_WAVES) void k_ltl_mfma(
+    DevSpin sa, DevSpin sb, int NW, int w0, int WT, int NG, int g_chunk, int n_chunks, int M,
+    int P16, const R* __restrict__ Sa, const R* __restrict__ Sb,
+    const typename Mfma<R>::cx_t* __restrict__ Ta, const typename Mfma<R>::cx_t* __restrict__ Tb,
+    typename Mfma<R>::cx_t* __restrict__ Lam_a, typename Mfma<R>::cx_t* __restrict__ Lam_b,
+    cd* __restrict__ v0, cd* __restrict__ ex0, cd* __restrict__ ZWa, cd* __restrict__ ZWb,
+    const cd* __restrict__ Q64a, const cd* __restrict__ Q64b) {
+  typedef typename Mfma<R>::cx_t C;
+  typedef typename Mfma<R>::acc_t acc_t;
+  extern __shared__ __align__(16) unsigned char lf_raw[];
+  R* lds = reinterpret_cast<R*>(lf_raw);
+  const int SE = LF_K * P16;  // reals of one spin's stage
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int qb = 4 * SE + wv * LF_WBUF, lsb = qb + LF_Q;
+  const int vbb = 4 * SE + LF_WAVES * LF_WBUF;  // [wave][re, im] traces
+  // workgroups of one chunk of vectors are consecutive on an XCD (shared L^g)
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int xcd = b & 7, per = nb >> 3, rem = nb & 7;
+  const int logical = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + (b >> 3);
+  const int n_wgrp = (WT + LF_WB - 1) / LF_WB;
+  const int chunk = logical / n_wgrp, wl = (logical % n_wgrp) * LF_WB + (wv & 3);
+  const int s2 = wv >> 2;
+  const bool active = wl < WT;
+  const int w = w0 + (active ? wl : 0);
+  const int nv = s2 ? sb.nv : sa.nv, X = nv * LM_N;
+  const int* __restrict__ vir = s2 ? sb.vir : sa.vir;
+  const C* __restrict__ T = s2 ? Tb : Ta;
+  C* __restrict__ Lam = s2 ? Lam_b : Lam_a;
+  cd* __restrict__ ZW = s2 ? ZWb : ZWa;
+  const int col = lane & 15, kq = lane >> 4;
+
+  // B operand of the contraction: [Tr Ti] of the walker, k = 4s + l / 16
+  R bt[LF_K / 4];
+#pragma unroll
+  for (int s = 0; s < LF_K / 4; ++s) {
+    const int k = 4 * s + kq;
+    R v = R(0);
+    if (k < M) {
+      const C t = T[((size_t)k * NW + w) * LM_N + (col & 7)];
+      v = col < 8 ? t.re : t.im;
+    }
+    bt[s] = v;
+  }
+  // A operand of Lam = T[V,:] Q: [Tr Ti] of the virtual rows
+  R av[4][4];
+#pragma unroll
+  for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int row = rt * 16 + col, k = 4 * s + kq;
+      R v = R(0);
+      if (row < nv) {
+        const C t = T[((size_t)vir[row] * NW + w) * LM_N + (k & 7)];
+        v = k < 8 ? t.re : t.im;
+      }
+      av[rt][s] = v;
+    }
+  acc_t zw[4];
+#pragma unroll
+  for (int rt = 0; rt < 4; ++rt) zw[rt] = acc_t{0, 0, 0, 0};
+
+  const int g0 = chunk * g_chunk, g1 = min(NG, g0 + g_chunk);
+  auto fetch = [&](int g, int buf) {
+    constexpr int per16 = 16 / sizeof(R);
+    const int n16 = SE / per16;
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp) {
+      const R* src = (sp ? Sb : Sa) + (size_t)g * SE;
+      const int dst = (buf * 2 + sp) * SE;
+      for (int c = wv; c * 64 < n16; c += LF_WAVES) {
+        const int e = c * 64 + lane;
+        if (e < n16) dma16(src + (size_t)e * per16, &lds[dst + c * 64 * per16]);
+      }
+    }
+  };
+  if (g0 < g1) fetch(g0, 0);
+  int it = 0;
+  for (int g = g0; g < g1; ++g, ++it) {
+    const int buf = it & 1;
+    lf_bar_all();  // this vector's stage has landed; the other buffer is free
+    if (g + 1 < g1) fetch(g + 1, buf ^ 1);
+    const int sb0 = (buf * 2 + s2) * SE;
+    acc_t acc[NT];
+#pragma unroll
+    for (int rt = 0; rt < NT; ++rt) acc[rt] = acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < LF_K / 4; ++s)
+#pragma unroll
+      for (int rt = 0; rt < NT; ++rt)
+        acc[rt] = Mfma<R>::run(lds[sb0 + (4 * s + kq) * P16 + rt * 16 + col], bt[s], acc[rt]);
+    // Q = rows nv .. nv + 7 of the tile, to the wave's scratch as [i][re 0..7 | im 0..7]
+#pragma unroll
+    for (int rt = 0; rt < NT; ++rt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = rt * 16 + Mfma<R>::row(lane, r) - nv;
+        if (row >= 0 && row < LM_N) lds[qb + row * 16 + col] = acc[rt][r];
+      }
+    lf_wave_lds();
+    R vr, vi;
+    if (Q64a) {  // traces from the FP64 Q tiles of both spins
+      const cd* q = (s2 ? Q64b : Q64a) + ((size_t)wl * NG + g) * LM_N * LM_N;
+      const cd* qo = (s2 ? Q64a : Q64b) + ((size_t)wl * NG + g) * LM_N * LM_N;
+      cd qe{0.0, 0.0}, qt{0.0, 0.0}, vo{0.0, 0.0};
+      if (active) {
+        qe = q[(lane >> 3) * LM_N + (lane & 7)];
+        qt = q[(lane & 7) * LM_N + (lane >> 3)];
+        if (lane < LM_N) vo = qo[lane * LM_N + lane];
+      }
+      cd x = qe * qt;
+      cd vd = (lane >> 3) == (lane & 7) ? qe : cd{0.0, 0.0};
+      vd.re = wsum(vd.re);
+      vd.im = wsum(vd.im);
+      x.re = wsum(x.re);
+      x.im = wsum(x.im);
+      vo.re = wsum(vo.re);
+      vo.im = wsum(vo.im);
+      if (lane == 0 && active) {
+        v0[((size_t)s2 * NW + w) * NG + g] = vd;
+        ex0[((size_t)s2 * NW + w) * NG + g] = x;
+      }
+      vr = R(vd.re + vo.re);
+      vi = R(vd.im + vo.im);
+      lf_bar_lds();  // keeps the barrier count of the exchange below
+    } else {
+      const int j = lane >> 3, c = lane & 7;
+      const R qjr = lds[qb + j * 16 + c], qji = lds[qb + j * 16 + 8 + c];
+      const R qcr = lds[qb + c * 16 + j], qci = lds[qb + c * 16 + 8 + j];
+      R xr = qjr * qcr - qji * qci, xi = qjr * qci + qji * qcr;
+      R dr = j == c ? qjr : R(0), di = j == c ? qji : R(0);
+      dr = wsum(dr);
+      di = wsum(di);
+      xr = wsum(xr);
+      xi = wsum(xi);
+      if (lane == 0) {
+        if (active) {
+          v0[((size_t)s2 * NW + w) * NG + g] = cd{(double)dr, (double)di};
+          ex0[((size_t)s2 * NW + w) * NG + g] = cd{(double)xr, (double)xi};
+        }
+        lds[vbb + 2 * wv] = dr;
+        lds[vbb + 2 * wv + 1] = di;
+      }
+      lf_bar_lds();  // the other spin's trace of this walker is in LDS
+      vr = dr + lds[vbb + 2 * (wv ^ 4)];
+      vi = di + lds[vbb + 2 * (wv ^ 4) + 1];
+    }
+    // block matrix [[Qr Qi]; [-Qi Qr]]: operand lane l, k 4s + l / 16, column l % 16
+    R bq[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int k = 4 * s + kq;
+      const R qr = lds[qb + (k & 7) * 16 + (col & 7)], qi = lds[qb + (k & 7) * 16 + 8 + (col & 7)];
+      bq[s] = k < 8 ? (col < 8 ? qr : qi) : (col < 8 ? -qi : qr);
+    }
+    C* lo = Lam + ((size_t)wl * NG + g) * X;
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) {
+      // Lam = T[V,:] Q - LT[V,:]; rows of the LT tile below nv are V_act
+      acc_t lam;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = rt * 16 + Mfma<R>::row(lane, r);
+        lam[r] = (rt < NT && a < nv) ? -acc[rt < NT ? rt : 0][r] : R(0);
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s) lam = Mfma<R>::run(av[rt][s], bq[s], lam);
+      // tile to LDS ([row][re 0..7 | im 0..7]) for the window store and as the
+      // A operand of Xi
+#pragma unroll
+      for (int r = 0; r < 4; ++r) lds[lsb + Mfma<R>::row(lane, r) * LF_LS + col] = lam[r];
+      lf_wave_lds();
+      if (active) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int e = h * 64 + lane, a = rt * 16 + (e >> 3), i = e & 7;
+          if (a < nv) lo[a * LM_N + i] = C{lds[lsb + (e >> 3) * LF_LS + i], lds[lsb + (e >> 3) * LF_LS + 8 + i]};
+        }
+      }
+      acc_t xi = acc_t{0, 0, 0, 0};
+#pragma unroll
+      for (int s = 0; s < 4; ++s) xi = Mfma<R>::run(lds[lsb + col * LF_LS + 4 * s + kq], bq[s], xi);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const R own = lam[r];
+        const R other = __shfl_xor(own, 8, 64);
+        const R lr = col < 8 ? own : other, li = col < 8 ? other : own;
+        const R sl = col < 8 ? vr * lr - vi * li : vr * li + vi * lr;
+        zw[rt][r] += xi[r] - sl;
+      }
+      lf_wave_lds();  // reads of this tile done before the next tile is written
+    }
+  }
+  if (!active) return;
+  // ZW partial of this chunk: [wl][chunk][a * 8 + i]
+#pragma unroll
+  for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const R own = zw[rt][r];
+      const R other = __shfl_xor(own, 8, 64);
+      const int a = rt * 16 + Mfma<R>::row(lane, r);
+      if (col < 8 && a < nv)
+        ZW[((size_t)wl * n_chunks + chunk) * X + a * LM_N + col] = cd{(double)own, (double)other};
+    }
+}
+
+// S[g][k][p] = L^g[row(p), k]: p < nv the active virtual orbitals, then the N
+// reference orbitals, zero beyond P and for k >= M.
+template <class R>
+__global__ void k_gather_lf(const double* __restrict__ L, int NG, int M, const int* __restrict__ rows,
+                            int N, int nv, int P16, R* __restrict__ S) {
+  const int64_t n = (int64_t)NG * LF_K * P16;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int p = (int)(e % P16);
+    const int k = (int)((e / P16) % LF_K);
+    const int64_t g = e / ((int64_t)P16 * LF_K);
+    double v = 0.0;
+    if (k < M && p < nv + N) {
+      const int row = p < nv ? rows[N + p] : rows[p - nv];
+      v = L[((size_t)g * M + row) * M + k];
+    }
+    S[e] = R(v);
+  }
+}
+
+int ltl_rows16(const DevSpin& sa, const DevSpin& sb) {
+  return (max(sa.nv, sb.nv) + LM_N + 15) / 16 * 16;
+}
+
+bool ltl_mfma_fits(const DevSpin& sa, const DevSpin& sb, int M, bool fp32) {
+  if (!lambda_mfma_fits(sa, sb) || M > LF_K) return false;
+  const int P16 = ltl_rows16(sa, sb);
+  if (P16 > 16 * (fp32 ? 5 : 4)) return false;
+  return lf_lds_bytes(P16, fp32 ? 4 : 8) <= 160 * 1024;
+}
+
+size_t ltl_stage_elems(const DevSpin& sa, const DevSpin& sb) {
+  return (size_t)LF_K * ltl_rows16(sa, sb);
+}
+
+void launch_gather_ltl(const double* L, int NG, int M, const DevSpin& D, int P16, double* S64,
+                       float* S32, hipStream_t st) {
+  const int64_t n = (int64_t)NG * LF_K * P16;
+  if (n == 0) return;
+  const int blocks = (int)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
+  if (S64)
+    hipLaunchKernelGGL(k_gather_lf<double>, dim3(blocks), dim3(256), 0, st, L, NG, M, D.rows, D.N,
+                       D.nv, P16, S64);
+  if (S32)
+    hipLaunchKernelGGL(k_gather_lf<float>, dim3(blocks), dim3(256), 0, st, L, NG, M, D.rows, D.N,
+                       D.nv, P16, S32);
+}
+
+namespace {
+template <class R>
+void launch_ltl_t(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
+                  int g_chunk, int M, const R* Sa, const R* Sb, const typename Mfma<R>::cx_t* Ta,
+                  const typename Mfma<R>::cx_t* Tb, typename Mfma<R>::cx_t* Lam_a,
+                  typename Mfma<R>::cx_t* Lam_b, cd* v0, cd* ex0, cd* ZWa, cd* ZWb,
+                  const cd* Q64a, const cd* Q64b, hipStream_t st) {
+  const int P16 = ltl_rows16(sa, sb), NT = P16 / 16;
+  const int n_chunks = (NG + g_chunk - 1) / g_chunk;
+  const int n_wgrp = (WT + LF_WB - 1) / LF_WB;
+  const dim3 grid(n_wgrp * n_chunks), block(64 * LF_WAVES);
+  const size_t lds = lf_lds_bytes(P16, sizeof(R));
+#define LTL_CASE(nt)                                                                          \
+  case nt:                                                                                    \
+    hipLaunchKernelGGL((k_ltl_mfma<R, nt>), grid, block, lds, st, sa, sb, NW, w0, WT, NG,     \
+                       g_chunk, n_chunks, M, P16, Sa, Sb, Ta, Tb, Lam_a, Lam_b, v0, ex0, ZWa, \
+                       ZWb, Q64a, Q64b);                                                      \
+    break;
+  switch (NT) {
+    LTL_CASE(1)
+    LTL_CASE(2)
+    LTL_CASE(3)
+    LTL_CASE(4)
+    LTL_CASE(5)
+    default:
+      break;
+  }
+#undef LTL_CASE
+}
+}  // namespace
+
+void launch_ltl_mfma(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
+                     int g_chunk, int M, const double* Sa, const double* Sb, const cd* Ta,
+                     const cd* Tb, cd* Lam_a, cd* Lam_b, cd* v0, cd* ex0, cd* ZWpart_a,
+                     cd* ZWpart_b, hipStream_t st) {
+  launch_ltl_t<double>(sa, sb, NW, w0, WT, NG, g_chunk, M, Sa, Sb, Ta, Tb, Lam_a, Lam_b, v0, ex0,
+                       ZWpart_a, ZWpart_b, nullptr, nullptr, st);
+}
+
+void launch_ltl_mfma32(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
+                       int g_chunk, int M, const float* Sa, const float* Sb, const cf* Ta,
+                       const cf* Tb, cf* Lam_a, cf* Lam_b, cd* v0, cd* ex0, cd* ZWpart_a,
+                       cd* ZWpart_b, const cd* Q64a, const cd* Q64b, hipStream_t st) {
+  launch_ltl_t<float>(sa, sb, NW, w0, WT, NG, g_chunk, M, Sa, Sb, Ta, Tb, Lam_a, Lam_b, v0, ex0,
+                      ZWpart_a, ZWpart_b, Q64a, Q64b, st);
+}
+
+void init_ltl_attributes() {
+  const int lim = 160 * 1024;
+  for (const void* f :
+       {(const void*)k_ltl_mfma<double, 1>, (const void*)k_ltl_mfma<double, 2>,
+        (const void*)k_ltl_mfma<double, 3>, (const void*)k_ltl_mfma<double, 4>,
+        (const void*)k_ltl_mfma<double, 5>, (const void*)k_ltl_mfma<float, 1>,
+        (const void*)k_ltl_mfma<float, 2>, (const void*)k_ltl_mfma<float, 3>,
+        (const void*)k_ltl_mfma<float, 4>, (const void*)k_ltl_mfma<float, 5>})
+    hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+}
+
 }  // namespace msd

@@ -541,6 +541,9 @@ def test_uneven_batch_graph_matches_separate_systems():
     dict(lambda_variant=3, lambda_chunk=11, second_gsplit=2, second_stage=2, fb_splitk=4),
     dict(lambda_variant=4, lambda_chunk=13, second_gsplit=2, second_stage=2, fb_splitk=4),
     dict(lambda_variant=4, lambda_chunk=1, second_gsplit=1, second_stage=1, fb_splitk=1),
+    dict(lambda_variant=5, lambda_chunk=13, second_gsplit=2, second_stage=2, fb_splitk=4),
+    dict(lambda_variant=5, lambda_chunk=1, walker_tile=4),
+    dict(lambda_variant=5),
     dict(second_waves=16, second_stage=5, second_gsplit=3, second_copy=2),
     dict(second_waves=16, second_stage=3, second_gsplit=1, second_copy=1, second_gather=2),
     dict(walker_tile=4),
@@ -564,7 +567,7 @@ def test_autotune_picks_valid_shapes_and_keeps_results():
     for precision in ("fp64", "mixed"):
         s = system_for(wl, precision=precision)
         t = s.autotune(wl.dt, reps=2)
-        assert 1 <= t["fb_splitk"] <= 16 and t["lambda_variant"] in (1, 2, 3, 4)
+        assert 1 <= t["fb_splitk"] <= 16 and t["lambda_variant"] in (1, 2, 3, 4, 5)
         assert t["lambda_chunk"] >= 1 and t["second_gsplit"] >= 1 and t["second_stage"] >= 1
         out = s.measure(wl.dt)
         np.testing.assert_array_equal(out["log_ovlp"], ref["log_ovlp"])
@@ -572,7 +575,7 @@ def test_autotune_picks_valid_shapes_and_keeps_results():
         assert np.max(np.abs(out["e_loc"] - ref["e_loc"])) <= tol
 
 
-@pytest.mark.parametrize("variant", [2, 3, 4])
+@pytest.mark.parametrize("variant", [2, 3, 4, 5])
 def test_mixed_lambda_variants_against_fp64(variant):
     """Each single-precision energy-intermediate kernel keeps every walker's
     local energy within 0.1 mHa of the FP64 path (Medium, 32 walkers)."""
