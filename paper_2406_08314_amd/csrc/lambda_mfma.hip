@@ -285,12 +285,16 @@ void launch_lambda_mfma32(const DevSpin& sa, const DevSpin& sb, int NW, int w0, 
 // vectors.  Per vector g both spins' restricted rows of L^g, stored k-major
 // as S[g][k][p] (p over V_act then R, zero padded to P16 rows and 64 k), are
 // staged in LDS by direct global-to-LDS loads, double-buffered one vector
-// ahead.  Each wave then forms
-//   [LTr LTi] = S^T [Tr Ti]             (P16 x 16 = (P16 x 64)(64 x 16))
-// with [Tr Ti] of its walker in registers for the whole chunk, extracts
-// Q = LT[R, :], exchanges tr Q with the other spin's wave of the same walker
-// through LDS, and continues as the LT-tile kernel above: Lam = T[V,:] Q -
-// LT[V,:] (C initialised from the LT accumulators), Xi = Lam Q, ZW, windows.
+// ahead.  Each wave forms transposed products, so that the result registers
+// of one MFMA are the B operand of the next (no transposes through LDS):
+//   LT^T   = [Tr Ti]^T S                     (16 x P16; [Tr Ti] in registers)
+//   Lam^T  = Bq^T [Tr Ti]_V^T - LT_V^T        (16 x n_v, 16 virtuals per tile)
+//   ZW^T  += (Bq - v Bi)^T Lam^T              (v = v0_alpha + v0_beta)
+// Bq = [[Qr Qi]; [-Qi Qr]] is the real form of Q = LT[R, :] (row vectors
+// times Q), Bi that of the identity; the 16 rows are the real and imaginary
+// parts of the N = 8 columns.  The last line is ZW += Xi - v Lam with
+// Xi = Lam Q.  tr Q is exchanged with the other spin's wave of the walker
+// through LDS.
 // ============================================================================
 
 namespace {
@@ -299,8 +303,6 @@ constexpr int LF_WB = 4;               // walkers per workgroup
 constexpr int LF_WAVES = 2 * LF_WB;    // one wave per (walker, spin)
 constexpr int LF_K = 64;               // contraction length (orbitals, zero padded)
 constexpr int LF_Q = LM_N * 16;        // Q scratch per wave (reals)
-constexpr int LF_LS = 2 * LM_N + 2;    // row stride of a Lambda tile (reals)
-constexpr int LF_WBUF = LF_Q + 16 * LF_LS;  // per-wave scratch (reals)
 
 // every outstanding memory operation of the wave done (including direct LDS
 // loads), then the workgroup barrier
@@ -316,7 +318,41 @@ __device__ __forceinline__ void lf_bar_lds() {
 __device__ __forceinline__ void lf_wave_lds() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
 size_t lf_lds_bytes(int P16, size_t rsize) {
-  return (4 * (size_t)LF_K * P16 + (size_t)LF_WAVES * LF_WBUF + 2 * LF_WAVES) * rsize;
+  return (4 * (size_t)LF_K * P16 + (size_t)LF_WAVES * LF_Q + 2 * LF_WAVES) * rsize;
+}
+
+// Row order of the 16 x 16 operands: hardware row i holds logical row sig(i)
+// (0..7 real parts, 8..15 imaginary parts of columns 0..7).  In FP64 the
+// identity: register r of lane group q holds rows q and q + 8 for r = 0, 2
+// (column q) and r = 1, 3 (column q + 4).  In FP32, where register r of lane
+// group q holds hardware row 4q + r, rows 4q .. 4q+3 are re/im of column 2q,
+// then of column 2q + 1.
+template <class R>
+__device__ __forceinline__ int lf_sig(int i) {
+  if constexpr (sizeof(R) == 8) return i;
+  else return ((i & 1) << 3) | (i >> 1);
+}
+// complex column held by a lane in registers (re, im) = (r0, r1) and (r2, r3)
+// of the pair h = 0, 1
+template <class R>
+__device__ __forceinline__ void lf_pair(int q, int h, int* rre, int* rim, int* n) {
+  if constexpr (sizeof(R) == 8) {
+    *rre = h;
+    *rim = h + 2;
+    *n = q + 4 * h;
+  } else {
+    *rre = 2 * h;
+    *rim = 2 * h + 1;
+    *n = 2 * q + h;
+  }
+}
+
+template <class R>
+__device__ __forceinline__ R lf_sum8(R v) {  // over lanes of a group of 8
+  v += __shfl_xor(v, 1, 64);
+  v += __shfl_xor(v, 2, 64);
+  v += __shfl_xor(v, 4, 64);
+  return v;
 }
 
 }  // namespace
@@ -329,14 +365,15 @@ __global__ __launch_bounds__(64 * LF_WAVES) void k_ltl_mfma(
     typename Mfma<R>::cx_t* __restrict__ Lam_a, typename Mfma<R>::cx_t* __restrict__ Lam_b,
     cd* __restrict__ v0, cd* __restrict__ ex0, cd* __restrict__ ZWa, cd* __restrict__ ZWb,
     const cd* __restrict__ Q64a, const cd* __restrict__ Q64b) {
-  typedef typename Mfma<R>::cx_t C;
-  typedef typename Mfma<R>::acc_t acc_t;
+  typedef Mfma<R> MF;
+  typedef typename MF::cx_t C;
+  typedef typename MF::acc_t acc_t;
   extern __shared__ __align__(16) unsigned char lf_raw[];
   R* lds = reinterpret_cast<R*>(lf_raw);
   const int SE = LF_K * P16;  // reals of one spin's stage
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int qb = 4 * SE + wv * LF_WBUF, lsb = qb + LF_Q;
-  const int vbb = 4 * SE + LF_WAVES * LF_WBUF;  // [wave][re, im] traces
+  const int qb = 4 * SE + wv * LF_Q;           // this wave's Q as [i][re 0..7 | im 0..7]
+  const int vbb = 4 * SE + LF_WAVES * LF_Q;    // [wave][re, im] traces
   // workgroups of one chunk of vectors are consecutive on an XCD (shared L^g)
   const int nb = gridDim.x, b = blockIdx.x;
   const int xcd = b & 7, per = nb >> 3, rem = nb & 7;
@@ -351,30 +388,31 @@ __global__ __launch_bounds__(64 * LF_WAVES) void k_ltl_mfma(
   const C* __restrict__ T = s2 ? Tb : Ta;
   C* __restrict__ Lam = s2 ? Lam_b : Lam_a;
   cd* __restrict__ ZW = s2 ? ZWb : ZWa;
-  const int col = lane & 15, kq = lane >> 4;
+  const int col = lane & 15, q = lane >> 4;
+  const int jc = lf_sig<R>(col);  // logical row of this lane's A-operand row
 
-  // B operand of the contraction: [Tr Ti] of the walker, k = 4s + l / 16
+  // A of LT^T: [Tr Ti]^T, row jc, k = orbital 4s + q
   R bt[LF_K / 4];
 #pragma unroll
   for (int s = 0; s < LF_K / 4; ++s) {
-    const int k = 4 * s + kq;
+    const int k = 4 * s + q;
     R v = R(0);
     if (k < M) {
-      const C t = T[((size_t)k * NW + w) * LM_N + (col & 7)];
-      v = col < 8 ? t.re : t.im;
+      const C t = T[((size_t)k * NW + w) * LM_N + (jc & 7)];
+      v = jc < 8 ? t.re : t.im;
     }
     bt[s] = v;
   }
-  // A operand of Lam = T[V,:] Q: [Tr Ti] of the virtual rows
+  // B of Lam^T: [Tr Ti]_V^T, k = 4s + q, column = virtual 16 rt + col
   R av[4][4];
 #pragma unroll
   for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      const int row = rt * 16 + col, k = 4 * s + kq;
+      const int a = rt * 16 + col, k = 4 * s + q;
       R v = R(0);
-      if (row < nv) {
-        const C t = T[((size_t)vir[row] * NW + w) * LM_N + (k & 7)];
+      if (a < nv) {
+        const C t = T[((size_t)vir[a] * NW + w) * LM_N + (k & 7)];
         v = k < 8 ? t.re : t.im;
       }
       av[rt][s] = v;
@@ -406,56 +444,64 @@ __global__ __launch_bounds__(64 * LF_WAVES) void k_ltl_mfma(
     const int sb0 = (buf * 2 + s2) * SE;
     acc_t acc[NT];
 #pragma unroll
-    for (int rt = 0; rt < NT; ++rt) acc[rt] = acc_t{0, 0, 0, 0};
+    for (int ct = 0; ct < NT; ++ct) acc[ct] = acc_t{0, 0, 0, 0};
 #pragma unroll
     for (int s = 0; s < LF_K / 4; ++s)
 #pragma unroll
-      for (int rt = 0; rt < NT; ++rt)
-        acc[rt] = Mfma<R>::run(lds[sb0 + (4 * s + kq) * P16 + rt * 16 + col], bt[s], acc[rt]);
-    // Q = rows nv .. nv + 7 of the tile, to the wave's scratch as [i][re 0..7 | im 0..7]
+      for (int ct = 0; ct < NT; ++ct)
+        acc[ct] = MF::run(bt[s], lds[sb0 + (4 * s + q) * P16 + ct * 16 + col], acc[ct]);
+    // Q = columns nv .. nv + 7 of LT^T
 #pragma unroll
-    for (int rt = 0; rt < NT; ++rt)
+    for (int ct = 0; ct < NT; ++ct)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = rt * 16 + Mfma<R>::row(lane, r) - nv;
-        if (row >= 0 && row < LM_N) lds[qb + row * 16 + col] = acc[rt][r];
+        const int i = ct * 16 + col - nv;
+        if (i >= 0 && i < LM_N) lds[qb + i * 16 + lf_sig<R>(MF::row(lane, r))] = acc[ct][r];
       }
     lf_wave_lds();
+    // traces on lanes 0..7 (row i = lane): tr Q and tr QQ = sum_ic Q_ic Q_ci
     R vr, vi;
-    if (Q64a) {  // traces from the FP64 Q tiles of both spins
-      const cd* q = (s2 ? Q64b : Q64a) + ((size_t)wl * NG + g) * LM_N * LM_N;
-      const cd* qo = (s2 ? Q64a : Q64b) + ((size_t)wl * NG + g) * LM_N * LM_N;
-      cd qe{0.0, 0.0}, qt{0.0, 0.0}, vo{0.0, 0.0};
-      if (active) {
-        qe = q[(lane >> 3) * LM_N + (lane & 7)];
-        qt = q[(lane & 7) * LM_N + (lane >> 3)];
-        if (lane < LM_N) vo = qo[lane * LM_N + lane];
+    if (Q64a) {  // from the FP64 Q tiles of both spins
+      cd vd{0.0, 0.0}, x{0.0, 0.0}, vo{0.0, 0.0};
+      if (active && lane < LM_N) {
+        const cd* qp = (s2 ? Q64b : Q64a) + ((size_t)wl * NG + g) * LM_N * LM_N;
+        const cd* qo = (s2 ? Q64a : Q64b) + ((size_t)wl * NG + g) * LM_N * LM_N;
+        vd = qp[lane * LM_N + lane];
+        vo = qo[lane * LM_N + lane];
+#pragma unroll
+        for (int c = 0; c < LM_N; ++c) x = x + qp[lane * LM_N + c] * qp[c * LM_N + lane];
       }
-      cd x = qe * qt;
-      cd vd = (lane >> 3) == (lane & 7) ? qe : cd{0.0, 0.0};
-      vd.re = wsum(vd.re);
-      vd.im = wsum(vd.im);
-      x.re = wsum(x.re);
-      x.im = wsum(x.im);
-      vo.re = wsum(vo.re);
-      vo.im = wsum(vo.im);
+      vd.re = lf_sum8(vd.re);
+      vd.im = lf_sum8(vd.im);
+      x.re = lf_sum8(x.re);
+      x.im = lf_sum8(x.im);
+      vo.re = lf_sum8(vo.re);
+      vo.im = lf_sum8(vo.im);
       if (lane == 0 && active) {
         v0[((size_t)s2 * NW + w) * NG + g] = vd;
         ex0[((size_t)s2 * NW + w) * NG + g] = x;
       }
-      vr = R(vd.re + vo.re);
-      vi = R(vd.im + vo.im);
+      vr = R(__shfl(vd.re + vo.re, 0, 64));
+      vi = R(__shfl(vd.im + vo.im, 0, 64));
       lf_bar_lds();  // keeps the barrier count of the exchange below
     } else {
-      const int j = lane >> 3, c = lane & 7;
-      const R qjr = lds[qb + j * 16 + c], qji = lds[qb + j * 16 + 8 + c];
-      const R qcr = lds[qb + c * 16 + j], qci = lds[qb + c * 16 + 8 + j];
-      R xr = qjr * qcr - qji * qci, xi = qjr * qci + qji * qcr;
-      R dr = j == c ? qjr : R(0), di = j == c ? qji : R(0);
-      dr = wsum(dr);
-      di = wsum(di);
-      xr = wsum(xr);
-      xi = wsum(xi);
+      R dr = R(0), di = R(0), xr = R(0), xi = R(0);
+      if (lane < LM_N) {
+        const int i = lane;
+        dr = lds[qb + i * 16 + i];
+        di = lds[qb + i * 16 + 8 + i];
+#pragma unroll
+        for (int c = 0; c < LM_N; ++c) {
+          const R ar = lds[qb + i * 16 + c], ai = lds[qb + i * 16 + 8 + c];
+          const R br = lds[qb + c * 16 + i], bi = lds[qb + c * 16 + 8 + i];
+          xr += ar * br - ai * bi;
+          xi += ar * bi + ai * br;
+        }
+      }
+      dr = lf_sum8(dr);
+      di = lf_sum8(di);
+      xr = lf_sum8(xr);
+      xi = lf_sum8(xi);
       if (lane == 0) {
         if (active) {
           v0[((size_t)s2 * NW + w) * NG + g] = cd{(double)dr, (double)di};
@@ -465,67 +511,75 @@ __global__ __launch_bounds__(64 * LF_WAVES) void k_ltl_mfma(
         lds[vbb + 2 * wv + 1] = di;
       }
       lf_bar_lds();  // the other spin's trace of this walker is in LDS
-      vr = dr + lds[vbb + 2 * (wv ^ 4)];
-      vi = di + lds[vbb + 2 * (wv ^ 4) + 1];
+      vr = lds[vbb + 2 * wv] + lds[vbb + 2 * (wv ^ 4)];
+      vi = lds[vbb + 2 * wv + 1] + lds[vbb + 2 * (wv ^ 4) + 1];
     }
-    // block matrix [[Qr Qi]; [-Qi Qr]]: operand lane l, k 4s + l / 16, column l % 16
-    R bq[4];
+    // A operands: Bq^T (row jc, k = 4s + q) and (Bq - v Bi)^T (row jc, k = the
+    // logical row that register s of lane group q holds in Lam^T)
+    R bqa[4], bqz[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      const int k = 4 * s + kq;
-      const R qr = lds[qb + (k & 7) * 16 + (col & 7)], qi = lds[qb + (k & 7) * 16 + 8 + (col & 7)];
-      bq[s] = k < 8 ? (col < 8 ? qr : qi) : (col < 8 ? -qi : qr);
-    }
-    C* lo = Lam + ((size_t)wl * NG + g) * X;
-#pragma unroll
-    for (int rt = 0; rt < 4; ++rt) {
-      // Lam = T[V,:] Q - LT[V,:]; rows of the LT tile below nv are V_act
-      acc_t lam;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int a = rt * 16 + Mfma<R>::row(lane, r);
-        lam[r] = (rt < NT && a < nv) ? -acc[rt < NT ? rt : 0][r] : R(0);
+      {
+        const int k = 4 * s + q;
+        const R qr = lds[qb + (k & 7) * 16 + (jc & 7)], qi = lds[qb + (k & 7) * 16 + 8 + (jc & 7)];
+        bqa[s] = k < 8 ? (jc < 8 ? qr : qi) : (jc < 8 ? -qi : qr);
       }
+      {
+        const int k = lf_sig<R>(MF::row(lane, s));
+        const R qr = lds[qb + (k & 7) * 16 + (jc & 7)], qi = lds[qb + (k & 7) * 16 + 8 + (jc & 7)];
+        R z = k < 8 ? (jc < 8 ? qr : qi) : (jc < 8 ? -qi : qr);
+        if ((k & 7) == (jc & 7)) z -= ((k < 8) == (jc < 8)) ? vr : (k < 8 ? vi : -vi);
+        bqz[s] = z;
+      }
+    }
+    // Lam^T tiles (C = -LT_V^T; columns at or beyond nv are zero)
+    acc_t lam[4];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) lam = Mfma<R>::run(av[rt][s], bq[s], lam);
-      // tile to LDS ([row][re 0..7 | im 0..7]) for the window store and as the
-      // A operand of Xi
+    for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) lds[lsb + Mfma<R>::row(lane, r) * LF_LS + col] = lam[r];
-      lf_wave_lds();
-      if (active) {
+      for (int r = 0; r < 4; ++r)
+        lam[rt][r] = (rt < NT && rt * 16 + col < nv) ? -acc[rt < NT ? rt : 0][r] : R(0);
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int e = h * 64 + lane, a = rt * 16 + (e >> 3), i = e & 7;
-          if (a < nv) lo[a * LM_N + i] = C{lds[lsb + (e >> 3) * LF_LS + i], lds[lsb + (e >> 3) * LF_LS + 8 + i]};
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt) lam[rt] = MF::run(bqa[s], av[rt][s], lam[rt]);
+    // window store Lam[w][g][a * 8 + n]
+    if (active) {
+      C* lo = Lam + ((size_t)wl * NG + g) * X;
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt) {
+        const int a = rt * 16 + col;
+        if (a < nv) {
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            int rre, rim, n;
+            lf_pair<R>(q, h, &rre, &rim, &n);
+            lo[a * LM_N + n] = C{lam[rt][rre], lam[rt][rim]};
+          }
         }
       }
-      acc_t xi = acc_t{0, 0, 0, 0};
-#pragma unroll
-      for (int s = 0; s < 4; ++s) xi = Mfma<R>::run(lds[lsb + col * LF_LS + 4 * s + kq], bq[s], xi);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const R own = lam[r];
-        const R other = __shfl_xor(own, 8, 64);
-        const R lr = col < 8 ? own : other, li = col < 8 ? other : own;
-        const R sl = col < 8 ? vr * lr - vi * li : vr * li + vi * lr;
-        zw[rt][r] += xi[r] - sl;
-      }
-      lf_wave_lds();  // reads of this tile done before the next tile is written
     }
+    // ZW^T += (Bq - v Bi)^T Lam^T: register s of Lam^T is the B operand of step s
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt) zw[rt] = MF::run(bqz[s], lam[rt][s], zw[rt]);
   }
   if (!active) return;
-  // ZW partial of this chunk: [wl][chunk][a * 8 + i]
+  // ZW partial of this chunk: [wl][chunk][a * 8 + n]
 #pragma unroll
-  for (int rt = 0; rt < 4; ++rt)
+  for (int rt = 0; rt < 4; ++rt) {
+    const int a = rt * 16 + col;
+    if (a < nv) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const R own = zw[rt][r];
-      const R other = __shfl_xor(own, 8, 64);
-      const int a = rt * 16 + Mfma<R>::row(lane, r);
-      if (col < 8 && a < nv)
-        ZW[((size_t)wl * n_chunks + chunk) * X + a * LM_N + col] = cd{(double)own, (double)other};
+      for (int h = 0; h < 2; ++h) {
+        int rre, rim, n;
+        lf_pair<R>(q, h, &rre, &rim, &n);
+        ZW[((size_t)wl * n_chunks + chunk) * X + a * LM_N + n] =
+            cd{(double)zw[rt][rre], (double)zw[rt][rim]};
+      }
     }
+  }
 }
 
 // S[g][k][p] = L^g[row(p), k]: p < nv the active virtual orbitals, then the N
