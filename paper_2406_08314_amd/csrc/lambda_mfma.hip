@@ -304,18 +304,34 @@ constexpr int LF_WAVES = 2 * LF_WB;    // one wave per (walker, spin)
 constexpr int LF_K = 64;               // contraction length (orbitals, zero padded)
 constexpr int LF_Q = LM_N * 16;        // Q scratch per wave (reals)
 
+// The waits are s_waitcnt instructions the compiler sees (so its own wait
+// placement stays exact); the signal fences keep memory accesses from moving
+// across them.  Encoding of s_waitcnt: vmcnt bits 3:0 and 15:14, expcnt 6:4,
+// lgkmcnt 11:8.
+constexpr int LF_WAIT_ALL = 0;       // vmcnt(0) expcnt(0) lgkmcnt(0)
+constexpr int LF_WAIT_LGKM = 0xC07F; // lgkmcnt(0) only
 // every outstanding memory operation of the wave done (including direct LDS
 // loads), then the workgroup barrier
 __device__ __forceinline__ void lf_bar_all() {
-  asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(LF_WAIT_ALL);
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 // LDS operations of the wave done, then the workgroup barrier (loads to LDS
 // still in flight stay in flight)
 __device__ __forceinline__ void lf_bar_lds() {
-  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(LF_WAIT_LGKM);
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 // LDS writes of this wave visible to its own later reads
-__device__ __forceinline__ void lf_wave_lds() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+__device__ __forceinline__ void lf_wave_lds() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(LF_WAIT_LGKM);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
 
 size_t lf_lds_bytes(int P16, size_t rsize) {
   return (4 * (size_t)LF_K * P16 + (size_t)LF_WAVES * LF_Q + 2 * LF_WAVES) * rsize;
@@ -445,11 +461,28 @@ __global__ __launch_bounds__(64 * LF_WAVES) void k_ltl_mfma(
     acc_t acc[NT];
 #pragma unroll
     for (int ct = 0; ct < NT; ++ct) acc[ct] = acc_t{0, 0, 0, 0};
+    // B operands of step s + 1 are read while the MFMAs of step s run
+    R bcur[NT], bnxt[NT];
 #pragma unroll
-    for (int s = 0; s < LF_K / 4; ++s)
+    for (int ct = 0; ct < NT; ++ct) bcur[ct] = lds[sb0 + q * P16 + ct * 16 + col];
 #pragma unroll
-      for (int ct = 0; ct < NT; ++ct)
-        acc[ct] = MF::run(bt[s], lds[sb0 + (4 * s + q) * P16 + ct * 16 + col], acc[ct]);
+    for (int s = 0; s < LF_K / 4; ++s) {
+      if (s + 1 < LF_K / 4) {
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct)
+          bnxt[ct] = lds[sb0 + (4 * (s + 1) + q) * P16 + ct * 16 + col];
+      }
+#pragma unroll
+      for (int ct = 0; ct < NT; ++ct) acc[ct] = MF::run(bt[s], bcur[ct], acc[ct]);
+      if (s + 1 < LF_K / 4) {
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct) bcur[ct] = bnxt[ct];
+      }
+      // this step's MFMAs, then the next step's LDS reads (their wait comes
+      // after the MFMAs queued on the matrix pipe)
+      __builtin_amdgcn_sched_group_barrier(0x008, NT, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, (NT + 1) / 2, 0);
+    }
     // Q = columns nv .. nv + 7 of LT^T
 #pragma unroll
     for (int ct = 0; ct < NT; ++ct)
