@@ -156,6 +156,7 @@ struct msd_system {
   bool lf_fits64 = false, lf_fits32 = false;
   double* Slf[2] = {nullptr, nullptr};
   float* Slf32[2] = {nullptr, nullptr};
+  double* Slr[2] = {nullptr, nullptr};  // reference rows only, [NG][64][8] (traces)
 
   // energy work (lazily sized)
   int WT = 0, gl_chunk = 16, n_lchunks = 0;
@@ -335,9 +336,13 @@ void build_derived(msd_system* s) {
   }
   msd::launch_gather_rows(s->L, s->NG, s->M, s->rows_all_dev, s->P_all, s->L_rows, s->st);
   for (int sp = 0; sp < 2; ++sp)
-    if (s->lf_fits64 || s->lf_fits32)
+    if (s->lf_fits64 || s->lf_fits32) {
       msd::launch_gather_ltl(s->L, s->NG, s->M, s->ds[sp], s->lf_P16, s->Slf[sp], s->Slf32[sp],
                              s->st);
+      msd::DevSpin R = s->ds[sp];  // reference rows only
+      R.nv = 0;
+      msd::launch_gather_ltl(s->L, s->NG, s->M, R, 8, s->Slr[sp], nullptr, s->st);
+    }
   if (s->mixed) {
     for (int sp = 0; sp < 2; ++sp) {
       msd::launch_f64_to_f32(s->L_lt[sp], s->Llt32[sp], (int64_t)s->NG * s->ds[sp].P * s->M, s->st);
@@ -482,7 +487,7 @@ void alloc_energy(msd_system* s) {
     if (s->energy_mixed) {
       if (s->lambda_variant != 5) s->LT32[sp] = E.get<cf>((size_t)NG * D.P * wt * D.N);
       s->Lam32[sp] = E.get<cf>((size_t)wt * NG * D.nv * D.no);
-      s->Q64[sp] = E.get<cd>((size_t)NG * D.N * wt * D.N);
+      if (s->lambda_variant != 5) s->Q64[sp] = E.get<cd>((size_t)NG * D.N * wt * D.N);
     } else {
       if (!(s->o.energy_algo == 3 && msd::chol_contract_fits(s->ds[0], s->ds[1], &wbf)) &&
           s->lambda_variant != 5)
@@ -673,6 +678,7 @@ void run_energy_mixed(msd_system* s) {
         g.c_block = 2 * D.N;  // LT tile of (walker, vector) contiguous: [wl][g][p][n]
         msd::launch_gemm32(g, s->st);
         }
+        if (s->lambda_variant == 5) return;  // traces from launch_qtr
         // FP64 Q = L[R, :] T for the mean-field traces
         msd::GemmArgs q;
         q.M = s->NG * D.N;
@@ -692,11 +698,13 @@ void run_energy_mixed(msd_system* s) {
     s->timed(ST_LAMBDA, [&] {
       const cf* Ta = reinterpret_cast<const cf*>(s->T32[0]);
       const cf* Tb = reinterpret_cast<const cf*>(s->T32[1]);
-      if (s->lambda_variant == 5)
+      if (s->lambda_variant == 5) {
+        msd::launch_qtr(s->NW, w0, wt, s->NG, s->M, s->Slr[0], s->Slr[1], s->sw[0].T, s->sw[1].T,
+                        s->v0, s->ex0, s->st);
         msd::launch_ltl_mfma32(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, s->M, s->Slf32[0],
-                               s->Slf32[1], Ta, Tb, s->Lam32[0], s->Lam32[1], s->v0, s->ex0,
-                               s->ZWp[0], s->ZWp[1], s->Q64[0], s->Q64[1], s->st);
-      else if (s->lambda_variant == 4)
+                               s->Slf32[1], Ta, Tb, s->Lam32[0], s->Lam32[1], s->v0, s->ZWp[0],
+                               s->ZWp[1], s->st);
+      } else if (s->lambda_variant == 4)
         msd::launch_lambda_mfma32(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, Ta, Tb, s->LT32[0],
                                   s->LT32[1], s->Lam32[0], s->Lam32[1], s->v0, s->ex0,
                                   s->ZWp[0], s->ZWp[1], s->Q64[0], s->Q64[1], s->st);
@@ -786,11 +794,13 @@ void run_energy(msd_system* s) {
       }
       int nmax = 0;
       s->timed(ST_LAMBDA, [&] {
-        if (s->lambda_variant == 5)
+        if (s->lambda_variant == 5) {
+          msd::launch_qtr(s->NW, w0, wt, s->NG, s->M, s->Slr[0], s->Slr[1], s->sw[0].T,
+                          s->sw[1].T, s->v0, s->ex0, s->st);
           msd::launch_ltl_mfma(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, s->M, s->Slf[0],
                                s->Slf[1], s->sw[0].T, s->sw[1].T, s->Lam[0], s->Lam[1], s->v0,
-                               s->ex0, s->ZWp[0], s->ZWp[1], s->st);
-        else if (s->lambda_variant == 4)
+                               s->ZWp[0], s->ZWp[1], s->st);
+        } else if (s->lambda_variant == 4)
           msd::launch_lambda_mfma(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, s->sw[0].T,
                                   s->sw[1].T, s->LT[0], s->LT[1], s->Lam[0], s->Lam[1], s->v0,
                                   s->ex0, s->ZWp[0], s->ZWp[1], s->st);
@@ -1370,6 +1380,7 @@ void set_trial_rows(msd_system* sys, const double* ci, const int32_t* occ_a,
     const size_t n = (size_t)NG * msd::ltl_stage_elems(sys->ds[0], sys->ds[1]);
     sys->Slf[sp] = sys->lf_fits64 ? T.get<double>(n) : nullptr;
     sys->Slf32[sp] = sys->lf_fits32 ? T.get<float>(n) : nullptr;
+    sys->Slr[sp] = (sys->lf_fits64 || sys->lf_fits32) ? T.get<double>((size_t)NG * 64 * 8) : nullptr;
   }
   if (sys->mixed) {
     sys->Gp32 = T.get<float>((size_t)2 * NW * sys->P_all * M);

@@ -168,21 +168,28 @@ void launch_lambda_mfma32(const DevSpin& sa, const DevSpin& sb, int NW, int w0, 
 // Fused Cholesky contraction + energy intermediates on the matrix cores (same
 // shapes as the LT-tile kernel, M <= 64): no LT in HBM.  S_a/S_b are the
 // restricted rows of L per spin, k-major and padded, [NG][64][P16] with rows
-// V_act then R (launch_gather_ltl); outputs as launch_lambda_mfma.
+// V_act then R (launch_gather_ltl); Lambda windows and ZW partials as
+// launch_lambda_mfma.
 bool ltl_mfma_fits(const DevSpin& sa, const DevSpin& sb, int M, bool fp32);
 size_t ltl_stage_elems(const DevSpin& sa, const DevSpin& sb);  // 64 * P16 per vector
 int ltl_rows16(const DevSpin& sa, const DevSpin& sb);
 void launch_gather_ltl(const double* L, int NG, int M, const DevSpin& D, int P16, double* S64,
                        float* S32, hipStream_t st);
+// v0 of both spins ([2][NW][NG], from launch_qtr) enters ZW = sum_g Xi - v Lam.
 void launch_ltl_mfma(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
                      int g_chunk, int M, const double* Sa, const double* Sb, const cd* Ta,
-                     const cd* Tb, cd* Lam_a, cd* Lam_b, cd* v0, cd* ex0, cd* ZWpart_a,
+                     const cd* Tb, cd* Lam_a, cd* Lam_b, const cd* v0, cd* ZWpart_a,
                      cd* ZWpart_b, hipStream_t st);
-// (mixed form: v0, ex0 from the FP64 Q tiles)
 void launch_ltl_mfma32(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
                        int g_chunk, int M, const float* Sa, const float* Sb, const cf* Ta,
-                       const cf* Tb, cf* Lam_a, cf* Lam_b, cd* v0, cd* ex0, cd* ZWpart_a,
-                       cd* ZWpart_b, const cd* Q64a, const cd* Q64b, hipStream_t st);
+                       const cf* Tb, cf* Lam_a, cf* Lam_b, const cd* v0, cd* ZWpart_a,
+                       cd* ZWpart_b, hipStream_t st);
+// FP64 mean-field traces v0, ex0 ([2][NW][NG]) of Q^g = L^g[R, :] T for the
+// walkers w0 .. w0 + WT - 1 (N = 8 per spin, M <= 64); SRa/SRb are the
+// reference rows of L, k-major [NG][64][8] (launch_gather_ltl with no
+// virtuals and 8 rows).
+void launch_qtr(int NW, int w0, int WT, int NG, int M, const double* SRa, const double* SRb,
+                const cd* Ta, const cd* Tb, cd* v0, cd* ex0, hipStream_t st);
 void init_ltl_attributes();
 // exact: both spins have N == nmax and an identity occupied window;
 // prefetch: next vector's LT row loaded ahead into registers (exact shapes).

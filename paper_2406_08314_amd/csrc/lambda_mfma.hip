@@ -379,8 +379,7 @@ __global__ __launch_bounds__(64 * LF_WAVES) void k_ltl_mfma(
     int P16, const R* __restrict__ Sa, const R* __restrict__ Sb,
     const typename Mfma<R>::cx_t* __restrict__ Ta, const typename Mfma<R>::cx_t* __restrict__ Tb,
     typename Mfma<R>::cx_t* __restrict__ Lam_a, typename Mfma<R>::cx_t* __restrict__ Lam_b,
-    cd* __restrict__ v0, cd* __restrict__ ex0, cd* __restrict__ ZWa, cd* __restrict__ ZWb,
-    const cd* __restrict__ Q64a, const cd* __restrict__ Q64b) {
+    const cd* __restrict__ v0, cd* __restrict__ ZWa, cd* __restrict__ ZWb) {
   typedef Mfma<R> MF;
   typedef typename MF::cx_t C;
   typedef typename MF::acc_t acc_t;
@@ -389,7 +388,6 @@ __global__ __launch_bounds__(64 * LF_WAVES) void k_ltl_mfma(
   const int SE = LF_K * P16;  // reals of one spin's stage
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int qb = 4 * SE + wv * LF_Q;           // this wave's Q as [i][re 0..7 | im 0..7]
-  const int vbb = 4 * SE + LF_WAVES * LF_Q;    // [wave][re, im] traces
   // workgroups of one chunk of vectors are consecutive on an XCD (shared L^g)
   const int nb = gridDim.x, b = blockIdx.x;
   const int xcd = b & 7, per = nb >> 3, rem = nb & 7;
@@ -451,12 +449,21 @@ __global__ __launch_bounds__(64 * LF_WAVES) void k_ltl_mfma(
       }
     }
   };
-  if (g0 < g1) fetch(g0, 0);
+  // v = v0_alpha + v0_beta of the walker and vector (read one vector ahead)
+  const cd* va = v0 + (size_t)w * NG;
+  const cd* vb = v0 + ((size_t)NW + w) * NG;
+  cd vnext{0.0, 0.0};
+  if (g0 < g1) {
+    fetch(g0, 0);
+    vnext = va[g0] + vb[g0];
+  }
   int it = 0;
   for (int g = g0; g < g1; ++g, ++it) {
     const int buf = it & 1;
     lf_bar_all();  // this vector's stage has landed; the other buffer is free
     if (g + 1 < g1) fetch(g + 1, buf ^ 1);
+    const R vr = R(vnext.re), vi = R(vnext.im);
+    if (g + 1 < g1) vnext = va[g + 1] + vb[g + 1];
     const int sb0 = (buf * 2 + s2) * SE;
     acc_t acc[NT];
 #pragma unroll
@@ -492,61 +499,6 @@ __global__ __launch_bounds__(64 * LF_WAVES) void k_ltl_mfma(
         if (i >= 0 && i < LM_N) lds[qb + i * 16 + lf_sig<R>(MF::row(lane, r))] = acc[ct][r];
       }
     lf_wave_lds();
-    // traces on lanes 0..7 (row i = lane): tr Q and tr QQ = sum_ic Q_ic Q_ci
-    R vr, vi;
-    if (Q64a) {  // from the FP64 Q tiles of both spins
-      cd vd{0.0, 0.0}, x{0.0, 0.0}, vo{0.0, 0.0};
-      if (active && lane < LM_N) {
-        const cd* qp = (s2 ? Q64b : Q64a) + ((size_t)wl * NG + g) * LM_N * LM_N;
-        const cd* qo = (s2 ? Q64a : Q64b) + ((size_t)wl * NG + g) * LM_N * LM_N;
-        vd = qp[lane * LM_N + lane];
-        vo = qo[lane * LM_N + lane];
-#pragma unroll
-        for (int c = 0; c < LM_N; ++c) x = x + qp[lane * LM_N + c] * qp[c * LM_N + lane];
-      }
-      vd.re = lf_sum8(vd.re);
-      vd.im = lf_sum8(vd.im);
-      x.re = lf_sum8(x.re);
-      x.im = lf_sum8(x.im);
-      vo.re = lf_sum8(vo.re);
-      vo.im = lf_sum8(vo.im);
-      if (lane == 0 && active) {
-        v0[((size_t)s2 * NW + w) * NG + g] = vd;
-        ex0[((size_t)s2 * NW + w) * NG + g] = x;
-      }
-      vr = R(__shfl(vd.re + vo.re, 0, 64));
-      vi = R(__shfl(vd.im + vo.im, 0, 64));
-      lf_bar_lds();  // keeps the barrier count of the exchange below
-    } else {
-      R dr = R(0), di = R(0), xr = R(0), xi = R(0);
-      if (lane < LM_N) {
-        const int i = lane;
-        dr = lds[qb + i * 16 + i];
-        di = lds[qb + i * 16 + 8 + i];
-#pragma unroll
-        for (int c = 0; c < LM_N; ++c) {
-          const R ar = lds[qb + i * 16 + c], ai = lds[qb + i * 16 + 8 + c];
-          const R br = lds[qb + c * 16 + i], bi = lds[qb + c * 16 + 8 + i];
-          xr += ar * br - ai * bi;
-          xi += ar * bi + ai * br;
-        }
-      }
-      dr = lf_sum8(dr);
-      di = lf_sum8(di);
-      xr = lf_sum8(xr);
-      xi = lf_sum8(xi);
-      if (lane == 0) {
-        if (active) {
-          v0[((size_t)s2 * NW + w) * NG + g] = cd{(double)dr, (double)di};
-          ex0[((size_t)s2 * NW + w) * NG + g] = cd{(double)xr, (double)xi};
-        }
-        lds[vbb + 2 * wv] = dr;
-        lds[vbb + 2 * wv + 1] = di;
-      }
-      lf_bar_lds();  // the other spin's trace of this walker is in LDS
-      vr = lds[vbb + 2 * wv] + lds[vbb + 2 * (wv ^ 4)];
-      vi = lds[vbb + 2 * wv + 1] + lds[vbb + 2 * (wv ^ 4) + 1];
-    }
     // A operands: Bq^T (row jc, k = 4s + q) and (Bq - v Bi)^T (row jc, k = the
     // logical row that register s of lane group q holds in Lam^T)
     R bqa[4], bqz[4];
@@ -668,8 +620,7 @@ template <class R>
 void launch_ltl_t(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
                   int g_chunk, int M, const R* Sa, const R* Sb, const typename Mfma<R>::cx_t* Ta,
                   const typename Mfma<R>::cx_t* Tb, typename Mfma<R>::cx_t* Lam_a,
-                  typename Mfma<R>::cx_t* Lam_b, cd* v0, cd* ex0, cd* ZWa, cd* ZWb,
-                  const cd* Q64a, const cd* Q64b, hipStream_t st) {
+                  typename Mfma<R>::cx_t* Lam_b, const cd* v0, cd* ZWa, cd* ZWb, hipStream_t st) {
   const int P16 = ltl_rows16(sa, sb), NT = P16 / 16;
   const int n_chunks = (NG + g_chunk - 1) / g_chunk;
   const int n_wgrp = (WT + LF_WB - 1) / LF_WB;
@@ -678,8 +629,7 @@ void launch_ltl_t(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, 
 #define LTL_CASE(nt)                                                                          \
   case nt:                                                                                    \
     hipLaunchKernelGGL((k_ltl_mfma<R, nt>), grid, block, lds, st, sa, sb, NW, w0, WT, NG,     \
-                       g_chunk, n_chunks, M, P16, Sa, Sb, Ta, Tb, Lam_a, Lam_b, v0, ex0, ZWa, \
-                       ZWb, Q64a, Q64b);                                                      \
+                       g_chunk, n_chunks, M, P16, Sa, Sb, Ta, Tb, Lam_a, Lam_b, v0, ZWa, ZWb); \
     break;
   switch (NT) {
     LTL_CASE(1)
@@ -696,18 +646,101 @@ void launch_ltl_t(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, 
 
 void launch_ltl_mfma(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
                      int g_chunk, int M, const double* Sa, const double* Sb, const cd* Ta,
-                     const cd* Tb, cd* Lam_a, cd* Lam_b, cd* v0, cd* ex0, cd* ZWpart_a,
+                     const cd* Tb, cd* Lam_a, cd* Lam_b, const cd* v0, cd* ZWpart_a,
                      cd* ZWpart_b, hipStream_t st) {
-  launch_ltl_t<double>(sa, sb, NW, w0, WT, NG, g_chunk, M, Sa, Sb, Ta, Tb, Lam_a, Lam_b, v0, ex0,
-                       ZWpart_a, ZWpart_b, nullptr, nullptr, st);
+  launch_ltl_t<double>(sa, sb, NW, w0, WT, NG, g_chunk, M, Sa, Sb, Ta, Tb, Lam_a, Lam_b, v0,
+                       ZWpart_a, ZWpart_b, st);
 }
 
 void launch_ltl_mfma32(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
                        int g_chunk, int M, const float* Sa, const float* Sb, const cf* Ta,
-                       const cf* Tb, cf* Lam_a, cf* Lam_b, cd* v0, cd* ex0, cd* ZWpart_a,
-                       cd* ZWpart_b, const cd* Q64a, const cd* Q64b, hipStream_t st) {
-  launch_ltl_t<float>(sa, sb, NW, w0, WT, NG, g_chunk, M, Sa, Sb, Ta, Tb, Lam_a, Lam_b, v0, ex0,
-                      ZWpart_a, ZWpart_b, Q64a, Q64b, st);
+                       const cf* Tb, cf* Lam_a, cf* Lam_b, const cd* v0, cd* ZWpart_a,
+                       cd* ZWpart_b, hipStream_t st) {
+  launch_ltl_t<float>(sa, sb, NW, w0, WT, NG, g_chunk, M, Sa, Sb, Ta, Tb, Lam_a, Lam_b, v0,
+                      ZWpart_a, ZWpart_b, st);
+}
+
+// ============================================================================
+// Mean-field traces in FP64 on the matrix cores (N = 8 per spin, M <= 64):
+// v0 = tr Q and ex0 = tr QQ of Q^g = L^g[R, :] T, two vectors per tile,
+//   D = [Tr Ti]^T [S_R^g | S_R^{g+1}]        (16 x 16 = (16 x 64)(64 x 16)),
+// D[j][c] = Re / Im (j < 8 / j >= 8) of Q^{g + c / 8}[c % 8][j % 8], with
+// S_R^g[k][i] = L^g[R_i, k] (k-major, zero for k >= M).  One wave per
+// (walker, spin) and chunk of vectors; the tile goes through LDS for the
+// products Q_in Q_ni.
+// ============================================================================
+
+constexpr int QT_WAVES = 8;
+constexpr int QT_LD = 17;  // row stride of the LDS tile (doubles)
+
+__global__ __launch_bounds__(64 * QT_WAVES) void k_qtr(int NW, int w0, int WT, int NG, int g_chunk,
+                                                       int M, const double* __restrict__ SRa,
+                                                       const double* __restrict__ SRb,
+                                                       const cd* __restrict__ Ta,
+                                                       const cd* __restrict__ Tb,
+                                                       cd* __restrict__ v0, cd* __restrict__ ex0) {
+  __shared__ double dt[QT_WAVES][16 * QT_LD];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int s2 = blockIdx.z, chunk = blockIdx.y;
+  const int wl = blockIdx.x * QT_WAVES + wv;
+  if (wl >= WT) return;  // no barriers below
+  const int w = w0 + wl;
+  const double* __restrict__ SR = s2 ? SRb : SRa;
+  const cd* __restrict__ T = s2 ? Tb : Ta;
+  const int col = lane & 15, q = lane >> 4;
+  double bt[LF_K / 4];
+#pragma unroll
+  for (int s = 0; s < LF_K / 4; ++s) {
+    const int k = 4 * s + q;
+    double v = 0.0;
+    if (k < M) {
+      const cd t = T[((size_t)k * NW + w) * LM_N + (col & 7)];
+      v = col < 8 ? t.re : t.im;
+    }
+    bt[s] = v;
+  }
+  double* d_t = dt[wv];
+  const int h = lane >> 5, t = lane & 31, i = t >> 2, n0 = 2 * (t & 3), ci = 8 * h + i;
+  const int g0 = chunk * g_chunk, g1 = min(NG, g0 + g_chunk);
+  for (int g = g0; g < g1; g += 2) {
+    const int gg = min(g + (col >> 3), NG - 1);  // the second vector of a last odd one is unused
+    dvec4 d = dvec4{0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < LF_K / 4; ++s)
+      d = __builtin_amdgcn_mfma_f64_16x16x4f64(
+          bt[s], SR[((size_t)gg * LF_K + 4 * s + q) * LM_N + (col & 7)], d, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) d_t[(q + 4 * r) * QT_LD + col] = d[r];
+    // lane (h, i, n0): Q_in Q_ni for n = n0, n0 + 1 of vector g + h; Q_ii on the diagonal
+    cd x{0.0, 0.0}, dv{0.0, 0.0};
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const int n = n0 + m;
+      const cd qin{d_t[n * QT_LD + ci], d_t[(8 + n) * QT_LD + ci]};
+      const cd qni{d_t[i * QT_LD + 8 * h + n], d_t[(8 + i) * QT_LD + 8 * h + n]};
+      x = x + qin * qni;
+      if (n == i) dv = qin;
+    }
+#pragma unroll
+    for (int off = 1; off < 32; off <<= 1) {
+      x.re += __shfl_xor(x.re, off, 64);
+      x.im += __shfl_xor(x.im, off, 64);
+      dv.re += __shfl_xor(dv.re, off, 64);
+      dv.im += __shfl_xor(dv.im, off, 64);
+    }
+    if (t == 0 && g + h < g1) {
+      v0[((size_t)s2 * NW + w) * NG + g + h] = dv;
+      ex0[((size_t)s2 * NW + w) * NG + g + h] = x;
+    }
+  }
+}
+
+void launch_qtr(int NW, int w0, int WT, int NG, int M, const double* SRa, const double* SRb,
+                const cd* Ta, const cd* Tb, cd* v0, cd* ex0, hipStream_t st) {
+  const int g_chunk = 16;  // even: vector pairs never straddle chunks
+  const dim3 grid((WT + QT_WAVES - 1) / QT_WAVES, (NG + g_chunk - 1) / g_chunk, 2);
+  hipLaunchKernelGGL(k_qtr, grid, dim3(64 * QT_WAVES), 0, st, NW, w0, WT, NG, g_chunk, M, SRa,
+                     SRb, Ta, Tb, v0, ex0);
 }
 
 void init_ltl_attributes() {
