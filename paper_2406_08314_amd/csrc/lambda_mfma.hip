@@ -673,6 +673,25 @@ void launch_ltl_mfma32(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int
 constexpr int QT_WAVES = 8;
 constexpr int QT_LD = 17;  // row stride of the LDS tile (doubles)
 
+// one DPP move of a double (row-local lane permutation dpp_ctrl)
+template <int CTRL>
+__device__ __forceinline__ double qt_dpp(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+// sum over the 16 lanes of a row, in every lane of it: xor 1 and xor 2 by
+// quad permutations, then the half-row mirror (quads 0 <-> 1) and the row
+// mirror (halves 0 <-> 1)
+__device__ __forceinline__ double qt_sum16(double v) {
+  v += qt_dpp<0xB1>(v);
+  v += qt_dpp<0x4E>(v);
+  v += qt_dpp<0x141>(v);
+  v += qt_dpp<0x140>(v);
+  return v;
+}
+
 __global__ __launch_bounds__(64 * QT_WAVES) void k_qtr(int NW, int w0, int WT, int NG, int g_chunk,
                                                        int M, const double* __restrict__ SRa,
                                                        const double* __restrict__ SRb,
@@ -700,37 +719,45 @@ __global__ __launch_bounds__(64 * QT_WAVES) void k_qtr(int NW, int w0, int WT, i
     bt[s] = v;
   }
   double* d_t = dt[wv];
-  const int h = lane >> 5, t = lane & 31, i = t >> 2, n0 = 2 * (t & 3), ci = 8 * h + i;
+  // products: row q of lanes takes vector g + q (q < 2); lane col: i = col / 2,
+  // n = 4 (col % 2) .. + 3
+  const int h = q & 1, i = col >> 1, nb = 4 * (col & 1);
   const int g0 = chunk * g_chunk, g1 = min(NG, g0 + g_chunk);
+  // B operands of the next vector pair are loaded while this pair is formed
+  auto load = [&](int g, double* b) __attribute__((always_inline)) {
+    const int gg = min(g + (col >> 3), NG - 1);  // the second of a last odd vector is unused
+#pragma unroll
+    for (int s = 0; s < LF_K / 4; ++s) b[s] = SR[((size_t)gg * LF_K + 4 * s + q) * LM_N + (col & 7)];
+  };
+  double bcur[LF_K / 4], bnxt[LF_K / 4];
+  if (g0 < g1) load(g0, bcur);
   for (int g = g0; g < g1; g += 2) {
-    const int gg = min(g + (col >> 3), NG - 1);  // the second vector of a last odd one is unused
+    if (g + 2 < g1) load(g + 2, bnxt);
     dvec4 d = dvec4{0, 0, 0, 0};
 #pragma unroll
-    for (int s = 0; s < LF_K / 4; ++s)
-      d = __builtin_amdgcn_mfma_f64_16x16x4f64(
-          bt[s], SR[((size_t)gg * LF_K + 4 * s + q) * LM_N + (col & 7)], d, 0, 0, 0);
+    for (int s = 0; s < LF_K / 4; ++s) d = __builtin_amdgcn_mfma_f64_16x16x4f64(bt[s], bcur[s], d, 0, 0, 0);
 #pragma unroll
     for (int r = 0; r < 4; ++r) d_t[(q + 4 * r) * QT_LD + col] = d[r];
-    // lane (h, i, n0): Q_in Q_ni for n = n0, n0 + 1 of vector g + h; Q_ii on the diagonal
     cd x{0.0, 0.0}, dv{0.0, 0.0};
 #pragma unroll
-    for (int m = 0; m < 2; ++m) {
-      const int n = n0 + m;
-      const cd qin{d_t[n * QT_LD + ci], d_t[(8 + n) * QT_LD + ci]};
+    for (int m = 0; m < 4; ++m) {
+      const int n = nb + m;
+      const cd qin{d_t[n * QT_LD + 8 * h + i], d_t[(8 + n) * QT_LD + 8 * h + i]};
       const cd qni{d_t[i * QT_LD + 8 * h + n], d_t[(8 + i) * QT_LD + 8 * h + n]};
       x = x + qin * qni;
       if (n == i) dv = qin;
     }
-#pragma unroll
-    for (int off = 1; off < 32; off <<= 1) {
-      x.re += __shfl_xor(x.re, off, 64);
-      x.im += __shfl_xor(x.im, off, 64);
-      dv.re += __shfl_xor(dv.re, off, 64);
-      dv.im += __shfl_xor(dv.im, off, 64);
-    }
-    if (t == 0 && g + h < g1) {
+    x.re = qt_sum16(x.re);
+    x.im = qt_sum16(x.im);
+    dv.re = qt_sum16(dv.re);
+    dv.im = qt_sum16(dv.im);
+    if (col == 0 && q < 2 && g + h < g1) {
       v0[((size_t)s2 * NW + w) * NG + g + h] = dv;
       ex0[((size_t)s2 * NW + w) * NG + g + h] = x;
+    }
+    if (g + 2 < g1) {
+#pragma unroll
+      for (int s = 0; s < LF_K / 4; ++s) bcur[s] = bnxt[s];
     }
   }
 }
