@@ -471,8 +471,8 @@ void alloc_energy(msd_system* s) {
   if (s->tune.lambda_chunk > 0) {
     s->gl_chunk = std::min(s->tune.lambda_chunk, NG);
   } else if (s->lambda_variant == 5) {
-    // about one workgroup of four walkers per CU and chunk (two in FP32)
-    const int n_wgrp = (wt + 3) / 4, target = s->energy_mixed ? 512 : 256;
+    // workgroups of four walkers and one spin: about two per CU (four in FP32)
+    const int n_wgrp = 2 * ((wt + 3) / 4), target = s->energy_mixed ? 1024 : 512;
     const int n_chunks = std::max(1, std::min(NG, (target + n_wgrp / 2) / n_wgrp));
     s->gl_chunk = (NG + n_chunks - 1) / n_chunks;
   } else {

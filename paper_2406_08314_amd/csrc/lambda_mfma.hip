@@ -281,11 +281,11 @@ void launch_lambda_mfma32(const DevSpin& sa, const DevSpin& sb, int NW, int w0, 
 // A2 + A6 fused on the matrix cores: the Cholesky contraction LT^g = L^g T and
 // the energy intermediates of Sec. III in one pass, without LT in HBM.
 //
-// Workgroup = 4 walkers x 2 spins (one wave each) and a chunk of Cholesky
-// vectors.  Per vector g both spins' restricted rows of L^g, stored k-major
-// as S[g][k][p] (p over V_act then R, zero padded to P16 rows and 64 k), are
-// staged in LDS by direct global-to-LDS loads, double-buffered one vector
-// ahead.  Each wave forms transposed products, so that the result registers
+// Workgroup = 4 walkers of one spin (one wave each) and a chunk of Cholesky
+// vectors; two or more workgroups share a CU and run out of step.  Per vector
+// g the spin's restricted rows of L^g, stored k-major as S[g][k][p] (p over
+// V_act then R, zero padded to P16 rows and 64 k), are staged in LDS by
+// direct global-to-LDS loads, double-buffered one vector ahead.  Each wave forms transposed products, so that the result registers
 // of one MFMA are the B operand of the next (no transposes through LDS):
 //   LT^T   = [Tr Ti]^T S                     (16 x P16; [Tr Ti] in registers)
 //   Lam^T  = Bq^T [Tr Ti]_V^T - LT_V^T        (16 x n_v, 16 virtuals per tile)
@@ -293,14 +293,13 @@ void launch_lambda_mfma32(const DevSpin& sa, const DevSpin& sb, int NW, int w0, 
 // Bq = [[Qr Qi]; [-Qi Qr]] is the real form of Q = LT[R, :] (row vectors
 // times Q), Bi that of the identity; the 16 rows are the real and imaginary
 // parts of the N = 8 columns.  The last line is ZW += Xi - v Lam with
-// Xi = Lam Q.  tr Q is exchanged with the other spin's wave of the walker
-// through LDS.
+// Xi = Lam Q; v comes from the trace pass (launch_qtr) before this kernel.
 // ============================================================================
 
 namespace {
 
 constexpr int LF_WB = 4;               // walkers per workgroup
-constexpr int LF_WAVES = 2 * LF_WB;    // one wave per (walker, spin)
+constexpr int LF_WAVES = LF_WB;        // one wave per walker (one spin per workgroup)
 constexpr int LF_K = 64;               // contraction length (orbitals, zero padded)
 constexpr int LF_Q = LM_N * 16;        // Q scratch per wave (reals)
 
@@ -334,7 +333,7 @@ __device__ __forceinline__ void lf_wave_lds() {
 }
 
 size_t lf_lds_bytes(int P16, size_t rsize) {
-  return (4 * (size_t)LF_K * P16 + (size_t)LF_WAVES * LF_Q + 2 * LF_WAVES) * rsize;
+  return (2 * (size_t)LF_K * P16 + (size_t)LF_WAVES * LF_Q) * rsize;
 }
 
 // Row order of the 16 x 16 operands: hardware row i holds logical row sig(i)
@@ -374,7 +373,7 @@ __device__ __forceinline__ R lf_sum8(R v) {  // over lanes of a group of 8
 }  // namespace
 
 template <class R, int NT>
-__global__ __launch_bounds__(64 * LF_WAVES) void k_ltl_mfma(
+__global__ __launch_bounds__(64 * LF_WAVES, 2) void k_ltl_mfma(
     DevSpin sa, DevSpin sb, int NW, int w0, int WT, int NG, int g_chunk, int n_chunks, int M,
     int P16, const R* __restrict__ Sa, const R* __restrict__ Sb,
     const typename Mfma<R>::cx_t* __restrict__ Ta, const typename Mfma<R>::cx_t* __restrict__ Tb,
@@ -387,14 +386,14 @@ __global__ __launch_bounds__(64 * LF_WAVES) void k_ltl_mfma(
   R* lds = reinterpret_cast<R*>(lf_raw);
   const int SE = LF_K * P16;  // reals of one spin's stage
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int qb = 4 * SE + wv * LF_Q;           // this wave's Q as [i][re 0..7 | im 0..7]
+  const int qb = 2 * SE + wv * LF_Q;           // this wave's Q as [i][re 0..7 | im 0..7]
   // workgroups of one chunk of vectors are consecutive on an XCD (shared L^g)
   const int nb = gridDim.x, b = blockIdx.x;
   const int xcd = b & 7, per = nb >> 3, rem = nb & 7;
   const int logical = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + (b >> 3);
   const int n_wgrp = (WT + LF_WB - 1) / LF_WB;
-  const int chunk = logical / n_wgrp, wl = (logical % n_wgrp) * LF_WB + (wv & 3);
-  const int s2 = wv >> 2;
+  const int chunk = logical / (2 * n_wgrp), s2 = (logical / n_wgrp) & 1;
+  const int wl = (logical % n_wgrp) * LF_WB + wv;
   const bool active = wl < WT;
   const int w = w0 + (active ? wl : 0);
   const int nv = s2 ? sb.nv : sa.nv, X = nv * LM_N;
@@ -439,14 +438,11 @@ __global__ __launch_bounds__(64 * LF_WAVES) void k_ltl_mfma(
   auto fetch = [&](int g, int buf) {
     constexpr int per16 = 16 / sizeof(R);
     const int n16 = SE / per16;
-#pragma unroll
-    for (int sp = 0; sp < 2; ++sp) {
-      const R* src = (sp ? Sb : Sa) + (size_t)g * SE;
-      const int dst = (buf * 2 + sp) * SE;
-      for (int c = wv; c * 64 < n16; c += LF_WAVES) {
-        const int e = c * 64 + lane;
-        if (e < n16) dma16(src + (size_t)e * per16, &lds[dst + c * 64 * per16]);
-      }
+    const R* src = (s2 ? Sb : Sa) + (size_t)g * SE;
+    const int dst = buf * SE;
+    for (int c = wv; c * 64 < n16; c += LF_WAVES) {
+      const int e = c * 64 + lane;
+      if (e < n16) dma16(src + (size_t)e * per16, &lds[dst + c * 64 * per16]);
     }
   };
   // v = v0_alpha + v0_beta of the walker and vector (read one vector ahead)
@@ -464,7 +460,7 @@ __global__ __launch_bounds__(64 * LF_WAVES) void k_ltl_mfma(
     if (g + 1 < g1) fetch(g + 1, buf ^ 1);
     const R vr = R(vnext.re), vi = R(vnext.im);
     if (g + 1 < g1) vnext = va[g + 1] + vb[g + 1];
-    const int sb0 = (buf * 2 + s2) * SE;
+    const int sb0 = buf * SE;
     acc_t acc[NT];
 #pragma unroll
     for (int ct = 0; ct < NT; ++ct) acc[ct] = acc_t{0, 0, 0, 0};
@@ -624,7 +620,7 @@ void launch_ltl_t(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, 
   const int P16 = ltl_rows16(sa, sb), NT = P16 / 16;
   const int n_chunks = (NG + g_chunk - 1) / g_chunk;
   const int n_wgrp = (WT + LF_WB - 1) / LF_WB;
-  const dim3 grid(n_wgrp * n_chunks), block(64 * LF_WAVES);
+  const dim3 grid(n_wgrp * n_chunks * 2), block(64 * LF_WAVES);
   const size_t lds = lf_lds_bytes(P16, sizeof(R));
 #define LTL_CASE(nt)                                                                          \
   case nt:                                                                                    \
