@@ -453,11 +453,30 @@ __global__ __launch_bounds__(64 * LF_WAVES, 2) void k_ltl_mfma(
     fetch(g0, 0);
     vnext = va[g0] + vb[g0];
   }
+  // window store Lam[w][g][a * 8 + n]
+  acc_t lam_prev[4];
+  auto store_window = [&](int g) __attribute__((always_inline)) {
+    if (!active) return;
+    C* lo = Lam + ((size_t)wl * NG + g) * X;
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) {
+      const int a = rt * 16 + col;
+      if (a < nv) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          int rre, rim, n;
+          lf_pair<R>(q, h, &rre, &rim, &n);
+          lo[a * LM_N + n] = C{lam_prev[rt][rre], lam_prev[rt][rim]};
+        }
+      }
+    }
+  };
   int it = 0;
   for (int g = g0; g < g1; ++g, ++it) {
     const int buf = it & 1;
     lf_bar_all();  // this vector's stage has landed; the other buffer is free
     if (g + 1 < g1) fetch(g + 1, buf ^ 1);
+    if (g > g0) store_window(g - 1);
     const R vr = R(vnext.re), vi = R(vnext.im);
     if (g + 1 < g1) vnext = va[g + 1] + vb[g + 1];
     const int sb0 = buf * SE;
@@ -524,28 +543,17 @@ __global__ __launch_bounds__(64 * LF_WAVES, 2) void k_ltl_mfma(
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int rt = 0; rt < 4; ++rt) lam[rt] = MF::run(bqa[s], av[rt][s], lam[rt]);
-    // window store Lam[w][g][a * 8 + n]
-    if (active) {
-      C* lo = Lam + ((size_t)wl * NG + g) * X;
-#pragma unroll
-      for (int rt = 0; rt < 4; ++rt) {
-        const int a = rt * 16 + col;
-        if (a < nv) {
-#pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            int rre, rim, n;
-            lf_pair<R>(q, h, &rre, &rim, &n);
-            lo[a * LM_N + n] = C{lam[rt][rre], lam[rt][rim]};
-          }
-        }
-      }
-    }
     // ZW^T += (Bq - v Bi)^T Lam^T: register s of Lam^T is the B operand of step s
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int rt = 0; rt < 4; ++rt) zw[rt] = MF::run(bqz[s], lam[rt][s], zw[rt]);
+    // the window of this vector is stored early in the next iteration, so its
+    // stores drain while that iteration runs rather than at its first barrier
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) lam_prev[rt] = lam[rt];
   }
+  if (g0 < g1) store_window(g1 - 1);
   if (!active) return;
   // ZW partial of this chunk: [wl][chunk][a * 8 + n]
 #pragma unroll
