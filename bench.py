@@ -28,7 +28,9 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 TRAFFIC_PROFILES = {
     "energy_gamma": os.path.join(ROOT, "profiles", "energy_second_medium_hbm_traffic.md"),
-    "lambda": os.path.join(ROOT, "profiles", "lambda_mfma_medium_hbm_traffic.md"),
+    # (stage, lambda variant): the LT-tile kernel and the fused contraction kernel
+    ("lambda", 4): os.path.join(ROOT, "profiles", "lambda_mfma_medium_hbm_traffic.md"),
+    ("lambda", 5): os.path.join(ROOT, "profiles", "ltl_mfma_medium_hbm_traffic.md"),
 }
 
 
@@ -39,7 +41,7 @@ def measured_traffic(stage):
     vectors per LDS stage, stage copy mode)."""
     import hashlib
     try:
-        text = open(TRAFFIC_PROFILES[stage]).read()
+        text = open(TRAFFIC_PROFILES[stage]).read()  # stage: name or (name, variant)
     except (KeyError, OSError):
         return None
     vals = dict(line.split(": ", 1) for line in text.splitlines()
@@ -73,6 +75,17 @@ def stage_work(wl, lib_sys, stage):
         return 6 * 8.0 * M * M * Ntot * NW, "flop", "mfma"
     if stage == "one_body":
         return 4.0 * M * M * Ntot * NW, "flop", "mfma"
+    if stage == "lambda" and lib_sys.get_tuning()["lambda_variant"] == 5:
+        # fused contraction kernel: matrix-core bound.  Per walker, vector and
+        # spin: LT = L[R u V, :] T (4 P N M flop, complex T), Lambda = T[V, :] Q
+        # and Xi = Lambda Q (8 flop per complex MAC, nv N N each)
+        f = 0.0
+        for N, nv in ((na, tt["nv"][0]), (nb, tt["nv"][1])):
+            f += NW * NG * (4.0 * (N + nv) * N * M + 2 * 8.0 * nv * N * N)
+        return f, "flop", "mfma"
+    if stage == "traces":
+        # Q = L[R, :] T (4 N N M flop) and tr QQ (8 N N) per walker, vector, spin
+        return sum(NW * NG * (4.0 * N * N * M + 8.0 * N * N) for N in (na, nb)), "flop", "mfma"
     if stage == "lambda":
         # matrix-core kernel: bound by its HBM stream (LT tiles in, Lambda
         # windows, ZW partials, v0 and ex0 out)
@@ -246,16 +259,18 @@ def main():
             peak = HBM_PEAK_GBS
             u = "GB/s"
         traffic = None
-        prof = measured_traffic(name)
         t = tunings["fp64"]
-        if prof and name == "energy_gamma":
-            if prof[1] == (t["second_gsplit"], t["second_stage"], t["second_copy"]):
+        if name == "energy_gamma":
+            prof = measured_traffic(name)
+            if prof and prof[1] == (t["second_gsplit"], t["second_stage"], t["second_copy"]):
                 traffic = prof[0]
-        elif prof and name == "lambda" and t["lambda_variant"] == 4:
-            traffic = prof[0]
+        elif name == "lambda":
+            prof = measured_traffic(("lambda", t["lambda_variant"]))
+            if prof and (not prof[1] or prof[1] == (t["lambda_chunk"],)):
+                traffic = prof[0]
         lam_kernel = {1: "k_lambda_rows", 2: "k_lambda_wave", 3: "k_lambda_wave",
-                      4: "k_lambda_mfma"}.get(t["lambda_variant"], "k_lambda")
-        kernel = {"energy_gamma": "k_energy_second", "lambda": lam_kernel,
+                      4: "k_lambda_mfma", 5: "k_ltl_mfma"}.get(t["lambda_variant"], "k_lambda")
+        kernel = {"energy_gamma": "k_energy_second", "lambda": lam_kernel, "traces": "k_qtr",
                   "lt_gemm": "k_gemm_f64 (LT)"}.get(name, name)
         roof = {"kernel": kernel, "stage": name, "bound": bound, "achieved": round(ach, 3), "peak": peak,
                 "unit": u, "frac": round(ach / peak, 4), "traffic": traffic,

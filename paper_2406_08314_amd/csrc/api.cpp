@@ -44,12 +44,13 @@ void hip_check(hipError_t e, const char* what) {
 
 enum Stage {
   ST_REF, ST_STR, ST_OVLP, ST_CIW, ST_CIM, ST_GREEN, ST_FB_GEMM, ST_LT_GEMM, ST_LAMBDA,
-  ST_COEF, ST_EGAMMA, ST_EFINAL, ST_VHS_GEMM, ST_B1, ST_TAYLOR, ST_WEIGHTS, ST_QR, ST_COUNT
+  ST_COEF, ST_EGAMMA, ST_EFINAL, ST_VHS_GEMM, ST_B1, ST_TAYLOR, ST_WEIGHTS, ST_QR, ST_TRACES,
+  ST_COUNT
 };
 const char* kStageNames[ST_COUNT] = {
     "ref_inverse", "strings",  "overlap",   "ci_weights", "ci_matrix",    "green",
     "fb_gemm",     "lt_gemm",  "lambda",    "coef",       "energy_gamma", "energy_final",
-    "vhs_gemm",    "one_body", "taylor",    "weights",    "qr"};
+    "vhs_gemm",    "one_body", "taylor",    "weights",    "qr",           "traces"};
 
 // Minimal device arena: every allocation is recorded and freed together.
 struct Arena {
@@ -80,6 +81,7 @@ struct Arena {
 
 struct msd_system {
   int dev = 0;
+  int n_cu = 256;  // compute units of the device (workgroup-slot heuristics)
   hipStream_t st = nullptr;
   msd_dims d{};
   msd_options o{};
@@ -420,9 +422,23 @@ void alloc_energy(msd_system* s) {
     }
     for (int q = 0; q < wpb; ++q) pl[ib * wpb + q].x |= need << 16;
   }
-  // split the Cholesky range so the second-order kernels have ~1024+ workgroups
+  // split the Cholesky range so the second-order workgroups fill whole rounds
+  // of the chip's workgroup slots (one 16-wave or two 8-wave workgroups per
+  // CU): the best fill of rounds over splits 1 .. 8, the smaller split on ties
   const int units = std::max(1, s->n_itemblocks);
-  s->gsplit = std::max(1, std::min((1024 + wt * units - 1) / (wt * units), std::max(1, NG / 8)));
+  {
+    const int slots = s->n_cu * (wpb == 16 ? 1 : 2);
+    double best = -1.0;
+    for (int gs = 1; gs <= std::min(8, std::max(1, NG / 8)); ++gs) {
+      const long nwg = (long)wt * units * gs;
+      const long rounds = (nwg + slots - 1) / slots;
+      const double fill = (double)nwg / ((double)rounds * slots) - (nwg < slots ? 1.0 : 0.0);
+      if (fill > best + 1e-9) {
+        best = fill;
+        s->gsplit = gs;
+      }
+    }
+  }
   if (s->tune.second_gsplit > 0) s->gsplit = std::min(s->tune.second_gsplit, NG);
   s->slot_second = slot;
   slot += s->n_itemblocks * s->gsplit;
@@ -439,7 +455,7 @@ void alloc_energy(msd_system* s) {
     const int elem = s->energy_mixed ? 8 : 16;  // bytes per staged Lambda entry
     // two 8-wave workgroups or one 16-wave workgroup per CU share its LDS
     const int budget = s->second_waves == 16 ? (144 << 10) : (72 << 10);
-    s->second_G = std::max(1, std::min(5, (int)(budget / (2 * elem * std::max(X, 1)))));
+    s->second_G = std::max(1, std::min(8, (int)(budget / (2 * elem * std::max(X, 1)))));
     if (s->tune.second_stage > 0)
       s->second_G = std::max(1, std::min(s->tune.second_stage,
                                          (int)((150 << 10) / (2 * elem * std::max(X, 1)))));
@@ -695,12 +711,16 @@ void run_energy_mixed(msd_system* s) {
         msd::launch_gemm(q, s->st);
       });
     }
+    if (s->lambda_variant == 5) {  // FP64 traces first: the fused kernel reads v0
+      s->timed(ST_TRACES, [&] {
+        msd::launch_qtr(s->NW, w0, wt, s->NG, s->M, s->Slr[0], s->Slr[1], s->sw[0].T, s->sw[1].T,
+                        s->v0, s->ex0, s->st);
+      });
+    }
     s->timed(ST_LAMBDA, [&] {
       const cf* Ta = reinterpret_cast<const cf*>(s->T32[0]);
       const cf* Tb = reinterpret_cast<const cf*>(s->T32[1]);
       if (s->lambda_variant == 5) {
-        msd::launch_qtr(s->NW, w0, wt, s->NG, s->M, s->Slr[0], s->Slr[1], s->sw[0].T, s->sw[1].T,
-                        s->v0, s->ex0, s->st);
         msd::launch_ltl_mfma32(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, s->M, s->Slf32[0],
                                s->Slf32[1], Ta, Tb, s->Lam32[0], s->Lam32[1], s->v0, s->ZWp[0],
                                s->ZWp[1], s->st);
@@ -722,7 +742,7 @@ void run_energy_mixed(msd_system* s) {
                                   s->ZWp[0], s->ZWp[1], s->st);
     });
     if (s->lambda_variant < 4) {  // the matrix-core kernels read the FP64 Q themselves
-      s->timed(ST_LAMBDA, [&] {
+      s->timed(ST_TRACES, [&] {
         msd::launch_traces64(s->Q64[0], s->Q64[1], A.N, B.N, s->NW, w0, wt, s->NG, s->v0, s->ex0,
                              s->st);
       });
@@ -793,10 +813,14 @@ void run_energy(msd_system* s) {
         });
       }
       int nmax = 0;
-      s->timed(ST_LAMBDA, [&] {
-        if (s->lambda_variant == 5) {
+      if (s->lambda_variant == 5) {  // FP64 traces first: the fused kernel reads v0
+        s->timed(ST_TRACES, [&] {
           msd::launch_qtr(s->NW, w0, wt, s->NG, s->M, s->Slr[0], s->Slr[1], s->sw[0].T,
                           s->sw[1].T, s->v0, s->ex0, s->st);
+        });
+      }
+      s->timed(ST_LAMBDA, [&] {
+        if (s->lambda_variant == 5) {
           msd::launch_ltl_mfma(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, s->M, s->Slf[0],
                                s->Slf[1], s->sw[0].T, s->sw[1].T, s->Lam[0], s->Lam[1], s->v0,
                                s->ZWp[0], s->ZWp[1], s->st);
@@ -1098,6 +1122,9 @@ msd_status msd_create(const msd_dims* d, const msd_options* o, int32_t device, v
   sys->ND = d->n_det;
   try {
     set_device(sys);
+    hip_check(hipDeviceGetAttribute(&sys->n_cu, hipDeviceAttributeMultiprocessorCount, sys->dev),
+              "hipDeviceGetAttribute");
+    if (sys->n_cu < 1) sys->n_cu = 1;
     msd::init_wick_attributes();
     msd::init_ltl_attributes();
     msd::init_prop_attributes();
