@@ -714,7 +714,7 @@ void run_energy_mixed(msd_system* s) {
     if (s->lambda_variant == 5) {  // FP64 traces first: the fused kernel reads v0
       s->timed(ST_TRACES, [&] {
         msd::launch_qtr(s->NW, w0, wt, s->NG, s->M, s->Slr[0], s->Slr[1], s->sw[0].T, s->sw[1].T,
-                        s->v0, s->ex0, s->st);
+                        s->v0, s->ex0, s->n_cu, s->st);
       });
     }
     s->timed(ST_LAMBDA, [&] {
@@ -816,7 +816,7 @@ void run_energy(msd_system* s) {
       if (s->lambda_variant == 5) {  // FP64 traces first: the fused kernel reads v0
         s->timed(ST_TRACES, [&] {
           msd::launch_qtr(s->NW, w0, wt, s->NG, s->M, s->Slr[0], s->Slr[1], s->sw[0].T,
-                          s->sw[1].T, s->v0, s->ex0, s->st);
+                          s->sw[1].T, s->v0, s->ex0, s->n_cu, s->st);
         });
       }
       s->timed(ST_LAMBDA, [&] {

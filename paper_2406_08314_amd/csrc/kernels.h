@@ -189,7 +189,7 @@ void launch_ltl_mfma32(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int
 // reference rows of L, k-major [NG][64][8] (launch_gather_ltl with no
 // virtuals and 8 rows).
 void launch_qtr(int NW, int w0, int WT, int NG, int M, const double* SRa, const double* SRb,
-                const cd* Ta, const cd* Tb, cd* v0, cd* ex0, hipStream_t st);
+                const cd* Ta, const cd* Tb, cd* v0, cd* ex0, int n_cu, hipStream_t st);
 void init_ltl_attributes();
 // exact: both spins have N == nmax and an identity occupied window;
 // prefetch: next vector's LT row loaded ahead into registers (exact shapes).

@@ -19,6 +19,8 @@
 // arrive by direct global-to-LDS loads, double-buffered one vector ahead.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -737,9 +739,14 @@ __global__ __launch_bounds__(64 * QT_WAVES) void k_qtr(int NW, int w0, int WT, i
   if (g0 < g1) load(g0, bcur);
   for (int g = g0; g < g1; g += 2) {
     if (g + 2 < g1) load(g + 2, bnxt);
-    dvec4 d = dvec4{0, 0, 0, 0};
+    // two independent accumulation chains (even and odd k steps)
+    dvec4 d = dvec4{0, 0, 0, 0}, e = dvec4{0, 0, 0, 0};
 #pragma unroll
-    for (int s = 0; s < LF_K / 4; ++s) d = __builtin_amdgcn_mfma_f64_16x16x4f64(bt[s], bcur[s], d, 0, 0, 0);
+    for (int s = 0; s < LF_K / 4; s += 2) {
+      d = __builtin_amdgcn_mfma_f64_16x16x4f64(bt[s], bcur[s], d, 0, 0, 0);
+      e = __builtin_amdgcn_mfma_f64_16x16x4f64(bt[s + 1], bcur[s + 1], e, 0, 0, 0);
+    }
+    d += e;
 #pragma unroll
     for (int r = 0; r < 4; ++r) d_t[(q + 4 * r) * QT_LD + col] = d[r];
     cd x{0.0, 0.0}, dv{0.0, 0.0};
@@ -767,8 +774,13 @@ __global__ __launch_bounds__(64 * QT_WAVES) void k_qtr(int NW, int w0, int WT, i
 }
 
 void launch_qtr(int NW, int w0, int WT, int NG, int M, const double* SRa, const double* SRb,
-                const cd* Ta, const cd* Tb, cd* v0, cd* ex0, hipStream_t st) {
-  const int g_chunk = 16;  // even: vector pairs never straddle chunks
+                const cd* Ta, const cd* Tb, cd* v0, cd* ex0, int n_cu, hipStream_t st) {
+  // about two workgroups per CU in one round; chunks even, so vector pairs
+  // never straddle them
+  const int n_wx = (WT + QT_WAVES - 1) / QT_WAVES;
+  const int n_chunks = std::max(1, std::min((NG + 1) / 2, (2 * n_cu + n_wx) / (2 * n_wx)));
+  int g_chunk = (NG + n_chunks - 1) / n_chunks;
+  g_chunk += g_chunk & 1;
   const dim3 grid((WT + QT_WAVES - 1) / QT_WAVES, (NG + g_chunk - 1) / g_chunk, 2);
   hipLaunchKernelGGL(k_qtr, grid, dim3(64 * QT_WAVES), 0, st, NW, w0, WT, NG, g_chunk, M, SRa,
                      SRb, Ta, Tb, v0, ex0);
