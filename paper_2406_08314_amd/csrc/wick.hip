@@ -1305,11 +1305,42 @@ __device__ __forceinline__ void rp_eval(const CT* sm, int base, const int* idx, 
     y0[n] = sm[base + idx[n]];
     y1[n] = sm[base + idx[K + n]];
   }
-  int q = 0;
+  if constexpr (K >= 4 && sizeof(CT) == sizeof(cd)) {
+    // sum over n < n' of mm (y0_n y1_n' - y0_n' y1_n) = sum_n y0_n z_n with
+    // z = S y1, S antisymmetric (S_nn' = mm for n < n'): K^2 complex MACs
+    // instead of 3 per two-by-two minor.  FP64 only: in FP32 the terms of a
+    // minor are better cancelled before they are weighted.
 #pragma unroll
-  for (int n = 0; n < K; ++n)
+    for (int n = 0; n < K; ++n) {
+      CT z{};
 #pragma unroll
-    for (int np = n + 1; np < K; ++np, ++q) cfma(acc, mm[q], y0[n] * y1[np] - y0[np] * y1[n]);
+      for (int np = 0; np < K; ++np) {
+        if (np == n) continue;
+        const int a = n < np ? n : np, b = n < np ? np : n;
+        const int q = a * (2 * K - a - 1) / 2 + (b - a - 1);  // index of the pair (a, b)
+        if (n < np) cfma(z, mm[q], y1[np]);
+        else cfma(z, -mm[q], y1[np]);
+      }
+      cfma(acc, y0[n], z);
+    }
+  } else {
+    int q = 0;
+#pragma unroll
+    for (int n = 0; n < K; ++n)
+#pragma unroll
+      for (int np = n + 1; np < K; ++np, ++q) {
+        // d = y0_n y1_n' - y0_n' y1_n as one fused chain per component
+        auto re = y0[n].re * y1[np].re;
+        re = fma(-y0[n].im, y1[np].im, re);
+        re = fma(-y0[np].re, y1[n].re, re);
+        re = fma(y0[np].im, y1[n].im, re);
+        auto im = y0[n].re * y1[np].im;
+        im = fma(y0[n].im, y1[np].re, im);
+        im = fma(-y0[np].re, y1[n].im, im);
+        im = fma(-y0[np].im, y1[n].re, im);
+        cfma(acc, mm[q], CT{re, im});
+      }
+  }
 }
 
 // Merged second-order kernel.  Workgroup = (walker, Cholesky range, item
