@@ -216,8 +216,7 @@ typedef struct {
                              (both spins N = 8 with the whole occupied window and at
                              most 64 active virtuals, else as 2), 5 = matrix-core kernel
                              that also forms the Cholesky contraction L^g T itself, so
-                             it never goes through HBM (shapes of 4 with M <= 64 and
-                             n_vir_act + 8 <= 64 in FP64 / 80 in the mixed form, else
+                             it never goes through HBM (shapes of 4 with M <= 64, else
                              as 4).  2-5 need N <= 16                                  */
   int32_t lambda_chunk;   /* Cholesky vectors per intermediates workgroup (1..NG); the
                              fused kernel's workgroup holds four walkers x two spins   */

@@ -600,7 +600,7 @@ int ltl_rows16(const DevSpin& sa, const DevSpin& sb) {
 bool ltl_mfma_fits(const DevSpin& sa, const DevSpin& sb, int M, bool fp32) {
   if (!lambda_mfma_fits(sa, sb) || M > LF_K) return false;
   const int P16 = ltl_rows16(sa, sb);
-  if (P16 > 16 * (fp32 ? 5 : 4)) return false;
+  if (P16 > 64) return false;  // P = 8 + n_vir_act <= M <= 64
   return lf_lds_bytes(P16, fp32 ? 4 : 8) <= 160 * 1024;
 }
 
@@ -642,7 +642,6 @@ void launch_ltl_t(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, 
     LTL_CASE(2)
     LTL_CASE(3)
     LTL_CASE(4)
-    LTL_CASE(5)
     default:
       break;
   }
@@ -791,9 +790,8 @@ void init_ltl_attributes() {
   for (const void* f :
        {(const void*)k_ltl_mfma<double, 1>, (const void*)k_ltl_mfma<double, 2>,
         (const void*)k_ltl_mfma<double, 3>, (const void*)k_ltl_mfma<double, 4>,
-        (const void*)k_ltl_mfma<double, 5>, (const void*)k_ltl_mfma<float, 1>,
-        (const void*)k_ltl_mfma<float, 2>, (const void*)k_ltl_mfma<float, 3>,
-        (const void*)k_ltl_mfma<float, 4>, (const void*)k_ltl_mfma<float, 5>})
+        (const void*)k_ltl_mfma<float, 1>, (const void*)k_ltl_mfma<float, 2>,
+        (const void*)k_ltl_mfma<float, 3>, (const void*)k_ltl_mfma<float, 4>})
     hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
 }
 

@@ -575,6 +575,23 @@ def test_autotune_picks_valid_shapes_and_keeps_results():
         assert np.max(np.abs(out["e_loc"] - ref["e_loc"])) <= tol
 
 
+@pytest.mark.parametrize("nv", [8, 16, 40])
+def test_fused_contraction_row_tiles(nv):
+    """The fused contraction kernel at 1, 2 and 3 tiles of 16 restricted rows
+    (n_vir_act + 8 = 16, 24, 48), with a partly filled group of four walkers:
+    FP64 against the oracle on every walker, the mixed form within 0.1 mHa."""
+    wl = make_workload("fused", M=8 + nv + 2, n_alpha=8, n_beta=8, n_chol=20, n_det=150,
+                       k_max=4, window=(8, nv), c_law="flat", n_walkers=5, seed=500 + nv)
+    s = system_for(wl)
+    out = s.measure(wl.dt)
+    assert s.get_tuning()["lambda_variant"] == 5
+    compare_walkers(wl, out, range(wl.n_walkers), wl.dt)
+    m = system_for(wl, precision="mixed")
+    outm = m.measure(wl.dt)
+    assert m.get_tuning()["lambda_variant"] == 5
+    assert np.max(np.abs(outm["e_loc"] - out["e_loc"])) <= MIXED_E_TOL
+
+
 @pytest.mark.parametrize("variant", [2, 3, 4, 5])
 def test_mixed_lambda_variants_against_fp64(variant):
     """Each single-precision energy-intermediate kernel keeps every walker's
