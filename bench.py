@@ -213,10 +213,23 @@ def main():
             step(s, k)
         ms, wall = timed(s, lambda k: step(s, args.warmup + k), args.steps)
         ms_meas, _ = timed(s, lambda k: s.measure_dev(wl.dt, lo, fb, el), args.steps)
+        ms_prop, _ = timed(s, lambda k: s.propagate_dev(fields[k % n_total].reshape(-1), wl.dt,
+                                                        0.0, 1), args.steps)
+
+        def block(_):  # the paper's block shape: 25 propagation steps + 1 measurement
+            for j in range(25):
+                s.propagate_dev(fields[j % n_total].reshape(-1), wl.dt, 0.0, 1)
+            s.measure_dev(wl.dt, lo, fb, el)
+        ms_block, _ = timed(s, block, 2)
         s.close()
+        extra[precision] = {"propagate_only_ms": round(ms_prop / args.steps, 4),
+                            "block_ms": round(ms_block / 2, 4),
+                            "block_note": "25 msd_propagate_dev steps (QR every step) + 1 "
+                                          "msd_measure_dev"}
         return ms / args.steps, ms_meas / args.steps, wall, e_init
 
     tunings = {}
+    extra = {}
     ms_step, ms_meas, wall, e64 = run_form("fp64")
     value = wl.n_walkers * wl.n_det / (ms_step * 1e-3)
     meas_value = wl.n_walkers * wl.n_det / (ms_meas * 1e-3)
@@ -226,7 +239,8 @@ def main():
              "measure_only_ms": round(mx_meas, 4),
              "speedup_vs_fp64": round(ms_step / mx_step, 3),
              "max_abs_dE_L_mHa": float(np.max(np.abs(emx - e64))) * 1e3,
-             "error_sample": f"all {wl.n_walkers} walkers, one measurement of the initial walkers"}
+             "error_sample": f"all {wl.n_walkers} walkers, one measurement of the initial walkers",
+             **extra["mixed"]}
     # instrumented passes of the same steps: HIP events around every stage
     def stage_pass(precision):
         s = system(True, precision)
@@ -299,6 +313,7 @@ def main():
         "wall_s": round(wall, 3),
         "measure_only": {"value": meas_value, "ms": round(ms_meas, 4),
                          "note": "msd_measure_dev alone (overlap, G, force bias, E_L)"},
+        **extra["fp64"],
         "mixed": mixed,
         "tuning": tunings,
         "stage_timing_note": "stages_ms (average per timed launch group; the LT group runs once "

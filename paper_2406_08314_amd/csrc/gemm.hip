@@ -104,8 +104,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
   const bool m_full = m0 + GB_M <= g.M;
   const bool n_full = n0 + GB_N <= g.N;
 
-  double ra[4], rb[4];
-  auto load = [&](int k0) {
+  auto load = [&](int k0, double* ra, double* rb) __attribute__((always_inline)) {
     const bool k_full = k0 + GB_K <= kend;
     // A
     if (a_vec && m_full && k_full) {
@@ -189,9 +188,10 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = double4_t{0.0, 0.0, 0.0, 0.0};
 
+  // K tiles go global -> registers two tiles ahead of their MFMAs (two
+  // register sets, loop unrolled by two), registers -> LDS double buffer
   int buf = 0;
-  if (kbeg < kend) load(kbeg);
-  for (int k0 = kbeg; k0 < kend; k0 += GB_K) {
+  auto store = [&](const double* ra, const double* rb) __attribute__((always_inline)) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       if (A_KMAJ) As[buf][a_kk + r][a_mm] = ra[r];
@@ -199,8 +199,8 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
       if (B_KMAJ) Bs[buf][b_kk + r][b_nn] = rb[r];
       else Bs[buf][b_kk][b_nn + r] = rb[r];
     }
-    __syncthreads();
-    if (k0 + GB_K < kend) load(k0 + GB_K);  // in flight during the MFMAs below
+  };
+  auto compute = [&]() __attribute__((always_inline)) {
 #pragma unroll
     for (int kk = 0; kk < GB_K; kk += 4) {
       const int kr = kk + (lane >> 4);
@@ -214,6 +214,20 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
       acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
     }
     buf ^= 1;
+  };
+  double ra0[4], rb0[4], ra1[4], rb1[4];
+  if (kbeg < kend) load(kbeg, ra0, rb0);
+  if (kbeg + GB_K < kend) load(kbeg + GB_K, ra1, rb1);
+  for (int k0 = kbeg; k0 < kend; k0 += 2 * GB_K) {
+    store(ra0, rb0);
+    __syncthreads();
+    if (k0 + 2 * GB_K < kend) load(k0 + 2 * GB_K, ra0, rb0);  // in flight for two tiles
+    compute();
+    if (k0 + GB_K >= kend) break;
+    store(ra1, rb1);
+    __syncthreads();
+    if (k0 + 3 * GB_K < kend) load(k0 + 3 * GB_K, ra1, rb1);
+    compute();
   }
 
   // ---- epilogue: register r of lane l holds D[l/16 + 4r][l % 16]
@@ -322,8 +336,7 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs32 g) {
   const bool m_full = m0 + GB_M <= g.M;
   const bool n_full = n0 + GB_N <= g.N;
 
-  float ra[4], rb[4];
-  auto load = [&](int k0) {
+  auto load = [&](int k0, float* ra, float* rb) __attribute__((always_inline)) {
     const bool k_full = k0 + GB_K <= kend;
     if (a_vec && m_full && k_full) {
       const int gm = m0 + a_mm, gk = k0 + a_kk;
@@ -361,9 +374,9 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs32 g) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
 
+  // as the FP64 kernel: two register sets, global loads two tiles ahead
   int buf = 0;
-  if (kbeg < kend) load(kbeg);
-  for (int k0 = kbeg; k0 < kend; k0 += GB_K) {
+  auto store = [&](const float* ra, const float* rb) __attribute__((always_inline)) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       if (A_KMAJ) As[buf][a_kk + r][a_mm] = ra[r];
@@ -371,8 +384,8 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs32 g) {
       if (B_KMAJ) Bs[buf][b_kk + r][b_nn] = rb[r];
       else Bs[buf][b_kk][b_nn + r] = rb[r];
     }
-    __syncthreads();
-    if (k0 + GB_K < kend) load(k0 + GB_K);
+  };
+  auto compute = [&]() __attribute__((always_inline)) {
 #pragma unroll
     for (int kk = 0; kk < GB_K; kk += 4) {
       const int kr = kk + (lane >> 4);
@@ -386,6 +399,20 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs32 g) {
       acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
     }
     buf ^= 1;
+  };
+  float ra0[4], rb0[4], ra1[4], rb1[4];
+  if (kbeg < kend) load(kbeg, ra0, rb0);
+  if (kbeg + GB_K < kend) load(kbeg + GB_K, ra1, rb1);
+  for (int k0 = kbeg; k0 < kend; k0 += 2 * GB_K) {
+    store(ra0, rb0);
+    __syncthreads();
+    if (k0 + 2 * GB_K < kend) load(k0 + 2 * GB_K, ra0, rb0);
+    compute();
+    if (k0 + GB_K >= kend) break;
+    store(ra1, rb1);
+    __syncthreads();
+    if (k0 + 3 * GB_K < kend) load(k0 + 3 * GB_K, ra1, rb1);
+    compute();
   }
 
   // epilogue: register r of lane l holds D[4 (l/16) + r][l % 16]
