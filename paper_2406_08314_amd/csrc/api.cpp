@@ -149,6 +149,7 @@ struct msd_system {
   cf* LT32[2] = {nullptr, nullptr};
   double* LR64[2] = {nullptr, nullptr};     // [NG][N_s][M] reference rows of L (FP64)
   cd* Q64[2] = {nullptr, nullptr};          // [wl][g][N_s x N_s] FP64 Q for the traces
+  cd* czw = nullptr;  // [2][NW][n_lchunks] C . ZW per chunk (fused kernel)
   cf* Lam32[2] = {nullptr, nullptr};
   bool energy_mixed = false;                // mixed energy path usable for this trial
 
@@ -472,7 +473,10 @@ void alloc_energy(msd_system* s) {
     // default: the fused contraction + Lambda kernel where it applies, else the
     // matrix-core LT-tile kernel, else the one-wave kernel
     const bool mfma_ok = s->lambda_exact && msd::lambda_mfma_fits(A, B);
-    const bool fused_ok = s->lambda_exact && (s->energy_mixed ? s->lf_fits32 : s->lf_fits64);
+    int wb_cc = 0;  // the option energy_algo = 3 takes its own fused contraction kernel
+    const bool cc = s->o.energy_algo == 3 && msd::chol_contract_fits(A, B, &wb_cc);
+    const bool fused_ok =
+        s->lambda_exact && !cc && (s->energy_mixed ? s->lf_fits32 : s->lf_fits64);
     const int want = s->tune.lambda_variant ? s->tune.lambda_variant
                      : fused_ok                 ? 5
                      : mfma_ok                  ? 4
@@ -510,10 +514,11 @@ void alloc_energy(msd_system* s) {
         s->LT[sp] = E.get<cd>((size_t)NG * D.P * wt * D.N);
       s->Lam[sp] = E.get<cd>((size_t)wt * NG * D.nv * D.no);
     }
-    s->ZWp[sp] = E.get<cd>((size_t)wt * s->n_lchunks * D.nv * D.no);
+    if (s->lambda_variant != 5) s->ZWp[sp] = E.get<cd>((size_t)wt * s->n_lchunks * D.nv * D.no);
     s->coef2[sp] = E.get<cd>((size_t)NW * D.n_minor);
   }
   s->v0 = E.get<cd>((size_t)2 * NW * NG);
+  if (s->lambda_variant == 5) s->czw = E.get<cd>((size_t)2 * NW * s->n_lchunks);
   s->ex0 = E.get<cd>((size_t)2 * NW * NG);
   s->coefAB = E.get<cd>((size_t)NW * s->dp.n_pair);
   s->epart = E.get<cd>((size_t)NW * std::max(s->n_slots, 1));
@@ -722,8 +727,8 @@ void run_energy_mixed(msd_system* s) {
       const cf* Tb = reinterpret_cast<const cf*>(s->T32[1]);
       if (s->lambda_variant == 5) {
         msd::launch_ltl_mfma32(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, s->M, s->Slf32[0],
-                               s->Slf32[1], Ta, Tb, s->Lam32[0], s->Lam32[1], s->v0, s->ZWp[0],
-                               s->ZWp[1], s->st);
+                               s->Slf32[1], Ta, Tb, s->Lam32[0], s->Lam32[1], s->v0, s->sw[0].C,
+                               s->sw[1].C, s->czw, s->st);
       } else if (s->lambda_variant == 4)
         msd::launch_lambda_mfma32(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, Ta, Tb, s->LT32[0],
                                   s->LT32[1], s->Lam32[0], s->Lam32[1], s->v0, s->ex0,
@@ -758,8 +763,8 @@ void run_energy_mixed(msd_system* s) {
     s->timed(ST_EFINAL, [&] {
       msd::launch_energy_final(A, B, s->NW, w0, wt, s->NG, s->n_lchunks, s->n_slots, s->obar,
                                s->v0, s->ex0, s->ZWp[0], s->ZWp[1], s->sw[0].C, s->sw[1].C,
-                               s->epart, s->onebody, s->onebody + s->NW, s->e0, s->eloc,
-                               s->st);
+                               s->lambda_variant == 5 ? s->czw : nullptr, s->epart, s->onebody,
+                               s->onebody + s->NW, s->e0, s->eloc, s->st);
     });
   }
   s->check_launch("energy");
@@ -823,7 +828,7 @@ void run_energy(msd_system* s) {
         if (s->lambda_variant == 5) {
           msd::launch_ltl_mfma(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, s->M, s->Slf[0],
                                s->Slf[1], s->sw[0].T, s->sw[1].T, s->Lam[0], s->Lam[1], s->v0,
-                               s->ZWp[0], s->ZWp[1], s->st);
+                               s->sw[0].C, s->sw[1].C, s->czw, s->st);
         } else if (s->lambda_variant == 4)
           msd::launch_lambda_mfma(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, s->sw[0].T,
                                   s->sw[1].T, s->LT[0], s->LT[1], s->Lam[0], s->Lam[1], s->v0,
@@ -859,8 +864,8 @@ void run_energy(msd_system* s) {
     s->timed(ST_EFINAL, [&] {
       msd::launch_energy_final(A, B, s->NW, w0, wt, s->NG, s->n_lchunks, s->n_slots, s->obar,
                                s->v0, s->ex0, s->ZWp[0], s->ZWp[1], s->sw[0].C, s->sw[1].C,
-                               s->epart, s->onebody, s->onebody + s->NW, s->e0, s->eloc,
-                               s->st);
+                               s->lambda_variant == 5 ? s->czw : nullptr, s->epart, s->onebody,
+                               s->onebody + s->NW, s->e0, s->eloc, s->st);
     });
   }
   s->check_launch("energy");

@@ -175,15 +175,18 @@ size_t ltl_stage_elems(const DevSpin& sa, const DevSpin& sb);  // 64 * P16 per v
 int ltl_rows16(const DevSpin& sa, const DevSpin& sb);
 void launch_gather_ltl(const double* L, int NG, int M, const DevSpin& D, int P16, double* S64,
                        float* S32, hipStream_t st);
-// v0 of both spins ([2][NW][NG], from launch_qtr) enters ZW = sum_g Xi - v Lam.
+// v0 of both spins ([2][NW][NG], from launch_qtr) enters ZW = sum_g Xi - v Lam;
+// ZW is contracted with the first-order CI matrices Ca/Cb ([w][X]) per chunk
+// of vectors: czw[2][NW][n_chunks] = sum_x C[w][x] ZW_chunk[x] (n_chunks =
+// ceil(NG / g_chunk)), which launch_energy_final sums.
 void launch_ltl_mfma(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
                      int g_chunk, int M, const double* Sa, const double* Sb, const cd* Ta,
-                     const cd* Tb, cd* Lam_a, cd* Lam_b, const cd* v0, cd* ZWpart_a,
-                     cd* ZWpart_b, hipStream_t st);
+                     const cd* Tb, cd* Lam_a, cd* Lam_b, const cd* v0, const cd* Ca,
+                     const cd* Cb, cd* czw, hipStream_t st);
 void launch_ltl_mfma32(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
                        int g_chunk, int M, const float* Sa, const float* Sb, const cf* Ta,
-                       const cf* Tb, cf* Lam_a, cf* Lam_b, const cd* v0, cd* ZWpart_a,
-                       cd* ZWpart_b, hipStream_t st);
+                       const cf* Tb, cf* Lam_a, cf* Lam_b, const cd* v0, const cd* Ca,
+                       const cd* Cb, cd* czw, hipStream_t st);
 // FP64 mean-field traces v0, ex0 ([2][NW][NG]) of Q^g = L^g[R, :] T for the
 // walkers w0 .. w0 + WT - 1 (N = 8 per spin, M <= 64); SRa/SRb are the
 // reference rows of L, k-major [NG][64][8] (launch_gather_ltl with no
@@ -229,11 +232,14 @@ int energy_minor_blocks(const DevSpin& s);
 void launch_energy_minors(const DevSpin& s, int NW, int w0, int WT, int NG, int n_gsplit,
                           const cd* Lam, const cd* coef, cd* partial, int n_slots, int slot0,
                           hipStream_t st);
+// czw (when not null, [2][NW][n_lchunks]) replaces the ZW partials: the
+// first-order term is then the sum of those contracted partials.
 void launch_energy_final(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
                          int n_lchunks, int n_echunks, const cd* obar, const cd* v0,
                          const cd* ex0, const cd* ZWpart_a, const cd* ZWpart_b,
-                         const cd* Ca, const cd* Cb, const cd* epart, const cd* onebody_a,
-                         const cd* onebody_b, double e0, cd* e_loc, hipStream_t st);
+                         const cd* Ca, const cd* Cb, const cd* czw, const cd* epart,
+                         const cd* onebody_a, const cd* onebody_b, double e0, cd* e_loc,
+                         hipStream_t st);
 
 // ---------------------------------------------------------------- propagation
 void launch_vhs_prep(int NW, int NG, const double* x, const cd* xbar, double sqrt_dt,

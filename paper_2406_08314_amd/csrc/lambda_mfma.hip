@@ -296,6 +296,8 @@ void launch_lambda_mfma32(const DevSpin& sa, const DevSpin& sb, int NW, int w0, 
 // times Q), Bi that of the identity; the 16 rows are the real and imaginary
 // parts of the N = 8 columns.  The last line is ZW += Xi - v Lam with
 // Xi = Lam Q; v comes from the trace pass (launch_qtr) before this kernel.
+// ZW itself is not stored: each wave contracts its chunk's ZW with the
+// walker's first-order CI matrix C and writes the scalar.
 // ============================================================================
 
 namespace {
@@ -380,7 +382,8 @@ __global__ __launch_bounds__(64 * LF_WAVES, 2) void k_ltl_mfma(
     int P16, const R* __restrict__ Sa, const R* __restrict__ Sb,
     const typename Mfma<R>::cx_t* __restrict__ Ta, const typename Mfma<R>::cx_t* __restrict__ Tb,
     typename Mfma<R>::cx_t* __restrict__ Lam_a, typename Mfma<R>::cx_t* __restrict__ Lam_b,
-    const cd* __restrict__ v0, cd* __restrict__ ZWa, cd* __restrict__ ZWb) {
+    const cd* __restrict__ v0, const cd* __restrict__ Ca, const cd* __restrict__ Cb,
+    cd* __restrict__ czw) {
   typedef Mfma<R> MF;
   typedef typename MF::cx_t C;
   typedef typename MF::acc_t acc_t;
@@ -402,7 +405,6 @@ __global__ __launch_bounds__(64 * LF_WAVES, 2) void k_ltl_mfma(
   const int* __restrict__ vir = s2 ? sb.vir : sa.vir;
   const C* __restrict__ T = s2 ? Tb : Ta;
   C* __restrict__ Lam = s2 ? Lam_b : Lam_a;
-  cd* __restrict__ ZW = s2 ? ZWb : ZWa;
   const int col = lane & 15, q = lane >> 4;
   const int jc = lf_sig<R>(col);  // logical row of this lane's A-operand row
 
@@ -557,7 +559,11 @@ __global__ __launch_bounds__(64 * LF_WAVES, 2) void k_ltl_mfma(
   }
   if (g0 < g1) store_window(g1 - 1);
   if (!active) return;
-  // ZW partial of this chunk: [wl][chunk][a * 8 + n]
+  // this chunk's ZW contracted with the walker's first-order CI matrix C
+  // (same window layout [a * 8 + n]) in FP64: one partial of sum C . ZW per
+  // (spin, walker, chunk), [2][NW][n_chunks]
+  const cd* __restrict__ Cw = (s2 ? Cb : Ca) + (size_t)w * X;
+  double pr = 0.0, pi = 0.0;
 #pragma unroll
   for (int rt = 0; rt < 4; ++rt) {
     const int a = rt * 16 + col;
@@ -566,11 +572,16 @@ __global__ __launch_bounds__(64 * LF_WAVES, 2) void k_ltl_mfma(
       for (int h = 0; h < 2; ++h) {
         int rre, rim, n;
         lf_pair<R>(q, h, &rre, &rim, &n);
-        ZW[((size_t)wl * n_chunks + chunk) * X + a * LM_N + n] =
-            cd{(double)zw[rt][rre], (double)zw[rt][rim]};
+        const cd c = Cw[a * LM_N + n];
+        const double zr = (double)zw[rt][rre], zi = (double)zw[rt][rim];
+        pr += c.re * zr - c.im * zi;
+        pi += c.re * zi + c.im * zr;
       }
     }
   }
+  pr = wsum(pr);
+  pi = wsum(pi);
+  if (lane == 0) czw[((size_t)s2 * NW + w) * n_chunks + chunk] = cd{pr, pi};
 }
 
 // S[g][k][p] = L^g[row(p), k]: p < nv the active virtual orbitals, then the N
@@ -626,7 +637,8 @@ template <class R>
 void launch_ltl_t(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
                   int g_chunk, int M, const R* Sa, const R* Sb, const typename Mfma<R>::cx_t* Ta,
                   const typename Mfma<R>::cx_t* Tb, typename Mfma<R>::cx_t* Lam_a,
-                  typename Mfma<R>::cx_t* Lam_b, const cd* v0, cd* ZWa, cd* ZWb, hipStream_t st) {
+                  typename Mfma<R>::cx_t* Lam_b, const cd* v0, const cd* Ca, const cd* Cb, cd* czw,
+                  hipStream_t st) {
   const int P16 = ltl_rows16(sa, sb), NT = P16 / 16;
   const int n_chunks = (NG + g_chunk - 1) / g_chunk;
   const int n_wgrp = (WT + LF_WB - 1) / LF_WB;
@@ -635,7 +647,7 @@ void launch_ltl_t(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, 
 #define LTL_CASE(nt)                                                                          \
   case nt:                                                                                    \
     hipLaunchKernelGGL((k_ltl_mfma<R, nt>), grid, block, lds, st, sa, sb, NW, w0, WT, NG,     \
-                       g_chunk, n_chunks, M, P16, Sa, Sb, Ta, Tb, Lam_a, Lam_b, v0, ZWa, ZWb); \
+                       g_chunk, n_chunks, M, P16, Sa, Sb, Ta, Tb, Lam_a, Lam_b, v0, Ca, Cb, czw); \
     break;
   switch (NT) {
     LTL_CASE(1)
@@ -651,18 +663,18 @@ void launch_ltl_t(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, 
 
 void launch_ltl_mfma(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
                      int g_chunk, int M, const double* Sa, const double* Sb, const cd* Ta,
-                     const cd* Tb, cd* Lam_a, cd* Lam_b, const cd* v0, cd* ZWpart_a,
-                     cd* ZWpart_b, hipStream_t st) {
-  launch_ltl_t<double>(sa, sb, NW, w0, WT, NG, g_chunk, M, Sa, Sb, Ta, Tb, Lam_a, Lam_b, v0,
-                       ZWpart_a, ZWpart_b, st);
+                     const cd* Tb, cd* Lam_a, cd* Lam_b, const cd* v0, const cd* Ca,
+                     const cd* Cb, cd* czw, hipStream_t st) {
+  launch_ltl_t<double>(sa, sb, NW, w0, WT, NG, g_chunk, M, Sa, Sb, Ta, Tb, Lam_a, Lam_b, v0, Ca,
+                       Cb, czw, st);
 }
 
 void launch_ltl_mfma32(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
                        int g_chunk, int M, const float* Sa, const float* Sb, const cf* Ta,
-                       const cf* Tb, cf* Lam_a, cf* Lam_b, const cd* v0, cd* ZWpart_a,
-                       cd* ZWpart_b, hipStream_t st) {
-  launch_ltl_t<float>(sa, sb, NW, w0, WT, NG, g_chunk, M, Sa, Sb, Ta, Tb, Lam_a, Lam_b, v0,
-                      ZWpart_a, ZWpart_b, st);
+                       const cf* Tb, cf* Lam_a, cf* Lam_b, const cd* v0, const cd* Ca,
+                       const cd* Cb, cd* czw, hipStream_t st) {
+  launch_ltl_t<float>(sa, sb, NW, w0, WT, NG, g_chunk, M, Sa, Sb, Ta, Tb, Lam_a, Lam_b, v0, Ca,
+                      Cb, czw, st);
 }
 
 // ============================================================================

@@ -1588,6 +1588,7 @@ __global__ __launch_bounds__(256) void k_energy_final(DevSpin sa, DevSpin sb, in
                                                       const cd* __restrict__ ZWb,
                                                       const cd* __restrict__ Ca,
                                                       const cd* __restrict__ Cb,
+                                                      const cd* __restrict__ czw_part,
                                                       const cd* __restrict__ epart,
                                                       const cd* __restrict__ oba,
                                                       const cd* __restrict__ obb, double e0,
@@ -1609,12 +1610,17 @@ __global__ __launch_bounds__(256) void k_energy_final(DevSpin sa, DevSpin sb, in
   const DevSpin* sp[2] = {&sa, &sb};
   const cd* ZW[2] = {ZWa, ZWb};
   const cd* C[2] = {Ca, Cb};
-  for (int s2 = 0; s2 < 2; ++s2) {
-    const int X = sp[s2]->nv * sp[s2]->no;
-    for (int e = tid; e < X; e += bd) {
-      cd z{0.0, 0.0};
-      for (int c = 0; c < n_lchunks; ++c) z += ZW[s2][((size_t)wl * n_lchunks + c) * X + e];
-      czw += C[s2][(size_t)w * X + e] * z;
+  if (czw_part) {  // already contracted with C per (spin, walker, chunk)
+    for (int c = tid; c < 2 * n_lchunks; c += bd)
+      czw += czw_part[((size_t)(c / n_lchunks) * NW + w) * n_lchunks + c % n_lchunks];
+  } else {
+    for (int s2 = 0; s2 < 2; ++s2) {
+      const int X = sp[s2]->nv * sp[s2]->no;
+      for (int e = tid; e < X; e += bd) {
+        cd z{0.0, 0.0};
+        for (int c = 0; c < n_lchunks; ++c) z += ZW[s2][((size_t)wl * n_lchunks + c) * X + e];
+        czw += C[s2][(size_t)w * X + e] * z;
+      }
     }
   }
   for (int c = tid; c < n_echunks; c += bd) czw += epart[(size_t)w * n_echunks + c];  // slots
@@ -1625,11 +1631,11 @@ __global__ __launch_bounds__(256) void k_energy_final(DevSpin sa, DevSpin sb, in
 void launch_energy_final(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
                          int n_lchunks, int n_echunks, const cd* obar, const cd* v0,
                          const cd* ex0, const cd* ZWpart_a, const cd* ZWpart_b, const cd* Ca,
-                         const cd* Cb, const cd* epart, const cd* onebody_a,
+                         const cd* Cb, const cd* czw, const cd* epart, const cd* onebody_a,
                          const cd* onebody_b, double e0, cd* e_loc, hipStream_t st) {
   hipLaunchKernelGGL(k_energy_final, dim3(WT), dim3(256), 0, st, sa, sb, NW, w0, NG, n_lchunks,
-                     n_echunks, obar, v0, ex0, ZWpart_a, ZWpart_b, Ca, Cb, epart, onebody_a,
-                     onebody_b, e0, e_loc);
+                     n_echunks, obar, v0, ex0, ZWpart_a, ZWpart_b, Ca, Cb, czw, epart,
+                     onebody_a, onebody_b, e0, e_loc);
 }
 
 // out[g][r][q] = L[g][rows[r]][q]: Cholesky rows restricted to an orbital subset
