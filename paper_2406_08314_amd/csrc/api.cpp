@@ -150,6 +150,7 @@ struct msd_system {
   double* LR64[2] = {nullptr, nullptr};     // [NG][N_s][M] reference rows of L (FP64)
   cd* Q64[2] = {nullptr, nullptr};          // [wl][g][N_s x N_s] FP64 Q for the traces
   cd* czw = nullptr;  // [2][NW][n_lchunks] C . ZW per chunk (fused kernel)
+  bool lam_swz = false;  // Lambda windows in the lam_swizzle layout (fused path)
   cf* Lam32[2] = {nullptr, nullptr};
   bool energy_mixed = false;                // mixed energy path usable for this trial
 
@@ -499,6 +500,10 @@ void alloc_energy(msd_system* s) {
     s->gl_chunk = std::min(32, NG);
   }
   s->n_lchunks = (NG + s->gl_chunk - 1) / s->gl_chunk;
+  // only the row-pair / pair second-order kernel reads the windows then (the
+  // minor-list form indexes them unswizzled)
+  s->lam_swz = s->lambda_variant == 5 && s->use_strings[0] && s->use_strings[1] &&
+               A.no == 8 && B.no == 8;
   s->n_slots = slot;  // every slot is written by exactly one workgroup
   Arena& E = s->energy_mem;
   for (int sp = 0; sp < 2; ++sp) {
@@ -728,7 +733,7 @@ void run_energy_mixed(msd_system* s) {
       if (s->lambda_variant == 5) {
         msd::launch_ltl_mfma32(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, s->M, s->Slf32[0],
                                s->Slf32[1], Ta, Tb, s->Lam32[0], s->Lam32[1], s->v0, s->sw[0].C,
-                               s->sw[1].C, s->czw, s->st);
+                               s->sw[1].C, s->czw, s->lam_swz, s->st);
       } else if (s->lambda_variant == 4)
         msd::launch_lambda_mfma32(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, Ta, Tb, s->LT32[0],
                                   s->LT32[1], s->Lam32[0], s->Lam32[1], s->v0, s->ex0,
@@ -755,7 +760,7 @@ void run_energy_mixed(msd_system* s) {
     s->timed(ST_EGAMMA, [&] {
       msd::launch_energy_second32(A, B, s->dp, s->plan, s->n_itemblocks, s->second_waves, s->NW,
                                   w0, wt, s->NG, s->gsplit, s->second_G, s->second_maxk,
-                                  s->second_flat, s->second_dma,
+                                  s->second_flat, s->second_dma, s->lam_swz,
                                   s->Lam32[0],
                                   s->Lam32[1], s->coefAB, s->sw[0].m2, s->sw[1].m2, s->sw[0].B,
                                   s->sw[1].B, s->epart, s->n_slots, s->slot_second, s->st);
@@ -828,7 +833,7 @@ void run_energy(msd_system* s) {
         if (s->lambda_variant == 5) {
           msd::launch_ltl_mfma(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, s->M, s->Slf[0],
                                s->Slf[1], s->sw[0].T, s->sw[1].T, s->Lam[0], s->Lam[1], s->v0,
-                               s->sw[0].C, s->sw[1].C, s->czw, s->st);
+                               s->sw[0].C, s->sw[1].C, s->czw, s->lam_swz, s->st);
         } else if (s->lambda_variant == 4)
           msd::launch_lambda_mfma(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, s->sw[0].T,
                                   s->sw[1].T, s->LT[0], s->LT[1], s->Lam[0], s->Lam[1], s->v0,
@@ -850,7 +855,7 @@ void run_energy(msd_system* s) {
     s->timed(ST_EGAMMA, [&] {
       msd::launch_energy_second(A, B, s->dp, s->plan, s->n_itemblocks, s->second_waves, s->NW, w0,
                                 wt, s->NG, s->gsplit, s->second_G, s->second_maxk,
-                                s->second_flat, s->second_dma, s->Lam[0],
+                                s->second_flat, s->second_dma, s->lam_swz, s->Lam[0],
                                 s->Lam[1],
                                 s->coefAB, s->sw[0].m2, s->sw[1].m2, s->sw[0].B, s->sw[1].B,
                                 s->epart, s->n_slots, s->slot_second, s->st);

@@ -50,6 +50,12 @@ void launch_gemm32(const GemmArgs32& g, hipStream_t st);
 // Element-wise precision conversions (n elements).
 void launch_f64_to_f32(const double* src, float* dst, int64_t n, hipStream_t st);
 
+// Window layout of Lambda with eight hole slots, as written by the fused
+// contraction kernel when the second-order terms read it (swz): entry
+// (a, i) at a * 8 + (i ^ ((a >> 1) & 7)), which spreads a wave's gathers of
+// one hole slot over the LDS banks.  Maps an unswizzled index a * 8 + i.
+__host__ __device__ inline int lam_swizzle(int x) { return (x & ~7) | ((x & 7) ^ ((x >> 4) & 7)); }
+
 // ---------------------------------------------------------------- device tables
 struct DevSpin {
   int N = 0, U = 0, nv = 0, no = 0, P = 0;  // P = N + nv (rows R then V_act)
@@ -179,14 +185,15 @@ void launch_gather_ltl(const double* L, int NG, int M, const DevSpin& D, int P16
 // ZW is contracted with the first-order CI matrices Ca/Cb ([w][X]) per chunk
 // of vectors: czw[2][NW][n_chunks] = sum_x C[w][x] ZW_chunk[x] (n_chunks =
 // ceil(NG / g_chunk)), which launch_energy_final sums.
+// swz: store the Lambda windows in the lam_swizzle layout.
 void launch_ltl_mfma(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
                      int g_chunk, int M, const double* Sa, const double* Sb, const cd* Ta,
                      const cd* Tb, cd* Lam_a, cd* Lam_b, const cd* v0, const cd* Ca,
-                     const cd* Cb, cd* czw, hipStream_t st);
+                     const cd* Cb, cd* czw, bool swz, hipStream_t st);
 void launch_ltl_mfma32(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
                        int g_chunk, int M, const float* Sa, const float* Sb, const cf* Ta,
                        const cf* Tb, cf* Lam_a, cf* Lam_b, const cd* v0, const cd* Ca,
-                       const cd* Cb, cd* czw, hipStream_t st);
+                       const cd* Cb, cd* czw, bool swz, hipStream_t st);
 // FP64 mean-field traces v0, ex0 ([2][NW][NG]) of Q^g = L^g[R, :] T for the
 // walkers w0 .. w0 + WT - 1 (N = 8 per spin, M <= 64); SRa/SRb are the
 // reference rows of L, k-major [NG][64][8] (launch_gather_ltl with no
@@ -217,7 +224,7 @@ constexpr int ER_PAIRS_PER_WAVE = 256;  // 64 lanes x 4 pairs
 void launch_energy_second(const DevSpin& sa, const DevSpin& sb, const DevPairs& pr,
                           const int4* plan, int n_itemblocks, int waves_per_block, int NW, int w0,
                           int WT, int NG, int n_gsplit, int G, int max_order, bool flat_gather,
-                          bool use_dma, const cd* Lam_a, const cd* Lam_b, const cd* coef,
+                          bool use_dma, bool swz, const cd* Lam_a, const cd* Lam_b, const cd* coef,
                           const cd* m2a, const cd* m2b, const cd* Ba, const cd* Bb, cd* partial,
                           int n_slots, int slot0, hipStream_t st);
 // Same with single-precision Lambda (mixed form); the minors, CI weights and
@@ -225,7 +232,7 @@ void launch_energy_second(const DevSpin& sa, const DevSpin& sb, const DevPairs& 
 void launch_energy_second32(const DevSpin& sa, const DevSpin& sb, const DevPairs& pr,
                             const int4* plan, int n_itemblocks, int waves_per_block, int NW,
                             int w0, int WT, int NG, int n_gsplit, int G, int max_order,
-                            bool flat_gather, bool use_dma, const cf* Lam_a, const cf* Lam_b,
+                            bool flat_gather, bool use_dma, bool swz, const cf* Lam_a, const cf* Lam_b,
                             const cd* coef, const cd* m2a, const cd* m2b, const cd* Ba,
                             const cd* Bb, cd* partial, int n_slots, int slot0, hipStream_t st);
 int energy_minor_blocks(const DevSpin& s);

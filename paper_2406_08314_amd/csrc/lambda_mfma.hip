@@ -383,7 +383,7 @@ __global__ __launch_bounds__(64 * LF_WAVES, 2) void k_ltl_mfma(
     const typename Mfma<R>::cx_t* __restrict__ Ta, const typename Mfma<R>::cx_t* __restrict__ Tb,
     typename Mfma<R>::cx_t* __restrict__ Lam_a, typename Mfma<R>::cx_t* __restrict__ Lam_b,
     const cd* __restrict__ v0, const cd* __restrict__ Ca, const cd* __restrict__ Cb,
-    cd* __restrict__ czw) {
+    cd* __restrict__ czw, bool swz) {
   typedef Mfma<R> MF;
   typedef typename MF::cx_t C;
   typedef typename MF::acc_t acc_t;
@@ -470,7 +470,7 @@ __global__ __launch_bounds__(64 * LF_WAVES, 2) void k_ltl_mfma(
         for (int h = 0; h < 2; ++h) {
           int rre, rim, n;
           lf_pair<R>(q, h, &rre, &rim, &n);
-          lo[a * LM_N + n] = C{lam_prev[rt][rre], lam_prev[rt][rim]};
+          lo[a * LM_N + (swz ? n ^ ((a >> 1) & 7) : n)] = C{lam_prev[rt][rre], lam_prev[rt][rim]};
         }
       }
     }
@@ -638,7 +638,7 @@ void launch_ltl_t(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, 
                   int g_chunk, int M, const R* Sa, const R* Sb, const typename Mfma<R>::cx_t* Ta,
                   const typename Mfma<R>::cx_t* Tb, typename Mfma<R>::cx_t* Lam_a,
                   typename Mfma<R>::cx_t* Lam_b, const cd* v0, const cd* Ca, const cd* Cb, cd* czw,
-                  hipStream_t st) {
+                  bool swz, hipStream_t st) {
   const int P16 = ltl_rows16(sa, sb), NT = P16 / 16;
   const int n_chunks = (NG + g_chunk - 1) / g_chunk;
   const int n_wgrp = (WT + LF_WB - 1) / LF_WB;
@@ -647,7 +647,7 @@ void launch_ltl_t(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, 
 #define LTL_CASE(nt)                                                                          \
   case nt:                                                                                    \
     hipLaunchKernelGGL((k_ltl_mfma<R, nt>), grid, block, lds, st, sa, sb, NW, w0, WT, NG,     \
-                       g_chunk, n_chunks, M, P16, Sa, Sb, Ta, Tb, Lam_a, Lam_b, v0, Ca, Cb, czw); \
+                       g_chunk, n_chunks, M, P16, Sa, Sb, Ta, Tb, Lam_a, Lam_b, v0, Ca, Cb, czw, swz); \
     break;
   switch (NT) {
     LTL_CASE(1)
@@ -664,17 +664,17 @@ void launch_ltl_t(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, 
 void launch_ltl_mfma(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
                      int g_chunk, int M, const double* Sa, const double* Sb, const cd* Ta,
                      const cd* Tb, cd* Lam_a, cd* Lam_b, const cd* v0, const cd* Ca,
-                     const cd* Cb, cd* czw, hipStream_t st) {
+                     const cd* Cb, cd* czw, bool swz, hipStream_t st) {
   launch_ltl_t<double>(sa, sb, NW, w0, WT, NG, g_chunk, M, Sa, Sb, Ta, Tb, Lam_a, Lam_b, v0, Ca,
-                       Cb, czw, st);
+                       Cb, czw, swz, st);
 }
 
 void launch_ltl_mfma32(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
                        int g_chunk, int M, const float* Sa, const float* Sb, const cf* Ta,
                        const cf* Tb, cf* Lam_a, cf* Lam_b, const cd* v0, const cd* Ca,
-                       const cd* Cb, cd* czw, hipStream_t st) {
+                       const cd* Cb, cd* czw, bool swz, hipStream_t st) {
   launch_ltl_t<float>(sa, sb, NW, w0, WT, NG, g_chunk, M, Sa, Sb, Ta, Tb, Lam_a, Lam_b, v0, Ca,
-                      Cb, czw, st);
+                      Cb, czw, swz, st);
 }
 
 // ============================================================================

@@ -1368,7 +1368,7 @@ __global__ __launch_bounds__((MAXK <= 4 ? 1024 : 512)) void k_energy_second(
     int waves_per_block, int NW, int w0, int NG, int n_gsplit, int G, const CT* __restrict__ Lam_a,
     const CT* __restrict__ Lam_b, const cd* __restrict__ coef, const cd* __restrict__ m2a,
     const cd* __restrict__ m2b, const cd* __restrict__ Ba, const cd* __restrict__ Bb,
-    cd* __restrict__ partial, int n_slots, int slot0, bool lds_dma) {
+    cd* __restrict__ partial, int n_slots, int slot0, bool lds_dma, bool swz) {
   constexpr int NIDX = 2 * MAXK > 2 * ER_PPL ? 2 * MAXK : 2 * ER_PPL;
   constexpr int NMM = MAXK * (MAXK - 1) / 2;
   extern __shared__ __align__(16) unsigned char sm_raw[];
@@ -1427,6 +1427,13 @@ __global__ __launch_bounds__((MAXK <= 4 ? 1024 : 512)) void k_energy_second(
         case 5: if constexpr (MAXK >= 5) rp_setup<5 <= MAXK ? 5 : 2, CT>(hwin, pwin, no, str, rp, m2s, idx, mm); break;
         default: if constexpr (MAXK >= 6) rp_setup<6 <= MAXK ? 6 : 2, CT>(hwin, pwin, no, str, rp, m2s, idx, mm); break;
       }
+    }
+    // windows stored with the hole slot of particle row a XOR-ed with
+    // (a >> 1) & 7 (eight hole slots): spreads a wave's gathers over the LDS
+    // banks
+    if (swz) {
+#pragma unroll
+      for (int j = 0; j < NIDX; ++j) idx[j] = lam_swizzle(idx[j]);
     }
   }
   // stage buffer b (0/1) starts at sm[b * G * X]: [alpha G x Xa][beta G x Xb].
@@ -1517,7 +1524,7 @@ template <class CT>
 static void launch_energy_second_t(const DevSpin& sa, const DevSpin& sb, const DevPairs& pr,
                                    const int4* plan, int n_itemblocks, int waves_per_block, int NW,
                                    int w0, int WT, int NG, int n_gsplit, int G, int max_order,
-                                   bool flat_gather, bool use_dma, const CT* Lam_a, const CT* Lam_b, const cd* coef,
+                                   bool flat_gather, bool use_dma, bool swz, const CT* Lam_a, const CT* Lam_b, const cd* coef,
                                    const cd* m2a, const cd* m2b, const cd* Ba, const cd* Bb,
                                    cd* partial, int n_slots, int slot0, hipStream_t st) {
   if (n_itemblocks == 0) return;
@@ -1526,7 +1533,7 @@ static void launch_energy_second_t(const DevSpin& sa, const DevSpin& sb, const D
 #define MSD_ES(MK, FL)                                                                       \
   hipLaunchKernelGGL((k_energy_second<CT, MK, FL>), grid, block, lds, st, sa, sb, pr, plan,   \
                      n_itemblocks, waves_per_block, NW, w0, NG, n_gsplit, G, Lam_a, Lam_b, coef, \
-                     m2a, m2b, Ba, Bb, partial, n_slots, slot0, lds_dma)
+                     m2a, m2b, Ba, Bb, partial, n_slots, slot0, lds_dma, swz)
   // direct LDS loads need 16-byte aligned runs: every Lambda row of both spins
   // (and each spin's stage region) starts on a 16-byte boundary
   const int per = 16 / (int)sizeof(CT);
@@ -1542,22 +1549,22 @@ static void launch_energy_second_t(const DevSpin& sa, const DevSpin& sb, const D
 void launch_energy_second(const DevSpin& sa, const DevSpin& sb, const DevPairs& pr,
                           const int4* plan, int n_itemblocks, int waves_per_block, int NW, int w0,
                           int WT, int NG, int n_gsplit, int G, int max_order, bool flat_gather,
-                          bool use_dma, const cd* Lam_a, const cd* Lam_b, const cd* coef,
+                          bool use_dma, bool swz, const cd* Lam_a, const cd* Lam_b, const cd* coef,
                           const cd* m2a, const cd* m2b, const cd* Ba, const cd* Bb, cd* partial,
                           int n_slots, int slot0, hipStream_t st) {
   launch_energy_second_t<cd>(sa, sb, pr, plan, n_itemblocks, waves_per_block, NW, w0, WT, NG,
-                             n_gsplit, G, max_order, flat_gather, use_dma, Lam_a, Lam_b, coef, m2a, m2b, Ba, Bb,
+                             n_gsplit, G, max_order, flat_gather, use_dma, swz, Lam_a, Lam_b, coef, m2a, m2b, Ba, Bb,
                              partial, n_slots, slot0, st);
 }
 
 void launch_energy_second32(const DevSpin& sa, const DevSpin& sb, const DevPairs& pr,
                             const int4* plan, int n_itemblocks, int waves_per_block, int NW,
                             int w0, int WT, int NG, int n_gsplit, int G, int max_order,
-                            bool flat_gather, bool use_dma, const cf* Lam_a, const cf* Lam_b,
+                            bool flat_gather, bool use_dma, bool swz, const cf* Lam_a, const cf* Lam_b,
                             const cd* coef, const cd* m2a, const cd* m2b, const cd* Ba,
                             const cd* Bb, cd* partial, int n_slots, int slot0, hipStream_t st) {
   launch_energy_second_t<cf>(sa, sb, pr, plan, n_itemblocks, waves_per_block, NW, w0, WT, NG,
-                             n_gsplit, G, max_order, flat_gather, use_dma, Lam_a, Lam_b, coef, m2a, m2b, Ba, Bb,
+                             n_gsplit, G, max_order, flat_gather, use_dma, swz, Lam_a, Lam_b, coef, m2a, m2b, Ba, Bb,
                              partial, n_slots, slot0, st);
 }
 
