@@ -321,14 +321,6 @@ __device__ __forceinline__ void lf_bar_all() {
   __builtin_amdgcn_s_barrier();
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
-// LDS operations of the wave done, then the workgroup barrier (loads to LDS
-// still in flight stay in flight)
-__device__ __forceinline__ void lf_bar_lds() {
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  __builtin_amdgcn_s_waitcnt(LF_WAIT_LGKM);
-  __builtin_amdgcn_s_barrier();
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-}
 // LDS writes of this wave visible to its own later reads
 __device__ __forceinline__ void lf_wave_lds() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -366,13 +358,6 @@ __device__ __forceinline__ void lf_pair(int q, int h, int* rre, int* rim, int* n
   }
 }
 
-template <class R>
-__device__ __forceinline__ R lf_sum8(R v) {  // over lanes of a group of 8
-  v += __shfl_xor(v, 1, 64);
-  v += __shfl_xor(v, 2, 64);
-  v += __shfl_xor(v, 4, 64);
-  return v;
-}
 
 }  // namespace
 

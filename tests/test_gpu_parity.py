@@ -575,12 +575,14 @@ def test_autotune_picks_valid_shapes_and_keeps_results():
         assert np.max(np.abs(out["e_loc"] - ref["e_loc"])) <= tol
 
 
-@pytest.mark.parametrize("nv", [8, 16, 40])
-def test_fused_contraction_row_tiles(nv):
+@pytest.mark.parametrize("nv,n_chol", [(8, 20), (16, 21), (40, 20)])
+def test_fused_contraction_row_tiles(nv, n_chol):
     """The fused contraction kernel at 1, 2 and 3 tiles of 16 restricted rows
-    (n_vir_act + 8 = 16, 24, 48), with a partly filled group of four walkers:
-    FP64 against the oracle on every walker, the mixed form within 0.1 mHa."""
-    wl = make_workload("fused", M=8 + nv + 2, n_alpha=8, n_beta=8, n_chol=20, n_det=150,
+    (n_vir_act + 8 = 16, 24, 48), with a partly filled group of four walkers
+    and an odd number of Cholesky vectors (the trace pass takes them in
+    pairs): FP64 against the oracle on every walker, the mixed form within
+    0.1 mHa."""
+    wl = make_workload("fused", M=8 + nv + 2, n_alpha=8, n_beta=8, n_chol=n_chol, n_det=150,
                        k_max=4, window=(8, nv), c_law="flat", n_walkers=5, seed=500 + nv)
     s = system_for(wl)
     out = s.measure(wl.dt)
