@@ -353,6 +353,26 @@ std::string build_trial(int M, int na, int nb, int64_t n_det, const double* ci,
     for (int pass = 0; pass < 2; ++pass) {
       std::vector<int64_t> fill;
       if (pass == 1) {
+        // pairs in (x, y) order: lanes of the second-order kernel then gather
+        // neighbouring (often equal) alpha entries, fewer LDS bank conflicts
+        const int np = (int)cnt.size();
+        std::vector<int> order(np), rank(np);
+        for (int q = 0; q < np; ++q) order[q] = q;
+        std::sort(order.begin(), order.end(), [&](int a, int b) {
+          return t.pr_x[a] != t.pr_x[b] ? t.pr_x[a] < t.pr_x[b] : t.pr_y[a] < t.pr_y[b];
+        });
+        std::vector<int> px(np), py(np);
+        std::vector<int64_t> pc(np);
+        for (int q = 0; q < np; ++q) {
+          rank[order[q]] = q;
+          px[q] = t.pr_x[order[q]];
+          py[q] = t.pr_y[order[q]];
+          pc[q] = cnt[order[q]];
+        }
+        t.pr_x.swap(px);
+        t.pr_y.swap(py);
+        cnt.swap(pc);
+        for (auto& kv : pid) kv.second = rank[kv.second];
         t.n_pair = (int)cnt.size();
         t.pr_ptr.assign(t.n_pair + 1, 0);
         for (int q = 0; q < t.n_pair; ++q) t.pr_ptr[q + 1] = t.pr_ptr[q] + cnt[q];
