@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 import scipy.linalg
 
-from oracle import fock, msd, propagate
+from oracle import driver, fock, msd, propagate
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -447,3 +447,142 @@ def test_step_overlap_bookkeeping():
     # frozen walker unchanged
     np.testing.assert_array_equal(na_[1], pa[1])
     assert w2[1] == 0.0
+
+
+# ----------------------------------------------------------------------------
+# block driver: comb population control (Sec. III.B, Listing 1; the comb is
+# the reading taken where the paper names no algorithm)
+# ----------------------------------------------------------------------------
+
+def _comb_brute(w, z):
+    """Tooth k at (k + z) W / n goes to the first walker whose running sum
+    passes it, found by walking the list (no library search)."""
+    n, total = len(w), sum(w)
+    out = []
+    for k in range(n):
+        t = (k + z) * total / n
+        run, pick = 0.0, None
+        for i, wi in enumerate(w):
+            if run <= t < run + wi:
+                pick = i
+                break
+            run += wi
+        out.append(pick)
+    return out
+
+
+def test_comb_equal_weights_is_identity():
+    for n in (1, 2, 7, 64):
+        for z in (0.0, 0.25, 0.999):
+            parent, wn = driver.comb(np.full(n, 1.5), z)
+            np.testing.assert_array_equal(parent, np.arange(n))
+            assert wn == 1.5
+
+
+def test_comb_copy_counts_and_total_weight():
+    rng = np.random.default_rng(71)
+    for n in (3, 10, 57):
+        w = rng.exponential(size=n)
+        w[rng.random(n) < 0.2] = 0.0
+        w[0] = 0.7  # at least one live walker
+        for z in rng.random(5):
+            parent, wn = driver.comb(w, z)
+            cnt = np.bincount(parent, minlength=n)
+            exp = n * w / w.sum()
+            assert cnt.sum() == n
+            assert np.all(cnt >= np.floor(exp) - 1e-9) and np.all(cnt <= np.ceil(exp) + 1e-9)
+            assert np.all(cnt[w == 0.0] == 0)
+            assert np.all(np.diff(parent) >= 0)
+            assert abs(wn * n - w.sum()) < 1e-12 * w.sum()
+
+
+def test_comb_unbiased_over_offsets():
+    """Averaged over a midpoint grid of J offsets, walker i is copied
+    n w_i / W times to within 1/J (exactly, for uniform z)."""
+    w = np.array([0.3, 0.0, 2.2, 0.9, 0.05, 1.1, 0.0, 0.45])
+    n, J = len(w), 2048
+    mean = np.zeros(n)
+    for j in range(J):
+        parent, _ = driver.comb(w, (j + 0.5) / J)
+        mean += np.bincount(parent, minlength=n)
+    mean /= J
+    np.testing.assert_allclose(mean, n * w / w.sum(), atol=1.0 / J)
+
+
+def test_comb_brute_force_small():
+    rng = np.random.default_rng(72)
+    for _ in range(200):
+        n = int(rng.integers(1, 9))
+        # dyadic weights: every running sum is exact, so ties are real ties
+        w = rng.integers(0, 5, size=n) / 4.0
+        if w.sum() == 0:
+            w[-1] = 0.25
+        z = rng.integers(0, 8) / 8.0
+        parent, _ = driver.comb(w, z)
+        assert list(parent) == _comb_brute(list(w), z)
+
+
+def test_comb_zero_weight_not_copied_at_ties():
+    # teeth at 0 and W/2 land exactly on the empty interval of walker 0
+    parent, wn = driver.comb(np.array([0.0, 1.0]), 0.0)
+    assert list(parent) == [1, 1] and wn == 0.5
+    parent, _ = driver.comb(np.array([1.0, 0.0, 1.0, 0.0]), 0.0)
+    assert list(parent) == [0, 0, 2, 2]
+
+
+def test_comb_all_frozen_changes_nothing():
+    parent, wn = driver.comb(np.zeros(4), 0.3)
+    assert wn is None and list(parent) == [0, 1, 2, 3]
+
+
+def test_block_without_population_control_is_steps_plus_measure():
+    rng = np.random.default_rng(73)
+    M, na, nb, ng, nw = 6, 2, 2, 4, 3
+    h1 = rand_sym(rng, 1, M)[0]
+    chol = rand_sym(rng, ng, M, 0.3)
+    ci, oa, ob = rand_trial(rng, M, na, nb, 5)
+    pa = np.stack([rand_walker(rng, M, na) for _ in range(nw)])
+    pb = np.stack([rand_walker(rng, M, nb) for _ in range(nw)])
+    lo = np.array([np.log(msd.trial_overlap(ci, oa, ob, pa[w], pb[w])) for w in range(nw)])
+    wts = np.array([1.0, 0.5, 2.0])
+    x = rng.standard_normal((3, nw, ng))
+    out = driver.block(h1, chol, 0.4, ci, oa, ob, pa, pb, wts, lo, x, 0.01, [],
+                       stabilize_freq=2, pop_freq=0, steps_before=1)
+    ra, rb, rw, rl = pa, pb, wts, lo
+    for s in range(3):
+        ra, rb, rw, rl, _ = propagate.step(h1, chol, ci, oa, ob, ra, rb, rw, rl, x[s], 0.01,
+                                           do_qr=(s + 2) % 2 == 0)
+    np.testing.assert_array_equal(out[0], ra)
+    np.testing.assert_array_equal(out[2], rw)
+    el = msd.measure(h1, chol, 0.4, ci, oa, ob, ra, rb, 0.01)["e_loc"]
+    np.testing.assert_array_equal(out[4], el)
+    assert abs(out[5] - np.sum(rw * el)) == 0 and out[6] == np.sum(rw)
+
+
+def test_block_population_control_copies_whole_walkers():
+    """After a combed block every walker is a copy of one propagated walker
+    (orbitals, overlap together) and the weights are equal."""
+    rng = np.random.default_rng(74)
+    M, na, nb, ng, nw = 6, 2, 2, 4, 5
+    h1 = rand_sym(rng, 1, M)[0]
+    chol = rand_sym(rng, ng, M, 0.3)
+    ci, oa, ob = rand_trial(rng, M, na, nb, 5)
+    pa = np.stack([rand_walker(rng, M, na) for _ in range(nw)])
+    pb = np.stack([rand_walker(rng, M, nb) for _ in range(nw)])
+    lo = np.array([np.log(msd.trial_overlap(ci, oa, ob, pa[w], pb[w])) for w in range(nw)])
+    wts = np.array([1.0, 0.2, 3.0, 0.0, 0.8])
+    x = rng.standard_normal((2, nw, ng))
+    out = driver.block(h1, chol, 0.0, ci, oa, ob, pa, pb, wts, lo, x, 0.01, [0.37],
+                       stabilize_freq=0, pop_freq=2)
+    ra, rb, rw, rl = pa, pb, wts, lo
+    for s in range(2):
+        ra, rb, rw, rl, _ = propagate.step(h1, chol, ci, oa, ob, ra, rb, rw, rl, x[s], 0.01)
+    parent, wn = driver.comb(rw, 0.37)
+    assert 3 not in parent  # the frozen walker is dropped
+    np.testing.assert_array_equal(out[0], ra[parent])
+    np.testing.assert_array_equal(out[1], rb[parent])
+    np.testing.assert_array_equal(out[3], rl[parent])
+    np.testing.assert_allclose(out[2], np.full(nw, rw.sum() / nw), rtol=0, atol=0)
+    for w in range(nw):
+        assert abs(np.exp(np.log(msd.trial_overlap(ci, oa, ob, out[0][w], out[1][w]))
+                          - out[3][w]) - 1) < 1e-11
