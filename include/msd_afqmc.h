@@ -191,6 +191,35 @@ msd_status msd_propagate(msd_system* sys, const double* fields, double dt, doubl
 msd_status msd_propagate_dev(msd_system* sys, const double* fields, double dt,
                              double e_shift, int32_t n_steps);
 
+/* Population control by the comb method (the simulation block of Sec. III.B
+ * and Listing 1 runs it every 5 steps; the paper names no algorithm, the comb
+ * is the reading taken).  With cumulative weights C_i = w_0 + ... + w_i and
+ * total W, tooth k (k = 0 .. n_walkers-1) sits at t_k = (k + z) W / n_walkers;
+ * walker k of the new population is a copy (orbitals and log overlap) of the
+ * walker i with C_{i-1} <= t_k < C_i, and every new weight is W / n_walkers.
+ * A walker of weight 0 is never copied.  z: the comb offset, a uniform random
+ * number in [0, 1) drawn by the caller (MSD_ERR_ARG otherwise).  parent:
+ * n_walkers int32 receiving i for every new walker k, host memory
+ * (synchronises) or NULL.  If W = 0 nothing changes.  MSD_ERR_STATE without
+ * walkers. */
+msd_status msd_population_control(msd_system* sys, double z, int32_t* parent);
+/* Same with parent a device pointer (or NULL); stream-ordered, does not
+ * synchronise. */
+msd_status msd_population_control_dev(msd_system* sys, double z, int32_t* parent);
+
+/* One simulation block (Sec. III.B, Listing 1): n_steps propagation steps as
+ * msd_propagate_dev (QR on the handle's stabilize_freq schedule), population
+ * control (msd_population_control) after every pop_freq-th step of the block
+ * (0 = never) with offsets z[0], z[1], ... (n_steps / pop_freq host doubles in
+ * [0, 1)), then one measurement with energies (as msd_measure; read it with
+ * msd_get_measurement).  fields: device pointer, n_steps*n_walkers*n_chol
+ * standard-normal fields, [step][w][g].  energy (host, 3 doubles) receives
+ * Re and Im of sum_w w E_L(w) and sum_w w over walkers of positive weight:
+ * the block's weighted mixed energy is their ratio.  Synchronises;
+ * MSD_ERR_SINGULAR as msd_measure. */
+msd_status msd_run_block(msd_system* sys, const double* fields, double dt, double e_shift,
+                         int32_t n_steps, int32_t pop_freq, const double* z, double* energy);
+
 /* Green's functions (Eq. 14) of one walker (M*M complex each, G_pq at [p][q]) from
  * the most recent measure or propagate evaluation. */
 msd_status msd_get_green(msd_system* sys, int32_t walker, double* g_a, double* g_b);

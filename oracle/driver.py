@@ -19,7 +19,8 @@ Readings of the paper used here:
   never copied.  Each walker is copied floor or ceil of n w_i / W times, and
   on average over z exactly n w_i / W times.  If W is 0 nothing changes.
 * The block's energy is the weighted mixed estimate
-  E = sum_w w E_L(w) / sum_w w; numerator and denominator are returned.
+  E = sum_w w E_L(w) / sum_w w over walkers of positive weight; numerator
+  and denominator are returned.
 
 Parity pinned by tests/test_oracle_pins.py: identity on equal weights, the
 floor/ceil copy counts, unbiasedness over a grid of offsets, zero-weight
@@ -77,4 +78,5 @@ def block(h1, chol, e0, ci, occ_a, occ_b, phi_a, phi_b, weights, log_ovlp, field
                 wts = np.full_like(wts, wn)
     out = msd.measure(h1, chol, e0, ci, occ_a, occ_b, pa, pb, dt, energy=True)
     e_loc = out["e_loc"]
-    return pa, pb, wts, lo, e_loc, np.sum(wts * e_loc), np.sum(wts)
+    live = wts > 0.0  # a walker of weight 0 adds nothing (its E_L is not used)
+    return (pa, pb, wts, lo, e_loc, np.sum(wts[live] * e_loc[live]), np.sum(wts[live]))

@@ -158,6 +158,25 @@ class MsdSystem:
         self._check(self.lib.msd_propagate_dev(self.h, _ptr(fields), float(dt), float(e_shift),
                                                int(n_steps)))
 
+    def population_control(self, z: float):
+        """Comb population control; returns the parent of every new walker."""
+        parent = np.empty(self.nw, np.int32)
+        self._check(self.lib.msd_population_control(self.h, float(z), _ptr(parent)))
+        return parent
+
+    def population_control_dev(self, z: float, parent=None):
+        self._check(self.lib.msd_population_control_dev(self.h, float(z), _ptr(parent)))
+
+    def run_block(self, fields_dev, n_steps: int, dt: float, e_shift: float = 0.0,
+                  pop_freq: int = 5, z=()):
+        """One block; returns (sum_w w E_L as complex, sum_w w)."""
+        zz = _host(np.asarray(z, dtype=np.float64).reshape(-1), np.float64)
+        e = np.zeros(3, np.float64)
+        self._check(self.lib.msd_run_block(self.h, _ptr(fields_dev), float(dt), float(e_shift),
+                                           int(n_steps), int(pop_freq),
+                                           _ptr(zz) if zz.size else None, _ptr(e)))
+        return complex(e[0], e[1]), float(e[2])
+
     def get_green(self, walker: int):
         ga = np.empty((self.M, self.M), np.complex128)
         gb = np.empty((self.M, self.M), np.complex128)

@@ -45,12 +45,13 @@ void hip_check(hipError_t e, const char* what) {
 enum Stage {
   ST_REF, ST_STR, ST_OVLP, ST_CIW, ST_CIM, ST_GREEN, ST_FB_GEMM, ST_LT_GEMM, ST_LAMBDA,
   ST_COEF, ST_EGAMMA, ST_EFINAL, ST_VHS_GEMM, ST_B1, ST_TAYLOR, ST_WEIGHTS, ST_QR, ST_TRACES,
-  ST_COUNT
+  ST_POP, ST_COUNT
 };
 const char* kStageNames[ST_COUNT] = {
     "ref_inverse", "strings",  "overlap",   "ci_weights", "ci_matrix",    "green",
     "fb_gemm",     "lt_gemm",  "lambda",    "coef",       "energy_gamma", "energy_final",
-    "vhs_gemm",    "one_body", "taylor",    "weights",    "qr",           "traces"};
+    "vhs_gemm",    "one_body", "taylor",    "weights",    "qr",           "traces",
+    "pop_control"};
 
 // Minimal device arena: every allocation is recorded and freed together.
 struct Arena {
@@ -116,6 +117,12 @@ struct msd_system {
   double* weights = nullptr;
   cd* logo = nullptr;
   int64_t steps_done = 0;
+  // block driver: comb scratch (running sums, parents, parents' log overlaps)
+  // and the weighted energy sums of the last block
+  double* pc_cum = nullptr;
+  int* pc_parent = nullptr;
+  cd* pc_logo = nullptr;
+  cd* blk = nullptr;
 
   // work
   msd::SpinWork sw[2];
@@ -1039,6 +1046,28 @@ void propagate_impl(msd_system* s, const double* fields_dev, double dt, double e
   }
 }
 
+// Comb population control of the walker state (orbitals, log overlaps,
+// weights); parent (device, NW int32) receives the parent of every new walker
+// (the handle's scratch if null).  The copies go through the Taylor
+// accumulator, which holds nothing between steps.
+void comb_impl(msd_system* s, double z, int* parent) {
+  need_ready(s);
+  if (!s->have_walkers) fail(MSD_ERR_STATE, "walkers have not been set");
+  if (!(z >= 0.0 && z < 1.0)) fail(MSD_ERR_ARG, "comb offset z must lie in [0, 1)");
+  int* par = parent ? parent : s->pc_parent;
+  s->timed(ST_POP, [&] {
+    msd::launch_comb(s->NW, z, s->weights, s->pc_cum, par, s->phi, s->logo,
+                     (int64_t)s->M * s->Ntot, s->acc, s->pc_logo, s->st);
+    hip_check(hipMemcpyAsync(s->phi, s->acc, sizeof(cd) * s->NW * s->M * s->Ntot,
+                             hipMemcpyDeviceToDevice, s->st),
+              "copy");
+    hip_check(hipMemcpyAsync(s->logo, s->pc_logo, sizeof(cd) * s->NW, hipMemcpyDeviceToDevice,
+                             s->st),
+              "copy");
+  });
+  s->check_launch("population control");
+}
+
 void set_walkers_impl(msd_system* s, const cd* pa_dev, const cd* pb_dev, const double* w_dev) {
   if (!s->have_trial || !s->have_ham)
     fail(MSD_ERR_STATE, "msd_set_hamiltonian and msd_set_trial_occ must precede msd_set_walkers");
@@ -1145,6 +1174,10 @@ msd_status msd_create(const msd_dims* d, const msd_options* o, int32_t device, v
     sys->weights = A.get<double>(NW);
     sys->logo = A.get<cd>(NW);
     sys->logo_tmp = A.get<cd>(NW);
+    sys->pc_cum = A.get<double>(NW);
+    sys->pc_parent = A.get<int>(NW);
+    sys->pc_logo = A.get<cd>(NW);
+    sys->blk = A.get<cd>(2);
     sys->obar = A.get<cd>(NW);
     sys->flag = A.get<int>(NW);
     sys->mask = A.get<int>(NW);
@@ -1647,6 +1680,53 @@ msd_status msd_propagate_dev(msd_system* sys, const double* fields, double dt, d
   if (!sys || (!fields && n_steps > 0)) fail(MSD_ERR_ARG, "null argument");
   set_device(sys);
   propagate_impl(sys, fields, dt, e_shift, n_steps);
+  API_END(sys)
+}
+
+msd_status msd_population_control(msd_system* sys, double z, int32_t* parent) {
+  API_BEGIN
+  if (!sys) fail(MSD_ERR_ARG, "null argument");
+  set_device(sys);
+  comb_impl(sys, z, nullptr);
+  copy_out(sys, parent, sys->pc_parent, sizeof(int) * sys->NW);
+  sys->sync();
+  API_END(sys)
+}
+
+msd_status msd_population_control_dev(msd_system* sys, double z, int32_t* parent) {
+  API_BEGIN
+  if (!sys) fail(MSD_ERR_ARG, "null argument");
+  set_device(sys);
+  comb_impl(sys, z, parent);
+  API_END(sys)
+}
+
+msd_status msd_run_block(msd_system* sys, const double* fields, double dt, double e_shift,
+                         int32_t n_steps, int32_t pop_freq, const double* z, double* energy) {
+  API_BEGIN
+  if (!sys || !fields || !energy) fail(MSD_ERR_ARG, "null argument");
+  if (n_steps < 1) fail(MSD_ERR_ARG, "n_steps must be >= 1");
+  if (pop_freq < 0) fail(MSD_ERR_ARG, "pop_freq must be >= 0");
+  const int n_comb = pop_freq > 0 ? n_steps / pop_freq : 0;
+  if (n_comb > 0 && !z) fail(MSD_ERR_ARG, "null comb offsets");
+  for (int j = 0; j < n_comb; ++j)
+    if (!(z[j] >= 0.0 && z[j] < 1.0))
+      fail(MSD_ERR_ARG, "comb offset " + std::to_string(j) + " outside [0, 1)");
+  set_device(sys);
+  const size_t per = (size_t)sys->NW * sys->NG;
+  for (int step = 0, j = 0; step < n_steps; ++step) {
+    propagate_impl(sys, fields + step * per, dt, e_shift, 1);
+    if (pop_freq > 0 && (step + 1) % pop_freq == 0) comb_impl(sys, z[j++], nullptr);
+  }
+  measure_impl(sys, dt, true);
+  check_flags(sys, "msd_run_block");
+  msd::launch_block_energy(sys->NW, sys->weights, sys->eloc, sys->blk, sys->st);
+  cd h[2];
+  copy_out(sys, h, sys->blk, sizeof(h));
+  sys->sync();
+  energy[0] = h[0].re;
+  energy[1] = h[0].im;
+  energy[2] = h[1].re;
   API_END(sys)
 }
 

@@ -262,6 +262,14 @@ void launch_traces64(const cd* Qa, const cd* Qb, int Na, int Nb, int NW, int w0,
 void launch_fill_i32(int* p, int n, int v, hipStream_t st);
 void launch_copy_walkers(int NW, int M, int Ntot, int na, int nb, const cd* pa, const cd* pb,
                          cd* phi, bool to_internal, cd* out_a, cd* out_b, hipStream_t st);
+// Comb population control: new weights W / n in place, parent[k] per new
+// walker, copies of the parents' orbitals (per_w complex per walker) and log
+// overlaps into phi_out / logo_out.  cum: NW doubles of scratch.
+void launch_comb(int NW, double z, double* weights, double* cum, int* parent, const cd* phi,
+                 const cd* logo, int64_t per_w, cd* phi_out, cd* logo_out, hipStream_t st);
+// out[0] = sum_w w E_L, out[1] = (sum_w w, 0) over walkers of positive weight.
+void launch_block_energy(int NW, const double* weights, const cd* eloc, cd* out,
+                         hipStream_t st);
 void launch_gather_rows(const double* L, int NG, int M, const int* rows, int P, double* out,
                         hipStream_t st);
 

@@ -255,6 +255,130 @@ void launch_traces64(const cd* Qa, const cd* Qb, int Na, int Nb, int NW, int w0,
                      w0, NG, v0, ex0);
 }
 
+// ---------------------------------------------------------------- block driver
+// Population control by the comb (the block of Sec. III.B runs it every five
+// steps): with cumulative weights C_i and total W, tooth k sits at
+// t_k = (k + z) W / n and walker k of the new population copies the walker i
+// with C_{i-1} <= t_k < C_i (a walker of weight 0 owns an empty interval);
+// every new weight is W / n.  One workgroup: each thread sums a contiguous
+// run of walkers, the run sums are scanned in LDS, and each thread then
+// writes the running sums of its run and binary-searches its teeth.  If W is
+// 0 nothing changes (parent[k] = k).
+constexpr int COMB_THREADS = 1024;
+
+__global__ __launch_bounds__(COMB_THREADS) void k_comb(int NW, double z,
+                                                       double* __restrict__ weights,
+                                                       double* __restrict__ cum,
+                                                       int* __restrict__ parent) {
+  __shared__ double part[COMB_THREADS];
+  __shared__ int last_pos;
+  const int tid = threadIdx.x;
+  const int per = (NW + COMB_THREADS - 1) / COMB_THREADS;
+  const int b = min(NW, tid * per), e = min(NW, b + per);
+  double s = 0.0;
+  int last = -1;
+  for (int i = b; i < e; ++i) {
+    s += weights[i];
+    if (weights[i] > 0.0) last = i;
+  }
+  part[tid] = s;
+  if (tid == 0) last_pos = -1;
+  __syncthreads();
+  if (last >= 0) atomicMax(&last_pos, last);
+  for (int off = 1; off < COMB_THREADS; off <<= 1) {  // inclusive scan of run sums
+    const double v = tid >= off ? part[tid - off] : 0.0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  double run = tid ? part[tid - 1] : 0.0;
+  for (int i = b; i < e; ++i) {
+    run += weights[i];
+    cum[i] = run;
+  }
+  __syncthreads();  // running sums and last_pos visible to the workgroup
+  const double total = part[COMB_THREADS - 1];
+  const bool live = total > 0.0 && last_pos >= 0;
+  for (int k = tid; k < NW; k += COMB_THREADS) {
+    int p = k;
+    if (live) {
+      const double t = ((double)k + z) * total / (double)NW;
+      int lo = 0, hi = NW;  // first i in [lo, hi) with cum[i] > t, else NW
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (cum[mid] > t) hi = mid;
+        else lo = mid + 1;
+      }
+      p = min(lo, (int)last_pos);  // a tooth rounded onto W: last live walker
+    }
+    parent[k] = p;
+  }
+  __syncthreads();  // every read of the old weights is done
+  if (live)
+    for (int k = tid; k < NW; k += COMB_THREADS) weights[k] = total / (double)NW;
+}
+
+// Copies of the parents: phi_out[k] = phi[parent[k]], logo_out[k] = logo[parent[k]].
+__global__ void k_comb_gather(int NW, int64_t per_w, const int* __restrict__ parent,
+                              const cd* __restrict__ phi, const cd* __restrict__ logo,
+                              cd* __restrict__ phi_out, cd* __restrict__ logo_out) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid < (int64_t)NW * per_w) {
+    const int k = (int)(tid / per_w);
+    phi_out[tid] = phi[(int64_t)parent[k] * per_w + tid % per_w];
+  }
+  if (tid < NW) logo_out[tid] = logo[parent[tid]];
+}
+
+void launch_comb(int NW, double z, double* weights, double* cum, int* parent, const cd* phi,
+                 const cd* logo, int64_t per_w, cd* phi_out, cd* logo_out, hipStream_t st) {
+  hipLaunchKernelGGL(k_comb, dim3(1), dim3(COMB_THREADS), 0, st, NW, z, weights, cum, parent);
+  const int64_t n = std::max((int64_t)NW * per_w, (int64_t)NW);
+  hipLaunchKernelGGL(k_comb_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, NW,
+                     per_w, parent, phi, logo, phi_out, logo_out);
+}
+
+// Weighted mixed estimate of a block: out[0] = sum_w w E_L(w), out[1] =
+// (sum_w w, 0).  Walkers of weight 0 add nothing (their E_L is not read).
+constexpr int BE_THREADS = 256;
+
+__global__ __launch_bounds__(BE_THREADS) void k_block_energy(int NW,
+                                                             const double* __restrict__ weights,
+                                                             const cd* __restrict__ eloc,
+                                                             cd* __restrict__ out) {
+  __shared__ cd red[BE_THREADS];
+  __shared__ double wred[BE_THREADS];
+  const int tid = threadIdx.x;
+  cd e{0.0, 0.0};
+  double ws = 0.0;
+  for (int w = tid; w < NW; w += BE_THREADS) {
+    const double x = weights[w];
+    if (x > 0.0) {
+      e += x * eloc[w];
+      ws += x;
+    }
+  }
+  red[tid] = e;
+  wred[tid] = ws;
+  __syncthreads();
+  for (int off = BE_THREADS / 2; off > 0; off >>= 1) {
+    if (tid < off) {
+      red[tid] += red[tid + off];
+      wred[tid] += wred[tid + off];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    out[0] = red[0];
+    out[1] = cd{wred[0], 0.0};
+  }
+}
+
+void launch_block_energy(int NW, const double* weights, const cd* eloc, cd* out,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_block_energy, dim3(1), dim3(BE_THREADS), 0, st, NW, weights, eloc, out);
+}
+
 }  // namespace msd
 
 namespace msd {
