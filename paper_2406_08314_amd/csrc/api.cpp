@@ -1719,11 +1719,10 @@ msd_status msd_run_block(msd_system* sys, const double* fields, double dt, doubl
     if (pop_freq > 0 && (step + 1) % pop_freq == 0) comb_impl(sys, z[j++], nullptr);
   }
   measure_impl(sys, dt, true);
-  check_flags(sys, "msd_run_block");
   msd::launch_block_energy(sys->NW, sys->weights, sys->eloc, sys->blk, sys->st);
   cd h[2];
   copy_out(sys, h, sys->blk, sizeof(h));
-  sys->sync();
+  check_flags(sys, "msd_run_block");  // synchronises: one wait for both copies
   energy[0] = h[0].re;
   energy[1] = h[0].im;
   energy[2] = h[1].re;
