@@ -21,6 +21,8 @@
 // reproducible.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -1294,17 +1296,19 @@ __device__ __forceinline__ void rp_setup(const int* __restrict__ hwin, const int
     }
 }
 
+// Gathers rows m and m' of Y for one Cholesky vector: y[0..K) and y[K..2K).
 // sm: the LDS stage (indexed with an integer offset, so with the LDS array
 // itself the compiler emits LDS instructions).
 template <int K, class CT>
-__device__ __forceinline__ void rp_eval(const CT* sm, int base, const int* idx, const CT* mm,
-                                        CT& acc) {
-  CT y0[K], y1[K];
+__device__ __forceinline__ void rp_load(const CT* sm, int base, const int* idx, CT* y) {
 #pragma unroll
-  for (int n = 0; n < K; ++n) {
-    y0[n] = sm[base + idx[n]];
-    y1[n] = sm[base + idx[K + n]];
-  }
+  for (int n = 0; n < 2 * K; ++n) y[n] = sm[base + idx[n]];
+}
+
+template <int K, class CT>
+__device__ __forceinline__ void rp_math(const CT* y, const CT* mm, CT& acc) {
+  const CT* y0 = y;
+  const CT* y1 = y + K;
   if constexpr (K >= 4 && sizeof(CT) == sizeof(cd)) {
     // sum over n < n' of mm (y0_n y1_n' - y0_n' y1_n) = sum_n y0_n z_n with
     // z = S y1, S antisymmetric (S_nn' = mm for n < n'): K^2 complex MACs
@@ -1381,7 +1385,10 @@ __global__ __launch_bounds__((MAXK <= 4 ? 1024 : 512)) void k_energy_second(
   const int per = nblk / 8, rem = nblk % 8, xcd = b % 8;
   const int logical = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + b / 8;
   const int ib = logical % n_ib, gs = (logical / n_ib) % n_gsplit, wl = logical / (n_ib * n_gsplit);
-  const int w = w0 + wl, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int w = w0 + wl, tid = threadIdx.x, lane = tid & 63;
+  // wave index as a scalar: the plan entry, role and spin are then
+  // wave-uniform registers and the role branches below are scalar branches
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int Xa = sa.nv * sa.no, Xb = sb.nv * sb.no, X = Xa + Xb;
   const int gper = (NG + n_gsplit - 1) / n_gsplit;
   const int g0 = gs * gper, g1 = min(NG, g0 + gper);
@@ -1467,38 +1474,100 @@ __global__ __launch_bounds__((MAXK <= 4 ? 1024 : 512)) void k_energy_second(
     asm volatile("" : "+s"(u));  // opaque: the compiler cannot tell it is LDS
     gs_ = reinterpret_cast<const CT*>(u);
   }
-  if (g0 < g1) stage(g0, 0);
-  __syncthreads();
-  int it = 0;
-  for (int gb = g0; gb < g1; gb += G, ++it) {
-    if (gb + G < g1) stage(gb + G, (it + 1) & 1);
-    const int oa = (it & 1) * G * X, ob = oa + G * Xa;
-    const int Gs = min(G, g1 - gb);
-    if (live) {
-      if (role == ER_PAIRS) {
+  // The vector loop, instantiated once per role (role is wave-uniform, so
+  // each wave runs exactly one instance and every instance passes the same
+  // barriers): body(oa, ob, Gs) consumes one LDS stage.
+  auto run_stages = [&](auto&& body) {
+    if (g0 < g1) stage(g0, 0);
+    __syncthreads();
+    int it = 0;
+    for (int gb = g0; gb < g1; gb += G, ++it) {
+      if (gb + G < g1) stage(gb + G, (it + 1) & 1);
+      const int oa = (it & 1) * G * X, ob = oa + G * Xa;
+      if (live) body(oa, ob, min(G, g1 - gb));
+      __syncthreads();
+    }
+  };
+  // row-pair items of order K: the next vector's gathers are issued before
+  // the current vector's arithmetic where the second register set fits
+  // (FP64 items of order >= 3 would spill; they load each vector when used)
+  auto rows = [&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    constexpr bool prefetch = 2 * K * sizeof(CT) <= 64;
+    const int Xs = sp ? Xb : Xa;
+    run_stages([&](int oa, int ob, int Gs) {
+      const int os = sp ? ob : oa;
+      CT ya[2 * K];
+      if constexpr (!prefetch) {
 #pragma unroll 2
         for (int gl = 0; gl < Gs; ++gl) {
-          const int x = oa + gl * Xa, y = ob + gl * Xb;
-#pragma unroll
-          for (int j = 0; j < ER_PPL; ++j) cfma(acc[j], gs_[x + idx[j]], gs_[y + idx[ER_PPL + j]]);
+          rp_load<K, CT>(gs_, os + gl * Xs, idx, ya);
+          rp_math<K, CT>(ya, mm, acc[0]);
         }
       } else {
-        const int os = sp ? ob : oa;
-        const int Xs = sp ? Xb : Xa;
-#pragma unroll 2
-        for (int gl = 0; gl < Gs; ++gl) {
-          const int base = os + gl * Xs;
-          switch (role) {
-            case 2: rp_eval<2, CT>(gs_, base, idx, mm, acc[0]); break;
-            case 3: rp_eval<3, CT>(gs_, base, idx, mm, acc[0]); break;
-            case 4: rp_eval<4, CT>(gs_, base, idx, mm, acc[0]); break;
-            case 5: if constexpr (MAXK >= 5) rp_eval<5 <= MAXK ? 5 : 2, CT>(gs_, base, idx, mm, acc[0]); break;
-            default: if constexpr (MAXK >= 6) rp_eval<6 <= MAXK ? 6 : 2, CT>(gs_, base, idx, mm, acc[0]); break;
-          }
+        // straight-line ping-pong (no conditional loads inside the loop, so
+        // each vector waits only for its own gathers)
+        CT yb[2 * K];
+        rp_load<K, CT>(gs_, os, idx, ya);
+        int gl = 0;
+        for (; gl + 2 < Gs; gl += 2) {
+          rp_load<K, CT>(gs_, os + (gl + 1) * Xs, idx, yb);
+          rp_math<K, CT>(ya, mm, acc[0]);
+          rp_load<K, CT>(gs_, os + (gl + 2) * Xs, idx, ya);
+          rp_math<K, CT>(yb, mm, acc[0]);
+        }
+        if (gl + 1 < Gs) {
+          rp_load<K, CT>(gs_, os + (gl + 1) * Xs, idx, yb);
+          rp_math<K, CT>(ya, mm, acc[0]);
+          rp_math<K, CT>(yb, mm, acc[0]);
+        } else {
+          rp_math<K, CT>(ya, mm, acc[0]);
         }
       }
-    }
-    __syncthreads();
+    });
+  };
+  if (role == ER_PAIRS) {
+    run_stages([&](int oa, int ob, int Gs) {
+      CT xa[ER_PPL], xb[ER_PPL], na[ER_PPL], nb[ER_PPL];
+      auto load = [&](int gl, CT* u, CT* v) {
+#pragma unroll
+        for (int j = 0; j < ER_PPL; ++j) {
+          u[j] = gs_[oa + gl * Xa + idx[j]];
+          v[j] = gs_[ob + gl * Xb + idx[ER_PPL + j]];
+        }
+      };
+      auto mac = [&](const CT* u, const CT* v) {
+#pragma unroll
+        for (int j = 0; j < ER_PPL; ++j) cfma(acc[j], u[j], v[j]);
+      };
+      load(0, xa, xb);
+      int gl = 0;
+      for (; gl + 2 < Gs; gl += 2) {
+        load(gl + 1, na, nb);
+        mac(xa, xb);
+        load(gl + 2, xa, xb);
+        mac(na, nb);
+      }
+      if (gl + 1 < Gs) {
+        load(gl + 1, na, nb);
+        mac(xa, xb);
+        mac(na, nb);
+      } else {
+        mac(xa, xb);
+      }
+    });
+  } else if (role == 2) {
+    rows(std::integral_constant<int, 2>{});
+  } else if (role == 3) {
+    rows(std::integral_constant<int, 3>{});
+  } else if (role == 4) {
+    rows(std::integral_constant<int, 4>{});
+  } else if (MAXK >= 5 && role == 5) {
+    rows(std::integral_constant<int, (5 <= MAXK ? 5 : 2)>{});
+  } else if (MAXK >= 6 && role >= 6) {
+    rows(std::integral_constant<int, (6 <= MAXK ? 6 : 2)>{});
+  } else {
+    run_stages([](int, int, int) {});
   }
   cd tot{0.0, 0.0};
   if (live) {
