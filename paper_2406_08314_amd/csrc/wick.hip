@@ -1528,33 +1528,26 @@ __global__ __launch_bounds__((MAXK <= 4 ? 1024 : 512)) void k_energy_second(
   };
   if (role == ER_PAIRS) {
     run_stages([&](int oa, int ob, int Gs) {
-      CT xa[ER_PPL], xb[ER_PPL], na[ER_PPL], nb[ER_PPL];
-      auto load = [&](int gl, CT* u, CT* v) {
+      // each pair's operands for the next vector are loaded into its own
+      // registers once the current product is formed (a second register
+      // set for all four pairs would spill in FP64)
+      CT xa[ER_PPL], xb[ER_PPL];
+#pragma unroll
+      for (int j = 0; j < ER_PPL; ++j) {
+        xa[j] = gs_[oa + idx[j]];
+        xb[j] = gs_[ob + idx[ER_PPL + j]];
+      }
+      for (int gl = 1; gl < Gs; ++gl) {
+        const int x = oa + gl * Xa, y = ob + gl * Xb;
 #pragma unroll
         for (int j = 0; j < ER_PPL; ++j) {
-          u[j] = gs_[oa + gl * Xa + idx[j]];
-          v[j] = gs_[ob + gl * Xb + idx[ER_PPL + j]];
+          cfma(acc[j], xa[j], xb[j]);
+          xa[j] = gs_[x + idx[j]];
+          xb[j] = gs_[y + idx[ER_PPL + j]];
         }
-      };
-      auto mac = [&](const CT* u, const CT* v) {
+      }
 #pragma unroll
-        for (int j = 0; j < ER_PPL; ++j) cfma(acc[j], u[j], v[j]);
-      };
-      load(0, xa, xb);
-      int gl = 0;
-      for (; gl + 2 < Gs; gl += 2) {
-        load(gl + 1, na, nb);
-        mac(xa, xb);
-        load(gl + 2, xa, xb);
-        mac(na, nb);
-      }
-      if (gl + 1 < Gs) {
-        load(gl + 1, na, nb);
-        mac(xa, xb);
-        mac(na, nb);
-      } else {
-        mac(xa, xb);
-      }
+      for (int j = 0; j < ER_PPL; ++j) cfma(acc[j], xa[j], xb[j]);
     });
   } else if (role == 2) {
     rows(std::integral_constant<int, 2>{});
