@@ -151,3 +151,39 @@ def test_driver_argument_errors():
         s.run_block(x, 5, wl.dt, 0.0, 5, [1.5])    # offset outside [0, 1)
     with pytest.raises(MsdError):
         s.run_block(x, 0, wl.dt, 0.0, 5, [])       # no steps
+
+
+def test_comb_single_walker_and_timing_stage():
+    """One walker: the comb copies it onto itself with its own weight; with
+    timing on, the population-control stage is recorded once per call."""
+    wl = make_config("tiny")
+    s = MsdSystem(wl.M, wl.n_alpha, wl.n_beta, wl.n_chol, 1, wl.n_det, timing=True)
+    s.set_hamiltonian(wl.h1, wl.chol, wl.e0)
+    s.set_trial(wl.ci, wl.occ_a, wl.occ_b)
+    s.set_walkers(wl.phi_a[:1], wl.phi_b[:1], np.array([0.625]))
+    before = s.get_walkers()
+    for z in (0.0, 0.99):
+        assert list(s.population_control(z)) == [0]
+    after = s.get_walkers()
+    for u, v in zip(after, before):
+        np.testing.assert_array_equal(u, v)
+    t = s.timings()
+    assert t["pop_control"][1] == 2
+
+
+def test_block_with_timing_matches_block_with_graphs():
+    """The same block through timed eager launches and through replayed
+    graphs gives identical walkers and energy sums."""
+    torch = pytest.importorskip("torch")
+    wl = make_config("tiny")
+    n_steps, zs = 4, [0.42, 0.07]
+    fields = torch.from_numpy(np.stack([fields_for_step(wl, k) for k in range(n_steps)])).to(
+        "cuda:0")
+    out = []
+    for kw in (dict(timing=True), dict(graphs=True)):
+        s = system_for(wl, stabilize_freq=2, **kw)
+        e = s.run_block(fields, n_steps, wl.dt, 0.1, 2, zs)
+        out.append((e, s.get_walkers()))
+    assert out[0][0] == out[1][0]
+    for u, v in zip(out[0][1], out[1][1]):
+        np.testing.assert_array_equal(u, v)
