@@ -230,18 +230,16 @@ struct StrOut {
   cd* m2;
 };
 
+// One (string of order K, walker) per thread; tid counts the threads of
+// order K.
 template <int K>
-__global__ __launch_bounds__(256) void k_strings_t(DevSpin sa, DevSpin sb, StrOut oa, StrOut ob,
-                                                   int NW, bool minors) {
-  const bool beta = blockIdx.y == 1;
-  const DevSpin& s = beta ? sb : sa;
-  const StrOut& o = beta ? ob : oa;
+__device__ __forceinline__ void strings_body(const DevSpin& s, const StrOut& o, int NW,
+                                             bool minors, int64_t tid) {
   const cd* __restrict__ T = o.T;
   cd* __restrict__ d = o.d;
   cd* __restrict__ adj = o.adj;
   cd* __restrict__ m2 = o.m2;
   const int s0 = s.bucket[K], ns = s.bucket[K + 1] - s.bucket[K];
-  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (tid >= (int64_t)ns * NW) return;
   const int str = s0 + (int)(tid % ns);
   const int w = (int)(tid / ns);
@@ -283,6 +281,30 @@ __global__ __launch_bounds__(256) void k_strings_t(DevSpin sa, DevSpin sb, StrOu
               mo[pair_index(m, mp, K) * P + pair_index(n, np, K)] = det_small<K - 2>(sub);
             }
     }
+  }
+}
+
+// Orders 0-4 in one launch: the blocks of order k are [first[k], first[k+1])
+// (block-uniform dispatch); blockIdx.y is the spin.
+struct StrGrid {
+  int first[6];
+};
+
+__global__ __launch_bounds__(256) void k_strings_t(DevSpin sa, DevSpin sb, StrOut oa, StrOut ob,
+                                                   int NW, bool minors, StrGrid g) {
+  const bool beta = blockIdx.y == 1;
+  const DevSpin& s = beta ? sb : sa;
+  const StrOut& o = beta ? ob : oa;
+  const int b = blockIdx.x;
+  int k = 0;
+  while (k < 4 && b >= g.first[k + 1]) ++k;
+  const int64_t tid = (int64_t)(b - g.first[k]) * blockDim.x + threadIdx.x;
+  switch (k) {
+    case 0: strings_body<0>(s, o, NW, minors, tid); break;
+    case 1: strings_body<1>(s, o, NW, minors, tid); break;
+    case 2: strings_body<2>(s, o, NW, minors, tid); break;
+    case 3: strings_body<3>(s, o, NW, minors, tid); break;
+    default: strings_body<4>(s, o, NW, minors, tid); break;
   }
 }
 
@@ -341,21 +363,24 @@ __global__ __launch_bounds__(128) void k_strings_big(DevSpin sa, DevSpin sb, Str
 void launch_strings(const DevSpin& sa, const DevSpin& sb, const cd* Ta, const cd* Tb, int NW,
                     bool minors, const SpinWork& wa, const SpinWork& wb, hipStream_t st) {
   const StrOut oa{Ta, wa.d, wa.adj, wa.m2}, ob{Tb, wb.d, wb.adj, wb.m2};
+  StrGrid g{};
+  int64_t nb = 0;
   for (int k = 0; k <= KMAX; ++k) {
     const int ns = max(sa.bucket[k + 1] - sa.bucket[k], sb.bucket[k + 1] - sb.bucket[k]);
-    if (ns <= 0) continue;
-    const int64_t n = (int64_t)ns * NW;
-    const int bs = k <= 4 ? 256 : 128;
-    dim3 grid((unsigned)((n + bs - 1) / bs), 2);
-    switch (k) {
-      case 0: hipLaunchKernelGGL(k_strings_t<0>, grid, dim3(bs), 0, st, sa, sb, oa, ob, NW, minors); break;
-      case 1: hipLaunchKernelGGL(k_strings_t<1>, grid, dim3(bs), 0, st, sa, sb, oa, ob, NW, minors); break;
-      case 2: hipLaunchKernelGGL(k_strings_t<2>, grid, dim3(bs), 0, st, sa, sb, oa, ob, NW, minors); break;
-      case 3: hipLaunchKernelGGL(k_strings_t<3>, grid, dim3(bs), 0, st, sa, sb, oa, ob, NW, minors); break;
-      case 4: hipLaunchKernelGGL(k_strings_t<4>, grid, dim3(bs), 0, st, sa, sb, oa, ob, NW, minors); break;
-      default: hipLaunchKernelGGL(k_strings_big, grid, dim3(bs), 0, st, sa, sb, oa, ob, NW, k, minors); break;
+    const int64_t n = (int64_t)max(ns, 0) * NW;
+    if (k <= 4) {
+      g.first[k] = (int)nb;
+      nb += (n + 255) / 256;
+      continue;
     }
+    if (ns <= 0) continue;
+    dim3 grid((unsigned)((n + 127) / 128), 2);
+    hipLaunchKernelGGL(k_strings_big, grid, dim3(128), 0, st, sa, sb, oa, ob, NW, k, minors);
   }
+  g.first[5] = (int)nb;
+  if (nb > 0)
+    hipLaunchKernelGGL(k_strings_t, dim3((unsigned)nb, 2), dim3(256), 0, st, sa, sb, oa, ob, NW,
+                       minors, g);
 }
 
 // ============================================================================
