@@ -184,7 +184,10 @@ __global__ void k_qr_logo(int NW, const int* __restrict__ mask, const double* __
 void launch_qr(cd* phi, int M, int Ntot, int NW, int na, int nb, const int* mask, double* ldet,
                cd* logo, hipStream_t st) {
   const int N = max(na, nb);
-  hipLaunchKernelGGL(k_qr, dim3(NW, 2), dim3(256), 2 * (size_t)N * N * sizeof(cd), st, phi, M, Ntot,
+  // one wave for small N (barrier-bound Cholesky steps; at most N*N Gram
+  // entries, one row of Phi per lane and pass)
+  const int bs = N <= 8 ? 64 : 256;
+  hipLaunchKernelGGL(k_qr, dim3(NW, 2), dim3(bs), 2 * (size_t)N * N * sizeof(cd), st, phi, M, Ntot,
                      NW, na, nb, mask, ldet);
   hipLaunchKernelGGL(k_qr_logo, dim3((NW + 255) / 256), dim3(256), 0, st, NW, mask, ldet, logo);
 }
