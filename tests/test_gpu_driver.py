@@ -187,3 +187,33 @@ def test_block_with_timing_matches_block_with_graphs():
     assert out[0][0] == out[1][0]
     for u, v in zip(out[0][1], out[1][1]):
         np.testing.assert_array_equal(u, v)
+
+
+def test_comb_general_weights_against_oracle():
+    """Non-dyadic weights (running sums round differently in the library's
+    parallel scan and the oracle's sequential sum): parents equal wherever
+    every tooth is farther than 1e-9 W from an interval boundary, and the
+    copy counts are floor or ceil of n w_i / W."""
+    wl = make_config("tiny")
+    n_walkers = 3000
+    rng = np.random.default_rng(83)
+    pa = np.resize(wl.phi_a, (n_walkers,) + wl.phi_a.shape[1:])
+    pb = np.resize(wl.phi_b, (n_walkers,) + wl.phi_b.shape[1:])
+    w = rng.lognormal(sigma=1.0, size=n_walkers)
+    w[rng.random(n_walkers) < 0.1] = 0.0
+    s = system_for(wl, weights=w, phi=(pa, pb), n_walkers=n_walkers)
+    for z in (0.113, 0.5821):
+        _, _, w0, _ = s.get_walkers()
+        parent = s.population_control(z)
+        ref, wn = driver.comb(w0, z)
+        c = np.cumsum(w0)
+        teeth = (np.arange(n_walkers) + z) * c[-1] / n_walkers
+        gap = np.min(np.abs(teeth[:, None] - c[None, :]))
+        assert gap > 1e-9 * c[-1]  # no tooth is near a boundary for this seed
+        np.testing.assert_array_equal(parent, ref)
+        cnt = np.bincount(parent, minlength=n_walkers)
+        exp = n_walkers * w0 / c[-1]
+        assert np.all(cnt >= np.floor(exp)) and np.all(cnt <= np.ceil(exp))
+        _, _, w1, _ = s.get_walkers()
+        np.testing.assert_allclose(w1, wn, rtol=1e-14)
+        s.set_walkers(pa, pb, rng.lognormal(sigma=1.0, size=n_walkers))
