@@ -261,8 +261,19 @@ __global__ void k_splitk_reduce(GemmArgs g) {
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (tid >= (int64_t)g.M * g.N) return;
   const int m = (int)(tid / g.N), n = (int)(tid % g.N);
+  // slices summed in order; four loads in flight per group (one wait each)
+  const int64_t mn = (int64_t)g.M * g.N;
   double s = 0.0;
-  for (int z = 0; z < g.splitk; ++z) s += g.ws[(int64_t)z * g.M * g.N + tid];
+  int z = 0;
+  for (; z + 4 <= g.splitk; z += 4) {
+    const double a0 = g.ws[(z + 0) * mn + tid], a1 = g.ws[(z + 1) * mn + tid];
+    const double a2 = g.ws[(z + 2) * mn + tid], a3 = g.ws[(z + 3) * mn + tid];
+    s += a0;
+    s += a1;
+    s += a2;
+    s += a3;
+  }
+  for (; z < g.splitk; ++z) s += g.ws[z * mn + tid];
   const int64_t off = (int64_t)m * g.ldc + n;
   double v = g.alpha * s;
   if (g.beta != 0.0) v += g.beta * g.C[off];
@@ -444,8 +455,18 @@ __global__ void k_splitk_reduce32(GemmArgs32 g) {
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (tid >= (int64_t)g.M * g.N) return;
   const int m = (int)(tid / g.N), n = (int)(tid % g.N);
+  const int64_t mn = (int64_t)g.M * g.N;
   double s = 0.0;
-  for (int z = 0; z < g.splitk; ++z) s += (double)g.ws[(int64_t)z * g.M * g.N + tid];
+  int z = 0;
+  for (; z + 4 <= g.splitk; z += 4) {
+    const float a0 = g.ws[(z + 0) * mn + tid], a1 = g.ws[(z + 1) * mn + tid];
+    const float a2 = g.ws[(z + 2) * mn + tid], a3 = g.ws[(z + 3) * mn + tid];
+    s += (double)a0;
+    s += (double)a1;
+    s += (double)a2;
+    s += (double)a3;
+  }
+  for (; z < g.splitk; ++z) s += (double)g.ws[z * mn + tid];
   const int64_t off = (int64_t)m * g.ldc + n;
   if (g.C64) g.C64[off] = g.alpha * s;
   else g.C32[off] = (float)(g.alpha * s);
