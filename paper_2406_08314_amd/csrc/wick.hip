@@ -482,9 +482,29 @@ __global__ void k_ci_segments(DevSpin sa, DevSpin sb, const cd* __restrict__ det
   if (tid >= (int64_t)s.n_seg * NW) return;
   const int seg = (int)(tid % s.n_seg), w = (int)(tid / s.n_seg);
   cd acc{0.0, 0.0};
-  for (int e = s.seg_ptr[seg]; e < s.seg_ptr[seg + 1]; ++e) {
+  const cd* __restrict__ dw = d_other + (size_t)w * o.U;
+  const int e1 = s.seg_ptr[seg + 1];
+  int e = s.seg_ptr[seg];
+  // groups of four: the index loads, then the value gathers, are issued
+  // together; the products are added in list order as before
+  for (; e + 4 <= e1; e += 4) {
+    int I[4], js[4];
+    cd c[4], d[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) I[k] = s.bw_det[e + k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) js[k] = o.det_s[I[k]];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      c[k] = det_c[I[k]];
+      d[k] = dw[js[k]];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) cfma(acc, c[k], d[k]);
+  }
+  for (; e < e1; ++e) {
     const int I = s.bw_det[e];
-    cfma(acc, det_c[I], d_other[(size_t)w * o.U + o.det_s[I]]);
+    cfma(acc, det_c[I], dw[o.det_s[I]]);
   }
   seg_part[(size_t)w * s.n_seg + seg] = acc;
 }
@@ -527,8 +547,28 @@ __global__ void k_ci_matrix(DevSpin sa, DevSpin sb, int NW, const cd* __restrict
   if (tid >= (int64_t)X * NW) return;
   const int e = (int)(tid % X), w = (int)(tid / X);
   cd acc{0.0, 0.0};
-  for (int q = s.c_ptr[e]; q < s.c_ptr[e + 1]; ++q)
-    cfma(acc, adj[(size_t)w * s.A + s.c_adj[q]], B[(size_t)w * s.U + s.c_str[q]]);
+  const cd* __restrict__ aw = adj + (size_t)w * s.A;
+  const cd* __restrict__ bw = B + (size_t)w * s.U;
+  const int q1 = s.c_ptr[e + 1];
+  int q = s.c_ptr[e];
+  // groups of four loads in flight; products added in list order as before
+  for (; q + 4 <= q1; q += 4) {
+    int ia[4], ib[4];
+    cd a[4], b[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      ia[k] = s.c_adj[q + k];
+      ib[k] = s.c_str[q + k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      a[k] = aw[ia[k]];
+      b[k] = bw[ib[k]];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) cfma(acc, a[k], b[k]);
+  }
+  for (; q < q1; ++q) cfma(acc, aw[s.c_adj[q]], bw[s.c_str[q]]);
   C[(size_t)w * X + e] = acc;
 }
 
