@@ -10,11 +10,14 @@ Modules
 -------
 msd        trial overlaps, mixed Green's function, force bias, local energy
            by brute force over determinants (Eqs. 6-7, 13-15).
+wick       the same quantities one determinant at a time relative to the
+           reference (generalised Wick, Sec. III / App. A), for the large
+           shapes; its Cholesky-vector sums are plain C (wick_gamma.c).
 propagate  one phaseless step: VHS, Taylor exp(VHS), one-body half steps,
            weight update, QR re-orthonormalisation (Eqs. 4-5, 8-12).
 driver     the block around the step: comb population control, weighted
            block energy (Sec. III.B, Listing 1).
 fock       explicit second-quantised (Jordan-Wigner) Fock-space objects for
-           tiny systems; used only to pin the two modules above.
+           tiny systems; used only to pin the modules above.
 """
-from . import msd, propagate, driver, fock  # noqa: F401
+from . import msd, propagate, driver, fock, wick  # noqa: F401
