@@ -4,9 +4,14 @@ One step = one pass of the whole hot path over the walker batch:
   propagate (force bias -> VHS -> one-body/Taylor/one-body -> new overlap ->
   phaseless weights -> QR) followed by a full measurement (overlap, Green's
   function, force bias, local energy).
-Metric: MSD Wick evaluations per second = n_walkers * n_det / step time.
-Workload: the Medium synthetic system (M=64, N=8+8, 320 Cholesky vectors,
-1,000 determinants of excitation order 0-4, 128 walkers), FP64.
+Metric: MSD Wick evaluations per second = n_walkers * n_det / step time, for the
+FP64 form (``value``) and the mixed form (``mixed``), with the mixed form's
+largest per-walker local-energy difference from FP64.
+Workload (default): the binuclear Cu-oxo-cluster-shaped synthetic system
+(M=200, N=30+30, 1,200 Cholesky vectors, 10,000 determinants of excitation
+order <= 4, 256 walkers).  ``--config medium`` times the Medium system (M=64,
+N=8+8, 320 vectors, 1,000 determinants, 128 walkers) instead; the default run
+also reports Medium as a secondary record.
 
 Prints ONE JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
 """
@@ -27,10 +32,11 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 TRAFFIC_PROFILES = {
-    "energy_gamma": os.path.join(ROOT, "profiles", "energy_second_medium_hbm_traffic.md"),
-    # (stage, lambda variant): the LT-tile kernel and the fused contraction kernel
-    ("lambda", 4): os.path.join(ROOT, "profiles", "lambda_mfma_medium_hbm_traffic.md"),
-    ("lambda", 5): os.path.join(ROOT, "profiles", "ltl_mfma_medium_hbm_traffic.md"),
+    # (stage, workload) or (stage, lambda variant, workload): committed counter
+    # summaries of the stage's kernel at that workload
+    ("energy_gamma", "medium"): os.path.join(ROOT, "profiles", "energy_second_medium_hbm_traffic.md"),
+    ("lambda", 4, "medium"): os.path.join(ROOT, "profiles", "lambda_mfma_medium_hbm_traffic.md"),
+    ("lambda", 5, "medium"): os.path.join(ROOT, "profiles", "ltl_mfma_medium_hbm_traffic.md"),
 }
 
 
@@ -109,37 +115,231 @@ def stage_work(wl, lib_sys, stage):
     return None
 
 
-def cpu_baseline(wl, n_sample=24):
-    """The oracle on a bounded sample: n_sample walkers, all determinants,
-    one propagation step + one full measurement each."""
-    from threadpoolctl import threadpool_info
-
+def cpu_baseline(wl, n_walk=2, n_det=None):
+    """The brute-force oracle on a bounded sample: the first ``n_walk``
+    walkers and the first ``n_det`` determinants of the trial (all if None),
+    one propagation step + one full measurement.  The one-body propagator
+    B1 = expm(-dt h'/2) is per-Hamiltonian set-up on both sides and is built
+    before the clock starts."""
     from oracle import msd, propagate
     from synth import fields_for_step
 
-    idx = list(range(n_sample))
-    t0 = time.perf_counter()
+    nd = wl.n_det if n_det is None else min(n_det, wl.n_det)
+    ci, oa, ob = wl.ci[:nd], wl.occ_a[:nd], wl.occ_b[:nd]
+    idx = list(range(n_walk))
     b1 = propagate.one_body_half_step(wl.h1, wl.chol, wl.dt)
-    lo = np.array([np.log(msd.trial_overlap(wl.ci, wl.occ_a, wl.occ_b, wl.phi_a[w], wl.phi_b[w]))
-                   for w in idx])
-    pa, pb, _, _, _ = propagate.step(wl.h1, wl.chol, wl.ci, wl.occ_a, wl.occ_b, wl.phi_a[idx],
-                                     wl.phi_b[idx], wl.weights[idx], lo,
-                                     fields_for_step(wl, 0)[idx], wl.dt, do_qr=True, b1=b1)
-    msd.measure(wl.h1, wl.chol, wl.e0, wl.ci, wl.occ_a, wl.occ_b, pa, pb, wl.dt)
+    t0 = time.perf_counter()
+    lo = np.array([np.log(msd.trial_overlap(ci, oa, ob, wl.phi_a[w], wl.phi_b[w])) for w in idx])
+    pa, pb, _, _, _ = propagate.step(wl.h1, wl.chol, ci, oa, ob, wl.phi_a[idx], wl.phi_b[idx],
+                                     wl.weights[idx], lo, fields_for_step(wl, 0)[idx], wl.dt,
+                                     do_qr=True, b1=b1)
+    msd.measure(wl.h1, wl.chol, wl.e0, ci, oa, ob, pa, pb, wl.dt)
     dt = time.perf_counter() - t0
-    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    return {"value": n_sample * wl.n_det / dt, "unit": "walker*det/s", "cores": int(threads),
-            "kind": "oracle",
-            "sample": f"{n_sample} of {wl.n_walkers} walkers x all {wl.n_det} dets, one step "
-                      f"(propagate + measure), {dt:.1f} s"}
+    return {"value": n_walk * nd / dt, "unit": "walker*det/s", "cores": _threads(),
+            "cpu_count": os.cpu_count(), "cpu_model": _cpu_model(), "kind": "oracle",
+            "sample": f"brute-force oracle (complex128 NumPy): first {n_walk} of {wl.n_walkers} "
+                      f"walkers x first {nd} of {wl.n_det} determinants (truncated trial), one "
+                      f"step (propagate with QR + measure), {dt:.1f} s"}
+
+
+def cpu_wick(wl, n_walk=2):
+    """The oracle's per-determinant generalised-Wick path (NumPy + plain C,
+    OpenMP over determinants) on the first ``n_walk`` walkers, all
+    determinants, one measurement each (overlap, G, force bias, E_L)."""
+    from oracle import wick
+
+    t0 = time.perf_counter()
+    wick.measure(wl.h1, wl.chol, wl.e0, wl.ci, wl.occ_a, wl.occ_b, wl.phi_a[:n_walk],
+                 wl.phi_b[:n_walk], wl.dt)
+    dt = time.perf_counter() - t0
+    return {"value": n_walk * wl.n_det / dt, "unit": "walker*det/s", "cores": _threads(),
+            "kind": "oracle (generalised-Wick CPU path)",
+            "sample": f"first {n_walk} walkers x all {wl.n_det} determinants, one measurement, "
+                      f"{dt:.1f} s"}
+
+
+def _threads():
+    from threadpoolctl import threadpool_info
+    return int(max([i.get("num_threads", 1) for i in threadpool_info()] + [1]))
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+WORKLOADS = {
+    "cu_oxo": "cu_oxo: M=200, N=30+30, Nchol=1200, Ndet=10000 (orders <= 4, window 16x32), "
+              "256 walkers, dt=0.005, QR every step",
+    "medium": "medium: M=64, N=8+8, Nchol=320, Ndet=1000 (orders 0-4), 128 walkers, dt=0.005, "
+              "QR every step",
+    "fe2s2": "fe2s2: M=300, N=45+45, Nchol=2000, Ndet=200000 (orders <= 6, window 15x5), "
+             "512 walkers, dt=0.005, QR every step",
+    "tiny": "tiny: M=12, N=3+3, Nchol=48, Ndet=20, 8 walkers, dt=0.005, QR every step",
+}
+
+
+def run_config(name, args, torch, stages=True, block=True):
+    """Time one workload in both forms; returns a dict of results."""
+    from paper_2406_08314_amd import MsdSystem
+    from synth import fields_for_step, make_config
+
+    wl = make_config(name)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+
+    def system(timing, precision="fp64"):
+        s = MsdSystem(wl.M, wl.n_alpha, wl.n_beta, wl.n_chol, wl.n_walkers, wl.n_det, device=0,
+                      stream=stream.cuda_stream, stabilize_freq=1, timing=timing,
+                      graphs=not timing, precision=precision)
+        s.set_hamiltonian(wl.h1, wl.chol, wl.e0)
+        s.set_trial(wl.ci, wl.occ_a, wl.occ_b)
+        s.set_walkers(wl.phi_a, wl.phi_b, wl.weights)
+        s.tables = _tables(wl)
+        return s
+
+    n_total = args.warmup + args.steps
+    fields = torch.from_numpy(np.stack([fields_for_step(wl, k) for k in range(n_total)])).to(dev)
+    lo = torch.empty(wl.n_walkers, dtype=torch.complex128, device=dev)
+    fb = torch.empty(wl.n_walkers, wl.n_chol, dtype=torch.complex128, device=dev)
+    el = torch.empty(wl.n_walkers, dtype=torch.complex128, device=dev)
+
+    def step(s, k):
+        s.propagate_dev(fields[k].reshape(-1), wl.dt, 0.0, 1)
+        s.measure_dev(wl.dt, lo, fb, el)
+
+    def timed(fn, n):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for k in range(n):
+            fn(k)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1), time.perf_counter() - t0
+
+    tunings, extra = {}, {}
+
+    def run_form(precision):
+        """Graph-replayed steps and measurements of one form; also returns the
+        local energies of the initial walkers (same input for both forms)."""
+        s = system(False, precision)
+        e_init = s.measure(wl.dt)["e_loc"]
+        tunings[precision] = s.get_tuning() if args.no_autotune else s.autotune(wl.dt, reps=3)
+        for k in range(args.warmup):
+            step(s, k)
+        ms, wall = timed(lambda k: step(s, args.warmup + k), args.steps)
+        ms_meas, _ = timed(lambda k: s.measure_dev(wl.dt, lo, fb, el), args.steps)
+        ms_prop, _ = timed(lambda k: s.propagate_dev(fields[k % n_total].reshape(-1), wl.dt,
+                                                     0.0, 1), args.steps)
+        extra[precision] = {"propagate_only_ms": round(ms_prop / args.steps, 4)}
+        if block:
+            # the paper's block shape: 25 propagation steps, population control
+            # every 5, one measurement (weighted block energy), on the
+            # library's block driver
+            blk_fields = torch.stack([fields[j % n_total] for j in range(25)]).contiguous()
+            zs = np.random.default_rng(wl.seed + 25).random(5)
+            ms_block, _ = timed(lambda _: s.run_block(blk_fields, 25, wl.dt, 0.0, 5, zs), 2)
+            extra[precision].update({
+                "block_ms": round(ms_block / 2, 4),
+                "block_note": "msd_run_block: 25 steps (QR every step), comb population "
+                              "control every 5 steps, 1 measurement with the weighted block "
+                              "energy"})
+        s.close()
+        return ms / args.steps, ms_meas / args.steps, wall, e_init
+
+    nwd = wl.n_walkers * wl.n_det
+    ms_step, ms_meas, wall, e64 = run_form("fp64")
+    mx_step, mx_meas, _, emx = run_form("mixed")
+    res = {"wl": wl, "value": nwd / (ms_step * 1e-3), "ms_per_step": ms_step, "wall_s": wall,
+           "measure_only": {"value": nwd / (ms_meas * 1e-3), "ms": round(ms_meas, 4),
+                            "note": "msd_measure_dev alone (overlap, G, force bias, E_L)"},
+           **extra["fp64"]}
+    res["mixed"] = {"value": nwd / (mx_step * 1e-3), "ms_per_step": round(mx_step, 4),
+                    "measure_only_value": nwd / (mx_meas * 1e-3),
+                    "measure_only_ms": round(mx_meas, 4),
+                    "speedup_vs_fp64": round(ms_step / mx_step, 3),
+                    "measure_speedup_vs_fp64": round(ms_meas / mx_meas, 3),
+                    "max_abs_dE_L_mHa": float(np.max(np.abs(emx - e64))) * 1e3,
+                    "error_sample": f"all {wl.n_walkers} walkers, one measurement of the "
+                                    f"initial walkers",
+                    **extra["mixed"]}
+    res["tuning"] = tunings
+    if not stages:
+        return res
+
+    # instrumented passes of the same steps: HIP events around every stage
+    def stage_pass(precision):
+        s = system(True, precision)
+        s.set_tuning(**tunings[precision])
+        for k in range(args.warmup):
+            step(s, k)
+        torch.cuda.synchronize()
+        s.reset_timings()
+        timed(lambda k: step(s, args.warmup + k), args.steps)
+        return s
+
+    sm = stage_pass("mixed")
+    res["mixed"]["stages_ms"] = {k: round(v[0] / max(v[1], 1), 4)
+                                 for k, v in sm.timings().items() if v[1]}
+    sm.close()
+    s = stage_pass("fp64")
+    stages = s.timings()
+    res["dominant_stage"] = max((k for k in stages if stages[k][1] > 0),
+                                key=lambda k: stages[k][0])
+    res["stages_ms"] = {k: round(v[0] / max(v[1], 1), 4) for k, v in stages.items() if v[1]}
+    res["roofline"] = roofline(wl, s, stages, tunings["fp64"])
+    s.close()
+    return res
+
+
+def roofline(wl, s, stages, t):
+    """Roofline record of the most expensive stage that has a work model."""
+    for name in sorted(stages, key=lambda k: -stages[k][0]):
+        work = stage_work(wl, s, name)
+        if work is None or stages[name][1] == 0:
+            continue
+        amount, unit, bound = work
+        avg_s = stages[name][0] / stages[name][1] * 1e-3
+        if unit == "flop":
+            ach, peak, u = amount / avg_s / 1e12, FP64_PEAK_TFLOPS, "TFLOP/s"
+        else:
+            ach, peak, u = amount / avg_s / 1e9, HBM_PEAK_GBS, "GB/s"
+        traffic = None
+        if name == "energy_gamma":
+            prof = measured_traffic((name, wl.name))
+            if prof and prof[1] == (t["second_gsplit"], t["second_stage"], t["second_copy"]):
+                traffic = prof[0]
+        elif name == "lambda":
+            prof = measured_traffic(("lambda", t["lambda_variant"], wl.name))
+            if prof and (not prof[1] or prof[1] == (t["lambda_chunk"],)):
+                traffic = prof[0]
+        lam_kernel = {1: "k_lambda_rows", 2: "k_lambda_wave", 3: "k_lambda_wave",
+                      4: "k_lambda_mfma", 5: "k_ltl_mfma"}.get(t["lambda_variant"], "k_lambda")
+        kernel = {"energy_gamma": "k_energy_second", "lambda": lam_kernel, "traces": "k_qtr",
+                  "lt_gemm": "k_gemm_f64 (LT)"}.get(name, name)
+        return {"kernel": kernel, "stage": name, "bound": bound, "achieved": round(ach, 3),
+                "peak": peak, "unit": u, "frac": round(ach / peak, 4), "traffic": traffic,
+                "avg_launch_ms": round(avg_s * 1e3, 4),
+                "work_per_launch": amount, "work_unit": unit}
+    return None
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="cu_oxo", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the secondary Medium record of the default run")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's default launch shapes (for counter runs)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -164,169 +364,40 @@ def main():
         print(json.dumps({"calibrate_copy_bytes_each_way": n * 8, "copies": 3}))
         return
 
-    from paper_2406_08314_amd import MsdSystem
-    from synth import fields_for_step, make_config
-
-    wl = make_config("medium")
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    stream = torch.cuda.current_stream()
-
-    def system(timing, precision="fp64"):
-        s = MsdSystem(wl.M, wl.n_alpha, wl.n_beta, wl.n_chol, wl.n_walkers, wl.n_det, device=0,
-                      stream=stream.cuda_stream, stabilize_freq=1, timing=timing,
-                      graphs=not timing, precision=precision)
-        s.set_hamiltonian(wl.h1, wl.chol, wl.e0)
-        s.set_trial(wl.ci, wl.occ_a, wl.occ_b)
-        s.set_walkers(wl.phi_a, wl.phi_b, wl.weights)
-        s.tables = _tables(wl)
-        return s
-
-    n_total = args.warmup + args.steps
-    fields = torch.from_numpy(np.stack([fields_for_step(wl, k) for k in range(n_total)])).to(dev)
-    lo = torch.empty(wl.n_walkers, dtype=torch.complex128, device=dev)
-    fb = torch.empty(wl.n_walkers, wl.n_chol, dtype=torch.complex128, device=dev)
-    el = torch.empty(wl.n_walkers, dtype=torch.complex128, device=dev)
-
-    def step(s, k):
-        s.propagate_dev(fields[k].reshape(-1), wl.dt, 0.0, 1)
-        s.measure_dev(wl.dt, lo, fb, el)
-
-    def timed(s, fn, n):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        e0.record(stream)
-        for k in range(n):
-            fn(k)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1), time.perf_counter() - t0
-
-    def run_form(precision):
-        """Graph-replayed steps and measurements of one form; also returns the
-        local energies of the initial walkers (same input for both forms)."""
-        s = system(False, precision)
-        e_init = s.measure(wl.dt)["e_loc"]
-        tunings[precision] = s.get_tuning() if args.no_autotune else s.autotune(wl.dt, reps=3)
-        for k in range(args.warmup):
-            step(s, k)
-        ms, wall = timed(s, lambda k: step(s, args.warmup + k), args.steps)
-        ms_meas, _ = timed(s, lambda k: s.measure_dev(wl.dt, lo, fb, el), args.steps)
-        ms_prop, _ = timed(s, lambda k: s.propagate_dev(fields[k % n_total].reshape(-1), wl.dt,
-                                                        0.0, 1), args.steps)
-
-        # the paper's block shape: 25 propagation steps, population control
-        # every 5, one measurement (weighted block energy), on the library's
-        # block driver
-        blk_fields = torch.stack([fields[j % n_total] for j in range(25)]).contiguous()
-        zs = np.random.default_rng(wl.seed + 25).random(5)
-
-        def block(_):
-            s.run_block(blk_fields, 25, wl.dt, 0.0, 5, zs)
-        ms_block, _ = timed(s, block, 2)
-        s.close()
-        extra[precision] = {"propagate_only_ms": round(ms_prop / args.steps, 4),
-                            "block_ms": round(ms_block / 2, 4),
-                            "block_note": "msd_run_block: 25 steps (QR every step), comb "
-                                          "population control every 5 steps, 1 measurement "
-                                          "with the weighted block energy"}
-        return ms / args.steps, ms_meas / args.steps, wall, e_init
-
-    tunings = {}
-    extra = {}
-    ms_step, ms_meas, wall, e64 = run_form("fp64")
-    value = wl.n_walkers * wl.n_det / (ms_step * 1e-3)
-    meas_value = wl.n_walkers * wl.n_det / (ms_meas * 1e-3)
-    mx_step, mx_meas, _, emx = run_form("mixed")
-    mixed = {"value": wl.n_walkers * wl.n_det / (mx_step * 1e-3), "ms_per_step": round(mx_step, 4),
-             "measure_only_value": wl.n_walkers * wl.n_det / (mx_meas * 1e-3),
-             "measure_only_ms": round(mx_meas, 4),
-             "speedup_vs_fp64": round(ms_step / mx_step, 3),
-             "max_abs_dE_L_mHa": float(np.max(np.abs(emx - e64))) * 1e3,
-             "error_sample": f"all {wl.n_walkers} walkers, one measurement of the initial walkers",
-             **extra["mixed"]}
-    # instrumented passes of the same steps: HIP events around every stage
-    def stage_pass(precision):
-        s = system(True, precision)
-        s.set_tuning(**tunings[precision])
-        for k in range(args.warmup):
-            step(s, k)
-        torch.cuda.synchronize()
-        s.reset_timings()
-        timed(s, lambda k: step(s, args.warmup + k), args.steps)
-        return s
-    sm = stage_pass("mixed")
-    mixed["stages_ms"] = {k: round(v[0] / max(v[1], 1), 4) for k, v in sm.timings().items() if v[1]}
-    sm.close()
-    s = stage_pass("fp64")
-    stages = s.timings()
-    dom = max((k for k in stages if stages[k][1] > 0), key=lambda k: stages[k][0])
-    roof = None
-    for name in sorted(stages, key=lambda k: -stages[k][0]):
-        work = stage_work(wl, s, name)
-        if work is None:
-            continue
-        amount, unit, bound = work
-        avg_s = stages[name][0] / stages[name][1] * 1e-3
-        if unit == "flop":
-            ach = amount / avg_s / 1e12
-            peak = FP64_PEAK_TFLOPS
-            u = "TFLOP/s"
-        else:
-            ach = amount / avg_s / 1e9
-            peak = HBM_PEAK_GBS
-            u = "GB/s"
-        traffic = None
-        t = tunings["fp64"]
-        if name == "energy_gamma":
-            prof = measured_traffic(name)
-            if prof and prof[1] == (t["second_gsplit"], t["second_stage"], t["second_copy"]):
-                traffic = prof[0]
-        elif name == "lambda":
-            prof = measured_traffic(("lambda", t["lambda_variant"]))
-            if prof and (not prof[1] or prof[1] == (t["lambda_chunk"],)):
-                traffic = prof[0]
-        lam_kernel = {1: "k_lambda_rows", 2: "k_lambda_wave", 3: "k_lambda_wave",
-                      4: "k_lambda_mfma", 5: "k_ltl_mfma"}.get(t["lambda_variant"], "k_lambda")
-        kernel = {"energy_gamma": "k_energy_second", "lambda": lam_kernel, "traces": "k_qtr",
-                  "lt_gemm": "k_gemm_f64 (LT)"}.get(name, name)
-        roof = {"kernel": kernel, "stage": name, "bound": bound, "achieved": round(ach, 3), "peak": peak,
-                "unit": u, "frac": round(ach / peak, 4), "traffic": traffic,
-                "avg_launch_ms": round(avg_s * 1e3, 4)}
-        break
-
+    torch.cuda.set_device(torch.device("cuda:0"))
+    r = run_config(args.config, args, torch)
+    wl = r.pop("wl")
     line = {
-        "metric": "MSD Wick evals/s (walker*det/s), FP64",
-        "value": value,
+        "metric": "MSD Wick evals/s (walker*det/s), FP64 form; mixed form in 'mixed'",
+        "value": r.pop("value"),
         "unit": "walker*det/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": r.pop("ms_per_step"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
-        "data": "synthetic (seeded Medium system; no molecular integrals)",
-        "config": {"workload": "medium: M=64, N=8+8, Nchol=320, Ndet=1000 (orders 0-4), "
-                               "128 walkers, dt=0.005, QR every step",
-                   "global_batch": wl.n_walkers, "n_det": wl.n_det, "parallelism": "none"},
-        "roofline": roof,
-        "dominant_stage": dom,
-        "stages_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in stages.items() if v[1]},
-        "wall_s": round(wall, 3),
-        "measure_only": {"value": meas_value, "ms": round(ms_meas, 4),
-                         "note": "msd_measure_dev alone (overlap, G, force bias, E_L)"},
-        **extra["fp64"],
-        "mixed": mixed,
-        "tuning": tunings,
-        "stage_timing_note": "stages_ms (average per timed launch group; the LT group runs once "
-                             "per spin) and roofline from a second pass of the same steps with "
-                             "HIP events around every stage (no graphs)",
+        "data": f"synthetic (seeded {wl.name} system; no molecular integrals)",
+        "config": {"workload": WORKLOADS[args.config], "global_batch": wl.n_walkers,
+                   "n_det": wl.n_det, "parallelism": "none"},
+        "roofline": r.pop("roofline"),
+        **r,
+        "stage_timing_note": "stages_ms (average per timed launch group; some groups run once "
+                             "per spin or per walker tile) and roofline from a second pass of "
+                             "the same steps with HIP events around every stage (no graphs)",
     }
+    if args.config != "medium" and not args.no_secondary:
+        m = run_config("medium", args, torch, stages=False, block=False)
+        m.pop("wl")
+        line["secondary"] = {"medium": {"workload": WORKLOADS["medium"], **m}}
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(wl)
+        n_det = 120 if args.config in ("cu_oxo", "fe2s2") else None
+        n_walk = 2 if args.config in ("cu_oxo", "fe2s2") else 24
+        line["cpu_baseline"] = cpu_baseline(wl, n_walk=n_walk, n_det=n_det)
+        if args.config in ("cu_oxo", "fe2s2"):
+            line["cpu_wick"] = cpu_wick(wl, n_walk=2 if args.config == "cu_oxo" else 1)
     print(json.dumps(line), flush=True)
 
 

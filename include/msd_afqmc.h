@@ -78,10 +78,16 @@ typedef struct {
   int32_t n_taylor;       /* Taylor order of exp(VHS) (terms 0..n_taylor), default 6 */
   int32_t stabilize_freq; /* QR every this many propagate steps (0 = never), default 5 */
   int32_t timing;         /* 1: record HIP events around every kernel stage   */
-  int32_t energy_algo;    /* same-spin second-order energy terms: 0 = choose per spin
-                             (fewest gathers), 1 = per-minor lists, 2 = per-string;
-                             3 = automatic choice with the fused Cholesky contraction
-                             (GEMM tile consumed in LDS) where its tile fits         */
+  int32_t energy_algo;    /* second-order energy terms: 0 = automatic (the W-form where
+                             its matrix-core GEMMs cost less than the direct form, else
+                             per spin the direct form with fewest gathers), 1 = direct,
+                             per-minor lists, 2 = direct, per-string; 3 = as 0 without
+                             the W-form, with the fused Cholesky contraction (GEMM tile
+                             consumed in LDS) where its tile fits; 4 = W-form:
+                             W^{st} = sum_g Lambda^{s,g} (x) Lambda^{t,g} per walker by
+                             matrix-core GEMMs over the Cholesky index, contracted with
+                             the pair and minor coefficient lists (memory bounded by the
+                             excitation window, independent of n_det)                 */
   int32_t graphs;         /* 1: record each measure / propagate step once as a HIP graph
                              (on a private stream) and replay it on the handle's stream;
                              ignored while timing is on.  Default 0                  */
@@ -93,7 +99,12 @@ typedef struct {
                              cofactors, Taylor propagator, QR, overlaps and weights
                              stay FP64.  Energies of trials with excitation orders
                              above 6 per spin are evaluated in FP64.                 */
-  int32_t reserved[2];
+  double mixed_tmax;      /* mixed form with the general contraction kernel: a walker
+                             whose largest |T_pj| (T = Phi A^{-1}, the ratios of its
+                             single-excitation overlaps to the reference overlap, Sec.
+                             III) exceeds this gets its local energy from the FP64
+                             energy kernels (the FP32 rounding of the Wick intermediates
+                             grows with |T|^2).  0 = default 2.0; negative = never.   */
 } msd_options;
 
 /* Limits of this implementation. */

@@ -32,7 +32,7 @@ class MsdTuning(C.Structure):
 class MsdOptions(C.Structure):
     _fields_ = [("n_taylor", C.c_int32), ("stabilize_freq", C.c_int32), ("timing", C.c_int32),
                 ("energy_algo", C.c_int32), ("graphs", C.c_int32), ("precision", C.c_int32),
-                ("reserved", C.c_int32 * 2)]
+                ("mixed_tmax", C.c_double)]
 
 
 _dp = C.POINTER(C.c_double)

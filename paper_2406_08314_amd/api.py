@@ -40,7 +40,8 @@ class MsdSystem:
     def __init__(self, M: int, n_alpha: int, n_beta: int, n_chol: int, n_walkers: int,
                  n_det: int, device: int = 0, stream: Optional[int] = None,
                  n_taylor: int = 6, stabilize_freq: int = 5, timing: bool = False,
-                 energy_algo: int = 0, graphs: bool = False, precision: str = "fp64"):
+                 energy_algo: int = 0, graphs: bool = False, precision: str = "fp64",
+                 mixed_tmax: float = 0.0):
         self.lib = _lib.load()
         self.dims = _lib.MsdDims(M, n_alpha, n_beta, n_chol, n_walkers, 0, n_det)
         opts = _lib.MsdOptions()
@@ -53,6 +54,7 @@ class MsdSystem:
         if precision not in ("fp64", "mixed"):
             raise ValueError("precision must be 'fp64' or 'mixed'")
         opts.precision = 1 if precision == "mixed" else 0
+        opts.mixed_tmax = float(mixed_tmax)
         self.M, self.na, self.nb, self.ng, self.nw, self.nd = (
             M, n_alpha, n_beta, n_chol, n_walkers, n_det)
         h = C.c_void_p()

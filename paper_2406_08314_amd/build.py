@@ -18,7 +18,8 @@ INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libmsd_afqmc.so")
 
-SOURCES = ["api.cpp", "trial.cpp", "gemm.hip", "wick.hip", "lambda_mfma.hip", "prop.hip"]
+SOURCES = ["api.cpp", "trial.cpp", "gemm.hip", "wick.hip", "lambda_mfma.hip", "ltl_general.hip",
+           "prop.hip"]
 
 # Packed-FP32 instructions are disabled for all device code (they are not used
 # deliberately anywhere and the compiler may otherwise form them).

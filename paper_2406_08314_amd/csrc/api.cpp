@@ -45,13 +45,13 @@ void hip_check(hipError_t e, const char* what) {
 enum Stage {
   ST_REF, ST_STR, ST_OVLP, ST_CIW, ST_CIM, ST_GREEN, ST_FB_GEMM, ST_LT_GEMM, ST_LAMBDA,
   ST_COEF, ST_EGAMMA, ST_EFINAL, ST_VHS_GEMM, ST_B1, ST_TAYLOR, ST_WEIGHTS, ST_QR, ST_TRACES,
-  ST_POP, ST_COUNT
+  ST_POP, ST_GUARD, ST_COUNT
 };
 const char* kStageNames[ST_COUNT] = {
     "ref_inverse", "strings",  "overlap",   "ci_weights", "ci_matrix",    "green",
     "fb_gemm",     "lt_gemm",  "lambda",    "coef",       "energy_gamma", "energy_final",
     "vhs_gemm",    "one_body", "taylor",    "weights",    "qr",           "traces",
-    "pop_control"};
+    "pop_control", "fp64_guard"};
 
 // Minimal device arena: every allocation is recorded and freed together.
 struct Arena {
@@ -141,7 +141,8 @@ struct msd_system {
   int fb_splitk = 1, fb_splitk_auto = 1, fb_ws_cap = 0;
   msd_tuning tune{};                 // launch-shape overrides (0 = automatic)
   int lambda_variant = 1;            // resolved: 0 generic, 1 rows, 2/3 one-wave, 4 matrix-core
-                                     // LT-tile kernel, 5 fused contraction + Lambda
+                                     // LT-tile kernel, 5 fused contraction + Lambda (N = 8),
+                                     // 6 general fused contraction
   bool lambda_exact = false;         // N == nmax per spin and identity occupied window
 
   // mixed form: single-precision copies of the GEMM operands
@@ -168,6 +169,28 @@ struct msd_system {
   double* Slf[2] = {nullptr, nullptr};
   float* Slf32[2] = {nullptr, nullptr};
   double* Slr[2] = {nullptr, nullptr};  // reference rows only, [NG][64][8] (traces)
+
+  // general fused contraction kernel (N <= 48 per spin, M <= 320, window of
+  // at most 32 virtual and 32 occupied orbitals): rows of L per spin, k-major,
+  // [NG][Mpad][P16], window virtual rows then reference rows
+  bool gl_fits = false;
+  double* Sgl[2] = {nullptr, nullptr};
+  float* Sgl32[2] = {nullptr, nullptr};
+  cd* lamc = nullptr;  // [2][NW][NG][gl_parts]: <C, Lambda window> per vector
+  int gl_parts = 1;
+  // mixed form with the general kernel: walkers whose largest |T| exceeds
+  // tmax get FP64 energies in a second, masked pass (FP64 Lambda windows)
+  double tmax = 2.0;
+  bool guard = false;
+  int* gmask = nullptr;  // [NW]
+  int second_G64 = 1;    // LDS stage depth of the FP64 second-order pass
+  int gl_chunk_guard = 1, n_lchunks_guard = 0;  // finer vector chunks: few walkers
+  // W-form of the second-order terms: per-walker GEMMs over the Cholesky index
+  // of the Lambda windows, [wl][2X_s][2X_t] for (aa, ab, bb), then the
+  // coefficient lists contracted with them (one energy slot per walker)
+  bool wform = false;
+  double* Gw[3] = {nullptr, nullptr, nullptr};
+  int slot_wform = 0;
 
   // energy work (lazily sized)
   int WT = 0, gl_chunk = 16, n_lchunks = 0;
@@ -354,6 +377,10 @@ void build_derived(msd_system* s) {
       R.nv = 0;
       msd::launch_gather_ltl(s->L, s->NG, s->M, R, 8, s->Slr[sp], nullptr, s->st);
     }
+  if (s->gl_fits)
+    for (int sp = 0; sp < 2; ++sp)
+      msd::launch_gather_general(s->L, s->NG, s->M, s->ds[sp], s->ds[0], s->ds[1], s->Sgl[sp],
+                                 s->Sgl32[sp], s->st);
   if (s->mixed) {
     for (int sp = 0; sp < 2; ++sp) {
       msd::launch_f64_to_f32(s->L_lt[sp], s->Llt32[sp], (int64_t)s->NG * s->ds[sp].P * s->M, s->st);
@@ -371,14 +398,6 @@ void alloc_energy(msd_system* s) {
   const msd::DevSpin& A = s->ds[0];
   const msd::DevSpin& B = s->ds[1];
   const int NG = s->NG, NW = s->NW;
-  const size_t per_w = (size_t)NG * ((size_t)A.P * A.N + (size_t)B.P * B.N) * sizeof(cd) +
-                       (size_t)NG * ((size_t)A.nv * A.no + (size_t)B.nv * B.no) * sizeof(cd) +
-                       (s->mixed ? (size_t)NG * ((size_t)A.N * A.N + (size_t)B.N * B.N) * sizeof(cd)
-                                 : 0);
-  const size_t budget = (size_t)16 << 30;
-  int wt = (int)std::max<size_t>(1, std::min<size_t>(NW, budget / std::max<size_t>(per_w, 1)));
-  if (s->tune.walker_tile > 0) wt = std::min(wt, s->tune.walker_tile);
-  s->WT = wt;
   int slot = 0;
   // Per spin: same-spin second-order terms as row-pair items of each string
   // (merged kernel) or as a list of distinct minors.  Cost per Cholesky vector
@@ -388,7 +407,29 @@ void alloc_energy(msd_system* s) {
   pl.clear();
   s->second_maxk = 0;
   const int np = s->dp.n_pair;
-  for (int f = 0; f < np; f += msd::ER_PAIRS_PER_WAVE) pl.push_back(int4{msd::ER_PAIRS, 0, f, np});
+  {
+    // W-form or direct form: algorithmic work per (walker, Cholesky vector)
+    // of each at a rate typical of its kernels (direct: vector ALU and LDS
+    // gathers; W-form: matrix-core GEMMs)
+    double direct = 8.0 * np;
+    for (int sp = 0; sp < 2; ++sp) {
+      const msd::SpinTable& S = s->tt.s[sp];
+      double fs = 0.0;
+      for (int i = 0; i < S.U; ++i) {
+        const double pk = S.k[i] * (S.k[i] - 1) / 2;
+        fs += 22.0 * pk * pk;
+      }
+      const double fm = 20.0 * S.n_minor;
+      direct += s->mixed ? fs : std::min(fs, fm);  // the mixed direct form runs strings
+    }
+    const double Xa = (double)A.nv * A.no, Xb = (double)B.nv * B.no;
+    const double wf = 8.0 * (Xa * Xa + Xa * Xb + Xb * Xb);
+    const double r_direct = s->mixed ? 40.0 : 25.0, r_mfma = s->mixed ? 80.0 : 40.0;
+    s->wform = s->o.energy_algo == 4 ||
+               (s->o.energy_algo == 0 && wf / r_mfma < direct / r_direct);
+  }
+  if (!s->wform)
+    for (int f = 0; f < np; f += msd::ER_PAIRS_PER_WAVE) pl.push_back(int4{msd::ER_PAIRS, 0, f, np});
   for (int sp = 0; sp < 2; ++sp) {
     const msd::SpinTable& S = s->tt.s[sp];
     long c_str = 0;
@@ -402,8 +443,9 @@ void alloc_energy(msd_system* s) {
     bool strings = c_str < c_min;
     if (s->o.energy_algo == 1) strings = false;
     if (s->o.energy_algo == 2) strings = true;
-    if (s->mixed) strings = true;  // the mixed form has only the row-pair kernel
+    if (s->mixed) strings = true;  // the mixed direct form has only the row-pair kernel
     if (big) strings = false;  // orders above ER_MAX_ORDER only in the minor-list form
+    if (s->wform) strings = false;  // the W-form reads the minor coefficient lists
     s->use_strings[sp] = strings;
     if (!strings) continue;
     for (int i = 0; i < S.U; ++i) s->second_maxk = std::max(s->second_maxk, (int)S.k[i]);
@@ -431,6 +473,56 @@ void alloc_energy(msd_system* s) {
     }
     for (int q = 0; q < wpb; ++q) pl[ib * wpb + q].x |= need << 16;
   }
+  // energy intermediates: which kernel
+  int nmax = 0;
+  const bool rows_fit = msd::lambda_rows_fits(A, B, &nmax);
+  s->energy_mixed = s->mixed && (s->wform || (s->use_strings[0] && s->use_strings[1]));
+  s->lambda_exact = rows_fit && A.N == nmax && B.N == nmax;
+  for (int sp = 0; sp < 2 && s->lambda_exact; ++sp) {
+    const msd::SpinTable& S = s->tt.s[sp];
+    if (S.no() != S.N) s->lambda_exact = false;
+    for (int i = 0; i < S.no() && s->lambda_exact; ++i)
+      if (S.occ_slot[i] != i) s->lambda_exact = false;
+  }
+  {
+    // 0: the generic one-wave kernel (windows beyond the row kernels' limits)
+    // default: the fused contraction + Lambda kernel for N = 8 where it
+    // applies, else the general fused contraction kernel, else the
+    // matrix-core LT-tile kernel, else the one-wave kernel
+    const bool mfma_ok = s->lambda_exact && msd::lambda_mfma_fits(A, B);
+    int wb_cc = 0;  // the option energy_algo = 3 takes its own fused contraction kernel
+    const bool cc = s->o.energy_algo == 3 && msd::chol_contract_fits(A, B, &wb_cc);
+    const bool fused_ok =
+        s->lambda_exact && !cc && (s->energy_mixed ? s->lf_fits32 : s->lf_fits64);
+    const bool gen_ok = s->gl_fits && !cc;
+    const int want = s->tune.lambda_variant ? s->tune.lambda_variant
+                     : fused_ok                 ? 5
+                     : gen_ok                   ? 6
+                     : mfma_ok                  ? 4
+                                                : 2;
+    s->lambda_variant = (want == 6 && gen_ok) ? 6
+                        : !rows_fit ? 0
+                        : (want == 1 || nmax > 16) ? 1
+                        : (want == 3 && s->lambda_exact) ? 3
+                        : (want == 4 && mfma_ok) ? 4
+                        : (want == 5 && fused_ok) ? 5
+                        : (want >= 4 && mfma_ok) ? 4 : 2;
+  }
+  const bool fused_kernel = s->lambda_variant >= 5;  // LT never stored
+  // walker tile: energy scratch of a tile within 16 GB
+  const size_t per_w =
+      (fused_kernel ? 0
+                    : (size_t)NG * ((size_t)A.P * A.N + (size_t)B.P * B.N) * sizeof(cd)) +
+      (size_t)NG * ((size_t)A.nv * A.no + (size_t)B.nv * B.no) * sizeof(cd) +
+      (s->mixed && !fused_kernel ? (size_t)NG * ((size_t)A.N * A.N + (size_t)B.N * B.N) * sizeof(cd)
+                                 : 0);
+  const size_t Xa = (size_t)A.nv * A.no, Xb = (size_t)B.nv * B.no;
+  const size_t per_w_all =
+      per_w + (s->wform ? 4 * (Xa * Xa + Xa * Xb + Xb * Xb) * sizeof(double) : 0);
+  const size_t budget = (size_t)16 << 30;
+  int wt = (int)std::max<size_t>(1, std::min<size_t>(NW, budget / std::max<size_t>(per_w_all, 1)));
+  if (s->tune.walker_tile > 0) wt = std::min(wt, s->tune.walker_tile);
+  s->WT = wt;
   // split the Cholesky range so the second-order workgroups fill whole rounds
   // of the chip's workgroup slots (one 16-wave or two 8-wave workgroups per
   // CU): the best fill of rounds over splits 1 .. 8, the smaller split on ties
@@ -451,51 +543,25 @@ void alloc_energy(msd_system* s) {
   if (s->tune.second_gsplit > 0) s->gsplit = std::min(s->tune.second_gsplit, NG);
   s->slot_second = slot;
   slot += s->n_itemblocks * s->gsplit;
-  for (int sp = 0; sp < 2; ++sp) {
+  for (int sp = 0; sp < 2 && !s->wform; ++sp) {
     if (s->use_strings[sp]) continue;
     s->slot_min[sp] = slot;
     slot += msd::energy_minor_blocks(s->ds[sp]) * s->gsplit;
   }
+  if (s->wform) s->slot_wform = slot++;
   {
-    int nmax = 0;
-    const bool rows_fit = msd::lambda_rows_fits(A, B, &nmax);
-    s->energy_mixed = s->mixed && s->use_strings[0] && s->use_strings[1];
     const int X = A.nv * A.no + B.nv * B.no;
     const int elem = s->energy_mixed ? 8 : 16;  // bytes per staged Lambda entry
     // two 8-wave workgroups or one 16-wave workgroup per CU share its LDS
-    const int budget = s->second_waves == 16 ? (144 << 10) : (72 << 10);
-    s->second_G = std::max(1, std::min(8, (int)(budget / (2 * elem * std::max(X, 1)))));
+    const int budget_lds = s->second_waves == 16 ? (144 << 10) : (72 << 10);
+    s->second_G = std::max(1, std::min(8, (int)(budget_lds / (2 * elem * std::max(X, 1)))));
     if (s->tune.second_stage > 0)
       s->second_G = std::max(1, std::min(s->tune.second_stage,
                                          (int)((150 << 10) / (2 * elem * std::max(X, 1)))));
     s->second_flat = s->tune.second_gather == 2;
     s->second_dma = s->tune.second_copy != 1;
-    s->lambda_exact = rows_fit && A.N == nmax && B.N == nmax;
-    for (int sp = 0; sp < 2 && s->lambda_exact; ++sp) {
-      const msd::SpinTable& S = s->tt.s[sp];
-      if (S.no() != S.N) s->lambda_exact = false;
-      for (int i = 0; i < S.no() && s->lambda_exact; ++i)
-        if (S.occ_slot[i] != i) s->lambda_exact = false;
-    }
-    // 0: the generic one-wave kernel (windows beyond the row kernels' limits)
-    // default: the fused contraction + Lambda kernel where it applies, else the
-    // matrix-core LT-tile kernel, else the one-wave kernel
-    const bool mfma_ok = s->lambda_exact && msd::lambda_mfma_fits(A, B);
-    int wb_cc = 0;  // the option energy_algo = 3 takes its own fused contraction kernel
-    const bool cc = s->o.energy_algo == 3 && msd::chol_contract_fits(A, B, &wb_cc);
-    const bool fused_ok =
-        s->lambda_exact && !cc && (s->energy_mixed ? s->lf_fits32 : s->lf_fits64);
-    const int want = s->tune.lambda_variant ? s->tune.lambda_variant
-                     : fused_ok                 ? 5
-                     : mfma_ok                  ? 4
-                                                : 2;
-    s->lambda_variant = !rows_fit ? 0
-                        : (want == 1 || nmax > 16) ? 1
-                        : (want == 3 && s->lambda_exact) ? 3
-                        : (want == 4 && mfma_ok) ? 4
-                        : (want == 5 && fused_ok) ? 5
-                        : (want >= 4 && mfma_ok) ? 4 : 2;
   }
+  s->gl_parts = 1;
   if (s->tune.lambda_chunk > 0) {
     s->gl_chunk = std::min(s->tune.lambda_chunk, NG);
   } else if (s->lambda_variant == 5) {
@@ -503,10 +569,19 @@ void alloc_energy(msd_system* s) {
     const int n_wgrp = 2 * ((wt + 3) / 4), target = s->energy_mixed ? 1024 : 512;
     const int n_chunks = std::max(1, std::min(NG, (target + n_wgrp / 2) / n_wgrp));
     s->gl_chunk = (NG + n_chunks - 1) / n_chunks;
+  } else if (s->lambda_variant == 6) {
+    // one workgroup per (spin, walker, chunk): about four per CU over the launch
+    const int n_wgrp = 2 * wt, target = 4 * s->n_cu;
+    const int n_chunks = std::max(1, std::min(NG, (target + n_wgrp / 2) / n_wgrp));
+    s->gl_chunk = (NG + n_chunks - 1) / n_chunks;
   } else {
     s->gl_chunk = std::min(32, NG);
   }
   s->n_lchunks = (NG + s->gl_chunk - 1) / s->gl_chunk;
+  if (s->lambda_variant == 6) {
+    s->gl_parts = msd::ltl_general_parts(A, B);
+    s->n_lchunks *= s->gl_parts;  // one partial of sum C . ZW per (chunk, wave)
+  }
   // only the row-pair / pair second-order kernel reads the windows then (the
   // minor-list form indexes them unswizzled)
   s->lam_swz = s->lambda_variant == 5 && s->use_strings[0] && s->use_strings[1] &&
@@ -517,21 +592,43 @@ void alloc_energy(msd_system* s) {
     const msd::DevSpin& D = s->ds[sp];
     int wbf = 0;
     if (s->energy_mixed) {
-      if (s->lambda_variant != 5) s->LT32[sp] = E.get<cf>((size_t)NG * D.P * wt * D.N);
+      if (!fused_kernel) s->LT32[sp] = E.get<cf>((size_t)NG * D.P * wt * D.N);
       s->Lam32[sp] = E.get<cf>((size_t)wt * NG * D.nv * D.no);
-      if (s->lambda_variant != 5) s->Q64[sp] = E.get<cd>((size_t)NG * D.N * wt * D.N);
+      if (!fused_kernel) s->Q64[sp] = E.get<cd>((size_t)NG * D.N * wt * D.N);
     } else {
       if (!(s->o.energy_algo == 3 && msd::chol_contract_fits(s->ds[0], s->ds[1], &wbf)) &&
-          s->lambda_variant != 5)
+          !fused_kernel)
         s->LT[sp] = E.get<cd>((size_t)NG * D.P * wt * D.N);
       s->Lam[sp] = E.get<cd>((size_t)wt * NG * D.nv * D.no);
     }
-    if (s->lambda_variant != 5) s->ZWp[sp] = E.get<cd>((size_t)wt * s->n_lchunks * D.nv * D.no);
+    if (!fused_kernel) s->ZWp[sp] = E.get<cd>((size_t)wt * s->n_lchunks * D.nv * D.no);
     s->coef2[sp] = E.get<cd>((size_t)NW * D.n_minor);
   }
-  s->v0 = E.get<cd>((size_t)2 * NW * NG);
-  if (s->lambda_variant == 5) s->czw = E.get<cd>((size_t)2 * NW * s->n_lchunks);
-  s->ex0 = E.get<cd>((size_t)2 * NW * NG);
+  // the mixed form's FP64 pass for walkers far from the reference (general kernel)
+  s->guard = s->energy_mixed && s->lambda_variant == 6 && s->tmax > 0.0;
+  if (s->guard) {
+    for (int sp = 0; sp < 2; ++sp)
+      s->Lam[sp] = E.get<cd>((size_t)wt * NG * s->ds[sp].nv * s->ds[sp].no);
+    // the FP64 pass usually has few walkers: split their vectors finely so
+    // they still fill the chip
+    const int n_chunks = std::max(1, std::min(NG, 32));
+    s->gl_chunk_guard = (NG + n_chunks - 1) / n_chunks;
+    s->n_lchunks_guard = (NG + s->gl_chunk_guard - 1) / s->gl_chunk_guard * s->gl_parts;
+    const int X = A.nv * A.no + B.nv * B.no;
+    const int budget_lds = s->second_waves == 16 ? (144 << 10) : (72 << 10);
+    s->second_G64 = std::max(1, std::min(8, (int)(budget_lds / (2 * 16 * std::max(X, 1)))));
+  }
+  if (s->wform) {
+    s->Gw[0] = E.get<double>((size_t)wt * 4 * Xa * Xa);
+    s->Gw[1] = E.get<double>((size_t)wt * 4 * Xa * Xb);
+    s->Gw[2] = E.get<double>((size_t)wt * 4 * Xb * Xb);
+  }
+  // the general kernel writes v0 and ex0 as per-wave partials
+  s->v0 = E.get<cd>((size_t)2 * NW * NG * s->gl_parts);
+  if (fused_kernel)
+    s->czw = E.get<cd>((size_t)2 * NW * std::max(s->n_lchunks, s->n_lchunks_guard));
+  if (s->lambda_variant == 6) s->lamc = E.get<cd>((size_t)2 * NW * NG * s->gl_parts);
+  s->ex0 = E.get<cd>((size_t)2 * NW * NG * s->gl_parts);
   s->coefAB = E.get<cd>((size_t)NW * s->dp.n_pair);
   s->epart = E.get<cd>((size_t)NW * std::max(s->n_slots, 1));
   s->plan = E.upload(s->plan_host, s->st);
@@ -677,6 +774,8 @@ void run_green_fb(msd_system* s, double dt) {
   s->check_launch("green/force bias");
 }
 
+void run_wform(msd_system* s, int w0, int wt, bool fp32, const int* wmask);
+
 // A6 + A7 in the mixed form: FP32 copies of T, FP32 MFMA LT GEMM, FP32 Lambda
 // and second-order Cholesky sums; v0, ex0, ZW, cofactors and the assembly in
 // FP64.
@@ -696,7 +795,7 @@ void run_energy_mixed(msd_system* s) {
       const msd::DevSpin& D = s->ds[sp];
       if (D.N == 0) continue;
       s->timed(ST_LT_GEMM, [&] {
-        if (s->lambda_variant != 5) {  // the fused kernel forms LT itself
+        if (s->lambda_variant < 5) {  // the fused kernels form LT themselves
         msd::GemmArgs32 g;
         g.M = s->NG * D.P;
         g.N = 2 * wt * D.N;
@@ -711,7 +810,7 @@ void run_energy_mixed(msd_system* s) {
         g.c_block = 2 * D.N;  // LT tile of (walker, vector) contiguous: [wl][g][p][n]
         msd::launch_gemm32(g, s->st);
         }
-        if (s->lambda_variant == 5) return;  // traces from launch_qtr
+        if (s->lambda_variant >= 5) return;  // traces from launch_qtr / the general kernel
         // FP64 Q = L[R, :] T for the mean-field traces
         msd::GemmArgs q;
         q.M = s->NG * D.N;
@@ -737,7 +836,11 @@ void run_energy_mixed(msd_system* s) {
     s->timed(ST_LAMBDA, [&] {
       const cf* Ta = reinterpret_cast<const cf*>(s->T32[0]);
       const cf* Tb = reinterpret_cast<const cf*>(s->T32[1]);
-      if (s->lambda_variant == 5) {
+      if (s->lambda_variant == 6) {
+        msd::launch_ltl_general32(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, s->M, s->Sgl32[0],
+                                  s->Sgl32[1], Ta, Tb, s->Lam32[0], s->Lam32[1], s->sw[0].C,
+                                  s->sw[1].C, s->v0, s->ex0, s->lamc, s->czw, s->st);
+      } else if (s->lambda_variant == 5) {
         msd::launch_ltl_mfma32(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, s->M, s->Slf32[0],
                                s->Slf32[1], Ta, Tb, s->Lam32[0], s->Lam32[1], s->v0, s->sw[0].C,
                                s->sw[1].C, s->czw, s->lam_swz, s->st);
@@ -765,6 +868,10 @@ void run_energy_mixed(msd_system* s) {
       });
     }
     s->timed(ST_EGAMMA, [&] {
+      if (s->wform) {
+        run_wform(s, w0, wt, true, nullptr);
+        return;
+      }
       msd::launch_energy_second32(A, B, s->dp, s->plan, s->n_itemblocks, s->second_waves, s->NW,
                                   w0, wt, s->NG, s->gsplit, s->second_G, s->second_maxk,
                                   s->second_flat, s->second_dma, s->lam_swz,
@@ -775,11 +882,101 @@ void run_energy_mixed(msd_system* s) {
     s->timed(ST_EFINAL, [&] {
       msd::launch_energy_final(A, B, s->NW, w0, wt, s->NG, s->n_lchunks, s->n_slots, s->obar,
                                s->v0, s->ex0, s->ZWp[0], s->ZWp[1], s->sw[0].C, s->sw[1].C,
-                               s->lambda_variant == 5 ? s->czw : nullptr, s->epart, s->onebody,
-                               s->onebody + s->NW, s->e0, s->eloc, s->st);
+                               s->lambda_variant >= 5 ? s->czw : nullptr, s->epart, s->onebody,
+                               s->onebody + s->NW, s->e0, s->eloc,
+                               s->lambda_variant == 6 ? s->lamc : nullptr, s->gl_parts, s->st);
     });
   }
   s->check_launch("energy");
+}
+
+// W-form for the walker tile [w0, w0 + wt): the three per-walker GEMMs of the
+// Lambda windows (FP64, or FP32 with double output in the mixed form) and
+// the contraction with the coefficient lists.
+void run_wform(msd_system* s, int w0, int wt, bool fp32, const int* wmask) {
+  const msd::DevSpin& A = s->ds[0];
+  const msd::DevSpin& B = s->ds[1];
+  const int X[2] = {A.nv * A.no, B.nv * B.no};
+  const int pairs[3][2] = {{0, 0}, {0, 1}, {1, 1}};
+  for (int q = 0; q < 3; ++q) {
+    const int sa = pairs[q][0], sb = pairs[q][1];
+    if (X[sa] == 0 || X[sb] == 0) continue;
+    if (fp32) {
+      msd::GemmArgs32 g;
+      g.M = 2 * X[sa];
+      g.N = 2 * X[sb];
+      g.K = s->NG;
+      g.batch = wt;
+      g.A = reinterpret_cast<const float*>(s->Lam32[sa]);
+      g.lda = 2 * X[sa];
+      g.a_kmaj = false;
+      g.strideA = (int64_t)s->NG * 2 * X[sa];
+      g.B = reinterpret_cast<const float*>(s->Lam32[sb]);
+      g.ldb = 2 * X[sb];
+      g.b_kmaj = false;
+      g.strideB = (int64_t)s->NG * 2 * X[sb];
+      g.C64 = s->Gw[q];
+      g.ldc = 2 * X[sb];
+      g.strideC = (int64_t)4 * X[sa] * X[sb];
+      g.mask = wmask ? wmask + w0 : nullptr;
+      msd::launch_gemm32(g, s->st);
+    } else {
+      msd::GemmArgs g;
+      g.M = 2 * X[sa];
+      g.N = 2 * X[sb];
+      g.K = s->NG;
+      g.batch = wt;
+      g.A = reinterpret_cast<const double*>(s->Lam[sa]);
+      g.lda = 2 * X[sa];
+      g.a_kmaj = false;
+      g.strideA = (int64_t)s->NG * 2 * X[sa];
+      g.B = reinterpret_cast<const double*>(s->Lam[sb]);
+      g.ldb = 2 * X[sb];
+      g.b_kmaj = false;
+      g.strideB = (int64_t)s->NG * 2 * X[sb];
+      g.C = s->Gw[q];
+      g.ldc = 2 * X[sb];
+      g.strideC = (int64_t)4 * X[sa] * X[sb];
+      g.mask = wmask ? wmask + w0 : nullptr;
+      msd::launch_gemm(g, s->st);
+    }
+  }
+  msd::launch_wform_contract(A, B, s->dp, s->NW, w0, wt, s->Gw[0], s->Gw[1], s->Gw[2], s->coefAB,
+                             s->coef2[0], s->coef2[1], s->epart, s->n_slots, s->slot_wform, s->st,
+                             wmask);
+}
+
+// Mixed form: FP64 local energies for the walkers whose largest |T| exceeds
+// tmax (the FP32 rounding of Q, Lambda and their products grows with |T|^2),
+// through the general contraction kernel and the FP64 second-order kernel,
+// every kernel skipping the walkers the mask leaves out.  Runs after the
+// mixed pass and overwrites those walkers' energies.
+void run_energy_guard(msd_system* s) {
+  const msd::DevSpin& A = s->ds[0];
+  const msd::DevSpin& B = s->ds[1];
+  s->timed(ST_GUARD, [&] {
+    msd::launch_walker_tmax(s->NW, s->M, A.N, B.N, s->sw[0].T, s->sw[1].T, s->tmax, s->gmask,
+                            s->st);
+    for (int w0 = 0; w0 < s->NW; w0 += s->WT) {
+      const int wt = std::min(s->WT, s->NW - w0);
+      msd::launch_ltl_general(A, B, s->NW, w0, wt, s->NG, s->gl_chunk_guard, s->M, s->Sgl[0],
+                              s->Sgl[1], s->sw[0].T, s->sw[1].T, s->Lam[0], s->Lam[1], s->sw[0].C,
+                              s->sw[1].C, s->v0, s->ex0, s->lamc, s->czw, s->gmask, s->st);
+      if (s->wform)
+        run_wform(s, w0, wt, false, s->gmask);
+      else
+        msd::launch_energy_second(A, B, s->dp, s->plan, s->n_itemblocks, s->second_waves, s->NW,
+                                  w0, wt, s->NG, s->gsplit, s->second_G64, s->second_maxk,
+                                  s->second_flat, s->second_dma, false, s->Lam[0], s->Lam[1],
+                                  s->coefAB, s->sw[0].m2, s->sw[1].m2, s->sw[0].B, s->sw[1].B,
+                                  s->epart, s->n_slots, s->slot_second, s->st, s->gmask);
+      msd::launch_energy_final(A, B, s->NW, w0, wt, s->NG, s->n_lchunks_guard, s->n_slots,
+                               s->obar, s->v0, s->ex0, s->ZWp[0], s->ZWp[1], s->sw[0].C,
+                               s->sw[1].C, s->czw, s->epart, s->onebody, s->onebody + s->NW,
+                               s->e0, s->eloc, s->lamc, s->gl_parts, s->st, s->gmask);
+    }
+  });
+  s->check_launch("energy (FP64 pass)");
 }
 
 // A6 + A7: local energies into s->eloc (needs run_overlap with minors and run_green_fb).
@@ -797,6 +994,7 @@ void run_energy(msd_system* s) {
   });
   if (s->energy_mixed) {
     run_energy_mixed(s);
+    if (s->guard) run_energy_guard(s);
     return;
   }
   int wb = 0;
@@ -810,7 +1008,7 @@ void run_energy(msd_system* s) {
                                   s->gl_chunk, wb, s->v0, s->ex0, s->st);
       });
     } else {
-      for (int sp = 0; sp < 2 && s->lambda_variant != 5; ++sp) {
+      for (int sp = 0; sp < 2 && s->lambda_variant < 5; ++sp) {
         const msd::DevSpin& D = s->ds[sp];
         if (D.N == 0) continue;
         s->timed(ST_LT_GEMM, [&] {
@@ -837,7 +1035,12 @@ void run_energy(msd_system* s) {
         });
       }
       s->timed(ST_LAMBDA, [&] {
-        if (s->lambda_variant == 5) {
+        if (s->lambda_variant == 6) {
+          msd::launch_ltl_general(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, s->M, s->Sgl[0],
+                                  s->Sgl[1], s->sw[0].T, s->sw[1].T, s->Lam[0], s->Lam[1],
+                                  s->sw[0].C, s->sw[1].C, s->v0, s->ex0, s->lamc, s->czw,
+                                  nullptr, s->st);
+        } else if (s->lambda_variant == 5) {
           msd::launch_ltl_mfma(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, s->M, s->Slf[0],
                                s->Slf[1], s->sw[0].T, s->sw[1].T, s->Lam[0], s->Lam[1], s->v0,
                                s->sw[0].C, s->sw[1].C, s->czw, s->lam_swz, s->st);
@@ -860,6 +1063,10 @@ void run_energy(msd_system* s) {
       });
     }
     s->timed(ST_EGAMMA, [&] {
+      if (s->wform) {
+        run_wform(s, w0, wt, false, nullptr);
+        return;
+      }
       msd::launch_energy_second(A, B, s->dp, s->plan, s->n_itemblocks, s->second_waves, s->NW, w0,
                                 wt, s->NG, s->gsplit, s->second_G, s->second_maxk,
                                 s->second_flat, s->second_dma, s->lam_swz, s->Lam[0],
@@ -876,8 +1083,9 @@ void run_energy(msd_system* s) {
     s->timed(ST_EFINAL, [&] {
       msd::launch_energy_final(A, B, s->NW, w0, wt, s->NG, s->n_lchunks, s->n_slots, s->obar,
                                s->v0, s->ex0, s->ZWp[0], s->ZWp[1], s->sw[0].C, s->sw[1].C,
-                               s->lambda_variant == 5 ? s->czw : nullptr, s->epart, s->onebody,
-                               s->onebody + s->NW, s->e0, s->eloc, s->st);
+                               s->lambda_variant >= 5 ? s->czw : nullptr, s->epart, s->onebody,
+                               s->onebody + s->NW, s->e0, s->eloc,
+                               s->lambda_variant == 6 ? s->lamc : nullptr, s->gl_parts, s->st);
     });
   }
   s->check_launch("energy");
@@ -1144,8 +1352,8 @@ msd_status msd_create(const msd_dims* d, const msd_options* o, int32_t device, v
   msd_default_options(&opt);
   if (o) opt = *o;
   if (opt.n_taylor < 0 || opt.n_taylor > 32 || opt.stabilize_freq < 0 || opt.energy_algo < 0 ||
-      opt.energy_algo > 3 || opt.graphs < 0 || opt.graphs > 1 || opt.precision < 0 ||
-      opt.precision > 1)
+      opt.energy_algo > 4 || opt.graphs < 0 || opt.graphs > 1 || opt.precision < 0 ||
+      opt.precision > 1 || !std::isfinite(opt.mixed_tmax))
     fail(MSD_ERR_ARG, "invalid options");
   sys = new msd_system();
   sys->dev = device;
@@ -1181,6 +1389,7 @@ msd_status msd_create(const msd_dims* d, const msd_options* o, int32_t device, v
     sys->obar = A.get<cd>(NW);
     sys->flag = A.get<int>(NW);
     sys->mask = A.get<int>(NW);
+    sys->gmask = A.get<int>(NW);
     sys->qr_ldet = A.get<double>(2 * (size_t)NW);
     sys->xraw = A.get<double>((size_t)NG * 2 * NW);
     sys->xbar = A.get<cd>((size_t)NW * NG);
@@ -1201,6 +1410,7 @@ msd_status msd_create(const msd_dims* d, const msd_options* o, int32_t device, v
       sys->sw[sp].logdetA = A.get<cd>(NW);
     }
     sys->mixed = opt.precision == 1;
+    sys->tmax = opt.mixed_tmax == 0.0 ? 2.0 : opt.mixed_tmax;
     if (sys->mixed) {
       sys->L32 = A.get<float>((size_t)NG * M * M);
       sys->Y32 = A.get<float>((size_t)2 * NW * NG);
@@ -1451,6 +1661,12 @@ void set_trial_rows(msd_system* sys, const double* ci, const int32_t* occ_a,
     sys->Slf[sp] = sys->lf_fits64 ? T.get<double>(n) : nullptr;
     sys->Slf32[sp] = sys->lf_fits32 ? T.get<float>(n) : nullptr;
     sys->Slr[sp] = (sys->lf_fits64 || sys->lf_fits32) ? T.get<double>((size_t)NG * 64 * 8) : nullptr;
+  }
+  sys->gl_fits = msd::ltl_general_fits(sys->ds[0], sys->ds[1], M);
+  for (int sp = 0; sp < 2; ++sp) {
+    const size_t n = sys->gl_fits ? msd::ltl_general_s_elems(sys->ds[0], sys->ds[1], M, NG) : 0;
+    sys->Sgl[sp] = sys->gl_fits ? T.get<double>(n) : nullptr;
+    sys->Sgl32[sp] = sys->gl_fits && sys->mixed ? T.get<float>(n) : nullptr;
   }
   if (sys->mixed) {
     sys->Gp32 = T.get<float>((size_t)2 * NW * sys->P_all * M);
@@ -1980,7 +2196,7 @@ namespace {
 void set_tuning_impl(msd_system* s, const msd_tuning& t) {
   auto bad = [](const char* f) { fail(MSD_ERR_ARG, std::string("tuning field ") + f + " out of range"); };
   if (t.fb_splitk < 0 || t.fb_splitk > 16) bad("fb_splitk");
-  if (t.lambda_variant < 0 || t.lambda_variant > 5) bad("lambda_variant");
+  if (t.lambda_variant < 0 || t.lambda_variant > 6) bad("lambda_variant");
   if (t.lambda_chunk < 0) bad("lambda_chunk");
   if (t.second_gsplit < 0 || t.second_gsplit > 64) bad("second_gsplit");
   if (t.second_stage < 0 || t.second_stage > 32) bad("second_stage");
@@ -2079,7 +2295,7 @@ msd_status msd_autotune(msd_system* sys, double dt, int32_t reps, msd_tuning* ou
     }
     int nmax = 0;
     if (msd::lambda_rows_fits(sys->ds[0], sys->ds[1], &nmax) && nmax <= 16)
-      sweep(&msd_tuning::lambda_variant, {1, 2, 3, 4, 5});
+      sweep(&msd_tuning::lambda_variant, {1, 2, 3, 4, 5, 6});
     sweep(&msd_tuning::lambda_chunk, {4, 8, 16, 32});
     sweep(&msd_tuning::second_gather, {1, 2});
     sweep(&msd_tuning::second_copy, {1, 2});

@@ -136,6 +136,30 @@ void launch_green_sum(int M, int NW, int P_all, const int* rmap_a, const int* rm
                       hipStream_t st);
 void launch_xbar(int NW, int NG, const double* raw, double sqrt_dt, cd* xbar, hipStream_t st);
 
+// General fused contraction kernel (ltl_general.hip): for each walker of the
+// tile, spin and Cholesky vector, LT = L[V u R, :] T on the matrix cores, then
+// Q, per-wave partials of v0 = tr Q, ex0 = tr QQ and <C, Lambda window> per
+// vector (v0 / ex0 / lamc, [2][NW][NG][parts]), the Lambda window (written
+// like the other kernels) and per-wave partials of <C, Lambda Q> per chunk
+// into czw ([2][NW][n_chunks * parts]).
+// The S arrays come from launch_gather_general.
+bool ltl_general_fits(const DevSpin& sa, const DevSpin& sb, int M);
+int ltl_general_parts(const DevSpin& sa, const DevSpin& sb);
+size_t ltl_general_s_elems(const DevSpin& sa, const DevSpin& sb, int M, int NG);
+void launch_gather_general(const double* L, int NG, int M, const DevSpin& D, const DevSpin& sa,
+                           const DevSpin& sb, double* S64, float* S32, hipStream_t st);
+void launch_ltl_general(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
+                        int g_chunk, int M, const double* Sa, const double* Sb, const cd* Ta,
+                        const cd* Tb, cd* Lam_a, cd* Lam_b, const cd* Ca, const cd* Cb, cd* v0,
+                        cd* ex0, cd* lamc, cd* czw, const int* wmask, hipStream_t st);
+// mask[w] = 1 where max |T| of walker w (either spin) exceeds tmax
+void launch_walker_tmax(int NW, int M, int na, int nb, const cd* Ta, const cd* Tb, double tmax,
+                        int* mask, hipStream_t st);
+void launch_ltl_general32(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
+                          int g_chunk, int M, const float* Sa, const float* Sb, const cf* Ta,
+                          const cf* Tb, cf* Lam_a, cf* Lam_b, const cd* Ca, const cd* Cb, cd* v0,
+                          cd* ex0, cd* lamc, cd* czw, hipStream_t st);
+
 // energy (one walker tile of WT walkers starting at w0)
 void launch_lambda(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
                    int g_chunk, const cd* Ta, const cd* Tb, const cd* LTa, const cd* LTb,
@@ -226,7 +250,7 @@ void launch_energy_second(const DevSpin& sa, const DevSpin& sb, const DevPairs& 
                           int WT, int NG, int n_gsplit, int G, int max_order, bool flat_gather,
                           bool use_dma, bool swz, const cd* Lam_a, const cd* Lam_b, const cd* coef,
                           const cd* m2a, const cd* m2b, const cd* Ba, const cd* Bb, cd* partial,
-                          int n_slots, int slot0, hipStream_t st);
+                          int n_slots, int slot0, hipStream_t st, const int* wmask = nullptr);
 // Same with single-precision Lambda (mixed form); the minors, CI weights and
 // the final products stay in double.
 void launch_energy_second32(const DevSpin& sa, const DevSpin& sb, const DevPairs& pr,
@@ -235,18 +259,30 @@ void launch_energy_second32(const DevSpin& sa, const DevSpin& sb, const DevPairs
                             bool flat_gather, bool use_dma, bool swz, const cf* Lam_a, const cf* Lam_b,
                             const cd* coef, const cd* m2a, const cd* m2b, const cd* Ba,
                             const cd* Bb, cd* partial, int n_slots, int slot0, hipStream_t st);
+// W-form of the second-order terms: G^{st} = per-walker real GEMMs of the
+// interleaved Lambda windows over the Cholesky index ([wl][2X_s][2X_t]); the
+// pair and minor coefficient lists contracted with W into one slot per walker.
+void launch_wform_contract(const DevSpin& sa, const DevSpin& sb, const DevPairs& pr, int NW,
+                           int w0, int WT, const double* Gaa, const double* Gab,
+                           const double* Gbb, const cd* coefAB, const cd* coef_a,
+                           const cd* coef_b, cd* partial, int n_slots, int slot, hipStream_t st,
+                           const int* wmask = nullptr);
 int energy_minor_blocks(const DevSpin& s);
 void launch_energy_minors(const DevSpin& s, int NW, int w0, int WT, int NG, int n_gsplit,
                           const cd* Lam, const cd* coef, cd* partial, int n_slots, int slot0,
                           hipStream_t st);
 // czw (when not null, [2][NW][n_lchunks]) replaces the ZW partials: the
-// first-order term is then the sum of those contracted partials.
+// first-order term is then the sum of those contracted partials.  lamc (when
+// not null, [2][NW][NG][n_lparts]) adds -(v0_a + v0_b) <C, Lambda> per vector.
+// wmask (when not null): only walkers with wmask[w] != 0 are assembled (as in
+// launch_energy_second).
 void launch_energy_final(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
                          int n_lchunks, int n_echunks, const cd* obar, const cd* v0,
                          const cd* ex0, const cd* ZWpart_a, const cd* ZWpart_b,
                          const cd* Ca, const cd* Cb, const cd* czw, const cd* epart,
                          const cd* onebody_a, const cd* onebody_b, double e0, cd* e_loc,
-                         hipStream_t st);
+                         const cd* lamc, int n_lparts, hipStream_t st,
+                         const int* wmask = nullptr);
 
 // ---------------------------------------------------------------- propagation
 void launch_vhs_prep(int NW, int NG, const double* x, const cd* xbar, double sqrt_dt,

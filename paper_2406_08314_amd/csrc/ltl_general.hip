@@ -1,0 +1,559 @@
+// A2 + A6 on the matrix cores for general shapes: the Cholesky contraction
+// and the energy intermediates of the generalised-Wick local energy (Sec. III;
+// App. A), for up to 64 electrons per spin, M <= 320 orbitals and an
+// excitation window of at most 32 virtual and 32 occupied orbitals.
+//
+// Per (walker w, spin, Cholesky vector g), with T = Phi A^{-1} (M x N) and
+// S^g = L^g[V u R, :] (rows: the n_v window virtual orbitals, zero padded to
+// nv16, then the N reference orbitals, zero padded to Np):
+//   LT  = S^g T                        (P16 x M)(M x N)
+//   Q   = LT[R rows]  (= L^g[R, :] T),  v0 = tr Q,  ex0 = tr(Q Q)
+//   Lam = T[V, :] Q - LT[V rows]       (n_v x N)
+//   D   = C Q_W^T                      (n_v x n_o)(n_o x N), with C the walker's
+//         first-order CI matrix and Q_W = Q[:, window slots]
+//   czw += <Lam, D>                    (= <C, (Lam Q)[:, window slots]>, summed over g)
+//   lc_g = <C, Lam[:, window slots]>   (per g; the energy assembly multiplies
+//                                       it by v0_alpha + v0_beta of the same g)
+//   Lam[:, window slots] -> HBM        (window layout [w][g][a * n_o + i])
+// (<X, Y> = sum_ij X_ij Y_ij, no conjugation.)
+//
+// Every complex product is a real GEMM on v_mfma_{f64,f32}_16x16x4.  A complex
+// matrix Z with Np columns is held as 2 Np real columns in tiles of 16: tile t
+// holds Re Z[:, 8t .. 8t+7] in its columns 0-7 and Im of the same columns in
+// 8-15, so the two parts of one complex entry sit in lanes l and l ^ 8.  Wave
+// t of a workgroup owns column tile t of LT, Lam and D; its B operand of LT
+// (the walker's T for those columns, all M orbitals) stays in registers for
+// the whole chunk of vectors.  S^g streams through LDS in slabs of 16
+// orbitals by direct global-to-LDS loads, a ring of four buffers over the
+// flattened (vector, slab) sequence with three slabs in flight, so the next
+// vector's first slabs load during the current vector's epilogue.  The
+// traces v0, ex0 and lc_g are written as per-wave partials ([..][g][wave]),
+// summed by the energy assembly.  One workgroup per (spin, vector chunk,
+// walker).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace msd {
+
+namespace {
+
+typedef double gdvec4 __attribute__((ext_vector_type(4)));
+typedef float gfvec4 __attribute__((ext_vector_type(4)));
+
+template <class R>
+struct GMfma;
+template <>
+struct GMfma<double> {
+  typedef gdvec4 acc_t;
+  typedef cd cx_t;
+  static __device__ __forceinline__ acc_t run(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // register r of lane l holds D[l/16 + 4r][l % 16]
+  static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <>
+struct GMfma<float> {
+  typedef gfvec4 acc_t;
+  typedef cf cx_t;
+  static __device__ __forceinline__ acc_t run(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // register r of lane l holds D[4 (l/16) + r][l % 16]
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+constexpr int GL_KS = 16;      // orbitals per LDS slab of S^g
+constexpr int GL_NB = 4;       // slab buffers (three slabs in flight)
+constexpr int GL_VTMAX = 2;    // virtual row tiles (n_v <= 32)
+constexpr int GL_OMAX = 32;    // window occupied orbitals
+
+__device__ __forceinline__ void gl_dma16(const void* g, void* lds) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void*)lds, 16, 0, 0);
+#endif
+}
+// all of this wave's memory operations (including direct-to-LDS loads) done,
+// then the workgroup barrier
+__device__ __forceinline__ void gl_bar_all() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+// at most N of this wave's vector-memory operations outstanding (the older
+// ones, including direct-to-LDS loads, done), then the workgroup barrier.
+// gfx9 s_waitcnt: vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8.
+template <int N>
+__device__ __forceinline__ void gl_bar_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  constexpr int imm = (N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(imm);
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+// this wave's LDS writes done, then the workgroup barrier
+__device__ __forceinline__ void gl_bar_lds() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+__device__ __forceinline__ double gl_wsum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+struct GlShape {
+  int nv16, Np, P16, no16, Mpad;
+};
+
+__host__ __device__ inline GlShape gl_shape(int no, int M, int NCT, int VT) {
+  GlShape s;
+  s.nv16 = VT * 16;
+  s.Np = 8 * NCT;
+  s.P16 = s.nv16 + s.Np;
+  s.no16 = no <= 16 ? 16 : 32;
+  s.Mpad = (M + GL_KS - 1) / GL_KS * GL_KS;
+  return s;
+}
+
+// direct-load pieces (16 bytes) per slab, rounded up to whole waves of every
+// wave of the workgroup: each wave issues the same number of slab loads, so a
+// fixed vmcnt tells when a slab has landed; the loads beyond the slab land in
+// a pad after the buffer
+__host__ __device__ constexpr int gl_slab_loads(int P16, int rsize, int NCT) {
+  const int pieces = GL_KS * P16 * rsize / 16;
+  return (pieces + 64 * NCT - 1) / (64 * NCT);
+}
+__host__ __device__ constexpr int gl_slab_stride(int P16, int rsize, int NCT) {
+  return gl_slab_loads(P16, rsize, NCT) * NCT * 64 * 16 / rsize;  // reals
+}
+
+// LDS reals: the slab ring (GL_NB buffers of 16 x P16, padded), Q (Np x Np
+// complex), the window columns of Q transposed (no16 x Np complex),
+// [Re T_V | Im T_V] k-major (2 Np x nv16), [Re C | Im C] k-major (2 no16 x nv16)
+__host__ __device__ inline int gl_lds_reals(const GlShape& s, int rsize, int NCT) {
+  return GL_NB * gl_slab_stride(s.P16, rsize, NCT) + 2 * s.Np * s.Np + 2 * s.no16 * s.Np +
+         2 * s.Np * s.nv16 + 2 * s.no16 * s.nv16;
+}
+
+}  // namespace
+
+template <class R, int NCT, int KSL, int VT>
+__global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
+    DevSpin sa, DevSpin sb, int NW, int w0, int WT, int NG, int g_chunk, int n_chunks, int M,
+    const R* __restrict__ Sa, const R* __restrict__ Sb,
+    const typename GMfma<R>::cx_t* __restrict__ Ta, const typename GMfma<R>::cx_t* __restrict__ Tb,
+    typename GMfma<R>::cx_t* __restrict__ Lam_a, typename GMfma<R>::cx_t* __restrict__ Lam_b,
+    const cd* __restrict__ Ca, const cd* __restrict__ Cb, cd* __restrict__ v0,
+    cd* __restrict__ ex0, cd* __restrict__ lamc, cd* __restrict__ czw,
+    const int* __restrict__ wmask) {
+  typedef GMfma<R> MF;
+  typedef typename MF::cx_t C;
+  typedef typename MF::acc_t acc_t;
+  constexpr int Np = 8 * NCT;
+  constexpr int RT = VT + NCT / 2;  // row tiles of LT (P16 / 16)
+  constexpr int P16 = 16 * RT;
+  constexpr int nv16 = 16 * VT;
+  extern __shared__ __align__(16) unsigned char gl_raw[];
+  R* lds = reinterpret_cast<R*>(gl_raw);
+
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int col = lane & 15, q = lane >> 4;
+  const int part = col >> 3;             // 0: real part, 1: imaginary part
+  const int j = 8 * wv + (col & 7);      // complex column of this lane
+  const int b = blockIdx.x;
+  const int wl = b % WT, chunk = (b / WT) % n_chunks, s2 = b / (WT * n_chunks);
+  const int w = w0 + wl;
+  if (wmask && !wmask[w]) return;  // walker not selected for this pass
+  const DevSpin& D = s2 ? sb : sa;
+  const int N = D.N, nv = D.nv, no = D.no, X = nv * no;
+  const GlShape sh = gl_shape(no, M, NCT, VT);
+  const int no16 = sh.no16, n_sl = sh.Mpad / GL_KS;
+  const C* __restrict__ T = s2 ? Tb : Ta;
+  const R* __restrict__ S = s2 ? Sb : Sa;
+  C* __restrict__ Lam = s2 ? Lam_b : Lam_a;
+  const cd* __restrict__ Cw = (s2 ? Cb : Ca) + (size_t)w * X;
+
+  // LDS carve-up
+  constexpr int SLOADS = gl_slab_loads(P16, (int)sizeof(R), NCT);
+  constexpr int SSTRIDE = gl_slab_stride(P16, (int)sizeof(R), NCT);
+  R* sS = lds;                              // [GL_NB][SSTRIDE] (16 x P16 used)
+  R* sQ = sS + GL_NB * SSTRIDE;             // [Np][Np][2]
+  R* sQT = sQ + 2 * Np * Np;                // [no16][Np][2]
+  R* sTV = sQT + 2 * no16 * Np;             // [2 Np][nv16]
+  R* sCA = sTV + 2 * Np * nv16;             // [2 no16][nv16]
+
+  // window index of this lane's column (slot j), -1 outside the window
+  int wi = -1;
+  for (int i = 0; i < no; ++i)
+    if (D.oslot[i] == j) wi = i;
+
+  // one-time LDS fills: the transposed window block of Q starts at zero (rows
+  // >= n_o are never written), [Re T_V | Im T_V] and [Re C | Im C]
+  const int nthr = 64 * NCT;
+  for (int e = threadIdx.x; e < 2 * no16 * Np; e += nthr) sQT[e] = R(0);
+  for (int e = threadIdx.x; e < 2 * Np * nv16; e += nthr) {
+    const int k = e / nv16, a = e % nv16, kc = k % Np;
+    R v = R(0);
+    if (a < nv && kc < N) {
+      const C t = T[((size_t)D.vir[a] * NW + w) * N + kc];
+      v = k < Np ? t.re : t.im;
+    }
+    sTV[e] = v;
+  }
+  for (int e = threadIdx.x; e < 2 * no16 * nv16; e += nthr) {
+    const int k = e / nv16, a = e % nv16, kc = k % no16;
+    R v = R(0);
+    if (a < nv && kc < no) {
+      const cd c = Cw[a * no + kc];
+      v = R(k < no16 ? c.re : c.im);
+    }
+    sCA[e] = v;
+  }
+
+  // B operand of LT: T[k][j] (real or imaginary part) for k = 4s + q
+  R bt[4 * KSL];
+#pragma unroll
+  for (int s = 0; s < 4 * KSL; ++s) {
+    const int k = 4 * s + q;
+    R v = R(0);
+    if (k < M && j < N) {
+      const C t = T[((size_t)k * NW + w) * N + j];
+      v = part ? t.im : t.re;
+    }
+    bt[s] = v;
+  }
+
+  const int g0 = chunk * g_chunk, g1 = min(NG, g0 + g_chunk);
+  // slab ring over the flattened (vector, slab) sequence: slab t = (g0 + t /
+  // n_sl, t % n_sl) sits in buffer t % GL_NB
+  const int n_t = (g1 - g0) * n_sl;
+  auto fetch = [&](int t) {
+    if (t >= n_t) return;  // uniform: no loads issued (the wait below allows for it)
+    constexpr int per16 = 16 / sizeof(R);
+    const int g = g0 + t / n_sl, sl = t % n_sl;
+    const R* src = S + ((size_t)g * sh.Mpad + (size_t)sl * GL_KS) * P16;
+    R* dst = sS + (t % GL_NB) * SSTRIDE;
+    constexpr int n16 = GL_KS * P16 / per16;
+#pragma unroll
+    for (int u = 0; u < SLOADS; ++u) {
+      const int c = u * NCT + wv, e = min(c * 64 + lane, n16 - 1);  // pad lanes re-read
+      gl_dma16(src + (size_t)e * per16, dst + c * 64 * per16);
+    }
+  };
+
+  double dot_re = 0.0, dot_im = 0.0;
+  for (int t = 0; t < GL_NB - 1; ++t) fetch(t);
+  int t = 0;
+  for (int g = g0; g < g1; ++g) {
+    // ---- LT = S^g T over slabs of 16 orbitals
+    acc_t acc[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) acc[rt] = acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int sl = 0; sl < KSL; ++sl) {
+      if (sl < n_sl) {
+        // slab t has landed once at most the loads of slabs t+1 .. t+GL_NB-2
+        // are outstanding (near the end fewer were issued: wait for all)
+        if (t + GL_NB - 2 < n_t) gl_bar_vm<(GL_NB - 2) * SLOADS>();
+        else gl_bar_vm<0>();
+        fetch(t + GL_NB - 1);  // into the buffer every wave finished with
+        const R* sb0 = sS + (t % GL_NB) * SSTRIDE;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          R a[RT];
+#pragma unroll
+          for (int rt = 0; rt < RT; ++rt) a[rt] = sb0[(4 * s + q) * P16 + rt * 16 + col];
+#pragma unroll
+          for (int rt = 0; rt < RT; ++rt) acc[rt] = MF::run(a[rt], bt[4 * sl + s], acc[rt]);
+        }
+        ++t;
+      }
+    }
+    // ---- Q (rows >= nv16 of LT) and its window columns, transposed, to LDS
+#pragma unroll
+    for (int rt = VT; rt < RT; ++rt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = rt * 16 + MF::row(lane, r) - nv16;
+        sQ[(i * Np + j) * 2 + part] = acc[rt][r];
+        if (wi >= 0) sQT[(wi * Np + i) * 2 + part] = acc[rt][r];
+      }
+    gl_bar_lds();
+    // ---- this wave's parts of the mean-field traces: v0 = sum_i Q_ii and
+    // ex0 = sum_ij Q_ij Q_ji over the entries Q_ij in its columns
+    double vr = 0.0, vi = 0.0, xr = 0.0, xi = 0.0;
+#pragma unroll
+    for (int rt = VT; rt < RT; ++rt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = rt * 16 + MF::row(lane, r) - nv16;
+        const double a = (double)acc[rt][r];
+        const double br = (double)sQ[(j * Np + i) * 2], bi = (double)sQ[(j * Np + i) * 2 + 1];
+        if (part == 0) {
+          if (i == j) vr += a;
+          xr += a * br;
+          xi += a * bi;
+        } else {
+          if (i == j) vi += a;
+          xr -= a * bi;
+          xi += a * br;
+        }
+      }
+    // ---- Lam = T_V Q - LT_V: K = 2 Np over [Re T_V | Im T_V]
+    acc_t lam[VT];
+#pragma unroll
+    for (int vt = 0; vt < VT; ++vt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) lam[vt][r] = -acc[vt][r];
+#pragma unroll
+    for (int kk = 0; kk < 2 * Np / 4; ++kk) {
+      const int k = 4 * kk + q;
+      const bool hi = kk >= Np / 4;  // imaginary rows of the block form of Q
+      const int kr = hi ? k - Np : k;
+      const int comp = hi ? 1 - part : part;
+      R bq = sQ[(kr * Np + j) * 2 + comp];
+      if (hi && part == 0) bq = -bq;
+#pragma unroll
+      for (int vt = 0; vt < VT; ++vt)
+        lam[vt] = MF::run(sTV[k * nv16 + vt * 16 + col], bq, lam[vt]);
+    }
+    // ---- D = C Q_W^T: K = 2 no16 over [Re C | Im C]
+    acc_t dd[VT];
+#pragma unroll
+    for (int vt = 0; vt < VT; ++vt) dd[vt] = acc_t{0, 0, 0, 0};
+    for (int kk = 0; kk < 2 * no16 / 4; ++kk) {
+      const int k = 4 * kk + q;
+      const bool hi = k >= no16;
+      const int kr = hi ? k - no16 : k;
+      const int comp = hi ? 1 - part : part;
+      R bx = sQT[(kr * Np + j) * 2 + comp];
+      if (hi && part == 0) bx = -bx;
+#pragma unroll
+      for (int vt = 0; vt < VT; ++vt)
+        dd[vt] = MF::run(sCA[k * nv16 + vt * 16 + col], bx, dd[vt]);
+    }
+    // ---- <Lam, D> (accumulated), lc_g = <C, Lam_W>, window store
+    double lr = 0.0, li = 0.0;
+#pragma unroll
+    for (int vt = 0; vt < VT; ++vt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double lv = (double)lam[vt][r];
+        const double dv = (double)dd[vt][r];
+        const double dp = (double)__shfl_xor(dd[vt][r], 8, 64);  // other part of D
+        if (part == 0) {
+          dot_re += lv * dv;
+          dot_im += lv * dp;
+        } else {
+          dot_re -= lv * dv;
+          dot_im += lv * dp;
+        }
+        const int a = vt * 16 + MF::row(lane, r);
+        if (wi >= 0 && a < nv) {
+          const double cr = (double)sCA[wi * nv16 + a], ci = (double)sCA[(no16 + wi) * nv16 + a];
+          if (part == 0) {
+            lr += cr * lv;
+            li += ci * lv;
+          } else {
+            lr -= ci * lv;
+            li += cr * lv;
+          }
+          R* dst = reinterpret_cast<R*>(Lam + ((size_t)wl * NG + g) * X + a * no + wi);
+          dst[part] = lam[vt][r];
+        }
+      }
+    lr = gl_wsum(lr);
+    li = gl_wsum(li);
+    vr = gl_wsum(vr);
+    vi = gl_wsum(vi);
+    xr = gl_wsum(xr);
+    xi = gl_wsum(xi);
+    if (lane == 0) {
+      const size_t o = (((size_t)s2 * NW + w) * NG + g) * NCT + wv;
+      lamc[o] = cd{lr, li};
+      v0[o] = cd{vr, vi};
+      ex0[o] = cd{xr, xi};
+    }
+  }
+  dot_re = gl_wsum(dot_re);
+  dot_im = gl_wsum(dot_im);
+  if (lane == 0) czw[((size_t)s2 * NW + w) * n_chunks * NCT + chunk * NCT + wv] = cd{dot_re, dot_im};
+}
+
+// S[g][k][p] = L^g[row(p), k]: p < nv the window virtual orbitals, nv16 <= p <
+// nv16 + N the reference orbitals, zero elsewhere and for k >= M.
+template <class R>
+__global__ void k_gather_general(const double* __restrict__ L, int NG, int M, int Mpad,
+                                 const int* __restrict__ ref, int N, const int* __restrict__ vir,
+                                 int nv, int nv16, int P16, R* __restrict__ S) {
+  const int64_t n = (int64_t)NG * Mpad * P16;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int p = (int)(e % P16);
+    const int k = (int)((e / P16) % Mpad);
+    const int64_t g = e / ((int64_t)P16 * Mpad);
+    double v = 0.0;
+    int row = -1;
+    if (p < nv) row = vir[p];
+    else if (p >= nv16 && p < nv16 + N) row = ref[p - nv16];
+    if (k < M && row >= 0) v = L[((size_t)g * M + row) * M + k];
+    S[e] = R(v);
+  }
+}
+
+int ltl_general_nct(const DevSpin& sa, const DevSpin& sb) {
+  const int n = std::max(sa.N, sb.N);
+  return 2 * ((n + 15) / 16);
+}
+
+int ltl_general_vt(const DevSpin& sa, const DevSpin& sb) {
+  return std::max(sa.nv, sb.nv) <= 16 ? 1 : 2;
+}
+
+int ltl_general_ksl(int M) {
+  const int n = (M + GL_KS - 1) / GL_KS;
+  for (int k : {4, 8, 13, 20})
+    if (n <= k) return k;
+  return 0;
+}
+
+bool ltl_general_fits(const DevSpin& sa, const DevSpin& sb, int M) {
+  const int nct = ltl_general_nct(sa, sb), ksl = ltl_general_ksl(M);
+  if (nct < 2 || nct > 6 || ksl == 0) return false;
+  // six column tiles put two waves on some SIMDs (at most 256 registers per
+  // wave): the register-resident T of more than 128 orbitals would spill
+  if (nct == 6 && ksl > 8) return false;
+  for (const DevSpin* d : {&sa, &sb}) {
+    if (d->N == 0 || d->nv == 0 || d->nv > GL_VTMAX * 16 || d->no > GL_OMAX) return false;
+  }
+  const GlShape s = gl_shape(std::max(sa.no, sb.no), M, nct, ltl_general_vt(sa, sb));
+  return (size_t)gl_lds_reals(s, sizeof(double), nct) * sizeof(double) <= 160 * 1024;
+}
+
+size_t ltl_general_s_elems(const DevSpin& sa, const DevSpin& sb, int M, int NG) {
+  const GlShape s = gl_shape(std::max(sa.no, sb.no), M, ltl_general_nct(sa, sb),
+                             ltl_general_vt(sa, sb));
+  return (size_t)NG * s.Mpad * s.P16;
+}
+
+void launch_gather_general(const double* L, int NG, int M, const DevSpin& D, const DevSpin& sa,
+                           const DevSpin& sb, double* S64, float* S32, hipStream_t st) {
+  const GlShape s = gl_shape(D.no, M, ltl_general_nct(sa, sb), ltl_general_vt(sa, sb));
+  const int64_t n = (int64_t)NG * s.Mpad * s.P16;
+  if (n == 0) return;
+  const int blocks = (int)std::min<int64_t>((n + 255) / 256, 65536);
+  if (S64)
+    hipLaunchKernelGGL(k_gather_general<double>, dim3(blocks), dim3(256), 0, st, L, NG, M, s.Mpad,
+                       D.ref, D.N, D.vir, D.nv, s.nv16, s.P16, S64);
+  if (S32)
+    hipLaunchKernelGGL(k_gather_general<float>, dim3(blocks), dim3(256), 0, st, L, NG, M, s.Mpad,
+                       D.ref, D.N, D.vir, D.nv, s.nv16, s.P16, S32);
+}
+
+namespace {
+template <class R, int NCT, int KSL, int VT>
+void gl_launch(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG, int g_chunk,
+               int n_chunks, int M, const R* Sa, const R* Sb, const typename GMfma<R>::cx_t* Ta,
+               const typename GMfma<R>::cx_t* Tb, typename GMfma<R>::cx_t* Lam_a,
+               typename GMfma<R>::cx_t* Lam_b, const cd* Ca, const cd* Cb, cd* v0, cd* ex0,
+               cd* lamc, cd* czw, const int* wmask, hipStream_t st) {
+  const GlShape s = gl_shape(std::max(sa.no, sb.no), M, NCT, VT);
+  const size_t lds = (size_t)gl_lds_reals(s, sizeof(R), NCT) * sizeof(R);
+  static bool attr = false;
+  if (!attr) {
+    hipFuncSetAttribute((const void*)k_ltl_general<R, NCT, KSL, VT>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr = true;
+  }
+  const dim3 grid(WT * n_chunks * 2), block(64 * NCT);
+  hipLaunchKernelGGL((k_ltl_general<R, NCT, KSL, VT>), grid, block, lds, st, sa, sb, NW, w0, WT,
+                     NG, g_chunk, n_chunks, M, Sa, Sb, Ta, Tb, Lam_a, Lam_b, Ca, Cb, v0, ex0,
+                     lamc, czw, wmask);
+}
+
+template <class R>
+void gl_dispatch(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
+                 int g_chunk, int M, const R* Sa, const R* Sb, const typename GMfma<R>::cx_t* Ta,
+                 const typename GMfma<R>::cx_t* Tb, typename GMfma<R>::cx_t* Lam_a,
+                 typename GMfma<R>::cx_t* Lam_b, const cd* Ca, const cd* Cb, cd* v0, cd* ex0,
+                 cd* lamc, cd* czw, const int* wmask, hipStream_t st) {
+  const int nct = ltl_general_nct(sa, sb), ksl = ltl_general_ksl(M), vt = ltl_general_vt(sa, sb);
+  const int n_chunks = (NG + g_chunk - 1) / g_chunk;
+#define GL_CASE(n, k, v)                                                                      \
+  if (nct == n && ksl == k && vt == v)                                                        \
+    return gl_launch<R, n, k, v>(sa, sb, NW, w0, WT, NG, g_chunk, n_chunks, M, Sa, Sb, Ta,    \
+                                 Tb, Lam_a, Lam_b, Ca, Cb, v0, ex0, lamc, czw, wmask, st);
+#define GL_KSL(n, v) GL_CASE(n, 4, v) GL_CASE(n, 8, v) GL_CASE(n, 13, v) GL_CASE(n, 20, v)
+  GL_KSL(2, 1)
+  GL_KSL(2, 2)
+  GL_KSL(4, 1)
+  GL_KSL(4, 2)
+  GL_CASE(6, 4, 1)
+  GL_CASE(6, 8, 1)
+  GL_CASE(6, 4, 2)
+  GL_CASE(6, 8, 2)
+#undef GL_KSL
+#undef GL_CASE
+}
+}  // namespace
+
+int ltl_general_parts(const DevSpin& sa, const DevSpin& sb) { return ltl_general_nct(sa, sb); }
+
+void launch_ltl_general(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
+                        int g_chunk, int M, const double* Sa, const double* Sb, const cd* Ta,
+                        const cd* Tb, cd* Lam_a, cd* Lam_b, const cd* Ca, const cd* Cb, cd* v0,
+                        cd* ex0, cd* lamc, cd* czw, const int* wmask, hipStream_t st) {
+  gl_dispatch<double>(sa, sb, NW, w0, WT, NG, g_chunk, M, Sa, Sb, Ta, Tb, Lam_a, Lam_b, Ca, Cb,
+                      v0, ex0, lamc, czw, wmask, st);
+}
+
+void launch_ltl_general32(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
+                          int g_chunk, int M, const float* Sa, const float* Sb, const cf* Ta,
+                          const cf* Tb, cf* Lam_a, cf* Lam_b, const cd* Ca, const cd* Cb, cd* v0,
+                          cd* ex0, cd* lamc, cd* czw, hipStream_t st) {
+  gl_dispatch<float>(sa, sb, NW, w0, WT, NG, g_chunk, M, Sa, Sb, Ta, Tb, Lam_a, Lam_b, Ca, Cb, v0,
+                     ex0, lamc, czw, nullptr, st);
+}
+
+// Walkers for the FP64 energy pass of the mixed form: mask[w] = 1 where the
+// largest |T_pj| of either spin exceeds tmax.  One workgroup per walker.
+__global__ __launch_bounds__(256) void k_walker_tmax(int NW, int M, int na, int nb,
+                                                     const cd* __restrict__ Ta,
+                                                     const cd* __restrict__ Tb, double tmax,
+                                                     int* __restrict__ mask) {
+  __shared__ double red[256];
+  const int w = blockIdx.x, tid = threadIdx.x;
+  double m = 0.0;
+  for (int e = tid; e < M * na; e += 256) {
+    const cd t = Ta[((size_t)(e / na) * NW + w) * na + e % na];
+    m = fmax(m, t.re * t.re + t.im * t.im);
+  }
+  for (int e = tid; e < M * nb; e += 256) {
+    const cd t = Tb[((size_t)(e / nb) * NW + w) * nb + e % nb];
+    m = fmax(m, t.re * t.re + t.im * t.im);
+  }
+  red[tid] = m;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (tid < off) red[tid] = fmax(red[tid], red[tid + off]);
+    __syncthreads();
+  }
+  if (tid == 0) mask[w] = red[0] > tmax * tmax ? 1 : 0;
+}
+
+void launch_walker_tmax(int NW, int M, int na, int nb, const cd* Ta, const cd* Tb, double tmax,
+                        int* mask, hipStream_t st) {
+  hipLaunchKernelGGL(k_walker_tmax, dim3(NW), dim3(256), 0, st, NW, M, na, nb, Ta, Tb, tmax, mask);
+}
+
+}  // namespace msd

@@ -1437,7 +1437,8 @@ __global__ __launch_bounds__((MAXK <= 4 ? 1024 : 512)) void k_energy_second(
     int waves_per_block, int NW, int w0, int NG, int n_gsplit, int G, const CT* __restrict__ Lam_a,
     const CT* __restrict__ Lam_b, const cd* __restrict__ coef, const cd* __restrict__ m2a,
     const cd* __restrict__ m2b, const cd* __restrict__ Ba, const cd* __restrict__ Bb,
-    cd* __restrict__ partial, int n_slots, int slot0, bool lds_dma, bool swz) {
+    cd* __restrict__ partial, int n_slots, int slot0, bool lds_dma, bool swz,
+    const int* __restrict__ wmask) {
   constexpr int NIDX = 2 * MAXK > 2 * ER_PPL ? 2 * MAXK : 2 * ER_PPL;
   constexpr int NMM = MAXK * (MAXK - 1) / 2;
   extern __shared__ __align__(16) unsigned char sm_raw[];
@@ -1451,6 +1452,7 @@ __global__ __launch_bounds__((MAXK <= 4 ? 1024 : 512)) void k_energy_second(
   const int logical = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + b / 8;
   const int ib = logical % n_ib, gs = (logical / n_ib) % n_gsplit, wl = logical / (n_ib * n_gsplit);
   const int w = w0 + wl, tid = threadIdx.x, lane = tid & 63;
+  if (wmask && !wmask[w]) return;  // walker not selected for this pass
   // wave index as a scalar: the plan entry, role and spin are then
   // wave-uniform registers and the role branches below are scalar branches
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -1653,14 +1655,15 @@ static void launch_energy_second_t(const DevSpin& sa, const DevSpin& sb, const D
                                    int w0, int WT, int NG, int n_gsplit, int G, int max_order,
                                    bool flat_gather, bool use_dma, bool swz, const CT* Lam_a, const CT* Lam_b, const cd* coef,
                                    const cd* m2a, const cd* m2b, const cd* Ba, const cd* Bb,
-                                   cd* partial, int n_slots, int slot0, hipStream_t st) {
+                                   cd* partial, int n_slots, int slot0, hipStream_t st,
+                                   const int* wmask) {
   if (n_itemblocks == 0) return;
   const size_t lds = 2 * (size_t)G * (sa.nv * sa.no + sb.nv * sb.no) * sizeof(CT);
   const dim3 grid(WT * n_gsplit * n_itemblocks), block(64 * waves_per_block);
 #define MSD_ES(MK, FL)                                                                       \
   hipLaunchKernelGGL((k_energy_second<CT, MK, FL>), grid, block, lds, st, sa, sb, pr, plan,   \
                      n_itemblocks, waves_per_block, NW, w0, NG, n_gsplit, G, Lam_a, Lam_b, coef, \
-                     m2a, m2b, Ba, Bb, partial, n_slots, slot0, lds_dma, swz)
+                     m2a, m2b, Ba, Bb, partial, n_slots, slot0, lds_dma, swz, wmask)
   // direct LDS loads need 16-byte aligned runs: every Lambda row of both spins
   // (and each spin's stage region) starts on a 16-byte boundary
   const int per = 16 / (int)sizeof(CT);
@@ -1678,10 +1681,10 @@ void launch_energy_second(const DevSpin& sa, const DevSpin& sb, const DevPairs& 
                           int WT, int NG, int n_gsplit, int G, int max_order, bool flat_gather,
                           bool use_dma, bool swz, const cd* Lam_a, const cd* Lam_b, const cd* coef,
                           const cd* m2a, const cd* m2b, const cd* Ba, const cd* Bb, cd* partial,
-                          int n_slots, int slot0, hipStream_t st) {
+                          int n_slots, int slot0, hipStream_t st, const int* wmask) {
   launch_energy_second_t<cd>(sa, sb, pr, plan, n_itemblocks, waves_per_block, NW, w0, WT, NG,
                              n_gsplit, G, max_order, flat_gather, use_dma, swz, Lam_a, Lam_b, coef, m2a, m2b, Ba, Bb,
-                             partial, n_slots, slot0, st);
+                             partial, n_slots, slot0, st, wmask);
 }
 
 void launch_energy_second32(const DevSpin& sa, const DevSpin& sb, const DevPairs& pr,
@@ -1692,7 +1695,7 @@ void launch_energy_second32(const DevSpin& sa, const DevSpin& sb, const DevPairs
                             const cd* Bb, cd* partial, int n_slots, int slot0, hipStream_t st) {
   launch_energy_second_t<cf>(sa, sb, pr, plan, n_itemblocks, waves_per_block, NW, w0, WT, NG,
                              n_gsplit, G, max_order, flat_gather, use_dma, swz, Lam_a, Lam_b, coef, m2a, m2b, Ba, Bb,
-                             partial, n_slots, slot0, st);
+                             partial, n_slots, slot0, st, nullptr);
 }
 
 int energy_minor_blocks(const DevSpin& s) {
@@ -1707,6 +1710,67 @@ void launch_energy_minors(const DevSpin& s, int NW, int w0, int WT, int NG, int 
   const size_t lds = 2 * (size_t)G_STAGE * s.nv * s.no * sizeof(cd);
   hipLaunchKernelGGL(k_energy_minors, dim3(WT, n_gsplit, nb), dim3(MINOR_THREADS), lds, st, s, NW,
                      w0, NG, n_gsplit, Lam, coef, partial, n_slots, slot0);
+}
+
+// ============================================================================
+// W-form of the second-order terms (memory bounded by the excitation window)
+// ============================================================================
+// With W^{st}[x][y] = sum_g Lam^{s,g}[x] Lam^{t,g}[y] (x, y window entries), the
+// second-order part of the numerator is
+//   sum_pairs coefAB[x,y] W^{ab}[x][y]
+//   + sum_s sum_minors coef_s[m] (W^{ss}[(a,i)][(b,j)] - W^{ss}[(a,j)][(b,i)]).
+// W comes from a real GEMM over the interleaved (re, im) windows:
+// G[2x + c][2y + d] = sum_g Lam_c[x] Lam_d[y], so W = (G_rr - G_ii) + i (G_ri + G_ir).
+// One workgroup per walker; the sum goes to the walker's energy slot.
+constexpr int WF_THREADS = 256;
+
+__device__ __forceinline__ cd wf_at(const double* __restrict__ G, int ld, int x, int y) {
+  const double* r0 = G + (size_t)(2 * x) * ld + 2 * y;
+  const double* r1 = r0 + ld;
+  return cd{r0[0] - r1[1], r0[1] + r1[0]};
+}
+
+__global__ __launch_bounds__(WF_THREADS) void k_wform_contract(
+    DevSpin sa, DevSpin sb, DevPairs pr, int NW, int w0, const double* __restrict__ Gaa,
+    const double* __restrict__ Gab, const double* __restrict__ Gbb, const cd* __restrict__ coefAB,
+    const cd* __restrict__ coef_a, const cd* __restrict__ coef_b, cd* __restrict__ partial,
+    int n_slots, int slot, const int* __restrict__ wmask) {
+  __shared__ cd red[WF_THREADS];
+  const int wl = blockIdx.x, w = w0 + wl, tid = threadIdx.x;
+  if (wmask && !wmask[w]) return;  // walker not selected for this pass
+  const int Xa = sa.nv * sa.no, Xb = sb.nv * sb.no;
+  const double* ga = Gaa + (size_t)wl * 4 * Xa * Xa;
+  const double* gab = Gab + (size_t)wl * 4 * Xa * Xb;
+  const double* gb = Gbb + (size_t)wl * 4 * Xb * Xb;
+  cd acc{0.0, 0.0};
+  for (int p = tid; p < pr.n_pair; p += WF_THREADS)
+    cfma(acc, coefAB[(size_t)w * pr.n_pair + p], wf_at(gab, 2 * Xb, pr.x[p], pr.y[p]));
+  for (int m = tid; m < sa.n_minor; m += WF_THREADS) {
+    const int* id = sa.mn_idx + 4 * m;
+    cfma(acc, coef_a[(size_t)w * sa.n_minor + m],
+         wf_at(ga, 2 * Xa, id[0], id[1]) - wf_at(ga, 2 * Xa, id[2], id[3]));
+  }
+  for (int m = tid; m < sb.n_minor; m += WF_THREADS) {
+    const int* id = sb.mn_idx + 4 * m;
+    cfma(acc, coef_b[(size_t)w * sb.n_minor + m],
+         wf_at(gb, 2 * Xb, id[0], id[1]) - wf_at(gb, 2 * Xb, id[2], id[3]));
+  }
+  red[tid] = acc;
+  __syncthreads();
+  for (int off = WF_THREADS / 2; off > 0; off >>= 1) {
+    if (tid < off) red[tid] += red[tid + off];
+    __syncthreads();
+  }
+  if (tid == 0) partial[(size_t)w * n_slots + slot] = red[0];
+}
+
+void launch_wform_contract(const DevSpin& sa, const DevSpin& sb, const DevPairs& pr, int NW,
+                           int w0, int WT, const double* Gaa, const double* Gab,
+                           const double* Gbb, const cd* coefAB, const cd* coef_a,
+                           const cd* coef_b, cd* partial, int n_slots, int slot, hipStream_t st,
+                           const int* wmask) {
+  hipLaunchKernelGGL(k_wform_contract, dim3(WT), dim3(WF_THREADS), 0, st, sa, sb, pr, NW, w0, Gaa,
+                     Gab, Gbb, coefAB, coef_a, coef_b, partial, n_slots, slot, wmask);
 }
 
 // ============================================================================
@@ -1726,21 +1790,42 @@ __global__ __launch_bounds__(256) void k_energy_final(DevSpin sa, DevSpin sb, in
                                                       const cd* __restrict__ epart,
                                                       const cd* __restrict__ oba,
                                                       const cd* __restrict__ obb, double e0,
-                                                      cd* __restrict__ e_loc) {
+                                                      cd* __restrict__ e_loc,
+                                                      const cd* __restrict__ lamc, int n_lparts,
+                                                      const int* __restrict__ wmask) {
   __shared__ cd red[256];
   const int wl = blockIdx.x, w = w0 + wl, tid = threadIdx.x, bd = blockDim.x;
+  if (wmask && !wmask[w]) return;  // walker not selected for this pass
   cd vab{0.0, 0.0}, kk{0.0, 0.0};
   const cd* va = v0 + (size_t)w * NG;
   const cd* vb = v0 + ((size_t)NW + w) * NG;
   const cd* xa = ex0 + (size_t)w * NG;
   const cd* xb = ex0 + ((size_t)NW + w) * NG;
+  cd czw{0.0, 0.0};
   for (int g = tid; g < NG; g += bd) {
-    vab += va[g] * vb[g];
-    kk += va[g] * va[g] - xa[g] + vb[g] * vb[g] - xb[g];
+    if (lamc) {
+      // the general contraction kernel writes v0, ex0 and <C^s, Lambda^s> as
+      // per-wave partials [spin][w][g][part]; -(v0_alpha + v0_beta) <C^s,
+      // Lambda^s> of this vector, both spins
+      const size_t oa = ((size_t)w * NG + g) * n_lparts, ob = (((size_t)NW + w) * NG + g) * n_lparts;
+      cd a{0.0, 0.0}, b{0.0, 0.0}, x{0.0, 0.0}, y{0.0, 0.0}, lc{0.0, 0.0};
+      for (int p = 0; p < n_lparts; ++p) {
+        a += v0[oa + p];
+        b += v0[ob + p];
+        x += ex0[oa + p];
+        y += ex0[ob + p];
+        lc += lamc[oa + p] + lamc[ob + p];
+      }
+      vab += a * b;
+      kk += a * a - x + b * b - y;
+      czw -= (a + b) * lc;
+    } else {
+      vab += va[g] * vb[g];
+      kk += va[g] * va[g] - xa[g] + vb[g] * vb[g] - xb[g];
+    }
   }
   cd first = vab + 0.5 * kk;
   first = block_reduce(first, red);
-  cd czw{0.0, 0.0};
   const DevSpin* sp[2] = {&sa, &sb};
   const cd* ZW[2] = {ZWa, ZWb};
   const cd* C[2] = {Ca, Cb};
@@ -1766,10 +1851,11 @@ void launch_energy_final(const DevSpin& sa, const DevSpin& sb, int NW, int w0, i
                          int n_lchunks, int n_echunks, const cd* obar, const cd* v0,
                          const cd* ex0, const cd* ZWpart_a, const cd* ZWpart_b, const cd* Ca,
                          const cd* Cb, const cd* czw, const cd* epart, const cd* onebody_a,
-                         const cd* onebody_b, double e0, cd* e_loc, hipStream_t st) {
+                         const cd* onebody_b, double e0, cd* e_loc, const cd* lamc,
+                         int n_lparts, hipStream_t st, const int* wmask) {
   hipLaunchKernelGGL(k_energy_final, dim3(WT), dim3(256), 0, st, sa, sb, NW, w0, NG, n_lchunks,
                      n_echunks, obar, v0, ex0, ZWpart_a, ZWpart_b, Ca, Cb, czw, epart,
-                     onebody_a, onebody_b, e0, e_loc);
+                     onebody_a, onebody_b, e0, e_loc, lamc, n_lparts, wmask);
 }
 
 // out[g][r][q] = L[g][rows[r]][q]: Cholesky rows restricted to an orbital subset
