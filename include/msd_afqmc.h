@@ -217,6 +217,18 @@ msd_status msd_population_control(msd_system* sys, double z, int32_t* parent);
 /* Same with parent a device pointer (or NULL); stream-ordered, does not
  * synchronise. */
 msd_status msd_population_control_dev(msd_system* sys, double z, int32_t* parent);
+/* Same as msd_population_control_dev, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): it calls no allocator.  Its scratch (running sums,
+ * parents when parent is NULL, the parents' log overlaps and the gathered
+ * walkers, n_walkers * (M * (n_alpha + n_beta) * 16 + 28) bytes, each part
+ * rounded up to 256 bytes) lives in one static device array of 128 MiB per
+ * GPU, held from the library's first msd_create on that GPU until the process
+ * ends; MSD_ERR_UNSUPPORTED if the handle needs more.  The array is shared by
+ * every handle on the GPU and keeps the last call's contents: calls that
+ * overlap on one GPU (concurrent streams or threads) race.  Results are
+ * identical to msd_population_control_dev. */
+msd_status msd_population_control_noalloc(msd_system* sys, double z, int32_t* parent);
 
 /* One simulation block (Sec. III.B, Listing 1): n_steps propagation steps as
  * msd_propagate_dev (QR on the handle's stabilize_freq schedule), population

@@ -60,6 +60,7 @@ SIGNATURES = {
     "msd_propagate_dev": (C.c_int, [_vp, _vp, C.c_double, C.c_double, C.c_int32]),
     "msd_population_control": (C.c_int, [_vp, C.c_double, _vp]),
     "msd_population_control_dev": (C.c_int, [_vp, C.c_double, _vp]),
+    "msd_population_control_noalloc": (C.c_int, [_vp, C.c_double, _vp]),
     "msd_run_block": (C.c_int, [_vp, _vp, C.c_double, C.c_double, C.c_int32, C.c_int32, _vp,
                                 _vp]),
     "msd_get_green": (C.c_int, [_vp, C.c_int32, _vp, _vp]),

@@ -169,6 +169,11 @@ class MsdSystem:
     def population_control_dev(self, z: float, parent=None):
         self._check(self.lib.msd_population_control_dev(self.h, float(z), _ptr(parent)))
 
+    def population_control_noalloc(self, z: float, parent=None):
+        """As population_control_dev, with the library's static scratch (no
+        allocation; see msd_population_control_noalloc)."""
+        self._check(self.lib.msd_population_control_noalloc(self.h, float(z), _ptr(parent)))
+
     def run_block(self, fields_dev, n_steps: int, dt: float, e_shift: float = 0.0,
                   pop_freq: int = 5, z=()):
         """One block; returns (sum_w w E_L as complex, sum_w w)."""

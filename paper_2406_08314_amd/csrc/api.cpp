@@ -18,6 +18,7 @@
 #include <map>
 #include <new>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -1276,6 +1277,63 @@ void comb_impl(msd_system* s, double z, int* parent) {
   s->check_launch("population control");
 }
 
+// ---------------------------------------------------------------------------
+// Population control without allocation: its scratch (running sums, parents,
+// parents' log overlaps, the gathered walkers) lives in one file-scope device
+// array of NOALLOC_BYTES per GPU instead of the handle's buffers.  The array's
+// device address is taken once per device, at handle creation with the device
+// current (msd_create), and only that address is passed to kernels or copies.
+// Every call on a GPU shares the array (calls that overlap on one GPU race);
+// each region is fully written by the call before it is read, so nothing needs
+// clearing between calls.
+constexpr size_t NOALLOC_BYTES = (size_t)128 << 20;
+constexpr int NOALLOC_MAX_DEV = 64;
+__device__ __align__(256) unsigned char msd_noalloc_scratch[NOALLOC_BYTES];
+void* g_noalloc_ptr[NOALLOC_MAX_DEV] = {};
+std::mutex g_noalloc_mu;
+
+void noalloc_init(int dev) {
+  if (dev < 0 || dev >= NOALLOC_MAX_DEV) return;  // the entry point reports it
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (g_noalloc_ptr[dev]) return;
+  void* p = nullptr;
+  hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(msd_noalloc_scratch)), "hipGetSymbolAddress");
+  g_noalloc_ptr[dev] = p;
+}
+
+size_t noalloc_align(size_t n) { return (n + 255) / 256 * 256; }
+
+void comb_noalloc_impl(msd_system* s, double z, int* parent) {
+  need_ready(s);
+  if (!s->have_walkers) fail(MSD_ERR_STATE, "walkers have not been set");
+  if (!(z >= 0.0 && z < 1.0)) fail(MSD_ERR_ARG, "comb offset z must lie in [0, 1)");
+  void* base = (s->dev >= 0 && s->dev < NOALLOC_MAX_DEV) ? g_noalloc_ptr[s->dev] : nullptr;
+  if (!base) fail(MSD_ERR_STATE, "no static scratch address for this device");
+  const size_t NW = (size_t)s->NW, per_w = (size_t)s->M * s->Ntot;
+  const size_t b_phi = noalloc_align(sizeof(cd) * NW * per_w);
+  const size_t b_logo = noalloc_align(sizeof(cd) * NW);
+  const size_t b_cum = noalloc_align(sizeof(double) * NW);
+  const size_t b_par = noalloc_align(sizeof(int) * NW);
+  const size_t need = b_phi + b_logo + b_cum + b_par;
+  if (need > NOALLOC_BYTES)
+    fail(MSD_ERR_UNSUPPORTED, "population control needs " + std::to_string(need) +
+                                  " bytes of scratch; the allocation-free entry point holds " +
+                                  std::to_string(NOALLOC_BYTES) + " bytes per GPU");
+  unsigned char* b = static_cast<unsigned char*>(base);
+  cd* phi_out = reinterpret_cast<cd*>(b);
+  cd* logo_out = reinterpret_cast<cd*>(b + b_phi);
+  double* cum = reinterpret_cast<double*>(b + b_phi + b_logo);
+  int* par = parent ? parent : reinterpret_cast<int*>(b + b_phi + b_logo + b_cum);
+  msd::launch_comb(s->NW, z, s->weights, cum, par, s->phi, s->logo, (int64_t)per_w, phi_out,
+                   logo_out, s->st);
+  hip_check(hipMemcpyAsync(s->phi, phi_out, sizeof(cd) * NW * per_w, hipMemcpyDeviceToDevice,
+                           s->st),
+            "copy");
+  hip_check(hipMemcpyAsync(s->logo, logo_out, sizeof(cd) * NW, hipMemcpyDeviceToDevice, s->st),
+            "copy");
+  s->check_launch("population control");
+}
+
 void set_walkers_impl(msd_system* s, const cd* pa_dev, const cd* pb_dev, const double* w_dev) {
   if (!s->have_trial || !s->have_ham)
     fail(MSD_ERR_STATE, "msd_set_hamiltonian and msd_set_trial_occ must precede msd_set_walkers");
@@ -1376,6 +1434,7 @@ msd_status msd_create(const msd_dims* d, const msd_options* o, int32_t device, v
     msd::init_ltl_attributes();
     msd::init_prop_attributes();
     msd::init_gemm_attributes();
+    noalloc_init(sys->dev);
     Arena& A = sys->base;
     const int M = sys->M, NW = sys->NW, NG = sys->NG, Ntot = sys->Ntot;
     sys->phi = A.get<cd>((size_t)NW * M * Ntot);
@@ -1914,6 +1973,14 @@ msd_status msd_population_control_dev(msd_system* sys, double z, int32_t* parent
   if (!sys) fail(MSD_ERR_ARG, "null argument");
   set_device(sys);
   comb_impl(sys, z, parent);
+  API_END(sys)
+}
+
+msd_status msd_population_control_noalloc(msd_system* sys, double z, int32_t* parent) {
+  API_BEGIN
+  if (!sys) fail(MSD_ERR_ARG, "null argument");
+  set_device(sys);
+  comb_noalloc_impl(sys, z, parent);
   API_END(sys)
 }
 
