@@ -89,6 +89,14 @@ def stage_work(wl, lib_sys, stage):
         for N, nv in ((na, tt["nv"][0]), (nb, tt["nv"][1])):
             f += NW * NG * (4.0 * (N + nv) * N * M + 2 * 8.0 * nv * N * N)
         return f, "flop", "mfma"
+    if stage == "lambda" and lib_sys.get_tuning()["lambda_variant"] == 6:
+        # general fused contraction kernel: per walker, vector and spin LT =
+        # L[R u V, :] T (4 P N M flop, real L times complex T, P = N + nv), Lambda
+        # = T[V, :] Q (8 nv N N) and D = C Q_W^T for <C, Lambda Q> (8 nv no N)
+        f = 0.0
+        for N, nv, no in ((na, tt["nv"][0], tt["no"][0]), (nb, tt["nv"][1], tt["no"][1])):
+            f += NW * NG * (4.0 * (N + nv) * N * M + 8.0 * nv * N * N + 8.0 * nv * no * N)
+        return f, "flop", "mfma"
     if stage == "traces":
         # Q = L[R, :] T (4 N N M flop) and tr QQ (8 N N) per walker, vector, spin
         return sum(NW * NG * (4.0 * N * N * M + 8.0 * N * N) for N in (na, nb)), "flop", "mfma"
@@ -102,6 +110,11 @@ def stage_work(wl, lib_sys, stage):
             b += NW * NG * 16.0 * ((N + nv) * N + nv * no) + NW * n_chunks * nv * no * 16.0
         b += 2 * 2 * NW * NG * 16.0
         return b, "byte", "hbm"
+    if stage == "energy_gamma" and lib_sys.get_tuning()["energy_form"] == 1:
+        # W-form: per walker and Cholesky vector, the real GEMMs of the
+        # interleaved windows give W^{ab}, W^{aa}, W^{bb} (8 flop per complex MAC)
+        xa, xb = tt["nv"][0] * tt["no"][0], tt["nv"][1] * tt["no"][1]
+        return NW * NG * 8.0 * (xa * xa + xa * xb + xb * xb), "flop", "mfma"
     if stage == "energy_gamma":
         # per walker and Cholesky vector: one complex MAC per opposite-spin
         # pair; per string of order k, k(k-1)/2 x k(k-1)/2 two-by-two minors of
@@ -231,14 +244,24 @@ def run_config(name, args, torch, stages=True, block=True):
         local energies of the initial walkers (same input for both forms)."""
         s = system(False, precision)
         e_init = s.measure(wl.dt)["e_loc"]
-        tunings[precision] = s.get_tuning() if args.no_autotune else s.autotune(wl.dt, reps=3)
+        tunings[precision] = s.autotune(wl.dt, reps=3) if args.autotune else s.get_tuning()
         for k in range(args.warmup):
             step(s, k)
         ms, wall = timed(lambda k: step(s, args.warmup + k), args.steps)
         ms_meas, _ = timed(lambda k: s.measure_dev(wl.dt, lo, fb, el), args.steps)
         ms_prop, _ = timed(lambda k: s.propagate_dev(fields[k % n_total].reshape(-1), wl.dt,
                                                      0.0, 1), args.steps)
-        extra[precision] = {"propagate_only_ms": round(ms_prop / args.steps, 4)}
+        # walkers far from the reference at this point (max |T| above the mixed
+        # form's threshold: those get FP64 energies in the mixed form)
+        pa, pb, _, _ = s.get_walkers()
+        far = int(np.sum(_tmax(pa, wl.n_alpha, pb, wl.n_beta) > 2.0))
+        # the measurement on the initial walkers (near the reference)
+        s.set_walkers(wl.phi_a, wl.phi_b, wl.weights)
+        s.measure_dev(wl.dt, lo, fb, el)
+        ms_init, _ = timed(lambda k: s.measure_dev(wl.dt, lo, fb, el), args.steps)
+        extra[precision] = {"propagate_only_ms": round(ms_prop / args.steps, 4),
+                            "measure_initial_ms": round(ms_init / args.steps, 4),
+                            "walkers_far_from_reference_after_steps": far}
         if block:
             # the paper's block shape: 25 propagation steps, population control
             # every 5, one measurement (weighted block energy), on the
@@ -266,6 +289,11 @@ def run_config(name, args, torch, stages=True, block=True):
                     "measure_only_ms": round(mx_meas, 4),
                     "speedup_vs_fp64": round(ms_step / mx_step, 3),
                     "measure_speedup_vs_fp64": round(ms_meas / mx_meas, 3),
+                    "measure_initial_speedup_vs_fp64": round(
+                        extra["fp64"]["measure_initial_ms"] / extra["mixed"]["measure_initial_ms"], 3),
+                    "note": "walkers with max|T| > 2 (T = Phi A^-1 relative to the reference) get "
+                            "FP64 energies in the mixed form; the synthetic trajectories leave the "
+                            "reference after the first step, the initial walkers stay near it",
                     "max_abs_dE_L_mHa": float(np.max(np.abs(emx - e64))) * 1e3,
                     "error_sample": f"all {wl.n_walkers} walkers, one measurement of the "
                                     f"initial walkers",
@@ -299,6 +327,70 @@ def run_config(name, args, torch, stages=True, block=True):
     return res
 
 
+def run_uneven(args, torch, steps=3, warmup=1):
+    """The uneven batch of 32 independent systems: one batch step (propagate +
+    measure every system) replayed as one HIP graph with a branch per system,
+    against the same systems stepped one after another (each with its own
+    graph replay), FP64 and mixed forms."""
+    from paper_2406_08314_amd import MsdBatch, MsdSystem
+    from synth import fields_for_step, make_uneven
+
+    wls = make_uneven()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    fields = [torch.from_numpy(fields_for_step(wl, 0)).to(dev) for wl in wls]
+    nwd = sum(wl.n_walkers * wl.n_det for wl in wls)
+    dt = wls[0].dt
+
+    def timed(fn, n):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(n):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    out = {"systems": len(wls), "walker_det_per_step": nwd,
+           "shapes": "M 38-199, N 4-30 per spin, 5M Cholesky vectors, 151-90,740 "
+                     "determinants (orders <= 4), 71-496 walkers"}
+    for precision in ("fp64", "mixed"):
+        systems = []
+        for wl in wls:
+            s = MsdSystem(wl.M, wl.n_alpha, wl.n_beta, wl.n_chol, wl.n_walkers, wl.n_det,
+                          device=0, stream=stream.cuda_stream, graphs=True, precision=precision)
+            s.set_hamiltonian(wl.h1, wl.chol, wl.e0)
+            s.set_trial(wl.ci, wl.occ_a, wl.occ_b)
+            s.set_walkers(wl.phi_a, wl.phi_b, wl.weights)
+            systems.append(s)
+        b = MsdBatch(systems, stream=stream.cuda_stream)
+        eloc = [torch.empty(wl.n_walkers, dtype=torch.complex128, device=dev) for wl in wls]
+
+        def batch_step():
+            b.step(fields, dt, 0.0, measure=True)
+
+        def separate():
+            for s, f, e in zip(systems, fields, eloc):
+                s.propagate_dev(f.reshape(-1), dt, 0.0, 1)
+                s.measure_dev(dt, e_loc=e)
+
+        for _ in range(warmup):
+            batch_step()
+            separate()
+        ms_b = timed(batch_step, steps)
+        ms_s = timed(separate, steps)
+        out[precision] = {"batch_graph_ms": round(ms_b, 3), "separate_ms": round(ms_s, 3),
+                          "value": nwd / (ms_b * 1e-3), "unit": "walker*det/s",
+                          "speedup_vs_separate": round(ms_s / ms_b, 3)}
+        b.close()
+        for s in systems:
+            s.close()
+    out["mixed_speedup_vs_fp64"] = round(out["fp64"]["batch_graph_ms"] /
+                                         out["mixed"]["batch_graph_ms"], 3)
+    return out
+
+
 def roofline(wl, s, stages, t):
     """Roofline record of the most expensive stage that has a work model."""
     for name in sorted(stages, key=lambda k: -stages[k][0]):
@@ -321,7 +413,8 @@ def roofline(wl, s, stages, t):
             if prof and (not prof[1] or prof[1] == (t["lambda_chunk"],)):
                 traffic = prof[0]
         lam_kernel = {1: "k_lambda_rows", 2: "k_lambda_wave", 3: "k_lambda_wave",
-                      4: "k_lambda_mfma", 5: "k_ltl_mfma"}.get(t["lambda_variant"], "k_lambda")
+                      4: "k_lambda_mfma", 5: "k_ltl_mfma",
+                      6: "k_ltl_general"}.get(t["lambda_variant"], "k_lambda")
         kernel = {"energy_gamma": "k_energy_second", "lambda": lam_kernel, "traces": "k_qtr",
                   "lt_gemm": "k_gemm_f64 (LT)"}.get(name, name)
         return {"kernel": kernel, "stage": name, "bound": bound, "achieved": round(ach, 3),
@@ -340,8 +433,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the secondary Medium record of the default run")
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="keep the library's default launch shapes (for counter runs)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="run the library's autotuner before timing (default: the library's "
+                         "own launch-shape heuristics, the shapes the committed profiles cover)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain elementwise copy kernel over MIB MiB (for "
                          "scaling rocprofv3 FETCH_SIZE/WRITE_SIZE counters) and exit")
@@ -391,7 +485,8 @@ def main():
     if args.config != "medium" and not args.no_secondary:
         m = run_config("medium", args, torch, stages=False, block=False)
         m.pop("wl")
-        line["secondary"] = {"medium": {"workload": WORKLOADS["medium"], **m}}
+        line["secondary"] = {"medium": {"workload": WORKLOADS["medium"], **m},
+                             "uneven_batch": run_uneven(args, torch)}
     if not args.no_cpu_baseline:
         n_det = 120 if args.config in ("cu_oxo", "fe2s2") else None
         n_walk = 2 if args.config in ("cu_oxo", "fe2s2") else 24
@@ -399,6 +494,18 @@ def main():
         if args.config in ("cu_oxo", "fe2s2"):
             line["cpu_wick"] = cpu_wick(wl, n_walk=2 if args.config == "cu_oxo" else 1)
     print(json.dumps(line), flush=True)
+
+
+def _tmax(pa, na, pb, nb):
+    """Largest |T_pj| per walker over both spins, T = Phi Phi[R, :]^-1 with the
+    reference R = the first N orbitals."""
+    out = np.zeros(pa.shape[0])
+    for w in range(pa.shape[0]):
+        for phi, n in ((pa[w], na), (pb[w], nb)):
+            if n:
+                t = np.linalg.solve(phi[:n].T, phi.T).T
+                out[w] = max(out[w], np.abs(t).max())
+    return out
 
 
 def _tables(wl):

@@ -97,8 +97,10 @@ typedef struct {
                              Cholesky-vector sums of the second-order energy terms in
                              FP32; the reference inverse, k x k determinants and
                              cofactors, Taylor propagator, QR, overlaps and weights
-                             stay FP64.  Energies of trials with excitation orders
-                             above 6 per spin are evaluated in FP64.                 */
+                             stay FP64.  Walkers far from the reference get FP64
+                             energies (see mixed_tmax).  Trials with excitation orders
+                             above 6 per spin are evaluated in FP64 unless the W-form
+                             applies (see energy_algo).                               */
   double mixed_tmax;      /* mixed form with the general contraction kernel: a walker
                              whose largest |T_pj| (T = Phi A^{-1}, the ratios of its
                              single-excitation overlaps to the reference overlap, Sec.
@@ -269,7 +271,10 @@ typedef struct {
                              most 64 active virtuals, else as 2), 5 = matrix-core kernel
                              that also forms the Cholesky contraction L^g T itself, so
                              it never goes through HBM (shapes of 4 with M <= 64, else
-                             as 4).  2-5 need N <= 16                                  */
+                             as 4), 6 = general matrix-core kernel forming L^g T, Q,
+                             Lambda and the first-order contraction for up to 48
+                             electrons per spin, M <= 320 and windows of at most 32 x 32
+                             (the default where 5 does not apply).  2-5 need N <= 16   */
   int32_t lambda_chunk;   /* Cholesky vectors per intermediates workgroup (1..NG); the
                              fused kernel's workgroup holds four walkers x two spins   */
   int32_t second_gsplit;  /* Cholesky-range split of the second-order kernel (1..64)      */
@@ -285,7 +290,10 @@ typedef struct {
   int32_t walker_tile;    /* walkers per pass of the energy stages (1..n_walkers); small
                              tiles keep the LT and Lambda intermediates of a pass in the
                              last-level cache                                            */
-  int32_t reserved[3];
+  int32_t energy_form;    /* read-only (msd_get_tuning): 1 when the second-order terms
+                             run in the W-form (see energy_algo), 0 for the direct form;
+                             ignored by msd_set_tuning                                     */
+  int32_t reserved[2];
 } msd_tuning;
 msd_status msd_get_tuning(msd_system* sys, msd_tuning* out);
 /* Sets overrides (validated; MSD_ERR_ARG names the bad field).  Drops the
@@ -311,8 +319,9 @@ msd_status msd_get_measurement(msd_system* sys, double* log_ovlp, double* force_
  * if do_measure, one measurement (as msd_measure_dev with energies), all on
  * the batch's stream.  With timing off on every system the whole step is
  * recorded once as one HIP graph (per combination of QR steps, measurement
- * flag, dt and e_shift) and replayed afterwards; graphs are re-recorded after
- * any system's trial or Hamiltonian changes.  The systems must be on one
+ * flag, dt and e_shift) in which each system's launches form an independent
+ * branch (so small systems can run side by side), and replayed afterwards;
+ * graphs are re-recorded after any system's trial or Hamiltonian changes.  The systems must be on one
  * device and stay alive until msd_batch_destroy; they may still be used on
  * their own between batch steps (the batch orders itself against each
  * system's stream with events).  A batch is not thread-safe.

@@ -26,7 +26,8 @@ class MsdTuning(C.Structure):
                 ("lambda_chunk", C.c_int32), ("second_gsplit", C.c_int32),
                 ("second_stage", C.c_int32), ("second_gather", C.c_int32),
                 ("second_copy", C.c_int32), ("second_waves", C.c_int32),
-                ("walker_tile", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("walker_tile", C.c_int32), ("energy_form", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
 
 
 class MsdOptions(C.Structure):

@@ -202,7 +202,7 @@ class MsdSystem:
         return out
 
     _TUNING = ("fb_splitk", "lambda_variant", "lambda_chunk", "second_gsplit", "second_stage",
-               "second_gather", "second_copy", "second_waves", "walker_tile")
+               "second_gather", "second_copy", "second_waves", "walker_tile", "energy_form")
 
     def get_tuning(self):
         t = _lib.MsdTuning()
@@ -213,8 +213,8 @@ class MsdSystem:
         """Launch-shape overrides (0 = automatic); see msd_tuning."""
         t = _lib.MsdTuning()
         for k, v in kw.items():
-            if k not in self._TUNING:
-                raise ValueError(f"unknown tuning field {k}")
+            if k not in self._TUNING or k == "energy_form":
+                raise ValueError(f"unknown or read-only tuning field {k}")
             setattr(t, k, int(v))
         self._check(self.lib.msd_set_tuning(self.h, C.byref(t)))
 

@@ -174,7 +174,7 @@ struct msd_system {
   // general fused contraction kernel (N <= 48 per spin, M <= 320, window of
   // at most 32 virtual and 32 occupied orbitals): rows of L per spin, k-major,
   // [NG][Mpad][P16], window virtual rows then reference rows
-  bool gl_fits = false;
+  bool gl_fits = false, gl_fits32 = false;  // FP64 / FP32 instances apply
   double* Sgl[2] = {nullptr, nullptr};
   float* Sgl32[2] = {nullptr, nullptr};
   cd* lamc = nullptr;  // [2][NW][NG][gl_parts]: <C, Lambda window> per vector
@@ -183,7 +183,8 @@ struct msd_system {
   // tmax get FP64 energies in a second, masked pass (FP64 Lambda windows)
   double tmax = 2.0;
   bool guard = false;
-  int* gmask = nullptr;  // [NW]
+  int* gmask = nullptr;  // [NW] 1: FP64 pass
+  int* fmask = nullptr;  // [NW] 1: single-precision pass (the complement of gmask)
   int second_G64 = 1;    // LDS stage depth of the FP64 second-order pass
   int gl_chunk_guard = 1, n_lchunks_guard = 0;  // finer vector chunks: few walkers
   // W-form of the second-order terms: per-walker GEMMs over the Cholesky index
@@ -378,7 +379,7 @@ void build_derived(msd_system* s) {
       R.nv = 0;
       msd::launch_gather_ltl(s->L, s->NG, s->M, R, 8, s->Slr[sp], nullptr, s->st);
     }
-  if (s->gl_fits)
+  if (s->gl_fits || s->gl_fits32)
     for (int sp = 0; sp < 2; ++sp)
       msd::launch_gather_general(s->L, s->NG, s->M, s->ds[sp], s->ds[0], s->ds[1], s->Sgl[sp],
                                  s->Sgl32[sp], s->st);
@@ -495,7 +496,7 @@ void alloc_energy(msd_system* s) {
     const bool cc = s->o.energy_algo == 3 && msd::chol_contract_fits(A, B, &wb_cc);
     const bool fused_ok =
         s->lambda_exact && !cc && (s->energy_mixed ? s->lf_fits32 : s->lf_fits64);
-    const bool gen_ok = s->gl_fits && !cc;
+    const bool gen_ok = (s->energy_mixed ? s->gl_fits32 : s->gl_fits) && !cc;
     const int want = s->tune.lambda_variant ? s->tune.lambda_variant
                      : fused_ok                 ? 5
                      : gen_ok                   ? 6
@@ -606,13 +607,13 @@ void alloc_energy(msd_system* s) {
     s->coef2[sp] = E.get<cd>((size_t)NW * D.n_minor);
   }
   // the mixed form's FP64 pass for walkers far from the reference (general kernel)
-  s->guard = s->energy_mixed && s->lambda_variant == 6 && s->tmax > 0.0;
+  s->guard = s->energy_mixed && s->lambda_variant == 6 && s->gl_fits && s->tmax > 0.0;
   if (s->guard) {
     for (int sp = 0; sp < 2; ++sp)
       s->Lam[sp] = E.get<cd>((size_t)wt * NG * s->ds[sp].nv * s->ds[sp].no);
-    // the FP64 pass usually has few walkers: split their vectors finely so
-    // they still fill the chip
-    const int n_chunks = std::max(1, std::min(NG, 32));
+    // the FP64 pass may have few walkers: split their vectors more finely so
+    // that a handful of walkers still spreads over the chip
+    const int n_chunks = std::max(1, std::min(NG, 8));
     s->gl_chunk_guard = (NG + n_chunks - 1) / n_chunks;
     s->n_lchunks_guard = (NG + s->gl_chunk_guard - 1) / s->gl_chunk_guard * s->gl_parts;
     const int X = A.nv * A.no + B.nv * B.no;
@@ -783,6 +784,8 @@ void run_wform(msd_system* s, int w0, int wt, bool fp32, const int* wmask);
 void run_energy_mixed(msd_system* s) {
   const msd::DevSpin& A = s->ds[0];
   const msd::DevSpin& B = s->ds[1];
+  // with the FP64 pass, the single-precision kernels skip the walkers it takes
+  const int* fm = s->guard ? s->fmask : nullptr;
   int nmax = 0;
   msd::lambda_rows_fits(A, B, &nmax);
   s->timed(ST_LT_GEMM, [&] {
@@ -840,7 +843,7 @@ void run_energy_mixed(msd_system* s) {
       if (s->lambda_variant == 6) {
         msd::launch_ltl_general32(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, s->M, s->Sgl32[0],
                                   s->Sgl32[1], Ta, Tb, s->Lam32[0], s->Lam32[1], s->sw[0].C,
-                                  s->sw[1].C, s->v0, s->ex0, s->lamc, s->czw, s->st);
+                                  s->sw[1].C, s->v0, s->ex0, s->lamc, s->czw, fm, s->st);
       } else if (s->lambda_variant == 5) {
         msd::launch_ltl_mfma32(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, s->M, s->Slf32[0],
                                s->Slf32[1], Ta, Tb, s->Lam32[0], s->Lam32[1], s->v0, s->sw[0].C,
@@ -870,7 +873,7 @@ void run_energy_mixed(msd_system* s) {
     }
     s->timed(ST_EGAMMA, [&] {
       if (s->wform) {
-        run_wform(s, w0, wt, true, nullptr);
+        run_wform(s, w0, wt, true, fm);
         return;
       }
       msd::launch_energy_second32(A, B, s->dp, s->plan, s->n_itemblocks, s->second_waves, s->NW,
@@ -878,14 +881,15 @@ void run_energy_mixed(msd_system* s) {
                                   s->second_flat, s->second_dma, s->lam_swz,
                                   s->Lam32[0],
                                   s->Lam32[1], s->coefAB, s->sw[0].m2, s->sw[1].m2, s->sw[0].B,
-                                  s->sw[1].B, s->epart, s->n_slots, s->slot_second, s->st);
+                                  s->sw[1].B, s->epart, s->n_slots, s->slot_second, s->st, fm);
     });
     s->timed(ST_EFINAL, [&] {
       msd::launch_energy_final(A, B, s->NW, w0, wt, s->NG, s->n_lchunks, s->n_slots, s->obar,
                                s->v0, s->ex0, s->ZWp[0], s->ZWp[1], s->sw[0].C, s->sw[1].C,
                                s->lambda_variant >= 5 ? s->czw : nullptr, s->epart, s->onebody,
                                s->onebody + s->NW, s->e0, s->eloc,
-                               s->lambda_variant == 6 ? s->lamc : nullptr, s->gl_parts, s->st);
+                               s->lambda_variant == 6 ? s->lamc : nullptr, s->gl_parts, s->st,
+                               fm);
     });
   }
   s->check_launch("energy");
@@ -950,14 +954,12 @@ void run_wform(msd_system* s, int w0, int wt, bool fp32, const int* wmask) {
 // Mixed form: FP64 local energies for the walkers whose largest |T| exceeds
 // tmax (the FP32 rounding of Q, Lambda and their products grows with |T|^2),
 // through the general contraction kernel and the FP64 second-order kernel,
-// every kernel skipping the walkers the mask leaves out.  Runs after the
-// mixed pass and overwrites those walkers' energies.
+// every kernel skipping the walkers the mask leaves out (the single-precision
+// pass skips exactly these walkers, so each walker is evaluated once).
 void run_energy_guard(msd_system* s) {
   const msd::DevSpin& A = s->ds[0];
   const msd::DevSpin& B = s->ds[1];
   s->timed(ST_GUARD, [&] {
-    msd::launch_walker_tmax(s->NW, s->M, A.N, B.N, s->sw[0].T, s->sw[1].T, s->tmax, s->gmask,
-                            s->st);
     for (int w0 = 0; w0 < s->NW; w0 += s->WT) {
       const int wt = std::min(s->WT, s->NW - w0);
       msd::launch_ltl_general(A, B, s->NW, w0, wt, s->NG, s->gl_chunk_guard, s->M, s->Sgl[0],
@@ -994,6 +996,11 @@ void run_energy(msd_system* s) {
                                s->coef2[sp], s->st);
   });
   if (s->energy_mixed) {
+    if (s->guard)  // which walkers go to the FP64 pass (gmask) and which stay (fmask)
+      s->timed(ST_GUARD, [&] {
+        msd::launch_walker_tmax(s->NW, s->M, A.N, B.N, s->sw[0].T, s->sw[1].T, s->tmax,
+                                s->gmask, s->fmask, s->st);
+      });
     run_energy_mixed(s);
     if (s->guard) run_energy_guard(s);
     return;
@@ -1449,6 +1456,7 @@ msd_status msd_create(const msd_dims* d, const msd_options* o, int32_t device, v
     sys->flag = A.get<int>(NW);
     sys->mask = A.get<int>(NW);
     sys->gmask = A.get<int>(NW);
+    sys->fmask = A.get<int>(NW);
     sys->qr_ldet = A.get<double>(2 * (size_t)NW);
     sys->xraw = A.get<double>((size_t)NG * 2 * NW);
     sys->xbar = A.get<cd>((size_t)NW * NG);
@@ -1721,11 +1729,13 @@ void set_trial_rows(msd_system* sys, const double* ci, const int32_t* occ_a,
     sys->Slf32[sp] = sys->lf_fits32 ? T.get<float>(n) : nullptr;
     sys->Slr[sp] = (sys->lf_fits64 || sys->lf_fits32) ? T.get<double>((size_t)NG * 64 * 8) : nullptr;
   }
-  sys->gl_fits = msd::ltl_general_fits(sys->ds[0], sys->ds[1], M);
+  sys->gl_fits = msd::ltl_general_fits(sys->ds[0], sys->ds[1], M, false);
+  sys->gl_fits32 = sys->mixed && msd::ltl_general_fits(sys->ds[0], sys->ds[1], M, true);
   for (int sp = 0; sp < 2; ++sp) {
-    const size_t n = sys->gl_fits ? msd::ltl_general_s_elems(sys->ds[0], sys->ds[1], M, NG) : 0;
+    const size_t n = (sys->gl_fits || sys->gl_fits32)
+                         ? msd::ltl_general_s_elems(sys->ds[0], sys->ds[1], M, NG) : 0;
     sys->Sgl[sp] = sys->gl_fits ? T.get<double>(n) : nullptr;
-    sys->Sgl32[sp] = sys->gl_fits && sys->mixed ? T.get<float>(n) : nullptr;
+    sys->Sgl32[sp] = sys->gl_fits32 ? T.get<float>(n) : nullptr;
   }
   if (sys->mixed) {
     sys->Gp32 = T.get<float>((size_t)2 * NW * sys->P_all * M);
@@ -2095,6 +2105,11 @@ struct msd_batch {
   hipStream_t cap_st = nullptr;
   hipEvent_t ev = nullptr;
   std::vector<msd_system*> sys;
+  // one capture branch per system: the graph holds the systems' launch
+  // chains as independent branches (forked from and joined to cap_st), so
+  // the runtime may run the systems concurrently
+  std::vector<hipStream_t> br_st;
+  std::vector<hipEvent_t> fork_ev, join_ev;
   struct Entry {
     std::vector<uint64_t> versions;
     hipGraphExec_t exec = nullptr;
@@ -2128,8 +2143,23 @@ msd_status msd_batch_create(msd_system* const* systems, int32_t n, void* hip_str
     hip_check(hipSetDevice(b->dev), "hipSetDevice");
     hip_check(hipStreamCreateWithFlags(&b->cap_st, hipStreamNonBlocking), "stream");
     hip_check(hipEventCreateWithFlags(&b->ev, hipEventDisableTiming), "event");
+    b->br_st.assign(n, nullptr);
+    b->fork_ev.assign(n, nullptr);
+    b->join_ev.assign(n, nullptr);
+    for (int i = 0; i < n; ++i) {
+      hip_check(hipStreamCreateWithFlags(&b->br_st[i], hipStreamNonBlocking), "stream");
+      hip_check(hipEventCreateWithFlags(&b->fork_ev[i], hipEventDisableTiming), "event");
+      hip_check(hipEventCreateWithFlags(&b->join_ev[i], hipEventDisableTiming), "event");
+    }
   } catch (...) {
     if (b->cap_st) (void)hipStreamDestroy(b->cap_st);
+    for (hipStream_t x : b->br_st)
+      if (x) (void)hipStreamDestroy(x);
+    for (hipEvent_t x : b->fork_ev)
+      if (x) (void)hipEventDestroy(x);
+    for (hipEvent_t x : b->join_ev)
+      if (x) (void)hipEventDestroy(x);
+    if (b->ev) (void)hipEventDestroy(b->ev);
     delete b;
     b = nullptr;
     throw;
@@ -2144,6 +2174,12 @@ void msd_batch_destroy(msd_batch* b) {
   (void)hipStreamSynchronize(b->st);
   b->drop();
   if (b->cap_st) (void)hipStreamDestroy(b->cap_st);
+  for (hipStream_t x : b->br_st)
+    if (x) (void)hipStreamDestroy(x);
+  for (hipEvent_t x : b->fork_ev)
+    if (x) (void)hipEventDestroy(x);
+  for (hipEvent_t x : b->join_ev)
+    if (x) (void)hipEventDestroy(x);
   if (b->ev) (void)hipEventDestroy(b->ev);
   delete b;
 }
@@ -2191,11 +2227,19 @@ msd_status msd_batch_step(msd_batch* b, const double* const* fields, double dt, 
   char buf[64];
   std::snprintf(buf, sizeof buf, "|%.17g|%.17g", dt, e_shift);
   key += buf;
-  auto body = [&](hipStream_t st) {
+  // branches: capture each system's launches on its own stream, forked from
+  // and joined to st (graph capture); otherwise one after another on st
+  auto body = [&](hipStream_t st, bool branches) {
     for (int i = 0; i < n; ++i) {
       msd_system* s = b->sys[i];
       hipStream_t own = s->st;
-      s->st = st;
+      hipStream_t run = st;
+      if (branches) {
+        hip_check(hipEventRecord(b->fork_ev[i], st), "fork");
+        hip_check(hipStreamWaitEvent(b->br_st[i], b->fork_ev[i], 0), "fork");
+        run = b->br_st[i];
+      }
+      s->st = run;
       try {
         propagate_step(s, s->fields, dt, e_shift, qr[i]);
         if (do_measure) measure_body(s, dt, true);
@@ -2204,10 +2248,14 @@ msd_status msd_batch_step(msd_batch* b, const double* const* fields, double dt, 
         throw;
       }
       s->st = own;
+      if (branches) {
+        hip_check(hipEventRecord(b->join_ev[i], run), "join");
+        hip_check(hipStreamWaitEvent(st, b->join_ev[i], 0), "join");
+      }
     }
   };
   if (timing) {
-    body(b->st);  // timing events cannot live in a graph: run the launches directly
+    body(b->st, false);  // timing events cannot live in a graph: run the launches directly
   } else {
     std::vector<uint64_t> versions(n);
     for (int i = 0; i < n; ++i) versions[i] = b->sys[i]->version;
@@ -2220,7 +2268,7 @@ msd_status msd_batch_step(msd_batch* b, const double* const* fields, double dt, 
       hipGraph_t g = nullptr;
       hip_check(hipStreamBeginCapture(b->cap_st, hipStreamCaptureModeThreadLocal), "begin capture");
       try {
-        body(b->cap_st);
+        body(b->cap_st, true);
       } catch (...) {
         (void)hipStreamEndCapture(b->cap_st, &g);
         if (g) (void)hipGraphDestroy(g);
@@ -2272,6 +2320,7 @@ void set_tuning_impl(msd_system* s, const msd_tuning& t) {
   if (t.second_waves != 0 && t.second_waves != 8 && t.second_waves != 16) bad("second_waves");
   if (t.walker_tile < 0) bad("walker_tile");
   s->tune = t;
+  s->tune.energy_form = 0;  // read-only
   free_energy(s);
   s->drop_graphs();
   if (s->have_trial) apply_fb_splitk(s);
@@ -2307,6 +2356,7 @@ msd_status msd_get_tuning(msd_system* sys, msd_tuning* out) {
     out->second_copy = sys->second_dma ? 2 : 1;
     out->second_waves = sys->second_waves;
     out->walker_tile = sys->WT;
+    out->energy_form = sys->wform ? 1 : 0;
   }
   API_END(sys)
 }
@@ -2396,6 +2446,7 @@ msd_status msd_autotune(msd_system* sys, double dt, int32_t reps, msd_tuning* ou
     out->second_copy = sys->second_dma ? 2 : 1;
     out->second_waves = sys->second_waves;
     out->walker_tile = sys->WT;
+    out->energy_form = sys->wform ? 1 : 0;
   }
   API_END(sys)
 }

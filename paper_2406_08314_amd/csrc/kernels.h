@@ -143,7 +143,7 @@ void launch_xbar(int NW, int NG, const double* raw, double sqrt_dt, cd* xbar, hi
 // like the other kernels) and per-wave partials of <C, Lambda Q> per chunk
 // into czw ([2][NW][n_chunks * parts]).
 // The S arrays come from launch_gather_general.
-bool ltl_general_fits(const DevSpin& sa, const DevSpin& sb, int M);
+bool ltl_general_fits(const DevSpin& sa, const DevSpin& sb, int M, bool fp32);
 int ltl_general_parts(const DevSpin& sa, const DevSpin& sb);
 size_t ltl_general_s_elems(const DevSpin& sa, const DevSpin& sb, int M, int NG);
 void launch_gather_general(const double* L, int NG, int M, const DevSpin& D, const DevSpin& sa,
@@ -152,13 +152,13 @@ void launch_ltl_general(const DevSpin& sa, const DevSpin& sb, int NW, int w0, in
                         int g_chunk, int M, const double* Sa, const double* Sb, const cd* Ta,
                         const cd* Tb, cd* Lam_a, cd* Lam_b, const cd* Ca, const cd* Cb, cd* v0,
                         cd* ex0, cd* lamc, cd* czw, const int* wmask, hipStream_t st);
-// mask[w] = 1 where max |T| of walker w (either spin) exceeds tmax
+// mask[w] = 1 where max |T| of walker w (either spin) exceeds tmax, rest[w] = 1 - mask[w]
 void launch_walker_tmax(int NW, int M, int na, int nb, const cd* Ta, const cd* Tb, double tmax,
-                        int* mask, hipStream_t st);
+                        int* mask, int* rest, hipStream_t st);
 void launch_ltl_general32(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
                           int g_chunk, int M, const float* Sa, const float* Sb, const cf* Ta,
                           const cf* Tb, cf* Lam_a, cf* Lam_b, const cd* Ca, const cd* Cb, cd* v0,
-                          cd* ex0, cd* lamc, cd* czw, hipStream_t st);
+                          cd* ex0, cd* lamc, cd* czw, const int* wmask, hipStream_t st);
 
 // energy (one walker tile of WT walkers starting at w0)
 void launch_lambda(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
@@ -258,7 +258,8 @@ void launch_energy_second32(const DevSpin& sa, const DevSpin& sb, const DevPairs
                             int w0, int WT, int NG, int n_gsplit, int G, int max_order,
                             bool flat_gather, bool use_dma, bool swz, const cf* Lam_a, const cf* Lam_b,
                             const cd* coef, const cd* m2a, const cd* m2b, const cd* Ba,
-                            const cd* Bb, cd* partial, int n_slots, int slot0, hipStream_t st);
+                            const cd* Bb, cd* partial, int n_slots, int slot0, hipStream_t st,
+                            const int* wmask = nullptr);
 // W-form of the second-order terms: G^{st} = per-walker real GEMMs of the
 // interleaved Lambda windows over the Cholesky index ([wl][2X_s][2X_t]); the
 // pair and minor coefficient lists contracted with W into one slot per walker.

@@ -111,6 +111,31 @@ __device__ __forceinline__ double gl_wsum(double v) {
   return v;
 }
 
+// one DPP move of a double (row-local lane permutation CTRL)
+template <int CTRL>
+__device__ __forceinline__ double gl_dpp(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double gl_readlane(double v, int l) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+// sum over the wave without LDS: within each row of 16 lanes by DPP (quad
+// swaps xor 1 and xor 2, then the half-row and row mirrors), then the four
+// row sums read as scalars; the result is wave-uniform
+__device__ __forceinline__ double gl_wsum_dpp(double v) {
+  v += gl_dpp<0xB1>(v);
+  v += gl_dpp<0x4E>(v);
+  v += gl_dpp<0x141>(v);
+  v += gl_dpp<0x140>(v);
+  return (gl_readlane(v, 0) + gl_readlane(v, 16)) + (gl_readlane(v, 32) + gl_readlane(v, 48));
+}
+
 struct GlShape {
   int nv16, Np, P16, no16, Mpad;
 };
@@ -138,16 +163,23 @@ __host__ __device__ constexpr int gl_slab_stride(int P16, int rsize, int NCT) {
 }
 
 // LDS reals: the slab ring (GL_NB buffers of 16 x P16, padded), Q (Np x Np
-// complex), the window columns of Q transposed (no16 x Np complex),
+// complex, rows padded to 2 Np + 1 reals so that a wave's reads down a column
+// of Q hit distinct banks), the window columns of Q transposed (no16 x Np complex),
 // [Re T_V | Im T_V] k-major (2 Np x nv16), [Re C | Im C] k-major (2 no16 x nv16)
-__host__ __device__ inline int gl_lds_reals(const GlShape& s, int rsize, int NCT) {
-  return GL_NB * gl_slab_stride(s.P16, rsize, NCT) + 2 * s.Np * s.Np + 2 * s.no16 * s.Np +
-         2 * s.Np * s.nv16 + 2 * s.no16 * s.nv16;
+// With TL (the walker's T held in LDS, [Mpad][2 Np + 1], instead of in
+// registers): three slab buffers, no separate T_V block (its rows are read
+// from T) and no transposed window block (read down the columns of Q).
+__host__ __device__ constexpr int gl_nb(bool TL) { return TL ? 3 : GL_NB; }
+__host__ __device__ inline int gl_lds_reals(const GlShape& s, int rsize, int NCT, bool TL) {
+  const int common = gl_nb(TL) * gl_slab_stride(s.P16, rsize, NCT) + s.Np * (2 * s.Np + 1) +
+                     2 * s.no16 * s.nv16;
+  if (TL) return common + s.Mpad * (2 * s.Np + 1) + GL_OMAX;  // + the window slots (ints)
+  return common + 2 * s.no16 * s.Np + 2 * s.Np * s.nv16;
 }
 
 }  // namespace
 
-template <class R, int NCT, int KSL, int VT>
+template <class R, int NCT, int KSL, int VT, bool TL>
 __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
     DevSpin sa, DevSpin sb, int NW, int w0, int WT, int NG, int g_chunk, int n_chunks, int M,
     const R* __restrict__ Sa, const R* __restrict__ Sb,
@@ -184,32 +216,24 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
   const cd* __restrict__ Cw = (s2 ? Cb : Ca) + (size_t)w * X;
 
   // LDS carve-up
+  constexpr int NB = gl_nb(TL);
   constexpr int SLOADS = gl_slab_loads(P16, (int)sizeof(R), NCT);
   constexpr int SSTRIDE = gl_slab_stride(P16, (int)sizeof(R), NCT);
-  R* sS = lds;                              // [GL_NB][SSTRIDE] (16 x P16 used)
-  R* sQ = sS + GL_NB * SSTRIDE;             // [Np][Np][2]
-  R* sQT = sQ + 2 * Np * Np;                // [no16][Np][2]
-  R* sTV = sQT + 2 * no16 * Np;             // [2 Np][nv16]
-  R* sCA = sTV + 2 * Np * nv16;             // [2 no16][nv16]
+  constexpr int QLD = 2 * Np + 1;           // row stride of Q and T (reals)
+  R* sS = lds;                              // [NB][SSTRIDE] (16 x P16 used)
+  R* sQ = sS + NB * SSTRIDE;                // [Np][QLD]: (re, im) of column j at 2j
+  R* sCA = sQ + Np * QLD;                   // [2 no16][nv16]
+  R* sQT = sCA + 2 * no16 * nv16;           // !TL: [no16][Np][2]
+  R* sTV = sQT + 2 * no16 * Np;             // !TL: [2 Np][nv16]
+  R* sT = sCA + 2 * no16 * nv16;            // TL: [Mpad][QLD], column c of tile t at 16 t + c
+  int* sSlot = reinterpret_cast<int*>(sT + sh.Mpad * QLD);  // TL: window slots
 
   // window index of this lane's column (slot j), -1 outside the window
   int wi = -1;
   for (int i = 0; i < no; ++i)
     if (D.oslot[i] == j) wi = i;
 
-  // one-time LDS fills: the transposed window block of Q starts at zero (rows
-  // >= n_o are never written), [Re T_V | Im T_V] and [Re C | Im C]
   const int nthr = 64 * NCT;
-  for (int e = threadIdx.x; e < 2 * no16 * Np; e += nthr) sQT[e] = R(0);
-  for (int e = threadIdx.x; e < 2 * Np * nv16; e += nthr) {
-    const int k = e / nv16, a = e % nv16, kc = k % Np;
-    R v = R(0);
-    if (a < nv && kc < N) {
-      const C t = T[((size_t)D.vir[a] * NW + w) * N + kc];
-      v = k < Np ? t.re : t.im;
-    }
-    sTV[e] = v;
-  }
   for (int e = threadIdx.x; e < 2 * no16 * nv16; e += nthr) {
     const int k = e / nv16, a = e % nv16, kc = k % no16;
     R v = R(0);
@@ -219,18 +243,51 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
     }
     sCA[e] = v;
   }
-
-  // B operand of LT: T[k][j] (real or imaginary part) for k = 4s + q
-  R bt[4 * KSL];
-#pragma unroll
-  for (int s = 0; s < 4 * KSL; ++s) {
-    const int k = 4 * s + q;
-    R v = R(0);
-    if (k < M && j < N) {
-      const C t = T[((size_t)k * NW + w) * N + j];
-      v = part ? t.im : t.re;
+  // B operand of LT: T[k][j] (real or imaginary part) for k = 4s + q, in
+  // registers (!TL) or in LDS (TL)
+  R bt[TL ? 1 : 4 * KSL];
+  int vrow[VT];  // TL: orbital of this lane's rows of T_V (-1 beyond n_v)
+  if constexpr (TL) {
+    // T[k][w][j] as 2 Np real columns per orbital k, in the tile layout
+    for (int e = threadIdx.x; e < sh.Mpad * 2 * Np; e += nthr) {
+      const int k = e / (2 * Np), c = e % (2 * Np);
+      const int jj = 8 * (c >> 4) + (c & 7), pp = (c >> 3) & 1;
+      R v = R(0);
+      if (k < M && jj < N) {
+        const C t = T[((size_t)k * NW + w) * N + jj];
+        v = pp ? t.im : t.re;
+      }
+      sT[k * QLD + c] = v;
     }
-    bt[s] = v;
+    for (int i = threadIdx.x; i < GL_OMAX; i += nthr) sSlot[i] = i < no ? D.oslot[i] : 0;
+#pragma unroll
+    for (int vt = 0; vt < VT; ++vt) {
+      const int a = vt * 16 + col;
+      vrow[vt] = a < nv ? D.vir[a] : -1;
+    }
+  } else {
+    // the transposed window block of Q starts at zero (rows >= n_o are never
+    // written); [Re T_V | Im T_V]
+    for (int e = threadIdx.x; e < 2 * no16 * Np; e += nthr) sQT[e] = R(0);
+    for (int e = threadIdx.x; e < 2 * Np * nv16; e += nthr) {
+      const int k = e / nv16, a = e % nv16, kc = k % Np;
+      R v = R(0);
+      if (a < nv && kc < N) {
+        const C t = T[((size_t)D.vir[a] * NW + w) * N + kc];
+        v = k < Np ? t.re : t.im;
+      }
+      sTV[e] = v;
+    }
+#pragma unroll
+    for (int s = 0; s < 4 * KSL; ++s) {
+      const int k = 4 * s + q;
+      R v = R(0);
+      if (k < M && j < N) {
+        const C t = T[((size_t)k * NW + w) * N + j];
+        v = part ? t.im : t.re;
+      }
+      bt[s] = v;
+    }
   }
 
   const int g0 = chunk * g_chunk, g1 = min(NG, g0 + g_chunk);
@@ -242,7 +299,7 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
     constexpr int per16 = 16 / sizeof(R);
     const int g = g0 + t / n_sl, sl = t % n_sl;
     const R* src = S + ((size_t)g * sh.Mpad + (size_t)sl * GL_KS) * P16;
-    R* dst = sS + (t % GL_NB) * SSTRIDE;
+    R* dst = sS + (t % NB) * SSTRIDE;
     constexpr int n16 = GL_KS * P16 / per16;
 #pragma unroll
     for (int u = 0; u < SLOADS; ++u) {
@@ -252,7 +309,7 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
   };
 
   double dot_re = 0.0, dot_im = 0.0;
-  for (int t = 0; t < GL_NB - 1; ++t) fetch(t);
+  for (int t = 0; t < NB - 1; ++t) fetch(t);
   int t = 0;
   for (int g = g0; g < g1; ++g) {
     // ---- LT = S^g T over slabs of 16 orbitals
@@ -262,19 +319,22 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
 #pragma unroll
     for (int sl = 0; sl < KSL; ++sl) {
       if (sl < n_sl) {
-        // slab t has landed once at most the loads of slabs t+1 .. t+GL_NB-2
+        // slab t has landed once at most the loads of slabs t+1 .. t+NB-2
         // are outstanding (near the end fewer were issued: wait for all)
-        if (t + GL_NB - 2 < n_t) gl_bar_vm<(GL_NB - 2) * SLOADS>();
+        if (t + NB - 2 < n_t) gl_bar_vm<(NB - 2) * SLOADS>();
         else gl_bar_vm<0>();
-        fetch(t + GL_NB - 1);  // into the buffer every wave finished with
-        const R* sb0 = sS + (t % GL_NB) * SSTRIDE;
+        fetch(t + NB - 1);  // into the buffer every wave finished with
+        const R* sb0 = sS + (t % NB) * SSTRIDE;
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           R a[RT];
 #pragma unroll
           for (int rt = 0; rt < RT; ++rt) a[rt] = sb0[(4 * s + q) * P16 + rt * 16 + col];
+          R bv;
+          if constexpr (TL) bv = sT[(16 * sl + 4 * s + q) * QLD + 16 * wv + col];
+          else bv = bt[4 * sl + s];
 #pragma unroll
-          for (int rt = 0; rt < RT; ++rt) acc[rt] = MF::run(a[rt], bt[4 * sl + s], acc[rt]);
+          for (int rt = 0; rt < RT; ++rt) acc[rt] = MF::run(a[rt], bv, acc[rt]);
         }
         ++t;
       }
@@ -285,8 +345,8 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = rt * 16 + MF::row(lane, r) - nv16;
-        sQ[(i * Np + j) * 2 + part] = acc[rt][r];
-        if (wi >= 0) sQT[(wi * Np + i) * 2 + part] = acc[rt][r];
+        sQ[i * QLD + 2 * j + part] = acc[rt][r];
+        if (!TL && wi >= 0) sQT[(wi * Np + i) * 2 + part] = acc[rt][r];
       }
     gl_bar_lds();
     // ---- this wave's parts of the mean-field traces: v0 = sum_i Q_ii and
@@ -298,7 +358,7 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
       for (int r = 0; r < 4; ++r) {
         const int i = rt * 16 + MF::row(lane, r) - nv16;
         const double a = (double)acc[rt][r];
-        const double br = (double)sQ[(j * Np + i) * 2], bi = (double)sQ[(j * Np + i) * 2 + 1];
+        const double br = (double)sQ[j * QLD + 2 * i], bi = (double)sQ[j * QLD + 2 * i + 1];
         if (part == 0) {
           if (i == j) vr += a;
           xr += a * br;
@@ -321,11 +381,18 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
       const bool hi = kk >= Np / 4;  // imaginary rows of the block form of Q
       const int kr = hi ? k - Np : k;
       const int comp = hi ? 1 - part : part;
-      R bq = sQ[(kr * Np + j) * 2 + comp];
+      R bq = sQ[kr * QLD + 2 * j + comp];
       if (hi && part == 0) bq = -bq;
+      // A: [Re T_V | Im T_V] row a = vt * 16 + col, column k
+      const int kc = hi ? k - Np : k;                 // complex column of T
+      const int tcol = 16 * (kc >> 3) + 8 * (hi ? 1 : 0) + (kc & 7);
 #pragma unroll
-      for (int vt = 0; vt < VT; ++vt)
-        lam[vt] = MF::run(sTV[k * nv16 + vt * 16 + col], bq, lam[vt]);
+      for (int vt = 0; vt < VT; ++vt) {
+        R av;
+        if constexpr (TL) av = vrow[vt] >= 0 ? sT[vrow[vt] * QLD + tcol] : R(0);
+        else av = sTV[k * nv16 + vt * 16 + col];
+        lam[vt] = MF::run(av, bq, lam[vt]);
+      }
     }
     // ---- D = C Q_W^T: K = 2 no16 over [Re C | Im C]
     acc_t dd[VT];
@@ -336,7 +403,9 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
       const bool hi = k >= no16;
       const int kr = hi ? k - no16 : k;
       const int comp = hi ? 1 - part : part;
-      R bx = sQT[(kr * Np + j) * 2 + comp];
+      R bx;
+      if constexpr (TL) bx = kr < no ? sQ[j * QLD + 2 * sSlot[kr] + comp] : R(0);  // Q[j][slot]
+      else bx = sQT[(kr * Np + j) * 2 + comp];
       if (hi && part == 0) bx = -bx;
 #pragma unroll
       for (int vt = 0; vt < VT; ++vt)
@@ -372,12 +441,12 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
           dst[part] = lam[vt][r];
         }
       }
-    lr = gl_wsum(lr);
-    li = gl_wsum(li);
-    vr = gl_wsum(vr);
-    vi = gl_wsum(vi);
-    xr = gl_wsum(xr);
-    xi = gl_wsum(xi);
+    lr = gl_wsum_dpp(lr);
+    li = gl_wsum_dpp(li);
+    vr = gl_wsum_dpp(vr);
+    vi = gl_wsum_dpp(vi);
+    xr = gl_wsum_dpp(xr);
+    xi = gl_wsum_dpp(xi);
     if (lane == 0) {
       const size_t o = (((size_t)s2 * NW + w) * NG + g) * NCT + wv;
       lamc[o] = cd{lr, li};
@@ -427,17 +496,25 @@ int ltl_general_ksl(int M) {
   return 0;
 }
 
-bool ltl_general_fits(const DevSpin& sa, const DevSpin& sb, int M) {
+// T in LDS where it fits (any precision); T in registers otherwise, only in
+// FP64 and where the register-resident T does not spill (at most four column
+// tiles, i.e. N <= 32 per spin)
+static bool gl_tl(const DevSpin& sa, const DevSpin& sb, int M, size_t rsize) {
+  const int nct = ltl_general_nct(sa, sb);
+  const GlShape s = gl_shape(std::max(sa.no, sb.no), M, nct, ltl_general_vt(sa, sb));
+  return (size_t)gl_lds_reals(s, (int)rsize, nct, true) * rsize <= 160 * 1024;
+}
+
+bool ltl_general_fits(const DevSpin& sa, const DevSpin& sb, int M, bool fp32) {
   const int nct = ltl_general_nct(sa, sb), ksl = ltl_general_ksl(M);
   if (nct < 2 || nct > 6 || ksl == 0) return false;
-  // six column tiles put two waves on some SIMDs (at most 256 registers per
-  // wave): the register-resident T of more than 128 orbitals would spill
-  if (nct == 6 && ksl > 8) return false;
   for (const DevSpin* d : {&sa, &sb}) {
     if (d->N == 0 || d->nv == 0 || d->nv > GL_VTMAX * 16 || d->no > GL_OMAX) return false;
   }
+  if (gl_tl(sa, sb, M, fp32 ? 4 : 8)) return true;
+  if (fp32 || nct > 4) return false;
   const GlShape s = gl_shape(std::max(sa.no, sb.no), M, nct, ltl_general_vt(sa, sb));
-  return (size_t)gl_lds_reals(s, sizeof(double), nct) * sizeof(double) <= 160 * 1024;
+  return (size_t)gl_lds_reals(s, 8, nct, false) * 8 <= 160 * 1024;
 }
 
 size_t ltl_general_s_elems(const DevSpin& sa, const DevSpin& sb, int M, int NG) {
@@ -461,23 +538,23 @@ void launch_gather_general(const double* L, int NG, int M, const DevSpin& D, con
 }
 
 namespace {
-template <class R, int NCT, int KSL, int VT>
+template <class R, int NCT, int KSL, int VT, bool TL>
 void gl_launch(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG, int g_chunk,
                int n_chunks, int M, const R* Sa, const R* Sb, const typename GMfma<R>::cx_t* Ta,
                const typename GMfma<R>::cx_t* Tb, typename GMfma<R>::cx_t* Lam_a,
                typename GMfma<R>::cx_t* Lam_b, const cd* Ca, const cd* Cb, cd* v0, cd* ex0,
                cd* lamc, cd* czw, const int* wmask, hipStream_t st) {
   const GlShape s = gl_shape(std::max(sa.no, sb.no), M, NCT, VT);
-  const size_t lds = (size_t)gl_lds_reals(s, sizeof(R), NCT) * sizeof(R);
+  const size_t lds = (size_t)gl_lds_reals(s, sizeof(R), NCT, TL) * sizeof(R);
   static bool attr = false;
   if (!attr) {
-    hipFuncSetAttribute((const void*)k_ltl_general<R, NCT, KSL, VT>,
+    hipFuncSetAttribute((const void*)k_ltl_general<R, NCT, KSL, VT, TL>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr = true;
   }
   const dim3 grid(WT * n_chunks * 2), block(64 * NCT);
-  hipLaunchKernelGGL((k_ltl_general<R, NCT, KSL, VT>), grid, block, lds, st, sa, sb, NW, w0, WT,
-                     NG, g_chunk, n_chunks, M, Sa, Sb, Ta, Tb, Lam_a, Lam_b, Ca, Cb, v0, ex0,
+  hipLaunchKernelGGL((k_ltl_general<R, NCT, KSL, VT, TL>), grid, block, lds, st, sa, sb, NW, w0,
+                     WT, NG, g_chunk, n_chunks, M, Sa, Sb, Ta, Tb, Lam_a, Lam_b, Ca, Cb, v0, ex0,
                      lamc, czw, wmask);
 }
 
@@ -489,19 +566,24 @@ void gl_dispatch(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, i
                  cd* lamc, cd* czw, const int* wmask, hipStream_t st) {
   const int nct = ltl_general_nct(sa, sb), ksl = ltl_general_ksl(M), vt = ltl_general_vt(sa, sb);
   const int n_chunks = (NG + g_chunk - 1) / g_chunk;
-#define GL_CASE(n, k, v)                                                                      \
-  if (nct == n && ksl == k && vt == v)                                                        \
-    return gl_launch<R, n, k, v>(sa, sb, NW, w0, WT, NG, g_chunk, n_chunks, M, Sa, Sb, Ta,    \
-                                 Tb, Lam_a, Lam_b, Ca, Cb, v0, ex0, lamc, czw, wmask, st);
-#define GL_KSL(n, v) GL_CASE(n, 4, v) GL_CASE(n, 8, v) GL_CASE(n, 13, v) GL_CASE(n, 20, v)
+  const bool tl = gl_tl(sa, sb, M, sizeof(R));
+#define GL_CASE(n, k, v, t)                                                                     if (nct == n && ksl == k && vt == v && tl == t)                                                 return gl_launch<R, n, k, v, t>(sa, sb, NW, w0, WT, NG, g_chunk, n_chunks, M, Sa, Sb, Ta,                                     Tb, Lam_a, Lam_b, Ca, Cb, v0, ex0, lamc, czw, wmask, st);
+#define GL_KSL(n, v) GL_CASE(n, 4, v, true) GL_CASE(n, 8, v, true) GL_CASE(n, 13, v, true) \
+                     GL_CASE(n, 20, v, true)
   GL_KSL(2, 1)
   GL_KSL(2, 2)
   GL_KSL(4, 1)
   GL_KSL(4, 2)
-  GL_CASE(6, 4, 1)
-  GL_CASE(6, 8, 1)
-  GL_CASE(6, 4, 2)
-  GL_CASE(6, 8, 2)
+  GL_KSL(6, 1)
+  GL_KSL(6, 2)
+  if constexpr (sizeof(R) == 8) {  // T in registers: FP64 where T does not fit LDS
+    GL_CASE(2, 20, 1, false)
+    GL_CASE(2, 20, 2, false)
+    GL_CASE(4, 13, 1, false)
+    GL_CASE(4, 13, 2, false)
+    GL_CASE(4, 20, 1, false)
+    GL_CASE(4, 20, 2, false)
+  }
 #undef GL_KSL
 #undef GL_CASE
 }
@@ -520,17 +602,19 @@ void launch_ltl_general(const DevSpin& sa, const DevSpin& sb, int NW, int w0, in
 void launch_ltl_general32(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
                           int g_chunk, int M, const float* Sa, const float* Sb, const cf* Ta,
                           const cf* Tb, cf* Lam_a, cf* Lam_b, const cd* Ca, const cd* Cb, cd* v0,
-                          cd* ex0, cd* lamc, cd* czw, hipStream_t st) {
+                          cd* ex0, cd* lamc, cd* czw, const int* wmask, hipStream_t st) {
   gl_dispatch<float>(sa, sb, NW, w0, WT, NG, g_chunk, M, Sa, Sb, Ta, Tb, Lam_a, Lam_b, Ca, Cb, v0,
-                     ex0, lamc, czw, nullptr, st);
+                     ex0, lamc, czw, wmask, st);
 }
 
 // Walkers for the FP64 energy pass of the mixed form: mask[w] = 1 where the
-// largest |T_pj| of either spin exceeds tmax.  One workgroup per walker.
+// largest |T_pj| of either spin exceeds tmax, rest[w] = 1 - mask[w].  One
+// workgroup per walker.
 __global__ __launch_bounds__(256) void k_walker_tmax(int NW, int M, int na, int nb,
                                                      const cd* __restrict__ Ta,
                                                      const cd* __restrict__ Tb, double tmax,
-                                                     int* __restrict__ mask) {
+                                                     int* __restrict__ mask,
+                                                     int* __restrict__ rest) {
   __shared__ double red[256];
   const int w = blockIdx.x, tid = threadIdx.x;
   double m = 0.0;
@@ -548,12 +632,17 @@ __global__ __launch_bounds__(256) void k_walker_tmax(int NW, int M, int na, int 
     if (tid < off) red[tid] = fmax(red[tid], red[tid + off]);
     __syncthreads();
   }
-  if (tid == 0) mask[w] = red[0] > tmax * tmax ? 1 : 0;
+  if (tid == 0) {
+    const int f = red[0] > tmax * tmax ? 1 : 0;
+    mask[w] = f;
+    rest[w] = 1 - f;
+  }
 }
 
 void launch_walker_tmax(int NW, int M, int na, int nb, const cd* Ta, const cd* Tb, double tmax,
-                        int* mask, hipStream_t st) {
-  hipLaunchKernelGGL(k_walker_tmax, dim3(NW), dim3(256), 0, st, NW, M, na, nb, Ta, Tb, tmax, mask);
+                        int* mask, int* rest, hipStream_t st) {
+  hipLaunchKernelGGL(k_walker_tmax, dim3(NW), dim3(256), 0, st, NW, M, na, nb, Ta, Tb, tmax, mask,
+                     rest);
 }
 
 }  // namespace msd

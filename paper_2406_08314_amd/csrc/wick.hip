@@ -308,56 +308,135 @@ __global__ __launch_bounds__(256) void k_strings_t(DevSpin sa, DevSpin sb, StrOu
   }
 }
 
-// Orders above 4: runtime k with LU-based sub-determinants.
-__global__ __launch_bounds__(128) void k_strings_big(DevSpin sa, DevSpin sb, StrOut oa, StrOut ob,
-                                                     int NW, int K, bool minors) {
+// Orders above 4: one thread per output entry of a (walker, string) -- the
+// determinant, one adjugate entry or one complementary two-minor -- each a
+// D x D determinant (D = K, K - 1, K - 2) gathered from T and evaluated by LU
+// with partial pivoting in registers (sizes fixed at compile time, so the
+// matrices stay in registers).  Consecutive threads write consecutive entries.
+template <int D>
+__device__ __forceinline__ cd det_fixed(cd* w) {
+  if constexpr (D <= 4) {
+    return det_small<D>(w);
+  } else {
+    // row swaps and the zero-pivot exit as selects, so every index is a
+    // compile-time constant
+    cd det{1.0, 0.0};
+    bool zero = false;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      int piv = j;
+      double best = abs2(w[j * D + j]);
+#pragma unroll
+      for (int i = j + 1; i < D; ++i) {
+        const double v = abs2(w[i * D + j]);
+        piv = v > best ? i : piv;
+        best = v > best ? v : best;
+      }
+      zero = zero || best == 0.0;
+      if (piv != j) det = -det;
+#pragma unroll
+      for (int i = j + 1; i < D; ++i) {
+        const bool sw = i == piv;
+#pragma unroll
+        for (int c = j; c < D; ++c) {
+          const cd a = w[j * D + c], b = w[i * D + c];
+          w[j * D + c] = sw ? b : a;
+          w[i * D + c] = sw ? a : b;
+        }
+      }
+      const cd p = zero ? cd{1.0, 0.0} : w[j * D + j];
+      det = det * p;
+#pragma unroll
+      for (int i = j + 1; i < D; ++i) {
+        const cd f = cdiv(w[i * D + j], p);
+#pragma unroll
+        for (int c = j + 1; c < D; ++c) w[i * D + c] -= f * w[j * D + c];
+      }
+    }
+    return zero ? cd{0.0, 0.0} : det;
+  }
+}
+
+// WHICH: 0 determinant, 1 adjugate entries, 2 complementary two-minors
+template <int K, int WHICH>
+__global__ __launch_bounds__(256) void k_str_entries(DevSpin sa, DevSpin sb, StrOut oa, StrOut ob,
+                                                     int NW) {
+  constexpr int P = K * (K - 1) / 2;
+  constexpr int E = WHICH == 0 ? 1 : WHICH == 1 ? K * K : P * P;
+  constexpr int D = WHICH == 0 ? K : WHICH == 1 ? K - 1 : K - 2;
   const bool beta = blockIdx.y == 1;
   const DevSpin& s = beta ? sb : sa;
   const StrOut& o = beta ? ob : oa;
-  const cd* __restrict__ T = o.T;
-  cd* __restrict__ d = o.d;
-  cd* __restrict__ adj = o.adj;
-  cd* __restrict__ m2 = o.m2;
   const int s0 = s.bucket[K], ns = s.bucket[K + 1] - s.bucket[K];
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid >= (int64_t)ns * NW) return;
-  const int str = s0 + (int)(tid % ns);
-  const int w = (int)(tid / ns);
-  const int N = s.N;
-  cd X[KMAX * KMAX], sub[KMAX * KMAX];
-  for (int m = 0; m < K; ++m)
-    for (int n = 0; n < K; ++n)
-      X[m * K + n] =
-          T[((size_t)s.part[str * KMAX + n] * NW + w) * N + s.hslot[str * KMAX + m]];
-  d[(size_t)w * s.U + str] = det_lu(X, K);
-  cd* ao = adj + (size_t)w * s.A + s.adj_off[str];
-  for (int n = 0; n < K; ++n)
-    for (int m = 0; m < K; ++m) {
-      int o = 0;
-      for (int r = 0; r < K; ++r) {
-        if (r == m) continue;
-        for (int c = 0; c < K; ++c)
-          if (c != n) sub[o++] = X[r * K + c];
-      }
-      cd v = det_lu(sub, K - 1);
-      ao[n * K + m] = ((n + m) & 1) ? -v : v;
-    }
-  if (minors) {
-    const int P = K * (K - 1) / 2;
-    cd* mo = m2 + (size_t)w * s.M2 + s.m2_off[str];
+  if (tid >= (int64_t)ns * NW * E) return;
+  const int e = (int)(tid % E);
+  const int64_t r = tid / E;
+  const int str = s0 + (int)(r % ns), w = (int)(r / ns);
+  // excluded rows (holes m) and columns (particles n)
+  int xr0 = -1, xr1 = -1, xc0 = -1, xc1 = -1;
+  if constexpr (WHICH == 1) {
+    xc0 = e / K;  // adj(X)[n][m] = (-1)^(n+m) det X without row m, column n
+    xr0 = e % K;
+  } else if constexpr (WHICH == 2) {
+    const int A = e / P, B = e % P;
+    int acc = 0;
     for (int m = 0; m < K; ++m)
-      for (int mp = m + 1; mp < K; ++mp)
-        for (int n = 0; n < K; ++n)
-          for (int np = n + 1; np < K; ++np) {
-            int o = 0;
-            for (int r = 0; r < K; ++r) {
-              if (r == m || r == mp) continue;
-              for (int c = 0; c < K; ++c)
-                if (c != n && c != np) sub[o++] = X[r * K + c];
-            }
-            mo[pair_index(m, mp, K) * P + pair_index(n, np, K)] = det_lu(sub, K - 2);
-          }
+      for (int mp = m + 1; mp < K; ++mp, ++acc) {
+        if (acc == A) {
+          xr0 = m;
+          xr1 = mp;
+        }
+        if (acc == B) {
+          xc0 = m;
+          xc1 = mp;
+        }
+      }
   }
+  // u-th kept row / column: skip the excluded ones (x0 < x1, -1 = none), with
+  // compile-time u so the index arrays stay in registers
+  auto kept = [](int u, int x0, int x1) {
+    int m = (x0 >= 0 && u >= x0) ? u + 1 : u;
+    if (x1 >= 0 && m >= x1) ++m;
+    return m;
+  };
+  int rs[D > 0 ? D : 1], cs[D > 0 ? D : 1];
+#pragma unroll
+  for (int u = 0; u < D; ++u) {
+    rs[u] = s.hslot[str * KMAX + kept(u, xr0, xr1)];
+    cs[u] = s.part[str * KMAX + kept(u, xc0, xc1)];
+  }
+  cd a[D > 0 ? D * D : 1];
+  const cd* __restrict__ T = o.T;
+  const int N = s.N;
+#pragma unroll
+  for (int u = 0; u < D; ++u)
+#pragma unroll
+    for (int v = 0; v < D; ++v) a[u * D + v] = T[((size_t)cs[v] * NW + w) * N + rs[u]];
+  const cd det = det_fixed<D>(a);
+  if constexpr (WHICH == 0) {
+    o.d[(size_t)w * s.U + str] = det;
+  } else if constexpr (WHICH == 1) {
+    o.adj[(size_t)w * s.A + s.adj_off[str] + e] = ((xr0 + xc0) & 1) ? -det : det;
+  } else {
+    o.m2[(size_t)w * s.M2 + s.m2_off[str] + e] = det;
+  }
+}
+
+template <int K>
+static void launch_str_entries(const DevSpin& sa, const DevSpin& sb, const StrOut& oa,
+                               const StrOut& ob, int NW, bool minors, hipStream_t st) {
+  const int ns = max(sa.bucket[K + 1] - sa.bucket[K], sb.bucket[K + 1] - sb.bucket[K]);
+  if (ns <= 0) return;
+  constexpr int P = K * (K - 1) / 2;
+  const int64_t n0 = (int64_t)ns * NW, n1 = n0 * K * K, n2 = n0 * P * P;
+  hipLaunchKernelGGL((k_str_entries<K, 0>), dim3((unsigned)((n0 + 255) / 256), 2), dim3(256), 0,
+                     st, sa, sb, oa, ob, NW);
+  hipLaunchKernelGGL((k_str_entries<K, 1>), dim3((unsigned)((n1 + 255) / 256), 2), dim3(256), 0,
+                     st, sa, sb, oa, ob, NW);
+  if (minors)
+    hipLaunchKernelGGL((k_str_entries<K, 2>), dim3((unsigned)((n2 + 255) / 256), 2), dim3(256), 0,
+                       st, sa, sb, oa, ob, NW);
 }
 
 void launch_strings(const DevSpin& sa, const DevSpin& sb, const cd* Ta, const cd* Tb, int NW,
@@ -373,10 +452,11 @@ void launch_strings(const DevSpin& sa, const DevSpin& sb, const cd* Ta, const cd
       nb += (n + 255) / 256;
       continue;
     }
-    if (ns <= 0) continue;
-    dim3 grid((unsigned)((n + 127) / 128), 2);
-    hipLaunchKernelGGL(k_strings_big, grid, dim3(128), 0, st, sa, sb, oa, ob, NW, k, minors);
   }
+  launch_str_entries<5>(sa, sb, oa, ob, NW, minors, st);
+  launch_str_entries<6>(sa, sb, oa, ob, NW, minors, st);
+  launch_str_entries<7>(sa, sb, oa, ob, NW, minors, st);
+  launch_str_entries<8>(sa, sb, oa, ob, NW, minors, st);
   g.first[5] = (int)nb;
   if (nb > 0)
     hipLaunchKernelGGL(k_strings_t, dim3((unsigned)nb, 2), dim3(256), 0, st, sa, sb, oa, ob, NW,
@@ -1692,10 +1772,11 @@ void launch_energy_second32(const DevSpin& sa, const DevSpin& sb, const DevPairs
                             int w0, int WT, int NG, int n_gsplit, int G, int max_order,
                             bool flat_gather, bool use_dma, bool swz, const cf* Lam_a, const cf* Lam_b,
                             const cd* coef, const cd* m2a, const cd* m2b, const cd* Ba,
-                            const cd* Bb, cd* partial, int n_slots, int slot0, hipStream_t st) {
+                            const cd* Bb, cd* partial, int n_slots, int slot0, hipStream_t st,
+                            const int* wmask) {
   launch_energy_second_t<cf>(sa, sb, pr, plan, n_itemblocks, waves_per_block, NW, w0, WT, NG,
                              n_gsplit, G, max_order, flat_gather, use_dma, swz, Lam_a, Lam_b, coef, m2a, m2b, Ba, Bb,
-                             partial, n_slots, slot0, st, nullptr);
+                             partial, n_slots, slot0, st, wmask);
 }
 
 int energy_minor_blocks(const DevSpin& s) {

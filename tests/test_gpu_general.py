@@ -24,6 +24,9 @@ SHAPES = {
     "n40_m96": (40, 40, 96, 16, (20, 12), 3, 30, 3),
     "n8_m70": (8, 8, 70, 40, (8, 20), 4, 50, 6),
     "n32_occ32": (32, 32, 72, 12, (32, 12), 3, 30, 3),
+    # T beyond the LDS (FP64): the register-resident form of T
+    "n20_m240": (20, 20, 240, 16, (12, 16), 3, 30, 3),
+    "n16_m300": (16, 14, 300, 12, (10, 14), 3, 30, 3),
 }
 
 
@@ -81,7 +84,7 @@ def test_general_kernel_chunks_and_tiles(tuning):
     _check(wl, out, [1, 3])
 
 
-@pytest.mark.parametrize("name", ["n12_m40", "n30_m150_unequal", "n40_m96"])
+@pytest.mark.parametrize("name", ["n12_m40", "n30_m150_unequal", "n40_m96", "n20_m240"])
 def test_general_kernel_mixed_against_fp64(name):
     wl = _workload(name)
     ref = _system(wl).measure(wl.dt)

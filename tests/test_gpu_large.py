@@ -148,3 +148,30 @@ def test_fe2s2_shape_energy_high_orders(precision):
             print(f"mixed-form |dE_L| at the Fe2S2 shape, walker {w}: {err * 1e3:.4f} mHa "
                   f"(|E_L| = {abs(e):.1f} Ha)")
             assert err <= MIXED_E_TOL
+
+
+@pytest.fixture(scope="module")
+def million():
+    """10^6 determinants on the Cu-oxo shape, 64 walkers, and the oracle's
+    Wick-path result for walker 7."""
+    wl = make_config("cu_oxo", n_det=1_000_000, n_walkers=64)
+    ex = (wick.Excitations(wl.occ_a, wl.M), wick.Excitations(wl.occ_b, wl.M))
+    return wl, _wick_walker(wl, ex, 7)
+
+
+@pytest.mark.parametrize("energy_algo", [0, 4])
+def test_cu_oxo_shape_million_determinants(million, energy_algo):
+    """10^6 determinants (orders up to 4) on the Cu-oxo shape (M=200, N=30+30,
+    1,200 Cholesky vectors), 64 walkers: one walker's log-overlap, Green's
+    function, force bias and local energy against the oracle's Wick path, in
+    the automatic energy form and in the W-form."""
+    wl, ref = million
+    s = MsdSystem(wl.M, wl.n_alpha, wl.n_beta, wl.n_chol, wl.n_walkers, wl.n_det,
+                  energy_algo=energy_algo)
+    s.set_hamiltonian(wl.h1, wl.chol, wl.e0)
+    s.set_trial(wl.ci, wl.occ_a, wl.occ_b)
+    s.set_walkers(wl.phi_a, wl.phi_b, wl.weights)
+    out = s.measure(wl.dt)
+    assert np.all(np.isfinite(out["e_loc"]))
+    _check_walker(s, out, ref, 7)
+    s.close()
