@@ -28,6 +28,13 @@ HIPFLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
             "-Wno-unused-result", "-I", CSRC, "-I", INCLUDE]
 
 
+# Per-file extra flags.  The general contraction kernel keeps its matrix-core
+# accumulators in ordinary VGPRs (the VGPR form of the MFMA instructions):
+# with the default AGPR form the compiler copies every accumulator between
+# the two register files around each slab of the K loop.
+FILE_FLAGS = {"ltl_general.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+
+
 def hipcc() -> str:
     for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
         if cand and os.path.exists(cand):
@@ -38,7 +45,7 @@ def hipcc() -> str:
 def _compile(src: str) -> str:
     obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
     path = os.path.join(CSRC, src)
-    cmd = [hipcc(), *HIPFLAGS, "-c", path, "-o", obj]
+    cmd = [hipcc(), *HIPFLAGS, *FILE_FLAGS.get(src, []), "-c", path, "-o", obj]
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -187,6 +187,9 @@ struct msd_system {
   int* fmask = nullptr;  // [NW] 1: single-precision pass (the complement of gmask)
   int second_G64 = 1;    // LDS stage depth of the FP64 second-order pass
   int gl_chunk_guard = 1, n_lchunks_guard = 0;  // finer vector chunks: few walkers
+  // the FP64 pass's second-order partials: a finer split of the Cholesky range
+  // (few walkers) into slots of their own, [slot_guard, slot_guard_end)
+  int gsplit_guard = 1, slot_guard = 0, slot_guard_end = 0;
   // W-form of the second-order terms: per-walker GEMMs over the Cholesky index
   // of the Lambda windows, [wl][2X_s][2X_t] for (aa, ab, bb), then the
   // coefficient lists contracted with them (one energy slot per walker)
@@ -198,6 +201,7 @@ struct msd_system {
   int WT = 0, gl_chunk = 16, n_lchunks = 0;
   // second-order energy plan: per-spin algorithm and partial slots
   int gsplit = 1, n_slots = 0;
+  int n_slots_main = 0;  // slots [0, n_slots_main) belong to the main energy pass
   bool use_strings[2] = {false, false};
   int slot_min[2] = {0, 0};
   // merged second-order kernel: wave plan (role | spin << 8, first string of
@@ -588,7 +592,21 @@ void alloc_energy(msd_system* s) {
   // minor-list form indexes them unswizzled)
   s->lam_swz = s->lambda_variant == 5 && s->use_strings[0] && s->use_strings[1] &&
                A.no == 8 && B.no == 8;
-  s->n_slots = slot;  // every slot is written by exactly one workgroup
+  // the mixed form's FP64 pass for walkers far from the reference (general kernel)
+  s->guard = s->energy_mixed && s->lambda_variant == 6 && s->gl_fits && s->tmax > 0.0;
+  s->n_slots_main = slot;
+  if (s->guard && s->wform) {
+    s->slot_guard = s->slot_wform;
+    s->slot_guard_end = s->slot_wform + 1;
+  } else if (s->guard) {
+    // the FP64 pass may have a handful of walkers: split their Cholesky range
+    // finely enough that they still spread over the chip
+    s->gsplit_guard = std::max(s->gsplit, std::min(16, std::max(1, NG / 16)));
+    s->slot_guard = slot;
+    slot += s->n_itemblocks * s->gsplit_guard;
+    s->slot_guard_end = slot;
+  }
+  s->n_slots = slot;  // every slot is written by exactly one workgroup of its pass
   Arena& E = s->energy_mem;
   for (int sp = 0; sp < 2; ++sp) {
     const msd::DevSpin& D = s->ds[sp];
@@ -606,14 +624,12 @@ void alloc_energy(msd_system* s) {
     if (!fused_kernel) s->ZWp[sp] = E.get<cd>((size_t)wt * s->n_lchunks * D.nv * D.no);
     s->coef2[sp] = E.get<cd>((size_t)NW * D.n_minor);
   }
-  // the mixed form's FP64 pass for walkers far from the reference (general kernel)
-  s->guard = s->energy_mixed && s->lambda_variant == 6 && s->gl_fits && s->tmax > 0.0;
   if (s->guard) {
     for (int sp = 0; sp < 2; ++sp)
       s->Lam[sp] = E.get<cd>((size_t)wt * NG * s->ds[sp].nv * s->ds[sp].no);
     // the FP64 pass may have few walkers: split their vectors more finely so
     // that a handful of walkers still spreads over the chip
-    const int n_chunks = std::max(1, std::min(NG, 8));
+    const int n_chunks = std::max(1, std::min(NG, 48));
     s->gl_chunk_guard = (NG + n_chunks - 1) / n_chunks;
     s->n_lchunks_guard = (NG + s->gl_chunk_guard - 1) / s->gl_chunk_guard * s->gl_parts;
     const int X = A.nv * A.no + B.nv * B.no;
@@ -884,7 +900,8 @@ void run_energy_mixed(msd_system* s) {
                                   s->sw[1].B, s->epart, s->n_slots, s->slot_second, s->st, fm);
     });
     s->timed(ST_EFINAL, [&] {
-      msd::launch_energy_final(A, B, s->NW, w0, wt, s->NG, s->n_lchunks, s->n_slots, s->obar,
+      msd::launch_energy_final(A, B, s->NW, w0, wt, s->NG, s->n_lchunks, s->n_slots, 0,
+                               s->n_slots_main, s->obar,
                                s->v0, s->ex0, s->ZWp[0], s->ZWp[1], s->sw[0].C, s->sw[1].C,
                                s->lambda_variant >= 5 ? s->czw : nullptr, s->epart, s->onebody,
                                s->onebody + s->NW, s->e0, s->eloc,
@@ -969,11 +986,12 @@ void run_energy_guard(msd_system* s) {
         run_wform(s, w0, wt, false, s->gmask);
       else
         msd::launch_energy_second(A, B, s->dp, s->plan, s->n_itemblocks, s->second_waves, s->NW,
-                                  w0, wt, s->NG, s->gsplit, s->second_G64, s->second_maxk,
+                                  w0, wt, s->NG, s->gsplit_guard, s->second_G64, s->second_maxk,
                                   s->second_flat, s->second_dma, false, s->Lam[0], s->Lam[1],
                                   s->coefAB, s->sw[0].m2, s->sw[1].m2, s->sw[0].B, s->sw[1].B,
-                                  s->epart, s->n_slots, s->slot_second, s->st, s->gmask);
+                                  s->epart, s->n_slots, s->slot_guard, s->st, s->gmask);
       msd::launch_energy_final(A, B, s->NW, w0, wt, s->NG, s->n_lchunks_guard, s->n_slots,
+                               s->slot_guard, s->slot_guard_end,
                                s->obar, s->v0, s->ex0, s->ZWp[0], s->ZWp[1], s->sw[0].C,
                                s->sw[1].C, s->czw, s->epart, s->onebody, s->onebody + s->NW,
                                s->e0, s->eloc, s->lamc, s->gl_parts, s->st, s->gmask);
@@ -1089,7 +1107,8 @@ void run_energy(msd_system* s) {
       }
     });
     s->timed(ST_EFINAL, [&] {
-      msd::launch_energy_final(A, B, s->NW, w0, wt, s->NG, s->n_lchunks, s->n_slots, s->obar,
+      msd::launch_energy_final(A, B, s->NW, w0, wt, s->NG, s->n_lchunks, s->n_slots, 0,
+                               s->n_slots_main, s->obar,
                                s->v0, s->ex0, s->ZWp[0], s->ZWp[1], s->sw[0].C, s->sw[1].C,
                                s->lambda_variant >= 5 ? s->czw : nullptr, s->epart, s->onebody,
                                s->onebody + s->NW, s->e0, s->eloc,

@@ -276,9 +276,11 @@ void launch_energy_minors(const DevSpin& s, int NW, int w0, int WT, int NG, int 
 // first-order term is then the sum of those contracted partials.  lamc (when
 // not null, [2][NW][NG][n_lparts]) adds -(v0_a + v0_b) <C, Lambda> per vector.
 // wmask (when not null): only walkers with wmask[w] != 0 are assembled (as in
-// launch_energy_second).
+// launch_energy_second).  The second-order partials of a walker are the slots
+// [e_lo, e_hi) of its row of epart (row length n_slots).
 void launch_energy_final(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
-                         int n_lchunks, int n_echunks, const cd* obar, const cd* v0,
+                         int n_lchunks, int n_slots, int e_lo, int e_hi, const cd* obar,
+                         const cd* v0,
                          const cd* ex0, const cd* ZWpart_a, const cd* ZWpart_b,
                          const cd* Ca, const cd* Cb, const cd* czw, const cd* epart,
                          const cd* onebody_a, const cd* onebody_b, double e0, cd* e_loc,

@@ -97,6 +97,17 @@ __device__ __forceinline__ void gl_bar_vm() {
   __builtin_amdgcn_s_barrier();
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
+// at most N of this wave's vector-memory operations outstanding and all its
+// LDS operations done, then the workgroup barrier
+template <int N>
+__device__ __forceinline__ void gl_bar_vm_lds() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  constexpr int imm = (N & 15) | ((N >> 4) << 14) | (7 << 4);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(imm);
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
 // this wave's LDS writes done, then the workgroup barrier
 __device__ __forceinline__ void gl_bar_lds() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -111,12 +122,18 @@ __device__ __forceinline__ double gl_wsum(double v) {
   return v;
 }
 
-// one DPP move of a double (row-local lane permutation CTRL)
-template <int CTRL>
+// one DPP move (row-local lane permutation CTRL) of a float or a double;
+// lanes of rows outside ROWS read 0
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ float gl_dpp(float v) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROWS, 0xF, false));
+}
+template <int CTRL, int ROWS = 0xF>
 __device__ __forceinline__ double gl_dpp(double v) {
   const long long b = __builtin_bit_cast(long long, v);
-  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xF, false);
   return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 __device__ __forceinline__ double gl_readlane(double v, int l) {
@@ -126,14 +143,24 @@ __device__ __forceinline__ double gl_readlane(double v, int l) {
   return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 // sum over the wave without LDS: within each row of 16 lanes by DPP (quad
-// swaps xor 1 and xor 2, then the half-row and row mirrors), then the four
-// row sums read as scalars; the result is wave-uniform
+// swaps xor 1 and xor 2, then the half-row and row mirrors), then row 1 +=
+// row 0 and row 3 += row 2 (broadcast of lane 15 of each row), then row 3 +=
+// row 1 (broadcast of lane 31); lane 63 holds the total, returned
+// wave-uniform
 __device__ __forceinline__ double gl_wsum_dpp(double v) {
   v += gl_dpp<0xB1>(v);
   v += gl_dpp<0x4E>(v);
   v += gl_dpp<0x141>(v);
   v += gl_dpp<0x140>(v);
-  return (gl_readlane(v, 0) + gl_readlane(v, 16)) + (gl_readlane(v, 32) + gl_readlane(v, 48));
+  v += gl_dpp<0x142, 0xA>(v);
+  v += gl_dpp<0x143, 0xC>(v);
+  return gl_readlane(v, 63);
+}
+// the value of lane l ^ 8 (the other part of the same complex entry in the
+// tile layout): a rotation of each 16-lane row by 8
+template <class R>
+__device__ __forceinline__ R gl_other_part(R v) {
+  return gl_dpp<0x128>(v);
 }
 
 struct GlShape {
@@ -164,17 +191,16 @@ __host__ __device__ constexpr int gl_slab_stride(int P16, int rsize, int NCT) {
 
 // LDS reals: the slab ring (GL_NB buffers of 16 x P16, padded), Q (Np x Np
 // complex, rows padded to 2 Np + 1 reals so that a wave's reads down a column
-// of Q hit distinct banks), the window columns of Q transposed (no16 x Np complex),
-// [Re T_V | Im T_V] k-major (2 Np x nv16), [Re C | Im C] k-major (2 no16 x nv16)
-// With TL (the walker's T held in LDS, [Mpad][2 Np + 1], instead of in
-// registers): three slab buffers, no separate T_V block (its rows are read
-// from T) and no transposed window block (read down the columns of Q).
+// of Q hit distinct banks), [Re C | Im C] k-major (2 no16 x nv16) and
+// [Re T_V | Im T_V] k-major (2 Np x nv16).  With TL (the walker's T held in
+// LDS, [Mpad][2 Np + 1], instead of in registers): three slab buffers and no
+// separate T_V block (its rows are read from T).
 __host__ __device__ constexpr int gl_nb(bool TL) { return TL ? 3 : GL_NB; }
 __host__ __device__ inline int gl_lds_reals(const GlShape& s, int rsize, int NCT, bool TL) {
   const int common = gl_nb(TL) * gl_slab_stride(s.P16, rsize, NCT) + s.Np * (2 * s.Np + 1) +
                      2 * s.no16 * s.nv16;
-  if (TL) return common + s.Mpad * (2 * s.Np + 1) + GL_OMAX;  // + the window slots (ints)
-  return common + 2 * s.no16 * s.Np + 2 * s.Np * s.nv16;
+  if (TL) return common + s.Mpad * (2 * s.Np + 1);
+  return common + 2 * s.Np * s.nv16;
 }
 
 }  // namespace
@@ -223,15 +249,19 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
   R* sS = lds;                              // [NB][SSTRIDE] (16 x P16 used)
   R* sQ = sS + NB * SSTRIDE;                // [Np][QLD]: (re, im) of column j at 2j
   R* sCA = sQ + Np * QLD;                   // [2 no16][nv16]
-  R* sQT = sCA + 2 * no16 * nv16;           // !TL: [no16][Np][2]
-  R* sTV = sQT + 2 * no16 * Np;             // !TL: [2 Np][nv16]
+  R* sTV = sCA + 2 * no16 * nv16;           // !TL: [2 Np][nv16]
   R* sT = sCA + 2 * no16 * nv16;            // TL: [Mpad][QLD], column c of tile t at 16 t + c
-  int* sSlot = reinterpret_cast<int*>(sT + sh.Mpad * QLD);  // TL: window slots
 
   // window index of this lane's column (slot j), -1 outside the window
   int wi = -1;
   for (int i = 0; i < no; ++i)
     if (D.oslot[i] == j) wi = i;
+
+  // offsets (reals) of Q[.][slot(i)] for this lane's window rows i = 4 u + q
+  // of the D product, -1 beyond n_o
+  int qs[GL_OMAX / 4];
+#pragma unroll
+  for (int u = 0; u < GL_OMAX / 4; ++u) qs[u] = 4 * u + q < no ? 2 * D.oslot[4 * u + q] : -1;
 
   const int nthr = 64 * NCT;
   for (int e = threadIdx.x; e < 2 * no16 * nv16; e += nthr) {
@@ -259,16 +289,13 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
       }
       sT[k * QLD + c] = v;
     }
-    for (int i = threadIdx.x; i < GL_OMAX; i += nthr) sSlot[i] = i < no ? D.oslot[i] : 0;
 #pragma unroll
     for (int vt = 0; vt < VT; ++vt) {
       const int a = vt * 16 + col;
       vrow[vt] = a < nv ? D.vir[a] : -1;
     }
   } else {
-    // the transposed window block of Q starts at zero (rows >= n_o are never
-    // written); [Re T_V | Im T_V]
-    for (int e = threadIdx.x; e < 2 * no16 * Np; e += nthr) sQT[e] = R(0);
+    // [Re T_V | Im T_V]
     for (int e = threadIdx.x; e < 2 * Np * nv16; e += nthr) {
       const int k = e / nv16, a = e % nv16, kc = k % Np;
       R v = R(0);
@@ -292,52 +319,108 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
 
   const int g0 = chunk * g_chunk, g1 = min(NG, g0 + g_chunk);
   // slab ring over the flattened (vector, slab) sequence: slab t = (g0 + t /
-  // n_sl, t % n_sl) sits in buffer t % GL_NB
+  // n_sl, t % n_sl) sits in buffer t % NB.  Slabs are fetched in order; the
+  // fetch cursor (ft, fg, fsl, fbuf) and the consumer buffer cb advance by
+  // one slab at a time.
   const int n_t = (g1 - g0) * n_sl;
-  auto fetch = [&](int t) {
-    if (t >= n_t) return;  // uniform: no loads issued (the wait below allows for it)
-    constexpr int per16 = 16 / sizeof(R);
-    const int g = g0 + t / n_sl, sl = t % n_sl;
-    const R* src = S + ((size_t)g * sh.Mpad + (size_t)sl * GL_KS) * P16;
-    R* dst = sS + (t % NB) * SSTRIDE;
-    constexpr int n16 = GL_KS * P16 / per16;
+  int ft = 0, fg = g0, fsl = 0, fbuf = 0, cb = 0;
+  auto fetch_next = [&]() {
+    if (ft < n_t) {  // uniform: no loads issued past the end (the wait below allows for it)
+      constexpr int per16 = 16 / sizeof(R);
+      const R* src = S + ((size_t)fg * sh.Mpad + (size_t)fsl * GL_KS) * P16;
+      R* dst = sS + fbuf * SSTRIDE;
+      constexpr int n16 = GL_KS * P16 / per16;
 #pragma unroll
-    for (int u = 0; u < SLOADS; ++u) {
-      const int c = u * NCT + wv, e = min(c * 64 + lane, n16 - 1);  // pad lanes re-read
-      gl_dma16(src + (size_t)e * per16, dst + c * 64 * per16);
+      for (int u = 0; u < SLOADS; ++u) {
+        const int c = u * NCT + wv, e = min(c * 64 + lane, n16 - 1);  // pad lanes re-read
+        gl_dma16(src + (size_t)e * per16, dst + c * 64 * per16);
+      }
+      if (++fsl == n_sl) {
+        fsl = 0;
+        ++fg;
+      }
+      fbuf = fbuf + 1 == NB ? 0 : fbuf + 1;
     }
+    ++ft;
+  };
+  // one slab of LT: wait until slab t has landed (at most the loads of slabs
+  // t+1 .. t+NB-2 outstanding; near the end fewer were issued: wait for all),
+  // refill the buffer every wave finished with, then 4 k-steps of RT tiles
+  auto slab = [&](acc_t* acc, int sl, auto&& bval) {
+    if (ft <= n_t) gl_bar_vm<(NB - 2) * SLOADS>();  // ft = t + NB - 1 here
+    else gl_bar_vm<0>();
+    fetch_next();
+    const R* sb0 = sS + cb * SSTRIDE;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      R a[RT];
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) a[rt] = sb0[(4 * s + q) * P16 + rt * 16 + col];
+      const R bv = bval(sl, s);
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) acc[rt] = MF::run(a[rt], bv, acc[rt]);
+    }
+    cb = cb + 1 == NB ? 0 : cb + 1;
   };
 
   double dot_re = 0.0, dot_im = 0.0;
-  for (int t = 0; t < NB - 1; ++t) fetch(t);
-  int t = 0;
+  for (int u = 0; u < NB - 1; ++u) fetch_next();
   for (int g = g0; g < g1; ++g) {
     // ---- LT = S^g T over slabs of 16 orbitals
     acc_t acc[RT];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) acc[rt] = acc_t{0, 0, 0, 0};
-#pragma unroll
-    for (int sl = 0; sl < KSL; ++sl) {
-      if (sl < n_sl) {
-        // slab t has landed once at most the loads of slabs t+1 .. t+NB-2
-        // are outstanding (near the end fewer were issued: wait for all)
-        if (t + NB - 2 < n_t) gl_bar_vm<(NB - 2) * SLOADS>();
-        else gl_bar_vm<0>();
-        fetch(t + NB - 1);  // into the buffer every wave finished with
-        const R* sb0 = sS + (t % NB) * SSTRIDE;
+    if constexpr (TL) {
+      // B from the LDS copy of T: a loop over the slabs, two at a time, the
+      // operands of the next slab read from LDS while the current slab's
+      // products run (the accumulators stay in place throughout).  The
+      // barrier before a slab's reads also waits for this wave's earlier LDS
+      // reads, so the buffer refilled there (the one read two slabs back) is
+      // free in every wave.
+      const R* tcol = sT + q * QLD + 16 * wv + col;
+      auto load = [&](R (&a)[4][RT], R (&bv)[4], int sl) {
+        if (ft <= n_t) gl_bar_vm_lds<(NB - 2) * SLOADS>();  // ft = t + NB - 1 here
+        else gl_bar_vm_lds<0>();
+        fetch_next();
+        const R* sb0 = sS + cb * SSTRIDE;
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-          R a[RT];
 #pragma unroll
-          for (int rt = 0; rt < RT; ++rt) a[rt] = sb0[(4 * s + q) * P16 + rt * 16 + col];
-          R bv;
-          if constexpr (TL) bv = sT[(16 * sl + 4 * s + q) * QLD + 16 * wv + col];
-          else bv = bt[4 * sl + s];
-#pragma unroll
-          for (int rt = 0; rt < RT; ++rt) acc[rt] = MF::run(a[rt], bv, acc[rt]);
+          for (int rt = 0; rt < RT; ++rt) a[s][rt] = sb0[(4 * s + q) * P16 + rt * 16 + col];
+          bv[s] = tcol[(16 * sl + 4 * s) * QLD];
         }
-        ++t;
+        cb = cb + 1 == NB ? 0 : cb + 1;
+      };
+      auto mma = [&](const R (&a)[4][RT], const R (&bv)[4]) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int rt = 0; rt < RT; ++rt) acc[rt] = MF::run(a[s][rt], bv[s], acc[rt]);
+      };
+      if constexpr (RT <= 4) {
+        R a0[4][RT], b0[4], a1[4][RT], b1[4];
+        load(a0, b0, 0);
+        for (int sl = 0; sl < n_sl; sl += 2) {
+          const bool more = sl + 1 < n_sl;
+          if (more) load(a1, b1, sl + 1);
+          mma(a0, b0);
+          if (!more) break;
+          if (sl + 2 < n_sl) load(a0, b0, sl + 2);
+          mma(a1, b1);
+        }
+      } else {
+        // five or more row tiles: one operand set (a second one would spill)
+        for (int sl = 0; sl < n_sl; ++sl) {
+          R a0[4][RT], b0[4];
+          load(a0, b0, sl);
+          mma(a0, b0);
+        }
       }
+    } else {
+      // B from registers (compile-time indices): unrolled over KSL slabs
+#pragma unroll
+      for (int sl = 0; sl < KSL; ++sl)
+        if (sl < n_sl) slab(acc, sl, [&](int l, int s) { return bt[4 * l + s]; });
     }
     // ---- Q (rows >= nv16 of LT) and its window columns, transposed, to LDS
 #pragma unroll
@@ -346,12 +429,12 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
       for (int r = 0; r < 4; ++r) {
         const int i = rt * 16 + MF::row(lane, r) - nv16;
         sQ[i * QLD + 2 * j + part] = acc[rt][r];
-        if (!TL && wi >= 0) sQT[(wi * Np + i) * 2 + part] = acc[rt][r];
       }
     gl_bar_lds();
     // ---- this wave's parts of the mean-field traces: v0 = sum_i Q_ii and
-    // ex0 = sum_ij Q_ij Q_ji over the entries Q_ij in its columns
-    double vr = 0.0, vi = 0.0, xr = 0.0, xi = 0.0;
+    // ex0 = sum_ij Q_ij Q_ji over the entries Q_ij in its columns (branch-free:
+    // a lane holds Re Q_ij (part 0) or Im Q_ij (part 1))
+    double vdg = 0.0, xr = 0.0, xi = 0.0;
 #pragma unroll
     for (int rt = VT; rt < RT; ++rt)
 #pragma unroll
@@ -359,16 +442,11 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
         const int i = rt * 16 + MF::row(lane, r) - nv16;
         const double a = (double)acc[rt][r];
         const double br = (double)sQ[j * QLD + 2 * i], bi = (double)sQ[j * QLD + 2 * i + 1];
-        if (part == 0) {
-          if (i == j) vr += a;
-          xr += a * br;
-          xi += a * bi;
-        } else {
-          if (i == j) vi += a;
-          xr -= a * bi;
-          xi += a * br;
-        }
+        vdg += i == j ? a : 0.0;
+        xr = fma(a, part ? -bi : br, xr);
+        xi = fma(a, part ? br : bi, xi);
       }
+    double vr = part ? 0.0 : vdg, vi = part ? vdg : 0.0;
     // ---- Lam = T_V Q - LT_V: K = 2 Np over [Re T_V | Im T_V]
     acc_t lam[VT];
 #pragma unroll
@@ -382,61 +460,67 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
       const int kr = hi ? k - Np : k;
       const int comp = hi ? 1 - part : part;
       R bq = sQ[kr * QLD + 2 * j + comp];
-      if (hi && part == 0) bq = -bq;
-      // A: [Re T_V | Im T_V] row a = vt * 16 + col, column k
-      const int kc = hi ? k - Np : k;                 // complex column of T
-      const int tcol = 16 * (kc >> 3) + 8 * (hi ? 1 : 0) + (kc & 7);
+      if (hi) bq = part ? bq : -bq;
+      // A: [Re T_V | Im T_V] row a = vt * 16 + col, column k (rows beyond
+      // n_v read row 0 and are zeroed)
+      const int tcol = 16 * (kr >> 3) + 8 * (hi ? 1 : 0) + (kr & 7);
 #pragma unroll
       for (int vt = 0; vt < VT; ++vt) {
         R av;
-        if constexpr (TL) av = vrow[vt] >= 0 ? sT[vrow[vt] * QLD + tcol] : R(0);
-        else av = sTV[k * nv16 + vt * 16 + col];
+        if constexpr (TL) {
+          av = sT[max(vrow[vt], 0) * QLD + tcol];
+          av = vrow[vt] >= 0 ? av : R(0);
+        } else {
+          av = sTV[k * nv16 + vt * 16 + col];
+        }
         lam[vt] = MF::run(av, bq, lam[vt]);
       }
     }
-    // ---- D = C Q_W^T: K = 2 no16 over [Re C | Im C]
+    // ---- D = C Q_W^T: K = 2 no16 over [Re C | Im C]; the B operand is
+    // Q[j][slot(i)] (k = i: real rows, k = no16 + i: imaginary rows)
     acc_t dd[VT];
 #pragma unroll
     for (int vt = 0; vt < VT; ++vt) dd[vt] = acc_t{0, 0, 0, 0};
-    for (int kk = 0; kk < 2 * no16 / 4; ++kk) {
-      const int k = 4 * kk + q;
-      const bool hi = k >= no16;
-      const int kr = hi ? k - no16 : k;
-      const int comp = hi ? 1 - part : part;
-      R bx;
-      if constexpr (TL) bx = kr < no ? sQ[j * QLD + 2 * sSlot[kr] + comp] : R(0);  // Q[j][slot]
-      else bx = sQT[(kr * Np + j) * 2 + comp];
-      if (hi && part == 0) bx = -bx;
+    auto dphase = [&](auto nc) {
+      constexpr int NO16 = decltype(nc)::value;
 #pragma unroll
-      for (int vt = 0; vt < VT; ++vt)
-        dd[vt] = MF::run(sCA[k * nv16 + vt * 16 + col], bx, dd[vt]);
-    }
-    // ---- <Lam, D> (accumulated), lc_g = <C, Lam_W>, window store
+      for (int u = 0; u < NO16 / 4; ++u) {
+        // rows beyond n_o read slot 0 and are zeroed
+        const int o = j * QLD + max(qs[u], 0);
+        R qre = sQ[o], qim = sQ[o + 1];
+        qre = qs[u] >= 0 ? qre : R(0);
+        qim = qs[u] >= 0 ? qim : R(0);
+        const R blo = part ? qim : qre, bhi = part ? qre : -qim;
+#pragma unroll
+        for (int vt = 0; vt < VT; ++vt)
+          dd[vt] = MF::run(sCA[(4 * u + q) * nv16 + vt * 16 + col], blo, dd[vt]);
+#pragma unroll
+        for (int vt = 0; vt < VT; ++vt)
+          dd[vt] = MF::run(sCA[(NO16 + 4 * u + q) * nv16 + vt * 16 + col], bhi, dd[vt]);
+      }
+    };
+    if (no16 == 16) dphase(std::integral_constant<int, 16>{});
+    else dphase(std::integral_constant<int, 32>{});
+    // ---- <Lam, D> (accumulated), lc_g = <C, Lam_W> (branch-free), window store
     double lr = 0.0, li = 0.0;
+    const int wic = max(wi, 0);
 #pragma unroll
     for (int vt = 0; vt < VT; ++vt)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const double lv = (double)lam[vt][r];
         const double dv = (double)dd[vt][r];
-        const double dp = (double)__shfl_xor(dd[vt][r], 8, 64);  // other part of D
-        if (part == 0) {
-          dot_re += lv * dv;
-          dot_im += lv * dp;
-        } else {
-          dot_re -= lv * dv;
-          dot_im += lv * dp;
-        }
+        const double dp = (double)gl_other_part(dd[vt][r]);  // other part of D
+        dot_re = fma(part ? -lv : lv, dv, dot_re);
+        dot_im = fma(lv, dp, dot_im);
         const int a = vt * 16 + MF::row(lane, r);
-        if (wi >= 0 && a < nv) {
-          const double cr = (double)sCA[wi * nv16 + a], ci = (double)sCA[(no16 + wi) * nv16 + a];
-          if (part == 0) {
-            lr += cr * lv;
-            li += ci * lv;
-          } else {
-            lr -= ci * lv;
-            li += cr * lv;
-          }
+        const bool inw = wi >= 0 && a < nv;
+        double cr = (double)sCA[wic * nv16 + a], ci = (double)sCA[(no16 + wic) * nv16 + a];
+        cr = inw ? cr : 0.0;
+        ci = inw ? ci : 0.0;
+        lr = fma(part ? -ci : cr, lv, lr);
+        li = fma(part ? cr : ci, lv, li);
+        if (inw) {
           R* dst = reinterpret_cast<R*>(Lam + ((size_t)wl * NG + g) * X + a * no + wi);
           dst[part] = lam[vt][r];
         }

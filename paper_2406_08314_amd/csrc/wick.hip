@@ -1859,7 +1859,8 @@ void launch_wform_contract(const DevSpin& sa, const DevSpin& sb, const DevPairs&
 // ============================================================================
 
 __global__ __launch_bounds__(256) void k_energy_final(DevSpin sa, DevSpin sb, int NW, int w0,
-                                                      int NG, int n_lchunks, int n_echunks,
+                                                      int NG, int n_lchunks, int n_slots,
+                                                      int e_lo, int e_hi,
                                                       const cd* __restrict__ obar,
                                                       const cd* __restrict__ v0,
                                                       const cd* __restrict__ ex0,
@@ -1923,19 +1924,20 @@ __global__ __launch_bounds__(256) void k_energy_final(DevSpin sa, DevSpin sb, in
       }
     }
   }
-  for (int c = tid; c < n_echunks; c += bd) czw += epart[(size_t)w * n_echunks + c];  // slots
+  for (int c = e_lo + tid; c < e_hi; c += bd) czw += epart[(size_t)w * n_slots + c];  // slots
   czw = block_reduce(czw, red);
   if (tid == 0) e_loc[w] = cd{e0, 0.0} + oba[w] + obb[w] + first + cdiv(czw, obar[w]);
 }
 
 void launch_energy_final(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
-                         int n_lchunks, int n_echunks, const cd* obar, const cd* v0,
+                         int n_lchunks, int n_slots, int e_lo, int e_hi, const cd* obar,
+                         const cd* v0,
                          const cd* ex0, const cd* ZWpart_a, const cd* ZWpart_b, const cd* Ca,
                          const cd* Cb, const cd* czw, const cd* epart, const cd* onebody_a,
                          const cd* onebody_b, double e0, cd* e_loc, const cd* lamc,
                          int n_lparts, hipStream_t st, const int* wmask) {
   hipLaunchKernelGGL(k_energy_final, dim3(WT), dim3(256), 0, st, sa, sb, NW, w0, NG, n_lchunks,
-                     n_echunks, obar, v0, ex0, ZWpart_a, ZWpart_b, Ca, Cb, czw, epart,
+                     n_slots, e_lo, e_hi, obar, v0, ex0, ZWpart_a, ZWpart_b, Ca, Cb, czw, epart,
                      onebody_a, onebody_b, e0, e_loc, lamc, n_lparts, wmask);
 }
 
