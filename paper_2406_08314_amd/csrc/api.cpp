@@ -185,6 +185,7 @@ struct msd_system {
   bool guard = false;
   int* gmask = nullptr;  // [NW] 1: FP64 pass
   int* fmask = nullptr;  // [NW] 1: single-precision pass (the complement of gmask)
+  int* glist = nullptr;  // [NW + 1] the walkers of the FP64 pass, then their count
   int second_G64 = 1;    // LDS stage depth of the FP64 second-order pass
   int gl_chunk_guard = 1, n_lchunks_guard = 0;  // finer vector chunks: few walkers
   // the FP64 pass's second-order partials: a finer split of the Cholesky range
@@ -976,12 +977,18 @@ void run_wform(msd_system* s, int w0, int wt, bool fp32, const int* wmask) {
 void run_energy_guard(msd_system* s) {
   const msd::DevSpin& A = s->ds[0];
   const msd::DevSpin& B = s->ds[1];
+  // the walkers of this pass as a list (persistent grids over their work
+  // items: no launch of idle workgroups for the walkers left out)
+  msd::WalkerList wls;
+  wls.list = s->glist;
+  wls.count = s->glist + s->NW;
+  wls.n_cu = s->n_cu;
   s->timed(ST_GUARD, [&] {
     for (int w0 = 0; w0 < s->NW; w0 += s->WT) {
       const int wt = std::min(s->WT, s->NW - w0);
       msd::launch_ltl_general(A, B, s->NW, w0, wt, s->NG, s->gl_chunk_guard, s->M, s->Sgl[0],
                               s->Sgl[1], s->sw[0].T, s->sw[1].T, s->Lam[0], s->Lam[1], s->sw[0].C,
-                              s->sw[1].C, s->v0, s->ex0, s->lamc, s->czw, s->gmask, s->st);
+                              s->sw[1].C, s->v0, s->ex0, s->lamc, s->czw, s->gmask, s->st, wls);
       if (s->wform)
         run_wform(s, w0, wt, false, s->gmask);
       else
@@ -989,7 +996,7 @@ void run_energy_guard(msd_system* s) {
                                   w0, wt, s->NG, s->gsplit_guard, s->second_G64, s->second_maxk,
                                   s->second_flat, s->second_dma, false, s->Lam[0], s->Lam[1],
                                   s->coefAB, s->sw[0].m2, s->sw[1].m2, s->sw[0].B, s->sw[1].B,
-                                  s->epart, s->n_slots, s->slot_guard, s->st, s->gmask);
+                                  s->epart, s->n_slots, s->slot_guard, s->st, s->gmask, wls);
       msd::launch_energy_final(A, B, s->NW, w0, wt, s->NG, s->n_lchunks_guard, s->n_slots,
                                s->slot_guard, s->slot_guard_end,
                                s->obar, s->v0, s->ex0, s->ZWp[0], s->ZWp[1], s->sw[0].C,
@@ -1017,7 +1024,7 @@ void run_energy(msd_system* s) {
     if (s->guard)  // which walkers go to the FP64 pass (gmask) and which stay (fmask)
       s->timed(ST_GUARD, [&] {
         msd::launch_walker_tmax(s->NW, s->M, A.N, B.N, s->sw[0].T, s->sw[1].T, s->tmax,
-                                s->gmask, s->fmask, s->st);
+                                s->gmask, s->fmask, s->glist, s->glist + s->NW, s->st);
       });
     run_energy_mixed(s);
     if (s->guard) run_energy_guard(s);
@@ -1476,6 +1483,7 @@ msd_status msd_create(const msd_dims* d, const msd_options* o, int32_t device, v
     sys->mask = A.get<int>(NW);
     sys->gmask = A.get<int>(NW);
     sys->fmask = A.get<int>(NW);
+    sys->glist = A.get<int>(NW + 1);
     sys->qr_ldet = A.get<double>(2 * (size_t)NW);
     sys->xraw = A.get<double>((size_t)NG * 2 * NW);
     sys->xbar = A.get<cd>((size_t)NW * NG);

@@ -143,6 +143,15 @@ void launch_xbar(int NW, int NG, const double* raw, double sqrt_dt, cd* xbar, hi
 // like the other kernels) and per-wave partials of <C, Lambda Q> per chunk
 // into czw ([2][NW][n_chunks * parts]).
 // The S arrays come from launch_gather_general.
+// With a walker list (wls.list: walker indices, wls.count: their number, both
+// on the device), only the listed walkers of the tile are processed, by a
+// persistent grid of the workgroups resident on wls.n_cu compute units; the
+// mask is then ignored.
+struct WalkerList {
+  const int* list = nullptr;
+  const int* count = nullptr;
+  int n_cu = 0;
+};
 bool ltl_general_fits(const DevSpin& sa, const DevSpin& sb, int M, bool fp32);
 int ltl_general_parts(const DevSpin& sa, const DevSpin& sb);
 size_t ltl_general_s_elems(const DevSpin& sa, const DevSpin& sb, int M, int NG);
@@ -151,14 +160,17 @@ void launch_gather_general(const double* L, int NG, int M, const DevSpin& D, con
 void launch_ltl_general(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
                         int g_chunk, int M, const double* Sa, const double* Sb, const cd* Ta,
                         const cd* Tb, cd* Lam_a, cd* Lam_b, const cd* Ca, const cd* Cb, cd* v0,
-                        cd* ex0, cd* lamc, cd* czw, const int* wmask, hipStream_t st);
-// mask[w] = 1 where max |T| of walker w (either spin) exceeds tmax, rest[w] = 1 - mask[w]
+                        cd* ex0, cd* lamc, cd* czw, const int* wmask, hipStream_t st,
+                        const WalkerList& wls = WalkerList());
+// mask[w] = 1 where max |T| of walker w (either spin) exceeds tmax, rest[w] =
+// 1 - mask[w]; list[0 .. *count) = the walkers with mask[w] = 1, in order
 void launch_walker_tmax(int NW, int M, int na, int nb, const cd* Ta, const cd* Tb, double tmax,
-                        int* mask, int* rest, hipStream_t st);
+                        int* mask, int* rest, int* list, int* count, hipStream_t st);
 void launch_ltl_general32(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
                           int g_chunk, int M, const float* Sa, const float* Sb, const cf* Ta,
                           const cf* Tb, cf* Lam_a, cf* Lam_b, const cd* Ca, const cd* Cb, cd* v0,
-                          cd* ex0, cd* lamc, cd* czw, const int* wmask, hipStream_t st);
+                          cd* ex0, cd* lamc, cd* czw, const int* wmask, hipStream_t st,
+                          const WalkerList& wls = WalkerList());
 
 // energy (one walker tile of WT walkers starting at w0)
 void launch_lambda(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
@@ -250,7 +262,8 @@ void launch_energy_second(const DevSpin& sa, const DevSpin& sb, const DevPairs& 
                           int WT, int NG, int n_gsplit, int G, int max_order, bool flat_gather,
                           bool use_dma, bool swz, const cd* Lam_a, const cd* Lam_b, const cd* coef,
                           const cd* m2a, const cd* m2b, const cd* Ba, const cd* Bb, cd* partial,
-                          int n_slots, int slot0, hipStream_t st, const int* wmask = nullptr);
+                          int n_slots, int slot0, hipStream_t st, const int* wmask = nullptr,
+                          const WalkerList& wls = WalkerList());
 // Same with single-precision Lambda (mixed form); the minors, CI weights and
 // the final products stay in double.
 void launch_energy_second32(const DevSpin& sa, const DevSpin& sb, const DevPairs& pr,

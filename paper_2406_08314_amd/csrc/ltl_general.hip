@@ -213,7 +213,7 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
     typename GMfma<R>::cx_t* __restrict__ Lam_a, typename GMfma<R>::cx_t* __restrict__ Lam_b,
     const cd* __restrict__ Ca, const cd* __restrict__ Cb, cd* __restrict__ v0,
     cd* __restrict__ ex0, cd* __restrict__ lamc, cd* __restrict__ czw,
-    const int* __restrict__ wmask) {
+    const int* __restrict__ wmask, const int* __restrict__ wlist, const int* __restrict__ wcount) {
   typedef GMfma<R> MF;
   typedef typename MF::cx_t C;
   typedef typename MF::acc_t acc_t;
@@ -228,10 +228,27 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
   const int col = lane & 15, q = lane >> 4;
   const int part = col >> 3;             // 0: real part, 1: imaginary part
   const int j = 8 * wv + (col & 7);      // complex column of this lane
-  const int b = blockIdx.x;
-  const int wl = b % WT, chunk = (b / WT) % n_chunks, s2 = b / (WT * n_chunks);
+  // Work items (walker, vector chunk, spin): one per workgroup (grid mode),
+  // or, with a walker list, a persistent grid striding over the items of the
+  // listed walkers (a few walkers then still spread over the chip without a
+  // launch of idle workgroups)
+  const int n_items = wlist ? *wcount * 2 * n_chunks : 1;
+  for (int it = wlist ? (int)blockIdx.x : 0; it < n_items; it += wlist ? (int)gridDim.x : 1) {
+  int wl, chunk, s2;
+  if (wlist) {
+    const int wi = it / (2 * n_chunks), rem = it % (2 * n_chunks);
+    wl = wlist[wi] - w0;
+    chunk = rem % n_chunks;
+    s2 = rem / n_chunks;
+    if (wl < 0 || wl >= WT) continue;  // listed walker outside this walker tile
+  } else {
+    const int b = blockIdx.x;
+    wl = b % WT;
+    chunk = (b / WT) % n_chunks;
+    s2 = b / (WT * n_chunks);
+    if (wmask && !wmask[w0 + wl]) return;  // walker not selected for this pass
+  }
   const int w = w0 + wl;
-  if (wmask && !wmask[w]) return;  // walker not selected for this pass
   const DevSpin& D = s2 ? sb : sa;
   const int N = D.N, nv = D.nv, no = D.no, X = nv * no;
   const GlShape sh = gl_shape(no, M, NCT, VT);
@@ -541,6 +558,8 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
   dot_re = gl_wsum(dot_re);
   dot_im = gl_wsum(dot_im);
   if (lane == 0) czw[((size_t)s2 * NW + w) * n_chunks * NCT + chunk * NCT + wv] = cd{dot_re, dot_im};
+  __syncthreads();  // the next item rewrites the LDS
+  }
 }
 
 // S[g][k][p] = L^g[row(p), k]: p < nv the window virtual orbitals, nv16 <= p <
@@ -627,19 +646,27 @@ void gl_launch(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int
                int n_chunks, int M, const R* Sa, const R* Sb, const typename GMfma<R>::cx_t* Ta,
                const typename GMfma<R>::cx_t* Tb, typename GMfma<R>::cx_t* Lam_a,
                typename GMfma<R>::cx_t* Lam_b, const cd* Ca, const cd* Cb, cd* v0, cd* ex0,
-               cd* lamc, cd* czw, const int* wmask, hipStream_t st) {
+               cd* lamc, cd* czw, const int* wmask, const WalkerList& wls, hipStream_t st) {
   const GlShape s = gl_shape(std::max(sa.no, sb.no), M, NCT, VT);
   const size_t lds = (size_t)gl_lds_reals(s, sizeof(R), NCT, TL) * sizeof(R);
+  const void* fn = (const void*)k_ltl_general<R, NCT, KSL, VT, TL>;
   static bool attr = false;
   if (!attr) {
-    hipFuncSetAttribute((const void*)k_ltl_general<R, NCT, KSL, VT, TL>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr = true;
   }
-  const dim3 grid(WT * n_chunks * 2), block(64 * NCT);
+  dim3 grid(WT * n_chunks * 2);
+  const dim3 block(64 * NCT);
+  if (wls.list) {  // persistent grid: the workgroups resident at once
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, (int)block.x, lds) != hipSuccess ||
+        per_cu < 1)
+      per_cu = 1;
+    grid = dim3(std::max(1, wls.n_cu) * per_cu);
+  }
   hipLaunchKernelGGL((k_ltl_general<R, NCT, KSL, VT, TL>), grid, block, lds, st, sa, sb, NW, w0,
                      WT, NG, g_chunk, n_chunks, M, Sa, Sb, Ta, Tb, Lam_a, Lam_b, Ca, Cb, v0, ex0,
-                     lamc, czw, wmask);
+                     lamc, czw, wmask, wls.list, wls.count);
 }
 
 template <class R>
@@ -647,11 +674,11 @@ void gl_dispatch(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, i
                  int g_chunk, int M, const R* Sa, const R* Sb, const typename GMfma<R>::cx_t* Ta,
                  const typename GMfma<R>::cx_t* Tb, typename GMfma<R>::cx_t* Lam_a,
                  typename GMfma<R>::cx_t* Lam_b, const cd* Ca, const cd* Cb, cd* v0, cd* ex0,
-                 cd* lamc, cd* czw, const int* wmask, hipStream_t st) {
+                 cd* lamc, cd* czw, const int* wmask, const WalkerList& wls, hipStream_t st) {
   const int nct = ltl_general_nct(sa, sb), ksl = ltl_general_ksl(M), vt = ltl_general_vt(sa, sb);
   const int n_chunks = (NG + g_chunk - 1) / g_chunk;
   const bool tl = gl_tl(sa, sb, M, sizeof(R));
-#define GL_CASE(n, k, v, t)                                                                     if (nct == n && ksl == k && vt == v && tl == t)                                                 return gl_launch<R, n, k, v, t>(sa, sb, NW, w0, WT, NG, g_chunk, n_chunks, M, Sa, Sb, Ta,                                     Tb, Lam_a, Lam_b, Ca, Cb, v0, ex0, lamc, czw, wmask, st);
+#define GL_CASE(n, k, v, t)                                                                     if (nct == n && ksl == k && vt == v && tl == t)                                                 return gl_launch<R, n, k, v, t>(sa, sb, NW, w0, WT, NG, g_chunk, n_chunks, M, Sa, Sb, Ta,                                     Tb, Lam_a, Lam_b, Ca, Cb, v0, ex0, lamc, czw, wmask, wls, st);
 #define GL_KSL(n, v) GL_CASE(n, 4, v, true) GL_CASE(n, 8, v, true) GL_CASE(n, 13, v, true) \
                      GL_CASE(n, 20, v, true)
   GL_KSL(2, 1)
@@ -678,17 +705,19 @@ int ltl_general_parts(const DevSpin& sa, const DevSpin& sb) { return ltl_general
 void launch_ltl_general(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
                         int g_chunk, int M, const double* Sa, const double* Sb, const cd* Ta,
                         const cd* Tb, cd* Lam_a, cd* Lam_b, const cd* Ca, const cd* Cb, cd* v0,
-                        cd* ex0, cd* lamc, cd* czw, const int* wmask, hipStream_t st) {
+                        cd* ex0, cd* lamc, cd* czw, const int* wmask, hipStream_t st,
+                        const WalkerList& wls) {
   gl_dispatch<double>(sa, sb, NW, w0, WT, NG, g_chunk, M, Sa, Sb, Ta, Tb, Lam_a, Lam_b, Ca, Cb,
-                      v0, ex0, lamc, czw, wmask, st);
+                      v0, ex0, lamc, czw, wmask, wls, st);
 }
 
 void launch_ltl_general32(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
                           int g_chunk, int M, const float* Sa, const float* Sb, const cf* Ta,
                           const cf* Tb, cf* Lam_a, cf* Lam_b, const cd* Ca, const cd* Cb, cd* v0,
-                          cd* ex0, cd* lamc, cd* czw, const int* wmask, hipStream_t st) {
+                          cd* ex0, cd* lamc, cd* czw, const int* wmask, hipStream_t st,
+                          const WalkerList& wls) {
   gl_dispatch<float>(sa, sb, NW, w0, WT, NG, g_chunk, M, Sa, Sb, Ta, Tb, Lam_a, Lam_b, Ca, Cb, v0,
-                     ex0, lamc, czw, wmask, st);
+                     ex0, lamc, czw, wmask, wls, st);
 }
 
 // Walkers for the FP64 energy pass of the mixed form: mask[w] = 1 where the
@@ -723,10 +752,42 @@ __global__ __launch_bounds__(256) void k_walker_tmax(int NW, int M, int na, int 
   }
 }
 
+// The walkers with mask[w] != 0 in increasing order, list[0 .. *count); one
+// workgroup (a ballot per wave, the wave counts summed in order).
+__global__ __launch_bounds__(1024) void k_walker_list(int NW, const int* __restrict__ mask,
+                                                      int* __restrict__ list,
+                                                      int* __restrict__ count) {
+  __shared__ int wsum[16];
+  __shared__ int base;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
+  if (tid == 0) base = 0;
+  __syncthreads();
+  for (int b = 0; b < NW; b += blockDim.x) {
+    const int w = b + tid;
+    const bool f = w < NW && mask[w] != 0;
+    const unsigned long long bal = __ballot(f);
+    const int before = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) wsum[wave] = __popcll(bal);
+    __syncthreads();
+    int off = base;
+    for (int q = 0; q < wave; ++q) off += wsum[q];
+    if (f) list[off + before] = w;
+    __syncthreads();
+    if (tid == 0) {
+      int t = 0;
+      for (int q = 0; q < nwaves; ++q) t += wsum[q];
+      base += t;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) *count = base;
+}
+
 void launch_walker_tmax(int NW, int M, int na, int nb, const cd* Ta, const cd* Tb, double tmax,
-                        int* mask, int* rest, hipStream_t st) {
+                        int* mask, int* rest, int* list, int* count, hipStream_t st) {
   hipLaunchKernelGGL(k_walker_tmax, dim3(NW), dim3(256), 0, st, NW, M, na, nb, Ta, Tb, tmax, mask,
                      rest);
+  hipLaunchKernelGGL(k_walker_list, dim3(1), dim3(1024), 0, st, NW, mask, list, count);
 }
 
 }  // namespace msd

@@ -1518,21 +1518,37 @@ __global__ __launch_bounds__((MAXK <= 4 ? 1024 : 512)) void k_energy_second(
     const CT* __restrict__ Lam_b, const cd* __restrict__ coef, const cd* __restrict__ m2a,
     const cd* __restrict__ m2b, const cd* __restrict__ Ba, const cd* __restrict__ Bb,
     cd* __restrict__ partial, int n_slots, int slot0, bool lds_dma, bool swz,
-    const int* __restrict__ wmask) {
+    const int* __restrict__ wmask, const int* __restrict__ wlist, const int* __restrict__ wcount,
+    int WT) {
   constexpr int NIDX = 2 * MAXK > 2 * ER_PPL ? 2 * MAXK : 2 * ER_PPL;
   constexpr int NMM = MAXK * (MAXK - 1) / 2;
   extern __shared__ __align__(16) unsigned char sm_raw[];
   CT* sm = reinterpret_cast<CT*>(sm_raw);
   __shared__ cd red[16];
-  // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs, so the
-  // item blocks of one (walker, Cholesky range), which stage the same Lambda
-  // slabs, are given consecutive ids on one XCD and share its L2.
-  const int nblk = gridDim.x, b = blockIdx.x;
-  const int per = nblk / 8, rem = nblk % 8, xcd = b % 8;
-  const int logical = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + b / 8;
-  const int ib = logical % n_ib, gs = (logical / n_ib) % n_gsplit, wl = logical / (n_ib * n_gsplit);
+  // Work items (item block, Cholesky range, walker): one per workgroup (grid
+  // mode), or, with a walker list, a persistent grid striding over the items
+  // of the listed walkers
+  const int n_items = wlist ? *wcount * n_ib * n_gsplit : 1;
+  for (int it = wlist ? (int)blockIdx.x : 0; it < n_items; it += wlist ? (int)gridDim.x : 1) {
+  int ib, gs, wl;
+  if (wlist) {
+    ib = it % n_ib;
+    gs = (it / n_ib) % n_gsplit;
+    wl = wlist[it / (n_ib * n_gsplit)] - w0;
+    if (wl < 0 || wl >= WT) continue;  // listed walker outside this walker tile
+  } else {
+    // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs, so the
+    // item blocks of one (walker, Cholesky range), which stage the same
+    // Lambda slabs, are given consecutive ids on one XCD and share its L2.
+    const int nblk = gridDim.x, b = blockIdx.x;
+    const int per = nblk / 8, rem = nblk % 8, xcd = b % 8;
+    const int logical = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + b / 8;
+    ib = logical % n_ib;
+    gs = (logical / n_ib) % n_gsplit;
+    wl = logical / (n_ib * n_gsplit);
+    if (wmask && !wmask[w0 + wl]) return;  // walker not selected for this pass
+  }
   const int w = w0 + wl, tid = threadIdx.x, lane = tid & 63;
-  if (wmask && !wmask[w]) return;  // walker not selected for this pass
   // wave index as a scalar: the plan entry, role and spin are then
   // wave-uniform registers and the role branches below are scalar branches
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -1727,6 +1743,8 @@ __global__ __launch_bounds__((MAXK <= 4 ? 1024 : 512)) void k_energy_second(
     for (int q = 0; q < (int)(blockDim.x >> 6); ++q) t += red[q];
     partial[(size_t)w * n_slots + slot0 + (size_t)ib * n_gsplit + gs] = t;
   }
+  __syncthreads();  // the next item rewrites the LDS stages and red
+  }
 }
 
 template <class CT>
@@ -1736,14 +1754,21 @@ static void launch_energy_second_t(const DevSpin& sa, const DevSpin& sb, const D
                                    bool flat_gather, bool use_dma, bool swz, const CT* Lam_a, const CT* Lam_b, const cd* coef,
                                    const cd* m2a, const cd* m2b, const cd* Ba, const cd* Bb,
                                    cd* partial, int n_slots, int slot0, hipStream_t st,
-                                   const int* wmask) {
+                                   const int* wmask, const WalkerList& wls) {
   if (n_itemblocks == 0) return;
   const size_t lds = 2 * (size_t)G * (sa.nv * sa.no + sb.nv * sb.no) * sizeof(CT);
-  const dim3 grid(WT * n_gsplit * n_itemblocks), block(64 * waves_per_block);
+  dim3 grid(WT * n_gsplit * n_itemblocks);
+  const dim3 block(64 * waves_per_block);
+  if (wls.list) {  // persistent grid: the workgroups resident at once (LDS bound)
+    const int per_cu = std::max(1, (int)((160u << 10) / std::max<size_t>(lds, 1)));
+    const int by_waves = std::max(1, 32 / waves_per_block);
+    grid = dim3(std::max(1, wls.n_cu) * std::min(per_cu, by_waves));
+  }
 #define MSD_ES(MK, FL)                                                                       \
   hipLaunchKernelGGL((k_energy_second<CT, MK, FL>), grid, block, lds, st, sa, sb, pr, plan,   \
                      n_itemblocks, waves_per_block, NW, w0, NG, n_gsplit, G, Lam_a, Lam_b, coef, \
-                     m2a, m2b, Ba, Bb, partial, n_slots, slot0, lds_dma, swz, wmask)
+                     m2a, m2b, Ba, Bb, partial, n_slots, slot0, lds_dma, swz, wmask, wls.list, \
+                     wls.count, WT)
   // direct LDS loads need 16-byte aligned runs: every Lambda row of both spins
   // (and each spin's stage region) starts on a 16-byte boundary
   const int per = 16 / (int)sizeof(CT);
@@ -1761,10 +1786,11 @@ void launch_energy_second(const DevSpin& sa, const DevSpin& sb, const DevPairs& 
                           int WT, int NG, int n_gsplit, int G, int max_order, bool flat_gather,
                           bool use_dma, bool swz, const cd* Lam_a, const cd* Lam_b, const cd* coef,
                           const cd* m2a, const cd* m2b, const cd* Ba, const cd* Bb, cd* partial,
-                          int n_slots, int slot0, hipStream_t st, const int* wmask) {
+                          int n_slots, int slot0, hipStream_t st, const int* wmask,
+                          const WalkerList& wls) {
   launch_energy_second_t<cd>(sa, sb, pr, plan, n_itemblocks, waves_per_block, NW, w0, WT, NG,
                              n_gsplit, G, max_order, flat_gather, use_dma, swz, Lam_a, Lam_b, coef, m2a, m2b, Ba, Bb,
-                             partial, n_slots, slot0, st, wmask);
+                             partial, n_slots, slot0, st, wmask, wls);
 }
 
 void launch_energy_second32(const DevSpin& sa, const DevSpin& sb, const DevPairs& pr,
@@ -1776,7 +1802,7 @@ void launch_energy_second32(const DevSpin& sa, const DevSpin& sb, const DevPairs
                             const int* wmask) {
   launch_energy_second_t<cf>(sa, sb, pr, plan, n_itemblocks, waves_per_block, NW, w0, WT, NG,
                              n_gsplit, G, max_order, flat_gather, use_dma, swz, Lam_a, Lam_b, coef, m2a, m2b, Ba, Bb,
-                             partial, n_slots, slot0, st, wmask);
+                             partial, n_slots, slot0, st, wmask, WalkerList());
 }
 
 int energy_minor_blocks(const DevSpin& s) {
