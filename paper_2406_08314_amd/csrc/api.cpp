@@ -137,6 +137,7 @@ struct msd_system {
   cd* logo_tmp = nullptr;
   cd* eloc = nullptr;
   cd* onebody = nullptr;   // [2][NW]
+  cd* ob_part = nullptr;   // [2][NW][orbital tiles] one-body partials of the Green kernel
   cd* segp[2] = {nullptr, nullptr};  // CI-weight segment partials
   double* fb_ws = nullptr;           // split-K workspace of the force-bias GEMM
   int fb_splitk = 1, fb_splitk_auto = 1, fb_ws_cap = 0;
@@ -237,16 +238,25 @@ struct msd_system {
     double dt = 0.0, e_shift = 0.0;
   };
   hipStream_t cap_st = nullptr;
-  GraphSlot g_step[2];     // [QR in this step]
-  GraphSlot g_measure[2];  // [energy requested]
+  GraphSlot g_step[2][2];     // [QR in this step][T fresh at the start]
+  GraphSlot g_measure[2][2];  // [energy requested][T fresh at the start]
   uint64_t version = 0;  // bumped whenever captured graphs become stale
   void drop_graphs() {
     ++version;
-    for (GraphSlot* g : {&g_step[0], &g_step[1], &g_measure[0], &g_measure[1]}) {
-      if (g->exec) (void)hipGraphExecDestroy(g->exec);
-      g->exec = nullptr;
-    }
+    for (auto* set : {&g_step, &g_measure})
+      for (auto& pair : *set)
+        for (GraphSlot& g : pair) {
+          if (g.exec) (void)hipGraphExecDestroy(g.exec);
+          g.exec = nullptr;
+        }
   }
+  // T = Phi A^-1, the excitation determinants, Obar and log det A hold for
+  // the current walkers: set by every overlap pass, kept by the QR step
+  // (Phi -> Phi R^-1 leaves T and the determinants unchanged and shifts log
+  // det A by -log det R), cleared by anything else that rewrites Phi or the
+  // trial (population control, new walkers, a new trial).  A propagation step
+  // then skips its first overlap pass and a measurement its reference inverse.
+  bool t_fresh = false;
   bool graphs_on() const { return o.graphs && !o.timing; }
 
   // timing
@@ -714,11 +724,12 @@ void check_flags(msd_system* s, const char* what) {
 
 // A1 + A3: T, log det A, per-string dets/adjugates (minors if requested),
 // Obar and log <Psi_T|Phi> into `logo_out`.
-void run_overlap(msd_system* s, bool minors, cd* logo_out) {
-  s->timed(ST_REF, [&] {
-    msd::launch_ref_inverse(s->phi, s->M, s->Ntot, s->NW, s->ds[0], s->ds[1], s->sw[0].T,
-                            s->sw[1].T, s->sw[0].logdetA, s->sw[1].logdetA, s->flag, s->st);
-  });
+void run_overlap(msd_system* s, bool minors, cd* logo_out, bool skip_ref = false) {
+  if (!skip_ref)
+    s->timed(ST_REF, [&] {
+      msd::launch_ref_inverse(s->phi, s->M, s->Ntot, s->NW, s->ds[0], s->ds[1], s->sw[0].T,
+                              s->sw[1].T, s->sw[0].logdetA, s->sw[1].logdetA, s->flag, s->st);
+    });
   s->timed(ST_STR, [&] {
     msd::launch_strings(s->ds[0], s->ds[1], s->sw[0].T, s->sw[1].T, s->NW, minors, s->sw[0],
                         s->sw[1], s->st);
@@ -742,8 +753,8 @@ void run_green_fb(msd_system* s, double dt) {
   });
   s->timed(ST_CIM, [&] { msd::launch_ci_matrix(s->ds[0], s->ds[1], s->NW, s->sw[0], s->sw[1], s->st); });
   s->timed(ST_GREEN, [&] {
-    msd::launch_green(s->ds[0], s->ds[1], s->M, s->NW, s->sw[0], s->sw[1], s->onebody,
-                      s->onebody + s->NW, s->obar, s->h1, s->st);
+    msd::launch_green(s->ds[0], s->ds[1], s->M, s->NW, s->sw[0], s->sw[1], s->onebody, s->obar,
+                      s->h1, s->ob_part, s->st);
   });
   s->timed(ST_GREEN, [&] {
     msd::launch_green_sum(s->M, s->NW, s->P_all, s->rmap[0], s->rmap[1], s->ds[0].P,
@@ -1127,8 +1138,10 @@ void run_energy(msd_system* s) {
 
 // The measurement kernels (A1-A7) into logo_tmp, xbar, eloc.
 void measure_body(msd_system* s, double dt, bool want_e) {
-  clear_flags(s);
-  run_overlap(s, want_e, s->logo_tmp);
+  // with T fresh the flags of the pass that made it still describe the walkers
+  if (!s->t_fresh) clear_flags(s);
+  run_overlap(s, want_e, s->logo_tmp, s->t_fresh);
+  s->t_fresh = true;
   run_green_fb(s, dt);
   if (want_e) run_energy(s);
 }
@@ -1139,7 +1152,9 @@ void measure_impl(msd_system* s, double dt, bool want_e) {
   if (!(dt >= 0.0) || !std::isfinite(dt)) fail(MSD_ERR_ARG, "dt must be finite and >= 0");
   if (want_e && s->tt.max_k() > msd::KMAX) fail(MSD_ERR_UNSUPPORTED, "excitation order too high");
   if (want_e) alloc_energy(s);
-  run_or_replay(s, s->g_measure[want_e ? 1 : 0], dt, 0.0, [&] { measure_body(s, dt, want_e); });
+  run_or_replay(s, s->g_measure[want_e ? 1 : 0][s->t_fresh ? 1 : 0], dt, 0.0,
+                [&] { measure_body(s, dt, want_e); });
+  s->t_fresh = true;
 }
 
 void ensure_b1(msd_system* s, double dt) {
@@ -1183,7 +1198,9 @@ void propagate_step(msd_system* s, const double* x, double dt, double e_shift, b
   const size_t mm = (size_t)M * M;
   clear_flags(s);
   msd::launch_frozen_mask(NW, s->weights, s->mask, s->st);
-  run_overlap(s, false, s->logo_tmp);
+  // the overlap pass at the current walkers (the force bias needs T, the
+  // determinants and Obar), unless the last pass left them valid
+  if (!s->t_fresh) run_overlap(s, false, s->logo_tmp);
   run_green_fb(s, dt);
   s->timed(ST_VHS_GEMM, [&] {
     msd::launch_vhs_prep(NW, NG, x, s->xbar, std::sqrt(dt), s->weights, s->Y, s->st);
@@ -1254,9 +1271,11 @@ void propagate_step(msd_system* s, const double* x, double dt, double e_shift, b
     msd::launch_weights(NW, NG, x, s->xbar, s->logo_tmp, s->logo, s->weights, dt, e_shift,
                         s->st);
   });
+  s->t_fresh = true;  // the second pass above; the QR step keeps it
   if (qr) {
     s->timed(ST_QR, [&] {
-      msd::launch_qr(s->phi, M, Ntot, NW, s->na, s->nb, s->mask, s->qr_ldet, s->logo, s->st);
+      msd::launch_qr(s->phi, M, Ntot, NW, s->na, s->nb, s->mask, s->qr_ldet, s->logo,
+                     s->sw[0].logdetA, s->sw[1].logdetA, s->st);
     });
   }
 }
@@ -1281,9 +1300,10 @@ void propagate_impl(msd_system* s, const double* fields_dev, double dt, double e
                 "fields");
       x = s->fields;
     }
-    run_or_replay(s, s->g_step[qr ? 1 : 0], dt, e_shift, [&] {
+    run_or_replay(s, s->g_step[qr ? 1 : 0][s->t_fresh ? 1 : 0], dt, e_shift, [&] {
       propagate_step(s, x, dt, e_shift, qr);
     });
+    s->t_fresh = true;
     s->check_launch("propagate");
   }
 }
@@ -1297,6 +1317,7 @@ void comb_impl(msd_system* s, double z, int* parent) {
   if (!s->have_walkers) fail(MSD_ERR_STATE, "walkers have not been set");
   if (!(z >= 0.0 && z < 1.0)) fail(MSD_ERR_ARG, "comb offset z must lie in [0, 1)");
   int* par = parent ? parent : s->pc_parent;
+  s->t_fresh = false;  // walkers are replaced by copies of their parents
   s->timed(ST_POP, [&] {
     msd::launch_comb(s->NW, z, s->weights, s->pc_cum, par, s->phi, s->logo,
                      (int64_t)s->M * s->Ntot, s->acc, s->pc_logo, s->st);
@@ -1357,6 +1378,7 @@ void comb_noalloc_impl(msd_system* s, double z, int* parent) {
   cd* logo_out = reinterpret_cast<cd*>(b + b_phi);
   double* cum = reinterpret_cast<double*>(b + b_phi + b_logo);
   int* par = parent ? parent : reinterpret_cast<int*>(b + b_phi + b_logo + b_cum);
+  s->t_fresh = false;  // walkers are replaced by copies of their parents
   msd::launch_comb(s->NW, z, s->weights, cum, par, s->phi, s->logo, (int64_t)per_w, phi_out,
                    logo_out, s->st);
   hip_check(hipMemcpyAsync(s->phi, phi_out, sizeof(cd) * NW * per_w, hipMemcpyDeviceToDevice,
@@ -1370,6 +1392,7 @@ void comb_noalloc_impl(msd_system* s, double z, int* parent) {
 void set_walkers_impl(msd_system* s, const cd* pa_dev, const cd* pb_dev, const double* w_dev) {
   if (!s->have_trial || !s->have_ham)
     fail(MSD_ERR_STATE, "msd_set_hamiltonian and msd_set_trial_occ must precede msd_set_walkers");
+  s->t_fresh = false;
   msd::launch_copy_walkers(s->NW, s->M, s->Ntot, s->na, s->nb, pa_dev, pb_dev, s->phi, true,
                            nullptr, nullptr, s->st);
   if (w_dev) {
@@ -1389,6 +1412,7 @@ void set_walkers_impl(msd_system* s, const cd* pa_dev, const cd* pb_dev, const d
   clear_flags(s);
   run_overlap(s, false, s->logo);
   check_flags(s, "msd_set_walkers");
+  s->t_fresh = true;
 }
 
 }  // namespace
@@ -1489,6 +1513,7 @@ msd_status msd_create(const msd_dims* d, const msd_options* o, int32_t device, v
     sys->xbar = A.get<cd>((size_t)NW * NG);
     sys->eloc = A.get<cd>(NW);
     sys->onebody = A.get<cd>(2 * (size_t)NW);
+    sys->ob_part = A.get<cd>(2 * (size_t)NW * msd::green_tiles(M));
     sys->Y = A.get<double>((size_t)2 * NW * NG);
     sys->VHS = A.get<double>((size_t)2 * NW * M * M);
     sys->term[0] = A.get<cd>((size_t)NW * M * Ntot);
@@ -1786,6 +1811,7 @@ void set_trial_rows(msd_system* sys, const double* ci, const int32_t* occ_a,
   sys->drop_graphs();
   sys->sync();
   sys->have_trial = true;
+  sys->t_fresh = false;
   sys->have_walkers = false;
   if (sys->have_ham) build_derived(sys);
 }
@@ -2247,6 +2273,7 @@ msd_status msd_batch_step(msd_batch* b, const double* const* fields, double dt, 
     s->steps_done++;
     qr[i] = s->o.stabilize_freq > 0 && s->steps_done % s->o.stabilize_freq == 0;
     key += qr[i] ? '1' : '0';
+    key += s->t_fresh ? 'f' : 'n';
     hip_check(hipMemcpyAsync(s->fields, fields[i], sizeof(double) * s->NW * s->NG,
                              hipMemcpyDeviceToDevice, b->st),
               "fields");
@@ -2309,6 +2336,7 @@ msd_status msd_batch_step(msd_batch* b, const double* const* fields, double dt, 
     }
     hip_check(hipGraphLaunch(e.exec, b->st), "hipGraphLaunch");
   }
+  for (msd_system* s : b->sys) s->t_fresh = true;  // each step ends with an overlap pass
   // later work on each system's stream sees this step
   hip_check(hipEventRecord(b->ev, b->st), "record");
   for (msd_system* s : b->sys) hip_check(hipStreamWaitEvent(s->st, b->ev, 0), "wait");

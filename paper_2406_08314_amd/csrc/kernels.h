@@ -128,9 +128,12 @@ void launch_ci_weights(const DevSpin& sa, const DevSpin& sb, const cd* det_c, co
                        const SpinWork& wb, cd* seg_a, cd* seg_b, int NW, hipStream_t st);
 void launch_ci_matrix(const DevSpin& sa, const DevSpin& sb, int NW, const SpinWork& wa,
                       const SpinWork& wb, hipStream_t st);
+// G rows and the one-body energies onebody[spin][w] ([2][NW]); ob_part is
+// scratch of 2 * NW * green_tiles(M) entries
+int green_tiles(int M);
 void launch_green(const DevSpin& sa, const DevSpin& sb, int M, int NW, const SpinWork& wa,
-                  const SpinWork& wb, cd* ob_a, cd* ob_b, const cd* obar, const double* h1,
-                  hipStream_t st);
+                  const SpinWork& wb, cd* onebody, const cd* obar, const double* h1,
+                  cd* ob_part, hipStream_t st);
 void launch_green_sum(int M, int NW, int P_all, const int* rmap_a, const int* rmap_b,
                       int Pa, int Pb, const cd* Ga, const cd* Gb, double* Gp,
                       hipStream_t st);
@@ -305,8 +308,10 @@ void launch_vhs_prep(int NW, int NG, const double* x, const cd* xbar, double sqr
                      const double* weights, double* Y, hipStream_t st);
 void launch_weights(int NW, int NG, const double* x, const cd* xbar, const cd* logo_new,
                     cd* logo, double* weights, double dt, double e_shift, hipStream_t st);
+// Cholesky-QR of every unmasked walker; logo and the per-spin log det A
+// (when not null) shift by -log det R
 void launch_qr(cd* phi, int M, int Ntot, int NW, int na, int nb, const int* mask, double* ldet,
-               cd* logo, hipStream_t st);
+               cd* logo, cd* logdetA_a, cd* logdetA_b, hipStream_t st);
 void launch_frozen_mask(int NW, const double* weights, int* mask, hipStream_t st);
 // v0 = tr Q, ex0 = tr QQ in FP64 from Q tiles [wl][g][N x N] of both spins.
 void launch_traces64(const cd* Qa, const cd* Qb, int Na, int Nb, int NW, int w0, int WT, int NG,

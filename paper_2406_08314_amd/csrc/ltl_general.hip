@@ -408,22 +408,37 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
         }
         cb = cb + 1 == NB ? 0 : cb + 1;
       };
-      auto mma = [&](const R (&a)[4][RT], const R (&bv)[4]) {
+      // k-steps 2h, 2h + 1 of a slab
+      auto mma_h = [&](const R (&a)[4][RT], const R (&bv)[4], int h) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
+        for (int s = 2 * h; s < 2 * h + 2; ++s)
 #pragma unroll
           for (int rt = 0; rt < RT; ++rt) acc[rt] = MF::run(a[s][rt], bv[s], acc[rt]);
       };
+      auto mma = [&](const R (&a)[4][RT], const R (&bv)[4]) {
+        mma_h(a, bv, 0);
+        mma_h(a, bv, 1);
+      };
       if constexpr (RT <= 4) {
+        // half of the current slab's products are issued before the wait for
+        // the next slab, the other half after its reads (kept in this order:
+        // the matrix cores stay busy through the wait and the reads land
+        // during the second half)
         R a0[4][RT], b0[4], a1[4][RT], b1[4];
         load(a0, b0, 0);
         for (int sl = 0; sl < n_sl; sl += 2) {
           const bool more = sl + 1 < n_sl;
+          mma_h(a0, b0, 0);
+          __builtin_amdgcn_sched_barrier(0);
           if (more) load(a1, b1, sl + 1);
-          mma(a0, b0);
+          __builtin_amdgcn_sched_barrier(0);
+          mma_h(a0, b0, 1);
           if (!more) break;
+          mma_h(a1, b1, 0);
+          __builtin_amdgcn_sched_barrier(0);
           if (sl + 2 < n_sl) load(a0, b0, sl + 2);
-          mma(a1, b1);
+          __builtin_amdgcn_sched_barrier(0);
+          mma_h(a1, b1, 1);
         }
       } else {
         // five or more row tiles: one operand set (a second one would spill)

@@ -171,25 +171,30 @@ __global__ __launch_bounds__(256) void k_qr(cd* __restrict__ phi, int M, int Nto
   if (tid == 0) ldet_out[2 * w + blockIdx.y] = bad ? INFINITY : ldet;
 }
 
-// log <Psi_T|Phi> -= sum_s log det R^s after the re-orthonormalisation
+// log <Psi_T|Phi> -= sum_s log det R^s after the re-orthonormalisation, and
+// log det A^s -= log det R^s (A^s = the reference rows of Phi^s, which become
+// A^s (R^s)^-1; T = Phi A^-1 itself is unchanged)
 __global__ void k_qr_logo(int NW, const int* __restrict__ mask, const double* __restrict__ ldet,
-                          cd* __restrict__ logo) {
+                          cd* __restrict__ logo, cd* __restrict__ lda, cd* __restrict__ ldb) {
   const int w = blockIdx.x * blockDim.x + threadIdx.x;
   if (w >= NW || (mask && mask[w] == 0)) return;
   const double l = ldet[2 * w] + ldet[2 * w + 1];
   const cd o = logo[w];
   logo[w] = l < INFINITY ? cd{o.re - l, o.im} : cd{-INFINITY, 0.0};
+  if (lda && ldet[2 * w] < INFINITY) lda[w] = cd{lda[w].re - ldet[2 * w], lda[w].im};
+  if (ldb && ldet[2 * w + 1] < INFINITY) ldb[w] = cd{ldb[w].re - ldet[2 * w + 1], ldb[w].im};
 }
 
 void launch_qr(cd* phi, int M, int Ntot, int NW, int na, int nb, const int* mask, double* ldet,
-               cd* logo, hipStream_t st) {
+               cd* logo, cd* logdetA_a, cd* logdetA_b, hipStream_t st) {
   const int N = max(na, nb);
   // one wave for small N (barrier-bound Cholesky steps; at most N*N Gram
   // entries, one row of Phi per lane and pass)
   const int bs = N <= 8 ? 64 : 256;
   hipLaunchKernelGGL(k_qr, dim3(NW, 2), dim3(bs), 2 * (size_t)N * N * sizeof(cd), st, phi, M, Ntot,
                      NW, na, nb, mask, ldet);
-  hipLaunchKernelGGL(k_qr_logo, dim3((NW + 255) / 256), dim3(256), 0, st, NW, mask, ldet, logo);
+  hipLaunchKernelGGL(k_qr_logo, dim3((NW + 255) / 256), dim3(256), 0, st, NW, mask, ldet, logo,
+                     logdetA_a, logdetA_b);
 }
 
 // Pack the per-spin boundary layouts [w][M][n_s] into the internal [w][M][Ntot]

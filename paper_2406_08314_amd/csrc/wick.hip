@@ -664,17 +664,25 @@ void launch_ci_matrix(const DevSpin& sa, const DevSpin& sb, int NW, const SpinWo
 // A5: Green's function rows R u V_act and one-body energy
 // ============================================================================
 
-constexpr int G_QT = 64;
+// One workgroup per (walker, spin, tile of G_QT orbitals q): the tile's rows
+// of T (T[q][w][:], contiguous per q) are staged in LDS once, then
+//   D[a][q]    = sum_i C[a][i] T[q][slot(i)]                 (n_v x G_QT)
+//   G[r][q]    = T[q][r] - sum_a T_V[a][r] D[a][q] / Obar    (reference rows r < N)
+//   G[N+a][q]  = D[a][q] / Obar                               (window virtual rows)
+// and the tile's part of the one-body energy sum_{r,q} h1[row r][q] G[r][q]
+// goes to ob_part[spin][w][tile] (summed by k_green_ob).
+constexpr int G_QT = 16;
 
 struct GreenIO {
   const cd* T;
   const cd* C;
   cd* G;
-  cd* onebody;
+  cd* ob_part;
 };
 
 __global__ __launch_bounds__(256) void k_green(DevSpin sa, DevSpin sb, GreenIO ia, GreenIO ib,
-                                               int M, int NW, const cd* __restrict__ obar,
+                                               int M, int NW, int n_qt,
+                                               const cd* __restrict__ obar,
                                                const double* __restrict__ h1) {
   const bool beta = blockIdx.y == 1;
   const DevSpin& s = beta ? sb : sa;
@@ -682,62 +690,78 @@ __global__ __launch_bounds__(256) void k_green(DevSpin sa, DevSpin sb, GreenIO i
   const cd* __restrict__ T = io.T;
   const cd* __restrict__ C = io.C;
   cd* __restrict__ G = io.G;
-  cd* __restrict__ onebody = io.onebody;
   extern __shared__ cd sm[];
   __shared__ cd red[256];
   const int nv = s.nv, no = s.no, N = s.N, P = s.P;
-  cd* Cs = sm;                 // [nv*no]
-  cd* TV = Cs + nv * no;       // [nv*N]
-  cd* D = TV + nv * N;         // [nv*G_QT]
-  const int w = blockIdx.x, tid = threadIdx.x, bd = blockDim.x;
+  const int w = blockIdx.x, qt = blockIdx.z, tid = threadIdx.x, bd = blockDim.x;
+  const int q0 = qt * G_QT, nq = min(G_QT, M - q0);
+  cd* Cs = sm;                 // [nv][no]
+  cd* TV = Cs + nv * no;       // [nv][N]
+  cd* Tq = TV + nv * N;        // [G_QT][N]: rows q0 .. q0 + nq of T
+  cd* D = Tq + G_QT * N;       // [nv][G_QT]
   const cd inv_o = cdiv(cd{1.0, 0.0}, obar[w]);
   for (int e = tid; e < nv * no; e += bd) Cs[e] = C[(size_t)w * nv * no + e];
   for (int e = tid; e < nv * N; e += bd) {
-    int a = e / N, j = e % N;
+    const int a = e / N, j = e % N;
     TV[e] = T[((size_t)s.vir[a] * NW + w) * N + j];
+  }
+  for (int e = tid; e < nq * N; e += bd) {
+    const int ql = e / N, j = e % N;
+    Tq[e] = T[((size_t)(q0 + ql) * NW + w) * N + j];
+  }
+  __syncthreads();
+  for (int e = tid; e < nv * G_QT; e += bd) {
+    const int a = e / G_QT, ql = e % G_QT;
+    cd acc{0.0, 0.0};
+    if (ql < nq)
+      for (int i = 0; i < no; ++i) cfma(acc, Cs[a * no + i], Tq[ql * N + s.oslot[i]]);
+    D[e] = acc;
   }
   __syncthreads();
   cd ob{0.0, 0.0};
-  for (int q0 = 0; q0 < M; q0 += G_QT) {
-    for (int e = tid; e < nv * G_QT; e += bd) {
-      int a = e / G_QT, q = q0 + e % G_QT;
+  for (int e = tid; e < P * G_QT; e += bd) {
+    const int r = e / G_QT, ql = e % G_QT, q = q0 + ql;
+    if (ql >= nq) continue;
+    cd g;
+    if (r < N) {
       cd acc{0.0, 0.0};
-      if (q < M) {
-        const cd* Tq = T + ((size_t)q * NW + w) * N;
-        for (int i = 0; i < no; ++i) cfma(acc, Cs[a * no + i], Tq[s.oslot[i]]);
-      }
-      D[e] = acc;
+      for (int a = 0; a < nv; ++a) cfma(acc, TV[a * N + r], D[a * G_QT + ql]);
+      g = Tq[ql * N + r] - inv_o * acc;
+    } else {
+      g = inv_o * D[(r - N) * G_QT + ql];
     }
-    __syncthreads();
-    for (int e = tid; e < P * G_QT; e += bd) {
-      int r = e / G_QT, ql = e % G_QT, q = q0 + ql;
-      if (q >= M) continue;
-      cd g;
-      if (r < N) {
-        cd acc{0.0, 0.0};
-        for (int a = 0; a < nv; ++a) cfma(acc, TV[a * N + r], D[a * G_QT + ql]);
-        g = T[((size_t)q * NW + w) * N + r] - inv_o * acc;
-      } else {
-        g = inv_o * D[(r - N) * G_QT + ql];
-      }
-      G[((size_t)w * P + r) * M + q] = g;
-      ob += h1[(size_t)s.rows[r] * M + q] * g;
-    }
-    __syncthreads();
+    G[((size_t)w * P + r) * M + q] = g;
+    ob += h1[(size_t)s.rows[r] * M + q] * g;
   }
-  cd tot = block_reduce(ob, red);
-  if (tid == 0) onebody[w] = tot;
+  const cd tot = block_reduce(ob, red);
+  if (tid == 0) io.ob_part[(size_t)w * n_qt + qt] = tot;
 }
 
+// onebody[w] = sum over the orbital tiles of ob_part[w][tile] (both spins)
+__global__ void k_green_ob(int n, int n_qt, const cd* __restrict__ ob_part,
+                           cd* __restrict__ onebody) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  cd t{0.0, 0.0};
+  for (int z = 0; z < n_qt; ++z) t += ob_part[(size_t)i * n_qt + z];
+  onebody[i] = t;
+}
+
+int green_tiles(int M) { return (M + G_QT - 1) / G_QT; }
+
 void launch_green(const DevSpin& sa, const DevSpin& sb, int M, int NW, const SpinWork& wa,
-                  const SpinWork& wb, cd* ob_a, cd* ob_b, const cd* obar, const double* h1,
-                  hipStream_t st) {
+                  const SpinWork& wb, cd* onebody, const cd* obar, const double* h1,
+                  cd* ob_part, hipStream_t st) {
   size_t lds = 0;
   for (const DevSpin* s : {&sa, &sb})
-    lds = max(lds, ((size_t)s->nv * s->no + (size_t)s->nv * s->N + (size_t)s->nv * G_QT) *
-                       sizeof(cd));
-  const GreenIO ia{wa.T, wa.C, wa.G, ob_a}, ib{wb.T, wb.C, wb.G, ob_b};
-  hipLaunchKernelGGL(k_green, dim3(NW, 2), dim3(256), lds, st, sa, sb, ia, ib, M, NW, obar, h1);
+    lds = max(lds, ((size_t)s->nv * s->no + (size_t)s->nv * s->N + (size_t)G_QT * s->N +
+                    (size_t)s->nv * G_QT) * sizeof(cd));
+  const int n_qt = green_tiles(M);
+  const GreenIO ia{wa.T, wa.C, wa.G, ob_part}, ib{wb.T, wb.C, wb.G, ob_part + (size_t)NW * n_qt};
+  hipLaunchKernelGGL(k_green, dim3(NW, 2, n_qt), dim3(256), lds, st, sa, sb, ia, ib, M, NW, n_qt,
+                     obar, h1);
+  hipLaunchKernelGGL(k_green_ob, dim3((2 * NW + 255) / 256), dim3(256), 0, st, 2 * NW, n_qt,
+                     ob_part, onebody);
 }
 
 __global__ void k_green_sum(int M, int NW, int P_all, const int* __restrict__ rmap_a,
