@@ -293,7 +293,11 @@ typedef struct {
   int32_t energy_form;    /* read-only (msd_get_tuning): 1 when the second-order terms
                              run in the W-form (see energy_algo), 0 for the direct form;
                              ignored by msd_set_tuning                                     */
-  int32_t reserved[2];
+  int32_t second_whole;   /* same-spin strings of order 3 in the second-order kernel:
+                             1 = one row pair (two columns of the string's 3 x 3 block)
+                             per lane, 2 = one whole string per lane (its block gathered
+                             once per Cholesky vector); 0 = automatic (2)                */
+  int32_t reserved;
 } msd_tuning;
 msd_status msd_get_tuning(msd_system* sys, msd_tuning* out);
 /* Sets overrides (validated; MSD_ERR_ARG names the bad field).  Drops the

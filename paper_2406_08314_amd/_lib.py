@@ -27,7 +27,7 @@ class MsdTuning(C.Structure):
                 ("second_stage", C.c_int32), ("second_gather", C.c_int32),
                 ("second_copy", C.c_int32), ("second_waves", C.c_int32),
                 ("walker_tile", C.c_int32), ("energy_form", C.c_int32),
-                ("reserved", C.c_int32 * 2)]
+                ("second_whole", C.c_int32), ("reserved", C.c_int32)]
 
 
 class MsdOptions(C.Structure):

@@ -202,7 +202,8 @@ class MsdSystem:
         return out
 
     _TUNING = ("fb_splitk", "lambda_variant", "lambda_chunk", "second_gsplit", "second_stage",
-               "second_gather", "second_copy", "second_waves", "walker_tile", "energy_form")
+               "second_gather", "second_copy", "second_waves", "walker_tile", "energy_form",
+               "second_whole")
 
     def get_tuning(self):
         t = _lib.MsdTuning()

@@ -467,7 +467,14 @@ void alloc_energy(msd_system* s) {
     if (!strings) continue;
     for (int i = 0; i < S.U; ++i) s->second_maxk = std::max(s->second_maxk, (int)S.k[i]);
     for (int k = 2; k <= msd::ER_MAX_ORDER; ++k) {
-      const int n_items = (S.bucket[k + 1] - S.bucket[k]) * (k * (k - 1) / 2);
+      const int n_str = S.bucket[k + 1] - S.bucket[k];
+      if (k == 3 && s->tune.second_whole != 1) {
+        // whole strings: one lane per string gathers its 3 x 3 block once
+        for (int f = 0; f < n_str; f += 64)
+          pl.push_back(int4{(msd::ER_WHOLE | k) | (sp << 8), S.bucket[k], f, n_str});
+        continue;
+      }
+      const int n_items = n_str * (k * (k - 1) / 2);
       for (int f = 0; f < n_items; f += 64) pl.push_back(int4{k | (sp << 8), S.bucket[k], f, n_items});
     }
   }
@@ -2374,6 +2381,7 @@ void set_tuning_impl(msd_system* s, const msd_tuning& t) {
   if (t.second_copy < 0 || t.second_copy > 2) bad("second_copy");
   if (t.second_waves != 0 && t.second_waves != 8 && t.second_waves != 16) bad("second_waves");
   if (t.walker_tile < 0) bad("walker_tile");
+  if (t.second_whole < 0 || t.second_whole > 2) bad("second_whole");
   s->tune = t;
   s->tune.energy_form = 0;  // read-only
   free_energy(s);
@@ -2412,6 +2420,7 @@ msd_status msd_get_tuning(msd_system* sys, msd_tuning* out) {
     out->second_waves = sys->second_waves;
     out->walker_tile = sys->WT;
     out->energy_form = sys->wform ? 1 : 0;
+    out->second_whole = sys->tune.second_whole == 1 ? 1 : 2;
   }
   API_END(sys)
 }
@@ -2502,6 +2511,7 @@ msd_status msd_autotune(msd_system* sys, double dt, int32_t reps, msd_tuning* ou
     out->second_waves = sys->second_waves;
     out->walker_tile = sys->WT;
     out->energy_form = sys->wform ? 1 : 0;
+    out->second_whole = sys->tune.second_whole == 1 ? 1 : 2;
   }
   API_END(sys)
 }

@@ -255,8 +255,9 @@ void launch_pair_coef(const DevPairs& pr, int NW, const cd* det_c, const cd* adj
 void launch_minor_coef(const DevSpin& s, int NW, const cd* B, int U, const cd* m2, cd* coef,
                        hipStream_t st);
 // second-order energy terms; each launch writes blocks into partial[w][slot0 + ...]
-// plan roles: ER_PAIRS, or 2..6 = row-pair items of strings of that order
-enum EnergyRole { ER_NONE = 0, ER_PAIRS = 1 };
+// plan roles: ER_PAIRS, 2..6 = row-pair items of strings of that order, or
+// ER_WHOLE | K (K = 3, 4) = whole strings of order K, one per lane
+enum EnergyRole { ER_NONE = 0, ER_PAIRS = 1, ER_WHOLE = 0x10 };
 constexpr int ER_MAX_ORDER = 6;
 constexpr int ER_WAVES = 8;  // waves per workgroup of the merged second-order kernel
 constexpr int ER_PAIRS_PER_WAVE = 256;  // 64 lanes x 4 pairs

@@ -1545,6 +1545,9 @@ __global__ __launch_bounds__((MAXK <= 4 ? 1024 : 512)) void k_energy_second(
     const int* __restrict__ wmask, const int* __restrict__ wlist, const int* __restrict__ wcount,
     int WT) {
   constexpr int NIDX = 2 * MAXK > 2 * ER_PPL ? 2 * MAXK : 2 * ER_PPL;
+  // whole strings of order 4 keep 36 complex coefficients per lane: single
+  // precision only (in FP64 they would spill)
+  constexpr bool WHOLE4 = sizeof(CT) == sizeof(cf);
   constexpr int NMM = MAXK * (MAXK - 1) / 2;
   extern __shared__ __align__(16) unsigned char sm_raw[];
   CT* sm = reinterpret_cast<CT*>(sm_raw);
@@ -1592,10 +1595,11 @@ __global__ __launch_bounds__((MAXK <= 4 ? 1024 : 512)) void k_energy_second(
   for (int j = 0; j < NMM; ++j) mm[j] = CT{};
 #pragma unroll
   for (int j = 0; j < ER_PPL; ++j) acc[j] = CT{};
+  const bool whole = (role & ER_WHOLE) != 0;  // one string per lane (all its row pairs)
   const int item = role == ER_PAIRS ? pl.z + lane * ER_PPL : pl.z + lane;
   const bool live = role != ER_NONE && item < pl.w;
-  int str = 0;
-  if (live) {
+  int str = whole ? pl.y + item : 0;
+  if (live && !whole) {
     if (role == ER_PAIRS) {
 #pragma unroll
       for (int j = 0; j < ER_PPL; ++j) {
@@ -1713,7 +1717,82 @@ __global__ __launch_bounds__((MAXK <= 4 ? 1024 : 512)) void k_energy_second(
       }
     });
   };
-  if (role == ER_PAIRS) {
+  // whole strings of order K: the K x K window block Y (Y[m][n] = Lambda at
+  // particle n, hole m) is gathered once per vector and every row pair (m, m')
+  // of the string is contracted from registers: K^2 gathers per string and
+  // vector instead of 2K per row pair
+  auto whole_rows = [&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    constexpr int P = K * (K - 1) / 2;
+    // window entry of (particle n, hole m) = pofs[n] + hofs[m] (offsets kept
+    // per particle and per hole: 2K registers instead of K^2)
+    int pofs[K], hofs[K];
+    CT wmm[P * P];
+#pragma unroll
+    for (int j = 0; j < K; ++j) pofs[j] = hofs[j] = 0;
+#pragma unroll
+    for (int j = 0; j < P * P; ++j) wmm[j] = CT{};
+    if (live) {
+      const int* hwin = sp ? sb.hwin : sa.hwin;
+      const int* pwin = sp ? sb.pwin : sa.pwin;
+      const int no = sp ? sb.no : sa.no;
+      const cd* m2s = (sp ? m2b + (size_t)w * sb.M2 + sb.m2_off[str]
+                          : m2a + (size_t)w * sa.M2 + sa.m2_off[str]);
+#pragma unroll
+      for (int n = 0; n < K; ++n) {
+        pofs[n] = pwin[str * KMAX + n] * no;
+        hofs[n] = hwin[str * KMAX + n];
+      }
+      int rp = 0;
+#pragma unroll
+      for (int m = 0; m < K; ++m)
+#pragma unroll
+        for (int mp = m + 1; mp < K; ++mp, ++rp) {
+          int q = 0;
+#pragma unroll
+          for (int n = 0; n < K; ++n)
+#pragma unroll
+            for (int np = n + 1; np < K; ++np, ++q) {
+              cd v = m2s[rp * P + q];
+              if ((m + mp + n + np) & 1) v = -v;
+              wmm[rp * P + q] = from_cd<CT>(v);
+            }
+        }
+    }
+    const int Xs = sp ? Xb : Xa;
+    run_stages([&](int oa, int ob, int Gs) {
+      const int os = sp ? ob : oa;
+      for (int gl = 0; gl < Gs; ++gl) {
+        CT y[K * K];
+        const int base = os + gl * Xs;
+#pragma unroll
+        for (int m = 0; m < K; ++m)
+#pragma unroll
+          for (int n = 0; n < K; ++n) {
+            const int e = pofs[n] + hofs[m];
+            y[m * K + n] = gs_[base + (swz ? lam_swizzle(e) : e)];
+          }
+        int rp = 0;
+#pragma unroll
+        for (int m = 0; m < K; ++m)
+#pragma unroll
+          for (int mp = m + 1; mp < K; ++mp, ++rp) {
+            CT yy[2 * K];
+#pragma unroll
+            for (int n = 0; n < K; ++n) {
+              yy[n] = y[m * K + n];
+              yy[K + n] = y[mp * K + n];
+            }
+            rp_math<K, CT>(yy, wmm + rp * P, acc[0]);
+          }
+      }
+    });
+  };
+  if (role == (ER_WHOLE | 3)) {
+    whole_rows(std::integral_constant<int, 3>{});
+  } else if (WHOLE4 && role == (ER_WHOLE | 4)) {
+    whole_rows(std::integral_constant<int, (WHOLE4 ? 4 : 3)>{});
+  } else if (role == ER_PAIRS) {
     run_stages([&](int oa, int ob, int Gs) {
       // each pair's operands for the next vector are loaded into its own
       // registers once the current product is formed (a second register

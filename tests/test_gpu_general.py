@@ -84,6 +84,25 @@ def test_general_kernel_chunks_and_tiles(tuning):
     _check(wl, out, [1, 3])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_whole_string_items_match_row_pairs(precision):
+    """Order-3 strings as whole-string items (one lane gathers the 3 x 3 block
+    once per vector) against one row pair per lane: the same sums in another
+    grouping (1e-10 relative in FP64; 1e-7 relative in the single-precision
+    form, whose products round differently)."""
+    wl = _workload("n30_m150_unequal")
+    out = {}
+    for whole in (1, 2):
+        s = _system(wl, precision, second_whole=whole)
+        out[whole] = s.measure(wl.dt)
+        assert s.get_tuning()["second_whole"] == whole
+    e1, e2 = out[1]["e_loc"], out[2]["e_loc"]
+    tol = (TOL if precision == "fp64" else 1e-7) * max(1.0, np.max(np.abs(e1)))
+    assert np.max(np.abs(e1 - e2)) <= tol
+    if precision == "fp64":
+        _check(wl, out[2], [0, wl.n_walkers - 1])
+
+
 @pytest.mark.parametrize("name", ["n12_m40", "n30_m150_unequal", "n40_m96", "n20_m240"])
 def test_general_kernel_mixed_against_fp64(name):
     wl = _workload(name)

@@ -550,6 +550,8 @@ def test_uneven_batch_graph_matches_separate_systems():
     dict(second_waves=16, second_stage=5, second_gsplit=3, second_copy=2),
     dict(second_waves=16, second_stage=3, second_gsplit=1, second_copy=1, second_gather=2),
     dict(walker_tile=4),
+    dict(second_whole=1),                       # order-3 strings as row-pair items
+    dict(second_whole=2, second_stage=3, second_gsplit=2, second_waves=8),
 ])
 def test_tuning_overrides_keep_parity(tuning):
     """Ragged Cholesky chunks and stages (320 vectors split 5/7/3 ways) in
