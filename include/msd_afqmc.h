@@ -159,10 +159,13 @@ msd_status msd_set_trial_exc(msd_system* sys, const int32_t* ref_a, const int32_
                              const int32_t* k_b, const int64_t* offsets, const int32_t* holes,
                              const int32_t* parts);
 
-/* Walkers (host arrays).  phi_a: n_walkers*M*n_alpha complex, [w][p][j];
- * phi_b likewise with n_beta; weights: n_walkers doubles (NULL: all 1).
- * Needs the trial (MSD_ERR_STATE otherwise): computes log <Psi_T|Phi_w>.
- * MSD_ERR_SINGULAR if a walker has a singular reference block. */
+/* Walkers (host arrays): the walker state of the weighted-walker expansion
+ * of the ground state (Eq. 6, Sec. II.A): for each walker w its Slater
+ * determinant |Phi_w> (orbital coefficients per spin) and its weight.
+ * phi_a: n_walkers*M*n_alpha complex, [w][p][j]; phi_b likewise with n_beta;
+ * weights: n_walkers doubles (NULL: all 1).  Needs the trial (MSD_ERR_STATE
+ * otherwise): computes log <Psi_T|Phi_w>.  MSD_ERR_SINGULAR if a walker has a
+ * singular reference block. */
 msd_status msd_set_walkers(msd_system* sys, const double* phi_a, const double* phi_b,
                            const double* weights);
 /* Same with device pointers (same layouts); synchronises the stream. */
