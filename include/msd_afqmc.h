@@ -299,7 +299,8 @@ typedef struct {
   int32_t second_whole;   /* same-spin strings of order 3 in the second-order kernel:
                              1 = one row pair (two columns of the string's 3 x 3 block)
                              per lane, 2 = one whole string per lane (its block gathered
-                             once per Cholesky vector); 0 = automatic (2)                */
+                             once per Cholesky vector); 0 = automatic (2 where a spin
+                             has at least 512 strings of order 3, else 1)              */
   int32_t reserved;
 } msd_tuning;
 msd_status msd_get_tuning(msd_system* sys, msd_tuning* out);

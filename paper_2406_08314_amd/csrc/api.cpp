@@ -212,6 +212,7 @@ struct msd_system {
   int4* plan = nullptr;
   int n_itemblocks = 0, slot_second = 0, second_G = 1, second_maxk = 0, second_waves = 8;
   bool second_flat = false;  // gathers through a generic pointer (see k_energy_second)
+  bool second_whole_used = false;  // order-3 strings as whole-string items
   bool second_dma = true;    // stages Lambda by direct global-to-LDS loads
   cd* LT[2] = {nullptr, nullptr};
   cd* Lam[2] = {nullptr, nullptr};
@@ -423,6 +424,7 @@ void alloc_energy(msd_system* s) {
   std::vector<int4>& pl = s->plan_host;
   pl.clear();
   s->second_maxk = 0;
+  s->second_whole_used = false;
   const int np = s->dp.n_pair;
   {
     // W-form or direct form: algorithmic work per (walker, Cholesky vector)
@@ -468,7 +470,13 @@ void alloc_energy(msd_system* s) {
     for (int i = 0; i < S.U; ++i) s->second_maxk = std::max(s->second_maxk, (int)S.k[i]);
     for (int k = 2; k <= msd::ER_MAX_ORDER; ++k) {
       const int n_str = S.bucket[k + 1] - S.bucket[k];
-      if (k == 3 && s->tune.second_whole != 1) {
+      // whole order-3 strings where there are many (a whole-string wave does
+      // about three row-pair waves' work: with few of them the workgroups
+      // holding one wait on it at every stage barrier)
+      const bool whole3 =
+          k == 3 && (s->tune.second_whole == 2 || (s->tune.second_whole == 0 && n_str >= 512));
+      s->second_whole_used = s->second_whole_used || whole3;
+      if (whole3) {
         // whole strings: one lane per string gathers its 3 x 3 block once
         for (int f = 0; f < n_str; f += 64)
           pl.push_back(int4{(msd::ER_WHOLE | k) | (sp << 8), S.bucket[k], f, n_str});
@@ -2420,7 +2428,7 @@ msd_status msd_get_tuning(msd_system* sys, msd_tuning* out) {
     out->second_waves = sys->second_waves;
     out->walker_tile = sys->WT;
     out->energy_form = sys->wform ? 1 : 0;
-    out->second_whole = sys->tune.second_whole == 1 ? 1 : 2;
+    out->second_whole = sys->second_whole_used ? 2 : 1;
   }
   API_END(sys)
 }
@@ -2511,7 +2519,7 @@ msd_status msd_autotune(msd_system* sys, double dt, int32_t reps, msd_tuning* ou
     out->second_waves = sys->second_waves;
     out->walker_tile = sys->WT;
     out->energy_form = sys->wform ? 1 : 0;
-    out->second_whole = sys->tune.second_whole == 1 ? 1 : 2;
+    out->second_whole = sys->second_whole_used ? 2 : 1;
   }
   API_END(sys)
 }

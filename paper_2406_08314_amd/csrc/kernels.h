@@ -256,7 +256,8 @@ void launch_minor_coef(const DevSpin& s, int NW, const cd* B, int U, const cd* m
                        hipStream_t st);
 // second-order energy terms; each launch writes blocks into partial[w][slot0 + ...]
 // plan roles: ER_PAIRS, 2..6 = row-pair items of strings of that order, or
-// ER_WHOLE | K (K = 3, 4) = whole strings of order K, one per lane
+// ER_WHOLE | 3 = whole strings of order 3, one per lane (order 4 would keep 36
+// complex minors per lane: they spill)
 enum EnergyRole { ER_NONE = 0, ER_PAIRS = 1, ER_WHOLE = 0x10 };
 constexpr int ER_MAX_ORDER = 6;
 constexpr int ER_WAVES = 8;  // waves per workgroup of the merged second-order kernel

@@ -454,6 +454,55 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
       for (int sl = 0; sl < KSL; ++sl)
         if (sl < n_sl) slab(acc, sl, [&](int l, int s) { return bt[4 * l + s]; });
     }
+    // ---- Lam = T_V Q - LT_V: K = 2 Np over [Re T_V | Im T_V].  In FP64 the
+    // B operand Q[k][j] is this lane's own accumulator (register r of lane
+    // group q holds row q + 4r of its tile: row k = 4 kk + q is register kk %
+    // 4 of tile kk / 4), the other part of the complex entry one DPP row
+    // rotation away, so the products need no LDS and run before the barrier
+    // that publishes Q; in FP32 (row 4q + r) Q is read back from LDS.
+    acc_t lam[VT];
+    auto lam_phase = [&]() {
+#pragma unroll
+      for (int vt = 0; vt < VT; ++vt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) lam[vt][r] = -acc[vt][r];
+#pragma unroll
+      for (int kk = 0; kk < 2 * Np / 4; ++kk) {
+        const int k = 4 * kk + q;
+        const bool hi = kk >= Np / 4;  // imaginary rows of the block form of Q
+        const int kr = hi ? k - Np : k;
+        R bq;
+        if constexpr (sizeof(R) == 8) {
+          const int kq = hi ? kk - Np / 4 : kk;
+          const R own = acc[VT + kq / 4][kq % 4];
+          if (hi) {
+            const R oth = gl_other_part(own);
+            bq = part ? oth : -oth;
+          } else {
+            bq = own;
+          }
+        } else {
+          const int comp = hi ? 1 - part : part;
+          bq = sQ[kr * QLD + 2 * j + comp];
+          if (hi) bq = part ? bq : -bq;
+        }
+        // A: [Re T_V | Im T_V] row a = vt * 16 + col, column k (rows beyond
+        // n_v read row 0 and are zeroed)
+        const int tcol = 16 * (kr >> 3) + 8 * (hi ? 1 : 0) + (kr & 7);
+#pragma unroll
+        for (int vt = 0; vt < VT; ++vt) {
+          R av;
+          if constexpr (TL) {
+            av = sT[max(vrow[vt], 0) * QLD + tcol];
+            av = vrow[vt] >= 0 ? av : R(0);
+          } else {
+            av = sTV[k * nv16 + vt * 16 + col];
+          }
+          lam[vt] = MF::run(av, bq, lam[vt]);
+        }
+      }
+    };
+    if constexpr (sizeof(R) == 8) lam_phase();
     // ---- Q (rows >= nv16 of LT) and its window columns, transposed, to LDS
 #pragma unroll
     for (int rt = VT; rt < RT; ++rt)
@@ -479,35 +528,7 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
         xi = fma(a, part ? br : bi, xi);
       }
     double vr = part ? 0.0 : vdg, vi = part ? vdg : 0.0;
-    // ---- Lam = T_V Q - LT_V: K = 2 Np over [Re T_V | Im T_V]
-    acc_t lam[VT];
-#pragma unroll
-    for (int vt = 0; vt < VT; ++vt)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) lam[vt][r] = -acc[vt][r];
-#pragma unroll
-    for (int kk = 0; kk < 2 * Np / 4; ++kk) {
-      const int k = 4 * kk + q;
-      const bool hi = kk >= Np / 4;  // imaginary rows of the block form of Q
-      const int kr = hi ? k - Np : k;
-      const int comp = hi ? 1 - part : part;
-      R bq = sQ[kr * QLD + 2 * j + comp];
-      if (hi) bq = part ? bq : -bq;
-      // A: [Re T_V | Im T_V] row a = vt * 16 + col, column k (rows beyond
-      // n_v read row 0 and are zeroed)
-      const int tcol = 16 * (kr >> 3) + 8 * (hi ? 1 : 0) + (kr & 7);
-#pragma unroll
-      for (int vt = 0; vt < VT; ++vt) {
-        R av;
-        if constexpr (TL) {
-          av = sT[max(vrow[vt], 0) * QLD + tcol];
-          av = vrow[vt] >= 0 ? av : R(0);
-        } else {
-          av = sTV[k * nv16 + vt * 16 + col];
-        }
-        lam[vt] = MF::run(av, bq, lam[vt]);
-      }
-    }
+    if constexpr (sizeof(R) != 8) lam_phase();
     // ---- D = C Q_W^T: K = 2 no16 over [Re C | Im C]; the B operand is
     // Q[j][slot(i)] (k = i: real rows, k = no16 + i: imaginary rows)
     acc_t dd[VT];

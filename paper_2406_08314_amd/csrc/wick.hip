@@ -1545,9 +1545,6 @@ __global__ __launch_bounds__((MAXK <= 4 ? 1024 : 512)) void k_energy_second(
     const int* __restrict__ wmask, const int* __restrict__ wlist, const int* __restrict__ wcount,
     int WT) {
   constexpr int NIDX = 2 * MAXK > 2 * ER_PPL ? 2 * MAXK : 2 * ER_PPL;
-  // whole strings of order 4 keep 36 complex coefficients per lane: single
-  // precision only (in FP64 they would spill)
-  constexpr bool WHOLE4 = sizeof(CT) == sizeof(cf);
   constexpr int NMM = MAXK * (MAXK - 1) / 2;
   extern __shared__ __align__(16) unsigned char sm_raw[];
   CT* sm = reinterpret_cast<CT*>(sm_raw);
@@ -1790,8 +1787,6 @@ __global__ __launch_bounds__((MAXK <= 4 ? 1024 : 512)) void k_energy_second(
   };
   if (role == (ER_WHOLE | 3)) {
     whole_rows(std::integral_constant<int, 3>{});
-  } else if (WHOLE4 && role == (ER_WHOLE | 4)) {
-    whole_rows(std::integral_constant<int, (WHOLE4 ? 4 : 3)>{});
   } else if (role == ER_PAIRS) {
     run_stages([&](int oa, int ob, int Gs) {
       // each pair's operands for the next vector are loaded into its own
