@@ -1726,6 +1726,20 @@ void set_trial_rows(msd_system* sys, const double* ci, const int32_t* occ_a,
     rows_all.insert(rows_all.end(), rows.begin(), rows.end());
     D.ref = T.upload(S.ref, st);
     D.vir = T.upload(S.vir_act, st);
+    {
+      // orbitals outside the reference, and each window virtual's place among them
+      std::vector<char> in_ref(M, 0);
+      for (int r : S.ref) in_ref[r] = 1;
+      std::vector<int> nref, pos(M, -1), vpos;
+      for (int p = 0; p < M; ++p)
+        if (!in_ref[p]) {
+          pos[p] = (int)nref.size();
+          nref.push_back(p);
+        }
+      for (int v : S.vir_act) vpos.push_back(pos[v]);
+      D.nref = T.upload(nref, st);
+      D.vpos = T.upload(vpos, st);
+    }
     D.oslot = T.upload(S.occ_slot, st);
     D.rows = T.upload(rows, st);
     D.k = T.upload(S.k, st);

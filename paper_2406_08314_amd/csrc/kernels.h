@@ -64,6 +64,8 @@ struct DevSpin {
   int n_minor = 0;
   const int* ref = nullptr;      // [N]
   const int* vir = nullptr;      // [nv]
+  const int* nref = nullptr;     // [M - N] orbitals outside the reference, ascending
+  const int* vpos = nullptr;     // [nv] position of each window virtual in nref
   const int* oslot = nullptr;    // [no]
   const int* rows = nullptr;     // [P]
   const int* k = nullptr;        // [U]

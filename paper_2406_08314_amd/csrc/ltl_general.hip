@@ -163,17 +163,25 @@ __device__ __forceinline__ R gl_other_part(R v) {
   return gl_dpp<0x128>(v);
 }
 
+// The orbital (K) axis of LT = L^g T is split at the reference: T[R, :] is
+// the identity, so LT = L^g[:, nR] T[nR, :] + L^g[:, R] (nR: the M - N
+// orbitals outside the reference).  Only the nR rows of T enter the
+// matrix-core products (in slabs of 16, zero padded: gl_mn of them); the
+// reference columns of L^g come first as Np / 16 slabs whose entries start
+// the real part of LT.
+__host__ __device__ inline int gl_mn(int M, int N) { return (M - N + GL_KS - 1) / GL_KS * GL_KS; }
+
 struct GlShape {
-  int nv16, Np, P16, no16, Mpad;
+  int nv16, Np, P16, no16, Mn;  // Mn: rows of T kept (outside the reference, padded)
 };
 
-__host__ __device__ inline GlShape gl_shape(int no, int M, int NCT, int VT) {
+__host__ __device__ inline GlShape gl_shape(int no, int M, int N, int NCT, int VT) {
   GlShape s;
   s.nv16 = VT * 16;
   s.Np = 8 * NCT;
   s.P16 = s.nv16 + s.Np;
   s.no16 = no <= 16 ? 16 : 32;
-  s.Mpad = (M + GL_KS - 1) / GL_KS * GL_KS;
+  s.Mn = gl_mn(M, N);
   return s;
 }
 
@@ -193,13 +201,13 @@ __host__ __device__ constexpr int gl_slab_stride(int P16, int rsize, int NCT) {
 // complex, rows padded to 2 Np + 1 reals so that a wave's reads down a column
 // of Q hit distinct banks), [Re C | Im C] k-major (2 no16 x nv16) and
 // [Re T_V | Im T_V] k-major (2 Np x nv16).  With TL (the walker's T held in
-// LDS, [Mpad][2 Np + 1], instead of in registers): three slab buffers and no
+// LDS, [Mn][2 Np + 1], instead of in registers): three slab buffers and no
 // separate T_V block (its rows are read from T).
 __host__ __device__ constexpr int gl_nb(bool TL) { return TL ? 3 : GL_NB; }
 __host__ __device__ inline int gl_lds_reals(const GlShape& s, int rsize, int NCT, bool TL) {
   const int common = gl_nb(TL) * gl_slab_stride(s.P16, rsize, NCT) + s.Np * (2 * s.Np + 1) +
                      2 * s.no16 * s.nv16;
-  if (TL) return common + s.Mpad * (2 * s.Np + 1);
+  if (TL) return common + s.Mn * (2 * s.Np + 1);
   return common + 2 * s.Np * s.nv16;
 }
 
@@ -251,8 +259,11 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
   const int w = w0 + wl;
   const DevSpin& D = s2 ? sb : sa;
   const int N = D.N, nv = D.nv, no = D.no, X = nv * no;
-  const GlShape sh = gl_shape(no, M, NCT, VT);
-  const int no16 = sh.no16, n_sl = sh.Mpad / GL_KS;
+  const GlShape sh = gl_shape(no, M, N, NCT, VT);
+  // per vector: n_rs slabs of the reference columns (added), then n_nr slabs
+  // of L^g[:, nR] (products with T); srows rows of S per vector
+  const int no16 = sh.no16, n_nr = sh.Mn / GL_KS, n_rs = Np / GL_KS, n_sl = n_nr + n_rs;
+  const int srows = sh.Mn + Np;
   const C* __restrict__ T = s2 ? Tb : Ta;
   const R* __restrict__ S = s2 ? Sb : Sa;
   C* __restrict__ Lam = s2 ? Lam_b : Lam_a;
@@ -267,7 +278,7 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
   R* sQ = sS + NB * SSTRIDE;                // [Np][QLD]: (re, im) of column j at 2j
   R* sCA = sQ + Np * QLD;                   // [2 no16][nv16]
   R* sTV = sCA + 2 * no16 * nv16;           // !TL: [2 Np][nv16]
-  R* sT = sCA + 2 * no16 * nv16;            // TL: [Mpad][QLD], column c of tile t at 16 t + c
+  R* sT = sCA + 2 * no16 * nv16;            // TL: [Mn][QLD], column c of tile t at 16 t + c
 
   // window index of this lane's column (slot j), -1 outside the window
   int wi = -1;
@@ -295,13 +306,13 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
   R bt[TL ? 1 : 4 * KSL];
   int vrow[VT];  // TL: orbital of this lane's rows of T_V (-1 beyond n_v)
   if constexpr (TL) {
-    // T[k][w][j] as 2 Np real columns per orbital k, in the tile layout
-    for (int e = threadIdx.x; e < sh.Mpad * 2 * Np; e += nthr) {
+    // T[nR[k]][w][j] as 2 Np real columns per kept orbital k, in the tile layout
+    for (int e = threadIdx.x; e < sh.Mn * 2 * Np; e += nthr) {
       const int k = e / (2 * Np), c = e % (2 * Np);
       const int jj = 8 * (c >> 4) + (c & 7), pp = (c >> 3) & 1;
       R v = R(0);
-      if (k < M && jj < N) {
-        const C t = T[((size_t)k * NW + w) * N + jj];
+      if (k < M - N && jj < N) {
+        const C t = T[((size_t)D.nref[k] * NW + w) * N + jj];
         v = pp ? t.im : t.re;
       }
       sT[k * QLD + c] = v;
@@ -309,7 +320,7 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
 #pragma unroll
     for (int vt = 0; vt < VT; ++vt) {
       const int a = vt * 16 + col;
-      vrow[vt] = a < nv ? D.vir[a] : -1;
+      vrow[vt] = a < nv ? D.vpos[a] : -1;  // position of the virtual among the kept rows
     }
   } else {
     // [Re T_V | Im T_V]
@@ -324,10 +335,10 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
     }
 #pragma unroll
     for (int s = 0; s < 4 * KSL; ++s) {
-      const int k = 4 * s + q;
+      const int k = 4 * s + q;  // kept row
       R v = R(0);
-      if (k < M && j < N) {
-        const C t = T[((size_t)k * NW + w) * N + j];
+      if (k < M - N && j < N) {
+        const C t = T[((size_t)D.nref[k] * NW + w) * N + j];
         v = part ? t.im : t.re;
       }
       bt[s] = v;
@@ -344,7 +355,7 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
   auto fetch_next = [&]() {
     if (ft < n_t) {  // uniform: no loads issued past the end (the wait below allows for it)
       constexpr int per16 = 16 / sizeof(R);
-      const R* src = S + ((size_t)fg * sh.Mpad + (size_t)fsl * GL_KS) * P16;
+      const R* src = S + ((size_t)fg * srows + (size_t)fsl * GL_KS) * P16;
       R* dst = sS + fbuf * SSTRIDE;
       constexpr int n16 = GL_KS * P16 / per16;
 #pragma unroll
@@ -387,6 +398,26 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
     acc_t acc[RT];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) acc[rt] = acc_t{0, 0, 0, 0};
+    // the reference columns first (the order of the orbital sum the products
+    // then continue): slab u holds L^g[p, r_j] for j = 16u .. 16u + 15, the
+    // start of the real part of LT[p][j] (the wave's columns j lie in slab
+    // wv / 2)
+    for (int u = 0; u < n_rs; ++u) {
+      if (ft <= n_t) gl_bar_vm_lds<(NB - 2) * SLOADS>();  // ft = t + NB - 1 here
+      else gl_bar_vm_lds<0>();
+      fetch_next();
+      const R* sb0 = sS + cb * SSTRIDE;
+      if (u == (j >> 4)) {  // wave-uniform
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const R v = sb0[(j & 15) * P16 + rt * 16 + MF::row(lane, r)];
+            acc[rt][r] += part ? R(0) : v;
+          }
+      }
+      cb = cb + 1 == NB ? 0 : cb + 1;
+    }
     if constexpr (TL) {
       // B from the LDS copy of T: a loop over the slabs, two at a time, the
       // operands of the next slab read from LDS while the current slab's
@@ -426,8 +457,8 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
         // during the second half)
         R a0[4][RT], b0[4], a1[4][RT], b1[4];
         load(a0, b0, 0);
-        for (int sl = 0; sl < n_sl; sl += 2) {
-          const bool more = sl + 1 < n_sl;
+        for (int sl = 0; sl < n_nr; sl += 2) {
+          const bool more = sl + 1 < n_nr;
           mma_h(a0, b0, 0);
           __builtin_amdgcn_sched_barrier(0);
           if (more) load(a1, b1, sl + 1);
@@ -436,13 +467,13 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
           if (!more) break;
           mma_h(a1, b1, 0);
           __builtin_amdgcn_sched_barrier(0);
-          if (sl + 2 < n_sl) load(a0, b0, sl + 2);
+          if (sl + 2 < n_nr) load(a0, b0, sl + 2);
           __builtin_amdgcn_sched_barrier(0);
           mma_h(a1, b1, 1);
         }
       } else {
         // five or more row tiles: one operand set (a second one would spill)
-        for (int sl = 0; sl < n_sl; ++sl) {
+        for (int sl = 0; sl < n_nr; ++sl) {
           R a0[4][RT], b0[4];
           load(a0, b0, sl);
           mma(a0, b0);
@@ -452,7 +483,7 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
       // B from registers (compile-time indices): unrolled over KSL slabs
 #pragma unroll
       for (int sl = 0; sl < KSL; ++sl)
-        if (sl < n_sl) slab(acc, sl, [&](int l, int s) { return bt[4 * l + s]; });
+        if (sl < n_nr) slab(acc, sl, [&](int l, int s) { return bt[4 * l + s]; });
     }
     // ---- Lam = T_V Q - LT_V: K = 2 Np over [Re T_V | Im T_V].  In FP64 the
     // B operand Q[k][j] is this lane's own accumulator (register r of lane
@@ -460,6 +491,7 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
     // 4 of tile kk / 4), the other part of the complex entry one DPP row
     // rotation away, so the products need no LDS and run before the barrier
     // that publishes Q; in FP32 (row 4q + r) Q is read back from LDS.
+    constexpr bool EARLY_LAM = sizeof(R) == 8;
     acc_t lam[VT];
     auto lam_phase = [&]() {
 #pragma unroll
@@ -472,7 +504,7 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
         const bool hi = kk >= Np / 4;  // imaginary rows of the block form of Q
         const int kr = hi ? k - Np : k;
         R bq;
-        if constexpr (sizeof(R) == 8) {
+        if constexpr (EARLY_LAM) {
           const int kq = hi ? kk - Np / 4 : kk;
           const R own = acc[VT + kq / 4][kq % 4];
           if (hi) {
@@ -502,7 +534,7 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
         }
       }
     };
-    if constexpr (sizeof(R) == 8) lam_phase();
+    if constexpr (EARLY_LAM) lam_phase();
     // ---- Q (rows >= nv16 of LT) and its window columns, transposed, to LDS
 #pragma unroll
     for (int rt = VT; rt < RT; ++rt)
@@ -528,7 +560,7 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
         xi = fma(a, part ? br : bi, xi);
       }
     double vr = part ? 0.0 : vdg, vi = part ? vdg : 0.0;
-    if constexpr (sizeof(R) != 8) lam_phase();
+    if constexpr (!EARLY_LAM) lam_phase();
     // ---- D = C Q_W^T: K = 2 no16 over [Re C | Im C]; the B operand is
     // Q[j][slot(i)] (k = i: real rows, k = no16 + i: imaginary rows)
     acc_t dd[VT];
@@ -598,23 +630,30 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
   }
 }
 
-// S[g][k][p] = L^g[row(p), k]: p < nv the window virtual orbitals, nv16 <= p <
-// nv16 + N the reference orbitals, zero elsewhere and for k >= M.
+// S[g][k][p] = L^g[row(p), orb(k)]: p < nv the window virtual orbitals, nv16
+// <= p < nv16 + N the reference orbitals, zero elsewhere; k = j < Np the
+// reference orbital r_j (zero for j >= N), then k = Np + i the orbitals
+// outside the reference (nref[i], zero beyond M - N).  Np + Mn rows per vector.
 template <class R>
-__global__ void k_gather_general(const double* __restrict__ L, int NG, int M, int Mpad,
-                                 const int* __restrict__ ref, int N, const int* __restrict__ vir,
-                                 int nv, int nv16, int P16, R* __restrict__ S) {
-  const int64_t n = (int64_t)NG * Mpad * P16;
+__global__ void k_gather_general(const double* __restrict__ L, int NG, int M, int Mn, int srows,
+                                 const int* __restrict__ ref, int N, const int* __restrict__ nref,
+                                 const int* __restrict__ vir, int nv, int nv16, int P16,
+                                 R* __restrict__ S) {
+  const int64_t n = (int64_t)NG * srows * P16;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int p = (int)(e % P16);
-    const int k = (int)((e / P16) % Mpad);
-    const int64_t g = e / ((int64_t)P16 * Mpad);
-    double v = 0.0;
+    const int k = (int)((e / P16) % srows);
+    const int64_t g = e / ((int64_t)P16 * srows);
+    const int Np = srows - Mn;
+    int orb = -1;
+    if (k < Np) orb = k < N ? ref[k] : -1;
+    else if (k - Np < M - N) orb = nref[k - Np];
     int row = -1;
     if (p < nv) row = vir[p];
     else if (p >= nv16 && p < nv16 + N) row = ref[p - nv16];
-    if (k < M && row >= 0) v = L[((size_t)g * M + row) * M + k];
+    double v = 0.0;
+    if (orb >= 0 && row >= 0) v = L[((size_t)g * M + row) * M + orb];
     S[e] = R(v);
   }
 }
@@ -628,8 +667,10 @@ int ltl_general_vt(const DevSpin& sa, const DevSpin& sb) {
   return std::max(sa.nv, sb.nv) <= 16 ? 1 : 2;
 }
 
-int ltl_general_ksl(int M) {
-  const int n = (M + GL_KS - 1) / GL_KS;
+// slabs of 16 kept rows of T (outside the reference) for the larger spin,
+// rounded up to an instantiated count
+int ltl_general_ksl(int M, int Nmin) {
+  const int n = gl_mn(M, Nmin) / GL_KS;
   for (int k : {4, 8, 13, 20})
     if (n <= k) return k;
   return 0;
@@ -640,40 +681,44 @@ int ltl_general_ksl(int M) {
 // tiles, i.e. N <= 32 per spin)
 static bool gl_tl(const DevSpin& sa, const DevSpin& sb, int M, size_t rsize) {
   const int nct = ltl_general_nct(sa, sb);
-  const GlShape s = gl_shape(std::max(sa.no, sb.no), M, nct, ltl_general_vt(sa, sb));
+  const GlShape s = gl_shape(std::max(sa.no, sb.no), M, std::min(sa.N, sb.N), nct,
+                             ltl_general_vt(sa, sb));
   return (size_t)gl_lds_reals(s, (int)rsize, nct, true) * rsize <= 160 * 1024;
 }
 
 bool ltl_general_fits(const DevSpin& sa, const DevSpin& sb, int M, bool fp32) {
-  const int nct = ltl_general_nct(sa, sb), ksl = ltl_general_ksl(M);
+  const int nct = ltl_general_nct(sa, sb), ksl = ltl_general_ksl(M, std::min(sa.N, sb.N));
   if (nct < 2 || nct > 6 || ksl == 0) return false;
   for (const DevSpin* d : {&sa, &sb}) {
     if (d->N == 0 || d->nv == 0 || d->nv > GL_VTMAX * 16 || d->no > GL_OMAX) return false;
   }
   if (gl_tl(sa, sb, M, fp32 ? 4 : 8)) return true;
   if (fp32 || nct > 4) return false;
-  const GlShape s = gl_shape(std::max(sa.no, sb.no), M, nct, ltl_general_vt(sa, sb));
+  const GlShape s = gl_shape(std::max(sa.no, sb.no), M, std::min(sa.N, sb.N), nct,
+                             ltl_general_vt(sa, sb));
   return (size_t)gl_lds_reals(s, 8, nct, false) * 8 <= 160 * 1024;
 }
 
+// elements of one spin's S array (sized for the spin with more kept rows)
 size_t ltl_general_s_elems(const DevSpin& sa, const DevSpin& sb, int M, int NG) {
-  const GlShape s = gl_shape(std::max(sa.no, sb.no), M, ltl_general_nct(sa, sb),
-                             ltl_general_vt(sa, sb));
-  return (size_t)NG * s.Mpad * s.P16;
+  const GlShape s = gl_shape(std::max(sa.no, sb.no), M, std::min(sa.N, sb.N),
+                             ltl_general_nct(sa, sb), ltl_general_vt(sa, sb));
+  return (size_t)NG * (s.Mn + s.Np) * s.P16;
 }
 
 void launch_gather_general(const double* L, int NG, int M, const DevSpin& D, const DevSpin& sa,
                            const DevSpin& sb, double* S64, float* S32, hipStream_t st) {
-  const GlShape s = gl_shape(D.no, M, ltl_general_nct(sa, sb), ltl_general_vt(sa, sb));
-  const int64_t n = (int64_t)NG * s.Mpad * s.P16;
+  const GlShape s = gl_shape(D.no, M, D.N, ltl_general_nct(sa, sb), ltl_general_vt(sa, sb));
+  const int srows = s.Mn + s.Np;
+  const int64_t n = (int64_t)NG * srows * s.P16;
   if (n == 0) return;
   const int blocks = (int)std::min<int64_t>((n + 255) / 256, 65536);
   if (S64)
-    hipLaunchKernelGGL(k_gather_general<double>, dim3(blocks), dim3(256), 0, st, L, NG, M, s.Mpad,
-                       D.ref, D.N, D.vir, D.nv, s.nv16, s.P16, S64);
+    hipLaunchKernelGGL(k_gather_general<double>, dim3(blocks), dim3(256), 0, st, L, NG, M, s.Mn,
+                       srows, D.ref, D.N, D.nref, D.vir, D.nv, s.nv16, s.P16, S64);
   if (S32)
-    hipLaunchKernelGGL(k_gather_general<float>, dim3(blocks), dim3(256), 0, st, L, NG, M, s.Mpad,
-                       D.ref, D.N, D.vir, D.nv, s.nv16, s.P16, S32);
+    hipLaunchKernelGGL(k_gather_general<float>, dim3(blocks), dim3(256), 0, st, L, NG, M, s.Mn,
+                       srows, D.ref, D.N, D.nref, D.vir, D.nv, s.nv16, s.P16, S32);
 }
 
 namespace {
@@ -683,7 +728,7 @@ void gl_launch(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int
                const typename GMfma<R>::cx_t* Tb, typename GMfma<R>::cx_t* Lam_a,
                typename GMfma<R>::cx_t* Lam_b, const cd* Ca, const cd* Cb, cd* v0, cd* ex0,
                cd* lamc, cd* czw, const int* wmask, const WalkerList& wls, hipStream_t st) {
-  const GlShape s = gl_shape(std::max(sa.no, sb.no), M, NCT, VT);
+  const GlShape s = gl_shape(std::max(sa.no, sb.no), M, std::min(sa.N, sb.N), NCT, VT);
   const size_t lds = (size_t)gl_lds_reals(s, sizeof(R), NCT, TL) * sizeof(R);
   const void* fn = (const void*)k_ltl_general<R, NCT, KSL, VT, TL>;
   static bool attr = false;
@@ -711,7 +756,8 @@ void gl_dispatch(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, i
                  const typename GMfma<R>::cx_t* Tb, typename GMfma<R>::cx_t* Lam_a,
                  typename GMfma<R>::cx_t* Lam_b, const cd* Ca, const cd* Cb, cd* v0, cd* ex0,
                  cd* lamc, cd* czw, const int* wmask, const WalkerList& wls, hipStream_t st) {
-  const int nct = ltl_general_nct(sa, sb), ksl = ltl_general_ksl(M), vt = ltl_general_vt(sa, sb);
+  const int nct = ltl_general_nct(sa, sb), ksl = ltl_general_ksl(M, std::min(sa.N, sb.N)),
+            vt = ltl_general_vt(sa, sb);
   const int n_chunks = (NG + g_chunk - 1) / g_chunk;
   const bool tl = gl_tl(sa, sb, M, sizeof(R));
 #define GL_CASE(n, k, v, t)                                                                     if (nct == n && ksl == k && vt == v && tl == t)                                                 return gl_launch<R, n, k, v, t>(sa, sb, NW, w0, WT, NG, g_chunk, n_chunks, M, Sa, Sb, Ta,                                     Tb, Lam_a, Lam_b, Ca, Cb, v0, ex0, lamc, czw, wmask, wls, st);
