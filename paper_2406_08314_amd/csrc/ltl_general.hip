@@ -86,19 +86,9 @@ __device__ __forceinline__ void gl_bar_all() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 // at most N of this wave's vector-memory operations outstanding (the older
-// ones, including direct-to-LDS loads, done), then the workgroup barrier.
-// gfx9 s_waitcnt: vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8.
-template <int N>
-__device__ __forceinline__ void gl_bar_vm() {
-  static_assert(N >= 0 && N < 64, "vmcnt range");
-  constexpr int imm = (N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8);
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  __builtin_amdgcn_s_waitcnt(imm);
-  __builtin_amdgcn_s_barrier();
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-}
-// at most N of this wave's vector-memory operations outstanding and all its
-// LDS operations done, then the workgroup barrier
+// ones, including direct-to-LDS loads, done) and all its LDS operations done,
+// then the workgroup barrier.  gfx9 s_waitcnt: vmcnt in bits 3:0 and 15:14,
+// expcnt 6:4, lgkmcnt 11:8.
 template <int N>
 __device__ __forceinline__ void gl_bar_vm_lds() {
   static_assert(N >= 0 && N < 64, "vmcnt range");
@@ -232,7 +222,7 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
   extern __shared__ __align__(16) unsigned char gl_raw[];
   R* lds = reinterpret_cast<R*>(gl_raw);
 
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int col = lane & 15, q = lane >> 4;
   const int part = col >> 3;             // 0: real part, 1: imaginary part
   const int j = 8 * wv + (col & 7);      // complex column of this lane
@@ -256,6 +246,8 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
     s2 = b / (WT * n_chunks);
     if (wmask && !wmask[w0 + wl]) return;  // walker not selected for this pass
   }
+  const int g0 = chunk * g_chunk, g1 = min(NG, g0 + g_chunk);
+  if (g1 <= g0) continue;  // no vectors in this chunk (uniform)
   const int w = w0 + wl;
   const DevSpin& D = s2 ? sb : sa;
   const int N = D.N, nv = D.nv, no = D.no, X = nv * no;
@@ -345,39 +337,40 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
     }
   }
 
-  const int g0 = chunk * g_chunk, g1 = min(NG, g0 + g_chunk);
   // slab ring over the flattened (vector, slab) sequence: slab t = (g0 + t /
-  // n_sl, t % n_sl) sits in buffer t % NB.  Slabs are fetched in order; the
-  // fetch cursor (ft, fg, fsl, fbuf) and the consumer buffer cb advance by
-  // one slab at a time.
+  // n_sl, t % n_sl) sits in buffer t % NB.  The slabs of consecutive vectors
+  // are contiguous in S, so the fetch pointer advances by one slab per fetch.
+  // Every step issues the same loads (past the last slab they re-read it into
+  // a buffer nobody reads), so the wait before slab t is always the same
+  // count: the loads of slabs t+1 .. t+NB-2 may be outstanding.
   const int n_t = (g1 - g0) * n_sl;
-  int ft = 0, fg = g0, fsl = 0, fbuf = 0, cb = 0;
+  constexpr int SLAB = GL_KS * P16;  // reals per slab in S
+  const R* fsrc = S + (size_t)g0 * srows * P16;
+  const R* const flast = fsrc + (size_t)(n_t - 1) * SLAB;
+  int ft = 0, fbuf = 0, cb = 0;
   auto fetch_next = [&]() {
-    if (ft < n_t) {  // uniform: no loads issued past the end (the wait below allows for it)
-      constexpr int per16 = 16 / sizeof(R);
-      const R* src = S + ((size_t)fg * srows + (size_t)fsl * GL_KS) * P16;
-      R* dst = sS + fbuf * SSTRIDE;
-      constexpr int n16 = GL_KS * P16 / per16;
+    constexpr int per16 = 16 / sizeof(R);
+    const R* src = ft < n_t ? fsrc : flast;  // uniform
+    R* dst = sS + fbuf * SSTRIDE;
+    constexpr int n16 = SLAB / per16;
 #pragma unroll
-      for (int u = 0; u < SLOADS; ++u) {
-        const int c = u * NCT + wv, e = min(c * 64 + lane, n16 - 1);  // pad lanes re-read
-        gl_dma16(src + (size_t)e * per16, dst + c * 64 * per16);
-      }
-      if (++fsl == n_sl) {
-        fsl = 0;
-        ++fg;
-      }
-      fbuf = fbuf + 1 == NB ? 0 : fbuf + 1;
+    for (int u = 0; u < SLOADS; ++u) {
+      const int c = u * NCT + wv, e = min(c * 64 + lane, n16 - 1);  // pad lanes re-read
+      gl_dma16(src + (size_t)e * per16, dst + c * 64 * per16);
     }
+    fsrc += SLAB;
     ++ft;
+    fbuf = fbuf + 1 == NB ? 0 : fbuf + 1;
   };
-  // one slab of LT: wait until slab t has landed (at most the loads of slabs
-  // t+1 .. t+NB-2 outstanding; near the end fewer were issued: wait for all),
-  // refill the buffer every wave finished with, then 4 k-steps of RT tiles
-  auto slab = [&](acc_t* acc, int sl, auto&& bval) {
-    if (ft <= n_t) gl_bar_vm<(NB - 2) * SLOADS>();  // ft = t + NB - 1 here
-    else gl_bar_vm<0>();
+  // before the reads of slab t: slab t has landed and every wave is done
+  // with slab t - 1, whose buffer then takes slab t + NB - 1
+  auto slab_sync = [&]() {
+    gl_bar_vm_lds<(NB - 2) * SLOADS>();
     fetch_next();
+  };
+  // one slab of LT: 4 k-steps of RT tiles
+  auto slab = [&](acc_t* acc, int sl, auto&& bval) {
+    slab_sync();
     const R* sb0 = sS + cb * SSTRIDE;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
@@ -403,9 +396,7 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
     // start of the real part of LT[p][j] (the wave's columns j lie in slab
     // wv / 2)
     for (int u = 0; u < n_rs; ++u) {
-      if (ft <= n_t) gl_bar_vm_lds<(NB - 2) * SLOADS>();  // ft = t + NB - 1 here
-      else gl_bar_vm_lds<0>();
-      fetch_next();
+      slab_sync();
       const R* sb0 = sS + cb * SSTRIDE;
       if (u == (j >> 4)) {  // wave-uniform
 #pragma unroll
@@ -421,15 +412,15 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
     if constexpr (TL) {
       // B from the LDS copy of T: a loop over the slabs, two at a time, the
       // operands of the next slab read from LDS while the current slab's
-      // products run (the accumulators stay in place throughout).  The
-      // barrier before a slab's reads also waits for this wave's earlier LDS
-      // reads, so the buffer refilled there (the one read two slabs back) is
-      // free in every wave.
+      // products run (the accumulators stay in place throughout).  A slab's
+      // first k-step is issued before the synchronisation for the next slab;
+      // the refill and the next slab's reads are then interleaved with the
+      // other three k-steps, so the matrix cores have work queued while the
+      // wave issues them.  The synchronisation also waits for this wave's
+      // earlier LDS reads, so the buffer refilled there (the slab read before
+      // the current one) is free in every wave.
       const R* tcol = sT + q * QLD + 16 * wv + col;
-      auto load = [&](R (&a)[4][RT], R (&bv)[4], int sl) {
-        if (ft <= n_t) gl_bar_vm_lds<(NB - 2) * SLOADS>();  // ft = t + NB - 1 here
-        else gl_bar_vm_lds<0>();
-        fetch_next();
+      auto read = [&](R (&a)[4][RT], R (&bv)[4], int sl) {
         const R* sb0 = sS + cb * SSTRIDE;
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -439,44 +430,68 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
         }
         cb = cb + 1 == NB ? 0 : cb + 1;
       };
-      // k-steps 2h, 2h + 1 of a slab
-      auto mma_h = [&](const R (&a)[4][RT], const R (&bv)[4], int h) {
+      auto kstep = [&](const R (&a)[4][RT], const R (&bv)[4], int s) {
 #pragma unroll
-        for (int s = 2 * h; s < 2 * h + 2; ++s)
-#pragma unroll
-          for (int rt = 0; rt < RT; ++rt) acc[rt] = MF::run(a[s][rt], bv[s], acc[rt]);
+        for (int rt = 0; rt < RT; ++rt) acc[rt] = MF::run(a[s][rt], bv[s], acc[rt]);
       };
-      auto mma = [&](const R (&a)[4][RT], const R (&bv)[4]) {
-        mma_h(a, bv, 0);
-        mma_h(a, bv, 1);
+      // the current slab's k-steps 1..3 (3 RT products) with the next slab's
+      // refill and reads (4 RT + 4 values, mostly merged pairwise by the
+      // compiler) placed between them
+      auto rest_and_next = [&](const R (&a)[4][RT], const R (&bv)[4], R (&na)[4][RT],
+                               R (&nb)[4], int nsl) {
+        slab_sync();
+        __builtin_amdgcn_sched_barrier(0);
+        read(na, nb, nsl);
+        kstep(a, bv, 1);
+        kstep(a, bv, 2);
+        kstep(a, bv, 3);
+        // two reads after each of the first products: every read is issued
+        // well before the next slab's first product (an LDS read after a
+        // direct-to-LDS load is waited for in full before its first use)
+#pragma unroll
+        for (int i = 0; i < 3 * RT / 2; ++i) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one product
+          __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);  // two LDS reads
+        }
+        __builtin_amdgcn_sched_group_barrier(0x008, 3 * RT - 3 * RT / 2, 0);
+        __builtin_amdgcn_sched_barrier(0);
+      };
+      auto rest = [&](const R (&a)[4][RT], const R (&bv)[4]) {
+        kstep(a, bv, 1);
+        kstep(a, bv, 2);
+        kstep(a, bv, 3);
       };
       if constexpr (RT <= 4) {
-        // half of the current slab's products are issued before the wait for
-        // the next slab, the other half after its reads (kept in this order:
-        // the matrix cores stay busy through the wait and the reads land
-        // during the second half)
         R a0[4][RT], b0[4], a1[4][RT], b1[4];
-        load(a0, b0, 0);
-        for (int sl = 0; sl < n_nr; sl += 2) {
-          const bool more = sl + 1 < n_nr;
-          mma_h(a0, b0, 0);
+        slab_sync();
+        read(a0, b0, 0);
+        int sl = 0;
+        for (; sl + 2 < n_nr; sl += 2) {  // two slabs, each followed by another
+          kstep(a0, b0, 0);
           __builtin_amdgcn_sched_barrier(0);
-          if (more) load(a1, b1, sl + 1);
+          rest_and_next(a0, b0, a1, b1, sl + 1);
+          kstep(a1, b1, 0);
           __builtin_amdgcn_sched_barrier(0);
-          mma_h(a0, b0, 1);
-          if (!more) break;
-          mma_h(a1, b1, 0);
-          __builtin_amdgcn_sched_barrier(0);
-          if (sl + 2 < n_nr) load(a0, b0, sl + 2);
-          __builtin_amdgcn_sched_barrier(0);
-          mma_h(a1, b1, 1);
+          rest_and_next(a1, b1, a0, b0, sl + 2);
+        }
+        // the last one or two slabs
+        kstep(a0, b0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+        if (sl + 1 < n_nr) {
+          rest_and_next(a0, b0, a1, b1, sl + 1);
+          kstep(a1, b1, 0);
+          rest(a1, b1);
+        } else {
+          rest(a0, b0);
         }
       } else {
         // five or more row tiles: one operand set (a second one would spill)
         for (int sl = 0; sl < n_nr; ++sl) {
           R a0[4][RT], b0[4];
-          load(a0, b0, sl);
-          mma(a0, b0);
+          slab_sync();
+          read(a0, b0, sl);
+          kstep(a0, b0, 0);
+          rest(a0, b0);
         }
       }
     } else {
@@ -626,7 +641,7 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
   dot_re = gl_wsum(dot_re);
   dot_im = gl_wsum(dot_im);
   if (lane == 0) czw[((size_t)s2 * NW + w) * n_chunks * NCT + chunk * NCT + wv] = cd{dot_re, dot_im};
-  __syncthreads();  // the next item rewrites the LDS
+  gl_bar_all();  // the re-reads past the last slab have landed; the next item rewrites the LDS
   }
 }
 
