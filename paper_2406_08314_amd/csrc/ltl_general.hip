@@ -508,18 +508,41 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
     // that publishes Q; in FP32 (row 4q + r) Q is read back from LDS.
     constexpr bool EARLY_LAM = sizeof(R) == 8;
     acc_t lam[VT];
+    // The LDS operands of the Lam and D products are read one group ahead:
+    // a group's reads are issued after the first product of the group before
+    // (once direct-to-LDS loads are in flight, the first use of an LDS read
+    // waits for every LDS read issued before it, so reads issued any earlier
+    // would be waited for with the previous group).
+    constexpr int KK = 2 * Np / 4;  // k-steps of the Lam products
     auto lam_phase = [&]() {
 #pragma unroll
       for (int vt = 0; vt < VT; ++vt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) lam[vt][r] = -acc[vt][r];
-#pragma unroll
-      for (int kk = 0; kk < 2 * Np / 4; ++kk) {
+      R lav[KK][VT], lbq[EARLY_LAM ? 1 : KK];
+      // A: [Re T_V | Im T_V] row a = vt * 16 + col, column k = 4 kk + q
+      // (rows beyond n_v read row 0 and are zeroed); FP32: B = Q[k][j].  The
+      // loaded values are not touched before their products (any arithmetic
+      // on them would wait for the whole group of reads).
+      auto lread = [&](int kk) {
         const int k = 4 * kk + q;
         const bool hi = kk >= Np / 4;  // imaginary rows of the block form of Q
         const int kr = hi ? k - Np : k;
+        const int tcol = 16 * (kr >> 3) + 8 * (hi ? 1 : 0) + (kr & 7);
+#pragma unroll
+        for (int vt = 0; vt < VT; ++vt) {
+          if constexpr (TL) lav[kk][vt] = sT[max(vrow[vt], 0) * QLD + tcol];
+          else lav[kk][vt] = sTV[k * nv16 + vt * 16 + col];
+        }
+        if constexpr (!EARLY_LAM) {
+          const int comp = hi ? 1 - part : part;
+          lbq[kk] = sQ[kr * QLD + 2 * j + comp];
+        }
+      };
+      auto lmma = [&](int kk) {
         R bq;
         if constexpr (EARLY_LAM) {
+          const bool hi = kk >= Np / 4;
           const int kq = hi ? kk - Np / 4 : kk;
           const R own = acc[VT + kq / 4][kq % 4];
           if (hi) {
@@ -529,24 +552,31 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
             bq = own;
           }
         } else {
-          const int comp = hi ? 1 - part : part;
-          bq = sQ[kr * QLD + 2 * j + comp];
-          if (hi) bq = part ? bq : -bq;
+          const bool hi = kk >= Np / 4;
+          bq = hi && !part ? -lbq[kk] : lbq[kk];
         }
-        // A: [Re T_V | Im T_V] row a = vt * 16 + col, column k (rows beyond
-        // n_v read row 0 and are zeroed)
-        const int tcol = 16 * (kr >> 3) + 8 * (hi ? 1 : 0) + (kr & 7);
 #pragma unroll
         for (int vt = 0; vt < VT; ++vt) {
-          R av;
-          if constexpr (TL) {
-            av = sT[max(vrow[vt], 0) * QLD + tcol];
-            av = vrow[vt] >= 0 ? av : R(0);
-          } else {
-            av = sTV[k * nv16 + vt * 16 + col];
-          }
+          const R av = TL && vrow[vt] < 0 ? R(0) : lav[kk][vt];
           lam[vt] = MF::run(av, bq, lam[vt]);
         }
+      };
+      // groups of two k-steps
+      lread(0);
+      lread(1);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int p = 0; p < KK / 2; ++p) {
+        lmma(2 * p);
+        lmma(2 * p + 1);
+        if (p + 1 < KK / 2) {
+          lread(2 * p + 2);
+          lread(2 * p + 3);
+        }
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 2);
+        __builtin_amdgcn_sched_group_barrier(0x100, 2 * (VT + (EARLY_LAM ? 0 : 1)), 2);
+        __builtin_amdgcn_sched_group_barrier(0x008, 2 * VT - 1, 2);
+        __builtin_amdgcn_sched_barrier(0);
       }
     };
     if constexpr (EARLY_LAM) lam_phase();
@@ -583,20 +613,34 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
     for (int vt = 0; vt < VT; ++vt) dd[vt] = acc_t{0, 0, 0, 0};
     auto dphase = [&](auto nc) {
       constexpr int NO16 = decltype(nc)::value;
-#pragma unroll
-      for (int u = 0; u < NO16 / 4; ++u) {
+      constexpr int NU = NO16 / 4;
+      R qv[NU][2], ca[NU][2][VT];
+      auto dread = [&](int u) {
         // rows beyond n_o read slot 0 and are zeroed
         const int o = j * QLD + max(qs[u], 0);
-        R qre = sQ[o], qim = sQ[o + 1];
-        qre = qs[u] >= 0 ? qre : R(0);
-        qim = qs[u] >= 0 ? qim : R(0);
+        qv[u][0] = sQ[o];
+        qv[u][1] = sQ[o + 1];
+#pragma unroll
+        for (int vt = 0; vt < VT; ++vt) {
+          ca[u][0][vt] = sCA[(4 * u + q) * nv16 + vt * 16 + col];
+          ca[u][1][vt] = sCA[(NO16 + 4 * u + q) * nv16 + vt * 16 + col];
+        }
+      };
+      dread(0);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < NU; ++u) {
+        const R qre = qs[u] >= 0 ? qv[u][0] : R(0), qim = qs[u] >= 0 ? qv[u][1] : R(0);
         const R blo = part ? qim : qre, bhi = part ? qre : -qim;
 #pragma unroll
-        for (int vt = 0; vt < VT; ++vt)
-          dd[vt] = MF::run(sCA[(4 * u + q) * nv16 + vt * 16 + col], blo, dd[vt]);
+        for (int vt = 0; vt < VT; ++vt) dd[vt] = MF::run(ca[u][0][vt], blo, dd[vt]);
 #pragma unroll
-        for (int vt = 0; vt < VT; ++vt)
-          dd[vt] = MF::run(sCA[(NO16 + 4 * u + q) * nv16 + vt * 16 + col], bhi, dd[vt]);
+        for (int vt = 0; vt < VT; ++vt) dd[vt] = MF::run(ca[u][1][vt], bhi, dd[vt]);
+        if (u + 1 < NU) dread(u + 1);
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 3);
+        __builtin_amdgcn_sched_group_barrier(0x100, 2 + 2 * VT, 3);
+        __builtin_amdgcn_sched_group_barrier(0x008, 2 * VT - 1, 3);
+        __builtin_amdgcn_sched_barrier(0);
       }
     };
     if (no16 == 16) dphase(std::integral_constant<int, 16>{});
