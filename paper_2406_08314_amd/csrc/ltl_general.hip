@@ -384,7 +384,25 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
     cb = cb + 1 == NB ? 0 : cb + 1;
   };
 
+  // <Lam, D> summed over the chunk: the sign of the real part (- on the
+  // imaginary-part lanes) is applied once at the end
   double dot_re = 0.0, dot_im = 0.0;
+  // lc_g = <C, Lam_W> coefficients of this lane's Lam entries (constant over
+  // the chunk): C at its window entry, signed and zeroed outside the window
+  gl_bar_lds();  // the C block is in LDS
+  R lcr[VT][4], lci[VT][4];
+#pragma unroll
+  for (int vt = 0; vt < VT; ++vt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int a = vt * 16 + MF::row(lane, r);
+      const bool inw = wi >= 0 && a < nv;
+      const int wic = max(wi, 0);
+      const R cr = inw ? sCA[wic * nv16 + a] : R(0);
+      const R ci = inw ? sCA[(no16 + wic) * nv16 + a] : R(0);
+      lcr[vt][r] = part ? -ci : cr;
+      lci[vt][r] = part ? cr : ci;
+    }
   for (int u = 0; u < NB - 1; ++u) fetch_next();
   for (int g = g0; g < g1; ++g) {
     // ---- LT = S^g T over slabs of 16 orbitals
@@ -647,7 +665,6 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
     else dphase(std::integral_constant<int, 32>{});
     // ---- <Lam, D> (accumulated), lc_g = <C, Lam_W> (branch-free), window store
     double lr = 0.0, li = 0.0;
-    const int wic = max(wi, 0);
 #pragma unroll
     for (int vt = 0; vt < VT; ++vt)
 #pragma unroll
@@ -655,16 +672,12 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
         const double lv = (double)lam[vt][r];
         const double dv = (double)dd[vt][r];
         const double dp = (double)gl_other_part(dd[vt][r]);  // other part of D
-        dot_re = fma(part ? -lv : lv, dv, dot_re);
+        dot_re = fma(lv, dv, dot_re);
         dot_im = fma(lv, dp, dot_im);
+        lr = fma((double)lcr[vt][r], lv, lr);
+        li = fma((double)lci[vt][r], lv, li);
         const int a = vt * 16 + MF::row(lane, r);
-        const bool inw = wi >= 0 && a < nv;
-        double cr = (double)sCA[wic * nv16 + a], ci = (double)sCA[(no16 + wic) * nv16 + a];
-        cr = inw ? cr : 0.0;
-        ci = inw ? ci : 0.0;
-        lr = fma(part ? -ci : cr, lv, lr);
-        li = fma(part ? cr : ci, lv, li);
-        if (inw) {
+        if (wi >= 0 && a < nv) {
           R* dst = reinterpret_cast<R*>(Lam + ((size_t)wl * NG + g) * X + a * no + wi);
           dst[part] = lam[vt][r];
         }
@@ -682,7 +695,7 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
       ex0[o] = cd{xr, xi};
     }
   }
-  dot_re = gl_wsum(dot_re);
+  dot_re = gl_wsum(part ? -dot_re : dot_re);
   dot_im = gl_wsum(dot_im);
   if (lane == 0) czw[((size_t)s2 * NW + w) * n_chunks * NCT + chunk * NCT + wv] = cd{dot_re, dot_im};
   gl_bar_all();  // the re-reads past the last slab have landed; the next item rewrites the LDS
