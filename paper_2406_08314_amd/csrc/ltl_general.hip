@@ -71,6 +71,7 @@ constexpr int GL_KS = 16;      // orbitals per LDS slab of S^g
 constexpr int GL_NB = 4;       // slab buffers (three slabs in flight)
 constexpr int GL_VTMAX = 2;    // virtual row tiles (n_v <= 32)
 constexpr int GL_OMAX = 32;    // window occupied orbitals
+constexpr int GL_KSL2 = 11;    // T in registers at two workgroups per CU: at most 11 slabs
 
 __device__ __forceinline__ void gl_dma16(const void* g, void* lds) {
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -204,7 +205,7 @@ __host__ __device__ inline int gl_lds_reals(const GlShape& s, int rsize, int NCT
 }  // namespace
 
 template <class R, int NCT, int KSL, int VT, bool TL>
-__global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
+__global__ __launch_bounds__(64 * NCT, (TL || KSL > GL_KSL2) ? 1 : 2) void k_ltl_general(
     DevSpin sa, DevSpin sb, int NW, int w0, int WT, int NG, int g_chunk, int n_chunks, int M,
     const R* __restrict__ Sa, const R* __restrict__ Sb,
     const typename GMfma<R>::cx_t* __restrict__ Ta, const typename GMfma<R>::cx_t* __restrict__ Tb,
@@ -387,22 +388,27 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
   // <Lam, D> summed over the chunk: the sign of the real part (- on the
   // imaginary-part lanes) is applied once at the end
   double dot_re = 0.0, dot_im = 0.0;
-  // lc_g = <C, Lam_W> coefficients of this lane's Lam entries (constant over
-  // the chunk): C at its window entry, signed and zeroed outside the window
+  // lc_g = <C, Lam_W> coefficients of this lane's Lam entries: C at its
+  // window entry, signed and zeroed outside the window.  Constant over the
+  // chunk: read once with T in LDS, per vector with T in registers (whose
+  // register budget is two workgroups per CU).
   gl_bar_lds();  // the C block is in LDS
   R lcr[VT][4], lci[VT][4];
+  auto lc_read = [&]() {
 #pragma unroll
-  for (int vt = 0; vt < VT; ++vt)
+    for (int vt = 0; vt < VT; ++vt)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int a = vt * 16 + MF::row(lane, r);
-      const bool inw = wi >= 0 && a < nv;
-      const int wic = max(wi, 0);
-      const R cr = inw ? sCA[wic * nv16 + a] : R(0);
-      const R ci = inw ? sCA[(no16 + wic) * nv16 + a] : R(0);
-      lcr[vt][r] = part ? -ci : cr;
-      lci[vt][r] = part ? cr : ci;
-    }
+      for (int r = 0; r < 4; ++r) {
+        const int a = vt * 16 + MF::row(lane, r);
+        const bool inw = wi >= 0 && a < nv;
+        const int wic = max(wi, 0);
+        const R cr = inw ? sCA[wic * nv16 + a] : R(0);
+        const R ci = inw ? sCA[(no16 + wic) * nv16 + a] : R(0);
+        lcr[vt][r] = part ? -ci : cr;
+        lci[vt][r] = part ? cr : ci;
+      }
+  };
+  if constexpr (TL) lc_read();
   for (int u = 0; u < NB - 1; ++u) fetch_next();
   for (int g = g0; g < g1; ++g) {
     // ---- LT = S^g T over slabs of 16 orbitals
@@ -665,6 +671,7 @@ __global__ __launch_bounds__(64 * NCT, 1) void k_ltl_general(
     else dphase(std::integral_constant<int, 32>{});
     // ---- <Lam, D> (accumulated), lc_g = <C, Lam_W> (branch-free), window store
     double lr = 0.0, li = 0.0;
+    if constexpr (!TL) lc_read();
 #pragma unroll
     for (int vt = 0; vt < VT; ++vt)
 #pragma unroll
@@ -740,22 +747,32 @@ int ltl_general_vt(const DevSpin& sa, const DevSpin& sb) {
 }
 
 // slabs of 16 kept rows of T (outside the reference) for the larger spin,
-// rounded up to an instantiated count
+// rounded up to an instantiated count (T in registers needs it at compile time)
 int ltl_general_ksl(int M, int Nmin) {
   const int n = gl_mn(M, Nmin) / GL_KS;
-  for (int k : {4, 8, 13, 20})
+  for (int k : {4, 8, GL_KSL2, 20})
     if (n <= k) return k;
   return 0;
 }
 
-// T in LDS where it fits (any precision); T in registers otherwise, only in
-// FP64 and where the register-resident T does not spill (at most four column
-// tiles, i.e. N <= 32 per spin)
-static bool gl_tl(const DevSpin& sa, const DevSpin& sb, int M, size_t rsize) {
-  const int nct = ltl_general_nct(sa, sb);
+// Where the walker's T lives.  In FP64 at four column tiles (16 < N <= 32)
+// T in LDS fills it, so one workgroup runs per CU and its barriers and
+// epilogue leave the matrix cores idle; with T in registers (each wave holds
+// its column tile, at most GL_KSL2 slabs: 44 values a lane) the LDS holds only
+// the slab ring, Q, C and T_V and two workgroups share a CU, each one's
+// products running through the other's waits.  Otherwise T in LDS where it
+// fits (any precision, one or more workgroups per CU), else T in registers at
+// one workgroup per CU (FP64, four column tiles, at most 20 slabs).
+enum GlMode { GL_NONE, GL_TL, GL_REG };
+static GlMode gl_mode(const DevSpin& sa, const DevSpin& sb, int M, size_t rsize) {
+  const int nct = ltl_general_nct(sa, sb), ksl = ltl_general_ksl(M, std::min(sa.N, sb.N));
   const GlShape s = gl_shape(std::max(sa.no, sb.no), M, std::min(sa.N, sb.N), nct,
                              ltl_general_vt(sa, sb));
-  return (size_t)gl_lds_reals(s, (int)rsize, nct, true) * rsize <= 160 * 1024;
+  const size_t reg = (size_t)gl_lds_reals(s, 8, nct, false) * 8;
+  if (rsize == 8 && nct == 4 && ksl <= GL_KSL2 && 2 * reg <= 160 * 1024) return GL_REG;
+  if ((size_t)gl_lds_reals(s, (int)rsize, nct, true) * rsize <= 160 * 1024) return GL_TL;
+  if (rsize == 8 && nct == 4 && ksl == 20 && reg <= 160 * 1024) return GL_REG;
+  return GL_NONE;
 }
 
 bool ltl_general_fits(const DevSpin& sa, const DevSpin& sb, int M, bool fp32) {
@@ -764,11 +781,7 @@ bool ltl_general_fits(const DevSpin& sa, const DevSpin& sb, int M, bool fp32) {
   for (const DevSpin* d : {&sa, &sb}) {
     if (d->N == 0 || d->nv == 0 || d->nv > GL_VTMAX * 16 || d->no > GL_OMAX) return false;
   }
-  if (gl_tl(sa, sb, M, fp32 ? 4 : 8)) return true;
-  if (fp32 || nct > 4) return false;
-  const GlShape s = gl_shape(std::max(sa.no, sb.no), M, std::min(sa.N, sb.N), nct,
-                             ltl_general_vt(sa, sb));
-  return (size_t)gl_lds_reals(s, 8, nct, false) * 8 <= 160 * 1024;
+  return gl_mode(sa, sb, M, fp32 ? 4 : 8) != GL_NONE;
 }
 
 // elements of one spin's S array (sized for the spin with more kept rows)
@@ -831,25 +844,29 @@ void gl_dispatch(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, i
   const int nct = ltl_general_nct(sa, sb), ksl = ltl_general_ksl(M, std::min(sa.N, sb.N)),
             vt = ltl_general_vt(sa, sb);
   const int n_chunks = (NG + g_chunk - 1) / g_chunk;
-  const bool tl = gl_tl(sa, sb, M, sizeof(R));
-#define GL_CASE(n, k, v, t)                                                                     if (nct == n && ksl == k && vt == v && tl == t)                                                 return gl_launch<R, n, k, v, t>(sa, sb, NW, w0, WT, NG, g_chunk, n_chunks, M, Sa, Sb, Ta,                                     Tb, Lam_a, Lam_b, Ca, Cb, v0, ex0, lamc, czw, wmask, wls, st);
-#define GL_KSL(n, v) GL_CASE(n, 4, v, true) GL_CASE(n, 8, v, true) GL_CASE(n, 13, v, true) \
-                     GL_CASE(n, 20, v, true)
-  GL_KSL(2, 1)
-  GL_KSL(2, 2)
-  GL_KSL(4, 1)
-  GL_KSL(4, 2)
-  GL_KSL(6, 1)
-  GL_KSL(6, 2)
-  if constexpr (sizeof(R) == 8) {  // T in registers: FP64 where T does not fit LDS
-    GL_CASE(2, 20, 1, false)
-    GL_CASE(2, 20, 2, false)
-    GL_CASE(4, 13, 1, false)
-    GL_CASE(4, 13, 2, false)
+  const bool tl = gl_mode(sa, sb, M, sizeof(R)) == GL_TL;
+  // T in LDS: the slab count is a run-time loop bound (one instance each, KSL 0)
+#define GL_CASE(n, k, v, t)                                                                     \
+  if (nct == n && (t || ksl == k) && vt == v && tl == t)                                        \
+    return gl_launch<R, n, t ? 0 : k, v, t>(sa, sb, NW, w0, WT, NG, g_chunk, n_chunks, M, Sa, Sb, \
+                                           Ta, Tb, Lam_a, Lam_b, Ca, Cb, v0, ex0, lamc, czw, wmask, \
+                                           wls, st);
+  GL_CASE(2, 0, 1, true)
+  GL_CASE(2, 0, 2, true)
+  GL_CASE(4, 0, 1, true)
+  GL_CASE(4, 0, 2, true)
+  GL_CASE(6, 0, 1, true)
+  GL_CASE(6, 0, 2, true)
+  if constexpr (sizeof(R) == 8) {  // T in registers (FP64, four column tiles)
+    GL_CASE(4, 4, 1, false)
+    GL_CASE(4, 4, 2, false)
+    GL_CASE(4, 8, 1, false)
+    GL_CASE(4, 8, 2, false)
+    GL_CASE(4, GL_KSL2, 1, false)
+    GL_CASE(4, GL_KSL2, 2, false)
     GL_CASE(4, 20, 1, false)
     GL_CASE(4, 20, 2, false)
   }
-#undef GL_KSL
 #undef GL_CASE
 }
 }  // namespace
