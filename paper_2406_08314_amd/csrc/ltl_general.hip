@@ -235,10 +235,12 @@ __global__ __launch_bounds__(64 * NCT, (TL || KSL > GL_KSL2) ? 1 : 2) void k_ltl
   for (int it = wlist ? (int)blockIdx.x : 0; it < n_items; it += wlist ? (int)gridDim.x : 1) {
   int wl, chunk, s2;
   if (wlist) {
-    const int wi = it / (2 * n_chunks), rem = it % (2 * n_chunks);
-    wl = wlist[wi] - w0;
-    chunk = rem % n_chunks;
-    s2 = rem / n_chunks;
+    // listed walker fastest, as the grid order below: the workgroups resident
+    // together stream the same slabs of L (one chunk of one spin)
+    const int nl = *wcount;
+    wl = wlist[it % nl] - w0;
+    chunk = (it / nl) % n_chunks;
+    s2 = it / (nl * n_chunks);
     if (wl < 0 || wl >= WT) continue;  // listed walker outside this walker tile
   } else {
     const int b = blockIdx.x;

@@ -1552,8 +1552,16 @@ __global__ __launch_bounds__((MAXK <= 4 ? 1024 : 512)) void k_energy_second(
   // Work items (item block, Cholesky range, walker): one per workgroup (grid
   // mode), or, with a walker list, a persistent grid striding over the items
   // of the listed walkers
+  // Persistent mode is XCD-aware as well: workgroup b runs on XCD b % 8 and
+  // takes the items of that XCD's contiguous share of the item list, so the
+  // item blocks of one walker stay on one XCD (and its L2).
   const int n_items = wlist ? *wcount * n_ib * n_gsplit : 1;
-  for (int it = wlist ? (int)blockIdx.x : 0; it < n_items; it += wlist ? (int)gridDim.x : 1) {
+  const bool xcd8 = wlist && gridDim.x % 8 == 0;
+  const int x_share = (n_items + 7) / 8, x_lo = xcd8 ? (int)(blockIdx.x % 8) * x_share : 0;
+  const int it_end = !wlist ? 1 : xcd8 ? min(n_items, x_lo + x_share) : n_items;
+  const int it_step = !wlist ? 1 : xcd8 ? (int)gridDim.x / 8 : (int)gridDim.x;
+  for (int it = !wlist ? 0 : xcd8 ? x_lo + (int)blockIdx.x / 8 : (int)blockIdx.x; it < it_end;
+       it += it_step) {
   int ib, gs, wl;
   if (wlist) {
     ib = it % n_ib;
