@@ -420,8 +420,7 @@ def rooflines(wl, s, stages, t, count=2):
             prof = measured_traffic(("lambda", t["lambda_variant"], wl.name))
             if prof and (not prof[1] or prof[1] == (t["lambda_chunk"],)):
                 traffic = prof[0]
-        lam_kernel = {1: "k_lambda_rows", 2: "k_lambda_wave", 3: "k_lambda_wave",
-                      4: "k_lambda_mfma", 5: "k_ltl_mfma",
+        lam_kernel = {1: "k_lambda_rows", 5: "k_ltl_mfma",
                       6: "k_ltl_general"}.get(t["lambda_variant"], "k_lambda")
         kernel = {"energy_gamma": "k_energy_second", "lambda": lam_kernel, "traces": "k_qtr",
                   "lt_gemm": "k_gemm_f64 (LT)"}.get(name, name)

@@ -265,19 +265,18 @@ msd_status msd_reset_timings(msd_system* sys);
  * results beyond floating-point summation order. */
 typedef struct {
   int32_t fb_splitk;      /* K slices of the force-bias GEMM (1..16)                      */
-  int32_t lambda_variant; /* energy intermediates: 1 = two-wave rows kernel,
-                             2 = one-wave kernel with the next vector's loads in flight,
-                             3 = one-wave kernel loading each vector when used (fewer
-                             registers; only where both spins have N = 8 or 16 and the
-                             whole occupied window, else as 2), 4 = matrix-core kernel
-                             (both spins N = 8 with the whole occupied window and at
-                             most 64 active virtuals, else as 2), 5 = matrix-core kernel
-                             that also forms the Cholesky contraction L^g T itself, so
-                             it never goes through HBM (shapes of 4 with M <= 64, else
-                             as 4), 6 = general matrix-core kernel forming L^g T, Q,
-                             Lambda and the first-order contraction for up to 48
-                             electrons per spin, M <= 320 and windows of at most 32 x 32
-                             (the default where 5 does not apply).  2-5 need N <= 16   */
+  int32_t lambda_variant; /* energy intermediates: 1 = two-wave rows kernel over the
+                             L^g T tiles (N <= 32 per spin; the one-wave generic kernel
+                             beyond its limits), 5 = matrix-core kernel forming
+                             the Cholesky contraction L^g T, Lambda and the first-order
+                             contraction itself, so L^g T never goes through HBM (both
+                             spins N = 8 with the whole occupied window, at most 56
+                             active virtuals, M <= 64), 6 = general matrix-core kernel
+                             forming L^g T, Q, Lambda and the first-order contraction
+                             for up to 48 electrons per spin, M <= 320 and windows of
+                             at most 32 x 32 (the default where 5 does not apply).  A
+                             variant that does not fit the shape falls back to 1.
+                             2-4 (earlier kernels no workload picked) are rejected    */
   int32_t lambda_chunk;   /* Cholesky vectors per intermediates workgroup (1..NG); the
                              fused kernel's workgroup holds four walkers x two spins   */
   int32_t second_gsplit;  /* Cholesky-range split of the second-order kernel (1..64)      */

@@ -142,7 +142,7 @@ struct msd_system {
   double* fb_ws = nullptr;           // split-K workspace of the force-bias GEMM
   int fb_splitk = 1, fb_splitk_auto = 1, fb_ws_cap = 0;
   msd_tuning tune{};                 // launch-shape overrides (0 = automatic)
-  int lambda_variant = 1;            // resolved: 0 generic, 1 rows, 2/3 one-wave, 4 matrix-core
+  int lambda_variant = 1;            // resolved: 0 generic, 1 rows, 5 fused N = 8, 6 general
                                      // LT-tile kernel, 5 fused contraction + Lambda (N = 8),
                                      // 6 general fused contraction
   bool lambda_exact = false;         // N == nmax per spin and identity occupied window
@@ -517,11 +517,10 @@ void alloc_energy(msd_system* s) {
       if (S.occ_slot[i] != i) s->lambda_exact = false;
   }
   {
-    // 0: the generic one-wave kernel (windows beyond the row kernels' limits)
     // default: the fused contraction + Lambda kernel for N = 8 where it
-    // applies, else the general fused contraction kernel, else the
-    // matrix-core LT-tile kernel, else the one-wave kernel
-    const bool mfma_ok = s->lambda_exact && msd::lambda_mfma_fits(A, B);
+    // applies, else the general fused contraction kernel, else the two-wave
+    // rows kernel over the LT tiles, else (windows beyond the rows kernel's
+    // limits) the generic one-wave kernel, variant 0
     int wb_cc = 0;  // the option energy_algo = 3 takes its own fused contraction kernel
     const bool cc = s->o.energy_algo == 3 && msd::chol_contract_fits(A, B, &wb_cc);
     const bool fused_ok =
@@ -530,15 +529,11 @@ void alloc_energy(msd_system* s) {
     const int want = s->tune.lambda_variant ? s->tune.lambda_variant
                      : fused_ok                 ? 5
                      : gen_ok                   ? 6
-                     : mfma_ok                  ? 4
-                                                : 2;
-    s->lambda_variant = (want == 6 && gen_ok) ? 6
-                        : !rows_fit ? 0
-                        : (want == 1 || nmax > 16) ? 1
-                        : (want == 3 && s->lambda_exact) ? 3
-                        : (want == 4 && mfma_ok) ? 4
+                                                : 1;
+    s->lambda_variant = (want == 6 && gen_ok)     ? 6
                         : (want == 5 && fused_ok) ? 5
-                        : (want >= 4 && mfma_ok) ? 4 : 2;
+                        : rows_fit                ? 1
+                                                  : 0;
   }
   const bool fused_kernel = s->lambda_variant >= 5;  // LT never stored
   // walker tile: energy scratch of a tile within 16 GB
@@ -891,24 +886,16 @@ void run_energy_mixed(msd_system* s) {
         msd::launch_ltl_mfma32(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, s->M, s->Slf32[0],
                                s->Slf32[1], Ta, Tb, s->Lam32[0], s->Lam32[1], s->v0, s->sw[0].C,
                                s->sw[1].C, s->czw, s->lam_swz, s->st);
-      } else if (s->lambda_variant == 4)
-        msd::launch_lambda_mfma32(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, Ta, Tb, s->LT32[0],
-                                  s->LT32[1], s->Lam32[0], s->Lam32[1], s->v0, s->ex0,
-                                  s->ZWp[0], s->ZWp[1], s->Q64[0], s->Q64[1], s->st);
-      else if (s->lambda_variant == 0)
+      } else if (s->lambda_variant == 0)
         msd::launch_lambda32(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, Ta, Tb, s->LT32[0],
                              s->LT32[1], s->Lam32[0], s->Lam32[1], s->v0, s->ex0, s->ZWp[0],
                              s->ZWp[1], s->st);
-      else if (s->lambda_variant >= 2)
-        msd::launch_lambda_wave32(A, B, nmax, s->lambda_exact, s->lambda_variant == 2, s->NW, w0, wt, s->NG, s->gl_chunk, Ta, Tb,
-                                  s->LT32[0], s->LT32[1], s->Lam32[0], s->Lam32[1], s->v0, s->ex0,
-                                  s->ZWp[0], s->ZWp[1], s->st);
       else
         msd::launch_lambda_rows32(A, B, nmax, s->NW, w0, wt, s->NG, s->gl_chunk, Ta, Tb,
                                   s->LT32[0], s->LT32[1], s->Lam32[0], s->Lam32[1], s->v0, s->ex0,
                                   s->ZWp[0], s->ZWp[1], s->st);
     });
-    if (s->lambda_variant < 4) {  // the matrix-core kernels read the FP64 Q themselves
+    if (s->lambda_variant < 5) {  // the fused kernels form the traces themselves
       s->timed(ST_TRACES, [&] {
         msd::launch_traces64(s->Q64[0], s->Q64[1], A.N, B.N, s->NW, w0, wt, s->NG, s->v0, s->ex0,
                              s->st);
@@ -1103,15 +1090,7 @@ void run_energy(msd_system* s) {
           msd::launch_ltl_mfma(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, s->M, s->Slf[0],
                                s->Slf[1], s->sw[0].T, s->sw[1].T, s->Lam[0], s->Lam[1], s->v0,
                                s->sw[0].C, s->sw[1].C, s->czw, s->lam_swz, s->st);
-        } else if (s->lambda_variant == 4)
-          msd::launch_lambda_mfma(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, s->sw[0].T,
-                                  s->sw[1].T, s->LT[0], s->LT[1], s->Lam[0], s->Lam[1], s->v0,
-                                  s->ex0, s->ZWp[0], s->ZWp[1], s->st);
-        else if (s->lambda_variant >= 2 && msd::lambda_rows_fits(A, B, &nmax))
-          msd::launch_lambda_wave(A, B, nmax, s->lambda_exact, s->lambda_variant == 2, s->NW, w0, wt, s->NG, s->gl_chunk, s->sw[0].T,
-                                  s->sw[1].T, s->LT[0], s->LT[1], s->Lam[0], s->Lam[1], s->v0,
-                                  s->ex0, s->ZWp[0], s->ZWp[1], s->st);
-        else if (s->lambda_variant == 1 && msd::lambda_rows_fits(A, B, &nmax))
+        } else if (s->lambda_variant == 1 && msd::lambda_rows_fits(A, B, &nmax))
           msd::launch_lambda_rows(A, B, nmax, s->NW, w0, wt, s->NG, s->gl_chunk, s->sw[0].T,
                                   s->sw[1].T, s->LT[0], s->LT[1], s->Lam[0], s->Lam[1], s->v0,
                                   s->ex0, s->ZWp[0], s->ZWp[1], s->st);
@@ -2395,7 +2374,9 @@ namespace {
 void set_tuning_impl(msd_system* s, const msd_tuning& t) {
   auto bad = [](const char* f) { fail(MSD_ERR_ARG, std::string("tuning field ") + f + " out of range"); };
   if (t.fb_splitk < 0 || t.fb_splitk > 16) bad("fb_splitk");
-  if (t.lambda_variant < 0 || t.lambda_variant > 6) bad("lambda_variant");
+  if (t.lambda_variant < 0 || t.lambda_variant > 6 ||
+      (t.lambda_variant >= 2 && t.lambda_variant <= 4))
+    bad("lambda_variant");
   if (t.lambda_chunk < 0) bad("lambda_chunk");
   if (t.second_gsplit < 0 || t.second_gsplit > 64) bad("second_gsplit");
   if (t.second_stage < 0 || t.second_stage > 32) bad("second_stage");
@@ -2498,7 +2479,7 @@ msd_status msd_autotune(msd_system* sys, double dt, int32_t reps, msd_tuning* ou
     }
     int nmax = 0;
     if (msd::lambda_rows_fits(sys->ds[0], sys->ds[1], &nmax) && nmax <= 16)
-      sweep(&msd_tuning::lambda_variant, {1, 2, 3, 4, 5, 6});
+      sweep(&msd_tuning::lambda_variant, {1, 5, 6});
     sweep(&msd_tuning::lambda_chunk, {4, 8, 16, 32});
     sweep(&msd_tuning::second_gather, {1, 2});
     sweep(&msd_tuning::second_copy, {1, 2});

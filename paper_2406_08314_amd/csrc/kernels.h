@@ -197,26 +197,11 @@ void launch_lambda_rows32(const DevSpin& sa, const DevSpin& sb, int nmax, int NW
                           int NG, int g_chunk, const cf* Ta, const cf* Tb, const cf* LTa,
                           const cf* LTb, cf* Lam_a, cf* Lam_b, cd* v0, cd* ex0, cd* ZWpart_a,
                           cd* ZWpart_b, hipStream_t st);
-// One-wave-per-(walker, chunk, spin) variant of the same computation (no
-// cross-wave barrier, next vector's loads in flight); same outputs.  For
-// N <= 16 (nmax 8 or 16 from lambda_rows_fits).
-// Matrix-core variant of the energy intermediates for N = 8 per spin with the
-// whole occupied set in the window (identity slots) and n_vir_act <= 64.
-bool lambda_mfma_fits(const DevSpin& sa, const DevSpin& sb);
-void launch_lambda_mfma(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
-                        int g_chunk, const cd* Ta, const cd* Tb, const cd* LTa, const cd* LTb,
-                        cd* Lam_a, cd* Lam_b, cd* v0, cd* ex0, cd* ZWpart_a, cd* ZWpart_b,
-                        hipStream_t st);
-// (mixed form; v0, ex0 from the FP64 Q tiles Q64a/b when not null)
-void launch_lambda_mfma32(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
-                          int g_chunk, const cf* Ta, const cf* Tb, const cf* LTa, const cf* LTb,
-                          cf* Lam_a, cf* Lam_b, cd* v0, cd* ex0, cd* ZWpart_a, cd* ZWpart_b,
-                          const cd* Q64a, const cd* Q64b, hipStream_t st);
-// Fused Cholesky contraction + energy intermediates on the matrix cores (same
-// shapes as the LT-tile kernel, M <= 64): no LT in HBM.  S_a/S_b are the
+// Fused Cholesky contraction + energy intermediates on the matrix cores for
+// N = 8 per spin with the whole occupied set in the window, n_vir_act <= 64
+// and M <= 64: no LT in HBM.  S_a/S_b are the
 // restricted rows of L per spin, k-major and padded, [NG][64][P16] with rows
-// V_act then R (launch_gather_ltl); Lambda windows and ZW partials as
-// launch_lambda_mfma.
+// V_act then R (launch_gather_ltl); Lambda windows [w][g][a * N + i].
 bool ltl_mfma_fits(const DevSpin& sa, const DevSpin& sb, int M, bool fp32);
 size_t ltl_stage_elems(const DevSpin& sa, const DevSpin& sb);  // 64 * P16 per vector
 int ltl_rows16(const DevSpin& sa, const DevSpin& sb);
@@ -242,16 +227,6 @@ void launch_ltl_mfma32(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int
 void launch_qtr(int NW, int w0, int WT, int NG, int M, const double* SRa, const double* SRb,
                 const cd* Ta, const cd* Tb, cd* v0, cd* ex0, int n_cu, hipStream_t st);
 void init_ltl_attributes();
-// exact: both spins have N == nmax and an identity occupied window;
-// prefetch: next vector's LT row loaded ahead into registers (exact shapes).
-void launch_lambda_wave(const DevSpin& sa, const DevSpin& sb, int nmax, bool exact, bool prefetch,
-                        int NW, int w0, int WT, int NG, int g_chunk, const cd* Ta, const cd* Tb,
-                        const cd* LTa, const cd* LTb, cd* Lam_a, cd* Lam_b, cd* v0, cd* ex0,
-                        cd* ZWpart_a, cd* ZWpart_b, hipStream_t st);
-void launch_lambda_wave32(const DevSpin& sa, const DevSpin& sb, int nmax, bool exact,
-                          bool prefetch, int NW, int w0, int WT, int NG, int g_chunk, const cf* Ta, const cf* Tb,
-                          const cf* LTa, const cf* LTb, cf* Lam_a, cf* Lam_b, cd* v0, cd* ex0,
-                          cd* ZWpart_a, cd* ZWpart_b, hipStream_t st);
 void launch_pair_coef(const DevPairs& pr, int NW, const cd* det_c, const cd* adj_a, int Aa,
                       const cd* adj_b, int Ab, cd* coef, hipStream_t st);
 void launch_minor_coef(const DevSpin& s, int NW, const cd* B, int U, const cd* m2, cd* coef,

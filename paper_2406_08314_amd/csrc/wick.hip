@@ -1037,208 +1037,6 @@ __global__ __launch_bounds__(128) void k_lambda_rows(DevSpin sa, DevSpin sb, int
   }
 }
 
-// Same quantities with one wave per (walker, Cholesky chunk, spin) and no
-// cross-wave barrier: each wave also sums the other spin's trace v0 from the
-// diagonal of its Q, and the loads of the next vector (Q entries, this lane's
-// LT row, the other spin's diagonal) are issued before the current vector's
-// arithmetic.
-// EXACT: both spins have N == NMAX electrons and the occupied window is all
-// of them in order (slot i = i), so every bound and the window columns are
-// compile-time constants.
-// PF: prefetch the next vector's LT row into registers (more registers,
-// fewer exposed loads).
-template <int NMAX, int NOX, bool EXACT, bool PF, class CT>
-__global__ __launch_bounds__(64) void k_lambda_wave(DevSpin sa, DevSpin sb, int NW, int w0,
-                                                    int WT, int NG, int g_chunk,
-                                                    const CT* __restrict__ Ta,
-                                                    const CT* __restrict__ Tb,
-                                                    const CT* __restrict__ LTa,
-                                                    const CT* __restrict__ LTb,
-                                                    CT* __restrict__ Lam_a, CT* __restrict__ Lam_b,
-                                                    cd* __restrict__ v0, cd* __restrict__ ex0,
-                                                    cd* __restrict__ ZWa, cd* __restrict__ ZWb) {
-  constexpr int QPL = (NMAX * NMAX + 63) / 64;  // Q entries per lane
-  __shared__ CT Qs[NMAX * NMAX];
-  const int wl = blockIdx.x, chunk = blockIdx.y, n_chunks = gridDim.y, s2 = blockIdx.z;
-  const int w = w0 + wl, lane = threadIdx.x;
-  const int N = s2 ? sb.N : sa.N, nv = s2 ? sb.nv : sa.nv, no = s2 ? sb.no : sa.no;
-  const int P = s2 ? sb.P : sa.P, X = nv * no;
-  const int No = s2 ? sa.N : sb.N, Po = s2 ? sa.P : sb.P;
-  const int* __restrict__ vir = s2 ? sb.vir : sa.vir;
-  const int* __restrict__ oslot = s2 ? sb.oslot : sa.oslot;
-  const CT* __restrict__ T = s2 ? Tb : Ta;
-  const CT* __restrict__ LT = s2 ? LTb : LTa;
-  const CT* __restrict__ LTo = s2 ? LTa : LTb;
-  CT* __restrict__ Lam = s2 ? Lam_b : Lam_a;
-  cd* __restrict__ ZW = s2 ? ZWb : ZWa;
-  const bool row = lane < nv;
-  CT tv[NMAX];
-  cd zw[NOX];
-  int osl[NOX];
-#pragma unroll
-  for (int j = 0; j < NMAX; ++j)
-    tv[j] = (row && j < N) ? T[((size_t)vir[lane] * NW + w) * N + j] : CT{};
-#pragma unroll
-  for (int i = 0; i < NOX; ++i) {
-    osl[i] = i < no ? oslot[i] : 0;
-    zw[i] = cd{0.0, 0.0};
-  }
-  const size_t ld = (size_t)N, ldo = (size_t)No;  // contiguous P x N tiles per (walker, vector)
-  const int g0 = chunk * g_chunk, g1 = min(NG, g0 + g_chunk);
-  CT qn[QPL], ltn[NMAX], dn{};
-  auto fetch = [&](int g) {
-    const CT* base = LT + ((size_t)wl * NG + g) * P * N;
-#pragma unroll
-    for (int r = 0; r < QPL; ++r) {
-      const int e = lane + 64 * r;
-      qn[r] = e < N * N ? base[(size_t)(e / N) * ld + e % N] : CT{};
-    }
-    if (PF) {
-#pragma unroll
-      for (int c = 0; c < NMAX; ++c)
-        ltn[c] = (row && c < N) ? base[(size_t)(N + lane) * ld + c] : CT{};
-    }
-    const CT* baseo = LTo + ((size_t)wl * NG + g) * Po * No;
-    dn = lane < No ? baseo[(size_t)lane * ldo + lane] : CT{};
-  };
-  if (g0 < g1) fetch(g0);
-  for (int g = g0; g < g1; ++g) {
-    CT q[QPL], ltv[NMAX];
-#pragma unroll
-    for (int r = 0; r < QPL; ++r) q[r] = qn[r];
-    if (PF) {
-#pragma unroll
-      for (int c = 0; c < NMAX; ++c) ltv[c] = ltn[c];
-    } else {
-      const CT* base = LT + ((size_t)wl * NG + g) * P * N;
-#pragma unroll
-      for (int c = 0; c < NMAX; ++c)
-        ltv[c] = (row && c < N) ? base[(size_t)(N + lane) * ld + c] : CT{};
-    }
-    const CT d = dn;
-    __syncthreads();  // the previous vector's reads of Qs are done
-#pragma unroll
-    for (int r = 0; r < QPL; ++r) {
-      const int e = lane + 64 * r;
-      if (e < N * N) Qs[e] = q[r];
-    }
-    if (g + 1 < g1) fetch(g + 1);
-    CT v{};
-#pragma unroll
-    for (int r = 0; r < QPL; ++r) {
-      const int e = lane + 64 * r;
-      if (e < N * N && e / N == e % N) v += q[r];
-    }
-    v = wave_sum(v);
-    const CT vo = wave_sum(d);
-    __syncthreads();
-    CT x{};
-#pragma unroll
-    for (int r = 0; r < QPL; ++r) {
-      const int e = lane + 64 * r;
-      if (e < N * N) cfma(x, q[r], Qs[(e % N) * N + e / N]);
-    }
-    x = wave_sum(x);
-    if (lane == 0) {
-      v0[((size_t)s2 * NW + w) * NG + g] = N > 0 ? to_cd(v) : cd{0.0, 0.0};
-      ex0[((size_t)s2 * NW + w) * NG + g] = N > 0 ? to_cd(x) : cd{0.0, 0.0};
-    }
-    const CT vsum = v + vo;
-    if (EXACT && row) {
-      // row j of Q at a time (scheduling barriers keep the compiler from
-      // hoisting all N^2 LDS reads into registers)
-      CT lam[NMAX];
-#pragma unroll
-      for (int c = 0; c < NMAX; ++c) lam[c] = -ltv[c];
-#pragma unroll
-      for (int j = 0; j < NMAX; ++j) {
-#pragma unroll
-        for (int c = 0; c < NMAX; ++c) cfma(lam[c], tv[j], Qs[j * NMAX + c]);
-        __builtin_amdgcn_sched_barrier(0);
-      }
-      CT* Lo = Lam + ((size_t)wl * NG + g) * X + (size_t)lane * NMAX;
-#pragma unroll
-      for (int i = 0; i < NMAX; ++i) {
-        CT xi{};
-#pragma unroll
-        for (int c = 0; c < NMAX; ++c) cfma(xi, lam[c], Qs[c * NMAX + i]);
-        Lo[i] = lam[i];
-        zw[i] += to_cd(xi - vsum * lam[i]);
-        __builtin_amdgcn_sched_barrier(0);
-      }
-    } else if (row) {
-      CT lam[NMAX];
-#pragma unroll
-      for (int c = 0; c < NMAX; ++c) {
-        CT a = -ltv[c];
-#pragma unroll
-        for (int j = 0; j < NMAX; ++j)
-          if (j < N && c < N) cfma(a, tv[j], Qs[j * N + c]);
-        lam[c] = a;
-      }
-      CT* Lo = Lam + ((size_t)wl * NG + g) * X + (size_t)lane * no;
-#pragma unroll
-      for (int i = 0; i < NOX; ++i) {
-        if (i < no) {
-          const int oc = osl[i];
-          CT xi{}, lw{};
-#pragma unroll
-          for (int c = 0; c < NMAX; ++c) {
-            if (c < N) cfma(xi, lam[c], Qs[c * N + oc]);
-            if (c == oc) lw = lam[c];
-          }
-          Lo[i] = lw;
-          zw[i] += to_cd(xi - vsum * lw);
-        }
-      }
-    }
-  }
-  if (row) {
-#pragma unroll
-    for (int i = 0; i < NOX; ++i)
-      if (i < no) ZW[((size_t)wl * n_chunks + chunk) * X + (size_t)lane * no + i] = zw[i];
-  }
-}
-
-template <class CT>
-static void launch_lambda_wave_t(const DevSpin& sa, const DevSpin& sb, int nmax, bool exact,
-                                 bool prefetch, int NW, int w0, int WT, int NG, int g_chunk, const CT* Ta,
-                                 const CT* Tb, const CT* LTa, const CT* LTb, CT* Lam_a, CT* Lam_b,
-                                 cd* v0, cd* ex0, cd* ZWpart_a, cd* ZWpart_b, hipStream_t st) {
-  const int n_chunks = (NG + g_chunk - 1) / g_chunk;
-  const dim3 grid(WT, n_chunks, 2);
-  const bool o8 = max(sa.no, sb.no) <= 8;
-#define MSD_LW(NM, NO, EX, PF) \
-  hipLaunchKernelGGL((k_lambda_wave<NM, NO, EX, PF, CT>), grid, dim3(64), 0, st, sa, sb, NW, w0, \
-                     WT, NG, g_chunk, Ta, Tb, LTa, LTb, Lam_a, Lam_b, v0, ex0, ZWpart_a, ZWpart_b)
-  if (exact && nmax == 8) {
-    if (prefetch) MSD_LW(8, 8, true, true); else MSD_LW(8, 8, true, false);
-  } else if (exact && nmax == 16) {
-    if (prefetch) MSD_LW(16, 16, true, true); else MSD_LW(16, 16, true, false);
-  } else if (nmax <= 8) {
-    if (o8) MSD_LW(8, 8, false, true); else MSD_LW(8, 16, false, true);
-  } else {
-    if (o8) MSD_LW(16, 8, false, true); else MSD_LW(16, 16, false, true);
-  }
-#undef MSD_LW
-}
-
-void launch_lambda_wave(const DevSpin& sa, const DevSpin& sb, int nmax, bool exact, bool prefetch,
-                        int NW, int w0, int WT, int NG, int g_chunk, const cd* Ta, const cd* Tb,
-                        const cd* LTa, const cd* LTb, cd* Lam_a, cd* Lam_b, cd* v0, cd* ex0,
-                        cd* ZWpart_a, cd* ZWpart_b, hipStream_t st) {
-  launch_lambda_wave_t<cd>(sa, sb, nmax, exact, prefetch, NW, w0, WT, NG, g_chunk, Ta, Tb, LTa, LTb, Lam_a, Lam_b,
-                           v0, ex0, ZWpart_a, ZWpart_b, st);
-}
-
-void launch_lambda_wave32(const DevSpin& sa, const DevSpin& sb, int nmax, bool exact,
-                          bool prefetch, int NW, int w0, int WT, int NG, int g_chunk, const cf* Ta, const cf* Tb,
-                          const cf* LTa, const cf* LTb, cf* Lam_a, cf* Lam_b, cd* v0, cd* ex0,
-                          cd* ZWpart_a, cd* ZWpart_b, hipStream_t st) {
-  launch_lambda_wave_t<cf>(sa, sb, nmax, exact, prefetch, NW, w0, WT, NG, g_chunk, Ta, Tb, LTa, LTb, Lam_a, Lam_b,
-                           v0, ex0, ZWpart_a, ZWpart_b, st);
-}
-
 bool lambda_rows_fits(const DevSpin& sa, const DevSpin& sb, int* nmax) {
   const int n = max(sa.N, sb.N);
   if (sa.nv > 64 || sb.nv > 64 || sa.no > NOMAX || sb.no > NOMAX || n > 32) return false;
