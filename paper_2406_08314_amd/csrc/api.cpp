@@ -160,7 +160,7 @@ struct msd_system {
   double* LR64[2] = {nullptr, nullptr};     // [NG][N_s][M] reference rows of L (FP64)
   cd* Q64[2] = {nullptr, nullptr};          // [wl][g][N_s x N_s] FP64 Q for the traces
   cd* czw = nullptr;  // [2][NW][n_lchunks] C . ZW per chunk (fused kernel)
-  bool lam_swz = false;  // Lambda windows in the lam_swizzle layout (fused path)
+  bool lam_swz = false;  // Lambda windows in the lam_swizzle layout (fused kernels)
   cf* Lam32[2] = {nullptr, nullptr};
   bool energy_mixed = false;                // mixed energy path usable for this trial
 
@@ -611,8 +611,9 @@ void alloc_energy(msd_system* s) {
   }
   // only the row-pair / pair second-order kernel reads the windows then (the
   // minor-list form indexes them unswizzled)
-  s->lam_swz = s->lambda_variant == 5 && s->use_strings[0] && s->use_strings[1] &&
-               A.no == 8 && B.no == 8;
+  s->lam_swz = s->use_strings[0] && s->use_strings[1] &&
+               ((s->lambda_variant == 5 && A.no == 8 && B.no == 8) ||
+                (s->lambda_variant == 6 && A.no % 8 == 0 && B.no % 8 == 0));
   // the mixed form's FP64 pass for walkers far from the reference (general kernel)
   s->guard = s->energy_mixed && s->lambda_variant == 6 && s->gl_fits && s->tmax > 0.0;
   s->n_slots_main = slot;
@@ -881,7 +882,8 @@ void run_energy_mixed(msd_system* s) {
       if (s->lambda_variant == 6) {
         msd::launch_ltl_general32(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, s->M, s->Sgl32[0],
                                   s->Sgl32[1], Ta, Tb, s->Lam32[0], s->Lam32[1], s->sw[0].C,
-                                  s->sw[1].C, s->v0, s->ex0, s->lamc, s->czw, fm, s->st);
+                                  s->sw[1].C, s->v0, s->ex0, s->lamc, s->czw, fm, s->lam_swz,
+                                  s->st);
       } else if (s->lambda_variant == 5) {
         msd::launch_ltl_mfma32(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, s->M, s->Slf32[0],
                                s->Slf32[1], Ta, Tb, s->Lam32[0], s->Lam32[1], s->v0, s->sw[0].C,
@@ -1001,13 +1003,14 @@ void run_energy_guard(msd_system* s) {
       const int wt = std::min(s->WT, s->NW - w0);
       msd::launch_ltl_general(A, B, s->NW, w0, wt, s->NG, s->gl_chunk_guard, s->M, s->Sgl[0],
                               s->Sgl[1], s->sw[0].T, s->sw[1].T, s->Lam[0], s->Lam[1], s->sw[0].C,
-                              s->sw[1].C, s->v0, s->ex0, s->lamc, s->czw, s->gmask, s->st, wls);
+                              s->sw[1].C, s->v0, s->ex0, s->lamc, s->czw, s->gmask, s->lam_swz,
+                              s->st, wls);
       if (s->wform)
         run_wform(s, w0, wt, false, s->gmask);
       else
         msd::launch_energy_second(A, B, s->dp, s->plan, s->n_itemblocks, s->second_waves, s->NW,
                                   w0, wt, s->NG, s->gsplit_guard, s->second_G64, s->second_maxk,
-                                  s->second_flat, s->second_dma, false, s->Lam[0], s->Lam[1],
+                                  s->second_flat, s->second_dma, s->lam_swz, s->Lam[0], s->Lam[1],
                                   s->coefAB, s->sw[0].m2, s->sw[1].m2, s->sw[0].B, s->sw[1].B,
                                   s->epart, s->n_slots, s->slot_guard, s->st, s->gmask, wls);
       msd::launch_energy_final(A, B, s->NW, w0, wt, s->NG, s->n_lchunks_guard, s->n_slots,
@@ -1085,7 +1088,7 @@ void run_energy(msd_system* s) {
           msd::launch_ltl_general(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, s->M, s->Sgl[0],
                                   s->Sgl[1], s->sw[0].T, s->sw[1].T, s->Lam[0], s->Lam[1],
                                   s->sw[0].C, s->sw[1].C, s->v0, s->ex0, s->lamc, s->czw,
-                                  nullptr, s->st);
+                                  nullptr, s->lam_swz, s->st);
         } else if (s->lambda_variant == 5) {
           msd::launch_ltl_mfma(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, s->M, s->Slf[0],
                                s->Slf[1], s->sw[0].T, s->sw[1].T, s->Lam[0], s->Lam[1], s->v0,

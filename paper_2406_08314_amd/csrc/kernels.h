@@ -162,10 +162,11 @@ int ltl_general_parts(const DevSpin& sa, const DevSpin& sb);
 size_t ltl_general_s_elems(const DevSpin& sa, const DevSpin& sb, int M, int NG);
 void launch_gather_general(const double* L, int NG, int M, const DevSpin& D, const DevSpin& sa,
                            const DevSpin& sb, double* S64, float* S32, hipStream_t st);
+// swz: store the Lambda windows in the lam_swizzle layout (n_o a multiple of 8).
 void launch_ltl_general(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
                         int g_chunk, int M, const double* Sa, const double* Sb, const cd* Ta,
                         const cd* Tb, cd* Lam_a, cd* Lam_b, const cd* Ca, const cd* Cb, cd* v0,
-                        cd* ex0, cd* lamc, cd* czw, const int* wmask, hipStream_t st,
+                        cd* ex0, cd* lamc, cd* czw, const int* wmask, bool swz, hipStream_t st,
                         const WalkerList& wls = WalkerList());
 // mask[w] = 1 where max |T| of walker w (either spin) exceeds tmax, rest[w] =
 // 1 - mask[w]; list[0 .. *count) = the walkers with mask[w] = 1, in order
@@ -174,7 +175,7 @@ void launch_walker_tmax(int NW, int M, int na, int nb, const cd* Ta, const cd* T
 void launch_ltl_general32(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
                           int g_chunk, int M, const float* Sa, const float* Sb, const cf* Ta,
                           const cf* Tb, cf* Lam_a, cf* Lam_b, const cd* Ca, const cd* Cb, cd* v0,
-                          cd* ex0, cd* lamc, cd* czw, const int* wmask, hipStream_t st,
+                          cd* ex0, cd* lamc, cd* czw, const int* wmask, bool swz, hipStream_t st,
                           const WalkerList& wls = WalkerList());
 
 // energy (one walker tile of WT walkers starting at w0)

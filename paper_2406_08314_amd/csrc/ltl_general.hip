@@ -212,7 +212,8 @@ __global__ __launch_bounds__(64 * NCT, (TL || KSL > GL_KSL2) ? 1 : 2) void k_ltl
     typename GMfma<R>::cx_t* __restrict__ Lam_a, typename GMfma<R>::cx_t* __restrict__ Lam_b,
     const cd* __restrict__ Ca, const cd* __restrict__ Cb, cd* __restrict__ v0,
     cd* __restrict__ ex0, cd* __restrict__ lamc, cd* __restrict__ czw,
-    const int* __restrict__ wmask, const int* __restrict__ wlist, const int* __restrict__ wcount) {
+    const int* __restrict__ wmask, const int* __restrict__ wlist, const int* __restrict__ wcount,
+    bool swz) {
   typedef GMfma<R> MF;
   typedef typename MF::cx_t C;
   typedef typename MF::acc_t acc_t;
@@ -687,7 +688,8 @@ __global__ __launch_bounds__(64 * NCT, (TL || KSL > GL_KSL2) ? 1 : 2) void k_ltl
         li = fma((double)lci[vt][r], lv, li);
         const int a = vt * 16 + MF::row(lane, r);
         if (wi >= 0 && a < nv) {
-          R* dst = reinterpret_cast<R*>(Lam + ((size_t)wl * NG + g) * X + a * no + wi);
+          const int e = a * no + wi;
+          R* dst = reinterpret_cast<R*>(Lam + ((size_t)wl * NG + g) * X + (swz ? lam_swizzle(e) : e));
           dst[part] = lam[vt][r];
         }
       }
@@ -814,7 +816,8 @@ void gl_launch(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int
                int n_chunks, int M, const R* Sa, const R* Sb, const typename GMfma<R>::cx_t* Ta,
                const typename GMfma<R>::cx_t* Tb, typename GMfma<R>::cx_t* Lam_a,
                typename GMfma<R>::cx_t* Lam_b, const cd* Ca, const cd* Cb, cd* v0, cd* ex0,
-               cd* lamc, cd* czw, const int* wmask, const WalkerList& wls, hipStream_t st) {
+               cd* lamc, cd* czw, const int* wmask, const WalkerList& wls, bool swz,
+               hipStream_t st) {
   const GlShape s = gl_shape(std::max(sa.no, sb.no), M, std::min(sa.N, sb.N), NCT, VT);
   const size_t lds = (size_t)gl_lds_reals(s, sizeof(R), NCT, TL) * sizeof(R);
   const void* fn = (const void*)k_ltl_general<R, NCT, KSL, VT, TL>;
@@ -834,7 +837,7 @@ void gl_launch(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int
   }
   hipLaunchKernelGGL((k_ltl_general<R, NCT, KSL, VT, TL>), grid, block, lds, st, sa, sb, NW, w0,
                      WT, NG, g_chunk, n_chunks, M, Sa, Sb, Ta, Tb, Lam_a, Lam_b, Ca, Cb, v0, ex0,
-                     lamc, czw, wmask, wls.list, wls.count);
+                     lamc, czw, wmask, wls.list, wls.count, swz);
 }
 
 template <class R>
@@ -842,7 +845,8 @@ void gl_dispatch(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, i
                  int g_chunk, int M, const R* Sa, const R* Sb, const typename GMfma<R>::cx_t* Ta,
                  const typename GMfma<R>::cx_t* Tb, typename GMfma<R>::cx_t* Lam_a,
                  typename GMfma<R>::cx_t* Lam_b, const cd* Ca, const cd* Cb, cd* v0, cd* ex0,
-                 cd* lamc, cd* czw, const int* wmask, const WalkerList& wls, hipStream_t st) {
+                 cd* lamc, cd* czw, const int* wmask, const WalkerList& wls, bool swz,
+                 hipStream_t st) {
   const int nct = ltl_general_nct(sa, sb), ksl = ltl_general_ksl(M, std::min(sa.N, sb.N)),
             vt = ltl_general_vt(sa, sb);
   const int n_chunks = (NG + g_chunk - 1) / g_chunk;
@@ -852,7 +856,7 @@ void gl_dispatch(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, i
   if (nct == n && (t || ksl == k) && vt == v && tl == t)                                        \
     return gl_launch<R, n, t ? 0 : k, v, t>(sa, sb, NW, w0, WT, NG, g_chunk, n_chunks, M, Sa, Sb, \
                                            Ta, Tb, Lam_a, Lam_b, Ca, Cb, v0, ex0, lamc, czw, wmask, \
-                                           wls, st);
+                                           wls, swz, st);
   GL_CASE(2, 0, 1, true)
   GL_CASE(2, 0, 2, true)
   GL_CASE(4, 0, 1, true)
@@ -878,19 +882,19 @@ int ltl_general_parts(const DevSpin& sa, const DevSpin& sb) { return ltl_general
 void launch_ltl_general(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
                         int g_chunk, int M, const double* Sa, const double* Sb, const cd* Ta,
                         const cd* Tb, cd* Lam_a, cd* Lam_b, const cd* Ca, const cd* Cb, cd* v0,
-                        cd* ex0, cd* lamc, cd* czw, const int* wmask, hipStream_t st,
+                        cd* ex0, cd* lamc, cd* czw, const int* wmask, bool swz, hipStream_t st,
                         const WalkerList& wls) {
   gl_dispatch<double>(sa, sb, NW, w0, WT, NG, g_chunk, M, Sa, Sb, Ta, Tb, Lam_a, Lam_b, Ca, Cb,
-                      v0, ex0, lamc, czw, wmask, wls, st);
+                      v0, ex0, lamc, czw, wmask, wls, swz, st);
 }
 
 void launch_ltl_general32(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
                           int g_chunk, int M, const float* Sa, const float* Sb, const cf* Ta,
                           const cf* Tb, cf* Lam_a, cf* Lam_b, const cd* Ca, const cd* Cb, cd* v0,
-                          cd* ex0, cd* lamc, cd* czw, const int* wmask, hipStream_t st,
+                          cd* ex0, cd* lamc, cd* czw, const int* wmask, bool swz, hipStream_t st,
                           const WalkerList& wls) {
   gl_dispatch<float>(sa, sb, NW, w0, WT, NG, g_chunk, M, Sa, Sb, Ta, Tb, Lam_a, Lam_b, Ca, Cb, v0,
-                     ex0, lamc, czw, wmask, wls, st);
+                     ex0, lamc, czw, wmask, wls, swz, st);
 }
 
 // Walkers for the FP64 energy pass of the mixed form: mask[w] = 1 where the
