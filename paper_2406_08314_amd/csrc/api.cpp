@@ -160,7 +160,7 @@ struct msd_system {
   double* LR64[2] = {nullptr, nullptr};     // [NG][N_s][M] reference rows of L (FP64)
   cd* Q64[2] = {nullptr, nullptr};          // [wl][g][N_s x N_s] FP64 Q for the traces
   cd* czw = nullptr;  // [2][NW][n_lchunks] C . ZW per chunk (fused kernel)
-  bool lam_swz = false;  // Lambda windows in the lam_swizzle layout (fused kernels)
+  int lam_swz = 0;  // Lambda windows in lam_swizzle layout lam_swz (fused kernels; 0 plain)
   cf* Lam32[2] = {nullptr, nullptr};
   bool energy_mixed = false;                // mixed energy path usable for this trial
 
@@ -611,9 +611,12 @@ void alloc_energy(msd_system* s) {
   }
   // only the row-pair / pair second-order kernel reads the windows then (the
   // minor-list form indexes them unswizzled)
-  s->lam_swz = s->use_strings[0] && s->use_strings[1] &&
-               ((s->lambda_variant == 5 && A.no == 8 && B.no == 8) ||
-                (s->lambda_variant == 6 && A.no % 8 == 0 && B.no % 8 == 0));
+  s->lam_swz = 0;
+  if (s->use_strings[0] && s->use_strings[1]) {
+    if (s->lambda_variant == 5 && A.no == 8 && B.no == 8) s->lam_swz = 1;
+    if (s->lambda_variant == 6)
+      s->lam_swz = A.no % 16 == 0 && B.no % 16 == 0 ? 2 : A.no % 8 == 0 && B.no % 8 == 0 ? 1 : 0;
+  }
   // the mixed form's FP64 pass for walkers far from the reference (general kernel)
   s->guard = s->energy_mixed && s->lambda_variant == 6 && s->gl_fits && s->tmax > 0.0;
   s->n_slots_main = slot;
@@ -887,7 +890,7 @@ void run_energy_mixed(msd_system* s) {
       } else if (s->lambda_variant == 5) {
         msd::launch_ltl_mfma32(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, s->M, s->Slf32[0],
                                s->Slf32[1], Ta, Tb, s->Lam32[0], s->Lam32[1], s->v0, s->sw[0].C,
-                               s->sw[1].C, s->czw, s->lam_swz, s->st);
+                               s->sw[1].C, s->czw, s->lam_swz != 0, s->st);
       } else if (s->lambda_variant == 0)
         msd::launch_lambda32(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, Ta, Tb, s->LT32[0],
                              s->LT32[1], s->Lam32[0], s->Lam32[1], s->v0, s->ex0, s->ZWp[0],
@@ -1092,7 +1095,7 @@ void run_energy(msd_system* s) {
         } else if (s->lambda_variant == 5) {
           msd::launch_ltl_mfma(A, B, s->NW, w0, wt, s->NG, s->gl_chunk, s->M, s->Slf[0],
                                s->Slf[1], s->sw[0].T, s->sw[1].T, s->Lam[0], s->Lam[1], s->v0,
-                               s->sw[0].C, s->sw[1].C, s->czw, s->lam_swz, s->st);
+                               s->sw[0].C, s->sw[1].C, s->czw, s->lam_swz != 0, s->st);
         } else if (s->lambda_variant == 1 && msd::lambda_rows_fits(A, B, &nmax))
           msd::launch_lambda_rows(A, B, nmax, s->NW, w0, wt, s->NG, s->gl_chunk, s->sw[0].T,
                                   s->sw[1].T, s->LT[0], s->LT[1], s->Lam[0], s->Lam[1], s->v0,

@@ -50,11 +50,15 @@ void launch_gemm32(const GemmArgs32& g, hipStream_t st);
 // Element-wise precision conversions (n elements).
 void launch_f64_to_f32(const double* src, float* dst, int64_t n, hipStream_t st);
 
-// Window layout of Lambda with eight hole slots, as written by the fused
-// contraction kernel when the second-order terms read it (swz): entry
-// (a, i) at a * 8 + (i ^ ((a >> 1) & 7)), which spreads a wave's gathers of
-// one hole slot over the LDS banks.  Maps an unswizzled index a * 8 + i.
-__host__ __device__ inline int lam_swizzle(int x) { return (x & ~7) | ((x & 7) ^ ((x >> 4) & 7)); }
+// Window layout of Lambda as the fused contraction kernels write it when the
+// second-order terms read it (swz mode): mode 1, eight hole slots, entry
+// (a, i) at a * 8 + (i ^ ((a >> 1) & 7)); mode 2, sixteen hole slots, entry
+// (a, i) at a * 16 + (i ^ (a & 15)).  Either spreads a wave's gathers of one
+// hole slot over the LDS banks.  Maps an unswizzled index a * n_o + i.
+__host__ __device__ inline int lam_swizzle(int x, int mode = 1) {
+  return mode == 2 ? (x & ~15) | ((x & 15) ^ ((x >> 4) & 15))  // n_o 16: the slot's four bits
+                   : (x & ~7) | ((x & 7) ^ ((x >> 4) & 7));   // n_o 8: (a >> 1) & 7
+}
 
 // ---------------------------------------------------------------- device tables
 struct DevSpin {
@@ -162,11 +166,11 @@ int ltl_general_parts(const DevSpin& sa, const DevSpin& sb);
 size_t ltl_general_s_elems(const DevSpin& sa, const DevSpin& sb, int M, int NG);
 void launch_gather_general(const double* L, int NG, int M, const DevSpin& D, const DevSpin& sa,
                            const DevSpin& sb, double* S64, float* S32, hipStream_t st);
-// swz: store the Lambda windows in the lam_swizzle layout (n_o a multiple of 8).
+// swz: store the Lambda windows in lam_swizzle layout swz (0: plain).
 void launch_ltl_general(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
                         int g_chunk, int M, const double* Sa, const double* Sb, const cd* Ta,
                         const cd* Tb, cd* Lam_a, cd* Lam_b, const cd* Ca, const cd* Cb, cd* v0,
-                        cd* ex0, cd* lamc, cd* czw, const int* wmask, bool swz, hipStream_t st,
+                        cd* ex0, cd* lamc, cd* czw, const int* wmask, int swz, hipStream_t st,
                         const WalkerList& wls = WalkerList());
 // mask[w] = 1 where max |T| of walker w (either spin) exceeds tmax, rest[w] =
 // 1 - mask[w]; list[0 .. *count) = the walkers with mask[w] = 1, in order
@@ -175,7 +179,7 @@ void launch_walker_tmax(int NW, int M, int na, int nb, const cd* Ta, const cd* T
 void launch_ltl_general32(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
                           int g_chunk, int M, const float* Sa, const float* Sb, const cf* Ta,
                           const cf* Tb, cf* Lam_a, cf* Lam_b, const cd* Ca, const cd* Cb, cd* v0,
-                          cd* ex0, cd* lamc, cd* czw, const int* wmask, bool swz, hipStream_t st,
+                          cd* ex0, cd* lamc, cd* czw, const int* wmask, int swz, hipStream_t st,
                           const WalkerList& wls = WalkerList());
 
 // energy (one walker tile of WT walkers starting at w0)
@@ -243,7 +247,7 @@ constexpr int ER_PAIRS_PER_WAVE = 256;  // 64 lanes x 4 pairs
 void launch_energy_second(const DevSpin& sa, const DevSpin& sb, const DevPairs& pr,
                           const int4* plan, int n_itemblocks, int waves_per_block, int NW, int w0,
                           int WT, int NG, int n_gsplit, int G, int max_order, bool flat_gather,
-                          bool use_dma, bool swz, const cd* Lam_a, const cd* Lam_b, const cd* coef,
+                          bool use_dma, int swz, const cd* Lam_a, const cd* Lam_b, const cd* coef,
                           const cd* m2a, const cd* m2b, const cd* Ba, const cd* Bb, cd* partial,
                           int n_slots, int slot0, hipStream_t st, const int* wmask = nullptr,
                           const WalkerList& wls = WalkerList());
@@ -252,7 +256,7 @@ void launch_energy_second(const DevSpin& sa, const DevSpin& sb, const DevPairs& 
 void launch_energy_second32(const DevSpin& sa, const DevSpin& sb, const DevPairs& pr,
                             const int4* plan, int n_itemblocks, int waves_per_block, int NW,
                             int w0, int WT, int NG, int n_gsplit, int G, int max_order,
-                            bool flat_gather, bool use_dma, bool swz, const cf* Lam_a, const cf* Lam_b,
+                            bool flat_gather, bool use_dma, int swz, const cf* Lam_a, const cf* Lam_b,
                             const cd* coef, const cd* m2a, const cd* m2b, const cd* Ba,
                             const cd* Bb, cd* partial, int n_slots, int slot0, hipStream_t st,
                             const int* wmask = nullptr);

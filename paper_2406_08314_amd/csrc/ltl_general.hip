@@ -213,7 +213,7 @@ __global__ __launch_bounds__(64 * NCT, (TL || KSL > GL_KSL2) ? 1 : 2) void k_ltl
     const cd* __restrict__ Ca, const cd* __restrict__ Cb, cd* __restrict__ v0,
     cd* __restrict__ ex0, cd* __restrict__ lamc, cd* __restrict__ czw,
     const int* __restrict__ wmask, const int* __restrict__ wlist, const int* __restrict__ wcount,
-    bool swz) {
+    int swz) {
   typedef GMfma<R> MF;
   typedef typename MF::cx_t C;
   typedef typename MF::acc_t acc_t;
@@ -689,7 +689,7 @@ __global__ __launch_bounds__(64 * NCT, (TL || KSL > GL_KSL2) ? 1 : 2) void k_ltl
         const int a = vt * 16 + MF::row(lane, r);
         if (wi >= 0 && a < nv) {
           const int e = a * no + wi;
-          R* dst = reinterpret_cast<R*>(Lam + ((size_t)wl * NG + g) * X + (swz ? lam_swizzle(e) : e));
+          R* dst = reinterpret_cast<R*>(Lam + ((size_t)wl * NG + g) * X + (swz ? lam_swizzle(e, swz) : e));
           dst[part] = lam[vt][r];
         }
       }
@@ -816,7 +816,7 @@ void gl_launch(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int
                int n_chunks, int M, const R* Sa, const R* Sb, const typename GMfma<R>::cx_t* Ta,
                const typename GMfma<R>::cx_t* Tb, typename GMfma<R>::cx_t* Lam_a,
                typename GMfma<R>::cx_t* Lam_b, const cd* Ca, const cd* Cb, cd* v0, cd* ex0,
-               cd* lamc, cd* czw, const int* wmask, const WalkerList& wls, bool swz,
+               cd* lamc, cd* czw, const int* wmask, const WalkerList& wls, int swz,
                hipStream_t st) {
   const GlShape s = gl_shape(std::max(sa.no, sb.no), M, std::min(sa.N, sb.N), NCT, VT);
   const size_t lds = (size_t)gl_lds_reals(s, sizeof(R), NCT, TL) * sizeof(R);
@@ -845,7 +845,7 @@ void gl_dispatch(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, i
                  int g_chunk, int M, const R* Sa, const R* Sb, const typename GMfma<R>::cx_t* Ta,
                  const typename GMfma<R>::cx_t* Tb, typename GMfma<R>::cx_t* Lam_a,
                  typename GMfma<R>::cx_t* Lam_b, const cd* Ca, const cd* Cb, cd* v0, cd* ex0,
-                 cd* lamc, cd* czw, const int* wmask, const WalkerList& wls, bool swz,
+                 cd* lamc, cd* czw, const int* wmask, const WalkerList& wls, int swz,
                  hipStream_t st) {
   const int nct = ltl_general_nct(sa, sb), ksl = ltl_general_ksl(M, std::min(sa.N, sb.N)),
             vt = ltl_general_vt(sa, sb);
@@ -882,7 +882,7 @@ int ltl_general_parts(const DevSpin& sa, const DevSpin& sb) { return ltl_general
 void launch_ltl_general(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
                         int g_chunk, int M, const double* Sa, const double* Sb, const cd* Ta,
                         const cd* Tb, cd* Lam_a, cd* Lam_b, const cd* Ca, const cd* Cb, cd* v0,
-                        cd* ex0, cd* lamc, cd* czw, const int* wmask, bool swz, hipStream_t st,
+                        cd* ex0, cd* lamc, cd* czw, const int* wmask, int swz, hipStream_t st,
                         const WalkerList& wls) {
   gl_dispatch<double>(sa, sb, NW, w0, WT, NG, g_chunk, M, Sa, Sb, Ta, Tb, Lam_a, Lam_b, Ca, Cb,
                       v0, ex0, lamc, czw, wmask, wls, swz, st);
@@ -891,7 +891,7 @@ void launch_ltl_general(const DevSpin& sa, const DevSpin& sb, int NW, int w0, in
 void launch_ltl_general32(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int NG,
                           int g_chunk, int M, const float* Sa, const float* Sb, const cf* Ta,
                           const cf* Tb, cf* Lam_a, cf* Lam_b, const cd* Ca, const cd* Cb, cd* v0,
-                          cd* ex0, cd* lamc, cd* czw, const int* wmask, bool swz, hipStream_t st,
+                          cd* ex0, cd* lamc, cd* czw, const int* wmask, int swz, hipStream_t st,
                           const WalkerList& wls) {
   gl_dispatch<float>(sa, sb, NW, w0, WT, NG, g_chunk, M, Sa, Sb, Ta, Tb, Lam_a, Lam_b, Ca, Cb, v0,
                      ex0, lamc, czw, wmask, wls, swz, st);

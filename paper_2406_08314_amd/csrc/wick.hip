@@ -1339,7 +1339,7 @@ __global__ __launch_bounds__((MAXK <= 4 ? 1024 : 512)) void k_energy_second(
     int waves_per_block, int NW, int w0, int NG, int n_gsplit, int G, const CT* __restrict__ Lam_a,
     const CT* __restrict__ Lam_b, const cd* __restrict__ coef, const cd* __restrict__ m2a,
     const cd* __restrict__ m2b, const cd* __restrict__ Ba, const cd* __restrict__ Bb,
-    cd* __restrict__ partial, int n_slots, int slot0, bool lds_dma, bool swz,
+    cd* __restrict__ partial, int n_slots, int slot0, bool lds_dma, int swz,
     const int* __restrict__ wmask, const int* __restrict__ wlist, const int* __restrict__ wcount,
     int WT) {
   constexpr int NIDX = 2 * MAXK > 2 * ER_PPL ? 2 * MAXK : 2 * ER_PPL;
@@ -1429,12 +1429,12 @@ __global__ __launch_bounds__((MAXK <= 4 ? 1024 : 512)) void k_energy_second(
         default: if constexpr (MAXK >= 6) rp_setup<6 <= MAXK ? 6 : 2, CT>(hwin, pwin, no, str, rp, m2s, idx, mm); break;
       }
     }
-    // windows stored with the hole slot of particle row a XOR-ed with
-    // (a >> 1) & 7 (eight hole slots): spreads a wave's gathers over the LDS
-    // banks
+    // windows stored in lam_swizzle layout swz (the hole slot of particle
+    // row a XOR-ed with a function of a): spreads a wave's gathers over the
+    // LDS banks
     if (swz) {
 #pragma unroll
-      for (int j = 0; j < NIDX; ++j) idx[j] = lam_swizzle(idx[j]);
+      for (int j = 0; j < NIDX; ++j) idx[j] = lam_swizzle(idx[j], swz);
     }
   }
   // stage buffer b (0/1) starts at sm[b * G * X]: [alpha G x Xa][beta G x Xb].
@@ -1573,7 +1573,7 @@ __global__ __launch_bounds__((MAXK <= 4 ? 1024 : 512)) void k_energy_second(
 #pragma unroll
           for (int n = 0; n < K; ++n) {
             const int e = pofs[n] + hofs[m];
-            y[m * K + n] = gs_[base + (swz ? lam_swizzle(e) : e)];
+            y[m * K + n] = gs_[base + (swz ? lam_swizzle(e, swz) : e)];
           }
         int rp = 0;
 #pragma unroll
@@ -1655,7 +1655,7 @@ template <class CT>
 static void launch_energy_second_t(const DevSpin& sa, const DevSpin& sb, const DevPairs& pr,
                                    const int4* plan, int n_itemblocks, int waves_per_block, int NW,
                                    int w0, int WT, int NG, int n_gsplit, int G, int max_order,
-                                   bool flat_gather, bool use_dma, bool swz, const CT* Lam_a, const CT* Lam_b, const cd* coef,
+                                   bool flat_gather, bool use_dma, int swz, const CT* Lam_a, const CT* Lam_b, const cd* coef,
                                    const cd* m2a, const cd* m2b, const cd* Ba, const cd* Bb,
                                    cd* partial, int n_slots, int slot0, hipStream_t st,
                                    const int* wmask, const WalkerList& wls) {
@@ -1688,7 +1688,7 @@ static void launch_energy_second_t(const DevSpin& sa, const DevSpin& sb, const D
 void launch_energy_second(const DevSpin& sa, const DevSpin& sb, const DevPairs& pr,
                           const int4* plan, int n_itemblocks, int waves_per_block, int NW, int w0,
                           int WT, int NG, int n_gsplit, int G, int max_order, bool flat_gather,
-                          bool use_dma, bool swz, const cd* Lam_a, const cd* Lam_b, const cd* coef,
+                          bool use_dma, int swz, const cd* Lam_a, const cd* Lam_b, const cd* coef,
                           const cd* m2a, const cd* m2b, const cd* Ba, const cd* Bb, cd* partial,
                           int n_slots, int slot0, hipStream_t st, const int* wmask,
                           const WalkerList& wls) {
@@ -1700,7 +1700,7 @@ void launch_energy_second(const DevSpin& sa, const DevSpin& sb, const DevPairs& 
 void launch_energy_second32(const DevSpin& sa, const DevSpin& sb, const DevPairs& pr,
                             const int4* plan, int n_itemblocks, int waves_per_block, int NW,
                             int w0, int WT, int NG, int n_gsplit, int G, int max_order,
-                            bool flat_gather, bool use_dma, bool swz, const cf* Lam_a, const cf* Lam_b,
+                            bool flat_gather, bool use_dma, int swz, const cf* Lam_a, const cf* Lam_b,
                             const cd* coef, const cd* m2a, const cd* m2b, const cd* Ba,
                             const cd* Bb, cd* partial, int n_slots, int slot0, hipStream_t st,
                             const int* wmask) {
