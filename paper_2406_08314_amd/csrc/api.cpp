@@ -552,17 +552,23 @@ void alloc_energy(msd_system* s) {
   s->WT = wt;
   // split the Cholesky range so the second-order workgroups fill whole rounds
   // of the chip's workgroup slots (one 16-wave or two 8-wave workgroups per
-  // CU): the best fill of rounds over splits 1 .. 8, the smaller split on ties
+  // CU): the best fill of rounds over splits 1 .. 8; on ties the smallest
+  // split that makes at least 32 rounds, else the smallest.  Item blocks of
+  // different orders cost differently, so the last round runs partly idle;
+  // with 32 rounds or more that idle time is a small part of the launch.
   const int units = std::max(1, s->n_itemblocks);
   {
     const int slots = s->n_cu * (wpb == 16 ? 1 : 2);
     double best = -1.0;
+    bool best_deep = false;
     for (int gs = 1; gs <= std::min(8, std::max(1, NG / 8)); ++gs) {
       const long nwg = (long)wt * units * gs;
       const long rounds = (nwg + slots - 1) / slots;
       const double fill = (double)nwg / ((double)rounds * slots) - (nwg < slots ? 1.0 : 0.0);
-      if (fill > best + 1e-9) {
-        best = fill;
+      const bool deep = rounds >= 32;
+      if (fill > best + 1e-9 || (fill > best - 1e-9 && deep && !best_deep)) {
+        best = std::max(best, fill);
+        best_deep = deep;
         s->gsplit = gs;
       }
     }
