@@ -274,7 +274,9 @@ typedef struct {
                              active virtuals, M <= 64), 6 = general matrix-core kernel
                              forming L^g T, Q, Lambda and the first-order contraction
                              for up to 48 electrons per spin, M <= 320 and windows of
-                             at most 32 x 32 (the default where 5 does not apply).  A
+                             at most 32 x 32 (the default where 5 does not apply,
+                             except in the FP64 form at 33-48 electrons where T does
+                             not fit the LDS: there 1 is faster for whole batches).  A
                              variant that does not fit the shape falls back to 1.
                              2-4 (earlier kernels no workload picked) are rejected    */
   int32_t lambda_chunk;   /* Cholesky vectors per intermediates workgroup (1..NG); the

@@ -176,6 +176,7 @@ struct msd_system {
   // at most 32 virtual and 32 occupied orbitals): rows of L per spin, k-major,
   // [NG][Mpad][P16], window virtual rows then reference rows
   bool gl_fits = false, gl_fits32 = false;  // FP64 / FP32 instances apply
+  bool gl_fast64 = true;  // the FP64 instance is the default for whole batches
   double* Sgl[2] = {nullptr, nullptr};
   float* Sgl32[2] = {nullptr, nullptr};
   cd* lamc = nullptr;  // [2][NW][NG][gl_parts]: <C, Lambda window> per vector
@@ -526,9 +527,12 @@ void alloc_energy(msd_system* s) {
     const bool fused_ok =
         s->lambda_exact && !cc && (s->energy_mixed ? s->lf_fits32 : s->lf_fits64);
     const bool gen_ok = (s->energy_mixed ? s->gl_fits32 : s->gl_fits) && !cc;
+    // (the FP64 form skips the six-tile register-T instance unless asked for:
+    // the LT-GEMM path is faster there)
+    const bool gen_default = gen_ok && (s->energy_mixed || s->gl_fast64);
     const int want = s->tune.lambda_variant ? s->tune.lambda_variant
                      : fused_ok                 ? 5
-                     : gen_ok                   ? 6
+                     : gen_default              ? 6
                                                 : 1;
     s->lambda_variant = (want == 6 && gen_ok)     ? 6
                         : (want == 5 && fused_ok) ? 5
@@ -1802,6 +1806,7 @@ void set_trial_rows(msd_system* sys, const double* ci, const int32_t* occ_a,
     sys->Slr[sp] = (sys->lf_fits64 || sys->lf_fits32) ? T.get<double>((size_t)NG * 64 * 8) : nullptr;
   }
   sys->gl_fits = msd::ltl_general_fits(sys->ds[0], sys->ds[1], M, false);
+  sys->gl_fast64 = msd::ltl_general_fast64(sys->ds[0], sys->ds[1], M);
   sys->gl_fits32 = sys->mixed && msd::ltl_general_fits(sys->ds[0], sys->ds[1], M, true);
   for (int sp = 0; sp < 2; ++sp) {
     const size_t n = (sys->gl_fits || sys->gl_fits32)

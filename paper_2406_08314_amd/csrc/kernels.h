@@ -162,6 +162,10 @@ struct WalkerList {
   int n_cu = 0;
 };
 bool ltl_general_fits(const DevSpin& sa, const DevSpin& sb, int M, bool fp32);
+// false where the FP64 instance that applies is the six-column-tile one with T
+// in registers (six waves on a CU, spilling): it serves the mixed form's FP64
+// pass over a few walkers, while the LT-GEMM path is faster for whole batches
+bool ltl_general_fast64(const DevSpin& sa, const DevSpin& sb, int M);
 int ltl_general_parts(const DevSpin& sa, const DevSpin& sb);
 size_t ltl_general_s_elems(const DevSpin& sa, const DevSpin& sb, int M, int NG);
 void launch_gather_general(const double* L, int NG, int M, const DevSpin& D, const DevSpin& sa,

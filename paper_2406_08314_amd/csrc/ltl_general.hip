@@ -766,7 +766,8 @@ int ltl_general_ksl(int M, int Nmin) {
 // the slab ring, Q, C and T_V and two workgroups share a CU, each one's
 // products running through the other's waits.  Otherwise T in LDS where it
 // fits (any precision, one or more workgroups per CU), else T in registers at
-// one workgroup per CU (FP64, four column tiles, at most 20 slabs).
+// one workgroup per CU (FP64, four or six column tiles, at most 20 slabs; six
+// tiles always take the 20-slab instance).
 enum GlMode { GL_NONE, GL_TL, GL_REG };
 static GlMode gl_mode(const DevSpin& sa, const DevSpin& sb, int M, size_t rsize) {
   const int nct = ltl_general_nct(sa, sb), ksl = ltl_general_ksl(M, std::min(sa.N, sb.N));
@@ -775,7 +776,7 @@ static GlMode gl_mode(const DevSpin& sa, const DevSpin& sb, int M, size_t rsize)
   const size_t reg = (size_t)gl_lds_reals(s, 8, nct, false) * 8;
   if (rsize == 8 && nct == 4 && ksl <= GL_KSL2 && 2 * reg <= 160 * 1024) return GL_REG;
   if ((size_t)gl_lds_reals(s, (int)rsize, nct, true) * rsize <= 160 * 1024) return GL_TL;
-  if (rsize == 8 && nct == 4 && ksl == 20 && reg <= 160 * 1024) return GL_REG;
+  if (rsize == 8 && ((nct == 4 && ksl == 20) || nct == 6) && reg <= 160 * 1024) return GL_REG;
   return GL_NONE;
 }
 
@@ -786,6 +787,10 @@ bool ltl_general_fits(const DevSpin& sa, const DevSpin& sb, int M, bool fp32) {
     if (d->N == 0 || d->nv == 0 || d->nv > GL_VTMAX * 16 || d->no > GL_OMAX) return false;
   }
   return gl_mode(sa, sb, M, fp32 ? 4 : 8) != GL_NONE;
+}
+
+bool ltl_general_fast64(const DevSpin& sa, const DevSpin& sb, int M) {
+  return !(ltl_general_nct(sa, sb) == 6 && gl_mode(sa, sb, M, 8) == GL_REG);
 }
 
 // elements of one spin's S array (sized for the spin with more kept rows)
@@ -872,6 +877,15 @@ void gl_dispatch(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, i
     GL_CASE(4, GL_KSL2, 2, false)
     GL_CASE(4, 20, 1, false)
     GL_CASE(4, 20, 2, false)
+    if (nct == 6 && !tl) {  // six column tiles: the 20-slab instance for any slab count
+      if (vt == 1)
+        return gl_launch<R, 6, 20, 1, false>(sa, sb, NW, w0, WT, NG, g_chunk, n_chunks, M, Sa,
+                                            Sb, Ta, Tb, Lam_a, Lam_b, Ca, Cb, v0, ex0, lamc, czw,
+                                            wmask, wls, swz, st);
+      return gl_launch<R, 6, 20, 2, false>(sa, sb, NW, w0, WT, NG, g_chunk, n_chunks, M, Sa, Sb,
+                                          Ta, Tb, Lam_a, Lam_b, Ca, Cb, v0, ex0, lamc, czw, wmask,
+                                          wls, swz, st);
+    }
   }
 #undef GL_CASE
 }
