@@ -221,6 +221,7 @@ struct msd_system {
   cd* ex0 = nullptr;
   cd* ZWp[2] = {nullptr, nullptr};
   cd* coefAB = nullptr;
+  cd* adjT[2] = {nullptr, nullptr};  // walker-fastest adjugate copies (pairs with many entries)
   cd* coef2[2] = {nullptr, nullptr};
   cd* epart = nullptr;
 
@@ -683,6 +684,13 @@ void alloc_energy(msd_system* s) {
   if (s->lambda_variant == 6) s->lamc = E.get<cd>((size_t)2 * NW * NG * s->gl_parts);
   s->ex0 = E.get<cd>((size_t)2 * NW * NG * s->gl_parts);
   s->coefAB = E.get<cd>((size_t)NW * s->dp.n_pair);
+  // pair coefficients with the walkers on the lanes where the pairs have 16
+  // or more entries each on average (large trials with high orders)
+  const int64_t n_ent = s->tt.pr_ptr.empty() ? 0 : s->tt.pr_ptr.back();
+  s->adjT[0] = s->adjT[1] = nullptr;
+  if (np > 0 && n_ent >= (int64_t)16 * np)
+    for (int sp = 0; sp < 2; ++sp)
+      s->adjT[sp] = E.get<cd>((size_t)std::max(s->ds[sp].A, 1) * NW);
   s->epart = E.get<cd>((size_t)NW * std::max(s->n_slots, 1));
   s->plan = E.upload(s->plan_host, s->st);
 }
@@ -1043,7 +1051,7 @@ void run_energy(msd_system* s) {
   const msd::DevSpin& B = s->ds[1];
   s->timed(ST_COEF, [&] {
     msd::launch_pair_coef(s->dp, s->NW, s->det_c, s->sw[0].adj, A.A, s->sw[1].adj, B.A,
-                          s->coefAB, s->st);
+                          s->coefAB, s->st, s->adjT[0], s->adjT[1]);
     for (int sp = 0; sp < 2; ++sp)
       if (!s->use_strings[sp])
         msd::launch_minor_coef(s->ds[sp], s->NW, s->sw[sp].B, s->ds[sp].U, s->sw[sp].m2,

@@ -236,8 +236,12 @@ void launch_ltl_mfma32(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int
 void launch_qtr(int NW, int w0, int WT, int NG, int M, const double* SRa, const double* SRb,
                 const cd* Ta, const cd* Tb, cd* v0, cd* ex0, int n_cu, hipStream_t st);
 void init_ltl_attributes();
+// adjT_a / adjT_b (A x NW each, or null): scratch for walker-fastest copies of
+// the adjugates; given, the sums run with the walkers on the lanes (for pairs
+// with many entries each)
 void launch_pair_coef(const DevPairs& pr, int NW, const cd* det_c, const cd* adj_a, int Aa,
-                      const cd* adj_b, int Ab, cd* coef, hipStream_t st);
+                      const cd* adj_b, int Ab, cd* coef, hipStream_t st, cd* adjT_a = nullptr,
+                      cd* adjT_b = nullptr);
 void launch_minor_coef(const DevSpin& s, int NW, const cd* B, int U, const cd* m2, cd* coef,
                        hipStream_t st);
 // second-order energy terms; each launch writes blocks into partial[w][slot0 + ...]

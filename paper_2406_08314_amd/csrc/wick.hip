@@ -1109,24 +1109,95 @@ void launch_lambda32(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int W
 // A7: two-body CI coefficients per walker
 // ============================================================================
 
+// coef[w][t] = sum over the entries e of pair t of c_det(e) adj_a[w][fa(e)]
+// adj_b[w][fb(e)].  One thread per (pair, block of PC_W walkers): the entry's
+// indices and CI coefficient are loaded once for the block, and each walker
+// sums its entries in the same order as a thread per (pair, walker) would.
+constexpr int PC_W = 8;
+
 __global__ void k_pair_coef(DevPairs pr, int NW, const cd* __restrict__ det_c,
                             const cd* __restrict__ adj_a, int Aa, const cd* __restrict__ adj_b,
                             int Ab, cd* __restrict__ coef) {
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid >= (int64_t)pr.n_pair * NW) return;
-  const int t = (int)(tid % pr.n_pair), w = (int)(tid / pr.n_pair);
+  const int n_wb = (NW + PC_W - 1) / PC_W;
+  if (tid >= (int64_t)pr.n_pair * n_wb) return;
+  const int t = (int)(tid % pr.n_pair), w0 = (int)(tid / pr.n_pair) * PC_W;
+  cd acc[PC_W];
+  const cd* aa[PC_W];
+  const cd* ab[PC_W];
+#pragma unroll
+  for (int j = 0; j < PC_W; ++j) {
+    const int w = min(w0 + j, NW - 1);  // past the last walker: repeats it, not stored
+    acc[j] = cd{0.0, 0.0};
+    aa[j] = adj_a + (size_t)w * Aa;
+    ab[j] = adj_b + (size_t)w * Ab;
+  }
+  for (int64_t e = pr.ptr[t]; e < pr.ptr[t + 1]; ++e) {
+    const cd c = det_c[pr.det[e]];
+    const int fa = pr.fa[e], fb = pr.fb[e];
+#pragma unroll
+    for (int j = 0; j < PC_W; ++j) cfma(acc[j], c * aa[j][fa], ab[j][fb]);
+  }
+#pragma unroll
+  for (int j = 0; j < PC_W; ++j)
+    if (w0 + j < NW) coef[(size_t)(w0 + j) * pr.n_pair + t] = acc[j];
+}
+
+// Walker-fastest copy of one spin's adjugates, adjT[f][w] = adj[w][f], in
+// 32 x 32 tiles through LDS.
+__global__ __launch_bounds__(256) void k_adj_transpose(const cd* __restrict__ adj, int A, int NW,
+                                                       cd* __restrict__ adjT) {
+  __shared__ cd tile[32][33];
+  const int f0 = blockIdx.x * 32, w0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) {
+    const int w = w0 + r, f = f0 + tx;
+    if (w < NW && f < A) tile[r][tx] = adj[(size_t)w * A + f];
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int f = f0 + r, w = w0 + tx;
+    if (f < A && w < NW) adjT[(size_t)f * NW + w] = tile[tx][r];
+  }
+}
+
+// The same sums with the walkers on the lanes: one wave per (pair, 64
+// walkers), so the pair's entries (indices and CI coefficient) are
+// wave-uniform and each adjugate read of a wave is one contiguous run of 64
+// walkers' values in the walker-fastest copies.  Each walker sums its entries
+// in the same order as above.
+__global__ __launch_bounds__(256) void k_pair_coef_wl(DevPairs pr, int NW,
+                                                      const cd* __restrict__ det_c,
+                                                      const cd* __restrict__ adjT_a,
+                                                      const cd* __restrict__ adjT_b,
+                                                      cd* __restrict__ coef) {
+  const int t = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (t >= pr.n_pair) return;  // wave-uniform; no barriers
+  const int w = blockIdx.y * 64 + (threadIdx.x & 63);
+  const int wc = min(w, NW - 1);  // past the last walker: repeats it, not stored
   cd acc{0.0, 0.0};
-  const cd* aa = adj_a + (size_t)w * Aa;
-  const cd* ab = adj_b + (size_t)w * Ab;
-  for (int64_t e = pr.ptr[t]; e < pr.ptr[t + 1]; ++e)
-    cfma(acc, det_c[pr.det[e]] * aa[pr.fa[e]], ab[pr.fb[e]]);
-  coef[(size_t)w * pr.n_pair + t] = acc;
+  const int64_t e1 = pr.ptr[t + 1];
+#pragma unroll 4
+  for (int64_t e = pr.ptr[t]; e < e1; ++e) {
+    const cd c = det_c[pr.det[e]];
+    cfma(acc, c * adjT_a[(size_t)pr.fa[e] * NW + wc], adjT_b[(size_t)pr.fb[e] * NW + wc]);
+  }
+  if (w < NW) coef[(size_t)w * pr.n_pair + t] = acc;
 }
 
 void launch_pair_coef(const DevPairs& pr, int NW, const cd* det_c, const cd* adj_a, int Aa,
-                      const cd* adj_b, int Ab, cd* coef, hipStream_t st) {
-  const int64_t n = (int64_t)pr.n_pair * NW;
-  if (n == 0) return;
+                      const cd* adj_b, int Ab, cd* coef, hipStream_t st, cd* adjT_a,
+                      cd* adjT_b) {
+  if ((int64_t)pr.n_pair * NW == 0) return;
+  if (adjT_a && adjT_b) {
+    const dim3 ga((Aa + 31) / 32, (NW + 31) / 32), gb((Ab + 31) / 32, (NW + 31) / 32);
+    hipLaunchKernelGGL(k_adj_transpose, ga, dim3(256), 0, st, adj_a, Aa, NW, adjT_a);
+    hipLaunchKernelGGL(k_adj_transpose, gb, dim3(256), 0, st, adj_b, Ab, NW, adjT_b);
+    hipLaunchKernelGGL(k_pair_coef_wl, dim3((pr.n_pair + 3) / 4, (NW + 63) / 64), dim3(256), 0,
+                       st, pr, NW, det_c, adjT_a, adjT_b, coef);
+    return;
+  }
+  const int64_t n = (int64_t)pr.n_pair * ((NW + PC_W - 1) / PC_W);
   hipLaunchKernelGGL(k_pair_coef, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pr, NW,
                      det_c, adj_a, Aa, adj_b, Ab, coef);
 }
