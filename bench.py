@@ -36,7 +36,6 @@ TRAFFIC_PROFILES = {
     # summaries of the stage's kernel at that workload
     ("energy_gamma", "medium"): os.path.join(ROOT, "profiles", "energy_second_medium_hbm_traffic.md"),
     ("energy_gamma", "cu_oxo"): os.path.join(ROOT, "profiles", "energy_second_cu_oxo_hbm_traffic.md"),
-    ("lambda", 4, "medium"): os.path.join(ROOT, "profiles", "lambda_mfma_medium_hbm_traffic.md"),
     ("lambda", 5, "medium"): os.path.join(ROOT, "profiles", "ltl_mfma_medium_hbm_traffic.md"),
     ("lambda", 6, "cu_oxo"): os.path.join(ROOT, "profiles", "ltl_general_cu_oxo_hbm_traffic.md"),
 }
