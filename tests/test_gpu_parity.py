@@ -110,6 +110,36 @@ def test_high_order_unequal_spins_complex_ci(na, nb, kmax, window, nd):
     compare_walkers(wl, out, range(5), 0.01, sys_=s)
 
 
+def _pair_entries(wl):
+    """(entries, distinct pairs) of the opposite-spin pair table: a determinant
+    with alpha order ka and beta order kb contributes ka^2 kb^2 entries, one per
+    (alpha (particle, hole), beta (particle, hole)) combination."""
+    ra, rb = set(wl.occ_a[0].tolist()), set(wl.occ_b[0].tolist())
+    pairs, ent = set(), 0
+    for a, b in zip(wl.occ_a, wl.occ_b):
+        sa, sb = set(a.tolist()), set(b.tolist())
+        xs = [(p, h) for p in sorted(sa - ra) for h in sorted(ra - sa)]
+        ys = [(p, h) for p in sorted(sb - rb) for h in sorted(rb - sb)]
+        ent += len(xs) * len(ys)
+        pairs |= {(x, y) for x in xs for y in ys}
+    return ent, len(pairs)
+
+
+def test_pair_coefficients_walkers_on_lanes():
+    """Pairs with many entries each (31 on average, 576 pairs) take the
+    pair-coefficient form with the walkers on the lanes; 70 walkers leave the
+    second block of 64 partly filled.  Walkers of both blocks against the
+    brute-force oracle."""
+    wl = make_workload("pairs", M=24, n_alpha=6, n_beta=6, n_chol=32, n_det=3000, k_max=4,
+                       window=(4, 6), c_law="power1", n_walkers=70, seed=4242,
+                       complex_ci=True, noise=0.3)
+    ent, n_pair = _pair_entries(wl)
+    assert ent >= 16 * n_pair  # the library's threshold for this form
+    s = system_for(wl)
+    out = s.measure(wl.dt)
+    compare_walkers(wl, out, [0, 63, 64, 69], wl.dt)
+
+
 def test_single_determinant():
     wl = make_config("tiny", n_det=1)
     s = system_for(wl)
