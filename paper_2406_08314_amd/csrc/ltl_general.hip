@@ -232,7 +232,23 @@ __global__ __launch_bounds__(64 * NCT, (TL || KSL > GL_KSL2) ? 1 : 2) void k_ltl
   // or, with a walker list, a persistent grid striding over the items of the
   // listed walkers (a few walkers then still spread over the chip without a
   // launch of idle workgroups)
-  const int n_items = wlist ? *wcount * 2 * n_chunks : 1;
+  // With a list, an item takes grp consecutive vector chunks: as few as still
+  // give about two items per resident workgroup (single chunks for a handful
+  // of listed walkers, runs as long as the grid mode's for a full list); its
+  // <C, Lam Q> partial goes to the first chunk's slot and the others of its
+  // group are cleared, so the slots still sum to the walker's total.
+  int grp = 1, n_grp = n_chunks;
+  if (wlist) {
+    const int nl = max(*wcount, 1);
+    const int want = min(n_chunks, (int)((2 * gridDim.x + 2 * nl - 1) / (2 * nl)));
+    for (int d = n_chunks; d >= 1; --d)
+      if (n_chunks % d == 0 && n_chunks / d >= want) {
+        grp = d;
+        break;
+      }
+    n_grp = n_chunks / grp;
+  }
+  const int n_items = wlist ? *wcount * 2 * n_grp : 1;
   for (int it = wlist ? (int)blockIdx.x : 0; it < n_items; it += wlist ? (int)gridDim.x : 1) {
   int wl, chunk, s2;
   if (wlist) {
@@ -240,8 +256,8 @@ __global__ __launch_bounds__(64 * NCT, (TL || KSL > GL_KSL2) ? 1 : 2) void k_ltl
     // together stream the same slabs of L (one chunk of one spin)
     const int nl = *wcount;
     wl = wlist[it % nl] - w0;
-    chunk = (it / nl) % n_chunks;
-    s2 = it / (nl * n_chunks);
+    chunk = ((it / nl) % n_grp) * grp;
+    s2 = it / (nl * n_grp);
     if (wl < 0 || wl >= WT) continue;  // listed walker outside this walker tile
   } else {
     const int b = blockIdx.x;
@@ -250,7 +266,7 @@ __global__ __launch_bounds__(64 * NCT, (TL || KSL > GL_KSL2) ? 1 : 2) void k_ltl
     s2 = b / (WT * n_chunks);
     if (wmask && !wmask[w0 + wl]) return;  // walker not selected for this pass
   }
-  const int g0 = chunk * g_chunk, g1 = min(NG, g0 + g_chunk);
+  const int g0 = chunk * g_chunk, g1 = min(NG, g0 + grp * g_chunk);
   if (g1 <= g0) continue;  // no vectors in this chunk (uniform)
   const int w = w0 + wl;
   const DevSpin& D = s2 ? sb : sa;
@@ -708,7 +724,11 @@ __global__ __launch_bounds__(64 * NCT, (TL || KSL > GL_KSL2) ? 1 : 2) void k_ltl
   }
   dot_re = gl_wsum(part ? -dot_re : dot_re);
   dot_im = gl_wsum(dot_im);
-  if (lane == 0) czw[((size_t)s2 * NW + w) * n_chunks * NCT + chunk * NCT + wv] = cd{dot_re, dot_im};
+  if (lane == 0) {
+    cd* zc = czw + ((size_t)s2 * NW + w) * n_chunks * NCT + chunk * NCT + wv;
+    zc[0] = cd{dot_re, dot_im};
+    for (int c = 1; c < grp; ++c) zc[c * NCT] = cd{0.0, 0.0};
+  }
   gl_bar_all();  // the re-reads past the last slab have landed; the next item rewrites the LDS
   }
 }

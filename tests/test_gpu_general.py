@@ -113,3 +113,37 @@ def test_general_kernel_mixed_against_fp64(name):
     np.testing.assert_array_equal(out["log_ovlp"], ref["log_ovlp"])
     de = np.abs(out["e_loc"] - ref["e_loc"])
     assert de.max() <= MIXED_E_TOL, de.max()
+
+
+def _flagged(wl, tmax=2.0):
+    """Walkers whose max |T| over both spins exceeds tmax, T = Phi Phi[R, :]^-1
+    with R the reference determinant's orbitals: the ones the mixed form sends
+    to its FP64 pass."""
+    out = []
+    for w in range(wl.n_walkers):
+        t = 0.0
+        for phi, occ in ((wl.phi_a[w], wl.occ_a[0]), (wl.phi_b[w], wl.occ_b[0])):
+            t = max(t, np.abs(phi @ np.linalg.inv(phi[occ])).max())
+        out.append(t > tmax)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("name", ["n20_m240", "n12_m40"])
+def test_general_kernel_mixed_many_flagged_walkers(name):
+    """Most walkers far from the reference: the mixed form's FP64 pass over the
+    walker list takes several vector chunks per item (many listed walkers);
+    their energies equal the FP64 form's up to summation order, the others stay
+    within 0.1 mHa."""
+    na, nb, M, _, window, kmax, nd, _ = SHAPES[name]
+    wl = make_workload(name, M=M, n_alpha=na, n_beta=nb, n_chol=96, n_det=nd, k_max=kmax,
+                       window=window, c_law="flat", n_walkers=48, seed=1201, complex_ci=True,
+                       noise=1.0)
+    flag = _flagged(wl)
+    assert flag.sum() >= 22, flag.sum()  # at least two chunks per item
+    ref = _system(wl).measure(wl.dt)
+    s = _system(wl, "mixed")
+    out = s.measure(wl.dt)
+    assert s.get_tuning()["lambda_variant"] == 6
+    e, e64 = out["e_loc"], ref["e_loc"]
+    assert np.max(np.abs(e - e64)[flag]) <= TOL * max(1.0, np.max(np.abs(e64)))
+    assert np.max(np.abs(e - e64)) <= MIXED_E_TOL
