@@ -204,7 +204,10 @@ __host__ __device__ inline int gl_lds_reals(const GlShape& s, int rsize, int NCT
 
 }  // namespace
 
-template <class R, int NCT, int KSL, int VT, bool TL>
+// LIST: the instance that walks a walker list (a separate instance, so that
+// the grid form's register allocation is not touched by the list form's item
+// arithmetic)
+template <class R, int NCT, int KSL, int VT, bool TL, bool LIST>
 __global__ __launch_bounds__(64 * NCT, (TL || KSL > GL_KSL2) ? 1 : 2) void k_ltl_general(
     DevSpin sa, DevSpin sb, int NW, int w0, int WT, int NG, int g_chunk, int n_chunks, int M,
     const R* __restrict__ Sa, const R* __restrict__ Sb,
@@ -238,7 +241,7 @@ __global__ __launch_bounds__(64 * NCT, (TL || KSL > GL_KSL2) ? 1 : 2) void k_ltl
   // <C, Lam Q> partial goes to the first chunk's slot and the others of its
   // group are cleared, so the slots still sum to the walker's total.
   int grp = 1, n_grp = n_chunks;
-  if (wlist) {
+  if constexpr (LIST) {
     const int nl = max(*wcount, 1);
     const int want = min(n_chunks, (int)((2 * gridDim.x + 2 * nl - 1) / (2 * nl)));
     for (int d = n_chunks; d >= 1; --d)
@@ -248,10 +251,10 @@ __global__ __launch_bounds__(64 * NCT, (TL || KSL > GL_KSL2) ? 1 : 2) void k_ltl
       }
     n_grp = n_chunks / grp;
   }
-  const int n_items = wlist ? *wcount * 2 * n_grp : 1;
-  for (int it = wlist ? (int)blockIdx.x : 0; it < n_items; it += wlist ? (int)gridDim.x : 1) {
+  const int n_items = LIST ? *wcount * 2 * n_grp : 1;
+  for (int it = LIST ? (int)blockIdx.x : 0; it < n_items; it += LIST ? (int)gridDim.x : 1) {
   int wl, chunk, s2;
-  if (wlist) {
+  if constexpr (LIST) {
     // listed walker fastest, as the grid order below: the workgroups resident
     // together stream the same slabs of L (one chunk of one spin)
     const int nl = *wcount;
@@ -266,9 +269,14 @@ __global__ __launch_bounds__(64 * NCT, (TL || KSL > GL_KSL2) ? 1 : 2) void k_ltl
     s2 = b / (WT * n_chunks);
     if (wmask && !wmask[w0 + wl]) return;  // walker not selected for this pass
   }
-  const int g0 = chunk * g_chunk, g1 = min(NG, g0 + grp * g_chunk);
+  const int g0 = chunk * g_chunk, g1 = min(NG, g0 + (LIST ? grp : 1) * g_chunk);
   if (g1 <= g0) continue;  // no vectors in this chunk (uniform)
   const int w = w0 + wl;
+  if constexpr (LIST) {  // the <C, Lam Q> slots of the group's other chunks stay zero
+    if (lane == 0)
+      for (int c = 1; c < grp; ++c)
+        czw[(((size_t)s2 * NW + w) * n_chunks + chunk + c) * NCT + wv] = cd{0.0, 0.0};
+  }
   const DevSpin& D = s2 ? sb : sa;
   const int N = D.N, nv = D.nv, no = D.no, X = nv * no;
   const GlShape sh = gl_shape(no, M, N, NCT, VT);
@@ -724,11 +732,7 @@ __global__ __launch_bounds__(64 * NCT, (TL || KSL > GL_KSL2) ? 1 : 2) void k_ltl
   }
   dot_re = gl_wsum(part ? -dot_re : dot_re);
   dot_im = gl_wsum(dot_im);
-  if (lane == 0) {
-    cd* zc = czw + ((size_t)s2 * NW + w) * n_chunks * NCT + chunk * NCT + wv;
-    zc[0] = cd{dot_re, dot_im};
-    for (int c = 1; c < grp; ++c) zc[c * NCT] = cd{0.0, 0.0};
-  }
+  if (lane == 0) czw[((size_t)s2 * NW + w) * n_chunks * NCT + chunk * NCT + wv] = cd{dot_re, dot_im};
   gl_bar_all();  // the re-reads past the last slab have landed; the next item rewrites the LDS
   }
 }
@@ -845,24 +849,29 @@ void gl_launch(const DevSpin& sa, const DevSpin& sb, int NW, int w0, int WT, int
                hipStream_t st) {
   const GlShape s = gl_shape(std::max(sa.no, sb.no), M, std::min(sa.N, sb.N), NCT, VT);
   const size_t lds = (size_t)gl_lds_reals(s, sizeof(R), NCT, TL) * sizeof(R);
-  const void* fn = (const void*)k_ltl_general<R, NCT, KSL, VT, TL>;
+  const void* fg = (const void*)k_ltl_general<R, NCT, KSL, VT, TL, false>;
+  const void* fl = (const void*)k_ltl_general<R, NCT, KSL, VT, TL, true>;
   static bool attr = false;
   if (!attr) {
-    hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    hipFuncSetAttribute(fg, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    hipFuncSetAttribute(fl, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr = true;
   }
-  dim3 grid(WT * n_chunks * 2);
   const dim3 block(64 * NCT);
   if (wls.list) {  // persistent grid: the workgroups resident at once
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, (int)block.x, lds) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fl, (int)block.x, lds) != hipSuccess ||
         per_cu < 1)
       per_cu = 1;
-    grid = dim3(std::max(1, wls.n_cu) * per_cu);
+    const dim3 grid(std::max(1, wls.n_cu) * per_cu);
+    hipLaunchKernelGGL((k_ltl_general<R, NCT, KSL, VT, TL, true>), grid, block, lds, st, sa, sb,
+                       NW, w0, WT, NG, g_chunk, n_chunks, M, Sa, Sb, Ta, Tb, Lam_a, Lam_b, Ca, Cb,
+                       v0, ex0, lamc, czw, wmask, wls.list, wls.count, swz);
+    return;
   }
-  hipLaunchKernelGGL((k_ltl_general<R, NCT, KSL, VT, TL>), grid, block, lds, st, sa, sb, NW, w0,
-                     WT, NG, g_chunk, n_chunks, M, Sa, Sb, Ta, Tb, Lam_a, Lam_b, Ca, Cb, v0, ex0,
-                     lamc, czw, wmask, wls.list, wls.count, swz);
+  hipLaunchKernelGGL((k_ltl_general<R, NCT, KSL, VT, TL, false>), dim3(WT * n_chunks * 2), block,
+                     lds, st, sa, sb, NW, w0, WT, NG, g_chunk, n_chunks, M, Sa, Sb, Ta, Tb, Lam_a,
+                     Lam_b, Ca, Cb, v0, ex0, lamc, czw, wmask, nullptr, nullptr, swz);
 }
 
 template <class R>
