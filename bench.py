@@ -70,8 +70,12 @@ def stage_work(wl, lib_sys, stage):
     M, na, nb, NG, NW = wl.M, wl.n_alpha, wl.n_beta, wl.n_chol, wl.n_walkers
     Ntot = na + nb
     tt = lib_sys.tables
+    # the energy stages run once per walker tile: a launch group covers
+    # NW / n_tiles walkers on average (the propagation GEMMs take all walkers)
+    wt = lib_sys.get_tuning().get("walker_tile") or NW
+    NWe = NW / -(-NW // max(wt, 1))
     if stage == "lt_gemm":  # both spins are separate launch groups; average them
-        f = sum(2.0 * NG * (N + nv) * M * 2 * NW * N for N, nv in
+        f = sum(2.0 * NG * (N + nv) * M * 2 * NWe * N for N, nv in
                 ((na, tt["nv"][0]), (nb, tt["nv"][1]))) / 2
         return f, "flop", "mfma"
     if stage == "fb_gemm":
@@ -88,7 +92,7 @@ def stage_work(wl, lib_sys, stage):
         # and Xi = Lambda Q (8 flop per complex MAC, nv N N each)
         f = 0.0
         for N, nv in ((na, tt["nv"][0]), (nb, tt["nv"][1])):
-            f += NW * NG * (4.0 * (N + nv) * N * M + 2 * 8.0 * nv * N * N)
+            f += NWe * NG * (4.0 * (N + nv) * N * M + 2 * 8.0 * nv * N * N)
         return f, "flop", "mfma"
     if stage == "lambda" and lib_sys.get_tuning()["lambda_variant"] == 6:
         # general fused contraction kernel: per walker, vector and spin LT =
@@ -96,11 +100,11 @@ def stage_work(wl, lib_sys, stage):
         # = T[V, :] Q (8 nv N N) and D = C Q_W^T for <C, Lambda Q> (8 nv no N)
         f = 0.0
         for N, nv, no in ((na, tt["nv"][0], tt["no"][0]), (nb, tt["nv"][1], tt["no"][1])):
-            f += NW * NG * (4.0 * (N + nv) * N * M + 8.0 * nv * N * N + 8.0 * nv * no * N)
+            f += NWe * NG * (4.0 * (N + nv) * N * M + 8.0 * nv * N * N + 8.0 * nv * no * N)
         return f, "flop", "mfma"
     if stage == "traces":
         # Q = L[R, :] T (4 N N M flop) and tr QQ (8 N N) per walker, vector, spin
-        return sum(NW * NG * (4.0 * N * N * M + 8.0 * N * N) for N in (na, nb)), "flop", "mfma"
+        return sum(NWe * NG * (4.0 * N * N * M + 8.0 * N * N) for N in (na, nb)), "flop", "mfma"
     if stage == "lambda":
         # matrix-core kernel: bound by its HBM stream (LT tiles in, Lambda
         # windows, ZW partials, v0 and ex0 out)
@@ -108,14 +112,14 @@ def stage_work(wl, lib_sys, stage):
         n_chunks = (NG + chunk - 1) // chunk
         b = 0.0
         for N, nv, no in ((na, tt["nv"][0], tt["no"][0]), (nb, tt["nv"][1], tt["no"][1])):
-            b += NW * NG * 16.0 * ((N + nv) * N + nv * no) + NW * n_chunks * nv * no * 16.0
-        b += 2 * 2 * NW * NG * 16.0
+            b += NWe * NG * 16.0 * ((N + nv) * N + nv * no) + NWe * n_chunks * nv * no * 16.0
+        b += 2 * 2 * NWe * NG * 16.0
         return b, "byte", "hbm"
     if stage == "energy_gamma" and lib_sys.get_tuning()["energy_form"] == 1:
         # W-form: per walker and Cholesky vector, the real GEMMs of the
         # interleaved windows give W^{ab}, W^{aa}, W^{bb} (8 flop per complex MAC)
         xa, xb = tt["nv"][0] * tt["no"][0], tt["nv"][1] * tt["no"][1]
-        return NW * NG * 8.0 * (xa * xa + xa * xb + xb * xb), "flop", "mfma"
+        return NWe * NG * 8.0 * (xa * xa + xa * xb + xb * xb), "flop", "mfma"
     if stage == "energy_gamma":
         # per walker and Cholesky vector: one complex MAC per opposite-spin
         # pair; per string of order k, k(k-1)/2 x k(k-1)/2 two-by-two minors of
@@ -125,7 +129,7 @@ def stage_work(wl, lib_sys, stage):
             for k, n in tt["strings"][sp].items():
                 p = k * (k - 1) // 2
                 f += 22.0 * p * p * n
-        return NW * NG * f, "flop", "alu"
+        return NWe * NG * f, "flop", "alu"
     return None
 
 
