@@ -829,8 +829,27 @@ __device__ __forceinline__ cd wave_sum(cd v) {
   return v;
 }
 
+// Sum of one value over the workgroup (LAM_WAVES waves), in every thread;
+// red: LAM_WAVES entries of LDS.  Two barriers: red is free again on return.
+constexpr int LAM_WAVES = 4;
 template <class CT>
-__global__ __launch_bounds__(64) void k_lambda(DevSpin sa, DevSpin sb, int NW, int w0, int WT,
+__device__ __forceinline__ CT lam_block_sum(CT v, CT* red) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  CT t{};
+#pragma unroll
+  for (int q = 0; q < LAM_WAVES; ++q) t += red[q];
+  __syncthreads();
+  return t;
+}
+
+// Generic form (any N, windows beyond the rows kernel): one workgroup of
+// LAM_WAVES waves per (walker, vector chunk).  The waves share the LDS copies
+// of T[V, :], each vector's Q and the Lambda rows, so the LDS per workgroup
+// (the N x N Q tile dominates) carries four waves instead of one.
+template <class CT>
+__global__ __launch_bounds__(64 * LAM_WAVES) void k_lambda(DevSpin sa, DevSpin sb, int NW, int w0, int WT,
                                                int NG, int g_chunk, const CT* __restrict__ Ta,
                                                const CT* __restrict__ Tb,
                                                const CT* __restrict__ LTa,
@@ -841,8 +860,10 @@ __global__ __launch_bounds__(64) void k_lambda(DevSpin sa, DevSpin sb, int NW, i
   // LDS: ZW accumulators (double) first, then T[V,:] of both spins, Q and the
   // Lambda rows in the working precision
   extern __shared__ __align__(16) unsigned char sm_raw[];
+  __shared__ CT red[LAM_WAVES];
+  constexpr int NT = 64 * LAM_WAVES;
   const int wl = blockIdx.x, chunk = blockIdx.y, n_chunks = gridDim.y;
-  const int w = w0 + wl, lane = threadIdx.x;
+  const int w = w0 + wl, tid = threadIdx.x;
   cd* ZWs[2];
   ZWs[0] = reinterpret_cast<cd*>(sm_raw);         // [nv_a*no_a] accumulators
   ZWs[1] = ZWs[0] + sa.nv * sa.no;                // [nv_b*no_b]
@@ -850,13 +871,13 @@ __global__ __launch_bounds__(64) void k_lambda(DevSpin sa, DevSpin sb, int NW, i
   CT* TVb = TVa + sa.nv * sa.N;                   // [nv_b*N_b]
   CT* Q = TVb + sb.nv * sb.N;                     // [max N^2]
   CT* Lf = Q + max(sa.N * sa.N, sb.N * sb.N);     // [max nv*N]
-  for (int e = lane; e < sa.nv * sa.no; e += 64) ZWs[0][e] = cd{0.0, 0.0};
-  for (int e = lane; e < sb.nv * sb.no; e += 64) ZWs[1][e] = cd{0.0, 0.0};
-  for (int e = lane; e < sa.nv * sa.N; e += 64) {
+  for (int e = tid; e < sa.nv * sa.no; e += NT) ZWs[0][e] = cd{0.0, 0.0};
+  for (int e = tid; e < sb.nv * sb.no; e += NT) ZWs[1][e] = cd{0.0, 0.0};
+  for (int e = tid; e < sa.nv * sa.N; e += NT) {
     const int a = e / sa.N, j = e % sa.N;
     TVa[e] = Ta[((size_t)sa.vir[a] * NW + w) * sa.N + j];
   }
-  for (int e = lane; e < sb.nv * sb.N; e += 64) {
+  for (int e = tid; e < sb.nv * sb.N; e += NT) {
     const int a = e / sb.N, j = e % sb.N;
     TVb[e] = Tb[((size_t)sb.vir[a] * NW + w) * sb.N + j];
   }
@@ -866,10 +887,10 @@ __global__ __launch_bounds__(64) void k_lambda(DevSpin sa, DevSpin sb, int NW, i
   for (int g = g0; g < g1; ++g) {
     // traces of both spins first: ZW needs v0a + v0b
     CT va{}, vb{};
-    if (lane < sa.N) va = LTa[(((size_t)wl * NG + g) * sa.P + lane) * sa.N + lane];
-    if (lane < sb.N) vb = LTb[(((size_t)wl * NG + g) * sb.P + lane) * sb.N + lane];
-    va = wave_sum(va);
-    vb = wave_sum(vb);
+    for (int j = tid; j < sa.N; j += NT) va += LTa[(((size_t)wl * NG + g) * sa.P + j) * sa.N + j];
+    for (int j = tid; j < sb.N; j += NT) vb += LTb[(((size_t)wl * NG + g) * sb.P + j) * sb.N + j];
+    va = lam_block_sum(va, red);
+    vb = lam_block_sum(vb, red);
     const CT vsum = va + vb;
 #pragma unroll
     for (int s2 = 0; s2 < 2; ++s2) {
@@ -877,7 +898,7 @@ __global__ __launch_bounds__(64) void k_lambda(DevSpin sa, DevSpin sb, int NW, i
       const CT* TV = s2 ? TVb : TVa;
       const int N = S.N, nv = S.nv, no = S.no, X = nv * no;
       if (N == 0) {  // spin without electrons: zero traces
-        if (lane == 0) {
+        if (tid == 0) {
           v0[((size_t)s2 * NW + w) * NG + g] = cd{0.0, 0.0};
           ex0[((size_t)s2 * NW + w) * NG + g] = cd{0.0, 0.0};
         }
@@ -886,21 +907,21 @@ __global__ __launch_bounds__(64) void k_lambda(DevSpin sa, DevSpin sb, int NW, i
       const CT* base = (s2 ? LTb : LTa) + ((size_t)wl * NG + g) * S.P * N;
       const size_t ld = (size_t)N;
       CT x{};
-      for (int e = lane; e < N * N; e += 64) {
+      for (int e = tid; e < N * N; e += NT) {
         const int j = e / N, c = e % N;
         Q[e] = base[(size_t)j * ld + c];
       }
       __syncthreads();
-      for (int e = lane; e < N * N; e += 64) {
+      for (int e = tid; e < N * N; e += NT) {
         const int j = e / N, c = e % N;
         cfma(x, Q[e], Q[c * N + j]);
       }
-      x = wave_sum(x);
-      if (lane == 0) {
+      x = lam_block_sum(x, red);
+      if (tid == 0) {
         v0[((size_t)s2 * NW + w) * NG + g] = to_cd(s2 ? vb : va);
         ex0[((size_t)s2 * NW + w) * NG + g] = to_cd(x);
       }
-      for (int e = lane; e < nv * N; e += 64) {
+      for (int e = tid; e < nv * N; e += NT) {
         const int a = e / N, c = e % N;
         CT acc = -base[(size_t)(N + a) * ld + c];
         for (int j = 0; j < N; ++j) cfma(acc, TV[a * N + j], Q[j * N + c]);
@@ -909,7 +930,7 @@ __global__ __launch_bounds__(64) void k_lambda(DevSpin sa, DevSpin sb, int NW, i
       __syncthreads();
       CT* Lo = (s2 ? Lam_b : Lam_a) + ((size_t)wl * NG + g) * X;
       cd* Z = ZWs[s2];
-      for (int e = lane; e < X; e += 64) {
+      for (int e = tid; e < X; e += NT) {
         const int a = e / no, i = e % no, oc = S.oslot[i];
         CT xi{};
         for (int c = 0; c < N; ++c) cfma(xi, Lf[a * N + c], Q[c * N + oc]);
@@ -923,7 +944,7 @@ __global__ __launch_bounds__(64) void k_lambda(DevSpin sa, DevSpin sb, int NW, i
   for (int s2 = 0; s2 < 2; ++s2) {
     const int X = (s2 ? sb : sa).nv * (s2 ? sb : sa).no;
     cd* ZW = s2 ? ZWb : ZWa;
-    for (int e = lane; e < X; e += 64) ZW[((size_t)wl * n_chunks + chunk) * X + e] = ZWs[s2][e];
+    for (int e = tid; e < X; e += NT) ZW[((size_t)wl * n_chunks + chunk) * X + e] = ZWs[s2][e];
   }
 }
 
@@ -1085,7 +1106,7 @@ static void launch_lambda_t(const DevSpin& sa, const DevSpin& sb, int NW, int w0
                        (size_t)max(sa.nv * sa.N, sb.nv * sb.N);
   const size_t bytes = ((size_t)sa.nv * sa.no + (size_t)sb.nv * sb.no) * sizeof(cd) +
                        words * sizeof(CT);
-  hipLaunchKernelGGL((k_lambda<CT>), dim3(WT, n_chunks), dim3(64), bytes, st, sa, sb, NW, w0, WT,
+  hipLaunchKernelGGL((k_lambda<CT>), dim3(WT, n_chunks), dim3(64 * LAM_WAVES), bytes, st, sa, sb, NW, w0, WT,
                      NG, g_chunk, Ta, Tb, LTa, LTb, Lam_a, Lam_b, v0, ex0, ZWpart_a, ZWpart_b);
 }
 
