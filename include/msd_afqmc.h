@@ -100,7 +100,10 @@ typedef struct {
                              stay FP64.  Walkers far from the reference get FP64
                              energies (see mixed_tmax).  Trials with excitation orders
                              above 6 per spin are evaluated in FP64 unless the W-form
-                             applies (see energy_algo).                               */
+                             applies (see energy_algo); so are all energies at 33-48
+                             electrons per spin where T does not fit the LDS in FP64
+                             (there the FP64 pass for far walkers would cost more than
+                             the FP64 energy path).                                   */
   double mixed_tmax;      /* mixed form with the general contraction kernel: a walker
                              whose largest |T_pj| (T = Phi A^{-1}, the ratios of its
                              single-excitation overlaps to the reference overlap, Sec.

@@ -510,7 +510,12 @@ void alloc_energy(msd_system* s) {
   // energy intermediates: which kernel
   int nmax = 0;
   const bool rows_fit = msd::lambda_rows_fits(A, B, &nmax);
-  s->energy_mixed = s->mixed && (s->wform || (s->use_strings[0] && s->use_strings[1]));
+  // (the FP32 energy path needs an FP64 pass over the walkers far from the
+  // reference; where the only FP64 instance of the general kernel is the
+  // spilling six-tile one, that pass and the FP32 path together cost more
+  // than the FP64 energy path, so the mixed form keeps FP64 energies there)
+  s->energy_mixed = s->mixed && s->gl_fast64 &&
+                    (s->wform || (s->use_strings[0] && s->use_strings[1]));
   s->lambda_exact = rows_fit && A.N == nmax && B.N == nmax;
   for (int sp = 0; sp < 2 && s->lambda_exact; ++sp) {
     const msd::SpinTable& S = s->tt.s[sp];

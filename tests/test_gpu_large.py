@@ -124,8 +124,9 @@ def test_fe2s2_shape_energy_high_orders(form):
     trial: all quantities of sampled walkers against the brute-force oracle;
     the mixed form's local energies within 0.1 mHa.  fp64_general: the FP64
     form through the general contraction kernel's six-column-tile instance
-    with T in registers (the mixed form's FP64 pass at this shape; not the
-    FP64 form's default here)."""
+    with T in registers (not the FP64 form's default here).  At this shape the
+    mixed form keeps FP64 energies (its FP32 path would need that instance for
+    the walkers far from the reference)."""
     precision = "mixed" if form == "mixed" else "fp64"
     wl = make_workload("fe2s2_small", M=300, n_alpha=45, n_beta=45, n_chol=2000, n_det=24,
                        k_max=6, window=(15, 5), c_law="power1", n_walkers=64,
@@ -134,7 +135,7 @@ def test_fe2s2_shape_energy_high_orders(form):
     if form == "fp64_general":
         s.set_tuning(lambda_variant=6)
     out = s.measure(wl.dt)
-    if form != "fp64":
+    if form == "fp64_general":
         assert s.get_tuning()["lambda_variant"] == 6
     walkers = [5, 40]
     ref = msd.measure(wl.h1, wl.chol, wl.e0, wl.ci, wl.occ_a, wl.occ_b, wl.phi_a, wl.phi_b,
